@@ -1,0 +1,389 @@
+"""FP64 CPU oracle of the FreeForm subspace-construction path (arXiv 2605.29318).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the CPU-baseline leg of
+the benchmark may import this module; the product library never does. It
+shares no code with the GPU path (the seeded input generators, which hold none
+of the method's arithmetic, are the only common module).
+
+Layers:
+  * ``ff_oracle.c`` (built here with gcc, no FMA contraction): cell binning,
+    neighbour lists, RKPM shape functions (Sec. 3.2 Eq. (7)-(11)), the
+    transpose of the neighbour relation, the Hessian of Prop. 1 and the mass
+    matrix of Eq. (14), CSR products.
+  * this file: the generalized eigenproblem of Eq. (15) - dense LAPACK
+    ``eigh`` for small n, and an FP64 block LOBPCG (Knyazev 2001) with SVQB
+    orthonormalisation (Stathopoulos & Wu 2002) and an optional Jacobi
+    preconditioner diag(H)^-1 for larger n - plus the
+    residual and subspace-angle metrics used to compare results.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ff_oracle.c")
+_LIB = os.path.join(_HERE, "libff_oracle.so")
+
+_i64p = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+_i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_f64p = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+
+
+def build(force: bool = False) -> str:
+    """Compile the C oracle (gcc, OpenMP, -ffp-contract=off)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+                               "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB)
+        vp = ctypes.c_void_p
+        L.orc_grid.argtypes = [ctypes.c_int64, _f64p, ctypes.c_double, _f64p, _i64p]
+        L.orc_grid.restype = ctypes.c_int
+        L.orc_bin.argtypes = [ctypes.c_int64, _f64p, ctypes.c_double, _f64p, _i64p, _i32p, _i64p]
+        L.orc_bin.restype = ctypes.c_int
+        L.orc_neighbors.argtypes = [ctypes.c_int64, _f64p, _f64p, ctypes.c_double, _f64p, _i64p,
+                                    _i64p, _i64p, vp]
+        L.orc_neighbors.restype = ctypes.c_int64
+        L.orc_neighbors_brute.argtypes = [ctypes.c_int64, _f64p, ctypes.c_int64, _f64p,
+                                          ctypes.c_double, _i64p, vp]
+        L.orc_neighbors_brute.restype = ctypes.c_int64
+        L.orc_rkpm.argtypes = [ctypes.c_int64, _f64p, _f64p, _i64p, _i32p, ctypes.c_double,
+                               ctypes.c_int, _f64p, _f64p, ctypes.POINTER(ctypes.c_int64)]
+        L.orc_rkpm.restype = ctypes.c_int
+        L.orc_transpose.argtypes = [ctypes.c_int64, ctypes.c_int64, _i64p, _i32p, _i64p, _i32p,
+                                    _i32p]
+        L.orc_transpose.restype = ctypes.c_int
+        L.orc_assemble.argtypes = [ctypes.c_int64, ctypes.c_int64, _i64p, _i32p, _f64p, _f64p,
+                                   _f64p, _f64p, _f64p, vp, _i64p, _i32p, _i32p, _i64p, vp, vp, vp]
+        L.orc_assemble.restype = ctypes.c_int64
+        L.orc_spmm.argtypes = [ctypes.c_int64, _i64p, _i32p, _f64p, ctypes.c_int64, _f64p, _f64p]
+        L.orc_spmm.restype = None
+        L.orc_norm_inf.argtypes = [ctypes.c_int64, _i64p, _f64p]
+        L.orc_norm_inf.restype = ctypes.c_double
+        _lib = L
+    return _lib
+
+
+def _c(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+# ----------------------------------------------------------------------------
+# binning and neighbours
+# ----------------------------------------------------------------------------
+
+def grid(xyz, h):
+    xyz = _c(xyz, np.float64)
+    origin = np.zeros(3)
+    dims = np.zeros(3, dtype=np.int64)
+    rc = lib().orc_grid(xyz.shape[0], xyz, float(h), origin, dims)
+    if rc != 0:
+        raise ValueError("bad grid arguments")
+    return origin, dims
+
+
+def bin_nodes(xyz, h):
+    """Stable counting sort of the nodes by cell. Returns perm, cell_start, origin, dims."""
+    xyz = _c(xyz, np.float64)
+    origin, dims = grid(xyz, h)
+    n = xyz.shape[0]
+    perm = np.zeros(n, dtype=np.int32)
+    cell_start = np.zeros(int(np.prod(dims)) + 1, dtype=np.int64)
+    lib().orc_bin(n, xyz, float(h), origin, dims, perm, cell_start)
+    return perm, cell_start, origin, dims
+
+
+def neighbors(qxyz, xyz_sorted, h, origin, dims, cell_start):
+    qxyz = _c(qxyz, np.float64)
+    xyz_sorted = _c(xyz_sorted, np.float64)
+    q = qxyz.shape[0]
+    off = np.zeros(q + 1, dtype=np.int64)
+    tot = lib().orc_neighbors(q, qxyz, xyz_sorted, float(h), _c(origin, np.float64),
+                              _c(dims, np.int64), _c(cell_start, np.int64), off, None)
+    ids = np.zeros(max(tot, 1), dtype=np.int32)
+    lib().orc_neighbors(q, qxyz, xyz_sorted, float(h), _c(origin, np.float64), _c(dims, np.int64),
+                        _c(cell_start, np.int64), off, _ptr(ids))
+    return off, ids[:tot]
+
+
+def neighbors_brute(qxyz, xyz_sorted, h):
+    qxyz = _c(qxyz, np.float64)
+    xyz_sorted = _c(xyz_sorted, np.float64)
+    q = qxyz.shape[0]
+    off = np.zeros(q + 1, dtype=np.int64)
+    tot = lib().orc_neighbors_brute(q, qxyz, xyz_sorted.shape[0], xyz_sorted, float(h), off, None)
+    ids = np.zeros(max(tot, 1), dtype=np.int32)
+    lib().orc_neighbors_brute(q, qxyz, xyz_sorted.shape[0], xyz_sorted, float(h), off, _ptr(ids))
+    return off, ids[:tot]
+
+
+# ----------------------------------------------------------------------------
+# shape functions and assembly
+# ----------------------------------------------------------------------------
+
+class SingularMoment(RuntimeError):
+    def __init__(self, index):
+        super().__init__(f"singular moment matrix at quadrature point {index}")
+        self.index = index
+
+
+def rkpm(qxyz, xyz_sorted, off, ids, h, kernel=0):
+    """phi[e], dphi[e, 3] for each neighbour entry e (Sec. 3.2 Eq. (7)-(11))."""
+    nnz = int(off[-1])
+    phi = np.zeros(max(nnz, 1))
+    dphi = np.zeros((max(nnz, 1), 3))
+    bad = ctypes.c_int64(-1)
+    rc = lib().orc_rkpm(len(off) - 1, _c(qxyz, np.float64), _c(xyz_sorted, np.float64),
+                        _c(off, np.int64), _c(ids, np.int32), float(h), int(kernel), phi, dphi,
+                        ctypes.byref(bad))
+    if rc != 0:
+        raise SingularMoment(bad.value)
+    return phi[:nnz], dphi[:nnz]
+
+
+def transpose(n, off, ids):
+    off = _c(off, np.int64)
+    ids = _c(ids, np.int32)
+    nt_off = np.zeros(n + 1, dtype=np.int64)
+    nt_id = np.zeros(max(len(ids), 1), dtype=np.int32)
+    nt_slot = np.zeros(max(len(ids), 1), dtype=np.int32)
+    lib().orc_transpose(n, len(off) - 1, off, ids, nt_off, nt_id, nt_slot)
+    return nt_off, nt_id, nt_slot
+
+
+def assemble(n, off, ids, phi, dphi, vol, lam, mu, rho=None):
+    """CSR (row_ptr, col, H, M) of Prop. 1 and Eq. (14), rows and columns in sorted numbering."""
+    off = _c(off, np.int64)
+    ids = _c(ids, np.int32)
+    q = len(off) - 1
+    phi = _c(phi, np.float64)
+    dphi = _c(dphi, np.float64).reshape(-1)
+    vol = _c(vol, np.float64)
+    lam = _c(lam, np.float64)
+    mu = _c(mu, np.float64)
+    rho = None if rho is None else _c(rho, np.float64)
+    nt_off, nt_id, nt_slot = transpose(n, off, ids)
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    nnz = lib().orc_assemble(n, q, off, ids, phi, dphi, vol, lam, mu, _ptr(rho), nt_off, nt_id,
+                             nt_slot, row_ptr, None, None, None)
+    col = np.zeros(max(nnz, 1), dtype=np.int32)
+    H = np.zeros(max(nnz, 1))
+    M = np.zeros(max(nnz, 1))
+    lib().orc_assemble(n, q, off, ids, phi, dphi, vol, lam, mu, _ptr(rho), nt_off, nt_id, nt_slot,
+                       row_ptr, _ptr(col), _ptr(H), _ptr(M))
+    return row_ptr, col[:nnz], H[:nnz], M[:nnz]
+
+
+def spmm(row_ptr, col, val, X):
+    X = _c(X, np.float64)
+    two = X.ndim == 2
+    X2 = X if two else X[:, None]
+    X2 = np.ascontiguousarray(X2)
+    Y = np.zeros_like(X2)
+    lib().orc_spmm(len(row_ptr) - 1, _c(row_ptr, np.int64), _c(col, np.int32),
+                   _c(val, np.float64), X2.shape[1], X2, Y)
+    return Y if two else Y[:, 0]
+
+
+def norm_inf(row_ptr, val):
+    return float(lib().orc_norm_inf(len(row_ptr) - 1, _c(row_ptr, np.int64), _c(val, np.float64)))
+
+
+def to_scipy(n, row_ptr, col, val):
+    import scipy.sparse as sp
+    return sp.csr_matrix((val, col, row_ptr), shape=(n, n))
+
+
+@dataclass
+class Problem:
+    """Everything the path produces for one object, in sorted numbering."""
+    n: int
+    h: float
+    perm: np.ndarray
+    cell_start: np.ndarray
+    origin: np.ndarray
+    dims: np.ndarray
+    xyz: np.ndarray
+    nbr_off: np.ndarray
+    nbr_id: np.ndarray
+    phi: np.ndarray
+    dphi: np.ndarray
+    vol: np.ndarray
+    lam: np.ndarray
+    mu: np.ndarray
+    rho: Optional[np.ndarray]
+    row_ptr: np.ndarray
+    col: np.ndarray
+    H: np.ndarray
+    M: np.ndarray
+
+    def Hs(self):
+        return to_scipy(self.n, self.row_ptr, self.col, self.H)
+
+    def Ms(self):
+        return to_scipy(self.n, self.row_ptr, self.col, self.M)
+
+
+def pipeline(cloud, use_rho: bool = False, kernel: int = 0) -> Problem:
+    """Binning -> neighbours -> shape functions -> H, M for a synthetic cloud.
+
+    Quadrature points are the particles themselves (one per particle), so the
+    per-point arrays are permuted into sorted numbering with ``perm``.
+    """
+    perm, cs, origin, dims = bin_nodes(cloud.xyz, cloud.h)
+    xs = np.ascontiguousarray(cloud.xyz[perm])
+    off, ids = neighbors(xs, xs, cloud.h, origin, dims, cs)
+    phi, dphi = rkpm(xs, xs, off, ids, cloud.h, kernel=kernel)
+    vol, lam, mu = cloud.vol[perm], cloud.lam[perm], cloud.mu[perm]
+    rho = cloud.rho[perm] if use_rho else None
+    rp, col, H, M = assemble(cloud.n, off, ids, phi, dphi, vol, lam, mu, rho)
+    return Problem(cloud.n, cloud.h, perm, cs, origin, dims, xs, off, ids, phi, dphi,
+                   np.ascontiguousarray(vol), np.ascontiguousarray(lam), np.ascontiguousarray(mu),
+                   rho, rp, col, H, M)
+
+
+# ----------------------------------------------------------------------------
+# eigenproblem (Eq. (15)): H w = lambda M w, k smallest, W^T M W = I
+# ----------------------------------------------------------------------------
+
+def sign_fix(W):
+    """Sign rule: in every column the entry of largest magnitude is positive (first on ties)."""
+    W = np.array(W, copy=True)
+    idx = np.argmax(np.abs(W), axis=0)
+    s = np.sign(W[idx, np.arange(W.shape[1])])
+    s[s == 0] = 1.0
+    return W * s
+
+
+def dense_eigh(H, M, k):
+    """Plain definition for small n: LAPACK generalized symmetric eigensolver."""
+    import scipy.linalg as sl
+    Hd = H.toarray() if hasattr(H, "toarray") else np.asarray(H)
+    Md = M.toarray() if hasattr(M, "toarray") else np.asarray(M)
+    w, V = sl.eigh(Hd, Md, subset_by_index=[0, k - 1])
+    return w, sign_fix(V)
+
+
+def residuals(H, M, lam, W, normH=None, normM=None):
+    """r_j = ||H w_j - lam_j M w_j|| / ((||H||_inf + |lam_j| ||M||_inf) ||w_j||)."""
+    if normH is None:
+        normH = float(abs(H).sum(axis=1).max())
+    if normM is None:
+        normM = float(abs(M).sum(axis=1).max())
+    R = H @ W - (M @ W) * lam[None, :]
+    return np.linalg.norm(R, axis=0) / ((normH + np.abs(lam) * normM) * np.linalg.norm(W, axis=0))
+
+
+def _svqb(S, MS, tau):
+    """M-orthonormalise the columns of S (Stathopoulos & Wu 2002); returns T with S T orthonormal."""
+    G = S.T @ MS
+    G = 0.5 * (G + G.T)
+    d = np.sqrt(np.maximum(np.diag(G), 1e-300))
+    Dinv = 1.0 / d
+    Gs = G * Dinv[:, None] * Dinv[None, :]
+    s, U = np.linalg.eigh(Gs)
+    keep = s > tau * s.max()
+    return (Dinv[:, None] * U[:, keep]) / np.sqrt(s[keep])[None, :]
+
+
+def lobpcg(H, M, X0, k=None, tol=1e-10, maxiter=5000, precond=None, normH=None, normM=None,
+           verbose=False):
+    """Block LOBPCG (Knyazev 2001) in FP64 for the smallest eigenpairs of (H, M).
+
+    Search space S = [X, W, P] with W the (optionally preconditioned) block
+    residual and P the previous search direction; the Rayleigh-Ritz step is
+    done in an M-orthonormal basis of S. Converged when the first k columns
+    satisfy the backward-error residual of ``residuals`` <= tol.
+    """
+    X = np.array(X0, dtype=np.float64, copy=True)
+    m = X.shape[1]
+    if isinstance(precond, str):
+        if precond != "jacobi":
+            raise ValueError(precond)
+        dH = np.asarray(H.diagonal(), dtype=np.float64)
+        precond = (lambda R, d=dH: R / d[:, None])
+    k = m if k is None else k
+    if normH is None:
+        normH = float(abs(H).sum(axis=1).max())
+    if normM is None:
+        normM = float(abs(M).sum(axis=1).max())
+    MX = M @ X
+    T = _svqb(X, MX, 1e-14)
+    X = X @ T
+    HX, MX = H @ X, M @ X
+    A = X.T @ HX
+    th, Y = np.linalg.eigh(0.5 * (A + A.T))
+    X, HX, MX = X @ Y, HX @ Y, MX @ Y
+    P = HP = MP = None
+    it = 0
+    res = None
+    for it in range(1, maxiter + 1):
+        R = HX - MX * th[None, :]
+        res = np.linalg.norm(R, axis=0) / ((normH + np.abs(th) * normM) *
+                                           np.linalg.norm(X, axis=0))
+        if verbose and it % 50 == 0:
+            print(it, res[:k].max())
+        if res[:k].max() <= tol:
+            break
+        W = R if precond is None else precond(R)
+        HW, MW = H @ W, M @ W
+        blocks = [X, W] + ([P] if P is not None else [])
+        S = np.concatenate(blocks, axis=1)
+        HS = np.concatenate([HX, HW] + ([HP] if P is not None else []), axis=1)
+        MS = np.concatenate([MX, MW] + ([MP] if P is not None else []), axis=1)
+        T = _svqb(S, MS, 1e-14)
+        A = T.T @ (S.T @ HS) @ T
+        th_all, Y = np.linalg.eigh(0.5 * (A + A.T))
+        C = T @ Y[:, :m]
+        th = th_all[:m]
+        Cn = C.copy()
+        Cn[:m, :] = 0.0                      # the part of the update outside span(X)
+        X, HX, MX = S @ C, HS @ C, MS @ C
+        P, HP, MP = S @ Cn, HS @ Cn, MS @ Cn
+    order = np.argsort(th)
+    th, X = th[order], X[:, order]
+    return th[:k], sign_fix(X[:, :k]), it, res[order][:k]
+
+
+def subspace_sines(Wa, Wb, M):
+    """Sines of the principal angles between span(Wa) and span(Wb) in the M inner product."""
+    Ta = _svqb(Wa, M @ Wa, 1e-14)
+    Qa = Wa @ Ta
+    Tb = _svqb(Wb, M @ Wb, 1e-14)
+    Qb = Wb @ Tb
+    E = Qb - Qa @ (Qa.T @ (M @ Qb))
+    G = E.T @ (M @ E)
+    s = np.linalg.eigvalsh(0.5 * (G + G.T))
+    return np.sqrt(np.clip(s, 0.0, None))[::-1]
+
+
+def cluster_safe_k(lam, k, rel_gap=1e-3):
+    """Largest k' <= k with (lam[k'] - lam[k'-1]) / lam[k'] >= rel_gap (no split cluster)."""
+    for kk in range(k, 0, -1):
+        if kk == len(lam):
+            continue
+        a, b = lam[kk - 1], lam[kk]
+        if b > 0 and (b - a) / b >= rel_gap:
+            return kk
+    return 0

@@ -1,0 +1,135 @@
+"""Pins of the oracle's RKPM shape functions (Sec. 3.2 Eq. (7)-(11)), CPU only.
+
+Checks: the reproducing conditions of Eq. (8) and their gradients, central
+finite differences of phi, the paper's literal (unshifted) moment-matrix
+formulation, the closed-form Shepard reduction at a symmetric stencil, the
+cubic B-spline as a 4-fold convolution of a box, and kernel-scale invariance.
+"""
+import numpy as np
+import pytest
+
+from paper_2605_29318_amd import synth
+
+
+def _prep(oracle, c, q=None):
+    perm, cs, origin, dims = oracle.bin_nodes(c.xyz, c.h)
+    xs = np.ascontiguousarray(c.xyz[perm])
+    qx = xs if q is None else np.ascontiguousarray(q)
+    off, ids = oracle.neighbors(qx, xs, c.h, origin, dims, cs)
+    return xs, qx, off, ids
+
+
+@pytest.mark.parametrize("which", ["cube", "random", "hetero"])
+def test_reproducing_conditions(oracle, which):
+    c = {"cube": synth.cube_lattice(), "random": synth.random_cloud(2000, seed=4),
+         "hetero": synth.random_cloud(1500, seed=8, hetero=True)}[which]
+    xs, qx, off, ids = _prep(oracle, c)
+    phi, dphi = oracle.rkpm(qx, xs, off, ids, c.h)
+    q = qx.shape[0]
+    rows = np.repeat(np.arange(q), np.diff(off))
+    # partition of unity and its gradient
+    s0 = np.bincount(rows, weights=phi, minlength=q)
+    assert np.abs(s0 - 1.0).max() <= 1e-12
+    for s in range(3):
+        g = np.bincount(rows, weights=dphi[:, s], minlength=q)
+        assert np.abs(g).max() * c.h <= 1e-12
+    # linear reproduction sum phi_k p_k = X and sum p_k grad phi_k^T = I
+    p = xs[ids]
+    for a in range(3):
+        lin = np.bincount(rows, weights=phi * p[:, a], minlength=q)
+        assert np.abs(lin - qx[:, a]).max() / c.h <= 1e-12
+        for s in range(3):
+            gl = np.bincount(rows, weights=dphi[:, s] * p[:, a], minlength=q)
+            assert np.abs(gl - (1.0 if a == s else 0.0)).max() <= 1e-12
+
+
+def test_gradient_matches_finite_differences(oracle):
+    c = synth.random_cloud(1500, seed=13)
+    xs, qx, off, ids = _prep(oracle, c)
+    phi, dphi = oracle.rkpm(qx, xs, off, ids, c.h)
+    sel = np.arange(0, c.n, 50)
+    d = 1e-6 * c.h
+    for s in range(3):
+        e = np.zeros(3)
+        e[s] = d
+        # same neighbour lists at the shifted points: the spline and its slope vanish at the support edge
+        sub_off = np.concatenate([[0], np.cumsum(np.diff(off)[sel])])
+        sub_ids = np.concatenate([ids[off[i]:off[i + 1]] for i in sel]).astype(np.int32)
+        pp, _ = oracle.rkpm(qx[sel] + e, xs, sub_off, sub_ids, c.h)
+        pm, _ = oracle.rkpm(qx[sel] - e, xs, sub_off, sub_ids, c.h)
+        fd = (pp - pm) / (2 * d)
+        ref = np.concatenate([dphi[off[i]:off[i + 1], s] for i in sel])
+        scale = np.abs(ref).max()
+        assert np.abs(fd - ref).max() <= 1e-6 * scale
+
+
+def _bspline_by_convolution(z):
+    """Cubic B-spline as the 4-fold self-convolution of a box of width 1/2 (knots at 0, 1/2, 1)."""
+    N = 4000                                # samples per unit
+    x = np.arange(-N // 4, N // 4) / N      # box on [-1/4, 1/4)
+    box = np.ones_like(x)
+    b = box
+    for _ in range(3):
+        b = np.convolve(b, box) / N
+    grid = (np.arange(b.size) - (b.size - 1) / 2) / N
+    return np.interp(z, grid, b)
+
+
+def test_shepard_reduction_and_spline_shape(oracle):
+    """At an interior node of an unjittered lattice the first moments vanish, so
+    phi_k = w_k / sum w; the ratios phi_k / phi_self then trace the kernel shape."""
+    c = synth.cube_lattice(m=12, jitter=0.0)
+    xs, qx, off, ids = _prep(oracle, c)
+    phi, _ = oracle.rkpm(qx, xs, off, ids, c.h)
+    centre = np.array([0.6, 0.6, 0.6]) - 0.05
+    i = int(np.argmin(np.sum((qx - centre) ** 2, axis=1)))
+    nb = ids[off[i]:off[i + 1]]
+    ph = phi[off[i]:off[i + 1]]
+    z = np.sqrt(np.sum((xs[nb] - qx[i]) ** 2, axis=1)) / c.h
+    self_ = ph[np.argmin(z)]
+    ratio = ph / self_
+    ref = _bspline_by_convolution(z) / _bspline_by_convolution(0.0)
+    assert np.abs(ratio - ref).max() <= 1e-5
+    # Shepard: all phi positive, symmetric stencil gives equal phi at equal distance
+    assert np.all(ph > 0)
+    for zz in np.unique(np.round(z, 9)):
+        grp = ph[np.abs(z - zz) < 1e-9]
+        assert np.ptp(grp) <= 1e-15
+
+
+def test_literal_moment_matrix_form(oracle):
+    """Eq. (7), (9)-(11) with the unshifted basis P = [1, x, y, z] agree with the oracle."""
+    c = synth.random_cloud(600, seed=17)
+    xs, qx, off, ids = _prep(oracle, c)
+    phi, _ = oracle.rkpm(qx, xs, off, ids, c.h)
+    for i in range(0, c.n, 41):
+        nb = ids[off[i]:off[i + 1]]
+        z = np.sqrt(np.sum((xs[nb] - qx[i]) ** 2, axis=1)) / c.h
+        w = _bspline_by_convolution(z)                  # raw kernel from its definition
+        P = np.concatenate([np.ones((len(nb), 1)), xs[nb]], axis=1)
+        Mx = (P * w[:, None]).T @ P
+        C = np.linalg.solve(Mx, np.concatenate([[1.0], qx[i]]))
+        lit = w * (P @ C)
+        assert np.abs(lit - phi[off[i]:off[i + 1]]).max() <= 1e-5
+
+
+def test_kernel_scale_invariance(oracle):
+    """The RKPM correction is invariant to scaling the raw kernel: Gaussian and spline
+    differ, but the reproduced linear fields are exact for both."""
+    c = synth.random_cloud(900, seed=23)
+    xs, qx, off, ids = _prep(oracle, c)
+    for kern in (0, 1):
+        phi, dphi = oracle.rkpm(qx, xs, off, ids, c.h, kernel=kern)
+        rows = np.repeat(np.arange(c.n), np.diff(off))
+        assert np.abs(np.bincount(rows, weights=phi) - 1).max() <= 1e-12
+
+
+def test_singular_moment_reported(oracle):
+    """Three collinear neighbours cannot reproduce a linear field: the index is reported."""
+    xs = np.array([[0.0, 0.0, 0.0], [0.1, 0.0, 0.0], [0.2, 0.0, 0.0]])
+    qx = np.array([[0.1, 0.0, 0.0]])
+    off = np.array([0, 3], dtype=np.int64)
+    ids = np.array([0, 1, 2], dtype=np.int32)
+    with pytest.raises(oracle.SingularMoment) as ei:
+        oracle.rkpm(qx, xs, off, ids, 0.25)
+    assert ei.value.index == 0
