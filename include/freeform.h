@@ -1,0 +1,284 @@
+/*
+ * freeform.h - C ABI of the MI355X (gfx950) subspace-construction path of
+ * "FreeForm: Reduced-Order Deformable Simulation from Particle-Based Skinning
+ * Eigenmodes" (arXiv 2605.29318): RKPM shape functions on particles, the
+ * weight-space Hessian of the Neo-Hookean energy and the RKPM mass matrix,
+ * and the smallest generalized eigenpairs H w = lambda M w (the skinning
+ * eigenmodes).
+ *
+ * Conventions (every entry point):
+ *  - Bulk arrays are DEVICE pointers owned by the caller; the library never
+ *    frees them. Scalars, status and small results are HOST pointers, as
+ *    marked. Library workspace lives in the context and is released by
+ *    ff_ctx_destroy.
+ *  - Work is enqueued on the context's stream. Calls that return sizes,
+ *    status or eigenvalues to the host synchronise that stream first.
+ *  - Return value: FF_OK (0) or a negative ff_status; ff_last_error() gives a
+ *    message that names the offending index where there is one. No C++
+ *    exception crosses the ABI.
+ *  - Two-phase sizing: pass NULL for a variable-size output to obtain its size
+ *    (e.g. *nbr_total, *nnz); then call again with a buffer of that capacity.
+ *    A capacity below the required size returns FF_ERR_CAPACITY and still
+ *    writes the required size.
+ *  - Index arrays inside lists are int32 (fewer than 2^31 particles); offsets
+ *    are int64. Positions are double[n][3] (x, y, z per point).
+ *  - After build_neighbors everything is in SORTED numbering: sorted node j is
+ *    original node perm[j]. Per-quadrature-point inputs of later calls may be
+ *    in original order if the permutation is passed (see assemble_HM).
+ *  - Not thread safe per context: calls on one context must not overlap.
+ */
+#ifndef FREEFORM_H
+#define FREEFORM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ff_ctx ff_ctx;
+
+typedef enum {
+    FF_OK = 0,
+    FF_ERR_INVALID_ARG = -1,      /* bad size, NULL where required, NaN input, limit exceeded */
+    FF_ERR_OOM = -2,              /* device allocation of library workspace failed */
+    FF_ERR_HIP = -3,              /* a HIP runtime call failed (message has the HIP error) */
+    FF_ERR_CAPACITY = -4,         /* caller buffer too small; required size written */
+    FF_ERR_SINGULAR_MOMENT = -5,  /* RKPM moment matrix not positive definite at a point */
+    FF_ERR_NOT_CONVERGED = -6,    /* max_iter reached; best results still written */
+    FF_ERR_BREAKDOWN = -7         /* eigensolver basis lost rank beyond recovery */
+} ff_status;
+
+/* Context: binds a device and a stream (NULL = the device's null stream). */
+int ff_ctx_create(ff_ctx **ctx, int device, void *hip_stream);
+void ff_ctx_destroy(ff_ctx *ctx);
+const char *ff_last_error(const ff_ctx *ctx);
+/* Elapsed device time of named stages of the last eigenmodes call, in ms (host out). */
+int ff_ctx_stage_times(const ff_ctx *ctx, double *spmm_ms, double *gram_ms, double *rr_ms,
+                       double *update_ms, double *total_ms);
+
+/* Uniform cell grid of edge h over the node bounding box. */
+typedef struct {
+    double origin[3];   /* componentwise minimum of the node positions */
+    double h;           /* cell edge = kernel support radius */
+    int64_t dims[3];    /* dims_a = floor((max_a - origin_a) / h) + 1 */
+    int64_t n_cells;    /* dims[0] * dims[1] * dims[2] */
+} ff_grid;
+
+/*
+ * build_neighbors - cell binning and neighbour lists.
+ *
+ * The paper's kernels have unbounded support (Gaussian RBF, Sec. 3.2); this
+ * path uses compact kernels of support radius h, so phi_k(X) is non-zero only
+ * for |X - p_k| < h. This call finds those pairs.
+ *
+ *  xyz        [n][3] node positions, original order (device, in)
+ *  qxyz       [q][3] quadrature points (device, in), or NULL: the quadrature
+ *             points are the nodes themselves, in sorted order (q must be n)
+ *  grid       host out: the cell grid
+ *  perm       [n] device out: perm[j] = original index of sorted node j.
+ *             Nodes are sorted by cell id (z, y, x with x fastest), ties by
+ *             original index (a stable counting sort).
+ *  xyz_sorted [n][3] device out: xyz[perm[j]]
+ *  cell_start [n_cells + 1] device out, or NULL on the sizing call: sorted
+ *             nodes of cell c are cell_start[c] .. cell_start[c+1]-1
+ *  nbr_off    [q+1] device out: list of quadrature point i is
+ *             nbr_id[nbr_off[i] .. nbr_off[i+1]-1]
+ *  nbr_id     [nbr_cap] device out or NULL on the sizing call: sorted node
+ *             ids j with d^2 < h*h, d^2 = ((dx*dx)+(dy*dy))+(dz*dz),
+ *             dx = X.x - p.x in IEEE double without contraction; ascending.
+ *  nbr_total  host out: total number of pairs
+ * Cell index per axis: min(max(floor((x - origin)/h), 0), dims-1) with IEEE
+ * division. Errors: FF_ERR_INVALID_ARG (n <= 0, h <= 0 or not finite, a
+ * non-finite coordinate, more than 2^31-1 cells or pairs, a cell holding more
+ * than 4096 nodes), FF_ERR_CAPACITY (cell_start or nbr_id too small).
+ */
+int build_neighbors(ff_ctx *ctx, int64_t n, const double *xyz, int64_t q, const double *qxyz,
+                    double h, ff_grid *grid, int32_t *perm, double *xyz_sorted,
+                    int64_t *cell_start, int64_t cell_cap, int64_t *nbr_off, int32_t *nbr_id,
+                    int64_t nbr_cap, int64_t *nbr_total);
+
+/*
+ * rkpm_shape - RKPM shape functions and gradients, Sec. 3.2 Eq. (7)-(11).
+ *
+ * For quadrature point X_i and each neighbour k in its list (linear basis
+ * P = [1, x, y, z]):  phi_k(X) = phi~_k(X) P(p_k)^T M(X)^-1 P(X) with the
+ * moment matrix M(X) = sum_k phi~_k(X) P(p_k) P(p_k)^T (Eq. (9)-(10)).
+ * It is evaluated in the equivalent shifted, scaled basis [1, (p_k - X)/h]
+ * and differentiated exactly in X.
+ *
+ *  kernel   0 = cubic B-spline of z = |X - p|/h (support h);
+ *           1 = Gaussian exp(-d^2/r^2) of Sec. 3.2 with r = h/2, truncated at h
+ *  phi      [nbr_total] device out, aligned with nbr_id
+ *  dphi     [nbr_total][3] device out: gradient of phi_k at X_i
+ *  feat     [q][8] device out or NULL: per-point raw features (4 eigenvalues
+ *           of the moment matrix over sum phi~, neighbour count, sum phi~,
+ *           |sum phi~ (p - X)| / (h sum phi~), std/mean of phi~)
+ *  bad_index host out: first quadrature point whose 4x4 moment matrix has a
+ *           Cholesky pivot <= 1e-14 * trace (FF_ERR_SINGULAR_MOMENT), else -1
+ */
+int rkpm_shape(ff_ctx *ctx, int64_t n, const double *xyz_sorted, int64_t q, const double *qxyz,
+               const int64_t *nbr_off, const int32_t *nbr_id, int64_t nbr_total, double h,
+               int kernel, double *phi, double *dphi, float *feat, int64_t *bad_index);
+
+/*
+ * assemble_HM - weight-space Hessian (Prop. 1) and RKPM mass matrix (Eq. (14)).
+ *
+ *   H_kl = sum_i v_i (lambda_i + 4 mu_i) grad phi_k(X_i) . grad phi_l(X_i)
+ *   M_kl = sum_i v_i [rho_i] phi_k(X_i) phi_l(X_i)
+ * (Prop. 1 with the quadrature of Supp. C; the Neo-Hookean energy of Eq. (16)
+ * at the rest state). CSR in sorted node numbering; the pattern of row k is
+ * the structural union of N(i) over the quadrature points i whose list holds
+ * k, columns ascending, numeric zeros kept. Each entry is summed over i in
+ * ascending order with term = (v_i (lambda_i + 4 mu_i)) * (((gx gx') + (gy
+ * gy')) + (gz gz')) in IEEE double, so H and M are bitwise symmetric and the
+ * call is deterministic (no atomics in the sums).
+ *
+ *  vol, lam, mu [q] device in: quadrature weight and Lame parameters
+ *  rho          [q] device in, or NULL for the density-free mass matrix of Eq. (14)
+ *  perm         [q] device in, or NULL: if given, the four per-point arrays
+ *               are in original order and point i reads entry perm[i]
+ *  grid, cell_start: as returned by build_neighbors
+ *  row_ptr      [n+1] device out
+ *  col, H, M    [nnz_cap] device out, or NULL on the sizing call
+ *  hm32         [nnz_cap][2] device out or NULL: FP32 copies (H, M) interleaved
+ *  nnz          host out
+ * Errors: FF_ERR_INVALID_ARG (a node with no quadrature point in its support,
+ * a row longer than 2048 or a window of more than 16384 candidate nodes),
+ * FF_ERR_CAPACITY.
+ */
+int assemble_HM(ff_ctx *ctx, int64_t n, int64_t q, const int64_t *nbr_off, const int32_t *nbr_id,
+                const double *phi, const double *dphi, const double *vol, const double *lam,
+                const double *mu, const double *rho, const int32_t *perm, const ff_grid *grid,
+                const int64_t *cell_start, int64_t *row_ptr, int32_t *col, double *H, double *M,
+                float *hm32, int64_t nnz_cap, int64_t *nnz);
+
+/* Eigensolver parameters. */
+typedef struct {
+    int k;              /* eigenpairs wanted, constant mode included (>= 1) */
+    int block;          /* block width m >= k (0 = choose); multiple of 4, <= 64 */
+    int precision;      /* 0 = FP64 throughout; 1 = mixed: FP32 products, FP64 Rayleigh-Ritz,
+                           then FP64 certification and FP64 iterations if needed */
+    double tol;         /* max_j r_j over the first k pairs, r_j as in eigenmodes() */
+    int max_iter;       /* total iteration cap (both phases) */
+    int precond;        /* 0 = none, 1 = Jacobi diag(H)^-1 */
+    uint64_t seed;      /* Philox-4x32-10 key for the random start when X0 == NULL */
+    int check_every;    /* host convergence check period in iterations (0 = 10) */
+    int use_graph;      /* 1 = replay one captured hipGraph per iteration */
+    int refresh_every;  /* recompute HX, MX explicitly every this many iterations (0 = auto) */
+} ff_eig_params;
+
+typedef struct {
+    int iters_fp32;     /* iterations in the FP32 phase (mixed) */
+    int iters_fp64;     /* iterations in the FP64 phase */
+    int converged;      /* 1 if max_j r_j <= tol */
+    int restarts;       /* basis restarts after Rayleigh-Ritz breakdown */
+    double max_resid;   /* final max_j r_j (FP64, certified) */
+    double seconds;     /* wall time of the call */
+} ff_eig_info;
+
+/*
+ * eigenmodes - k smallest generalized eigenpairs of (H, M), Eq. (15): the
+ * minimiser of tr(c^T H c) subject to c^T M c = I is the block of the k
+ * smallest generalized eigenvectors. The constant vector is always the first
+ * mode (eigenvalue 0, Supp. B.1); it is counted in k.
+ *
+ * Blocked LOBPCG (Knyazev 2001) on S = [X, W, P] with a Rayleigh-Ritz step in
+ * FP64 on the device. Residual (FP64, with the FP64 matrices):
+ *   r_j = ||H w_j - lambda_j M w_j||_2 / ((||H||_inf + |lambda_j| ||M||_inf) ||w_j||_2)
+ *
+ *  row_ptr, col, H, M: FP64 CSR from assemble_HM (device in)
+ *  hm32     FP32 interleaved copy (device in), required when precision = 1
+ *  X0       [n][block] device in (row-major), or NULL: Philox uniform [-1, 1)
+ *  eigval   [k] host out, ascending
+ *  W        [n][k] device out (row-major, sorted node numbering): M-orthonormal
+ *           eigenvectors; sign: the entry of largest magnitude is positive
+ *  resid    [k] host out: r_j
+ *  info     host out or NULL
+ * Returns FF_ERR_NOT_CONVERGED (results still written) when max_iter is reached.
+ */
+int eigenmodes(ff_ctx *ctx, int64_t n, const int64_t *row_ptr, const int32_t *col, const double *H,
+               const double *M, const float *hm32, const ff_eig_params *p, const double *X0,
+               double *eigval, double *W, double *resid, ff_eig_info *info);
+
+/*
+ * eigenmodes_batched - independent problems solved together: the CSR is the
+ * block-diagonal concatenation of n_obj matrices; object o owns rows and
+ * columns obj_row_off[o] .. obj_row_off[o+1]-1 (host array). One launch per
+ * stage covers every object; objects that converge are masked out.
+ *
+ *  eigval [n_obj][k], resid [n_obj][k] host out; W [N][k] device out;
+ *  info   [n_obj] host out or NULL.
+ */
+int eigenmodes_batched(ff_ctx *ctx, int n_obj, const int64_t *obj_row_off, const int64_t *row_ptr,
+                       const int32_t *col, const double *H, const double *M, const float *hm32,
+                       const ff_eig_params *p, const double *X0, double *eigval, double *W,
+                       double *resid, ff_eig_info *info);
+
+/*
+ * spmm_hm - the fused block product [HY, MY] = [H, M] Y used inside eigenmodes,
+ * exposed for measurement and tests. Y, HY, MY are [n][m] row-major with
+ * leading dimension ld (>= m). precision 1 reads hm32 and FP32 blocks,
+ * precision 0 reads H, M and FP64 blocks (the block pointers are float* or
+ * double* accordingly). variant selects a tile shape (-1 = tuned/default).
+ */
+int spmm_hm(ff_ctx *ctx, int64_t n, const int64_t *row_ptr, const int32_t *col, const double *H,
+            const double *M, const float *hm32, int precision, int m, const void *Y, int64_t ld_y,
+            void *HY, void *MY, int64_t ld_out, int variant);
+
+/*
+ * spmm_autotune - time every SpMM tile shape on the given matrix with hipEvents
+ * and keep the fastest for matrices of this shape (n, nnz/row, m, precision);
+ * results are cached in the JSON file at cache_path (NULL = no file).
+ * best_variant, best_ms host out.
+ */
+int spmm_autotune(ff_ctx *ctx, int64_t n, const int64_t *row_ptr, const int32_t *col,
+                  const double *H, const double *M, const float *hm32, int precision, int m,
+                  const char *cache_path, int *best_variant, double *best_ms);
+
+/*
+ * gram_hm - the Gram products of the Rayleigh-Ritz step, G_H = S^T HS and
+ * G_M = S^T MS, for row-major [n][w] blocks with leading dimension ld (MFMA
+ * 16x16x4; FP32 blocks accumulate in FP32 over 64 rows and in FP64 beyond).
+ *  precision 1: S, HS, MS are float*; 0: double*
+ *  G  [2][w][w] device out (FP64): G[0] = G_H, G[1] = G_M
+ */
+int gram_hm(ff_ctx *ctx, int64_t n, int w, int precision, const void *S, const void *HS,
+            const void *MS, int64_t ld, double *G);
+
+/*
+ * rayleigh_ritz - FP64 Rayleigh-Ritz on the pencil (G_H, G_M) of order w
+ * (device [2][w][w], symmetric parts used): scale by diag(G_M)^-1/2, Cholesky
+ * of G_M in column order dropping a column whose scaled pivot is <= tau,
+ * reduce, cyclic Jacobi, and return the m smallest eigenpairs of the pencil on
+ * the kept columns: theta [m] ascending and C [w][m] (zero rows for dropped
+ * columns) with C^T G_M C = I and C^T G_H C = diag(theta). Device outputs;
+ * kept host out. FF_ERR_BREAKDOWN if fewer than m columns are kept.
+ */
+int rayleigh_ritz(ff_ctx *ctx, int w, int m, const double *G, double tau, double *C, double *theta,
+                  int *kept);
+
+/* Number of SpMM tile variants and a description of one (host strings). */
+int spmm_variant_count(void);
+const char *spmm_variant_name(int variant);
+
+/*
+ * rand_block - Philox-4x32-10 (Salmon et al., SC'11) uniform numbers in [-1, 1):
+ * element e of the n*m block (row-major) takes 32-bit word e % 4 of the
+ * Philox output for counter (e / 4 low, e / 4 high, 0, 0) and key
+ * (seed low, seed high); value = word * 2^-31 - 1 (exact in double).
+ * out [n][m] device, double.
+ */
+int rand_block(ff_ctx *ctx, int64_t n, int m, uint64_t seed, double *out);
+
+/*
+ * philox4x32_10 - the raw generator behind rand_block, for checking against the
+ * published known-answer vectors: out[4t..4t+3] = Philox-4x32-10 of counter
+ * ctr[4t..4t+3] under key key[2t..2t+1]. All three arrays are device memory.
+ */
+int philox4x32_10(ff_ctx *ctx, int count, const uint32_t *ctr, const uint32_t *key, uint32_t *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FREEFORM_H */

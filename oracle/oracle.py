@@ -387,3 +387,19 @@ def cluster_safe_k(lam, k, rel_gap=1e-3):
         if b > 0 and (b - a) / b >= rel_gap:
             return kk
     return 0
+
+
+def philox4x32_10(ctr, key):
+    """Philox-4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 multiplies
+    with multipliers 0xD2511F53 and 0xCD9E8D57 and a Weyl key schedule
+    (0x9E3779B9, 0xBB67AE85). Returns the four output words."""
+    c = [int(x) & 0xFFFFFFFF for x in ctr]
+    k0, k1 = int(key[0]) & 0xFFFFFFFF, int(key[1]) & 0xFFFFFFFF
+    for _ in range(10):
+        p0 = 0xD2511F53 * c[0]
+        p1 = 0xCD9E8D57 * c[2]
+        c = [((p1 >> 32) ^ c[1] ^ k0) & 0xFFFFFFFF, p1 & 0xFFFFFFFF,
+             ((p0 >> 32) ^ c[3] ^ k1) & 0xFFFFFFFF, p0 & 0xFFFFFFFF]
+        k0 = (k0 + 0x9E3779B9) & 0xFFFFFFFF
+        k1 = (k1 + 0xBB67AE85) & 0xFFFFFFFF
+    return c

@@ -1,0 +1,87 @@
+// Internal runtime of the freeform library: context, error reporting,
+// device workspace and small launch helpers shared by the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/freeform.h"
+
+namespace ff {
+
+// Workspace slots: each names one reusable device buffer owned by the context.
+enum WsSlot {
+    WS_BBOX = 0, WS_KEYS, WS_COUNTS, WS_CURSOR, WS_CELLS, WS_SCAN, WS_FLAG,
+    WS_NT_OFF, WS_NT, WS_ROWLEN, WS_ASM_FLAG,
+    WS_S0, WS_S1, WS_HS0, WS_HS1, WS_MS0, WS_MS1,            // working precision blocks
+    WS_D0, WS_D1, WS_HD0, WS_HD1, WS_MD0, WS_MD1,            // FP64 blocks of the mixed path
+    WS_GPART, WS_G, WS_C, WS_C32, WS_THETA, WS_RPART, WS_RES, WS_STATE, WS_RRSCR,
+    WS_DINV, WS_DINV32, WS_NORMS, WS_CHUNKS, WS_GCHUNKS, WS_OBJ, WS_SIGN, WS_TUNE,
+    WS_MLP0, WS_MLP1, WS_MLP2, WS_MLP3, WS_MLP4, WS_MLP5, WS_MLP6, WS_MLP7,
+    WS_COUNT
+};
+
+}  // namespace ff
+
+struct ff_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string last_error;
+    void *ws[ff::WS_COUNT] = {};
+    size_t ws_size[ff::WS_COUNT] = {};
+    void *pinned = nullptr;          // small pinned host staging area
+    size_t pinned_size = 0;
+    std::unordered_map<std::string, int> tuned;   // SpMM shape key -> variant
+    double stage_ms[5] = {0, 0, 0, 0, 0};
+};
+
+namespace ff {
+
+int set_error(ff_ctx *ctx, int code, const char *fmt, ...);
+
+// Grow-only device buffer for a workspace slot; returns nullptr on failure
+// (and records FF_ERR_OOM in the context).
+void *ws_get(ff_ctx *ctx, int slot, size_t bytes);
+void *pinned_get(ff_ctx *ctx, size_t bytes);
+
+#define FF_HIP(ctx, call)                                                              \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return ff::set_error((ctx), FF_ERR_HIP, "%s failed: %s (%s:%d)", #call,    \
+                                 hipGetErrorString(e_), __FILE__, __LINE__);           \
+    } while (0)
+
+#define FF_CHECK_LAUNCH(ctx)                                                           \
+    do {                                                                               \
+        hipError_t e_ = hipGetLastError();                                             \
+        if (e_ != hipSuccess)                                                          \
+            return ff::set_error((ctx), FF_ERR_HIP, "kernel launch failed: %s (%s:%d)", \
+                                 hipGetErrorString(e_), __FILE__, __LINE__);           \
+    } while (0)
+
+#define FF_REQUIRE(ctx, cond, ...)                                                     \
+    do {                                                                               \
+        if (!(cond)) return ff::set_error((ctx), FF_ERR_INVALID_ARG, __VA_ARGS__);     \
+    } while (0)
+
+// Device-wide exclusive scan of int64 values: out[0] = 0, out[i+1] = out[i] + in[i].
+// `in` and `out` may alias only if out == in + 1 is not required; out has len+1 entries.
+int scan_exclusive_i64(ff_ctx *ctx, const int64_t *in, int64_t *out, int64_t len);
+// Same for int32 counts into int64 offsets.
+int scan_exclusive_i32_to_i64(ff_ctx *ctx, const int32_t *in, int64_t *out, int64_t len);
+
+inline unsigned grid_for(int64_t items, int per_block) {
+    int64_t g = (items + per_block - 1) / per_block;
+    return (unsigned)(g < 1 ? 1 : g);
+}
+
+}  // namespace ff

@@ -1,0 +1,377 @@
+// Atomic-free CSR assembly of the weight-space Hessian (Prop. 1) and the RKPM
+// mass matrix (Eq. (14)) on gfx950.
+//
+//   H_kl = sum_i v_i (lambda_i + 4 mu_i) grad phi_k(X_i) . grad phi_l(X_i)
+//   M_kl = sum_i v_i [rho_i] phi_k(X_i) phi_l(X_i)
+//
+// Row k is owned by one wavefront. Its columns are the union of N(i) over the
+// quadrature points i with k in N(i). Every such column lies in the 5x5x5
+// block of cells around k's cell (k and l are both within one cell of i's
+// cell by construction of the lists), i.e. in at most 25 runs of consecutive
+// sorted node ids. The wave marks columns in an LDS bitmap over those runs;
+// the rank of a bit (prefix popcount) is the entry's slot in the row, so
+// columns come out ascending. Values are accumulated in LDS while the wave
+// walks i in ascending order, so every entry is the same ordered sum on every
+// run, and H_kl and H_lk are the same sum (bitwise symmetry).
+//
+// Compiled with -ffp-contract=off so each term is rounded exactly as written.
+#include "ff_internal.h"
+
+namespace ff {
+namespace {
+
+constexpr int kWinMax = 16384;                 // candidate nodes per row window
+constexpr int kWinWords = kWinMax / 32;
+constexpr int kRowMax = 2048;                  // entries per row
+
+struct GridI {
+    int64_t d[3];
+    int64_t ncell;
+};
+
+struct Win {
+    int64_t start[25];
+    int32_t base[26];
+    int32_t nr;
+    int32_t pad;
+};
+
+__device__ inline int wave_incl_scan_i32(int v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int t = __shfl_up(v, d, 64);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
+__device__ inline int wave_sum_i32(int v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+// Runs of candidate columns for row k; returns the window size (sum of run lengths).
+__device__ int64_t build_window(int64_t k, const int64_t *cs, GridI g, Win *win) {
+    const int lane = threadIdx.x & 63;
+    int64_t lo = 0, hi = g.ncell - 1;           // last cell c with cs[c] <= k
+    while (lo < hi) {
+        int64_t mid = (lo + hi + 1) >> 1;
+        if (cs[mid] <= k) lo = mid; else hi = mid - 1;
+    }
+    const int64_t c = lo;
+    const int64_t cx = c % g.d[0], cy = (c / g.d[0]) % g.d[1], cz = c / (g.d[0] * g.d[1]);
+    int64_t start = 0, len = 0;
+    if (lane < 25) {
+        const int64_t z = cz + lane / 5 - 2, y = cy + lane % 5 - 2;
+        if (z >= 0 && z < g.d[2] && y >= 0 && y < g.d[1]) {
+            const int64_t x0 = cx >= 2 ? cx - 2 : 0;
+            const int64_t x1 = cx + 2 < g.d[0] ? cx + 2 : g.d[0] - 1;
+            const int64_t row = (z * g.d[1] + y) * g.d[0];
+            start = cs[row + x0];
+            len = cs[row + x1 + 1] - start;
+        }
+    }
+    const int64_t lenc = len > (int64_t)kWinMax ? (int64_t)kWinMax + 1 : len;   // keep the scan in int range
+    const int incl = wave_incl_scan_i32((int)lenc);
+    const uint64_t mask = __ballot(len > 0);
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    if (len > 0) {
+        const int pos = __popcll(mask & below);
+        win->start[pos] = start;
+        win->base[pos] = incl - (int)lenc;
+    }
+    const int total = __shfl(incl, 63, 64);
+    if (lane == 0) {
+        const int nr = __popcll(mask);
+        win->nr = nr;
+        win->base[nr] = total;
+    }
+    __builtin_amdgcn_wave_barrier();
+    return total;
+}
+
+__device__ inline int local_of(int64_t l, const Win *w) {
+    int lo = 0, hi = w->nr - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (w->start[mid] <= l) lo = mid; else hi = mid - 1;
+    }
+    return w->base[lo] + (int)(l - w->start[lo]);
+}
+
+__device__ inline int64_t global_of(int x, const Win *w) {
+    int lo = 0, hi = w->nr - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (w->base[mid] <= x) lo = mid; else hi = mid - 1;
+    }
+    return w->start[lo] + (int64_t)(x - w->base[lo]);
+}
+
+// mark the columns of row k in the bitmap
+__device__ inline void mark_row(int64_t k, const int64_t *nt_off, const int2 *nt, const int64_t *off,
+                                const int32_t *ids, const Win *win, uint32_t *bm, int nwords) {
+    const int lane = threadIdx.x & 63;
+    for (int w = lane; w < nwords; w += 64) bm[w] = 0u;
+    __builtin_amdgcn_wave_barrier();
+    const int64_t a = nt_off[k], b = nt_off[k + 1];
+    for (int64_t e = a; e < b; ++e) {
+        const int64_t i = nt[e].x;
+        const int64_t f1 = off[i + 1];
+        for (int64_t f = off[i] + lane; f < f1; f += 64) {
+            const int x = local_of(ids[f], win);
+            if (x >= 0 && x < win->base[win->nr]) atomicOr(&bm[x >> 5], 1u << (x & 31));
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
+// ---------------------------------------------------------------------------
+// transpose of the neighbour relation: NT(k) = {(i, slot) : N(i)[slot] = k}, i ascending
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(256) nt_count_kernel(const int32_t *ids, int64_t total, int32_t *cnt) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < total) atomicAdd(&cnt[ids[e]], 1);
+}
+
+__global__ void __launch_bounds__(256) nt_fill_kernel(const int64_t *off, const int32_t *ids, int64_t q,
+                                                      const int64_t *nt_off, int32_t *cursor, int2 *nt) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= q) return;
+    const int64_t a = off[i], b = off[i + 1];
+    for (int64_t e = a; e < b; ++e) {
+        const int32_t k = ids[e];
+        const int64_t pos = nt_off[k] + atomicAdd(&cursor[k], 1);
+        nt[pos] = make_int2((int)i, (int)(e - a));
+    }
+}
+
+__global__ void __launch_bounds__(256) nt_sort_kernel(const int64_t *nt_off, int64_t n, int2 *nt,
+                                                      unsigned long long *empty_node) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int64_t a = nt_off[k], b = nt_off[k + 1];
+    if (a == b) atomicMin(empty_node, (unsigned long long)k);
+    for (int64_t j = a + 1; j < b; ++j) {
+        const int2 v = nt[j];
+        int64_t t = j - 1;
+        while (t >= a && nt[t].x > v.x) {
+            nt[t + 1] = nt[t];
+            --t;
+        }
+        nt[t + 1] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// symbolic pass: row lengths
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(256) sym_kernel(int64_t n, const int64_t *cs, GridI g, const int64_t *nt_off,
+                                                  const int2 *nt, const int64_t *off, const int32_t *ids,
+                                                  int32_t *rowlen, int *stats) {
+    __shared__ Win wins[4];
+    __shared__ uint32_t bms[4][kWinWords];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (k >= n) return;
+    Win *win = &wins[wv];
+    uint32_t *bm = bms[wv];
+    const int64_t W = build_window(k, cs, g, win);
+    if (W > kWinMax) {
+        if (lane == 0) {
+            rowlen[k] = 0;
+            atomicOr(&stats[0], 1);
+        }
+        return;
+    }
+    const int nwords = (int)((W + 31) >> 5);
+    mark_row(k, nt_off, nt, off, ids, win, bm, nwords);
+    int c = 0;
+    for (int w = lane; w < nwords; w += 64) c += __popc(bm[w]);
+    c = wave_sum_i32(c);
+    if (lane == 0) {
+        rowlen[k] = c;
+        atomicMax(&stats[1], c);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// numeric pass
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(256) num_kernel(int64_t n, const int64_t *cs, GridI g, const int64_t *nt_off,
+                                                  const int2 *nt, const int64_t *off, const int32_t *ids,
+                                                  const double *phi, const double *dphi, const double *vol,
+                                                  const double *lam, const double *mu, const double *rho,
+                                                  const int32_t *perm, const int64_t *row_ptr, int32_t *col,
+                                                  double *H, double *M, float *hm32, int rmax, int per_wave) {
+    extern __shared__ __align__(16) char smem[];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (k >= n) return;
+    char *base = smem + (size_t)wv * per_wave;
+    double *aH = (double *)base;
+    double *aM = aH + rmax;
+    Win *win = (Win *)(aM + rmax);
+    uint32_t *bm = (uint32_t *)(win + 1);
+    int32_t *pre = (int32_t *)(bm + kWinWords);
+
+    const int64_t W = build_window(k, cs, g, win);
+    const int nwords = (int)((W + 31) >> 5);
+    mark_row(k, nt_off, nt, off, ids, win, bm, nwords);
+
+    // exclusive prefix of popcounts over the bitmap words
+    int carry = 0;
+    for (int wb = 0; wb < nwords; wb += 64) {
+        const int w = wb + lane;
+        const int c = w < nwords ? __popc(bm[w]) : 0;
+        const int incl = wave_incl_scan_i32(c);
+        if (w < nwords) pre[w] = carry + incl - c;
+        carry += __shfl(incl, 63, 64);
+    }
+    const int len = carry;
+    const int64_t rp = row_ptr[k];
+    __builtin_amdgcn_wave_barrier();
+
+    if (col) {
+        for (int w = lane; w < nwords; w += 64) {
+            uint32_t bits = bm[w];
+            int r = pre[w];
+            while (bits) {
+                const int b = __ffs(bits) - 1;
+                bits &= bits - 1u;
+                col[rp + r] = (int32_t)global_of(w * 32 + b, win);
+                ++r;
+            }
+        }
+    }
+    for (int t = lane; t < len; t += 64) {
+        aH[t] = 0.0;
+        aM[t] = 0.0;
+    }
+    __builtin_amdgcn_wave_barrier();
+
+    const int64_t a = nt_off[k], b = nt_off[k + 1];
+    for (int64_t e = a; e < b; ++e) {
+        const int2 ent = nt[e];
+        const int64_t i = ent.x;
+        const int64_t ek = off[i] + ent.y;
+        const double gk0 = dphi[3 * ek], gk1 = dphi[3 * ek + 1], gk2 = dphi[3 * ek + 2];
+        const double pk = phi[ek];
+        const int64_t ii = perm ? (int64_t)perm[i] : i;
+        const double wi = vol[ii] * (lam[ii] + 4.0 * mu[ii]);
+        const double mi = rho ? vol[ii] * rho[ii] : vol[ii];
+        const int64_t f1 = off[i + 1];
+        for (int64_t f = off[i] + lane; f < f1; f += 64) {
+            const int x = local_of(ids[f], win);
+            if (x < 0 || x >= win->base[win->nr]) continue;
+            const uint32_t word = bm[x >> 5];
+            const int r = pre[x >> 5] + __popc(word & ((1u << (x & 31)) - 1u));
+            const double dot = ((gk0 * dphi[3 * f]) + (gk1 * dphi[3 * f + 1])) + (gk2 * dphi[3 * f + 2]);
+            aH[r] += wi * dot;
+            aM[r] += mi * (pk * phi[f]);
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    for (int t = lane; t < len; t += 64) {
+        const double h = aH[t], m = aM[t];
+        H[rp + t] = h;
+        M[rp + t] = m;
+        if (hm32) {
+            hm32[2 * (rp + t)] = (float)h;
+            hm32[2 * (rp + t) + 1] = (float)m;
+        }
+    }
+}
+
+}  // namespace
+}  // namespace ff
+
+using namespace ff;
+
+extern "C" int assemble_HM(ff_ctx *ctx, int64_t n, int64_t q, const int64_t *nbr_off, const int32_t *nbr_id,
+                           const double *phi, const double *dphi, const double *vol, const double *lam,
+                           const double *mu, const double *rho, const int32_t *perm, const ff_grid *grid,
+                           const int64_t *cell_start, int64_t *row_ptr, int32_t *col, double *H, double *M,
+                           float *hm32, int64_t nnz_cap, int64_t *nnz) {
+    if (!ctx) return FF_ERR_INVALID_ARG;
+    FF_REQUIRE(ctx, n > 0 && q > 0 && n < INT32_MAX && q < INT32_MAX, "bad sizes n=%lld q=%lld", (long long)n,
+               (long long)q);
+    FF_REQUIRE(ctx, nbr_off && nbr_id && phi && dphi && vol && lam && mu && grid && cell_start && row_ptr && nnz,
+               "required pointer is NULL");
+    FF_REQUIRE(ctx, (col == nullptr) == (H == nullptr) && (col == nullptr) == (M == nullptr),
+               "col, H and M must be all given or all NULL");
+    FF_REQUIRE(ctx, grid->n_cells == grid->dims[0] * grid->dims[1] * grid->dims[2] && grid->n_cells > 0,
+               "inconsistent grid");
+    FF_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+
+    int64_t total = 0;
+    int64_t *host = (int64_t *)pinned_get(ctx, 4096);
+    if (!host) return FF_ERR_OOM;
+    FF_HIP(ctx, hipMemcpyAsync(host, nbr_off + q, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    FF_HIP(ctx, hipStreamSynchronize(st));
+    total = host[0];
+
+    // transpose
+    int32_t *cnt = (int32_t *)ws_get(ctx, WS_COUNTS, (size_t)n * sizeof(int32_t));
+    int32_t *cursor = (int32_t *)ws_get(ctx, WS_CURSOR, (size_t)n * sizeof(int32_t));
+    int64_t *nt_off = (int64_t *)ws_get(ctx, WS_NT_OFF, (size_t)(n + 1) * sizeof(int64_t));
+    int2 *nt = (int2 *)ws_get(ctx, WS_NT, (size_t)(total > 0 ? total : 1) * sizeof(int2));
+    int32_t *rowlen = (int32_t *)ws_get(ctx, WS_ROWLEN, (size_t)n * sizeof(int32_t));
+    int *stats = (int *)ws_get(ctx, WS_ASM_FLAG, 64);
+    if (!cnt || !cursor || !nt_off || !nt || !rowlen || !stats) return FF_ERR_OOM;
+    unsigned long long *empty_node = (unsigned long long *)(stats + 4);
+    FF_HIP(ctx, hipMemsetAsync(cnt, 0, (size_t)n * sizeof(int32_t), st));
+    FF_HIP(ctx, hipMemsetAsync(cursor, 0, (size_t)n * sizeof(int32_t), st));
+    FF_HIP(ctx, hipMemsetAsync(stats, 0, 16, st));
+    FF_HIP(ctx, hipMemsetAsync(empty_node, 0xff, 8, st));
+    hipLaunchKernelGGL(nt_count_kernel, dim3(grid_for(total, 256)), dim3(256), 0, st, nbr_id, total, cnt);
+    FF_CHECK_LAUNCH(ctx);
+    int rc = scan_exclusive_i32_to_i64(ctx, cnt, nt_off, n);
+    if (rc) return rc;
+    hipLaunchKernelGGL(nt_fill_kernel, dim3(grid_for(q, 256)), dim3(256), 0, st, nbr_off, nbr_id, q, nt_off, cursor,
+                       nt);
+    FF_CHECK_LAUNCH(ctx);
+    hipLaunchKernelGGL(nt_sort_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, nt_off, n, nt, empty_node);
+    FF_CHECK_LAUNCH(ctx);
+
+    GridI g;
+    for (int a = 0; a < 3; ++a) g.d[a] = grid->dims[a];
+    g.ncell = grid->n_cells;
+    hipLaunchKernelGGL(sym_kernel, dim3(grid_for(n, 4)), dim3(256), 0, st, n, cell_start, g, nt_off, nt, nbr_off,
+                       nbr_id, rowlen, stats);
+    FF_CHECK_LAUNCH(ctx);
+    rc = scan_exclusive_i32_to_i64(ctx, rowlen, row_ptr, n);
+    if (rc) return rc;
+    FF_HIP(ctx, hipMemcpyAsync(host, row_ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    FF_HIP(ctx, hipMemcpyAsync(host + 1, stats, 16, hipMemcpyDeviceToHost, st));
+    FF_HIP(ctx, hipMemcpyAsync(host + 3, empty_node, 8, hipMemcpyDeviceToHost, st));
+    FF_HIP(ctx, hipStreamSynchronize(st));
+    const int *hs = (const int *)(host + 1);
+    const unsigned long long en = (unsigned long long)host[3];
+    if (en != ~0ull)
+        return set_error(ctx, FF_ERR_INVALID_ARG, "node %llu has no quadrature point in its support", en);
+    FF_REQUIRE(ctx, hs[0] == 0, "a row's candidate window exceeds %d nodes; decrease h", kWinMax);
+    FF_REQUIRE(ctx, hs[1] <= kRowMax, "a row has %d entries (limit %d); decrease h", hs[1], kRowMax);
+    *nnz = host[0];
+    if (!col) return FF_OK;
+    if (nnz_cap < host[0])
+        return set_error(ctx, FF_ERR_CAPACITY, "CSR needs %lld entries, capacity %lld", (long long)host[0],
+                         (long long)nnz_cap);
+
+    const int rmax = ((hs[1] + 63) / 64) * 64;
+    const int per_wave = (int)(((size_t)2 * rmax * sizeof(double) + sizeof(Win) + kWinWords * 8 + 255) & ~255);
+    int waves = 4;
+    while (waves > 1 && waves * per_wave > 64 * 1024) waves >>= 1;
+    const size_t shmem = (size_t)waves * per_wave;
+    hipLaunchKernelGGL(num_kernel, dim3(grid_for(n, waves)), dim3(64 * waves), shmem, st, n, cell_start, g, nt_off,
+                       nt, nbr_off, nbr_id, phi, dphi, vol, lam, mu, rho, perm, row_ptr, col, H, M, hm32, rmax,
+                       per_wave);
+    FF_CHECK_LAUNCH(ctx);
+    return FF_OK;
+}

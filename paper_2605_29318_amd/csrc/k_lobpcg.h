@@ -1,0 +1,18 @@
+// Row-chunk descriptors shared by the eigensolver kernels and their driver.
+#pragma once
+#include <cstdint>
+
+namespace ff {
+namespace lob {
+
+// A run of rows of one object: resid/update work unit (<= 256 rows) or
+// Gram partial-sum unit (<= 2048 rows). Chunks never straddle objects.
+struct UChunk {
+    int64_t r0;
+    int32_t len;
+    int32_t obj;
+};
+typedef UChunk GChunk;
+
+}  // namespace lob
+}  // namespace ff

@@ -1,0 +1,346 @@
+"""Python binding of libfreeform.so (the C ABI declared in include/freeform.h).
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels. Device arrays are torch tensors on a ROCm device; the functions
+allocate the outputs with torch and pass raw pointers plus sizes. The names
+follow the C entry points.
+
+The library must be built (``python -m paper_2605_29318_amd.build``); loading
+fails loudly if it is missing - there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfreeform.so")
+
+FF_OK = 0
+FF_ERR_INVALID_ARG = -1
+FF_ERR_OOM = -2
+FF_ERR_HIP = -3
+FF_ERR_CAPACITY = -4
+FF_ERR_SINGULAR_MOMENT = -5
+FF_ERR_NOT_CONVERGED = -6
+FF_ERR_BREAKDOWN = -7
+
+
+class FFError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"freeform error {code}: {msg}")
+        self.code = code
+        self.msg = msg
+
+
+class ff_grid(ctypes.Structure):
+    _fields_ = [("origin", ctypes.c_double * 3), ("h", ctypes.c_double),
+                ("dims", ctypes.c_int64 * 3), ("n_cells", ctypes.c_int64)]
+
+
+class ff_eig_params(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int), ("block", ctypes.c_int), ("precision", ctypes.c_int),
+                ("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("precond", ctypes.c_int),
+                ("seed", ctypes.c_uint64), ("check_every", ctypes.c_int), ("use_graph", ctypes.c_int),
+                ("refresh_every", ctypes.c_int)]
+
+
+class ff_eig_info(ctypes.Structure):
+    _fields_ = [("iters_fp32", ctypes.c_int), ("iters_fp64", ctypes.c_int), ("converged", ctypes.c_int),
+                ("restarts", ctypes.c_int), ("max_resid", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+
+_lib = None
+vp = ctypes.c_void_p
+i64 = ctypes.c_int64
+i32 = ctypes.c_int
+f64 = ctypes.c_double
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise FileNotFoundError(f"{LIB_PATH} is not built; run python -m paper_2605_29318_amd.build")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    sig = {
+        "ff_ctx_create": (i32, [P(vp), i32, vp]),
+        "ff_ctx_destroy": (None, [vp]),
+        "ff_last_error": (ctypes.c_char_p, [vp]),
+        "ff_ctx_stage_times": (i32, [vp, P(f64), P(f64), P(f64), P(f64), P(f64)]),
+        "build_neighbors": (i32, [vp, i64, vp, i64, vp, f64, P(ff_grid), vp, vp, vp, i64, vp, vp, i64,
+                                  P(i64)]),
+        "rkpm_shape": (i32, [vp, i64, vp, i64, vp, vp, vp, i64, f64, i32, vp, vp, vp, P(i64)]),
+        "assemble_HM": (i32, [vp, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, P(ff_grid), vp, vp, vp,
+                              vp, vp, vp, i64, P(i64)]),
+        "eigenmodes": (i32, [vp, i64, vp, vp, vp, vp, vp, P(ff_eig_params), vp, vp, vp, vp,
+                             P(ff_eig_info)]),
+        "eigenmodes_batched": (i32, [vp, i32, vp, vp, vp, vp, vp, vp, P(ff_eig_params), vp, vp, vp, vp,
+                                     vp]),
+        "spmm_hm": (i32, [vp, i64, vp, vp, vp, vp, vp, i32, i32, vp, i64, vp, vp, i64, i32]),
+        "spmm_autotune": (i32, [vp, i64, vp, vp, vp, vp, vp, i32, i32, ctypes.c_char_p, P(i32), P(f64)]),
+        "gram_hm": (i32, [vp, i64, i32, i32, vp, vp, vp, i64, vp]),
+        "rayleigh_ritz": (i32, [vp, i32, i32, vp, f64, vp, vp, P(i32)]),
+        "spmm_variant_count": (i32, []),
+        "spmm_variant_name": (ctypes.c_char_p, [i32]),
+        "rand_block": (i32, [vp, i64, i32, ctypes.c_uint64, vp]),
+        "philox4x32_10": (i32, [vp, i32, vp, vp, vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def _p(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """A library context bound to a device and the current torch stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        rc = lib().ff_ctx_create(ctypes.byref(h), device, ctypes.c_void_p(stream.cuda_stream))
+        if rc != 0:
+            raise FFError(rc, "ff_ctx_create failed")
+        self.h = h
+
+    def check(self, rc: int):
+        if rc != 0:
+            raise FFError(rc, lib().ff_last_error(self.h).decode())
+
+    def close(self):
+        if self.h:
+            lib().ff_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class Neighbors:
+    grid: ff_grid
+    perm: "object"
+    xyz_sorted: "object"
+    cell_start: "object"
+    nbr_off: "object"
+    nbr_id: "object"
+
+
+def build_neighbors(ctx: Context, xyz, h: float, qxyz=None) -> Neighbors:
+    import torch
+    dev = xyz.device
+    xyz = xyz.contiguous()
+    n = xyz.shape[0]
+    q = n if qxyz is None else qxyz.shape[0]
+    grid = ff_grid()
+    perm = torch.empty(n, dtype=torch.int32, device=dev)
+    xs = torch.empty((n, 3), dtype=torch.float64, device=dev)
+    off = torch.empty(q + 1, dtype=torch.int64, device=dev)
+    tot = ctypes.c_int64()
+    L = lib()
+    ctx.check(L.build_neighbors(ctx.h, n, _p(xyz), q, _p(qxyz), float(h), ctypes.byref(grid), _p(perm), _p(xs),
+                                None, 0, _p(off), None, 0, ctypes.byref(tot)))
+    cs = torch.empty(grid.n_cells + 1, dtype=torch.int64, device=dev)
+    ids = torch.empty(max(tot.value, 1), dtype=torch.int32, device=dev)
+    ctx.check(L.build_neighbors(ctx.h, n, _p(xyz), q, _p(qxyz), float(h), ctypes.byref(grid), _p(perm), _p(xs),
+                                _p(cs), cs.numel(), _p(off), _p(ids), ids.numel(), ctypes.byref(tot)))
+    return Neighbors(grid, perm, xs, cs, off, ids[:tot.value])
+
+
+def rkpm_shape(ctx: Context, xyz_sorted, nbr_off, nbr_id, h: float, qxyz=None, kernel: int = 0,
+               features: bool = False):
+    import torch
+    dev = xyz_sorted.device
+    n = xyz_sorted.shape[0]
+    q = nbr_off.shape[0] - 1
+    tot = nbr_id.shape[0]
+    phi = torch.empty(max(tot, 1), dtype=torch.float64, device=dev)
+    dphi = torch.empty((max(tot, 1), 3), dtype=torch.float64, device=dev)
+    feat = torch.empty((q, 8), dtype=torch.float32, device=dev) if features else None
+    bad = ctypes.c_int64(-1)
+    rc = lib().rkpm_shape(ctx.h, n, _p(xyz_sorted), q, _p(qxyz), _p(nbr_off), _p(nbr_id), tot, float(h), kernel,
+                          _p(phi), _p(dphi), _p(feat), ctypes.byref(bad))
+    if rc != 0:
+        e = FFError(rc, lib().ff_last_error(ctx.h).decode())
+        e.bad_index = bad.value
+        raise e
+    return phi[:tot], dphi[:tot], feat
+
+
+def assemble_HM(ctx: Context, n: int, nbr_off, nbr_id, phi, dphi, vol, lam, mu, grid: ff_grid, cell_start,
+                rho=None, perm=None, fp32: bool = True):
+    import torch
+    dev = phi.device
+    q = nbr_off.shape[0] - 1
+    row_ptr = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    nnz = ctypes.c_int64()
+    L = lib()
+    args = (ctx.h, n, q, _p(nbr_off), _p(nbr_id), _p(phi), _p(dphi), _p(vol), _p(lam), _p(mu), _p(rho), _p(perm),
+            ctypes.byref(grid), _p(cell_start), _p(row_ptr))
+    ctx.check(L.assemble_HM(*args, None, None, None, None, 0, ctypes.byref(nnz)))
+    m = nnz.value
+    col = torch.empty(max(m, 1), dtype=torch.int32, device=dev)
+    H = torch.empty(max(m, 1), dtype=torch.float64, device=dev)
+    M = torch.empty(max(m, 1), dtype=torch.float64, device=dev)
+    hm32 = torch.empty((max(m, 1), 2), dtype=torch.float32, device=dev) if fp32 else None
+    ctx.check(L.assemble_HM(*args, _p(col), _p(H), _p(M), _p(hm32), m, ctypes.byref(nnz)))
+    return row_ptr, col[:m], H[:m], M[:m], (hm32[:m] if fp32 else None)
+
+
+def _params(k, block, precision, tol, max_iter, precond, seed, check_every, use_graph, refresh_every):
+    return ff_eig_params(k, block, precision, tol, max_iter, precond, seed, check_every, int(use_graph),
+                         refresh_every)
+
+
+def eigenmodes(ctx: Context, n: int, row_ptr, col, H, M, hm32, k: int, block: int = 0, precision: int = 1,
+               tol: float = 1e-6, max_iter: int = 5000, precond: int = 1, seed: int = 0, X0=None,
+               check_every: int = 10, use_graph: bool = False, refresh_every: int = 0, allow_unconverged=False):
+    import torch
+    p = _params(k, block, precision, tol, max_iter, precond, seed, check_every, use_graph, refresh_every)
+    lam = np.zeros(k)
+    res = np.zeros(k)
+    W = torch.empty((n, k), dtype=torch.float64, device=H.device)
+    info = ff_eig_info()
+    rc = lib().eigenmodes(ctx.h, n, _p(row_ptr), _p(col), _p(H), _p(M), _p(hm32), ctypes.byref(p),
+                          _p(X0), lam.ctypes.data_as(vp), _p(W), res.ctypes.data_as(vp), ctypes.byref(info))
+    out = dict(iters_fp32=info.iters_fp32, iters_fp64=info.iters_fp64, converged=info.converged,
+               restarts=info.restarts, max_resid=info.max_resid, seconds=info.seconds, status=rc)
+    if rc != 0 and not (allow_unconverged and rc == FF_ERR_NOT_CONVERGED):
+        ctx.check(rc)
+    return lam, W, res, out
+
+
+def eigenmodes_batched(ctx: Context, obj_row_off, row_ptr, col, H, M, hm32, k: int, block: int = 0,
+                       precision: int = 1, tol: float = 1e-6, max_iter: int = 5000, precond: int = 1,
+                       seed: int = 0, X0=None, check_every: int = 10, use_graph: bool = False,
+                       refresh_every: int = 0, allow_unconverged=False):
+    import torch
+    off = np.ascontiguousarray(obj_row_off, dtype=np.int64)
+    n_obj = len(off) - 1
+    N = int(off[-1])
+    p = _params(k, block, precision, tol, max_iter, precond, seed, check_every, use_graph, refresh_every)
+    lam = np.zeros((n_obj, k))
+    res = np.zeros((n_obj, k))
+    W = torch.empty((N, k), dtype=torch.float64, device=H.device)
+    info = (ff_eig_info * n_obj)()
+    rc = lib().eigenmodes_batched(ctx.h, n_obj, off.ctypes.data_as(vp), _p(row_ptr), _p(col), _p(H), _p(M),
+                                  _p(hm32), ctypes.byref(p), _p(X0), lam.ctypes.data_as(vp), _p(W),
+                                  res.ctypes.data_as(vp), ctypes.cast(info, vp))
+    infos = [dict(iters_fp32=i.iters_fp32, iters_fp64=i.iters_fp64, converged=i.converged,
+                  max_resid=i.max_resid, seconds=i.seconds) for i in info]
+    if rc != 0 and not (allow_unconverged and rc == FF_ERR_NOT_CONVERGED):
+        ctx.check(rc)
+    return lam, W, res, infos, rc
+
+
+def spmm_hm(ctx: Context, row_ptr, col, H, M, hm32, Y, precision: int, variant: int = -1, out=None):
+    import torch
+    n, m = Y.shape
+    if out is None:
+        HY = torch.empty_like(Y)
+        MY = torch.empty_like(Y)
+    else:
+        HY, MY = out
+    ctx.check(lib().spmm_hm(ctx.h, n, _p(row_ptr), _p(col), _p(H), _p(M), _p(hm32), precision, m, _p(Y),
+                            Y.stride(0), _p(HY), _p(MY), HY.stride(0), variant))
+    return HY, MY
+
+
+def spmm_autotune(ctx: Context, n: int, row_ptr, col, H, M, hm32, precision: int, m: int,
+                  cache_path: Optional[str] = None):
+    best = ctypes.c_int()
+    ms = ctypes.c_double()
+    ctx.check(lib().spmm_autotune(ctx.h, n, _p(row_ptr), _p(col), _p(H), _p(M), _p(hm32), precision, m,
+                                  None if cache_path is None else cache_path.encode(), ctypes.byref(best),
+                                  ctypes.byref(ms)))
+    return best.value, ms.value
+
+
+def gram_hm(ctx: Context, S, HS, MS, w: int = None):
+    """G[0] = S^T HS, G[1] = S^T MS over the first w columns (FP64 result)."""
+    import torch
+    n = S.shape[0]
+    w = S.shape[1] if w is None else w
+    precision = 1 if S.dtype == torch.float32 else 0
+    G = torch.empty((2, w, w), dtype=torch.float64, device=S.device)
+    ctx.check(lib().gram_hm(ctx.h, n, w, precision, _p(S), _p(HS), _p(MS), S.stride(0), _p(G)))
+    return G
+
+
+def rayleigh_ritz(ctx: Context, G, m: int, tau: float = 1e-13):
+    import torch
+    w = G.shape[1]
+    C = torch.empty((w, m), dtype=torch.float64, device=G.device)
+    theta = torch.empty(m, dtype=torch.float64, device=G.device)
+    kept = ctypes.c_int()
+    ctx.check(lib().rayleigh_ritz(ctx.h, w, m, _p(G.contiguous()), tau, _p(C), _p(theta), ctypes.byref(kept)))
+    return theta, C, kept.value
+
+
+def spmm_variant_names():
+    L = lib()
+    return [L.spmm_variant_name(i).decode() for i in range(L.spmm_variant_count())]
+
+
+def rand_block(ctx: Context, n: int, m: int, seed: int, device="cuda"):
+    import torch
+    out = torch.empty((n, m), dtype=torch.float64, device=device)
+    ctx.check(lib().rand_block(ctx.h, n, m, seed, _p(out)))
+    return out
+
+
+def philox4x32_10(ctx: Context, ctr, key):
+    """ctr: uint32 tensor (count, 4), key: (count, 2) on the device; returns (count, 4)."""
+    import torch
+    out = torch.empty_like(ctr)
+    ctx.check(lib().philox4x32_10(ctx.h, ctr.shape[0], _p(ctr), _p(key), _p(out)))
+    return out
+
+
+# ----------------------------------------------------------------------------
+# convenience: the whole path for one synthetic cloud
+# ----------------------------------------------------------------------------
+
+@dataclass
+class Assembled:
+    n: int
+    h: float
+    nb: Neighbors
+    phi: "object"
+    dphi: "object"
+    feat: "object"
+    row_ptr: "object"
+    col: "object"
+    H: "object"
+    M: "object"
+    hm32: "object"
+
+
+def assemble_cloud(ctx: Context, xyz, vol, lam, mu, h: float, rho=None, features: bool = False,
+                   kernel: int = 0) -> Assembled:
+    """build_neighbors -> rkpm_shape -> assemble_HM; per-point arrays in original order."""
+    nb = build_neighbors(ctx, xyz, h)
+    phi, dphi, feat = rkpm_shape(ctx, nb.xyz_sorted, nb.nbr_off, nb.nbr_id, h, kernel=kernel, features=features)
+    n = xyz.shape[0]
+    rp, col, H, M, hm32 = assemble_HM(ctx, n, nb.nbr_off, nb.nbr_id, phi, dphi, vol, lam, mu, nb.grid,
+                                      nb.cell_start, rho=rho, perm=nb.perm)
+    return Assembled(n, h, nb, phi, dphi, feat, rp, col, H, M, hm32)

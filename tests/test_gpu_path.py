@@ -1,0 +1,246 @@
+"""GPU parity of the HIP path against the FP64 CPU oracle, through the C ABI.
+
+Integer outputs (permutation, cell starts, neighbour lists, CSR pattern) must
+be bit-exact; FP64 values within 1e-12 of the oracle relative to their scale;
+eigenpairs to the eigenvalue, angle and residual bounds stated per test.
+"""
+import numpy as np
+import pytest
+
+from paper_2605_29318_amd import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ff():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2605_29318_amd import freeform
+    freeform.lib()
+    return freeform
+
+
+@pytest.fixture(scope="module")
+def ctx(ff):
+    c = ff.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a, dt=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def _slab():
+    c = synth.random_cloud(1700, seed=9)
+    c.xyz[:, 2] *= 0.05
+    return c
+
+
+CLOUDS = {
+    "cube1k": lambda: synth.cube_lattice(),
+    "cube_unjittered": lambda: synth.cube_lattice(m=9, jitter=0.0, seed=1),
+    "random3k_hetero": lambda: synth.random_cloud(3000, seed=5, hetero=True),
+    "spheres4k": lambda: synth.sphere_union(n=4000, seed=2, mc_samples=200_000),
+    "slab1700": _slab,
+}
+
+
+@pytest.fixture(scope="module", params=sorted(CLOUDS))
+def case(request, oracle, ctx, ff):
+    c = CLOUDS[request.param]()
+    P = oracle.pipeline(c)
+    xyz = dev(c.xyz)
+    A = ff.assemble_cloud(ctx, xyz, dev(c.vol), dev(c.lam), dev(c.mu), c.h)
+    torch.cuda.synchronize()
+    return request.param, c, P, A
+
+
+def test_binning_bitexact(case):
+    name, c, P, A = case
+    g = A.nb.grid
+    assert tuple(g.dims) == tuple(P.dims)
+    assert tuple(g.origin) == tuple(P.origin)
+    assert np.array_equal(host(A.nb.perm), P.perm)
+    assert np.array_equal(host(A.nb.cell_start), P.cell_start)
+    assert np.array_equal(host(A.nb.xyz_sorted), P.xyz)
+
+
+def test_neighbors_bitexact(case):
+    name, c, P, A = case
+    assert np.array_equal(host(A.nb.nbr_off), P.nbr_off)
+    assert np.array_equal(host(A.nb.nbr_id), P.nbr_id)
+
+
+def test_shape_functions(case):
+    name, c, P, A = case
+    phi, dphi = host(A.phi), host(A.dphi)
+    assert np.abs(phi - P.phi).max() <= 1e-12
+    assert np.abs(dphi - P.dphi).max() <= 1e-12 * np.abs(P.dphi).max()
+
+
+def test_assembly(case):
+    name, c, P, A = case
+    assert np.array_equal(host(A.row_ptr), P.row_ptr)
+    assert np.array_equal(host(A.col), P.col)
+    H, M = host(A.H), host(A.M)
+    assert np.abs(H - P.H).max() <= 1e-12 * np.abs(P.H).max()
+    assert np.abs(M - P.M).max() <= 1e-12 * np.abs(P.M).max()
+    hm = host(A.hm32)
+    assert np.array_equal(hm[:, 0], H.astype(np.float32))
+    assert np.array_equal(hm[:, 1], M.astype(np.float32))
+
+
+def test_assembly_bitwise_symmetric_and_deterministic(case, ctx, ff):
+    name, c, P, A = case
+    import scipy.sparse as sp
+    n = c.n
+    Hs = sp.csr_matrix((host(A.H), host(A.col), host(A.row_ptr)), shape=(n, n))
+    assert (Hs != Hs.T).nnz == 0
+    B = ff.assemble_cloud(ctx, dev(c.xyz), dev(c.vol), dev(c.lam), dev(c.mu), c.h)
+    assert torch.equal(A.H, B.H) and torch.equal(A.M, B.M) and torch.equal(A.col, B.col)
+
+
+def test_separate_quadrature_points(oracle, ctx, ff):
+    c = synth.random_cloud(2000, seed=14)
+    rng = np.random.default_rng(3)
+    q = rng.uniform(-0.1, 1.1, size=(1500, 3))
+    nb = ff.build_neighbors(ctx, dev(c.xyz), c.h, qxyz=dev(q))
+    perm, cs, origin, dims = oracle.bin_nodes(c.xyz, c.h)
+    xs = np.ascontiguousarray(c.xyz[perm])
+    off, ids = oracle.neighbors(q, xs, c.h, origin, dims, cs)
+    assert np.array_equal(host(nb.nbr_off), off)
+    assert np.array_equal(host(nb.nbr_id), ids)
+    # points with too few neighbours make the moment matrix singular: report the first
+    with pytest.raises(ff.FFError) as ei:
+        ff.rkpm_shape(ctx, nb.xyz_sorted, nb.nbr_off, nb.nbr_id, c.h, qxyz=dev(q))
+    cnt = np.diff(off)
+    if (cnt >= 4).all():
+        pytest.skip("no singular point in this draw")
+    assert ei.value.code == ff.FF_ERR_SINGULAR_MOMENT
+
+
+def test_singular_moment_index(ctx, ff):
+    xs = dev(np.array([[0.0, 0.0, 0.0], [0.1, 0.0, 0.0], [0.2, 0.0, 0.0], [0.9, 0.9, 0.9]]))
+    nb = ff.build_neighbors(ctx, xs, 0.25)
+    with pytest.raises(ff.FFError) as ei:
+        ff.rkpm_shape(ctx, nb.xyz_sorted, nb.nbr_off, nb.nbr_id, 0.25)
+    assert ei.value.code == ff.FF_ERR_SINGULAR_MOMENT
+    assert ei.value.bad_index == 0
+
+
+def test_invalid_arguments(ctx, ff):
+    bad = dev(np.array([[0.0, np.nan, 0.0], [1.0, 1.0, 1.0]]))
+    with pytest.raises(ff.FFError) as ei:
+        ff.build_neighbors(ctx, bad, 0.5)
+    assert ei.value.code == ff.FF_ERR_INVALID_ARG
+    with pytest.raises(ff.FFError):
+        ff.build_neighbors(ctx, dev(np.zeros((4, 3))), -1.0)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("m", [8, 16, 24, 32, 64])
+def test_spmm(oracle, ctx, ff, precision, m):
+    c = synth.random_cloud(2500, seed=21, hetero=True)
+    P = oracle.pipeline(c)
+    A = ff.assemble_cloud(ctx, dev(c.xyz), dev(c.vol), dev(c.lam), dev(c.mu), c.h)
+    rng = np.random.default_rng(m)
+    Y = rng.standard_normal((c.n, m))
+    dt = torch.float32 if precision else torch.float64
+    refH = oracle.spmm(P.row_ptr, P.col, P.H, Y)
+    refM = oracle.spmm(P.row_ptr, P.col, P.M, Y)
+    absH = oracle.spmm(P.row_ptr, P.col, np.abs(P.H), np.abs(Y))
+    absM = oracle.spmm(P.row_ptr, P.col, np.abs(P.M), np.abs(Y))
+    for v in range(len(ff.spmm_variant_names())):
+        HY, MY = ff.spmm_hm(ctx, A.row_ptr, A.col, A.H, A.M, A.hm32, dev(Y, dt), precision, variant=v)
+        eps = 2e-6 if precision else 1e-13
+        assert np.all(np.abs(host(HY) - refH) <= eps * absH + 1e-300)
+        assert np.all(np.abs(host(MY) - refM) <= eps * absM + 1e-300)
+
+
+def test_philox_known_answers(ctx, ff):
+    """Known-answer vectors of Philox-4x32-10 (Salmon et al., SC'11, Random123 distribution)."""
+    import os
+    rows = []
+    with open(os.path.join(os.path.dirname(__file__), "golden", "philox4x32_10_kat.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                rows.append([int(x, 16) for x in line.split()])
+    rows = np.array(rows, dtype=np.uint64)
+    ctr = dev(rows[:, 0:4].astype(np.int64).astype(np.uint32).view(np.int32), torch.int32)
+    key = dev(rows[:, 4:6].astype(np.int64).astype(np.uint32).view(np.int32), torch.int32)
+    out = host(ff.philox4x32_10(ctx, ctr, key)).view(np.uint32)
+    assert np.array_equal(out.astype(np.uint64), rows[:, 6:10])
+
+
+def _check_modes(oracle, P, lam, W, res, k, rel_tol, sin_tol, resid_tol):
+    H, M = P.Hs(), P.Ms()
+    wd, Vd = oracle.dense_eigh(H, M, k + 4)
+    assert np.abs(lam[1:] - wd[1:k]).max() / wd[1:k].min() <= rel_tol
+    assert abs(lam[0]) <= rel_tol * wd[1]
+    assert res.max() <= resid_tol
+    # residuals recomputed on the CPU with the oracle's matrices
+    r_cpu = oracle.residuals(H, M, lam, W)
+    assert r_cpu.max() <= 2 * resid_tol
+    # M-orthonormal
+    G = W.T @ (M @ W)
+    assert np.abs(G - np.eye(k)).max() <= 1e-6
+    kk = oracle.cluster_safe_k(wd, k)
+    if kk > 0:
+        s = oracle.subspace_sines(Vd[:, :kk], W[:, :kk], M)
+        assert s.max() <= sin_tol
+    # sign rule
+    idx = np.argmax(np.abs(W), axis=0)
+    assert np.all(W[idx, np.arange(k)] > 0)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_eigenmodes_cube(oracle, ctx, ff, precision):
+    c = synth.cube_lattice()
+    P = oracle.pipeline(c)
+    A = ff.assemble_cloud(ctx, dev(c.xyz), dev(c.vol), dev(c.lam), dev(c.mu), c.h)
+    k = 8
+    lam, W, res, info = ff.eigenmodes(ctx, c.n, A.row_ptr, A.col, A.H, A.M, A.hm32, k=k, precision=precision,
+                                      tol=1e-8 if precision == 0 else 1e-6, max_iter=4000)
+    _check_modes(oracle, P, lam, host(W), res, k, 1e-8 if precision == 0 else 1e-5,
+                 1e-6 if precision == 0 else 1e-3, 1e-8 if precision == 0 else 1e-6)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_eigenmodes_random_hetero(oracle, ctx, ff, precision):
+    """i.i.d. random particles give cond(M) ~ 2e7: a backward-error residual of 1e-6
+    leaves ~3e-4 eigenvalue error even in exact FP64, so parity is checked at 1e-8
+    (where the oracle's own solve is accurate to ~4e-8)."""
+    c = synth.random_cloud(2500, seed=33, hetero=True)
+    P = oracle.pipeline(c)
+    A = ff.assemble_cloud(ctx, dev(c.xyz), dev(c.vol), dev(c.lam), dev(c.mu), c.h)
+    k = 16
+    lam, W, res, info = ff.eigenmodes(ctx, c.n, A.row_ptr, A.col, A.H, A.M, A.hm32, k=k, precision=precision,
+                                      tol=1e-8, max_iter=8000)
+    _check_modes(oracle, P, lam, host(W), res, k, 1e-5, 1e-3, 1e-8)
+
+
+def test_eigenmodes_given_start_block(oracle, ctx, ff):
+    c = synth.cube_lattice()
+    P = oracle.pipeline(c)
+    A = ff.assemble_cloud(ctx, dev(c.xyz), dev(c.vol), dev(c.lam), dev(c.mu), c.h)
+    X0 = synth.initial_block(c.n, 8, seed=4)
+    perm = P.perm
+    lam, W, res, info = ff.eigenmodes(ctx, c.n, A.row_ptr, A.col, A.H, A.M, A.hm32, k=8, precision=0, tol=1e-8,
+                                      X0=dev(X0[perm]))
+    _check_modes(oracle, P, lam, host(W), res, 8, 1e-8, 1e-6, 1e-8)
+
+
+def test_not_converged_still_returns(ctx, ff):
+    c = synth.cube_lattice()
+    A = ff.assemble_cloud(ctx, dev(c.xyz), dev(c.vol), dev(c.lam), dev(c.mu), c.h)
+    lam, W, res, info = ff.eigenmodes(ctx, c.n, A.row_ptr, A.col, A.H, A.M, A.hm32, k=8, precision=0, tol=1e-12,
+                                      max_iter=3, allow_unconverged=True)
+    assert info["status"] == ff.FF_ERR_NOT_CONVERGED
+    assert np.all(np.isfinite(lam)) and np.all(res > 0)
