@@ -310,31 +310,43 @@ __global__ void __launch_bounds__(256) resid_kernel(const UChunk *chunks, const 
     }
 }
 
-// r_j = ||R_j|| / ((||H|| + |theta_j| ||M||) ||x_j||); status: 0 active, 1 converged, 2 stagnated
-__global__ void __launch_bounds__(64) norms_kernel(int *obj_status, const int *ufirst, const int *ucount,
-                                                   const double *rpart, int m, int k, const double *theta,
-                                                   const double *norms, double tol, int stall_limit,
-                                                   double *res, double *track) {
+// r_j = ||R_j|| / ((||H|| + |theta_j| ||M||) ||x_j||); status: 0 active, 1 converged, 2 stagnated.
+// 1024 threads: thread (part, q) sums the chunks c = part (mod 16) of output q in
+// ascending order, then the 16 parts are added in a fixed order.
+__global__ void __launch_bounds__(1024) norms_kernel(int *obj_status, const int *cfirst, const int *ccount,
+                                                     const double *rpart, int m, int k, const double *theta,
+                                                     const double *norms, double tol, int stall_limit,
+                                                     double *res, double *track) {
     const int o = blockIdx.x;
     if (obj_status[o] != 0) return;
-    const int c = threadIdx.x;
-    double rj = 0.0;
-    if (c < m) {
+    __shared__ double part[16][128];
+    __shared__ double rj[64];
+    const int q = threadIdx.x & 127, pp = threadIdx.x >> 7;   // 8 parts of 128 outputs
+    const int c0 = cfirst[o], nc = ccount[o];
+    for (int pp2 = pp; pp2 < 16; pp2 += 8) {
+        double s = 0.0;
+        if (q < 2 * m)
+            for (int c = pp2; c < nc; c += 16) s += rpart[(size_t)(c0 + c) * 2 * m + q];
+        part[pp2][q] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < m) {
+        const int c = threadIdx.x;
         double a = 0.0, b = 0.0;
-        const int c0 = ufirst[o], nc = ucount[o];
-        for (int q = 0; q < nc; ++q) {
-            a += rpart[(size_t)(c0 + q) * 2 * m + c];
-            b += rpart[(size_t)(c0 + q) * 2 * m + m + c];
+        for (int t = 0; t < 16; ++t) {
+            a += part[t][c];
+            b += part[t][m + c];
         }
         const double th = theta[(size_t)o * m + c];
-        rj = sqrt(a) / ((norms[2 * o] + fabs(th) * norms[2 * o + 1]) * sqrt(b));
-        if (!(rj == rj)) rj = INFINITY;
-        res[(size_t)o * m + c] = rj;
+        double r = sqrt(a) / ((norms[2 * o] + fabs(th) * norms[2 * o + 1]) * sqrt(b));
+        if (!(r == r)) r = INFINITY;
+        res[(size_t)o * m + c] = r;
+        rj[c] = c < k ? r : 0.0;
     }
-    // max over the first k columns
-    double v = (c < k) ? rj : 0.0;
-    for (int d = 32; d >= 1; d >>= 1) v = fmax(v, __shfl_xor(v, d, 64));
-    if (c == 0) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double v = 0.0;
+        for (int c = 0; c < k; ++c) v = fmax(v, rj[c]);
         double *tr = track + 2 * o;               // [best max residual, iterations since improvement]
         if (v <= tol) {
             obj_status[o] = 1;
@@ -353,53 +365,66 @@ __global__ void __launch_bounds__(64) norms_kernel(int *obj_status, const int *u
 // ---------------------------------------------------------------------------
 // in-place block update: X <- S C, P <- S[:, m:w] C[m:w, :] (and for HS, MS)
 // ---------------------------------------------------------------------------
-
+//
+// One wavefront owns 16 rows: for each of S, HS, MS it forms the 16 x m
+// products with MFMA 16x16x4 (C staged in LDS, zero padded), accumulating the
+// X-row part and the W/P-row part separately, then writes X = both and P =
+// the W/P part. A wave reads its rows completely before writing them, and no
+// other wave touches them, so the update is in place.
 template <typename T>
 __global__ void __launch_bounds__(256) update_kernel(const UChunk *chunks, const int *obj_status, const int *width,
                                                      T *S, T *HS, T *MS, int64_t ld, int m, int wmax,
                                                      const T *C, int write_p) {
+    typedef typename MfmaAcc<T>::type Acc;
     const UChunk ch = chunks[blockIdx.x];
     if (obj_status[ch.obj] != 0) return;
     const int w = width[ch.obj];
-    const int rows_per = 256 / m;
+    const int wpad = (w + 3) & ~3, mpad = (m + 15) & ~15, nct = mpad >> 4;
     extern __shared__ __align__(16) char smem[];
-    T *rowbuf = (T *)smem;                          // [rows_per][3][w]
+    T *Cs = (T *)smem;                             // [wpad][mpad]
     const T *Co = C + (size_t)ch.obj * wmax * m;
-    const int t = threadIdx.x;
-    const int rr = t / m, c = t - (t / m) * m;
-    for (int64_t rb = ch.r0; rb < ch.r0 + ch.len; rb += rows_per) {
-        const int nr = (int)((ch.r0 + ch.len - rb) < rows_per ? (ch.r0 + ch.len - rb) : rows_per);
-        __syncthreads();
-        for (int idx = t; idx < nr * 3 * w; idx += 256) {
-            const int q = idx / (3 * w), rem = idx - q * 3 * w;
-            const int a = rem / w, j = rem - a * w;
-            const T *src = a == 0 ? S : (a == 1 ? HS : MS);
-            rowbuf[idx] = src[(rb + q) * ld + j];
-        }
-        __syncthreads();
-        if (rr < nr) {
-            const T *sr = rowbuf + (size_t)rr * 3 * w;
-            double x[3] = {0.0, 0.0, 0.0}, p[3] = {0.0, 0.0, 0.0};
-            for (int j = 0; j < m; ++j) {
-                const double cj = (double)Co[(size_t)j * m + c];
-                x[0] += (double)sr[j] * cj;
-                x[1] += (double)sr[w + j] * cj;
-                x[2] += (double)sr[2 * w + j] * cj;
+    for (int idx = threadIdx.x; idx < wpad * mpad; idx += 256) {
+        const int k = idx / mpad, c = idx - k * mpad;
+        Cs[idx] = (k < w && c < m) ? Co[(size_t)k * m + c] : (T)0;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int64_t rend = ch.r0 + ch.len;
+    for (int64_t rt = ch.r0 + 16 * wv; rt < rend; rt += 64) {
+        const int64_t arow = rt + li;
+        const bool av = arow < rend;
+        for (int a = 0; a < 3; ++a) {
+            T *Arr = a == 0 ? S : (a == 1 ? HS : MS);
+            Acc ax[4], ap[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                ax[t] = Acc{0, 0, 0, 0};
+                ap[t] = Acc{0, 0, 0, 0};
             }
-            for (int j = m; j < w; ++j) {
-                const double cj = (double)Co[(size_t)j * m + c];
-                p[0] += (double)sr[j] * cj;
-                p[1] += (double)sr[w + j] * cj;
-                p[2] += (double)sr[2 * w + j] * cj;
+            for (int k0 = 0; k0 < wpad; k0 += 4) {
+                const int kk = k0 + lk;
+                const T av_ = (av && kk < w) ? Arr[arow * ld + kk] : (T)0;
+                const bool xpart = k0 < m;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    if (t >= nct) break;
+                    const T bv = Cs[kk * mpad + t * 16 + li];
+                    if (xpart) ax[t] = mfma(av_, bv, ax[t]);
+                    else ap[t] = mfma(av_, bv, ap[t]);
+                }
             }
-            const int64_t r = rb + rr;
-            S[r * ld + c] = (T)(x[0] + p[0]);
-            HS[r * ld + c] = (T)(x[1] + p[1]);
-            MS[r * ld + c] = (T)(x[2] + p[2]);
-            if (write_p) {
-                S[r * ld + 2 * m + c] = (T)p[0];
-                HS[r * ld + 2 * m + c] = (T)p[1];
-                MS[r * ld + 2 * m + c] = (T)p[2];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                if (t >= nct) break;
+                const int c = t * 16 + li;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int64_t row = rt + MfmaAcc<T>::row(lk, v);
+                    if (row >= rend || c >= m) continue;
+                    Arr[row * ld + c] = ax[t][v] + ap[t][v];
+                    if (write_p) Arr[row * ld + 2 * m + c] = ap[t][v];
+                }
             }
         }
     }
@@ -414,14 +439,148 @@ __global__ void __launch_bounds__(256) update_kernel(const UChunk *chunks, const
 //   2. Cholesky of the scaled G_M in column order, dropping a column whose
 //      pivot falls to tau or below (a direction already spanned); the X
 //      columns come first, so only W and P directions are dropped
-//   3. A = L^-1 G_H L^-T on the kept columns
-//   4. cyclic Jacobi (parallel round-robin order) for A = V diag V^T
-//   5. the m smallest: theta ascending, C = D^-1/2 L^-T V (zero rows for dropped)
+//   3. L^-1 (one thread per column), then A = L^-1 G_H L^-T as two FP64 MFMA
+//      products
+//   4. Householder reduction of A to tridiagonal T = Q^T A Q (reflector j is
+//      kept in row j, contiguous, for the back-transform)
+//   5. the m smallest eigenvalues of T by multisection on Sturm counts (a
+//      group of threads per eigenvalue), eigenvectors by inverse iteration
+//      with partial pivoting; eigenvalues closer than 1e-9 ||T|| form a cluster
+//      that one thread handles in order, orthogonalising each member against
+//      the earlier ones
+//   6. one wavefront per vector: y -> Q y -> L^-T Q y -> D^-1/2 L^-T Q y = C;
+//      theta = Rayleigh quotient on T
 // A and B live in LDS when 2 w^2 doubles fit, else in a global scratch area.
 
 constexpr int kRRThreads = 256;
+constexpr int kRRMax = 192;
+
+// per-object Rayleigh-Ritz scratch (doubles): A, B, two staging areas, vectors, solver work
+__host__ __device__ inline size_t rr_scratch_doubles(int wmax, int m) {
+    return (size_t)4 * wmax * wmax + (size_t)m * wmax + (size_t)m * 4 * wmax;
+}
+
+// LDS plan: the two w x w FP64 matrices plus 10 per-column arrays when they fit
+// next to the kernel's static arrays, else only the per-column arrays
+inline int rr_use_lds(int wmax) {
+    return ((size_t)2 * wmax * wmax + (size_t)10 * wmax) * sizeof(double) <= 156 * 1024;
+}
+inline size_t rr_shmem_bytes(int wmax, int use_lds) {
+    return ((use_lds ? (size_t)2 * wmax * wmax : 0) + (size_t)10 * wmax) * sizeof(double);
+}
 
 __device__ inline void rr_barrier() { __syncthreads(); }
+
+// one-barrier block sum; parity alternates between calls so the partials of
+// one call are never overwritten before every thread has read them
+__device__ inline double rr_sum(double v, double (*wsum)[4], int &par) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    if ((threadIdx.x & 63) == 0) wsum[par][threadIdx.x >> 6] = v;
+    __syncthreads();
+    const double s = (wsum[par][0] + wsum[par][1]) + (wsum[par][2] + wsum[par][3]);
+    par ^= 1;
+    return s;
+}
+
+// number of eigenvalues of T (diag dg, offdiag eg) below x
+__device__ inline int sturm_count(const double *dg, const double *eg, int r, double x, double pivmin) {
+    int cnt = 0;
+    double q = dg[0] - x;
+    if (fabs(q) < pivmin) q = -pivmin;
+    cnt += q < 0.0;
+    for (int i = 1; i < r; ++i) {
+        q = dg[i] - x - eg[i - 1] * eg[i - 1] / q;
+        if (fabs(q) < pivmin) q = -pivmin;
+        cnt += q < 0.0;
+    }
+    return cnt;
+}
+
+// Solve (T - lam I) x = b in place (b -> x) with partial pivoting. Work
+// arrays are interleaved across threads: element i of this thread's array a
+// lives at wk[(a * r + i) * stride] (stride = number of solving threads).
+__device__ inline void tri_solve(const double *dg, const double *eg, int r, double lam, double tiny,
+                                 double *__restrict__ x, int xs, double *__restrict__ wk, int ws) {
+    double *dd = wk, *du = wk + (size_t)r * ws, *du2 = wk + (size_t)2 * r * ws;
+    // forward elimination, applied to the right-hand side on the fly; the sign of fac marks a pivot swap
+    double dcur = dg[0] - lam, ucur = r > 1 ? eg[0] : 0.0;
+    double bcur = x[0];
+    for (int i = 0; i + 1 < r; ++i) {
+        const double ai1 = dg[i + 1] - lam, ei = eg[i], ei1 = (i + 2 < r) ? eg[i + 1] : 0.0;
+        const double bnext = x[(size_t)(i + 1) * xs];
+        double dnext, unext, f, u2, di, ui, bi, bn;
+        if (fabs(dcur) >= fabs(ei)) {
+            if (dcur == 0.0) dcur = tiny;
+            f = ei / dcur;
+            di = dcur;
+            ui = ucur;
+            u2 = 0.0;
+            dnext = ai1 - f * ucur;
+            unext = ei1;
+            bi = bcur;
+            bn = bnext - f * bcur;
+        } else {
+            f = dcur / ei;
+            di = ei;
+            ui = ai1;
+            u2 = ei1;
+            dnext = ucur - f * ai1;
+            unext = -f * ei1;
+            bi = bnext;
+            bn = bcur - f * bnext;
+        }
+        dd[(size_t)i * ws] = di;
+        du[(size_t)i * ws] = ui;
+        du2[(size_t)i * ws] = u2;
+        x[(size_t)i * xs] = bi;
+        dcur = dnext;
+        ucur = unext;
+        bcur = bn;
+    }
+    if (dcur == 0.0) dcur = tiny;
+    // back substitution
+    double x1 = bcur / dcur, x2 = 0.0;
+    x[(size_t)(r - 1) * xs] = x1;
+    for (int i = r - 2; i >= 0; --i) {
+        const double xi = (x[(size_t)i * xs] - du[(size_t)i * ws] * x1 - du2[(size_t)i * ws] * x2) / dd[(size_t)i * ws];
+        x[(size_t)i * xs] = xi;
+        x2 = x1;
+        x1 = xi;
+    }
+}
+
+#ifdef FF_RR_TIMING
+__device__ unsigned long long rr_clock[16];
+#define RR_MARK(i) do { if (blockIdx.x == 0 && threadIdx.x == 0) rr_clock[i] = wall_clock64(); } while (0)
+#else
+#define RR_MARK(i) do { } while (0)
+#endif
+
+// Dst = X Y (transY = 0) or X Y^T (transY = 1), r x r, stride ld, FP64 MFMA 16x16x4;
+// the result goes to dst (a different buffer); entries beyond r are not written.
+__device__ inline void rr_gemm(const double *X, const double *Y, int transY, int r, int ld, double *dst) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int nt = (r + 15) >> 4;
+    for (int tile = wv; tile < nt * nt; tile += kRRThreads / 64) {
+        const int ti = tile / nt, tj = tile - (tile / nt) * nt;
+        f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+        const int row = ti * 16 + li, col = tj * 16 + li;
+        for (int k0 = 0; k0 < r; k0 += 4) {
+            const int kk = k0 + lk;
+            const double a = (row < r && kk < r) ? X[(size_t)row * ld + kk] : 0.0;
+            double b = 0.0;
+            if (col < r && kk < r) b = transY ? Y[(size_t)col * ld + kk] : Y[(size_t)kk * ld + col];
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = ti * 16 + 4 * v + lk, j = tj * 16 + li;   // FP64 result layout
+            if (i < r && j < r) dst[(size_t)i * ld + j] = acc[v];
+        }
+    }
+}
 
 template <typename CT>
 __global__ void __launch_bounds__(kRRThreads) rr_kernel(int *obj_status, int *width, const double *G, int wmax,
@@ -430,26 +589,29 @@ __global__ void __launch_bounds__(kRRThreads) rr_kernel(int *obj_status, int *wi
     const int o = blockIdx.x;
     if (obj_status[o] != 0) return;
     const int w = width[o];
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     extern __shared__ __align__(16) double sm[];
     const size_t ww = (size_t)wmax * wmax;
-    double *gscr = scratch + (size_t)o * 3 * ww;
-    double *A = use_lds ? sm : gscr;               // [wmax][wmax]
-    double *B = use_lds ? sm + ww : gscr + ww;     // [wmax][wmax]
-    double *L = gscr + 2 * ww;                     // kept-column Cholesky factor (global)
-    __shared__ double sc[256];                     // D^-1/2
-    __shared__ double dl[256];                     // Cholesky diagonal
-    __shared__ int keep[256];
-    __shared__ int kidx[256];
-    __shared__ int nkeep;
-    __shared__ int xdrop;
-    __shared__ double rot_c[128], rot_s[128];
-    __shared__ int rot_p[128], rot_q[128];
-    __shared__ double offmax;
-    __shared__ int sel[128];
+    double *gs = scratch + (size_t)o * rr_scratch_doubles(wmax, m);
+    double *A = use_lds ? sm : gs;
+    double *B = use_lds ? sm + ww : gs + ww;
+    double *st1 = gs + 2 * ww;                     // staging (ww)
+    double *st2 = gs + 3 * ww;                     // staging (ww)
+    double *Yv = gs + 4 * ww;                      // eigenvectors of T, element i of vector t at Yv[i*m + t]
+    double *wk = Yv + (size_t)m * wmax;            // inverse iteration work, 4 wmax per thread, interleaved
+    // per-column arrays after the matrices in dynamic LDS: sc, dl, dg, eg, tg, psh, ppart[4]
+    double *aux = sm + (use_lds ? 2 * ww : 0);
+    double *sc = aux, *dl = aux + wmax, *dg = aux + 2 * wmax, *eg = aux + 3 * wmax, *tg = aux + 4 * wmax;
+    double *psh = aux + 5 * wmax, *ppart = aux + 6 * wmax;
+    __shared__ int keep[kRRMax], kidx[kRRMax];
+    __shared__ double wsum[2][4];
+    __shared__ double evs[128];
+    __shared__ int nkeep, xdrop;
+    int par = 0;
     const double *GH = G + (size_t)o * 2 * ww;
     const double *GM = GH + ww;
 
+    RR_MARK(0);
     // 1. load, symmetrise, scale
     for (int j = tid; j < w; j += kRRThreads) {
         const double d = GM[(size_t)j * wmax + j];
@@ -457,15 +619,16 @@ __global__ void __launch_bounds__(kRRThreads) rr_kernel(int *obj_status, int *wi
     }
     if (tid == 0) xdrop = 0;
     rr_barrier();
-    for (int idx = tid; idx < w * w; idx += kRRThreads) {
-        const int i = idx / w, j = idx - i * w;
-        const double s = sc[i] * sc[j];
-        A[(size_t)i * wmax + j] = 0.5 * (GH[(size_t)i * wmax + j] + GH[(size_t)j * wmax + i]) * s;
-        B[(size_t)i * wmax + j] = 0.5 * (GM[(size_t)i * wmax + j] + GM[(size_t)j * wmax + i]) * s;
-    }
+    for (int i = wv; i < w; i += 4)
+        for (int j = lane; j < w; j += 64) {
+            const double s = sc[i] * sc[j];
+            A[(size_t)i * wmax + j] = 0.5 * (GH[(size_t)i * wmax + j] + GH[(size_t)j * wmax + i]) * s;
+            B[(size_t)i * wmax + j] = 0.5 * (GM[(size_t)i * wmax + j] + GM[(size_t)j * wmax + i]) * s;
+        }
     rr_barrier();
 
-    // 2. right-looking Cholesky with dropping
+    RR_MARK(1);
+    // 2. right-looking Cholesky with dropping (column j staged in psh)
     for (int j = 0; j < w; ++j) {
         const double piv = B[(size_t)j * wmax + j];
         const bool kj = sc[j] > 0.0 && piv > tau;
@@ -476,16 +639,17 @@ __global__ void __launch_bounds__(kRRThreads) rr_kernel(int *obj_status, int *wi
         }
         if (kj) {
             const double inv = 1.0 / sqrt(piv);
-            for (int i = j + 1 + tid; i < w; i += kRRThreads) B[(size_t)i * wmax + j] *= inv;
+            for (int i = j + 1 + tid; i < w; i += kRRThreads) {
+                const double v = B[(size_t)i * wmax + j] * inv;
+                B[(size_t)i * wmax + j] = v;
+                psh[i] = v;
+            }
         }
         rr_barrier();
         if (kj) {
-            const int nt = w - j - 1;
-            for (int idx = tid; idx < nt * nt; idx += kRRThreads) {
-                const int a = idx / nt, b = idx - a * nt;
-                if (b > a) continue;
-                const int i = j + 1 + a, l = j + 1 + b;
-                B[(size_t)i * wmax + l] -= B[(size_t)i * wmax + j] * B[(size_t)l * wmax + j];
+            for (int i = j + 1 + wv; i < w; i += 4) {
+                const double pi = psh[i];
+                for (int l = j + 1 + lane; l <= i; l += 64) B[(size_t)i * wmax + l] -= pi * psh[l];
             }
         }
         rr_barrier();
@@ -503,178 +667,244 @@ __global__ void __launch_bounds__(kRRThreads) rr_kernel(int *obj_status, int *wi
         if (tid == 0) obj_status[o] = 3;
         return;
     }
-    // kept-column factor to global L[r][r] (lower), diagonal from dl
-    for (int idx = tid; idx < r * r; idx += kRRThreads) {
-        const int a = idx / r, b = idx - a * r;
-        double v = 0.0;
-        if (b < a) v = B[(size_t)kidx[a] * wmax + kidx[b]];
-        else if (a == b) v = dl[kidx[a]];
-        L[(size_t)a * r + b] = v;
-    }
-    rr_barrier();
-    // 3. Y = L^-1 A_KK (column c by thread c), stored in B with stride r
-    for (int idx = tid; idx < r * r; idx += kRRThreads) {
-        const int a = idx / r, b = idx - a * r;
-        B[(size_t)a * r + b] = A[(size_t)kidx[a] * wmax + kidx[b]];
-    }
-    rr_barrier();
+    const int ld = r < w ? r : wmax;               // compact stride when columns were dropped
+
+    RR_MARK(2);
+    // 3. L^-1 (thread c solves L x = e_c on the kept columns) into st1, A_KK into st2
     for (int c = tid; c < r; c += kRRThreads) {
-        for (int i = 0; i < r; ++i) {
-            double s = B[(size_t)i * r + c];
-            for (int t = 0; t < i; ++t) s -= L[(size_t)i * r + t] * B[(size_t)t * r + c];
-            B[(size_t)i * r + c] = s / L[(size_t)i * r + i];
+        for (int i = 0; i < c; ++i) st1[(size_t)i * ld + c] = 0.0;
+        for (int i = c; i < r; ++i) {
+            double sacc = i == c ? 1.0 : 0.0;
+            const double *Li = B + (size_t)kidx[i] * wmax;
+            for (int t = c; t < i; ++t) sacc -= Li[kidx[t]] * st1[(size_t)t * ld + c];
+            st1[(size_t)i * ld + c] = sacc / dl[kidx[i]];
         }
     }
+    if (ld != wmax)
+        for (int i = wv; i < r; i += 4)
+            for (int j = lane; j < r; j += 64) st2[(size_t)i * ld + j] = A[(size_t)kidx[i] * wmax + kidx[j]];
+    __threadfence_block();
     rr_barrier();
-    // A_red = L^-1 Y^T: column c of A_red from row c of Y; padded to even size re
-    const int re = r + (r & 1);
-    for (int c = tid; c < r; c += kRRThreads) {
-        for (int i = 0; i < r; ++i) {
-            double s = B[(size_t)c * r + i];
-            for (int t = 0; t < i; ++t) s -= L[(size_t)i * r + t] * A[(size_t)t * re + c];
-            A[(size_t)i * re + c] = s / L[(size_t)i * r + i];
+    for (int i = wv; i < r; i += 4)
+        for (int j = lane; j < r; j += 64) {
+            B[(size_t)i * ld + j] = st1[(size_t)i * ld + j];
+            if (ld != wmax) A[(size_t)i * ld + j] = st2[(size_t)i * ld + j];
         }
-    }
     rr_barrier();
-    // symmetrise the reduced matrix, pad, and set V = I (V in B with stride re)
-    for (int idx = tid; idx < re * re; idx += kRRThreads) {
-        const int a = idx / re, b = idx - a * re;
-        if (a < r && b < r && b > a) {
-            const double v = 0.5 * (A[(size_t)a * re + b] + A[(size_t)b * re + a]);
-            A[(size_t)a * re + b] = v;
-            A[(size_t)b * re + a] = v;
-        } else if (a >= r || b >= r) {
-            A[(size_t)a * re + b] = (a == b) ? 0.0 : 0.0;
+    // A <- (L^-1 A) L^-T, symmetrised
+    rr_gemm(B, A, 0, r, ld, st1);
+    __threadfence_block();
+    rr_barrier();
+    for (int i = wv; i < r; i += 4)
+        for (int j = lane; j < r; j += 64) A[(size_t)i * ld + j] = st1[(size_t)i * ld + j];
+    rr_barrier();
+    rr_gemm(A, B, 1, r, ld, st2);
+    __threadfence_block();
+    rr_barrier();
+    for (int i = wv; i < r; i += 4)
+        for (int j = lane; j < r; j += 64)
+            A[(size_t)i * ld + j] = 0.5 * (st2[(size_t)i * ld + j] + st2[(size_t)j * ld + i]);
+    rr_barrier();
+
+    RR_MARK(3);
+    // 4. Householder tridiagonalisation; reflector j: v = [1, x/(x0 - beta)] kept in row j, columns j+1..
+    for (int j = 0; j + 2 < r; ++j) {
+        const double x0 = A[(size_t)(j + 1) * ld + j];
+        double part = 0.0;
+        for (int i = j + 2 + tid; i < r; i += kRRThreads) {
+            const double x = A[(size_t)i * ld + j];
+            part += x * x;
         }
-        B[(size_t)a * re + b] = (a == b) ? 1.0 : 0.0;
-    }
-    rr_barrier();
-    // 4. cyclic Jacobi, round-robin pairing (circle method), 2x2 block updates
-    const int np = re / 2;
-    __shared__ double wsum[kRRThreads / 64];
-    {
-        double f2 = 0.0;
-        for (int idx = tid; idx < r * r; idx += kRRThreads) {
-            const int a = idx / r, b = idx - a * r;
-            f2 += A[(size_t)a * re + b] * A[(size_t)a * re + b];
+        const double sigma = rr_sum(part, wsum, par);
+        double tj = 0.0, beta = x0, scale = 0.0;
+        if (sigma > 0.0) {
+            const double mu = sqrt(x0 * x0 + sigma);
+            beta = x0 <= 0.0 ? mu : -mu;
+            tj = (beta - x0) / beta;
+            scale = 1.0 / (x0 - beta);
         }
-        for (int d = 32; d >= 1; d >>= 1) f2 += __shfl_xor(f2, d, 64);
-        if ((tid & 63) == 0) wsum[tid >> 6] = f2;
+        if (tid == 0) {
+            dg[j] = A[(size_t)j * ld + j];
+            eg[j] = beta;
+            tg[j] = tj;
+        }
+        if (tj == 0.0) continue;
+        // v into row j (columns j+1..r-1); p = tau A_sub v by k-quarters (wave) and rows (lane)
+        for (int i = j + 1 + tid; i < r; i += kRRThreads)
+            A[(size_t)j * ld + i] = i == j + 1 ? 1.0 : A[(size_t)i * ld + j] * scale;
+        rr_barrier();
+        const double *vrow = A + (size_t)j * ld;
+        for (int i = j + 1 + lane; i < r; i += 64) {
+            double sacc = 0.0;
+            for (int k = j + 1 + wv; k < r; k += 4) sacc += A[(size_t)k * ld + i] * vrow[k];
+            ppart[wv * wmax + i] = sacc;
+        }
+        rr_barrier();
+        double part2 = 0.0;
+        for (int i = j + 1 + tid; i < r; i += kRRThreads) {
+            const double pi = tj * ((ppart[i] + ppart[wmax + i]) + (ppart[2 * wmax + i] + ppart[3 * wmax + i]));
+            psh[i] = pi;
+            part2 += pi * vrow[i];
+        }
+        const double K = 0.5 * tj * rr_sum(part2, wsum, par);
+        for (int i = j + 1 + wv; i < r; i += 4) {
+            const double vi = vrow[i], wi = psh[i] - K * vi;
+            for (int k = j + 1 + lane; k < r; k += 64) {
+                const double vk = vrow[k], wk_ = psh[k] - K * vk;
+                A[(size_t)i * ld + k] -= vi * wk_ + wi * vk;
+            }
+        }
+        rr_barrier();
     }
-    rr_barrier();
     if (tid == 0) {
-        double f2 = 0.0;
-        for (int q = 0; q < kRRThreads / 64; ++q) f2 += wsum[q];
-        offmax = f2;
+        if (r >= 2) {
+            dg[r - 2] = A[(size_t)(r - 2) * ld + (r - 2)];
+            eg[r - 2] = A[(size_t)(r - 1) * ld + (r - 2)];
+            tg[r - 2] = 0.0;
+        }
+        dg[r - 1] = A[(size_t)(r - 1) * ld + (r - 1)];
+        tg[r - 1] = 0.0;
+        eg[r - 1] = 0.0;
     }
     rr_barrier();
-    const double fro = sqrt(offmax);
-    rr_barrier();
-    for (int sweep = 0; sweep < 30; ++sweep) {
-        for (int round = 0; round < re - 1; ++round) {
-            for (int pi = tid; pi < np; pi += kRRThreads) {
-                auto pos = [&](int x) { return x == 0 ? 0 : 1 + (x - 1 + round) % (re - 1); };
-                int p = pos(pi), q = pos(re - 1 - pi);
-                if (p > q) { int t = p; p = q; q = t; }
-                const double app = A[(size_t)p * re + p], aqq = A[(size_t)q * re + q], apq = A[(size_t)p * re + q];
-                double c = 1.0, s = 0.0;
-                if (apq != 0.0 && fabs(apq) > 1e-300 && (p < r && q < r)) {
-                    const double tau_ = (aqq - app) / (2.0 * apq);
-                    const double t = (tau_ >= 0.0 ? 1.0 : -1.0) / (fabs(tau_) + sqrt(1.0 + tau_ * tau_));
-                    c = 1.0 / sqrt(1.0 + t * t);
-                    s = t * c;
-                }
-                rot_p[pi] = p;
-                rot_q[pi] = q;
-                rot_c[pi] = c;
-                rot_s[pi] = s;
-            }
-            rr_barrier();
-            // A <- J^T A J by 2x2 blocks (I <= J, mirrored); V <- V J
-            for (int idx = tid; idx < np * np; idx += kRRThreads) {
-                const int I = idx / np, J = idx - (idx / np) * np;
-                if (I > J) continue;
-                const int p1 = rot_p[I], q1 = rot_q[I], p2 = rot_p[J], q2 = rot_q[J];
-                const double c1 = rot_c[I], s1 = rot_s[I], c2 = rot_c[J], s2 = rot_s[J];
-                const double a11 = A[(size_t)p1 * re + p2], a12 = A[(size_t)p1 * re + q2];
-                const double a21 = A[(size_t)q1 * re + p2], a22 = A[(size_t)q1 * re + q2];
-                // B = A_blk J2
-                const double b11 = a11 * c2 - a12 * s2, b12 = a11 * s2 + a12 * c2;
-                const double b21 = a21 * c2 - a22 * s2, b22 = a21 * s2 + a22 * c2;
-                // J1^T B
-                double n11 = c1 * b11 - s1 * b21, n12 = c1 * b12 - s1 * b22;
-                double n21 = s1 * b11 + c1 * b21, n22 = s1 * b12 + c1 * b22;
-                if (I == J) {
-                    n12 = 0.0;
-                    n21 = 0.0;
-                    if (rot_s[I] == 0.0) { n12 = a12; n21 = a21; }
-                }
-                A[(size_t)p1 * re + p2] = n11;
-                A[(size_t)p1 * re + q2] = n12;
-                A[(size_t)q1 * re + p2] = n21;
-                A[(size_t)q1 * re + q2] = n22;
-                if (I != J) {
-                    A[(size_t)p2 * re + p1] = n11;
-                    A[(size_t)q2 * re + p1] = n12;
-                    A[(size_t)p2 * re + q1] = n21;
-                    A[(size_t)q2 * re + q1] = n22;
-                }
-            }
-            for (int idx = tid; idx < re * np; idx += kRRThreads) {
-                const int x = idx / np, I = idx - x * np;
-                const int p = rot_p[I], q = rot_q[I];
-                const double c = rot_c[I], s = rot_s[I];
-                const double vp = B[(size_t)x * re + p], vq = B[(size_t)x * re + q];
-                B[(size_t)x * re + p] = c * vp - s * vq;
-                B[(size_t)x * re + q] = s * vp + c * vq;
-            }
-            rr_barrier();
-        }
-        // convergence: max_{i<j} |a_ij| <= 1e-15 ||A||_F (the Frobenius norm is invariant)
-        if (tid == 0) offmax = 0.0;
-        rr_barrier();
-        double mx = 0.0;
-        for (int idx = tid; idx < r * r; idx += kRRThreads) {
-            const int a = idx / r, b = idx - a * r;
-            if (b <= a) continue;
-            mx = fmax(mx, fabs(A[(size_t)a * re + b]));
-        }
-        for (int d = 32; d >= 1; d >>= 1) mx = fmax(mx, __shfl_xor(mx, d, 64));
-        if ((tid & 63) == 0) atomicMax((unsigned long long *)&offmax, __double_as_longlong(mx));
-        rr_barrier();
-        const double om = offmax;
-        rr_barrier();
-        if (om <= 1e-15 * fro) break;
+
+    RR_MARK(4);
+    // 5. eigenvalues by multisection: a group of P threads per eigenvalue
+    double gl = 0.0, gu = 0.0, maxe2 = 0.0;
+    for (int i = 0; i < r; ++i) {
+        const double off = (i > 0 ? fabs(eg[i - 1]) : 0.0) + (i + 1 < r ? fabs(eg[i]) : 0.0);
+        gl = i == 0 ? dg[i] - off : fmin(gl, dg[i] - off);
+        gu = i == 0 ? dg[i] + off : fmax(gu, dg[i] + off);
+        if (i + 1 < r) maxe2 = fmax(maxe2, eg[i] * eg[i]);
     }
-    // 5. the m smallest eigenvalues, ascending (ties by index)
-    for (int i = tid; i < r; i += kRRThreads) {
-        const double di = A[(size_t)i * re + i];
-        int rank = 0;
-        for (int j = 0; j < r; ++j) {
-            const double dj = A[(size_t)j * re + j];
-            rank += (dj < di) || (dj == di && j < i);
+    const double tnorm = fmax(fabs(gl), fabs(gu));
+    const double eps = 2.220446049250313e-16;
+    gl -= 4.0 * eps * tnorm + 1e-300;
+    gu += 4.0 * eps * tnorm + 1e-300;
+    const double pivmin = 2.2250738585072014e-308 * fmax(1.0, maxe2);
+    {
+        int P = 1;
+        while (P * 2 * m <= kRRThreads && P < 64) P *= 2;
+        const int t = tid / P, sub = tid - (tid / P) * P;
+        double lo = gl, hi = gu;
+        if (t < m) {
+            for (int it = 0; it < 64; ++it) {
+                if (hi - lo <= 2.0 * eps * fmax(fabs(lo), fabs(hi)) + pivmin) break;
+                const double x = lo + (hi - lo) * (double)(sub + 1) / (double)(P + 1);
+                const bool above = sturm_count(dg, eg, r, x, pivmin) > t;
+                // new bracket: the highest point still below the eigenvalue and the lowest above it
+                double nlo = above ? lo : x, nhi = above ? x : hi;
+                for (int d = 1; d < P; d <<= 1) {
+                    nlo = fmax(nlo, __shfl_xor(nlo, d, 64));
+                    nhi = fmin(nhi, __shfl_xor(nhi, d, 64));
+                }
+                lo = nlo;
+                hi = nhi;
+            }
+            if (sub == 0) evs[t] = 0.5 * (lo + hi);
         }
-        if (rank < m) sel[rank] = i;
     }
     rr_barrier();
-    // z = L^-T v for each selected eigenvector; C = D^-1/2 z scattered to basis rows
+
+    RR_MARK(5);
+    // eigenvectors by inverse iteration; clusters handled in order by their first thread
+    const double ctol = 1e-9 * tnorm;
+    const double tiny = eps * tnorm + 1e-300;
+    if (tid < m && (tid == 0 || evs[tid] - evs[tid - 1] > ctol)) {
+        int u = tid;
+        const int u0 = tid;
+        double *wkt = wk + tid;
+        do {
+            double *x = Yv + u;                      // stride m
+            for (int i = 0; i < r; ++i) {
+                const unsigned hsh = (unsigned)i * 2654435761u + (unsigned)u * 2246822519u + 12345u;
+                x[(size_t)i * m] = 1.0 + ((double)((hsh >> 8) & 0xffff) / 65536.0 - 0.5);
+            }
+            for (int it = 0; it < 3; ++it) {
+                tri_solve(dg, eg, r, evs[u], tiny, x, m, wkt, m);
+                for (int q = u0; q < u; ++q) {
+                    double d = 0.0;
+                    for (int i = 0; i < r; ++i) d += Yv[(size_t)i * m + q] * x[(size_t)i * m];
+                    for (int i = 0; i < r; ++i) x[(size_t)i * m] -= d * Yv[(size_t)i * m + q];
+                }
+                double nx = 0.0;
+                for (int i = 0; i < r; ++i) nx += x[(size_t)i * m] * x[(size_t)i * m];
+                const double inv = nx > 0.0 ? 1.0 / sqrt(nx) : 0.0;
+                for (int i = 0; i < r; ++i) x[(size_t)i * m] *= inv;
+            }
+            ++u;
+        } while (u < m && evs[u] - evs[u - 1] <= ctol);
+    }
+    __threadfence_block();
+    rr_barrier();
+
+    RR_MARK(6);
+    // 6. one wavefront per vector: Rayleigh quotient, y <- Q y, z = L^-T y, C = D^-1/2 z
     double *Co = C + (size_t)o * wmax * m;
-    for (int idx = tid; idx < w * m; idx += kRRThreads) Co[idx] = 0.0;
-    rr_barrier();
-    for (int t = tid; t < m; t += kRRThreads) {
-        const int v = sel[t];
-        theta[(size_t)o * m + t] = A[(size_t)v * re + v];
-        for (int i = r - 1; i >= 0; --i) {
-            double s = B[(size_t)i * re + v];
-            for (int u = i + 1; u < r; ++u) s -= L[(size_t)u * r + i] * Co[(size_t)kidx[u] * m + t];
-            Co[(size_t)kidx[i] * m + t] = s / L[(size_t)i * r + i];
+    for (int t = wv; t < m; t += 4) {
+        double y[3], z[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int i = lane + 64 * q;
+            y[q] = i < r ? Yv[(size_t)i * m + t] : 0.0;
+        }
+        double rq = 0.0;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int i = lane + 64 * q;
+            if (i < r) {
+                double ty = dg[i] * y[q];
+                if (i > 0) ty += eg[i - 1] * Yv[(size_t)(i - 1) * m + t];
+                if (i + 1 < r) ty += eg[i] * Yv[(size_t)(i + 1) * m + t];
+                rq += y[q] * ty;
+            }
+        }
+        for (int d = 32; d >= 1; d >>= 1) rq += __shfl_xor(rq, d, 64);
+        if (lane == 0) theta[(size_t)o * m + t] = rq;
+        for (int j = r - 3; j >= 0; --j) {
+            const double tj = tg[j];
+            if (tj == 0.0) continue;
+            const double *vrow = A + (size_t)j * ld;
+            double sacc = 0.0;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const int i = lane + 64 * q;
+                if (i > j && i < r) sacc += vrow[i] * y[q];
+            }
+            for (int d = 32; d >= 1; d >>= 1) sacc += __shfl_xor(sacc, d, 64);
+            sacc *= tj;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const int i = lane + 64 * q;
+                if (i > j && i < r) y[q] -= sacc * vrow[i];
+            }
+        }
+        // z_i = sum_{s >= i} Linv[s][i] y_s
+        z[0] = z[1] = z[2] = 0.0;
+        for (int sidx = 0; sidx < r; ++sidx) {
+            const double ysrc = sidx < 64 ? y[0] : (sidx < 128 ? y[1] : y[2]);
+            const double ys = __shfl(ysrc, sidx & 63, 64);
+            const double *Ls = B + (size_t)sidx * ld;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const int i = lane + 64 * q;
+                if (i <= sidx) z[q] += Ls[i] * ys;
+            }
+        }
+        for (int i = lane; i < w; i += 64)
+            if (!keep[i]) Co[(size_t)i * m + t] = 0.0;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int i = lane + 64 * q;
+            if (i < r) Co[(size_t)kidx[i] * m + t] = sc[kidx[i]] * z[q];
         }
     }
+    __threadfence_block();
     rr_barrier();
-    for (int idx = tid; idx < w * m; idx += kRRThreads) Co[idx] *= sc[idx / m];
-    rr_barrier();
+    RR_MARK(7);
     CT *Cwo = Cw + (size_t)o * wmax * m;
     for (int idx = tid; idx < w * m; idx += kRRThreads) Cwo[idx] = (CT)Co[idx];
+    RR_MARK(8);
 }
 
 // ---------------------------------------------------------------------------
@@ -815,13 +1045,10 @@ __global__ void __launch_bounds__(256) sign_partial_kernel(int64_t a, int64_t b,
     }
 }
 
-__global__ void sign_apply_kernel(int64_t a, int64_t b, int m, int k, const double *X, int64_t ld, int nparts,
-                                  const double *pv, const int64_t *pi, double *W, int64_t ldw) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t rows = b - a;
-    if (t >= rows * k) return;
-    const int64_t r = a + t / k;
-    const int c = (int)(t % k);
+__global__ void sign_final_kernel(int k, const double *X, int64_t ld, int nparts, const double *pv, const int64_t *pi,
+                                  double *sgn) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= k) return;
     double best = -1.0;
     int64_t bi = INT64_MAX;
     for (int p = 0; p < nparts; ++p) {
@@ -829,8 +1056,16 @@ __global__ void sign_apply_kernel(int64_t a, int64_t b, int m, int k, const doub
         const int64_t i = pi[(size_t)c * nparts + p];
         if (v > best || (v == best && i < bi)) { best = v; bi = i; }
     }
-    const double s = (bi != INT64_MAX && X[bi * ld + c] < 0.0) ? -1.0 : 1.0;
-    W[r * ldw + c] = s * X[r * ld + c];
+    sgn[c] = (bi != INT64_MAX && X[bi * ld + c] < 0.0) ? -1.0 : 1.0;
+}
+
+__global__ void sign_apply_kernel(int64_t a, int64_t b, int k, const double *X, int64_t ld, const double *sgn,
+                                  double *W, int64_t ldw) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (b - a) * k) return;
+    const int64_t r = a + t / k;
+    const int c = (int)(t % k);
+    W[r * ldw + c] = sgn[c] * X[r * ld + c];
 }
 
 }  // namespace lob
@@ -843,36 +1078,33 @@ __global__ void sign_apply_kernel(int64_t a, int64_t b, int m, int k, const doub
 namespace ff {
 namespace lob {
 
-__global__ void rownorm_chunk_kernel(const UChunk *chunks, const int64_t *row_ptr, const double *H, const double *M,
-                                     double *part) {
+__global__ void __launch_bounds__(256) rownorm_chunk_kernel(const UChunk *chunks, const int64_t *row_ptr,
+                                                            const double *H, const double *M, double *part) {
     const UChunk ch = chunks[blockIdx.x];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     double mh = 0.0, mm = 0.0;
-    for (int64_t r = ch.r0 + threadIdx.x; r < ch.r0 + ch.len; r += blockDim.x) {
-        double sh = 0.0, sm = 0.0;
-        for (int64_t e = row_ptr[r]; e < row_ptr[r + 1]; ++e) {
+    for (int64_t r = ch.r0 + wv; r < ch.r0 + ch.len; r += 4) {
+        double sh = 0.0, smv = 0.0;
+        for (int64_t e = row_ptr[r] + lane; e < row_ptr[r + 1]; e += 64) {
             sh += fabs(H[e]);
-            sm += fabs(M[e]);
+            smv += fabs(M[e]);
+        }
+        for (int d = 32; d >= 1; d >>= 1) {
+            sh += __shfl_xor(sh, d, 64);
+            smv += __shfl_xor(smv, d, 64);
         }
         mh = fmax(mh, sh);
-        mm = fmax(mm, sm);
-    }
-    for (int d = 32; d >= 1; d >>= 1) {
-        mh = fmax(mh, __shfl_xor(mh, d, 64));
-        mm = fmax(mm, __shfl_xor(mm, d, 64));
+        mm = fmax(mm, smv);
     }
     __shared__ double s[2][4];
-    if ((threadIdx.x & 63) == 0) {
-        s[0][threadIdx.x >> 6] = mh;
-        s[1][threadIdx.x >> 6] = mm;
+    if (lane == 0) {
+        s[0][wv] = mh;
+        s[1][wv] = mm;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int q = 1; q < (int)(blockDim.x >> 6); ++q) {
-            mh = fmax(mh, s[0][q]);
-            mm = fmax(mm, s[1][q]);
-        }
-        part[2 * blockIdx.x] = fmax(mh, s[0][0]);
-        part[2 * blockIdx.x + 1] = fmax(mm, s[1][0]);
+        part[2 * blockIdx.x] = fmax(fmax(s[0][0], s[0][1]), fmax(s[0][2], s[0][3]));
+        part[2 * blockIdx.x + 1] = fmax(fmax(s[1][0], s[1][1]), fmax(s[1][2], s[1][3]));
     }
 }
 
@@ -979,7 +1211,7 @@ struct Solver {
     int nu = 0, ng = 0;
     int rr_lds = 0;
     size_t rr_shmem = 0;
-    int refresh32 = 20, refresh64 = 200;
+    int refresh32 = 30, refresh64 = 0;
     int total_iters = 0;
 };
 
@@ -1025,7 +1257,7 @@ int stage_gram_rr(Solver &s, T *S, T *HS, T *MS, double tau) {
 
 template <typename T>
 int stage_update(Solver &s, T *S, T *HS, T *MS, int write_p) {
-    const size_t shmem = (size_t)(256 / s.m) * 3 * s.wmax * sizeof(T);
+    const size_t shmem = (size_t)((s.wmax + 3) & ~3) * ((s.m + 15) & ~15) * sizeof(T);
     hipLaunchKernelGGL(update_kernel<T>, dim3(s.nu), dim3(256), shmem, s.st, s.uch, s.status, s.width, S, HS, MS,
                        (int64_t)3 * s.m, s.m, s.wmax, (const T *)cw_of<T>(s), write_p);
     FF_CHECK_LAUNCH(s.ctx);
@@ -1034,11 +1266,11 @@ int stage_update(Solver &s, T *S, T *HS, T *MS, int write_p) {
 
 template <typename T>
 int stage_resid(Solver &s, T *S, T *HS, T *MS, double tol, int stall) {
-    hipLaunchKernelGGL(resid_kernel<T>, dim3(s.nu), dim3(256), 0, s.st, s.uch, s.status, S, (const T *)HS,
+    hipLaunchKernelGGL(resid_kernel<T>, dim3(s.ng), dim3(256), 0, s.st, s.gch, s.status, S, (const T *)HS,
                        (const T *)MS, (int64_t)3 * s.m, s.m, s.theta, s.jacobi ? dinv_of<T>(s) : (const T *)nullptr,
                        s.rpart);
     FF_CHECK_LAUNCH(s.ctx);
-    hipLaunchKernelGGL(norms_kernel, dim3(s.n_obj), dim3(64), 0, s.st, s.status, s.ufirst, s.ucount, s.rpart, s.m,
+    hipLaunchKernelGGL(norms_kernel, dim3(s.n_obj), dim3(1024), 0, s.st, s.status, s.gfirst, s.gcount, s.rpart, s.m,
                        s.k, s.theta, s.norms, tol, stall, s.res, s.track);
     FF_CHECK_LAUNCH(s.ctx);
     hipLaunchKernelGGL(count_iter_kernel, dim3(grid_for(s.n_obj, 64)), dim3(64), 0, s.st, s.n_obj, s.status, s.iters);
@@ -1099,8 +1331,9 @@ int run_phase(Solver &s, T *S, T *HS, T *MS, int max_iters, double tol, int stal
         const int steps = std::min(check_every, max_iters - it);
         for (int j = 0; j < steps; ++j) {
             if (refresh > 0 && it > 0 && it % refresh == 0) {
+                // recompute the images of X and P so the recurrences do not drift
                 if ((rc = stage_spmm<T>(s, S, HS, MS, 0))) break;
-                if ((rc = set_width(s, 2 * s.m, 1))) break;
+                if ((rc = stage_spmm<T>(s, S, HS, MS, 2))) break;
             }
             if (exec) {
                 if (hipGraphLaunch(exec, s.st) != hipSuccess) {
@@ -1201,7 +1434,7 @@ int setup(Solver &s, const ff_eig_params *p) {
     s.G = (double *)ws_get(ctx, WS_G, (size_t)n_obj * 2 * wmax * wmax * sizeof(double));
     s.gpart = (double *)ws_get(ctx, WS_GPART, (size_t)s.ng * 2 * wmax * wmax * sizeof(double));
     s.rpart = (double *)ws_get(ctx, WS_RPART, (size_t)std::max(s.nu, s.ng) * 2 * std::max(m, 2) * sizeof(double));
-    s.rrscr = (double *)ws_get(ctx, WS_RRSCR, (size_t)n_obj * 3 * wmax * wmax * sizeof(double));
+    s.rrscr = (double *)ws_get(ctx, WS_RRSCR, (size_t)n_obj * rr_scratch_doubles(wmax, m) * sizeof(double));
     if (!s.theta || !s.C || !s.C32 || !s.G || !s.gpart || !s.rpart || !s.rrscr) return FF_ERR_OOM;
     FF_HIP(ctx, hipMemsetAsync(s.theta, 0, (size_t)n_obj * m * sizeof(double) * 2, s.st));
 
@@ -1220,16 +1453,20 @@ int setup(Solver &s, const ff_eig_params *p) {
                            s.dinv64, s.dinv32);
         FF_CHECK_LAUNCH(ctx);
     }
-    // Rayleigh-Ritz storage: LDS when the two w x w FP64 matrices fit
-    const size_t two = (size_t)2 * wmax * wmax * sizeof(double);
-    s.rr_lds = two <= 144 * 1024;
-    s.rr_shmem = s.rr_lds ? two : 0;
-    if (s.rr_lds) {
-        FF_HIP(ctx, hipFuncSetAttribute((const void *)rr_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                        (int)two));
-        FF_HIP(ctx, hipFuncSetAttribute((const void *)rr_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                        (int)two));
+    {
+        const int upd = (int)(((size_t)((wmax + 3) & ~3) * ((m + 15) & ~15)) * sizeof(double));
+        FF_HIP(ctx, hipFuncSetAttribute((const void *)update_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        upd));
+        FF_HIP(ctx, hipFuncSetAttribute((const void *)update_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        upd));
     }
+    // Rayleigh-Ritz storage: LDS when the two w x w FP64 matrices fit
+    s.rr_lds = rr_use_lds(wmax);
+    s.rr_shmem = rr_shmem_bytes(wmax, s.rr_lds);
+    FF_HIP(ctx, hipFuncSetAttribute((const void *)rr_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)s.rr_shmem));
+    FF_HIP(ctx, hipFuncSetAttribute((const void *)rr_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)s.rr_shmem));
     return FF_OK;
 }
 
@@ -1340,16 +1577,20 @@ int solve(ff_ctx *ctx, int n_obj, const int64_t *obj_off, const int64_t *row_ptr
     FF_HIP(ctx, hipMemcpyAsync(its.data(), s.iters, its.size() * sizeof(int), hipMemcpyDeviceToHost, s.st));
     FF_HIP(ctx, hipMemcpyAsync(inf.data(), s.info, inf.size() * sizeof(int), hipMemcpyDeviceToHost, s.st));
     const int nparts = 64;
-    double *pv = (double *)ws_get(ctx, WS_RES, (size_t)m * nparts * (sizeof(double) + sizeof(int64_t)));
+    double *pv = (double *)ws_get(ctx, WS_RES, (size_t)m * nparts * (sizeof(double) + sizeof(int64_t)) + 64 * 8);
     if (!pv) return FF_ERR_OOM;
     int64_t *pi = (int64_t *)(pv + (size_t)m * nparts);
+    double *sgn = (double *)(pi + (size_t)m * nparts);
     for (int o = 0; o < n_obj; ++o) {
         hipLaunchKernelGGL(sign_partial_kernel, dim3(nparts, s.k), dim3(256), 0, s.st, s.off[o], s.off[o + 1], m, S64,
                            (int64_t)3 * m, pv, pi);
         FF_CHECK_LAUNCH(ctx);
         const int64_t rows = s.off[o + 1] - s.off[o];
+        hipLaunchKernelGGL(sign_final_kernel, dim3(1), dim3(64), 0, s.st, s.k, S64, (int64_t)3 * m, nparts, pv, pi,
+                           sgn);
+        FF_CHECK_LAUNCH(ctx);
         hipLaunchKernelGGL(sign_apply_kernel, dim3(grid_for(rows * s.k, 256)), dim3(256), 0, s.st, s.off[o],
-                           s.off[o + 1], m, s.k, S64, (int64_t)3 * m, nparts, pv, pi, W, (int64_t)s.k);
+                           s.off[o + 1], s.k, S64, (int64_t)3 * m, sgn, W, (int64_t)s.k);
         FF_CHECK_LAUNCH(ctx);
     }
     FF_HIP(ctx, hipStreamSynchronize(s.st));
@@ -1600,18 +1841,17 @@ extern "C" int rayleigh_ritz(ff_ctx *ctx, int w, int m, const double *G, double 
     FF_HIP(ctx, hipSetDevice(ctx->device));
     hipStream_t st = ctx->stream;
     int *ints = (int *)ws_get(ctx, WS_OBJ, 256);
-    double *scr = (double *)ws_get(ctx, WS_RRSCR, (size_t)3 * w * w * sizeof(double));
+    double *scr = (double *)ws_get(ctx, WS_RRSCR, rr_scratch_doubles(w, m) * sizeof(double));
     double *cw = (double *)ws_get(ctx, WS_C, (size_t)w * m * sizeof(double));
     if (!ints || !scr || !cw) return FF_ERR_OOM;
     int hi[3] = {0, w, 0};   // status, width, info
     FF_HIP(ctx, hipMemcpyAsync(ints, hi, sizeof(hi), hipMemcpyHostToDevice, st));
     FF_HIP(ctx, hipStreamSynchronize(st));
-    const size_t two = (size_t)2 * w * w * sizeof(double);
-    const int lds = two <= 144 * 1024;
-    if (lds)
-        FF_HIP(ctx, hipFuncSetAttribute((const void *)rr_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                        (int)two));
-    hipLaunchKernelGGL(rr_kernel<double>, dim3(1), dim3(kRRThreads), lds ? two : 0, st, ints, ints + 1, G, w, m, tau,
+    const int lds = rr_use_lds(w);
+    const size_t shm = rr_shmem_bytes(w, lds);
+    FF_HIP(ctx, hipFuncSetAttribute((const void *)rr_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)shm));
+    hipLaunchKernelGGL(rr_kernel<double>, dim3(1), dim3(kRRThreads), shm, st, ints, ints + 1, G, w, m, tau,
                        scr, lds, C, cw, theta, ints + 2);
     FF_CHECK_LAUNCH(ctx);
     int h[3];
@@ -1621,3 +1861,9 @@ extern "C" int rayleigh_ritz(ff_ctx *ctx, int w, int m, const double *G, double 
     if (h[0] == 3) return set_error(ctx, FF_ERR_BREAKDOWN, "only %d of %d columns kept (need %d)", *kept, w, m);
     return FF_OK;
 }
+
+#ifdef FF_RR_TIMING
+extern "C" int rr_phase_clock(unsigned long long *out16) {
+    return hipMemcpyFromSymbol(out16, HIP_SYMBOL(ff::lob::rr_clock), 16 * sizeof(unsigned long long)) == hipSuccess ? 0 : -3;
+}
+#endif
