@@ -1,6 +1,8 @@
 // Context lifetime, error reporting and workspace management.
 #include "ff_internal.h"
 
+#include <cstdlib>
+
 namespace ff {
 
 int set_error(ff_ctx *ctx, int code, const char *fmt, ...) {
@@ -75,6 +77,8 @@ int ff_ctx_create(ff_ctx **out, int device, void *hip_stream) {
     ff_ctx *ctx = new ff_ctx();
     ctx->device = device;
     ctx->stream = (hipStream_t)hip_stream;
+    const char *v = getenv("FF_VERBOSE");
+    ctx->verbose = v && v[0] == '1';
     *out = ctx;
     return FF_OK;
 }

@@ -41,6 +41,7 @@ struct ff_ctx {
     size_t pinned_size = 0;
     std::unordered_map<std::string, int> tuned;   // SpMM shape key -> variant
     double stage_ms[5] = {0, 0, 0, 0, 0};
+    int verbose = 0;                 // FF_VERBOSE=1: residual trace on stderr
 };
 
 namespace ff {

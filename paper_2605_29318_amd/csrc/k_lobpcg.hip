@@ -59,23 +59,24 @@ template <> struct HMPair<double> {
     }
 };
 
-__device__ inline void fma_vec(float4 &acc, float a, const float4 &x) {
-    acc.x += a * x.x; acc.y += a * x.y; acc.z += a * x.z; acc.w += a * x.w;
+// FP64 accumulators for both precisions: a product of two FP32 numbers is
+// exact in FP64, so the FP32 path's only rounding is the final store.
+struct Acc4 { double v[4]; };
+__device__ inline void acc_zero(Acc4 &a) { a.v[0] = a.v[1] = a.v[2] = a.v[3] = 0.0; }
+__device__ inline void acc_fma(Acc4 &a, float h, const float4 &x) {
+    const double d = (double)h;
+    a.v[0] += d * (double)x.x; a.v[1] += d * (double)x.y; a.v[2] += d * (double)x.z; a.v[3] += d * (double)x.w;
 }
-__device__ inline void fma_vec(double2 &acc, double a, const double2 &x) {
-    acc.x += a * x.x; acc.y += a * x.y;
+__device__ inline void acc_fma(Acc4 &a, double h, const double2 &x) {
+    a.v[0] += h * x.x; a.v[1] += h * x.y;
 }
-__device__ inline float4 shfl_xor_vec(const float4 &v, int d) {
-    return make_float4(__shfl_xor(v.x, d, 64), __shfl_xor(v.y, d, 64), __shfl_xor(v.z, d, 64), __shfl_xor(v.w, d, 64));
+__device__ inline void acc_add_shfl(Acc4 &a, int d, int nv) {
+    for (int q = 0; q < nv; ++q) a.v[q] += __shfl_xor(a.v[q], d, 64);
 }
-__device__ inline double2 shfl_xor_vec(const double2 &v, int d) {
-    return make_double2(__shfl_xor(v.x, d, 64), __shfl_xor(v.y, d, 64));
+__device__ inline void acc_store(float *p, const Acc4 &a) {
+    *(float4 *)p = make_float4((float)a.v[0], (float)a.v[1], (float)a.v[2], (float)a.v[3]);
 }
-__device__ inline void add_vec(float4 &a, const float4 &b) { a.x += b.x; a.y += b.y; a.z += b.z; a.w += b.w; }
-__device__ inline void add_vec(double2 &a, const double2 &b) { a.x += b.x; a.y += b.y; }
-template <typename V> __device__ inline V zero_vec();
-template <> __device__ inline float4 zero_vec<float4>() { return make_float4(0.f, 0.f, 0.f, 0.f); }
-template <> __device__ inline double2 zero_vec<double2>() { return make_double2(0.0, 0.0); }
+__device__ inline void acc_store(double *p, const Acc4 &a) { *(double2 *)p = make_double2(a.v[0], a.v[1]); }
 
 // kWaves rows per block, kUnroll independent gathers in flight per lane.
 // Lanes are split into groups of G = m / VEC lanes; each group walks every
@@ -97,7 +98,9 @@ __global__ void __launch_bounds__(64 * kWaves) spmm_kernel(int64_t nrows, const 
     const int g = lane / G, c = lane - g * G;
     const bool on = g < NG;
     const int64_t e0 = row_ptr[r], e1 = row_ptr[r + 1];
-    V aH = zero_vec<V>(), aM = zero_vec<V>();
+    Acc4 aH, aM;
+    acc_zero(aH);
+    acc_zero(aM);
     if (on) {
         int64_t e = e0 + g;
         for (; e + (kUnroll - 1) * NG < e1; e += kUnroll * NG) {
@@ -113,8 +116,8 @@ __global__ void __launch_bounds__(64 * kWaves) spmm_kernel(int64_t nrows, const 
             for (int u = 0; u < kUnroll; ++u) x[u] = *(const V *)(Y + (int64_t)j[u] * ldy + c * VN);
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
-                fma_vec(aH, h[u], x[u]);
-                fma_vec(aM, mm[u], x[u]);
+                acc_fma(aH, h[u], x[u]);
+                acc_fma(aM, mm[u], x[u]);
             }
         }
         for (; e < e1; e += NG) {
@@ -122,30 +125,33 @@ __global__ void __launch_bounds__(64 * kWaves) spmm_kernel(int64_t nrows, const 
             T h, mm;
             hm.get(e, h, mm);
             const V x = *(const V *)(Y + (int64_t)j * ldy + c * VN);
-            fma_vec(aH, h, x);
-            fma_vec(aM, mm, x);
+            acc_fma(aH, h, x);
+            acc_fma(aM, mm, x);
         }
     }
     if ((64 % G) == 0) {
         for (int d = G; d < 64; d <<= 1) {
-            add_vec(aH, shfl_xor_vec(aH, d));
-            add_vec(aM, shfl_xor_vec(aM, d));
+            acc_add_shfl(aH, d, VN);
+            acc_add_shfl(aM, d, VN);
         }
     } else {
-        __shared__ V red[kWaves][2][64];
-        red[wv][0][lane] = aH;
-        red[wv][1][lane] = aM;
+        __shared__ double red[kWaves][2][4][64];
+        for (int q = 0; q < VN; ++q) {
+            red[wv][0][q][lane] = aH.v[q];
+            red[wv][1][q][lane] = aM.v[q];
+        }
         __builtin_amdgcn_wave_barrier();
         if (g == 0) {
-            for (int t = 1; t < NG; ++t) {
-                add_vec(aH, red[wv][0][t * G + c]);
-                add_vec(aM, red[wv][1][t * G + c]);
-            }
+            for (int t = 1; t < NG; ++t)
+                for (int q = 0; q < VN; ++q) {
+                    aH.v[q] += red[wv][0][q][t * G + c];
+                    aM.v[q] += red[wv][1][q][t * G + c];
+                }
         }
     }
     if (g == 0) {
-        *(V *)(HY + r * ldo + c * VN) = aH;
-        *(V *)(MY + r * ldo + c * VN) = aM;
+        acc_store(HY + r * ldo + c * VN, aH);
+        acc_store(MY + r * ldo + c * VN, aM);
     }
 }
 
@@ -225,7 +231,7 @@ __global__ void __launch_bounds__(512) gram_kernel(const GChunk *chunks, const i
         for (int a = 0; a < 3; ++a)
 #pragma unroll
             for (int c = 0; c < 3; ++c) acc[a][c] = mfma(fa[a], fb[c], acc[a][c]);
-        if (++steps == 16) {                       // promote to FP64 every 64 rows
+        if (++steps == 4) {                        // promote to FP64 every 16 rows
             steps = 0;
 #pragma unroll
             for (int a = 0; a < 3; ++a)
@@ -366,28 +372,34 @@ __global__ void __launch_bounds__(1024) norms_kernel(int *obj_status, const int 
 // in-place block update: X <- S C, P <- S[:, m:w] C[m:w, :] (and for HS, MS)
 // ---------------------------------------------------------------------------
 //
-// One wavefront owns 16 rows: for each of S, HS, MS it forms the 16 x m
-// products with MFMA 16x16x4 (C staged in LDS, zero padded), accumulating the
-// X-row part and the W/P-row part separately, then writes X = both and P =
-// the W/P part. A wave reads its rows completely before writing them, and no
-// other wave touches them, so the update is in place.
+// One wavefront owns 16 rows: for each of S, HS, MS it forms X' = S C and
+// P' = S C_p' (16 x m each) with MFMA 16x16x4 (C and C_p' staged in LDS, zero
+// padded, when they fit). A wave reads its rows completely before writing
+// them, and no other wave touches them, so the update is in place.
 template <typename T>
 __global__ void __launch_bounds__(256) update_kernel(const UChunk *chunks, const int *obj_status, const int *width,
                                                      T *S, T *HS, T *MS, int64_t ld, int m, int wmax,
-                                                     const T *C, int write_p) {
+                                                     const T *C, const T *Cp, int write_p, int c_in_lds) {
     typedef typename MfmaAcc<T>::type Acc;
     const UChunk ch = chunks[blockIdx.x];
     if (obj_status[ch.obj] != 0) return;
     const int w = width[ch.obj];
     const int wpad = (w + 3) & ~3, mpad = (m + 15) & ~15, nct = mpad >> 4;
     extern __shared__ __align__(16) char smem[];
-    T *Cs = (T *)smem;                             // [wpad][mpad]
     const T *Co = C + (size_t)ch.obj * wmax * m;
-    for (int idx = threadIdx.x; idx < wpad * mpad; idx += 256) {
-        const int k = idx / mpad, c = idx - k * mpad;
-        Cs[idx] = (k < w && c < m) ? Co[(size_t)k * m + c] : (T)0;
+    const T *Cpo = Cp + (size_t)ch.obj * wmax * m;
+    // B operands: padded copies in LDS, or the global arrays with bounds checks
+    T *Cs = (T *)smem;
+    T *Cps = Cs + (size_t)wpad * mpad;
+    if (c_in_lds) {
+        for (int idx = threadIdx.x; idx < wpad * mpad; idx += 256) {
+            const int k = idx / mpad, c = idx - k * mpad;
+            const bool in = k < w && c < m;
+            Cs[idx] = in ? Co[(size_t)k * m + c] : (T)0;
+            Cps[idx] = (in && write_p) ? Cpo[(size_t)k * m + c] : (T)0;
+        }
+        __syncthreads();
     }
-    __syncthreads();
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int li = lane & 15, lk = lane >> 4;
     const int64_t rend = ch.r0 + ch.len;
@@ -405,13 +417,21 @@ __global__ void __launch_bounds__(256) update_kernel(const UChunk *chunks, const
             for (int k0 = 0; k0 < wpad; k0 += 4) {
                 const int kk = k0 + lk;
                 const T av_ = (av && kk < w) ? Arr[arow * ld + kk] : (T)0;
-                const bool xpart = k0 < m;
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
                     if (t >= nct) break;
-                    const T bv = Cs[kk * mpad + t * 16 + li];
-                    if (xpart) ax[t] = mfma(av_, bv, ax[t]);
-                    else ap[t] = mfma(av_, bv, ap[t]);
+                    const int cc = t * 16 + li;
+                    T bx, bp;
+                    if (c_in_lds) {
+                        bx = Cs[kk * mpad + cc];
+                        bp = Cps[kk * mpad + cc];
+                    } else {
+                        const bool in = kk < w && cc < m;
+                        bx = in ? Co[(size_t)kk * m + cc] : (T)0;
+                        bp = (in && write_p) ? Cpo[(size_t)kk * m + cc] : (T)0;
+                    }
+                    ax[t] = mfma(av_, bx, ax[t]);
+                    if (write_p) ap[t] = mfma(av_, bp, ap[t]);
                 }
             }
 #pragma unroll
@@ -422,7 +442,7 @@ __global__ void __launch_bounds__(256) update_kernel(const UChunk *chunks, const
                 for (int v = 0; v < 4; ++v) {
                     const int64_t row = rt + MfmaAcc<T>::row(lk, v);
                     if (row >= rend || c >= m) continue;
-                    Arr[row * ld + c] = ax[t][v] + ap[t][v];
+                    Arr[row * ld + c] = ax[t][v];
                     if (write_p) Arr[row * ld + 2 * m + c] = ap[t][v];
                 }
             }
@@ -585,7 +605,8 @@ __device__ inline void rr_gemm(const double *X, const double *Y, int transY, int
 template <typename CT>
 __global__ void __launch_bounds__(kRRThreads) rr_kernel(int *obj_status, int *width, const double *G, int wmax,
                                                         int m, double tau, double *scratch, int use_lds,
-                                                        double *C, CT *Cw, double *theta, int *info) {
+                                                        double *C, CT *Cw, double *Cp, CT *Cpw, double *theta,
+                                                        int *info) {
     const int o = blockIdx.x;
     if (obj_status[o] != 0) return;
     const int w = width[o];
@@ -902,8 +923,36 @@ __global__ void __launch_bounds__(kRRThreads) rr_kernel(int *obj_status, int *wi
     __threadfence_block();
     rr_barrier();
     RR_MARK(7);
+    // P coefficients: C_p (C without its X rows) minus its M-projection on the new X,
+    // Q = C^T G_M C_p, C_p' = C_p - C Q, so that P' = S C_p' is M-orthogonal to X' = S C
+    double *T1 = st1, *Qm = st2;
+    for (int idx = tid; idx < w * m; idx += kRRThreads) {
+        const int i = idx / m, c = idx - (idx / m) * m;
+        double acc = 0.0;
+        for (int j = m; j < w; ++j) acc += GM[(size_t)i * wmax + j] * Co[(size_t)j * m + c];
+        T1[idx] = acc;
+    }
+    __threadfence_block();
+    rr_barrier();
+    for (int idx = tid; idx < m * m; idx += kRRThreads) {
+        const int a = idx / m, c = idx - (idx / m) * m;
+        double acc = 0.0;
+        for (int i = 0; i < w; ++i) acc += Co[(size_t)i * m + a] * T1[(size_t)i * m + c];
+        Qm[idx] = acc;
+    }
+    __threadfence_block();
+    rr_barrier();
+    double *Cpo = Cp + (size_t)o * wmax * m;
+    CT *Cpwo = Cpw + (size_t)o * wmax * m;
     CT *Cwo = Cw + (size_t)o * wmax * m;
-    for (int idx = tid; idx < w * m; idx += kRRThreads) Cwo[idx] = (CT)Co[idx];
+    for (int idx = tid; idx < w * m; idx += kRRThreads) {
+        const int i = idx / m, c = idx - (idx / m) * m;
+        double acc = i >= m ? Co[idx] : 0.0;
+        for (int a = 0; a < m; ++a) acc -= Co[(size_t)i * m + a] * Qm[(size_t)a * m + c];
+        Cpo[idx] = acc;
+        Cpwo[idx] = (CT)acc;
+        Cwo[idx] = (CT)Co[idx];
+    }
     RR_MARK(8);
 }
 
@@ -1203,7 +1252,9 @@ struct Solver {
     int *status = nullptr, *width = nullptr, *info = nullptr, *iters = nullptr, *row_obj = nullptr;
     int *ufirst = nullptr, *ucount = nullptr, *gfirst = nullptr, *gcount = nullptr;
     int64_t *obj_off = nullptr;
-    double *theta = nullptr, *C = nullptr, *C64w = nullptr, *G = nullptr, *gpart = nullptr, *rpart = nullptr;
+    double *theta = nullptr, *C = nullptr, *C64w = nullptr, *Cp = nullptr, *Cp64w = nullptr;
+    double *G = nullptr, *gpart = nullptr, *rpart = nullptr;
+    float *Cp32 = nullptr;
     double *res = nullptr, *track = nullptr, *norms = nullptr, *rrscr = nullptr, *dinv64 = nullptr;
     float *C32 = nullptr, *dinv32 = nullptr;
     UChunk *uch = nullptr;
@@ -1224,6 +1275,17 @@ template <> const double *dinv_of<double>(const Solver &s) { return s.dinv64; }
 template <typename T> typename Prec<T>::CT *cw_of(const Solver &s);
 template <> float *cw_of<float>(const Solver &s) { return s.C32; }
 template <> double *cw_of<double>(const Solver &s) { return s.C64w; }
+template <typename T> typename Prec<T>::CT *cpw_of(const Solver &s);
+template <> float *cpw_of<float>(const Solver &s) { return s.Cp32; }
+template <> double *cpw_of<double>(const Solver &s) { return s.Cp64w; }
+
+// C and C_p' in LDS for the block update when both padded copies fit in 128 KB
+template <typename T> inline int update_c_in_lds(int wmax, int m) {
+    return (size_t)2 * ((wmax + 3) & ~3) * ((m + 15) & ~15) * sizeof(T) <= 128 * 1024;
+}
+template <typename T> inline size_t update_shmem(int wmax, int m) {
+    return update_c_in_lds<T>(wmax, m) ? (size_t)2 * ((wmax + 3) & ~3) * ((m + 15) & ~15) * sizeof(T) : 0;
+}
 
 int set_width(Solver &s, int w, int only_active) {
     hipLaunchKernelGGL(set_width_kernel, dim3(grid_for(s.n_obj, 64)), dim3(64), 0, s.st, s.n_obj, s.status, s.width,
@@ -1250,16 +1312,17 @@ int stage_gram_rr(Solver &s, T *S, T *HS, T *MS, double tau) {
                        s.gfirst, s.gcount, s.gpart, s.wmax, s.G);
     FF_CHECK_LAUNCH(s.ctx);
     hipLaunchKernelGGL(rr_kernel<typename Prec<T>::CT>, dim3(s.n_obj), dim3(kRRThreads), s.rr_shmem, s.st, s.status,
-                       s.width, s.G, s.wmax, s.m, tau, s.rrscr, s.rr_lds, s.C, cw_of<T>(s), s.theta, s.info);
+                       s.width, s.G, s.wmax, s.m, tau, s.rrscr, s.rr_lds, s.C, cw_of<T>(s), s.Cp, cpw_of<T>(s),
+                       s.theta, s.info);
     FF_CHECK_LAUNCH(s.ctx);
     return FF_OK;
 }
 
 template <typename T>
 int stage_update(Solver &s, T *S, T *HS, T *MS, int write_p) {
-    const size_t shmem = (size_t)((s.wmax + 3) & ~3) * ((s.m + 15) & ~15) * sizeof(T);
-    hipLaunchKernelGGL(update_kernel<T>, dim3(s.nu), dim3(256), shmem, s.st, s.uch, s.status, s.width, S, HS, MS,
-                       (int64_t)3 * s.m, s.m, s.wmax, (const T *)cw_of<T>(s), write_p);
+    hipLaunchKernelGGL(update_kernel<T>, dim3(s.nu), dim3(256), update_shmem<T>(s.wmax, s.m), s.st, s.uch, s.status,
+                       s.width, S, HS, MS, (int64_t)3 * s.m, s.m, s.wmax, (const T *)cw_of<T>(s),
+                       (const T *)cpw_of<T>(s), write_p, update_c_in_lds<T>(s.wmax, s.m));
     FF_CHECK_LAUNCH(s.ctx);
     return FF_OK;
 }
@@ -1353,6 +1416,15 @@ int run_phase(Solver &s, T *S, T *HS, T *MS, int max_iters, double tol, int stal
         }
         bool all = true;
         for (int o = 0; o < s.n_obj; ++o) all = all && hstat[o] != 0;
+        if (s.ctx->verbose) {
+            std::vector<double> rs((size_t)s.m);
+            if (hipMemcpy(rs.data(), s.res, rs.size() * sizeof(double), hipMemcpyDeviceToHost) == hipSuccess) {
+                double mx = 0.0;
+                for (int j = 0; j < s.k; ++j) mx = std::max(mx, rs[j]);
+                fprintf(stderr, "[freeform] %s it %d: object 0 max resid %.3e status %d\n",
+                        sizeof(T) == 4 ? "fp32" : "fp64", it, mx, hstat[0]);
+            }
+        }
         if (all) break;
     }
     if (exec) (void)hipGraphExecDestroy(exec);
@@ -1428,9 +1500,12 @@ int setup(Solver &s, const ff_eig_params *p) {
     s.res = s.theta + (size_t)n_obj * m;
     s.track = s.res + (size_t)n_obj * m;
     s.norms = s.track + 2 * (size_t)n_obj;
-    s.C = (double *)ws_get(ctx, WS_C, (size_t)n_obj * wmax * m * sizeof(double) * 2);
+    s.C = (double *)ws_get(ctx, WS_C, (size_t)n_obj * wmax * m * sizeof(double) * 4);
     s.C64w = s.C ? s.C + (size_t)n_obj * wmax * m : nullptr;
-    s.C32 = (float *)ws_get(ctx, WS_C32, (size_t)n_obj * wmax * m * sizeof(float));
+    s.Cp = s.C ? s.C + (size_t)2 * n_obj * wmax * m : nullptr;
+    s.Cp64w = s.C ? s.C + (size_t)3 * n_obj * wmax * m : nullptr;
+    s.C32 = (float *)ws_get(ctx, WS_C32, (size_t)n_obj * wmax * m * sizeof(float) * 2);
+    s.Cp32 = s.C32 ? s.C32 + (size_t)n_obj * wmax * m : nullptr;
     s.G = (double *)ws_get(ctx, WS_G, (size_t)n_obj * 2 * wmax * wmax * sizeof(double));
     s.gpart = (double *)ws_get(ctx, WS_GPART, (size_t)s.ng * 2 * wmax * wmax * sizeof(double));
     s.rpart = (double *)ws_get(ctx, WS_RPART, (size_t)std::max(s.nu, s.ng) * 2 * std::max(m, 2) * sizeof(double));
@@ -1453,13 +1528,10 @@ int setup(Solver &s, const ff_eig_params *p) {
                            s.dinv64, s.dinv32);
         FF_CHECK_LAUNCH(ctx);
     }
-    {
-        const int upd = (int)(((size_t)((wmax + 3) & ~3) * ((m + 15) & ~15)) * sizeof(double));
-        FF_HIP(ctx, hipFuncSetAttribute((const void *)update_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                        upd));
-        FF_HIP(ctx, hipFuncSetAttribute((const void *)update_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                        upd));
-    }
+    FF_HIP(ctx, hipFuncSetAttribute((const void *)update_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)update_shmem<double>(wmax, m)));
+    FF_HIP(ctx, hipFuncSetAttribute((const void *)update_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)update_shmem<float>(wmax, m)));
     // Rayleigh-Ritz storage: LDS when the two w x w FP64 matrices fit
     s.rr_lds = rr_use_lds(wmax);
     s.rr_shmem = rr_shmem_bytes(wmax, s.rr_lds);
@@ -1524,7 +1596,7 @@ int solve(ff_ctx *ctx, int n_obj, const int64_t *obj_off, const int64_t *row_ptr
     int rc = setup(s, p);
     if (rc) return rc;
     const int check_every = p->check_every > 0 ? p->check_every : 10;
-    const double tau32 = 3e-6, tau64 = 1e-13;
+    const double tau32 = 1e-5, tau64 = 1e-13;
 
     double *S64, *HS64, *MS64;
     if ((rc = alloc_blocks<double>(s, WS_D0, WS_HD0, WS_MD0, &S64, &HS64, &MS64))) return rc;
@@ -1548,7 +1620,7 @@ int solve(ff_ctx *ctx, int n_obj, const int64_t *obj_off, const int64_t *row_ptr
                            (const double *)X0d, (int64_t)m, S32, (int64_t)3 * m);
         FF_CHECK_LAUNCH(ctx);
         if ((rc = init_block<float>(s, S32, HS32, MS32, tau32))) return rc;
-        if ((rc = run_phase<float>(s, S32, HS32, MS32, p->max_iter, p->tol, 25, tau32, check_every, p->use_graph,
+        if ((rc = run_phase<float>(s, S32, HS32, MS32, p->max_iter, p->tol, 50, tau32, check_every, p->use_graph,
                                    s.refresh32, &it32)))
             return rc;
         hipLaunchKernelGGL((copy_block_kernel<double, float>), dim3(grid_for(s.N * m, 256)), dim3(256), 0, s.st, s.N, m,
@@ -1842,7 +1914,7 @@ extern "C" int rayleigh_ritz(ff_ctx *ctx, int w, int m, const double *G, double 
     hipStream_t st = ctx->stream;
     int *ints = (int *)ws_get(ctx, WS_OBJ, 256);
     double *scr = (double *)ws_get(ctx, WS_RRSCR, rr_scratch_doubles(w, m) * sizeof(double));
-    double *cw = (double *)ws_get(ctx, WS_C, (size_t)w * m * sizeof(double));
+    double *cw = (double *)ws_get(ctx, WS_C, (size_t)w * m * sizeof(double) * 3);
     if (!ints || !scr || !cw) return FF_ERR_OOM;
     int hi[3] = {0, w, 0};   // status, width, info
     FF_HIP(ctx, hipMemcpyAsync(ints, hi, sizeof(hi), hipMemcpyHostToDevice, st));
@@ -1852,7 +1924,7 @@ extern "C" int rayleigh_ritz(ff_ctx *ctx, int w, int m, const double *G, double 
     FF_HIP(ctx, hipFuncSetAttribute((const void *)rr_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)shm));
     hipLaunchKernelGGL(rr_kernel<double>, dim3(1), dim3(kRRThreads), shm, st, ints, ints + 1, G, w, m, tau,
-                       scr, lds, C, cw, theta, ints + 2);
+                       scr, lds, C, cw, cw + (size_t)w * m, cw + (size_t)2 * w * m, theta, ints + 2);
     FF_CHECK_LAUNCH(ctx);
     int h[3];
     FF_HIP(ctx, hipMemcpyAsync(h, ints, sizeof(h), hipMemcpyDeviceToHost, st));
