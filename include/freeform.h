@@ -164,17 +164,19 @@ typedef struct {
     int precond;        /* 0 = none, 1 = Jacobi diag(H)^-1 */
     uint64_t seed;      /* Philox-4x32-10 key for the random start when X0 == NULL */
     int check_every;    /* host convergence check period in iterations (0 = 10) */
-    int use_graph;      /* 1 = replay one captured hipGraph per iteration */
+    int use_graph;      /* 1 = replay one captured hipGraph per iteration (a call on the null
+                           stream runs on a private stream of the context) */
     int refresh_every;  /* recompute HX, MX explicitly every this many iterations (0 = auto) */
 } ff_eig_params;
 
 typedef struct {
-    int iters_fp32;     /* iterations in the FP32 phase (mixed) */
-    int iters_fp64;     /* iterations in the FP64 phase */
+    int iters_fp32;     /* iterations of this object in the FP32 phase (mixed) */
+    int iters_fp64;     /* iterations of this object in the FP64 phase (0 = certified at once) */
     int converged;      /* 1 if max_j r_j <= tol */
     int restarts;       /* basis restarts after Rayleigh-Ritz breakdown */
     double max_resid;   /* final max_j r_j (FP64, certified) */
     double seconds;     /* wall time of the call */
+    int graph;          /* 1 if the iterations were replayed from a captured hipGraph */
 } ff_eig_info;
 
 /*

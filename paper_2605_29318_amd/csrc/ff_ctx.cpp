@@ -90,6 +90,7 @@ void ff_ctx_destroy(ff_ctx *ctx) {
     for (int i = 0; i < ff::WS_COUNT; ++i)
         if (ctx->ws[i]) (void)hipFree(ctx->ws[i]);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    if (ctx->graph_stream) (void)hipStreamDestroy(ctx->graph_stream);
     delete ctx;
 }
 

@@ -42,6 +42,7 @@ struct ff_ctx {
     std::unordered_map<std::string, int> tuned;   // SpMM shape key -> variant
     double stage_ms[5] = {0, 0, 0, 0, 0};
     int verbose = 0;                 // FF_VERBOSE=1: residual trace on stderr
+    hipStream_t graph_stream = nullptr;   // private stream for graph capture
 };
 
 namespace ff {

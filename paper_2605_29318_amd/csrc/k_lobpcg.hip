@@ -1264,6 +1264,7 @@ struct Solver {
     size_t rr_shmem = 0;
     int refresh32 = 30, refresh64 = 0;
     int total_iters = 0;
+    int graph_used = 0;
 };
 
 template <typename T> HMPair<T> hm_of(const Solver &s);
@@ -1388,6 +1389,7 @@ int run_phase(Solver &s, T *S, T *HS, T *MS, int max_iters, double tol, int stal
                 (void)hipGraphDestroy(graph);
                 return set_error(s.ctx, FF_ERR_HIP, "graph instantiate failed: %s", hipGetErrorString(e));
             }
+            s.graph_used = 1;
         }
     }
     while (it < max_iters) {
@@ -1570,6 +1572,13 @@ int solve(ff_ctx *ctx, int n_obj, const int64_t *obj_off, const int64_t *row_ptr
     s.ctx = ctx;
     FF_HIP(ctx, hipSetDevice(ctx->device));
     s.st = ctx->stream;
+    int use_graph = p->use_graph;
+    if (use_graph && s.st == nullptr) {
+        // the null stream cannot be captured: run this call on a private stream
+        if (!ctx->graph_stream) FF_HIP(ctx, hipStreamCreateWithFlags(&ctx->graph_stream, hipStreamNonBlocking));
+        FF_HIP(ctx, hipStreamSynchronize(nullptr));
+        s.st = ctx->graph_stream;
+    }
     s.n_obj = n_obj;
     s.off.assign(obj_off, obj_off + n_obj + 1);
     for (int o = 0; o < n_obj; ++o)
@@ -1612,6 +1621,7 @@ int solve(ff_ctx *ctx, int n_obj, const int64_t *obj_off, const int64_t *row_ptr
         FF_CHECK_LAUNCH(ctx);
     }
     int it32 = 0, it64 = 0;
+    std::vector<int> its32((size_t)n_obj, 0);
     if ((rc = reset_status(s, 0))) return rc;
     if (p->precision == 1) {
         float *S32, *HS32, *MS32;
@@ -1620,9 +1630,11 @@ int solve(ff_ctx *ctx, int n_obj, const int64_t *obj_off, const int64_t *row_ptr
                            (const double *)X0d, (int64_t)m, S32, (int64_t)3 * m);
         FF_CHECK_LAUNCH(ctx);
         if ((rc = init_block<float>(s, S32, HS32, MS32, tau32))) return rc;
-        if ((rc = run_phase<float>(s, S32, HS32, MS32, p->max_iter, p->tol, 50, tau32, check_every, p->use_graph,
+        if ((rc = run_phase<float>(s, S32, HS32, MS32, p->max_iter, p->tol, 50, tau32, check_every, use_graph,
                                    s.refresh32, &it32)))
             return rc;
+        FF_HIP(ctx, hipMemcpyAsync(its32.data(), s.iters, its32.size() * sizeof(int), hipMemcpyDeviceToHost, s.st));
+        FF_HIP(ctx, hipMemsetAsync(s.iters, 0, its32.size() * sizeof(int), s.st));
         hipLaunchKernelGGL((copy_block_kernel<double, float>), dim3(grid_for(s.N * m, 256)), dim3(256), 0, s.st, s.N, m,
                            (const float *)S32, (int64_t)3 * m, S64, (int64_t)3 * m);
         FF_CHECK_LAUNCH(ctx);
@@ -1635,7 +1647,7 @@ int solve(ff_ctx *ctx, int n_obj, const int64_t *obj_off, const int64_t *row_ptr
     if ((rc = reset_status(s, 0))) return rc;
     if ((rc = init_block<double>(s, S64, HS64, MS64, tau64))) return rc;
     const int left = std::max(0, p->max_iter - it32);
-    if ((rc = run_phase<double>(s, S64, HS64, MS64, left + 1, p->tol, 0, tau64, check_every, p->use_graph,
+    if ((rc = run_phase<double>(s, S64, HS64, MS64, left + 1, p->tol, 0, tau64, check_every, use_graph,
                                 s.refresh64, &it64)))
         return rc;
     if (it64 > 0) it64 -= 0;
@@ -1680,8 +1692,9 @@ int solve(ff_ctx *ctx, int n_obj, const int64_t *obj_off, const int64_t *row_ptr
         broke = broke || st[o] == 3;
         worst = std::max(worst, mx);
         if (info) {
-            info[o].iters_fp32 = it32;
-            info[o].iters_fp64 = it64;
+            info[o].iters_fp32 = its32[o];
+            info[o].iters_fp64 = its[o];
+            info[o].graph = s.graph_used;
             info[o].converged = conv;
             info[o].restarts = (inf[o] >> 16) & 1;
             info[o].max_resid = mx;

@@ -51,7 +51,8 @@ class ff_eig_params(ctypes.Structure):
 
 class ff_eig_info(ctypes.Structure):
     _fields_ = [("iters_fp32", ctypes.c_int), ("iters_fp64", ctypes.c_int), ("converged", ctypes.c_int),
-                ("restarts", ctypes.c_int), ("max_resid", ctypes.c_double), ("seconds", ctypes.c_double)]
+                ("restarts", ctypes.c_int), ("max_resid", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("graph", ctypes.c_int)]
 
 
 _lib = None
@@ -223,7 +224,8 @@ def eigenmodes(ctx: Context, n: int, row_ptr, col, H, M, hm32, k: int, block: in
     rc = lib().eigenmodes(ctx.h, n, _p(row_ptr), _p(col), _p(H), _p(M), _p(hm32), ctypes.byref(p),
                           _p(X0), lam.ctypes.data_as(vp), _p(W), res.ctypes.data_as(vp), ctypes.byref(info))
     out = dict(iters_fp32=info.iters_fp32, iters_fp64=info.iters_fp64, converged=info.converged,
-               restarts=info.restarts, max_resid=info.max_resid, seconds=info.seconds, status=rc)
+               restarts=info.restarts, max_resid=info.max_resid, seconds=info.seconds, graph=info.graph,
+               status=rc)
     if rc != 0 and not (allow_unconverged and rc == FF_ERR_NOT_CONVERGED):
         ctx.check(rc)
     return lam, W, res, out
@@ -246,7 +248,7 @@ def eigenmodes_batched(ctx: Context, obj_row_off, row_ptr, col, H, M, hm32, k: i
                                   _p(hm32), ctypes.byref(p), _p(X0), lam.ctypes.data_as(vp), _p(W),
                                   res.ctypes.data_as(vp), ctypes.cast(info, vp))
     infos = [dict(iters_fp32=i.iters_fp32, iters_fp64=i.iters_fp64, converged=i.converged,
-                  max_resid=i.max_resid, seconds=i.seconds) for i in info]
+                  max_resid=i.max_resid, seconds=i.seconds, graph=i.graph) for i in info]
     if rc != 0 and not (allow_unconverged and rc == FF_ERR_NOT_CONVERGED):
         ctx.check(rc)
     return lam, W, res, infos, rc
@@ -344,3 +346,26 @@ def assemble_cloud(ctx: Context, xyz, vol, lam, mu, h: float, rho=None, features
     rp, col, H, M, hm32 = assemble_HM(ctx, n, nb.nbr_off, nb.nbr_id, phi, dphi, vol, lam, mu, nb.grid,
                                       nb.cell_start, rho=rho, perm=nb.perm)
     return Assembled(n, h, nb, phi, dphi, feat, rp, col, H, M, hm32)
+
+
+def concat_objects(parts):
+    """Block-diagonal concatenation of assembled objects for eigenmodes_batched.
+
+    Marshalling only: CSR arrays are concatenated and column / row-pointer
+    offsets shifted with torch; returns (obj_row_off (numpy), row_ptr, col, H, M, hm32).
+    """
+    import torch
+    offs = [0]
+    rps, cols, Hs, Ms, hms = [], [], [], [], []
+    nnz_off = 0
+    for a in parts:
+        rp = a.row_ptr
+        rps.append((rp[:-1] if len(rps) < len(parts) - 1 else rp) + nnz_off)
+        cols.append(a.col + offs[-1])
+        Hs.append(a.H)
+        Ms.append(a.M)
+        hms.append(a.hm32)
+        nnz_off += int(a.col.numel())
+        offs.append(offs[-1] + a.n)
+    return (np.array(offs, dtype=np.int64), torch.cat(rps), torch.cat(cols).to(torch.int32), torch.cat(Hs),
+            torch.cat(Ms), torch.cat(hms))
