@@ -280,6 +280,72 @@ int rand_block(ff_ctx *ctx, int64_t n, int m, uint64_t seed, double *out);
  */
 int philox4x32_10(ff_ctx *ctx, int count, const uint32_t *ctr, const uint32_t *key, uint32_t *out);
 
+/*
+ * Learned warm start (not in the paper, whose eigensolve starts from scratch;
+ * the sole network it trains is a comparison method). A small MLP maps
+ * per-point inputs to a block Y of k columns whose span approximates the span
+ * of the k smallest eigenmodes; eigenmodes() then starts from X0 = Y.
+ *
+ * Network: n_in -> 128 -> 128 -> 128 -> k, GELU(z) = z Phi(z) (exact erf
+ * form) after each hidden layer; BF16 weights and hidden activations, FP32
+ * accumulation and FP32 master parameters. Flat parameter order
+ * [W1 (128 x n_in), b1, W2 (128x128), b2, W3 (128x128), b3, W4 (k x 128), b4],
+ * each W output-major (row = output unit). n_in = 11 + 6 n_freq (mlp_inputs). Training minimises the subspace loss
+ *   L = k - tr(A^-1 B E B^T),  A = Y^T D Y,  B = Y^T D T,  E = (T^T D T)^-1
+ * (D = lumped mass, T = target modes of one object), which is zero when
+ * span(Y) = span(T) and does not depend on the scaling, sign or mixing of the
+ * columns of Y or T, with Adam (beta1 0.9, beta2 0.999, eps 1e-8).
+ * An ff_mlp belongs to the context it was created on; calls on it enqueue on
+ * that context's stream and must not overlap. Destroy it before that context
+ * (mlp_destroy itself does not touch the context).
+ */
+typedef struct ff_mlp ff_mlp;
+
+/* Parameter count for output width k (1 <= k <= 64) and input width n_in (1 <= n_in <= 128), or -1. */
+int mlp_param_count(int k, int n_in);
+/* New network with uniform(-1/sqrt(fan_in), 1/sqrt(fan_in)) weights (seeded) and zero biases. */
+int mlp_create(ff_ctx *ctx, int k, int n_in, uint64_t seed, ff_mlp **out);
+void mlp_destroy(ff_mlp *mlp);
+/* Copy all parameters in (host in, FP32, mlp_param_count(k) values); resets Adam's state. */
+int mlp_set_params(ff_mlp *mlp, const float *params);
+/* Copy the FP32 master parameters out (host out). */
+int mlp_get_params(ff_mlp *mlp, float *params);
+/* Copy the gradient of the last mlp_train_step out (host out, FP32). */
+int mlp_get_grad(ff_mlp *mlp, float *grad);
+
+/*
+ * mlp_inputs - the network inputs per node, from sorted positions and the raw
+ * features of rkpm_shape: position x centred on the bounding box and divided
+ * by its largest half extent, the 4 moment-matrix eigenvalues, neighbour count
+ * and kernel sum each divided by their mean over the object, the boundary
+ * indicator and the kernel-value spread (11 values); then for each octave
+ * l < n_freq, sin(pi 2^l x_a) for a = 0..2 and cos(pi 2^l x_a) for a = 0..2.
+ *  xyz_sorted [n][3] device in; feat [n][8] device in; 0 <= n_freq <= 19;
+ *  in [n][11 + 6 n_freq] device out (FP32)
+ */
+int mlp_inputs(ff_ctx *ctx, int64_t n, const double *xyz_sorted, const float *feat, int n_freq,
+               float *in);
+
+/*
+ * mlp_forward - Y = MLP(in) for n rows: in [n][n_in] device in (FP32);
+ * Y [n][ldy] device out (FP64, first k columns written, ldy >= k), ready as X0
+ * of eigenmodes (the columns beyond k can be filled with rand_block).
+ */
+int mlp_forward(ff_mlp *mlp, int64_t n, const float *in, double *Y, int64_t ldy);
+
+/*
+ * mlp_train_step - one Adam step on one object: forward, loss, backward, update.
+ *  in    [n][n_in] device in (FP32); T [n][ldt] device in (FP64, the first k
+ *  columns are the target modes, linearly independent); d [n] device in: the
+ *  lumped mass (positive); lr the step size; loss host out or NULL: L before
+ *  the step. n >= k.
+ */
+int mlp_train_step(ff_mlp *mlp, int64_t n, const float *in, const double *T, int64_t ldt,
+                   const double *d, float lr, double *loss);
+
+/* lumped_mass - d_i = sum_j M_ij (row sums of the FP64 CSR mass matrix). d [n] device out. */
+int lumped_mass(ff_ctx *ctx, int64_t n, const int64_t *row_ptr, const double *M, double *d);
+
 #ifdef __cplusplus
 }
 #endif

@@ -51,7 +51,7 @@ def _compile(src: str, nocontract: bool) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    srcs = [(s, nc) for s, nc in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+    srcs = list(SOURCES)
     with ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(lambda a: _compile(*a), srcs))
     tmp = OUT + ".tmp"

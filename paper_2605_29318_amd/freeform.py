@@ -12,6 +12,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import weakref
 from dataclasses import dataclass
 from typing import Optional
 
@@ -92,6 +93,16 @@ def lib():
         "spmm_variant_name": (ctypes.c_char_p, [i32]),
         "rand_block": (i32, [vp, i64, i32, ctypes.c_uint64, vp]),
         "philox4x32_10": (i32, [vp, i32, vp, vp, vp]),
+        "mlp_param_count": (i32, [i32, i32]),
+        "mlp_create": (i32, [vp, i32, i32, ctypes.c_uint64, P(vp)]),
+        "mlp_destroy": (None, [vp]),
+        "mlp_set_params": (i32, [vp, vp]),
+        "mlp_get_params": (i32, [vp, vp]),
+        "mlp_get_grad": (i32, [vp, vp]),
+        "mlp_inputs": (i32, [vp, i64, vp, vp, i32, vp]),
+        "mlp_forward": (i32, [vp, i64, vp, vp, i64]),
+        "mlp_train_step": (i32, [vp, i64, vp, vp, i64, vp, ctypes.c_float, P(f64)]),
+        "lumped_mass": (i32, [vp, i64, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -119,6 +130,7 @@ class Context:
         if rc != 0:
             raise FFError(rc, "ff_ctx_create failed")
         self.h = h
+        self._children = weakref.WeakSet()   # handles that must be released before the context
 
     def check(self, rc: int):
         if rc != 0:
@@ -126,6 +138,8 @@ class Context:
 
     def close(self):
         if self.h:
+            for c in list(self._children):
+                c.close()
             lib().ff_ctx_destroy(self.h)
             self.h = None
 
@@ -316,6 +330,93 @@ def philox4x32_10(ctx: Context, ctr, key):
     out = torch.empty_like(ctr)
     ctx.check(lib().philox4x32_10(ctx.h, ctr.shape[0], _p(ctr), _p(key), _p(out)))
     return out
+
+
+# ----------------------------------------------------------------------------
+# learned warm start
+# ----------------------------------------------------------------------------
+
+def mlp_param_count(k: int, n_in: int = 11) -> int:
+    return lib().mlp_param_count(k, n_in)
+
+
+class MLP:
+    """Handle of an ff_mlp (the warm-start network) on a context."""
+
+    def __init__(self, ctx: Context, k: int, n_in: int = 11, seed: int = 0):
+        self.ctx = ctx
+        self.k = k
+        self.n_in = n_in
+        self.h = None
+        self.P = mlp_param_count(k, n_in)
+        if self.P < 0:
+            raise FFError(FF_ERR_INVALID_ARG, f"k = {k} or n_in = {n_in} out of range")
+        h = ctypes.c_void_p()
+        ctx.check(lib().mlp_create(ctx.h, k, n_in, seed, ctypes.byref(h)))
+        self.h = h
+        ctx._children.add(self)
+
+    def close(self):
+        if self.h:
+            lib().mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params):
+        a = np.ascontiguousarray(params, dtype=np.float32)
+        assert a.size == self.P
+        self.ctx.check(lib().mlp_set_params(self.h, a.ctypes.data_as(vp)))
+
+    def get_params(self):
+        a = np.empty(self.P, dtype=np.float32)
+        self.ctx.check(lib().mlp_get_params(self.h, a.ctypes.data_as(vp)))
+        return a
+
+    def get_grad(self):
+        a = np.empty(self.P, dtype=np.float32)
+        self.ctx.check(lib().mlp_get_grad(self.h, a.ctypes.data_as(vp)))
+        return a
+
+    def _check_in(self, x):
+        if x.shape[1] != self.n_in or x.stride(0) != self.n_in:
+            raise FFError(FF_ERR_INVALID_ARG, f"inputs must be contiguous [n][{self.n_in}]")
+
+    def forward(self, x, ldy: Optional[int] = None, out=None):
+        """Y [n][ldy] FP64 with the first k columns written."""
+        import torch
+        self._check_in(x)
+        n = x.shape[0]
+        if out is None:
+            out = torch.zeros((n, ldy or self.k), dtype=torch.float64, device=x.device)
+        self.ctx.check(lib().mlp_forward(self.h, n, _p(x), _p(out), out.stride(0)))
+        return out
+
+    def train_step(self, x, T, d, lr: float) -> float:
+        self._check_in(x)
+        loss = ctypes.c_double()
+        self.ctx.check(lib().mlp_train_step(self.h, x.shape[0], _p(x), _p(T), T.stride(0), _p(d), lr,
+                                            ctypes.byref(loss)))
+        return loss.value
+
+
+def mlp_inputs(ctx: Context, xyz_sorted, feat, n_freq: int = 0):
+    import torch
+    n = xyz_sorted.shape[0]
+    out = torch.empty((n, 11 + 6 * n_freq), dtype=torch.float32, device=xyz_sorted.device)
+    ctx.check(lib().mlp_inputs(ctx.h, n, _p(xyz_sorted), _p(feat), n_freq, _p(out)))
+    return out
+
+
+def lumped_mass(ctx: Context, n: int, row_ptr, M):
+    import torch
+    d = torch.empty(n, dtype=torch.float64, device=M.device)
+    ctx.check(lib().lumped_mass(ctx.h, n, _p(row_ptr), _p(M), _p(d)))
+    return d
 
 
 # ----------------------------------------------------------------------------

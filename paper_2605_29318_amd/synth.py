@@ -249,12 +249,14 @@ def sphere_union(n: int = 100_000, seed: int = 1, r_disk: Optional[float] = None
 def ellipsoid_union(n: int = 1_000_000, seed: int = 3, hetero: bool = True, k: int = 32,
                     count: int = 20, support: float = 2.5, mc_samples: int = 4_000_000,
                     E: Optional[float] = None, nu: float = 0.45, rho: float = 1000.0,
-                    min_volume: float = 0.05) -> Cloud:
+                    min_volume: float = 0.05, sample_seed: Optional[int] = None) -> Cloud:
     """Uniform samples inside a union of 20 random ellipsoids (semi-axes U(0.05, 0.4)).
 
     ``hetero`` draws per-particle E log-uniform in [1e4, 1e6] Pa and nu
     uniform in [0.3, 0.48]; otherwise E (default: log-uniform per shape) and
-    nu are uniform over the object.
+    nu are uniform over the object. ``sample_seed`` (optional) seeds the
+    particle positions and materials separately from the shape, so one shape
+    can be sampled at several resolutions.
     """
     rng = np.random.default_rng(seed)
     while True:
@@ -262,6 +264,8 @@ def ellipsoid_union(n: int = 1_000_000, seed: int = 3, hetero: bool = True, k: i
         V = _mc_volume(shape, rng, mc_samples)
         if V >= min_volume and _connected(shape):
             break
+    if sample_seed is not None:
+        rng = np.random.default_rng([seed, sample_seed])
     xyz = _rejection_sample(shape, rng, n)
     s = (V / n) ** (1.0 / 3.0)
     if hetero:

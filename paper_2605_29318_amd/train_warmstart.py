@@ -1,0 +1,120 @@
+"""Train the warm-start network on seeded ellipsoid-union shapes and evaluate it
+on held-out shapes: LOBPCG iterations and seconds to residual tol from the
+network's block against a random block, on the same GPU.
+
+    python -m paper_2605_29318_amd.train_warmstart --train 48 --test 6 \
+        --train-n 20000 40000 --test-n 100000 100000 --k 32 --freq 6 --out weights.npy
+
+The full workload trains on 512 shapes of 20,000-100,000 particles and tests on
+100 shapes of 100,000-500,000 (--train 512 --train-n 20000 100000 --test 100
+--test-n 100000 500000). Shapes are homogeneous (one E per shape): the inputs
+carry no material, and homogeneous modes do not depend on E. Prints one JSON
+line per held-out shape and a summary line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+
+from . import freeform as ff
+from . import synth
+from . import warmstart as ws
+
+
+def _log(msg: str):
+    print(msg, flush=True)
+
+
+def _shapes(count: int, nmin: int, nmax: int, seed0: int, rng, k: int):
+    for j in range(count):
+        n = int(round(math.exp(rng.uniform(math.log(nmin), math.log(nmax)))))
+        yield j, synth.ellipsoid_union(n=n, seed=seed0 + j, hetero=False, k=k, mc_samples=400_000)
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--train", type=int, default=48)
+    ap.add_argument("--test", type=int, default=6)
+    ap.add_argument("--train-n", type=int, nargs=2, default=[20000, 40000])
+    ap.add_argument("--test-n", type=int, nargs=2, default=[100000, 100000])
+    ap.add_argument("--k", type=int, default=32)
+    ap.add_argument("--freq", type=int, default=ws.DEFAULT_FREQ)
+    ap.add_argument("--epochs", type=int, default=100)
+    ap.add_argument("--lr", type=float, default=3e-3)
+    ap.add_argument("--lr-final", type=float, default=3e-4)
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--precision", type=int, nargs="+", default=[1, 0])
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--out", type=str, default=None, help="save the FP32 parameters (.npy)")
+    a = ap.parse_args(argv)
+
+    import torch
+    if not torch.cuda.is_available():
+        _log("no GPU: the warm start trains and runs only on the device")
+        return 2
+    ctx = ff.Context(0)
+    k = a.k
+    rng = np.random.default_rng(a.seed)
+    t0 = time.time()
+    train = []
+    for j, c in _shapes(a.train, a.train_n[0], a.train_n[1], 10_000, rng, k):
+        try:
+            s = ws.with_targets(ctx, ws.prepare(ctx, c, n_freq=a.freq), k, tol=a.tol)
+        except ff.FFError as e:            # e.g. a thin part sampled too sparsely for the kernel support
+            _log(f"train shape {j}: skipped ({e})")
+            continue
+        train.append(s)
+        _log(f"train shape {j}: n={s.n} iters={s.info['iters_fp32']}+{s.info['iters_fp64']} "
+             f"({time.time() - t0:.1f} s)")
+    t1 = time.time()
+    net = ws.train(ctx, train, k, a.epochs, lr=a.lr, lr_final=a.lr_final, seed=a.seed,
+                   log=lambda m: _log(m) if int(m.split()[1].split("/")[0]) % 10 == 0 else None)
+    torch.cuda.synchronize()
+    train_s = time.time() - t1
+    if a.out:
+        np.save(a.out, net.get_params(), allow_pickle=False)
+    rows = []
+    for j, c in _shapes(a.test, a.test_n[0], a.test_n[1], 90_000, rng, k):
+        try:
+            s = ws.prepare(ctx, c, n_freq=a.freq)
+        except ff.FFError as e:
+            _log(f"test shape {j}: skipped ({e})")
+            continue
+        m = ((k + 7) // 8) * 8
+        row = dict(shape=j, n=s.n)
+        for prec in a.precision:
+            for mode in ("random", "warm"):
+                X0, used = ws.warm_block(ctx, net if mode == "warm" else None, s, m, seed=a.seed + 1)
+                lam, W, info = ws.solve(ctx, s, k, X0=X0, precision=prec, tol=a.tol)
+                row[f"p{prec}_{mode}"] = dict(iters=info["iters_fp32"] + info["iters_fp64"],
+                                              seconds=round(info["seconds"], 3), converged=info["converged"],
+                                              used_network=used, max_resid=info["max_resid"])
+                if mode == "random":
+                    lam_r = lam
+                else:
+                    row[f"p{prec}_dlam"] = float(np.abs(lam[1:] - lam_r[1:]).max() / np.abs(lam_r[1:]).max())
+        rows.append(row)
+        _log(json.dumps(row))
+    summ = dict(train_shapes=len(train), train_seconds=round(train_s, 2), k=k, freq=a.freq, epochs=a.epochs)
+    for prec in a.precision:
+        r = [x[f"p{prec}_random"]["iters"] for x in rows]
+        w = [x[f"p{prec}_warm"]["iters"] for x in rows]
+        rs = [x[f"p{prec}_random"]["seconds"] for x in rows]
+        wsec = [x[f"p{prec}_warm"]["seconds"] for x in rows]
+        summ[f"p{prec}"] = dict(iters_random=float(np.mean(r)), iters_warm=float(np.mean(w)),
+                                seconds_random=float(np.mean(rs)), seconds_warm=float(np.mean(wsec)),
+                                iter_ratio=float(np.mean(np.array(w) / np.array(r))),
+                                used_network=sum(x[f"p{prec}_warm"]["used_network"] for x in rows))
+    _log("SUMMARY " + json.dumps(summ))
+    net.close()
+    ctx.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -34,8 +34,22 @@ def test_library_exports_every_declared_symbol():
 def test_binding_names_match_header():
     from paper_2605_29318_amd import freeform
     for n in ("build_neighbors", "rkpm_shape", "assemble_HM", "eigenmodes", "eigenmodes_batched", "spmm_hm",
-              "spmm_autotune", "rand_block", "philox4x32_10"):
+              "spmm_autotune", "rand_block", "philox4x32_10", "mlp_param_count", "mlp_inputs", "lumped_mass"):
         assert callable(getattr(freeform, n))
+    # every declared entry point has a ctypes signature in the binding
+    L = freeform.lib()
+    unbound = [n for n in _declared() if getattr(L, n).argtypes is None]
+    assert not unbound, unbound
+
+
+def test_mlp_param_count_matches_reference_layout():
+    from paper_2605_29318_amd import freeform
+    from oracle import mlp
+    for k in (1, 8, 16, 32, 64):
+        for n_in in (11, 47, 128):
+            assert freeform.mlp_param_count(k, n_in) == mlp.param_count(k, n_in)
+    assert freeform.mlp_param_count(0) == -1 and freeform.mlp_param_count(65) == -1
+    assert freeform.mlp_param_count(8, 129) == -1 and freeform.mlp_param_count(8, 0) == -1
 
 
 def test_philox_reference_matches_published_vectors():

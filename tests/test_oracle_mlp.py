@@ -73,3 +73,115 @@ def test_adam_moves_against_the_gradient_and_lowers_the_loss():
         L, g = R.loss_and_grad(p, X, T, d, k)
         p, m, v = R.adam_step(p, g, m, v, t, lr=3e-3)
     assert L < L0
+
+
+def _lattice(m=7, a=0.1, jitter=0.0, seed=0):
+    g = np.arange(m) * a
+    X = np.stack(np.meshgrid(g, g, g, indexing="ij"), axis=-1).reshape(-1, 3)
+    if jitter:
+        X = X + np.random.default_rng(seed).uniform(-jitter, jitter, X.shape)
+    return X
+
+
+def _features(oracle, X, h, kernel=0):
+    off, ids = oracle.neighbors_brute(X, X, h)
+    return R.rkpm_features(X, X, off, ids, h, kernel), off
+
+
+@pytest.mark.parametrize("kernel", [0, 1])
+def test_features_symmetric_lattice_interior(oracle, kernel):
+    """At the centre of a cubic lattice the neighbourhood is symmetric: the first
+    moments vanish (boundary indicator 0) and the normalised moment matrix is
+    diag(1, s, s, s) with s < 1, so three eigenvalues coincide and the largest is 1."""
+    X = _lattice()
+    h = 0.25
+    F, off = _features(oracle, X, h, kernel)
+    c = int(np.argmin(((X - X.mean(axis=0)) ** 2).sum(axis=1)))
+    f = F[c]
+    assert abs(f[6]) <= 1e-14
+    assert abs(f[3] - 1.0) <= 1e-14
+    assert np.ptp(f[0:3]) <= 1e-14 and 0 < f[0] < 1
+    assert f[4] == off[c + 1] - off[c]
+    # 4/3 pi (h/a)^3 lattice points in the ball, up to the shell: a count check by enumeration
+    g = np.arange(-3, 4)
+    cnt = sum(1 for i in g for j in g for k in g if (i * i + j * j + k * k) * 0.01 < h * h)
+    assert f[4] == cnt
+
+
+def test_features_face_points_inward(oracle):
+    """On the z = 0 face the kernel-weighted offset points into the body (+z)."""
+    X = _lattice()
+    h = 0.25
+    off, ids = oracle.neighbors_brute(X, X, h)
+    face = np.where((X[:, 2] == 0) & (np.abs(X[:, 0] - 0.3) < 1e-9) & (np.abs(X[:, 1] - 0.3) < 1e-9))[0][0]
+    f = R.rkpm_features(X, X, off, ids, h)[face]
+    nb = X[ids[off[face]:off[face + 1]]]
+    w = R._raw_kernel(np.linalg.norm(nb - X[face], axis=1), h, 0)
+    v = (w[:, None] * (nb - X[face])).sum(axis=0)
+    assert abs(v[0]) <= 1e-14 and abs(v[1]) <= 1e-14 and v[2] > 0
+    assert f[6] > 0.1
+
+
+def test_features_rigid_motion_invariant(oracle):
+    X = _lattice(m=6, jitter=0.02, seed=4)
+    h = 0.25
+    F, _ = _features(oracle, X, h)
+    Q = np.linalg.qr(np.random.default_rng(5).standard_normal((3, 3)))[0]
+    Y = X @ Q.T + np.array([3.0, -1.0, 0.5])
+    G, _ = _features(oracle, Y, h)
+    assert np.allclose(F, G, rtol=1e-10, atol=1e-12)
+
+
+def test_features_flat_kernel_limit(oracle):
+    """Gaussian with support far beyond the cloud: every phi~ is about 1, so the
+    spread tends to 0, the sum to n, and the moment matrix to [[1, m^T], [m, C]]
+    with C the second moments of (p - X)/h, all small next to 1."""
+    X = _lattice(m=4, a=0.01, jitter=0.002, seed=1)
+    h = 1000.0
+    F, _ = _features(oracle, X, h, kernel=1)
+    n = X.shape[0]
+    assert np.all(F[:, 4] == n)
+    assert np.allclose(F[:, 5], n, rtol=1e-7)
+    assert np.all(F[:, 7] <= 1e-7)
+    assert np.all(np.abs(F[:, 3] - 1.0) <= 1e-7) and np.all(np.abs(F[:, 0:3]) <= 1e-7)
+    Xc = X - X.mean(axis=0)
+    assert np.allclose(F[:, 6], np.linalg.norm(-Xc, axis=1) / h, rtol=1e-6)
+
+
+def test_position_encoding_octaves():
+    """Each octave doubles the angle of the previous one: sin 2t = 2 sin t cos t,
+    cos 2t = cos^2 t - sin^2 t; the first octave is sin/cos(pi x) of the normalised
+    position; the base 11 inputs are unchanged."""
+    rng = np.random.default_rng(3)
+    xyz = rng.uniform(-2, 5, size=(200, 3))
+    feat = rng.uniform(0.1, 1.0, size=(200, 8))
+    base = R.inputs(xyz, feat)
+    enc = R.inputs(xyz, feat, n_freq=5)
+    assert enc.shape == (200, 41)
+    assert np.array_equal(enc[:, :11], base)
+    x = base[:, 0:3]
+    assert np.abs(x).max() == pytest.approx(1.0)
+    assert np.allclose(enc[:, 11:14], np.sin(np.pi * x), atol=1e-15)
+    for l in range(1, 5):
+        s0, c0 = enc[:, 5 + 6 * l: 8 + 6 * l], enc[:, 8 + 6 * l: 11 + 6 * l]
+        s1, c1 = enc[:, 11 + 6 * l: 14 + 6 * l], enc[:, 14 + 6 * l: 17 + 6 * l]
+        assert np.allclose(s1, 2 * s0 * c0, atol=1e-12)
+        assert np.allclose(c1, c0 * c0 - s0 * s0, atol=1e-12)
+
+
+def test_gradient_with_encoded_inputs():
+    rng = np.random.default_rng(4)
+    n, k, n_in = 200, 5, 23
+    X = rng.standard_normal((n, n_in))
+    T = np.linalg.qr(rng.standard_normal((n, k)))[0]
+    d = rng.uniform(0.5, 2.0, size=n)
+    p = R.init_params(k, seed=1, n_in=n_in)
+    assert p.size == R.param_count(k, n_in) and R.input_width(p, k) == n_in
+    L, g = R.loss_and_grad(p, X, T, d, k)
+    for i in rng.choice(128 * n_in, size=20, replace=False):     # first-layer weights
+        h = 1e-6
+        pp, pm = p.copy(), p.copy()
+        pp[i] += h
+        pm[i] -= h
+        fd = (R.loss_and_grad(pp, X, T, d, k)[0] - R.loss_and_grad(pm, X, T, d, k)[0]) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, np.abs(g).max())
