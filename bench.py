@@ -159,6 +159,7 @@ def main():
 
     m = args.k if args.k % 8 == 0 else ((args.k + 7) // 8) * 8
     spmm_ms, alg_bytes = spmm_rate(ff, ctx, A, c.n, m)
+    variant = ff.spmm_variant_names()[ff.spmm_variant_selected(ctx, c.n, nnz, m, 1)]
     achieved = alg_bytes / (spmm_ms * 1e-3) / 1e9
     log(f"[bench] spmm fp32: {spmm_ms:.3f} ms, {achieved:.0f} GB/s algorithmic")
 
@@ -195,7 +196,7 @@ def main():
         "spmm_gbps": round(achieved, 1),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "spmm_kernel<float> (fused [H,M] Y, m=%d)" % m,
+                     "kernel": "fused [H,M] Y SpMM, FP32, m=%d, variant %s" % (m, variant),
                      "bytes_per_launch": alg_bytes, "launch_ms": round(spmm_ms, 4)},
         "cpu_baseline": cpu,
     }

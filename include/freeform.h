@@ -263,6 +263,9 @@ int rayleigh_ritz(ff_ctx *ctx, int w, int m, const double *G, double tau, double
 /* Number of SpMM tile variants and a description of one (host strings). */
 int spmm_variant_count(void);
 const char *spmm_variant_name(int variant);
+/* The variant that spmm_hm(variant = -1) and eigenmodes use for a matrix of this shape:
+ * the one spmm_autotune stored in the context, else the built-in default. */
+int spmm_variant_selected(ff_ctx *ctx, int64_t n, int64_t nnz, int m, int precision);
 
 /*
  * rand_block - Philox-4x32-10 (Salmon et al., SC'11) uniform numbers in [-1, 1):

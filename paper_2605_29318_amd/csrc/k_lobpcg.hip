@@ -155,6 +155,96 @@ __global__ void __launch_bounds__(64 * kWaves) spmm_kernel(int64_t nrows, const 
     }
 }
 
+// Chunked variant: the wave reads 64 (col, h, m) entries of its row with one
+// coalesced load per lane, prefetches the next 64 while it works on these,
+// hands each entry to the lane group that needs it by cross-lane shuffles and
+// keeps kBatch independent gathers of Y rows in flight per lane.
+template <typename T, int kWaves, int kBatch, int kOcc>
+__global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(kOcc, 8)))
+spmm_chunk_kernel(int64_t nrows, const int64_t *row_ptr, const int32_t *col, HMPair<T> hm, const T *Y, int64_t ldy,
+                  T *HY, T *MY, int64_t ldo, int m, const int *row_obj, const int *obj_status) {
+    typedef typename Vec<T>::type V;
+    constexpr int VN = Vec<T>::n;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t r = (int64_t)b * kWaves + wv;
+    if (r >= nrows) return;
+    if (obj_status && obj_status[row_obj[r]] != 0) return;
+    const int G = m / VN;
+    const int NG = 64 / G;
+    const int g = lane / G, c = lane - g * G;
+    const bool on = g < NG;
+    const int steps = (64 + NG - 1) / NG;
+    const int64_t e0 = row_ptr[r], e1 = row_ptr[r + 1];
+    Acc4 aH, aM;
+    acc_zero(aH);
+    acc_zero(aM);
+    int32_t jn = 0;
+    T hn = 0, mn = 0;
+    if (e0 + lane < e1) {
+        jn = __builtin_nontemporal_load(col + e0 + lane);
+        hm.get(e0 + lane, hn, mn);
+    }
+    for (int64_t base = e0; base < e1; base += 64) {
+        const int cnt = (int)(e1 - base < 64 ? e1 - base : 64);
+        const int32_t jc = jn;
+        const T hc = hn, mc = mn;
+        jn = 0;
+        hn = mn = 0;
+        if (base + 64 + lane < e1) {
+            jn = __builtin_nontemporal_load(col + base + 64 + lane);
+            hm.get(base + 64 + lane, hn, mn);
+        }
+        for (int s0 = 0; s0 < steps; s0 += kBatch) {
+            // issue every gather of the batch first, then fetch the values and accumulate
+            V x[kBatch];
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                const int src = (s0 + u) * NG + g;
+                const int32_t j = __shfl(jc, src < 64 ? src : 63, 64);
+                const bool ok = on && (s0 + u < steps) && src < cnt;
+                if (ok)
+                    x[u] = *(const V *)(Y + (int64_t)j * ldy + c * VN);
+                else
+                    x[u] = V{};
+            }
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                const int src = (s0 + u) * NG + g;
+                const int sl = src < 64 ? src : 63;
+                const bool ok = on && (s0 + u < steps) && src < cnt;
+                const T hv = __shfl(hc, sl, 64), mvv = __shfl(mc, sl, 64);
+                acc_fma(aH, ok ? hv : T(0), x[u]);
+                acc_fma(aM, ok ? mvv : T(0), x[u]);
+            }
+        }
+    }
+    if ((64 % G) == 0) {
+        for (int d = G; d < 64; d <<= 1) {
+            acc_add_shfl(aH, d, VN);
+            acc_add_shfl(aM, d, VN);
+        }
+    } else {
+        __shared__ double red[kWaves][2][4][64];
+        for (int q = 0; q < VN; ++q) {
+            red[wv][0][q][lane] = aH.v[q];
+            red[wv][1][q][lane] = aM.v[q];
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (g == 0) {
+            for (int t = 1; t < NG; ++t)
+                for (int q = 0; q < VN; ++q) {
+                    aH.v[q] += red[wv][0][q][t * G + c];
+                    aM.v[q] += red[wv][1][q][t * G + c];
+                }
+        }
+    }
+    if (g == 0) {
+        acc_store(HY + r * ldo + c * VN, aH);
+        acc_store(MY + r * ldo + c * VN, aM);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Gram products G_H = S^T HS, G_M = S^T MS over the first w columns (MFMA)
 // ---------------------------------------------------------------------------
@@ -179,11 +269,12 @@ template <> struct MfmaAcc<double> {
 __device__ inline f32x4 mfma(float a, float b, f32x4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
 __device__ inline f64x4 mfma(double a, double b, f64x4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
 
-template <typename T>
+// MT is the arithmetic type: FP32 blocks may run on FP64 MFMA (their products are exact in FP64).
+template <typename T, typename MT>
 __global__ void __launch_bounds__(512) gram_kernel(const GChunk *chunks, const int *obj_status, const int *width,
                                                    const T *S, const T *HS, const T *MS, int64_t ld, int wmax,
                                                    double *part) {
-    typedef typename MfmaAcc<T>::type Acc;
+    typedef typename MfmaAcc<MT>::type Acc;
     const GChunk ch = chunks[blockIdx.x];
     if (obj_status[ch.obj] != 0) return;
     const int w = width[ch.obj];
@@ -221,11 +312,11 @@ __global__ void __launch_bounds__(512) gram_kernel(const GChunk *chunks, const i
     for (int64_t r = r0; r < r1; r += 4) {
         const int64_t row = r + lk;
         const bool rv = row < r1;
-        T fa[3], fb[3];
+        MT fa[3], fb[3];
 #pragma unroll
         for (int t = 0; t < 3; ++t) {
-            fa[t] = (rv && va[t]) ? S[row * ld + ca[t]] : (T)0;
-            fb[t] = (rv && vb[t]) ? B[row * ld + cb[t]] : (T)0;
+            fa[t] = (rv && va[t]) ? (MT)S[row * ld + ca[t]] : (MT)0;
+            fb[t] = (rv && vb[t]) ? (MT)B[row * ld + cb[t]] : (MT)0;
         }
 #pragma unroll
         for (int a = 0; a < 3; ++a)
@@ -253,7 +344,7 @@ __global__ void __launch_bounds__(512) gram_kernel(const GChunk *chunks, const i
             if (tI >= T16 || tJ >= T16) continue;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int i = tI * 16 + MfmaAcc<T>::row(lk, v), j = tJ * 16 + li;
+                const int i = tI * 16 + MfmaAcc<MT>::row(lk, v), j = tJ * 16 + li;
                 if (i < w && j < w) P[(size_t)i * wmax + j] = tot[a][c][v] + (double)acc[a][c][v];
             }
         }
@@ -1203,8 +1294,12 @@ __global__ void count_iter_kernel(int n_obj, const int *obj_status, int *iters) 
 }
 
 static const char *kVariantNames[] = {"waves4_unroll2_xcd", "waves4_unroll4_xcd", "waves8_unroll2_xcd",
-                                      "waves4_unroll2_linear", "waves2_unroll4_xcd", "waves8_unroll4_xcd"};
-constexpr int kNumVariants = 6;
+                                      "waves4_unroll2_linear", "waves2_unroll4_xcd", "waves8_unroll4_xcd",
+                                      "chunk64_waves4_batch8", "chunk64_waves2_batch8", "chunk64_waves8_batch8",
+                                      "chunk64_waves4_batch4", "chunk64_waves2_batch8_occ6",
+                                      "chunk64_waves4_batch4_occ8", "chunk64_waves2_batch16"};
+constexpr int kNumVariants = 13;
+constexpr int kDefaultVariant = 11;    // fastest untuned choice on 10^5-10^6-row RKPM matrices
 
 template <typename T>
 int launch_spmm(ff_ctx *ctx, hipStream_t st, int variant, int64_t nrows, const int64_t *row_ptr, const int32_t *col,
@@ -1213,7 +1308,17 @@ int launch_spmm(ff_ctx *ctx, hipStream_t st, int variant, int64_t nrows, const i
 #define FF_SPMM(W, U, X)                                                                                        \
     hipLaunchKernelGGL((spmm_kernel<T, W, U, X>), dim3(grid_for(nrows, W)), dim3(64 * W), 0, st, nrows, row_ptr, \
                        col, hm, Y, ldy, HY, MY, ldo, m, row_obj, status)
+#define FF_SPMMC(W, B, O)                                                                                         \
+    hipLaunchKernelGGL((spmm_chunk_kernel<T, W, B, O>), dim3(grid_for(nrows, W)), dim3(64 * W), 0, st, nrows,      \
+                       row_ptr, col, hm, Y, ldy, HY, MY, ldo, m, row_obj, status)
     switch (variant) {
+        case 6: FF_SPMMC(4, 8, 1); break;
+        case 7: FF_SPMMC(2, 8, 1); break;
+        case 8: FF_SPMMC(8, 8, 1); break;
+        case 9: FF_SPMMC(4, 4, 1); break;
+        case 10: FF_SPMMC(2, 8, 6); break;
+        case 11: FF_SPMMC(4, 4, 8); break;
+        case 12: FF_SPMMC(2, 16, 1); break;
         case 1: FF_SPMM(4, 4, true); break;
         case 2: FF_SPMM(8, 2, true); break;
         case 3: FF_SPMM(4, 2, false); break;
@@ -1222,6 +1327,7 @@ int launch_spmm(ff_ctx *ctx, hipStream_t st, int variant, int64_t nrows, const i
         default: FF_SPMM(4, 2, true); break;
     }
 #undef FF_SPMM
+#undef FF_SPMMC
     FF_CHECK_LAUNCH(ctx);
     return FF_OK;
 }
@@ -1305,8 +1411,8 @@ int stage_spmm(Solver &s, T *S, T *HS, T *MS, int slot) {
 template <typename T>
 int stage_gram_rr(Solver &s, T *S, T *HS, T *MS, double tau) {
     const int T16 = (s.wmax + 15) / 16, nsup = (T16 + 5) / 6;
-    hipLaunchKernelGGL(gram_kernel<T>, dim3(s.ng, nsup * nsup), dim3(512), 0, s.st, s.gch, s.status, s.width, S, HS,
-                       MS, (int64_t)3 * s.m, s.wmax, s.gpart);
+    hipLaunchKernelGGL((gram_kernel<T, T>), dim3(s.ng, nsup * nsup), dim3(512), 0, s.st, s.gch, s.status, s.width, S,
+                       HS, MS, (int64_t)3 * s.m, s.wmax, s.gpart);
     FF_CHECK_LAUNCH(s.ctx);
     const int64_t per2 = 2 * (int64_t)s.wmax * s.wmax;
     hipLaunchKernelGGL(gram_reduce_kernel, dim3(grid_for(per2, 256), s.n_obj), dim3(256), 0, s.st, s.status, s.width,
@@ -1553,7 +1659,7 @@ std::string tune_key(int64_t n, int64_t nnz, int m, int precision) {
 
 int lookup_variant(ff_ctx *ctx, int64_t n, int64_t nnz, int m, int precision) {
     auto it = ctx->tuned.find(tune_key(n, nnz, m, precision));
-    return it == ctx->tuned.end() ? 0 : it->second;
+    return it == ctx->tuned.end() ? kDefaultVariant : it->second;
 }
 
 int solve(ff_ctx *ctx, int n_obj, const int64_t *obj_off, const int64_t *row_ptr, const int32_t *col, const double *H,
@@ -1606,6 +1712,7 @@ int solve(ff_ctx *ctx, int n_obj, const int64_t *obj_off, const int64_t *row_ptr
     if (rc) return rc;
     const int check_every = p->check_every > 0 ? p->check_every : 10;
     const double tau32 = 1e-5, tau64 = 1e-13;
+    constexpr int kStall32 = 200;
 
     double *S64, *HS64, *MS64;
     if ((rc = alloc_blocks<double>(s, WS_D0, WS_HD0, WS_MD0, &S64, &HS64, &MS64))) return rc;
@@ -1630,7 +1737,10 @@ int solve(ff_ctx *ctx, int n_obj, const int64_t *obj_off, const int64_t *row_ptr
                            (const double *)X0d, (int64_t)m, S32, (int64_t)3 * m);
         FF_CHECK_LAUNCH(ctx);
         if ((rc = init_block<float>(s, S32, HS32, MS32, tau32))) return rc;
-        if ((rc = run_phase<float>(s, S32, HS32, MS32, p->max_iter, p->tol, 50, tau32, check_every, use_graph,
+        // the FP32 phase ends at tol, or when its residual has not dropped by 10% for kStall32
+        // iterations (its rounding floor); the largest residual is not monotone, and bumps
+        // lasting tens of iterations occur in exact arithmetic too
+        if ((rc = run_phase<float>(s, S32, HS32, MS32, p->max_iter, p->tol, kStall32, tau32, check_every, use_graph,
                                    s.refresh32, &it32)))
             return rc;
         FF_HIP(ctx, hipMemcpyAsync(its32.data(), s.iters, its32.size() * sizeof(int), hipMemcpyDeviceToHost, s.st));
@@ -1765,6 +1875,11 @@ extern "C" int spmm_hm(ff_ctx *ctx, int64_t n, const int64_t *row_ptr, const int
 }
 
 extern "C" int spmm_variant_count(void) { return kNumVariants; }
+
+extern "C" int spmm_variant_selected(ff_ctx *ctx, int64_t n, int64_t nnz, int m, int precision) {
+    if (!ctx) return FF_ERR_INVALID_ARG;
+    return lookup_variant(ctx, n, nnz, m, precision);
+}
 
 extern "C" const char *spmm_variant_name(int variant) {
     return (variant >= 0 && variant < kNumVariants) ? kVariantNames[variant] : "invalid";
@@ -1905,10 +2020,10 @@ extern "C" int gram_hm(ff_ctx *ctx, int64_t n, int w, int precision, const void 
     FF_HIP(ctx, hipStreamSynchronize(st));
     const int T16 = (w + 15) / 16, nsup = (T16 + 5) / 6;
     if (precision)
-        hipLaunchKernelGGL(gram_kernel<float>, dim3(ng, nsup * nsup), dim3(512), 0, st, gch, ints, ints + 1,
+        hipLaunchKernelGGL((gram_kernel<float, float>), dim3(ng, nsup * nsup), dim3(512), 0, st, gch, ints, ints + 1,
                            (const float *)S, (const float *)HS, (const float *)MS, ld, w, part);
     else
-        hipLaunchKernelGGL(gram_kernel<double>, dim3(ng, nsup * nsup), dim3(512), 0, st, gch, ints, ints + 1,
+        hipLaunchKernelGGL((gram_kernel<double, double>), dim3(ng, nsup * nsup), dim3(512), 0, st, gch, ints, ints + 1,
                            (const double *)S, (const double *)HS, (const double *)MS, ld, w, part);
     FF_CHECK_LAUNCH(ctx);
     const int64_t per2 = 2 * (int64_t)w * w;

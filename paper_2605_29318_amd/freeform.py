@@ -91,6 +91,7 @@ def lib():
         "rayleigh_ritz": (i32, [vp, i32, i32, vp, f64, vp, vp, P(i32)]),
         "spmm_variant_count": (i32, []),
         "spmm_variant_name": (ctypes.c_char_p, [i32]),
+        "spmm_variant_selected": (i32, [vp, i64, i64, i32, i32]),
         "rand_block": (i32, [vp, i64, i32, ctypes.c_uint64, vp]),
         "philox4x32_10": (i32, [vp, i32, vp, vp, vp]),
         "mlp_param_count": (i32, [i32, i32]),
@@ -310,6 +311,12 @@ def rayleigh_ritz(ctx: Context, G, m: int, tau: float = 1e-13):
     kept = ctypes.c_int()
     ctx.check(lib().rayleigh_ritz(ctx.h, w, m, _p(G.contiguous()), tau, _p(C), _p(theta), ctypes.byref(kept)))
     return theta, C, kept.value
+
+
+def spmm_variant_selected(ctx: Context, n: int, nnz: int, m: int, precision: int) -> int:
+    v = lib().spmm_variant_selected(ctx.h, n, nnz, m, precision)
+    ctx.check(min(v, 0))
+    return v
 
 
 def spmm_variant_names():

@@ -304,7 +304,7 @@ def initial_block(n: int, m: int, seed: int) -> np.ndarray:
 # ----------------------------------------------------------------------------
 
 def workload(name: str) -> Cloud:
-    """The named synthetic workloads (see the design doc for the recipes)."""
+    """The named synthetic workloads, built by the generators above."""
     if name == "cube1k":
         return cube_lattice()
     if name == "spheres100k":
