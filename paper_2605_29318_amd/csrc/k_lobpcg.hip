@@ -541,57 +541,69 @@ __global__ void __launch_bounds__(256) update_kernel(const UChunk *chunks, const
     }
 }
 
-// ---------------------------------------------------------------------------
-// FP64 Rayleigh-Ritz, one workgroup per object
-// ---------------------------------------------------------------------------
-//
-// Input: G_H, G_M over the object's w basis columns. Steps:
-//   1. symmetrise, scale both by D^-1/2 with D = diag(G_M)
-//   2. Cholesky of the scaled G_M in column order, dropping a column whose
-//      pivot falls to tau or below (a direction already spanned); the X
-//      columns come first, so only W and P directions are dropped
-//   3. L^-1 (one thread per column), then A = L^-1 G_H L^-T as two FP64 MFMA
-//      products
-//   4. Householder reduction of A to tridiagonal T = Q^T A Q (reflector j is
-//      kept in row j, contiguous, for the back-transform)
-//   5. the m smallest eigenvalues of T by multisection on Sturm counts (a
-//      group of threads per eigenvalue), eigenvectors by inverse iteration
-//      with partial pivoting; eigenvalues closer than 1e-9 ||T|| form a cluster
-//      that one thread handles in order, orthogonalising each member against
-//      the earlier ones
-//   6. one wavefront per vector: y -> Q y -> L^-T Q y -> D^-1/2 L^-T Q y = C;
-//      theta = Rayleigh quotient on T
-// A and B live in LDS when 2 w^2 doubles fit, else in a global scratch area.
-
-constexpr int kRRThreads = 256;
+constexpr int kRRThreads = 1024;          // stage 1: one workgroup per object
+constexpr int kRRWaves = kRRThreads / 64;
 constexpr int kRRMax = 192;
+constexpr size_t kRRLdsLimit = 156 * 1024;
 
-// per-object Rayleigh-Ritz scratch (doubles): A, B, two staging areas, vectors, solver work
+// Per-object Rayleigh-Ritz scratch in global memory (doubles):
+//   A    [wmax^2]  on exit of stage 1 the Householder reflectors (reflector j in
+//                  row j, stride ld); the working matrix when it does not fit in LDS
+//   B    [wmax^2]  on exit L^-1 (lower triangle, stride ld); working G_M likewise
+//   S1, S2 [wmax^2] staging for the two MFMA products
+//   sc, dg, eg, tg, evs [wmax each]; kidx [wmax] (kept column -> original),
+//   kpos [wmax] (original column -> kept index or -1); meta [16]; Yv [m * wmax]
+struct RRScr {
+    double *A, *B, *S1, *S2, *sc, *dg, *eg, *tg, *evs, *kidx, *kpos, *meta, *Yv;
+};
 __host__ __device__ inline size_t rr_scratch_doubles(int wmax, int m) {
-    return (size_t)4 * wmax * wmax + (size_t)m * wmax + (size_t)m * 4 * wmax;
+    return (size_t)4 * wmax * wmax + (size_t)7 * wmax + 16 + (size_t)m * wmax;
 }
+__device__ inline RRScr rr_scr(double *scratch, int o, int wmax, int m) {
+    const size_t ww = (size_t)wmax * wmax;
+    double *base = scratch + (size_t)o * rr_scratch_doubles(wmax, m);
+    RRScr g;
+    g.A = base;
+    g.B = base + ww;
+    g.S1 = base + 2 * ww;
+    g.S2 = base + 3 * ww;
+    g.sc = base + 4 * ww;
+    g.dg = g.sc + wmax;
+    g.eg = g.dg + wmax;
+    g.tg = g.eg + wmax;
+    g.evs = g.tg + wmax;
+    g.kidx = g.evs + wmax;
+    g.kpos = g.kidx + wmax;
+    g.meta = g.kpos + wmax;
+    g.Yv = g.meta + 16;
+    return g;
+}
+enum { RR_R = 0, RR_LD, RR_GL, RR_GU, RR_TNORM, RR_PIVMIN };
 
-// LDS plan: the two w x w FP64 matrices plus 10 per-column arrays when they fit
-// next to the kernel's static arrays, else only the per-column arrays
+// stage 1 keeps A and B in LDS when both fit next to its per-column arrays
+// (sc, dl, psh, dg, eg, tg and eight partial-sum rows)
+constexpr int kRRAux = 14;
 inline int rr_use_lds(int wmax) {
-    return ((size_t)2 * wmax * wmax + (size_t)10 * wmax) * sizeof(double) <= 156 * 1024;
+    return ((size_t)2 * wmax * wmax + (size_t)kRRAux * wmax) * sizeof(double) <= kRRLdsLimit;
 }
 inline size_t rr_shmem_bytes(int wmax, int use_lds) {
-    return ((use_lds ? (size_t)2 * wmax * wmax : 0) + (size_t)10 * wmax) * sizeof(double);
+    return ((use_lds ? (size_t)2 * wmax * wmax : 0) + (size_t)kRRAux * wmax) * sizeof(double);
+}
+// stage 3 keeps the reflectors in LDS when they fit
+inline int rr_vec_lds(int wmax) { return ((size_t)wmax * wmax + (size_t)6 * wmax) * sizeof(double) <= kRRLdsLimit; }
+inline size_t rr_vec_shmem_bytes(int wmax, int refl_lds) {
+    return ((refl_lds ? (size_t)wmax * wmax : 0) + (size_t)6 * wmax) * sizeof(double);
 }
 
-__device__ inline void rr_barrier() { __syncthreads(); }
-
-// one-barrier block sum; parity alternates between calls so the partials of
-// one call are never overwritten before every thread has read them
-__device__ inline double rr_sum(double v, double (*wsum)[4], int &par) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-    if ((threadIdx.x & 63) == 0) wsum[par][threadIdx.x >> 6] = v;
+// workgroup barrier that also orders the group's global scratch accesses
+__device__ inline void rr_sync() {
+    __threadfence_block();
     __syncthreads();
-    const double s = (wsum[par][0] + wsum[par][1]) + (wsum[par][2] + wsum[par][3]);
-    par ^= 1;
-    return s;
+}
+// barrier for the working matrices: LDS only, or global scratch
+template <bool kLds> __device__ inline void rr_bar() {
+    if (!kLds) __threadfence_block();
+    __syncthreads();
 }
 
 // number of eigenvalues of T (diag dg, offdiag eg) below x
@@ -608,18 +620,15 @@ __device__ inline int sturm_count(const double *dg, const double *eg, int r, dou
     return cnt;
 }
 
-// Solve (T - lam I) x = b in place (b -> x) with partial pivoting. Work
-// arrays are interleaved across threads: element i of this thread's array a
-// lives at wk[(a * r + i) * stride] (stride = number of solving threads).
-__device__ inline void tri_solve(const double *dg, const double *eg, int r, double lam, double tiny,
-                                 double *__restrict__ x, int xs, double *__restrict__ wk, int ws) {
-    double *dd = wk, *du = wk + (size_t)r * ws, *du2 = wk + (size_t)2 * r * ws;
-    // forward elimination, applied to the right-hand side on the fly; the sign of fac marks a pivot swap
+// Solve (T - lam I) x = b in place (b -> x) with partial pivoting; wk holds 3 r doubles.
+__device__ inline void tri_solve(const double *dg, const double *eg, int r, double lam, double tiny, double *x,
+                                 double *wk) {
+    double *dd = wk, *du = wk + r, *du2 = wk + 2 * r;
     double dcur = dg[0] - lam, ucur = r > 1 ? eg[0] : 0.0;
     double bcur = x[0];
     for (int i = 0; i + 1 < r; ++i) {
         const double ai1 = dg[i + 1] - lam, ei = eg[i], ei1 = (i + 2 < r) ? eg[i + 1] : 0.0;
-        const double bnext = x[(size_t)(i + 1) * xs];
+        const double bnext = x[i + 1];
         double dnext, unext, f, u2, di, ui, bi, bn;
         if (fabs(dcur) >= fabs(ei)) {
             if (dcur == 0.0) dcur = tiny;
@@ -631,7 +640,7 @@ __device__ inline void tri_solve(const double *dg, const double *eg, int r, doub
             unext = ei1;
             bi = bcur;
             bn = bnext - f * bcur;
-        } else {
+        } else {                                   // row swap
             f = dcur / ei;
             di = ei;
             ui = ai1;
@@ -641,21 +650,20 @@ __device__ inline void tri_solve(const double *dg, const double *eg, int r, doub
             bi = bnext;
             bn = bcur - f * bnext;
         }
-        dd[(size_t)i * ws] = di;
-        du[(size_t)i * ws] = ui;
-        du2[(size_t)i * ws] = u2;
-        x[(size_t)i * xs] = bi;
+        dd[i] = di;
+        du[i] = ui;
+        du2[i] = u2;
+        x[i] = bi;
         dcur = dnext;
         ucur = unext;
         bcur = bn;
     }
     if (dcur == 0.0) dcur = tiny;
-    // back substitution
     double x1 = bcur / dcur, x2 = 0.0;
-    x[(size_t)(r - 1) * xs] = x1;
+    x[r - 1] = x1;
     for (int i = r - 2; i >= 0; --i) {
-        const double xi = (x[(size_t)i * xs] - du[(size_t)i * ws] * x1 - du2[(size_t)i * ws] * x2) / dd[(size_t)i * ws];
-        x[(size_t)i * xs] = xi;
+        const double xi = (x[i] - du[i] * x1 - du2[i] * x2) / dd[i];
+        x[i] = xi;
         x2 = x1;
         x1 = xi;
     }
@@ -668,19 +676,20 @@ __device__ unsigned long long rr_clock[16];
 #define RR_MARK(i) do { } while (0)
 #endif
 
-// Dst = X Y (transY = 0) or X Y^T (transY = 1), r x r, stride ld, FP64 MFMA 16x16x4;
+// Dst = op(X) op(Y) with op(Z) = Z or Z^T, r x r, stride ld, FP64 MFMA 16x16x4;
 // the result goes to dst (a different buffer); entries beyond r are not written.
-__device__ inline void rr_gemm(const double *X, const double *Y, int transY, int r, int ld, double *dst) {
+__device__ inline void rr_gemm(const double *X, const double *Y, int transX, int transY, int r, int ld, double *dst) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int li = lane & 15, lk = lane >> 4;
     const int nt = (r + 15) >> 4;
-    for (int tile = wv; tile < nt * nt; tile += kRRThreads / 64) {
+    for (int tile = wv; tile < nt * nt; tile += kRRWaves) {
         const int ti = tile / nt, tj = tile - (tile / nt) * nt;
         f64x4 acc = {0.0, 0.0, 0.0, 0.0};
         const int row = ti * 16 + li, col = tj * 16 + li;
         for (int k0 = 0; k0 < r; k0 += 4) {
             const int kk = k0 + lk;
-            const double a = (row < r && kk < r) ? X[(size_t)row * ld + kk] : 0.0;
+            double a = 0.0;
+            if (row < r && kk < r) a = transX ? X[(size_t)kk * ld + row] : X[(size_t)row * ld + kk];
             double b = 0.0;
             if (col < r && kk < r) b = transY ? Y[(size_t)col * ld + kk] : Y[(size_t)kk * ld + col];
             acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
@@ -693,35 +702,59 @@ __device__ inline void rr_gemm(const double *X, const double *Y, int transY, int
     }
 }
 
-template <typename CT>
-__global__ void __launch_bounds__(kRRThreads) rr_kernel(int *obj_status, int *width, const double *G, int wmax,
-                                                        int m, double tau, double *scratch, int use_lds,
-                                                        double *C, CT *Cw, double *Cp, CT *Cpw, double *theta,
-                                                        int *info) {
+// ---------------------------------------------------------------------------
+// FP64 Rayleigh-Ritz on the pencil (G_H, G_M) of order w, in four launches
+// ---------------------------------------------------------------------------
+//
+// Stage 1 (rr_tridiag_kernel, one 1024-thread workgroup per object):
+//   1. symmetrise, scale both by D^-1/2 with D = diag(G_M)
+//   2. Cholesky of the scaled G_M in column order (one barrier per column),
+//      dropping a column whose pivot falls to tau or below (a direction
+//      already spanned); the X columns come first, so normally only W and P
+//      directions are dropped
+//   3. compaction to the kept columns, L^-1 in place, A = L^-1 G_H L^-T as two
+//      FP64 MFMA products
+//   4. Householder reduction of A to tridiagonal T = Q^T A Q (reflector j
+//      kept in row j), three barriers per column
+// Stage 2 (rr_eig_kernel, one wavefront per wanted eigenvalue): multisection
+//   on Sturm counts, 64 points per round.
+// Stage 3 (rr_vec_kernel, one wavefront per eigenvalue): inverse iteration
+//   with partial pivoting; eigenvalues closer than 1e-9 ||T|| form a cluster
+//   that its first wavefront handles in order, orthogonalising each member
+//   against the earlier ones; then y -> Q y -> L^-T Q y -> D^-1/2 L^-T Q y = C,
+//   theta = Rayleigh quotient on T.
+// Stage 4 (rr_post_kernel, one workgroup per column): the P coefficients
+//   C_p' = C_p - C (C^T G_M C_p) with C_p = C without its X rows, so that
+//   P' = S C_p' is M-orthogonal to X' = S C; FP32 copies for the FP32 update.
+
+// kLds: A and B in LDS (a compile-time choice, so that their accesses are LDS
+// instructions rather than generic ones)
+template <bool kLds>
+__global__ void __launch_bounds__(kRRThreads) rr_tridiag_kernel(int *obj_status, const int *width, const double *G,
+                                                                int wmax, int m, double tau, double *scratch,
+                                                                int *info) {
+    constexpr bool use_lds = kLds;
     const int o = blockIdx.x;
     if (obj_status[o] != 0) return;
     const int w = width[o];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     extern __shared__ __align__(16) double sm[];
     const size_t ww = (size_t)wmax * wmax;
-    double *gs = scratch + (size_t)o * rr_scratch_doubles(wmax, m);
-    double *A = use_lds ? sm : gs;
-    double *B = use_lds ? sm + ww : gs + ww;
-    double *st1 = gs + 2 * ww;                     // staging (ww)
-    double *st2 = gs + 3 * ww;                     // staging (ww)
-    double *Yv = gs + 4 * ww;                      // eigenvectors of T, element i of vector t at Yv[i*m + t]
-    double *wk = Yv + (size_t)m * wmax;            // inverse iteration work, 4 wmax per thread, interleaved
-    // per-column arrays after the matrices in dynamic LDS: sc, dl, dg, eg, tg, psh, ppart[4]
+    const RRScr g = rr_scr(scratch, o, wmax, m);
+    double *A = use_lds ? sm : g.A;
+    double *B = use_lds ? sm + ww : g.B;
     double *aux = sm + (use_lds ? 2 * ww : 0);
-    double *sc = aux, *dl = aux + wmax, *dg = aux + 2 * wmax, *eg = aux + 3 * wmax, *tg = aux + 4 * wmax;
-    double *psh = aux + 5 * wmax, *ppart = aux + 6 * wmax;
+    double *sc = aux, *dl = aux + wmax, *psh = aux + 2 * wmax, *dg = aux + 3 * wmax, *eg = aux + 4 * wmax;
+    double *tg = aux + 5 * wmax, *ppart = aux + 6 * wmax;   // ppart: 8 rows of partial sums
     __shared__ int keep[kRRMax], kidx[kRRMax];
-    __shared__ double wsum[2][4];
-    __shared__ double evs[128];
     __shared__ int nkeep, xdrop;
-    int par = 0;
+    // partial sums: wave wv takes every 8th inner index (kset) for one 64-wide pass of outputs
+    const int kset = wv & 7, opass = wv >> 3;
     const double *GH = G + (size_t)o * 2 * ww;
     const double *GM = GH + ww;
+    // Every LDS matrix access below runs along a row (consecutive lanes, consecutive
+    // addresses): with a row stride of 96 doubles a column access would put all
+    // 64 lanes on one bank.
 
     RR_MARK(0);
     // 1. load, symmetrise, scale
@@ -730,17 +763,19 @@ __global__ void __launch_bounds__(kRRThreads) rr_kernel(int *obj_status, int *wi
         sc[j] = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
     }
     if (tid == 0) xdrop = 0;
-    rr_barrier();
-    for (int i = wv; i < w; i += 4)
+    rr_sync();
+    for (int i = wv; i < w; i += kRRWaves)
         for (int j = lane; j < w; j += 64) {
             const double s = sc[i] * sc[j];
             A[(size_t)i * wmax + j] = 0.5 * (GH[(size_t)i * wmax + j] + GH[(size_t)j * wmax + i]) * s;
             B[(size_t)i * wmax + j] = 0.5 * (GM[(size_t)i * wmax + j] + GM[(size_t)j * wmax + i]) * s;
         }
-    rr_barrier();
+    rr_sync();
 
     RR_MARK(1);
-    // 2. right-looking Cholesky with dropping (column j staged in psh)
+    // 2. Cholesky G_M = U^T U on the upper triangle with dropping. Step j updates
+    //    the trailing upper triangle with the unscaled row j (B_il -= B_ji B_jl / piv)
+    //    and scales the previous row, which nothing reads any more.
     for (int j = 0; j < w; ++j) {
         const double piv = B[(size_t)j * wmax + j];
         const bool kj = sc[j] > 0.0 && piv > tau;
@@ -749,22 +784,19 @@ __global__ void __launch_bounds__(kRRThreads) rr_kernel(int *obj_status, int *wi
             dl[j] = kj ? sqrt(piv) : 0.0;
             if (!kj && j < m) xdrop = 1;
         }
+        if (j > 0 && keep[j - 1]) {
+            const double inv = 1.0 / dl[j - 1];
+            for (int l = j + tid; l < w; l += kRRThreads) B[(size_t)(j - 1) * wmax + l] *= inv;
+        }
         if (kj) {
-            const double inv = 1.0 / sqrt(piv);
-            for (int i = j + 1 + tid; i < w; i += kRRThreads) {
-                const double v = B[(size_t)i * wmax + j] * inv;
-                B[(size_t)i * wmax + j] = v;
-                psh[i] = v;
+            const double ip = 1.0 / piv;
+            const double *rowj = B + (size_t)j * wmax;
+            for (int i = j + 1 + wv; i < w; i += kRRWaves) {
+                const double bji = rowj[i] * ip;
+                for (int l = i + lane; l < w; l += 64) B[(size_t)i * wmax + l] -= bji * rowj[l];
             }
         }
-        rr_barrier();
-        if (kj) {
-            for (int i = j + 1 + wv; i < w; i += 4) {
-                const double pi = psh[i];
-                for (int l = j + 1 + lane; l <= i; l += 64) B[(size_t)i * wmax + l] -= pi * psh[l];
-            }
-        }
-        rr_barrier();
+        rr_bar<kLds>();
     }
     if (tid == 0) {
         int r = 0;
@@ -773,61 +805,88 @@ __global__ void __launch_bounds__(kRRThreads) rr_kernel(int *obj_status, int *wi
         nkeep = r;
         info[o] = r | (xdrop << 16);
     }
-    rr_barrier();
+    for (int j = tid; j < w; j += kRRThreads)     // diagonal of U
+        if (keep[j]) B[(size_t)j * wmax + j] = dl[j];
+    rr_sync();
     const int r = nkeep;
     if (r < m) {                                   // basis lost rank: report and leave C untouched
         if (tid == 0) obj_status[o] = 3;
         return;
     }
-    const int ld = r < w ? r : wmax;               // compact stride when columns were dropped
+    const int ld = r < w ? r : wmax;
 
     RR_MARK(2);
-    // 3. L^-1 (thread c solves L x = e_c on the kept columns) into st1, A_KK into st2
-    for (int c = tid; c < r; c += kRRThreads) {
-        for (int i = 0; i < c; ++i) st1[(size_t)i * ld + c] = 0.0;
-        for (int i = c; i < r; ++i) {
-            double sacc = i == c ? 1.0 : 0.0;
-            const double *Li = B + (size_t)kidx[i] * wmax;
-            for (int t = c; t < i; ++t) sacc -= Li[kidx[t]] * st1[(size_t)t * ld + c];
-            st1[(size_t)i * ld + c] = sacc / dl[kidx[i]];
+    // 3a. compaction to the kept rows and columns at stride r: a destination
+    //     never lies after its source, and each chunk is read before it is written
+    if (r < w) {
+        const int tot = r * r;
+        for (int base = 0; base < tot; base += kRRThreads) {
+            const int idx = base + tid;
+            double va = 0.0, vb = 0.0;
+            if (idx < tot) {
+                const int i = idx / r, jj = idx - (idx / r) * r;
+                va = A[(size_t)kidx[i] * wmax + kidx[jj]];
+                vb = jj >= i ? B[(size_t)kidx[i] * wmax + kidx[jj]] : 0.0;
+            }
+            rr_sync();
+            if (idx < tot) {
+                A[idx] = va;
+                B[idx] = vb;
+            }
+            rr_sync();
         }
     }
-    if (ld != wmax)
-        for (int i = wv; i < r; i += 4)
-            for (int j = lane; j < r; j += 64) st2[(size_t)i * ld + j] = A[(size_t)kidx[i] * wmax + kidx[j]];
-    __threadfence_block();
-    rr_barrier();
-    for (int i = wv; i < r; i += 4)
-        for (int j = lane; j < r; j += 64) {
-            B[(size_t)i * ld + j] = st1[(size_t)i * ld + j];
-            if (ld != wmax) A[(size_t)i * ld + j] = st2[(size_t)i * ld + j];
+    // 3b. V = U^-1 in place, rows from the last: with U = [a b^T; 0 U2],
+    //     U^-1 = [1/a, -b^T U2^-1 / a; 0, U2^-1]
+    //     The sums over t run as eight partial sums (t = kset mod 8) along rows t of V.
+    for (int j = r - 1; j >= 0; --j) {
+        const double *bj = B + (size_t)j * ld;
+        const double d = 1.0 / bj[j];
+        for (int l = j + 1 + lane + 64 * opass; l < r; l += 128) {
+            double s = 0.0;
+            for (int t = j + 1 + kset; t <= l; t += 8) s += bj[t] * B[(size_t)t * ld + l];
+            ppart[kset * wmax + l] = s;
         }
-    rr_barrier();
-    // A <- (L^-1 A) L^-T, symmetrised
-    rr_gemm(B, A, 0, r, ld, st1);
-    __threadfence_block();
-    rr_barrier();
-    for (int i = wv; i < r; i += 4)
-        for (int j = lane; j < r; j += 64) A[(size_t)i * ld + j] = st1[(size_t)i * ld + j];
-    rr_barrier();
-    rr_gemm(A, B, 1, r, ld, st2);
-    __threadfence_block();
-    rr_barrier();
-    for (int i = wv; i < r; i += 4)
+        rr_bar<kLds>();
+        for (int l = j + 1 + tid; l < r; l += kRRThreads) {
+            double s = 0.0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) s += ppart[q * wmax + l];
+            B[(size_t)j * ld + l] = -d * s;
+        }
+        if (tid == 0) B[(size_t)j * ld + j] = d;
+        rr_bar<kLds>();
+    }
+    for (int i = wv; i < r; i += kRRWaves)         // zero the strict lower triangle for the products
+        for (int j = lane; j < i; j += 64) B[(size_t)i * ld + j] = 0.0;
+    rr_sync();
+    // 3c. A <- (V^T A) V = L^-1 A L^-T (L = U^T) through the global staging areas, symmetrised
+    rr_gemm(B, A, 1, 0, r, ld, g.S1);
+    rr_sync();
+    rr_gemm(g.S1, B, 0, 0, r, ld, g.S2);
+    rr_sync();
+    for (int i = wv; i < r; i += kRRWaves)
         for (int j = lane; j < r; j += 64)
-            A[(size_t)i * ld + j] = 0.5 * (st2[(size_t)i * ld + j] + st2[(size_t)j * ld + i]);
-    rr_barrier();
+            A[(size_t)i * ld + j] = 0.5 * (g.S2[(size_t)i * ld + j] + g.S2[(size_t)j * ld + i]);
+    rr_sync();
 
     RR_MARK(3);
-    // 4. Householder tridiagonalisation; reflector j: v = [1, x/(x0 - beta)] kept in row j, columns j+1..
+    // 4. Householder tridiagonalisation of the symmetric A. Column j is read as
+    //    row j; reflector j, v = [1, x/(x0 - beta)], is written over row j at
+    //    step j + 1 (no step reads a row above its own).
+    double scale_prev = 0.0, tj_prev = 0.0;
     for (int j = 0; j + 2 < r; ++j) {
-        const double x0 = A[(size_t)(j + 1) * ld + j];
-        double part = 0.0;
-        for (int i = j + 2 + tid; i < r; i += kRRThreads) {
-            const double x = A[(size_t)i * ld + j];
-            part += x * x;
+        if (j > 0 && tj_prev != 0.0) {
+            double *rp = A + (size_t)(j - 1) * ld;
+            for (int k = j + tid; k < r; k += kRRThreads) rp[k] = k == j ? 1.0 : rp[k] * scale_prev;
         }
-        const double sigma = rr_sum(part, wsum, par);
+        const double *rowj = A + (size_t)j * ld;
+        const double x0 = rowj[j + 1];
+        double part = 0.0;                         // every wave forms sigma itself
+        for (int i = j + 2 + lane; i < r; i += 64) part += rowj[i] * rowj[i];
+#pragma unroll
+        for (int dd = 32; dd >= 1; dd >>= 1) part += __shfl_xor(part, dd, 64);
+        const double sigma = part;
         double tj = 0.0, beta = x0, scale = 0.0;
         if (sigma > 0.0) {
             const double mu = sqrt(x0 * x0 + sigma);
@@ -840,149 +899,229 @@ __global__ void __launch_bounds__(kRRThreads) rr_kernel(int *obj_status, int *wi
             eg[j] = beta;
             tg[j] = tj;
         }
-        if (tj == 0.0) continue;
-        // v into row j (columns j+1..r-1); p = tau A_sub v by k-quarters (wave) and rows (lane)
-        for (int i = j + 1 + tid; i < r; i += kRRThreads)
-            A[(size_t)j * ld + i] = i == j + 1 ? 1.0 : A[(size_t)i * ld + j] * scale;
-        rr_barrier();
-        const double *vrow = A + (size_t)j * ld;
-        for (int i = j + 1 + lane; i < r; i += 64) {
-            double sacc = 0.0;
-            for (int k = j + 1 + wv; k < r; k += 4) sacc += A[(size_t)k * ld + i] * vrow[k];
-            ppart[wv * wmax + i] = sacc;
+        scale_prev = scale;
+        tj_prev = tj;
+        if (tj == 0.0) {                           // uniform: every wave has the same sigma
+            rr_bar<kLds>();
+            continue;
         }
-        rr_barrier();
-        double part2 = 0.0;
-        for (int i = j + 1 + tid; i < r; i += kRRThreads) {
-            const double pi = tj * ((ppart[i] + ppart[wmax + i]) + (ppart[2 * wmax + i] + ppart[3 * wmax + i]));
-            psh[i] = pi;
-            part2 += pi * vrow[i];
+        // p = tau A v as eight partial sums over k (rows k of the symmetric A, lanes along i)
+        for (int i = j + 1 + lane + 64 * opass; i < r; i += 128) {
+            double s = 0.0;
+            for (int k = j + 1 + kset; k < r; k += 8) s += A[(size_t)k * ld + i] * (k == j + 1 ? 1.0 : rowj[k] * scale);
+            ppart[kset * wmax + i] = s;
         }
-        const double K = 0.5 * tj * rr_sum(part2, wsum, par);
-        for (int i = j + 1 + wv; i < r; i += 4) {
-            const double vi = vrow[i], wi = psh[i] - K * vi;
-            for (int k = j + 1 + lane; k < r; k += 64) {
-                const double vk = vrow[k], wk_ = psh[k] - K * vk;
-                A[(size_t)i * ld + k] -= vi * wk_ + wi * vk;
+        rr_bar<kLds>();
+        // every wave: p and v on its lanes' columns, then K = tau/2 p^T v
+        double pk[3], vk3[3], kp = 0.0;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int k = j + 1 + lane + 64 * q;
+            pk[q] = 0.0;
+            vk3[q] = 0.0;
+            if (k < r) {
+                double s = 0.0;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) s += ppart[u * wmax + k];
+                pk[q] = tj * s;
+                vk3[q] = k == j + 1 ? 1.0 : rowj[k] * scale;
+                kp += pk[q] * vk3[q];
             }
         }
-        rr_barrier();
+#pragma unroll
+        for (int dd = 32; dd >= 1; dd >>= 1) kp += __shfl_xor(kp, dd, 64);
+        const double K = 0.5 * tj * kp;
+        for (int i = j + 1 + wv; i < r; i += kRRWaves) {
+            double pi = 0.0;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) pi += ppart[u * wmax + i];
+            const double vi = i == j + 1 ? 1.0 : rowj[i] * scale, wi = tj * pi - K * vi;
+            double *ai = A + (size_t)i * ld;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const int k = j + 1 + lane + 64 * q;
+                if (k < r) ai[k] -= vi * (pk[q] - K * vk3[q]) + wi * vk3[q];
+            }
+        }
+        rr_bar<kLds>();
+    }
+    if (r >= 3 && tj_prev != 0.0) {                // the last reflector's row
+        double *rp = A + (size_t)(r - 3) * ld;
+        for (int k = r - 2 + tid; k < r; k += kRRThreads) rp[k] = k == r - 2 ? 1.0 : rp[k] * scale_prev;
     }
     if (tid == 0) {
         if (r >= 2) {
             dg[r - 2] = A[(size_t)(r - 2) * ld + (r - 2)];
-            eg[r - 2] = A[(size_t)(r - 1) * ld + (r - 2)];
+            eg[r - 2] = A[(size_t)(r - 2) * ld + (r - 1)];
             tg[r - 2] = 0.0;
         }
         dg[r - 1] = A[(size_t)(r - 1) * ld + (r - 1)];
         tg[r - 1] = 0.0;
         eg[r - 1] = 0.0;
     }
-    rr_barrier();
+    rr_sync();
 
     RR_MARK(4);
-    // 5. eigenvalues by multisection: a group of P threads per eigenvalue
-    double gl = 0.0, gu = 0.0, maxe2 = 0.0;
-    for (int i = 0; i < r; ++i) {
-        const double off = (i > 0 ? fabs(eg[i - 1]) : 0.0) + (i + 1 < r ? fabs(eg[i]) : 0.0);
-        gl = i == 0 ? dg[i] - off : fmin(gl, dg[i] - off);
-        gu = i == 0 ? dg[i] + off : fmax(gu, dg[i] + off);
-        if (i + 1 < r) maxe2 = fmax(maxe2, eg[i] * eg[i]);
+    // 5. hand over: T, reflectors (rows of A), L^-1 = V^T (row s of L^-1 = column s
+    //    of V), column maps and Gershgorin bounds
+    for (int idx = tid; idx < r * r; idx += kRRThreads) {
+        const int i = idx / r, sidx = idx - (idx / r) * r;
+        if (use_lds) g.A[(size_t)i * ld + sidx] = A[(size_t)i * ld + sidx];
+        g.S1[(size_t)sidx * ld + i] = B[(size_t)i * ld + sidx];
     }
-    const double tnorm = fmax(fabs(gl), fabs(gu));
-    const double eps = 2.220446049250313e-16;
-    gl -= 4.0 * eps * tnorm + 1e-300;
-    gu += 4.0 * eps * tnorm + 1e-300;
-    const double pivmin = 2.2250738585072014e-308 * fmax(1.0, maxe2);
-    {
-        int P = 1;
-        while (P * 2 * m <= kRRThreads && P < 64) P *= 2;
-        const int t = tid / P, sub = tid - (tid / P) * P;
-        double lo = gl, hi = gu;
-        if (t < m) {
-            for (int it = 0; it < 64; ++it) {
-                if (hi - lo <= 2.0 * eps * fmax(fabs(lo), fabs(hi)) + pivmin) break;
-                const double x = lo + (hi - lo) * (double)(sub + 1) / (double)(P + 1);
-                const bool above = sturm_count(dg, eg, r, x, pivmin) > t;
-                // new bracket: the highest point still below the eigenvalue and the lowest above it
-                double nlo = above ? lo : x, nhi = above ? x : hi;
-                for (int d = 1; d < P; d <<= 1) {
-                    nlo = fmax(nlo, __shfl_xor(nlo, d, 64));
-                    nhi = fmin(nhi, __shfl_xor(nhi, d, 64));
-                }
-                lo = nlo;
-                hi = nhi;
-            }
-            if (sub == 0) evs[t] = 0.5 * (lo + hi);
+    for (int i = tid; i < w; i += kRRThreads) {
+        g.sc[i] = sc[i];
+        g.kpos[i] = -1.0;
+    }
+    rr_sync();
+    for (int idx = tid; idx < r * r; idx += kRRThreads) {
+        const int i = idx / r, sidx = idx - (idx / r) * r;
+        g.B[(size_t)i * ld + sidx] = g.S1[(size_t)i * ld + sidx];
+    }
+    for (int i = tid; i < r; i += kRRThreads) {
+        g.dg[i] = dg[i];
+        g.eg[i] = eg[i];
+        g.tg[i] = tg[i];
+        g.kidx[i] = (double)kidx[i];
+        g.kpos[kidx[i]] = (double)i;
+    }
+    if (tid == 0) {
+        double gl = 0.0, gu = 0.0, maxe2 = 0.0;
+        for (int i = 0; i < r; ++i) {
+            const double off = (i > 0 ? fabs(eg[i - 1]) : 0.0) + (i + 1 < r ? fabs(eg[i]) : 0.0);
+            gl = i == 0 ? dg[i] - off : fmin(gl, dg[i] - off);
+            gu = i == 0 ? dg[i] + off : fmax(gu, dg[i] + off);
+            if (i + 1 < r) maxe2 = fmax(maxe2, eg[i] * eg[i]);
         }
+        const double tnorm = fmax(fabs(gl), fabs(gu));
+        const double eps = 2.220446049250313e-16;
+        g.meta[RR_R] = r;
+        g.meta[RR_LD] = ld;
+        g.meta[RR_GL] = gl - (4.0 * eps * tnorm + 1e-300);
+        g.meta[RR_GU] = gu + (4.0 * eps * tnorm + 1e-300);
+        g.meta[RR_TNORM] = tnorm;
+        g.meta[RR_PIVMIN] = 2.2250738585072014e-308 * fmax(1.0, maxe2);
     }
-    rr_barrier();
-
     RR_MARK(5);
-    // eigenvectors by inverse iteration; clusters handled in order by their first thread
-    const double ctol = 1e-9 * tnorm;
-    const double tiny = eps * tnorm + 1e-300;
-    if (tid < m && (tid == 0 || evs[tid] - evs[tid - 1] > ctol)) {
-        int u = tid;
-        const int u0 = tid;
-        double *wkt = wk + tid;
-        do {
-            double *x = Yv + u;                      // stride m
+}
+
+// stage 2: eigenvalue t of T by multisection (64 Sturm counts per round)
+__global__ void __launch_bounds__(64) rr_eig_kernel(const int *obj_status, int wmax, int m, double *scratch) {
+    const int t = blockIdx.x, o = blockIdx.y, lane = threadIdx.x;
+    if (obj_status[o] != 0) return;
+    const RRScr g = rr_scr(scratch, o, wmax, m);
+    const int r = (int)g.meta[RR_R];
+    __shared__ double dg[kRRMax], eg[kRRMax];
+    for (int i = lane; i < r; i += 64) {
+        dg[i] = g.dg[i];
+        eg[i] = g.eg[i];
+    }
+    __syncthreads();
+    const double eps = 2.220446049250313e-16, pivmin = g.meta[RR_PIVMIN];
+    double lo = g.meta[RR_GL], hi = g.meta[RR_GU];
+    for (int it = 0; it < 64; ++it) {
+        if (hi - lo <= 2.0 * eps * fmax(fabs(lo), fabs(hi)) + pivmin) break;
+        const double x = lo + (hi - lo) * (double)(lane + 1) / 65.0;
+        const bool above = sturm_count(dg, eg, r, x, pivmin) > t;
+        double nlo = above ? lo : x, nhi = above ? x : hi;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            nlo = fmax(nlo, __shfl_xor(nlo, d, 64));
+            nhi = fmin(nhi, __shfl_xor(nhi, d, 64));
+        }
+        lo = nlo;
+        hi = nhi;
+    }
+    if (lane == 0) g.evs[t] = 0.5 * (lo + hi);
+}
+
+// stage 3: eigenvector(s) of T for eigenvalue t (its whole cluster when t leads one),
+// back-transformed to the coefficients C[:, u] (rows = basis columns, stride m)
+template <bool kLds>
+__global__ void __launch_bounds__(64) rr_vec_kernel(const int *obj_status, const int *width, int wmax, int m,
+                                                    double *scratch, double *C, double *theta) {
+    constexpr bool refl_lds = kLds;
+    const int t0 = blockIdx.x, o = blockIdx.y, lane = threadIdx.x;
+    if (obj_status[o] != 0) return;
+    const RRScr g = rr_scr(scratch, o, wmax, m);
+    const int w = width[o];
+    const int r = (int)g.meta[RR_R], ld = (int)g.meta[RR_LD];
+    const double tnorm = g.meta[RR_TNORM];
+    const double eps = 2.220446049250313e-16;
+    const double ctol = 1e-9 * tnorm, tiny = eps * tnorm + 1e-300;
+    const double *evs = g.evs;
+    if (t0 > 0 && evs[t0] - evs[t0 - 1] <= ctol) return;   // handled by the cluster's first eigenvalue
+    int t1 = t0 + 1;
+    while (t1 < m && evs[t1] - evs[t1 - 1] <= ctol) ++t1;
+    extern __shared__ __align__(16) double sm[];
+    const double *refl = refl_lds ? sm : g.A;
+    double *aux = sm + (refl_lds ? (size_t)wmax * wmax : 0);
+    double *dg = aux, *eg = aux + wmax, *x = aux + 2 * wmax, *wk = aux + 3 * wmax;
+    for (int i = lane; i < r; i += 64) {
+        dg[i] = g.dg[i];
+        eg[i] = g.eg[i];
+    }
+    if (refl_lds)
+        for (int idx = lane; idx < r * ld; idx += 64) sm[idx] = g.A[idx];
+    __syncthreads();
+    double *Co = C + (size_t)o * wmax * m;
+    for (int u = t0; u < t1; ++u) {
+        if (lane == 0) {
             for (int i = 0; i < r; ++i) {
                 const unsigned hsh = (unsigned)i * 2654435761u + (unsigned)u * 2246822519u + 12345u;
-                x[(size_t)i * m] = 1.0 + ((double)((hsh >> 8) & 0xffff) / 65536.0 - 0.5);
+                x[i] = 1.0 + ((double)((hsh >> 8) & 0xffff) / 65536.0 - 0.5);
             }
             for (int it = 0; it < 3; ++it) {
-                tri_solve(dg, eg, r, evs[u], tiny, x, m, wkt, m);
-                for (int q = u0; q < u; ++q) {
+                tri_solve(dg, eg, r, evs[u], tiny, x, wk);
+                for (int q = t0; q < u; ++q) {           // earlier members of the cluster
+                    const double *yq = g.Yv + (size_t)q * wmax;
                     double d = 0.0;
-                    for (int i = 0; i < r; ++i) d += Yv[(size_t)i * m + q] * x[(size_t)i * m];
-                    for (int i = 0; i < r; ++i) x[(size_t)i * m] -= d * Yv[(size_t)i * m + q];
+                    for (int i = 0; i < r; ++i) d += yq[i] * x[i];
+                    for (int i = 0; i < r; ++i) x[i] -= d * yq[i];
                 }
                 double nx = 0.0;
-                for (int i = 0; i < r; ++i) nx += x[(size_t)i * m] * x[(size_t)i * m];
+                for (int i = 0; i < r; ++i) nx += x[i] * x[i];
                 const double inv = nx > 0.0 ? 1.0 / sqrt(nx) : 0.0;
-                for (int i = 0; i < r; ++i) x[(size_t)i * m] *= inv;
+                for (int i = 0; i < r; ++i) x[i] *= inv;
             }
-            ++u;
-        } while (u < m && evs[u] - evs[u - 1] <= ctol);
-    }
-    __threadfence_block();
-    rr_barrier();
-
-    RR_MARK(6);
-    // 6. one wavefront per vector: Rayleigh quotient, y <- Q y, z = L^-T y, C = D^-1/2 z
-    double *Co = C + (size_t)o * wmax * m;
-    for (int t = wv; t < m; t += 4) {
+            if (t1 - t0 > 1)
+                for (int i = 0; i < r; ++i) g.Yv[(size_t)u * wmax + i] = x[i];
+        }
+        __threadfence_block();
+        __syncthreads();
         double y[3], z[3];
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
             const int i = lane + 64 * q;
-            y[q] = i < r ? Yv[(size_t)i * m + t] : 0.0;
+            y[q] = i < r ? x[i] : 0.0;
         }
+        // Rayleigh quotient on T
         double rq = 0.0;
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
             const int i = lane + 64 * q;
             if (i < r) {
                 double ty = dg[i] * y[q];
-                if (i > 0) ty += eg[i - 1] * Yv[(size_t)(i - 1) * m + t];
-                if (i + 1 < r) ty += eg[i] * Yv[(size_t)(i + 1) * m + t];
+                if (i > 0) ty += eg[i - 1] * x[i - 1];
+                if (i + 1 < r) ty += eg[i] * x[i + 1];
                 rq += y[q] * ty;
             }
         }
+#pragma unroll
         for (int d = 32; d >= 1; d >>= 1) rq += __shfl_xor(rq, d, 64);
-        if (lane == 0) theta[(size_t)o * m + t] = rq;
+        if (lane == 0) theta[(size_t)o * m + u] = rq;
+        // y <- Q y: reflectors applied last to first
         for (int j = r - 3; j >= 0; --j) {
-            const double tj = tg[j];
+            const double tj = g.tg[j];
             if (tj == 0.0) continue;
-            const double *vrow = A + (size_t)j * ld;
+            const double *vrow = refl + (size_t)j * ld;
             double sacc = 0.0;
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
                 const int i = lane + 64 * q;
                 if (i > j && i < r) sacc += vrow[i] * y[q];
             }
+#pragma unroll
             for (int d = 32; d >= 1; d >>= 1) sacc += __shfl_xor(sacc, d, 64);
             sacc *= tj;
 #pragma unroll
@@ -991,60 +1130,70 @@ __global__ void __launch_bounds__(kRRThreads) rr_kernel(int *obj_status, int *wi
                 if (i > j && i < r) y[q] -= sacc * vrow[i];
             }
         }
-        // z_i = sum_{s >= i} Linv[s][i] y_s
+        // z = L^-T y: z_i = sum_{s >= i} Linv[s][i] y_s
         z[0] = z[1] = z[2] = 0.0;
         for (int sidx = 0; sidx < r; ++sidx) {
             const double ysrc = sidx < 64 ? y[0] : (sidx < 128 ? y[1] : y[2]);
             const double ys = __shfl(ysrc, sidx & 63, 64);
-            const double *Ls = B + (size_t)sidx * ld;
+            const double *Ls = g.B + (size_t)sidx * ld;
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
                 const int i = lane + 64 * q;
                 if (i <= sidx) z[q] += Ls[i] * ys;
             }
         }
-        for (int i = lane; i < w; i += 64)
-            if (!keep[i]) Co[(size_t)i * m + t] = 0.0;
+        // C column u: D^-1/2 z on the kept basis columns, zero on the dropped ones
+        for (int i = lane; i < w; i += 64) {
+            const int p = (int)g.kpos[i];
+            if (p < 0) Co[(size_t)i * m + u] = 0.0;
+        }
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
             const int i = lane + 64 * q;
-            if (i < r) Co[(size_t)kidx[i] * m + t] = sc[kidx[i]] * z[q];
+            if (i < r) {
+                const int c = (int)g.kidx[i];
+                Co[(size_t)c * m + u] = g.sc[c] * z[q];
+            }
         }
+        __syncthreads();
     }
-    __threadfence_block();
-    rr_barrier();
-    RR_MARK(7);
-    // P coefficients: C_p (C without its X rows) minus its M-projection on the new X,
-    // Q = C^T G_M C_p, C_p' = C_p - C Q, so that P' = S C_p' is M-orthogonal to X' = S C
-    double *T1 = st1, *Qm = st2;
-    for (int idx = tid; idx < w * m; idx += kRRThreads) {
-        const int i = idx / m, c = idx - (idx / m) * m;
+}
+
+// stage 4: column c of C_p' = C_p - C (C^T G_M C_p), and the working-precision copies
+template <typename CT>
+__global__ void __launch_bounds__(256) rr_post_kernel(const int *obj_status, const int *width, const double *G,
+                                                      int wmax, int m, const double *C, CT *Cw, double *Cp,
+                                                      CT *Cpw) {
+    const int c = blockIdx.x, o = blockIdx.y, tid = threadIdx.x;
+    if (obj_status[o] != 0) return;
+    const int w = width[o];
+    const size_t ww = (size_t)wmax * wmax;
+    const double *GM = G + (size_t)o * 2 * ww + ww;
+    const double *Co = C + (size_t)o * wmax * m;
+    __shared__ double T1[kRRMax], Q[kRRMax];
+    for (int i = tid; i < w; i += 256) {
         double acc = 0.0;
         for (int j = m; j < w; ++j) acc += GM[(size_t)i * wmax + j] * Co[(size_t)j * m + c];
-        T1[idx] = acc;
+        T1[i] = acc;
     }
-    __threadfence_block();
-    rr_barrier();
-    for (int idx = tid; idx < m * m; idx += kRRThreads) {
-        const int a = idx / m, c = idx - (idx / m) * m;
+    __syncthreads();
+    for (int a = tid; a < m; a += 256) {
         double acc = 0.0;
-        for (int i = 0; i < w; ++i) acc += Co[(size_t)i * m + a] * T1[(size_t)i * m + c];
-        Qm[idx] = acc;
+        for (int i = 0; i < w; ++i) acc += Co[(size_t)i * m + a] * T1[i];
+        Q[a] = acc;
     }
-    __threadfence_block();
-    rr_barrier();
+    __syncthreads();
     double *Cpo = Cp + (size_t)o * wmax * m;
     CT *Cpwo = Cpw + (size_t)o * wmax * m;
     CT *Cwo = Cw + (size_t)o * wmax * m;
-    for (int idx = tid; idx < w * m; idx += kRRThreads) {
-        const int i = idx / m, c = idx - (idx / m) * m;
+    for (int i = tid; i < w; i += 256) {
+        const size_t idx = (size_t)i * m + c;
         double acc = i >= m ? Co[idx] : 0.0;
-        for (int a = 0; a < m; ++a) acc -= Co[(size_t)i * m + a] * Qm[(size_t)a * m + c];
+        for (int a = 0; a < m; ++a) acc -= Co[(size_t)i * m + a] * Q[a];
         Cpo[idx] = acc;
         Cpwo[idx] = (CT)acc;
         Cwo[idx] = (CT)Co[idx];
     }
-    RR_MARK(8);
 }
 
 // ---------------------------------------------------------------------------
@@ -1366,8 +1515,6 @@ struct Solver {
     UChunk *uch = nullptr;
     GChunk *gch = nullptr;
     int nu = 0, ng = 0;
-    int rr_lds = 0;
-    size_t rr_shmem = 0;
     int refresh32 = 30, refresh64 = 0;
     int total_iters = 0;
     int graph_used = 0;
@@ -1408,6 +1555,40 @@ int stage_spmm(Solver &s, T *S, T *HS, T *MS, int slot) {
                           S + slot * s.m, ld, HS + slot * s.m, MS + slot * s.m, ld, s.m, s.row_obj, s.status);
 }
 
+// the four Rayleigh-Ritz stages on every active object (LDS limits set by rr_prepare)
+template <typename CT>
+int launch_rr(ff_ctx *ctx, hipStream_t st, int n_obj, int *status, const int *width, const double *G, int wmax, int m,
+              double tau, double *scratch, double *C, CT *Cw, double *Cp, CT *Cpw, double *theta, int *info) {
+    const int lds = rr_use_lds(wmax), vlds = rr_vec_lds(wmax);
+    if (lds)
+        hipLaunchKernelGGL(rr_tridiag_kernel<true>, dim3(n_obj), dim3(kRRThreads), rr_shmem_bytes(wmax, 1), st, status,
+                           width, G, wmax, m, tau, scratch, info);
+    else
+        hipLaunchKernelGGL(rr_tridiag_kernel<false>, dim3(n_obj), dim3(kRRThreads), rr_shmem_bytes(wmax, 0), st,
+                           status, width, G, wmax, m, tau, scratch, info);
+    hipLaunchKernelGGL(rr_eig_kernel, dim3(m, n_obj), dim3(64), 0, st, status, wmax, m, scratch);
+    if (vlds)
+        hipLaunchKernelGGL(rr_vec_kernel<true>, dim3(m, n_obj), dim3(64), rr_vec_shmem_bytes(wmax, 1), st, status,
+                           width, wmax, m, scratch, C, theta);
+    else
+        hipLaunchKernelGGL(rr_vec_kernel<false>, dim3(m, n_obj), dim3(64), rr_vec_shmem_bytes(wmax, 0), st, status,
+                           width, wmax, m, scratch, C, theta);
+    hipLaunchKernelGGL(rr_post_kernel<CT>, dim3(m, n_obj), dim3(256), 0, st, status, width, G, wmax, m, C, Cw, Cp,
+                       Cpw);
+    FF_CHECK_LAUNCH(ctx);
+    return FF_OK;
+}
+
+// raise the dynamic LDS limits of the Rayleigh-Ritz kernels for blocks of width wmax
+int rr_prepare(ff_ctx *ctx, int wmax) {
+    const int lds = rr_use_lds(wmax), vlds = rr_vec_lds(wmax);
+    FF_HIP(ctx, hipFuncSetAttribute(lds ? (const void *)rr_tridiag_kernel<true> : (const void *)rr_tridiag_kernel<false>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)rr_shmem_bytes(wmax, lds)));
+    FF_HIP(ctx, hipFuncSetAttribute(vlds ? (const void *)rr_vec_kernel<true> : (const void *)rr_vec_kernel<false>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)rr_vec_shmem_bytes(wmax, vlds)));
+    return FF_OK;
+}
+
 template <typename T>
 int stage_gram_rr(Solver &s, T *S, T *HS, T *MS, double tau) {
     const int T16 = (s.wmax + 15) / 16, nsup = (T16 + 5) / 6;
@@ -1418,11 +1599,8 @@ int stage_gram_rr(Solver &s, T *S, T *HS, T *MS, double tau) {
     hipLaunchKernelGGL(gram_reduce_kernel, dim3(grid_for(per2, 256), s.n_obj), dim3(256), 0, s.st, s.status, s.width,
                        s.gfirst, s.gcount, s.gpart, s.wmax, s.G);
     FF_CHECK_LAUNCH(s.ctx);
-    hipLaunchKernelGGL(rr_kernel<typename Prec<T>::CT>, dim3(s.n_obj), dim3(kRRThreads), s.rr_shmem, s.st, s.status,
-                       s.width, s.G, s.wmax, s.m, tau, s.rrscr, s.rr_lds, s.C, cw_of<T>(s), s.Cp, cpw_of<T>(s),
-                       s.theta, s.info);
-    FF_CHECK_LAUNCH(s.ctx);
-    return FF_OK;
+    return launch_rr<typename Prec<T>::CT>(s.ctx, s.st, s.n_obj, s.status, s.width, s.G, s.wmax, s.m, tau, s.rrscr,
+                                           s.C, cw_of<T>(s), s.Cp, cpw_of<T>(s), s.theta, s.info);
 }
 
 template <typename T>
@@ -1640,14 +1818,7 @@ int setup(Solver &s, const ff_eig_params *p) {
                                     (int)update_shmem<double>(wmax, m)));
     FF_HIP(ctx, hipFuncSetAttribute((const void *)update_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)update_shmem<float>(wmax, m)));
-    // Rayleigh-Ritz storage: LDS when the two w x w FP64 matrices fit
-    s.rr_lds = rr_use_lds(wmax);
-    s.rr_shmem = rr_shmem_bytes(wmax, s.rr_lds);
-    FF_HIP(ctx, hipFuncSetAttribute((const void *)rr_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)s.rr_shmem));
-    FF_HIP(ctx, hipFuncSetAttribute((const void *)rr_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)s.rr_shmem));
-    return FF_OK;
+    return rr_prepare(ctx, wmax);
 }
 
 std::string tune_key(int64_t n, int64_t nnz, int m, int precision) {
@@ -2047,13 +2218,10 @@ extern "C" int rayleigh_ritz(ff_ctx *ctx, int w, int m, const double *G, double 
     int hi[3] = {0, w, 0};   // status, width, info
     FF_HIP(ctx, hipMemcpyAsync(ints, hi, sizeof(hi), hipMemcpyHostToDevice, st));
     FF_HIP(ctx, hipStreamSynchronize(st));
-    const int lds = rr_use_lds(w);
-    const size_t shm = rr_shmem_bytes(w, lds);
-    FF_HIP(ctx, hipFuncSetAttribute((const void *)rr_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)shm));
-    hipLaunchKernelGGL(rr_kernel<double>, dim3(1), dim3(kRRThreads), shm, st, ints, ints + 1, G, w, m, tau,
-                       scr, lds, C, cw, cw + (size_t)w * m, cw + (size_t)2 * w * m, theta, ints + 2);
-    FF_CHECK_LAUNCH(ctx);
+    int rc = rr_prepare(ctx, w);
+    if (!rc) rc = launch_rr<double>(ctx, st, 1, ints, ints + 1, G, w, m, tau, scr, C, cw, cw + (size_t)w * m,
+                                    cw + (size_t)2 * w * m, theta, ints + 2);
+    if (rc) return rc;
     int h[3];
     FF_HIP(ctx, hipMemcpyAsync(h, ints, sizeof(h), hipMemcpyDeviceToHost, st));
     FF_HIP(ctx, hipStreamSynchronize(st));
