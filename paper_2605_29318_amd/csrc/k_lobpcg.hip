@@ -270,34 +270,90 @@ __device__ inline f32x4 mfma(float a, float b, f32x4 c) { return __builtin_amdgc
 __device__ inline f64x4 mfma(double a, double b, f64x4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
 
 // MT is the arithmetic type: FP32 blocks may run on FP64 MFMA (their products are exact in FP64).
+// The block streams its chunk in 16-row sub-blocks: the three 16 x 96 windows
+// of S, HS, MS it needs go to LDS with 16-byte loads (double buffered: the
+// next sub-block's loads are in flight during the MFMAs), at a row stride that
+// puts a fragment read's lanes on distinct banks.
+constexpr int kGramTS = 96 + 16;
+
+// the first min(n, VN) elements at p, zeros after them, element by element
+template <typename T> __device__ inline typename Vec<T>::type vec_load_partial(const T *p, int n);
+template <> __device__ inline float4 vec_load_partial<float>(const float *p, int n) {
+    return make_float4(n > 0 ? p[0] : 0.0f, n > 1 ? p[1] : 0.0f, n > 2 ? p[2] : 0.0f, n > 3 ? p[3] : 0.0f);
+}
+template <> __device__ inline double2 vec_load_partial<double>(const double *p, int n) {
+    return make_double2(n > 0 ? p[0] : 0.0, n > 1 ? p[1] : 0.0);
+}
+template <typename T> constexpr size_t gram_shmem_bytes() { return (size_t)2 * 3 * 16 * kGramTS * sizeof(T); }
+
+// one sub-block of the Gram stream: vector qv of the 3 x 16 x 96 staging area
+// (array, row, column vector) into registers, then into LDS buffer b
+template <typename T, int kPer>
+__device__ inline void gram_stage_load(typename Vec<T>::type *pre, int tid, int64_t rb, int64_t r1, int cs0, int cb0,
+                                       int w, const T *S, const T *HS, const T *MS, int64_t ld, int vec_ok) {
+    typedef typename Vec<T>::type V;
+    constexpr int VN = Vec<T>::n, kWinVec = 96 / VN, kStage = 3 * 16 * kWinVec;
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int qv = tid + u * 512;
+        pre[u] = V{};
+        if (qv < kStage) {
+            const int arr = qv / (16 * kWinVec), rem = qv - arr * (16 * kWinVec);
+            const int rr = rem / kWinVec, cv = rem - rr * kWinVec;
+            const int col = (arr == 0 ? cs0 : cb0) + cv * VN;
+            const int64_t row = rb + rr;
+            const T *src = arr == 0 ? S : (arr == 1 ? HS : MS);
+            if (row < r1 && col < w) {
+                if (vec_ok && col + VN <= w)
+                    pre[u] = *(const V *)(src + row * ld + col);
+                else                               // unaligned rows or the ragged end of a row
+                    pre[u] = vec_load_partial<T>(src + row * ld + col, w - col);
+            }
+        }
+    }
+}
+template <typename T, int kPer>
+__device__ inline void gram_stage_store(const typename Vec<T>::type *pre, int tid, T *buf, int b) {
+    typedef typename Vec<T>::type V;
+    constexpr int VN = Vec<T>::n, kWinVec = 96 / VN, kStage = 3 * 16 * kWinVec;
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int qv = tid + u * 512;
+        if (qv < kStage) {
+            const int arr = qv / (16 * kWinVec), rem = qv - arr * (16 * kWinVec);
+            const int rr = rem / kWinVec, cv = rem - rr * kWinVec;
+            *(V *)(buf + ((size_t)(b * 3 + arr) * 16 + rr) * kGramTS + cv * VN) = pre[u];
+        }
+    }
+}
+
 template <typename T, typename MT>
-__global__ void __launch_bounds__(512) gram_kernel(const GChunk *chunks, const int *obj_status, const int *width,
-                                                   const T *S, const T *HS, const T *MS, int64_t ld, int wmax,
-                                                   double *part) {
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))
+gram_kernel(const GChunk *chunks, const int *obj_status, const int *width, const T *S, const T *HS, const T *MS,
+            int64_t ld, int wmax, double *part, int vec_ok) {
     typedef typename MfmaAcc<MT>::type Acc;
+    typedef typename Vec<T>::type V;
+    constexpr int VN = Vec<T>::n;
+    constexpr int kWinVec = 96 / VN;               // vectors per window row
+    constexpr int kStage = 3 * 16 * kWinVec;       // vectors per sub-block
+    constexpr int kPer = (kStage + 511) / 512;
     const GChunk ch = chunks[blockIdx.x];
     if (obj_status[ch.obj] != 0) return;
     const int w = width[ch.obj];
     const int T16 = (w + 15) >> 4;                 // tiles per dimension
-    const int nsup = (T16 + 5) / 6;                // super blocks per dimension
+    const int nsup = (T16 + 5) / 6;                // super blocks (96-column windows) per dimension
     const int sy = blockIdx.y / nsup, sx = blockIdx.y - (blockIdx.y / nsup) * nsup;
     if (sy >= nsup) return;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int prod = wv >> 2;                      // 0: H, 1: M
     const int q = wv & 3;
-    const int ti0 = sy * 6 + (q >> 1) * 3, tj0 = sx * 6 + (q & 1) * 3;
-    const T *B = prod ? MS : HS;
+    const int ti0 = (q >> 1) * 3, tj0 = (q & 1) * 3;   // tiles within the windows
+    const int cs0 = sy * 96, cb0 = sx * 96;
     const int li = lane & 15, lk = lane >> 4;
-    // column indices of the A (rows of G) and B (columns of G) fragments
-    int ca[3], cb[3];
-    bool va[3], vb[3];
-#pragma unroll
-    for (int t = 0; t < 3; ++t) {
-        ca[t] = (ti0 + t) * 16 + li;
-        cb[t] = (tj0 + t) * 16 + li;
-        va[t] = (ti0 + t) < T16 && ca[t] < w;
-        vb[t] = (tj0 + t) < T16 && cb[t] < w;
-    }
+    extern __shared__ __align__(16) char smem[];
+    T *buf = (T *)smem;                            // [2][3][16][kGramTS]
+    const int64_t r0 = ch.r0, r1 = ch.r0 + ch.len;
+    V pre[kPer];
     Acc acc[3][3];
     double tot[3][3][4];
 #pragma unroll
@@ -307,32 +363,40 @@ __global__ void __launch_bounds__(512) gram_kernel(const GChunk *chunks, const i
             acc[a][c] = Acc{0, 0, 0, 0};
             tot[a][c][0] = tot[a][c][1] = tot[a][c][2] = tot[a][c][3] = 0.0;
         }
-    const int64_t r0 = ch.r0, r1 = ch.r0 + ch.len;
-    int steps = 0;
-    for (int64_t r = r0; r < r1; r += 4) {
-        const int64_t row = r + lk;
-        const bool rv = row < r1;
-        MT fa[3], fb[3];
+    gram_stage_load<T, kPer>(pre, tid, r0, r1, cs0, cb0, w, S, HS, MS, ld, vec_ok);
+    gram_stage_store<T, kPer>(pre, tid, buf, 0);
+    __syncthreads();
+    int b = 0;
+    for (int64_t rb = r0; rb < r1; rb += 16) {
+        const bool more = rb + 16 < r1;
+        if (more) gram_stage_load<T, kPer>(pre, tid, rb + 16, r1, cs0, cb0, w, S, HS, MS, ld, vec_ok);
+        const T *Sb = buf + (size_t)(b * 3) * 16 * kGramTS;
+        const T *Bb = buf + (size_t)(b * 3 + 1 + prod) * 16 * kGramTS;
 #pragma unroll
-        for (int t = 0; t < 3; ++t) {
-            fa[t] = (rv && va[t]) ? (MT)S[row * ld + ca[t]] : (MT)0;
-            fb[t] = (rv && vb[t]) ? (MT)B[row * ld + cb[t]] : (MT)0;
-        }
+        for (int k0 = 0; k0 < 16; k0 += 4) {
+            const int kr = k0 + lk;
+            MT fa[3], fb[3];
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) acc[a][c] = mfma(fa[a], fb[c], acc[a][c]);
-        if (++steps == 4) {                        // promote to FP64 every 16 rows
-            steps = 0;
+            for (int t = 0; t < 3; ++t) {
+                fa[t] = (MT)Sb[kr * kGramTS + (ti0 + t) * 16 + li];
+                fb[t] = (MT)Bb[kr * kGramTS + (tj0 + t) * 16 + li];
+            }
 #pragma unroll
             for (int a = 0; a < 3; ++a)
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) tot[a][c][v] += (double)acc[a][c][v];
-                    acc[a][c] = Acc{0, 0, 0, 0};
-                }
+                for (int c = 0; c < 3; ++c) acc[a][c] = mfma(fa[a], fb[c], acc[a][c]);
         }
+#pragma unroll
+        for (int a = 0; a < 3; ++a)                 // promote to FP64 every 16 rows
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) tot[a][c][v] += (double)acc[a][c][v];
+                acc[a][c] = Acc{0, 0, 0, 0};
+            }
+        if (more) gram_stage_store<T, kPer>(pre, tid, buf, b ^ 1);
+        __syncthreads();
+        b ^= 1;
     }
     // write this chunk's partial: part[chunk][prod][i][j]
     double *P = part + ((size_t)blockIdx.x * 2 + prod) * (size_t)wmax * wmax;
@@ -340,12 +404,12 @@ __global__ void __launch_bounds__(512) gram_kernel(const GChunk *chunks, const i
     for (int a = 0; a < 3; ++a)
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const int tI = ti0 + a, tJ = tj0 + c;
+            const int tI = sy * 6 + ti0 + a, tJ = sx * 6 + tj0 + c;
             if (tI >= T16 || tJ >= T16) continue;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int i = tI * 16 + MfmaAcc<MT>::row(lk, v), j = tJ * 16 + li;
-                if (i < w && j < w) P[(size_t)i * wmax + j] = tot[a][c][v] + (double)acc[a][c][v];
+                if (i < w && j < w) P[(size_t)i * wmax + j] = tot[a][c][v];
             }
         }
 }
@@ -1580,6 +1644,14 @@ int launch_rr(ff_ctx *ctx, hipStream_t st, int n_obj, int *status, const int *wi
 }
 
 // raise the dynamic LDS limits of the Rayleigh-Ritz kernels for blocks of width wmax
+int gram_prepare(ff_ctx *ctx) {
+    FF_HIP(ctx, hipFuncSetAttribute((const void *)gram_kernel<double, double>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)gram_shmem_bytes<double>()));
+    FF_HIP(ctx, hipFuncSetAttribute((const void *)gram_kernel<float, float>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)gram_shmem_bytes<float>()));
+    return FF_OK;
+}
+
 int rr_prepare(ff_ctx *ctx, int wmax) {
     const int lds = rr_use_lds(wmax), vlds = rr_vec_lds(wmax);
     FF_HIP(ctx, hipFuncSetAttribute(lds ? (const void *)rr_tridiag_kernel<true> : (const void *)rr_tridiag_kernel<false>,
@@ -1592,8 +1664,8 @@ int rr_prepare(ff_ctx *ctx, int wmax) {
 template <typename T>
 int stage_gram_rr(Solver &s, T *S, T *HS, T *MS, double tau) {
     const int T16 = (s.wmax + 15) / 16, nsup = (T16 + 5) / 6;
-    hipLaunchKernelGGL((gram_kernel<T, T>), dim3(s.ng, nsup * nsup), dim3(512), 0, s.st, s.gch, s.status, s.width, S,
-                       HS, MS, (int64_t)3 * s.m, s.wmax, s.gpart);
+    hipLaunchKernelGGL((gram_kernel<T, T>), dim3(s.ng, nsup * nsup), dim3(512), gram_shmem_bytes<T>(), s.st, s.gch,
+                       s.status, s.width, S, HS, MS, (int64_t)3 * s.m, s.wmax, s.gpart, 1);
     FF_CHECK_LAUNCH(s.ctx);
     const int64_t per2 = 2 * (int64_t)s.wmax * s.wmax;
     hipLaunchKernelGGL(gram_reduce_kernel, dim3(grid_for(per2, 256), s.n_obj), dim3(256), 0, s.st, s.status, s.width,
@@ -1818,7 +1890,8 @@ int setup(Solver &s, const ff_eig_params *p) {
                                     (int)update_shmem<double>(wmax, m)));
     FF_HIP(ctx, hipFuncSetAttribute((const void *)update_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)update_shmem<float>(wmax, m)));
-    return rr_prepare(ctx, wmax);
+    int rc = gram_prepare(ctx);
+    return rc ? rc : rr_prepare(ctx, wmax);
 }
 
 std::string tune_key(int64_t n, int64_t nnz, int m, int precision) {
@@ -2190,12 +2263,19 @@ extern "C" int gram_hm(ff_ctx *ctx, int64_t n, int w, int precision, const void 
     FF_HIP(ctx, hipMemcpyAsync(ints, hi, sizeof(hi), hipMemcpyHostToDevice, st));
     FF_HIP(ctx, hipStreamSynchronize(st));
     const int T16 = (w + 15) / 16, nsup = (T16 + 5) / 6;
+    int rc = gram_prepare(ctx);
+    if (rc) return rc;
+    // 16-byte row loads need 16-byte aligned bases and a leading dimension of whole vectors
+    const int vn = precision ? 4 : 2;
+    const int vec_ok = ld % vn == 0 && ((uintptr_t)S | (uintptr_t)HS | (uintptr_t)MS) % 16 == 0;
     if (precision)
-        hipLaunchKernelGGL((gram_kernel<float, float>), dim3(ng, nsup * nsup), dim3(512), 0, st, gch, ints, ints + 1,
-                           (const float *)S, (const float *)HS, (const float *)MS, ld, w, part);
+        hipLaunchKernelGGL((gram_kernel<float, float>), dim3(ng, nsup * nsup), dim3(512), gram_shmem_bytes<float>(), st,
+                           gch, ints, ints + 1, (const float *)S, (const float *)HS, (const float *)MS, ld, w, part,
+                           vec_ok);
     else
-        hipLaunchKernelGGL((gram_kernel<double, double>), dim3(ng, nsup * nsup), dim3(512), 0, st, gch, ints, ints + 1,
-                           (const double *)S, (const double *)HS, (const double *)MS, ld, w, part);
+        hipLaunchKernelGGL((gram_kernel<double, double>), dim3(ng, nsup * nsup), dim3(512),
+                           gram_shmem_bytes<double>(), st, gch, ints, ints + 1, (const double *)S, (const double *)HS,
+                           (const double *)MS, ld, w, part, vec_ok);
     FF_CHECK_LAUNCH(ctx);
     const int64_t per2 = 2 * (int64_t)w * w;
     hipLaunchKernelGGL(gram_reduce_kernel, dim3(grid_for(per2, 256), 1), dim3(256), 0, st, ints, ints + 1, ints + 2,
