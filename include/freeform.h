@@ -222,7 +222,8 @@ int eigenmodes_batched(ff_ctx *ctx, int n_obj, const int64_t *obj_row_off, const
  * exposed for measurement and tests. Y, HY, MY are [n][m] row-major with
  * leading dimension ld (>= m). precision 1 reads hm32 and FP32 blocks,
  * precision 0 reads H, M and FP64 blocks (the block pointers are float* or
- * double* accordingly). variant selects a tile shape (-1 = tuned/default).
+ * double* accordingly). variant selects a tile shape (-1 = tuned/default);
+ * the row-tile variants (see rowtiles_build) build their copy for each call.
  */
 int spmm_hm(ff_ctx *ctx, int64_t n, const int64_t *row_ptr, const int32_t *col, const double *H,
             const double *M, const float *hm32, int precision, int m, const void *Y, int64_t ld_y,
@@ -259,6 +260,31 @@ int gram_hm(ff_ctx *ctx, int64_t n, int w, int precision, const void *S, const v
  */
 int rayleigh_ritz(ff_ctx *ctx, int w, int m, const double *G, double tau, double *C, double *theta,
                   int *kept);
+
+/*
+ * Row-tile copy of [H, M] for the fused SpMM. Rows are grouped in tiles of
+ * four consecutive rows (in the cell-sorted numbering, so spatially close);
+ * a tile keeps the ascending union of its rows' column lists and, per union
+ * entry, the four H and four M values of its rows (zero where a row lacks the
+ * column). The product then gathers each row of Y once per tile instead of
+ * once per row. eigenmodes builds such a copy itself when a row-tile SpMM
+ * variant is selected; these calls keep one for repeated products.
+ *
+ * rowtiles_build: from the FP64 CSR of assemble_HM (rows with ascending
+ *   columns); precision 1 keeps FP32 values (rounded from H, M), 0 FP64, 2
+ *   both. Device memory owned by the handle until rowtiles_destroy (destroy it
+ *   before its context). The CSR may be freed afterwards.
+ * spmm_rowtiles: [HY, MY] = [H, M] Y as spmm_hm, on the copy; sub selects a
+ *   launch shape (0 .. 2).
+ */
+typedef struct ff_rowtiles ff_rowtiles;
+int rowtiles_build(ff_ctx *ctx, int64_t n, const int64_t *row_ptr, const int32_t *col, const double *H,
+                   const double *M, int precision, ff_rowtiles **out);
+/* Number of tiles and of union entries (host out, either may be NULL). */
+int rowtiles_info(const ff_rowtiles *rt, int64_t *ntiles, int64_t *entries);
+int spmm_rowtiles(ff_ctx *ctx, const ff_rowtiles *rt, int precision, int m, const void *Y, int64_t ld_y, void *HY,
+                  void *MY, int64_t ld_out, int sub);
+void rowtiles_destroy(ff_rowtiles *rt);
 
 /* Number of SpMM tile variants and a description of one (host strings). */
 int spmm_variant_count(void);

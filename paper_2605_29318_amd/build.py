@@ -25,6 +25,7 @@ SOURCES = [
     ("k_assemble.hip", True),
     ("k_lobpcg.hip", False),
     ("k_mlp.hip", False),
+    ("k_rowtile.hip", False),
 ]
 
 COMMON = ["-x", "hip", "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",

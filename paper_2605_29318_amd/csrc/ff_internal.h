@@ -26,6 +26,7 @@ enum WsSlot {
     WS_GPART, WS_G, WS_C, WS_C32, WS_THETA, WS_RPART, WS_RES, WS_STATE, WS_RRSCR,
     WS_DINV, WS_DINV32, WS_NORMS, WS_CHUNKS, WS_GCHUNKS, WS_OBJ, WS_SIGN, WS_TUNE,
     WS_MLP0, WS_MLP1, WS_MLP2, WS_MLP3, WS_MLP4, WS_MLP5, WS_MLP6, WS_MLP7,
+    WS_RT_CNT, WS_RT_PTR, WS_RT_COL, WS_RT_VAL32, WS_RT_VAL64,   // row-tile SpMM copies
     WS_COUNT
 };
 

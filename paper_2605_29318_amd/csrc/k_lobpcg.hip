@@ -14,6 +14,7 @@
 // converged, so many independent problems share one launch per stage.
 #include "ff_internal.h"
 #include "k_lobpcg.h"
+#include "k_rowtile.h"
 
 #include <algorithm>
 #include <chrono>
@@ -1510,14 +1511,30 @@ static const char *kVariantNames[] = {"waves4_unroll2_xcd", "waves4_unroll4_xcd"
                                       "waves4_unroll2_linear", "waves2_unroll4_xcd", "waves8_unroll4_xcd",
                                       "chunk64_waves4_batch8", "chunk64_waves2_batch8", "chunk64_waves8_batch8",
                                       "chunk64_waves4_batch4", "chunk64_waves2_batch8_occ6",
-                                      "chunk64_waves4_batch4_occ8", "chunk64_waves2_batch16"};
-constexpr int kNumVariants = 13;
-constexpr int kDefaultVariant = 11;    // fastest untuned choice on 10^5-10^6-row RKPM matrices
+                                      "chunk64_waves4_batch4_occ8", "chunk64_waves2_batch16",
+                                      "rowtile4_waves4_batch4", "rowtile4_waves2_batch8",
+                                      "rowtile4_waves4_batch4_occ4"};
+constexpr int kNumVariants = 16;
+constexpr int kRowTileBase = 13;               // variants from here on run on the row-tile copy
+constexpr int kDefaultVariant = 14;    // fastest untuned choice on 10^5-10^6-row RKPM matrices (row tiles)
+
+inline int rt_spmm(ff_ctx *ctx, hipStream_t st, const rt::RTView &v, int sub, int m, const float *Y, int64_t ldy,
+                   float *HY, float *MY, int64_t ldo, const int *row_obj, const int *status) {
+    return rt::spmm32(ctx, st, v, sub, m, Y, ldy, HY, MY, ldo, row_obj, status);
+}
+inline int rt_spmm(ff_ctx *ctx, hipStream_t st, const rt::RTView &v, int sub, int m, const double *Y, int64_t ldy,
+                   double *HY, double *MY, int64_t ldo, const int *row_obj, const int *status) {
+    return rt::spmm64(ctx, st, v, sub, m, Y, ldy, HY, MY, ldo, row_obj, status);
+}
 
 template <typename T>
 int launch_spmm(ff_ctx *ctx, hipStream_t st, int variant, int64_t nrows, const int64_t *row_ptr, const int32_t *col,
                 HMPair<T> hm, const T *Y, int64_t ldy, T *HY, T *MY, int64_t ldo, int m, const int *row_obj,
-                const int *status) {
+                const int *status, const rt::RTView *rtv) {
+    if (variant >= kRowTileBase) {
+        FF_REQUIRE(ctx, rtv != nullptr, "row-tile SpMM variant without a row-tile copy");
+        return rt_spmm(ctx, st, *rtv, variant - kRowTileBase, m, Y, ldy, HY, MY, ldo, row_obj, status);
+    }
 #define FF_SPMM(W, U, X)                                                                                        \
     hipLaunchKernelGGL((spmm_kernel<T, W, U, X>), dim3(grid_for(nrows, W)), dim3(64 * W), 0, st, nrows, row_ptr, \
                        col, hm, Y, ldy, HY, MY, ldo, m, row_obj, status)
@@ -1567,6 +1584,7 @@ struct Solver {
     const float *hm32 = nullptr;
     int m = 0, k = 0, wmax = 0;
     int var32 = 0, var64 = 0;
+    rt::RTView rtv;                                // row-tile copy when a row-tile variant is selected
     bool jacobi = false;
     int *status = nullptr, *width = nullptr, *info = nullptr, *iters = nullptr, *row_obj = nullptr;
     int *ufirst = nullptr, *ucount = nullptr, *gfirst = nullptr, *gcount = nullptr;
@@ -1616,7 +1634,8 @@ template <typename T>
 int stage_spmm(Solver &s, T *S, T *HS, T *MS, int slot) {
     const int64_t ld = 3 * (int64_t)s.m;
     return launch_spmm<T>(s.ctx, s.st, sizeof(T) == 4 ? s.var32 : s.var64, s.N, s.row_ptr, s.col, hm_of<T>(s),
-                          S + slot * s.m, ld, HS + slot * s.m, MS + slot * s.m, ld, s.m, s.row_obj, s.status);
+                          S + slot * s.m, ld, HS + slot * s.m, MS + slot * s.m, ld, s.m, s.row_obj, s.status,
+                          &s.rtv);
 }
 
 // the four Rayleigh-Ritz stages on every active object (LDS limits set by rr_prepare)
@@ -1952,6 +1971,13 @@ int solve(ff_ctx *ctx, int n_obj, const int64_t *obj_off, const int64_t *row_ptr
     const int64_t nnz = hnnz[0];
     s.var32 = lookup_variant(ctx, s.N, nnz, m, 1);
     s.var64 = lookup_variant(ctx, s.N, nnz, m, 0);
+    {
+        const int want32 = p->precision == 1 && s.var32 >= kRowTileBase, want64 = s.var64 >= kRowTileBase;
+        if (want32 || want64) {
+            int rc0 = rt::build_ws(ctx, s.st, s.N, row_ptr, col, H, M, want32, want64, &s.rtv);
+            if (rc0) return rc0;
+        }
+    }
     int rc = setup(s, p);
     if (rc) return rc;
     const int check_every = p->check_every > 0 ? p->check_every : 10;
@@ -2108,14 +2134,22 @@ extern "C" int spmm_hm(ff_ctx *ctx, int64_t n, const int64_t *row_ptr, const int
         v = lookup_variant(ctx, n, h[0], m, precision);
     }
     FF_REQUIRE(ctx, v >= 0 && v < kNumVariants, "variant %d out of range", v);
+    // a row-tile variant builds its copy of the matrix for this call (rowtiles_build keeps one)
+    rt::RTView view;
+    if (v >= kRowTileBase) {
+        FF_REQUIRE(ctx, H && M, "row-tile variants need H and M");
+        int rc = rt::build_ws(ctx, ctx->stream, n, row_ptr, col, H, M, precision, !precision, &view);
+        if (rc) return rc;
+    }
     if (precision) {
-        FF_REQUIRE(ctx, hm32 != nullptr, "hm32 is NULL");
+        FF_REQUIRE(ctx, hm32 != nullptr || v >= kRowTileBase, "hm32 is NULL");
         return launch_spmm<float>(ctx, ctx->stream, v, n, row_ptr, col, HMPair<float>{(const float2 *)hm32},
-                                  (const float *)Y, ld_y, (float *)HY, (float *)MY, ld_out, m, nullptr, nullptr);
+                                  (const float *)Y, ld_y, (float *)HY, (float *)MY, ld_out, m, nullptr, nullptr,
+                                  &view);
     }
     FF_REQUIRE(ctx, H && M, "H or M is NULL");
     return launch_spmm<double>(ctx, ctx->stream, v, n, row_ptr, col, HMPair<double>{H, M}, (const double *)Y, ld_y,
-                               (double *)HY, (double *)MY, ld_out, m, nullptr, nullptr);
+                               (double *)HY, (double *)MY, ld_out, m, nullptr, nullptr, &view);
 }
 
 extern "C" int spmm_variant_count(void) { return kNumVariants; }
@@ -2134,6 +2168,10 @@ extern "C" int spmm_autotune(ff_ctx *ctx, int64_t n, const int64_t *row_ptr, con
                              int *best_variant, double *best_ms) {
     if (!ctx) return FF_ERR_INVALID_ARG;
     FF_REQUIRE(ctx, best_variant && best_ms, "required pointer is NULL");
+    FF_REQUIRE(ctx, n > 0 && row_ptr && col && H && M && (precision == 0 || hm32), "bad arguments");
+    FF_REQUIRE(ctx, precision == 0 || precision == 1, "precision must be 0 or 1");
+    FF_REQUIRE(ctx, m > 0 && m % (precision ? 4 : 2) == 0 && m / (precision ? 4 : 2) <= 64,
+               "block width %d not supported", m);
     FF_HIP(ctx, hipSetDevice(ctx->device));
     int64_t *h = (int64_t *)pinned_get(ctx, 4096);
     if (!h) return FF_ERR_OOM;
@@ -2170,17 +2208,30 @@ extern "C" int spmm_autotune(ff_ctx *ctx, int64_t n, const int64_t *row_ptr, con
     FF_HIP(ctx, hipEventCreate(&e1));
     int best = 0;
     double bms = 1e30;
+    rt::RTView view;
+    int have_view = 0;
     for (int v = 0; v < kNumVariants; ++v) {
-        int rc = spmm_hm(ctx, n, row_ptr, col, H, M, hm32, precision, m, buf, m, buf + (size_t)n * m * esz,
-                         buf + 2 * (size_t)n * m * esz, m, v);
+        if (v >= kRowTileBase && !have_view) {
+            int rc0 = rt::build_ws(ctx, ctx->stream, n, row_ptr, col, H, M, precision, !precision, &view);
+            if (rc0) return rc0;
+            have_view = 1;
+        }
+        auto run = [&]() -> int {
+            if (precision)
+                return launch_spmm<float>(ctx, ctx->stream, v, n, row_ptr, col,
+                                          HMPair<float>{(const float2 *)hm32}, (const float *)buf, m,
+                                          (float *)(buf + (size_t)n * m * esz), (float *)(buf + 2 * (size_t)n * m * esz),
+                                          m, m, nullptr, nullptr, &view);
+            return launch_spmm<double>(ctx, ctx->stream, v, n, row_ptr, col, HMPair<double>{H, M},
+                                       (const double *)buf, m, (double *)(buf + (size_t)n * m * esz),
+                                       (double *)(buf + 2 * (size_t)n * m * esz), m, m, nullptr, nullptr, &view);
+        };
+        int rc = run();
         if (rc) return rc;
         FF_HIP(ctx, hipEventRecord(e0, ctx->stream));
         const int reps = 5;
-        for (int r = 0; r < reps; ++r) {
-            rc = spmm_hm(ctx, n, row_ptr, col, H, M, hm32, precision, m, buf, m, buf + (size_t)n * m * esz,
-                         buf + 2 * (size_t)n * m * esz, m, v);
-            if (rc) return rc;
-        }
+        for (int r = 0; r < reps; ++r)
+            if ((rc = run())) return rc;
         FF_HIP(ctx, hipEventRecord(e1, ctx->stream));
         FF_HIP(ctx, hipEventSynchronize(e1));
         float ms = 0.f;

@@ -92,6 +92,10 @@ def lib():
         "spmm_variant_count": (i32, []),
         "spmm_variant_name": (ctypes.c_char_p, [i32]),
         "spmm_variant_selected": (i32, [vp, i64, i64, i32, i32]),
+        "rowtiles_build": (i32, [vp, i64, vp, vp, vp, vp, i32, P(vp)]),
+        "rowtiles_info": (i32, [vp, P(i64), P(i64)]),
+        "spmm_rowtiles": (i32, [vp, vp, i32, i32, vp, i64, vp, vp, i64, i32]),
+        "rowtiles_destroy": (None, [vp]),
         "rand_block": (i32, [vp, i64, i32, ctypes.c_uint64, vp]),
         "philox4x32_10": (i32, [vp, i32, vp, vp, vp]),
         "mlp_param_count": (i32, [i32, i32]),
@@ -311,6 +315,46 @@ def rayleigh_ritz(ctx: Context, G, m: int, tau: float = 1e-13):
     kept = ctypes.c_int()
     ctx.check(lib().rayleigh_ritz(ctx.h, w, m, _p(G.contiguous()), tau, _p(C), _p(theta), ctypes.byref(kept)))
     return theta, C, kept.value
+
+
+class RowTiles:
+    """Handle of an ff_rowtiles copy of [H, M] (tiles of four rows sharing one column list)."""
+
+    def __init__(self, ctx: Context, n: int, row_ptr, col, H, M, precision: int = 1):
+        self.ctx = ctx
+        self.h = None
+        h = ctypes.c_void_p()
+        ctx.check(lib().rowtiles_build(ctx.h, n, _p(row_ptr), _p(col), _p(H), _p(M), precision, ctypes.byref(h)))
+        self.h = h
+        ctx._children.add(self)
+
+    def info(self):
+        nt, ne = ctypes.c_int64(), ctypes.c_int64()
+        lib().rowtiles_info(self.h, ctypes.byref(nt), ctypes.byref(ne))
+        return nt.value, ne.value
+
+    def spmm(self, Y, precision: int, sub: int = 0, out=None):
+        import torch
+        n, m = Y.shape
+        if out is None:
+            HY = torch.empty_like(Y)
+            MY = torch.empty_like(Y)
+        else:
+            HY, MY = out
+        self.ctx.check(lib().spmm_rowtiles(self.ctx.h, self.h, precision, m, _p(Y), Y.stride(0), _p(HY), _p(MY),
+                                           HY.stride(0), sub))
+        return HY, MY
+
+    def close(self):
+        if self.h:
+            lib().rowtiles_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def spmm_variant_selected(ctx: Context, n: int, nnz: int, m: int, precision: int) -> int:

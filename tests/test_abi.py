@@ -34,7 +34,8 @@ def test_library_exports_every_declared_symbol():
 def test_binding_names_match_header():
     from paper_2605_29318_amd import freeform
     for n in ("build_neighbors", "rkpm_shape", "assemble_HM", "eigenmodes", "eigenmodes_batched", "spmm_hm",
-              "spmm_autotune", "rand_block", "philox4x32_10", "mlp_param_count", "mlp_inputs", "lumped_mass"):
+              "spmm_autotune", "rand_block", "philox4x32_10", "mlp_param_count", "mlp_inputs", "lumped_mass",
+              "RowTiles", "spmm_variant_selected"):
         assert callable(getattr(freeform, n))
     # every declared entry point has a ctypes signature in the binding
     L = freeform.lib()

@@ -164,6 +164,33 @@ def test_spmm(oracle, ctx, ff, precision, m):
         assert np.all(np.abs(host(MY) - refM) <= eps * absM + 1e-300)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_rowtiles_spmm(oracle, ctx, ff, precision):
+    """The row-tile copy (tiles of four rows, ragged last tile) gives the same products;
+    its union entries are at least the largest row and at most the sum of four rows."""
+    c = synth.random_cloud(2501, seed=23, hetero=True)
+    P = oracle.pipeline(c)
+    A = ff.assemble_cloud(ctx, dev(c.xyz), dev(c.vol), dev(c.lam), dev(c.mu), c.h)
+    rt = ff.RowTiles(ctx, A.n, A.row_ptr, A.col, A.H, A.M, precision=precision)
+    ntiles, entries = rt.info()
+    assert ntiles == (c.n + 3) // 4
+    rl = np.diff(P.row_ptr)
+    assert rl.max() <= entries <= rl.sum()
+    dt = torch.float32 if precision else torch.float64
+    eps = 2e-6 if precision else 1e-13
+    for m in (8, 24, 32):
+        Y = np.random.default_rng(m).standard_normal((c.n, m))
+        refH = oracle.spmm(P.row_ptr, P.col, P.H, Y)
+        refM = oracle.spmm(P.row_ptr, P.col, P.M, Y)
+        absH = oracle.spmm(P.row_ptr, P.col, np.abs(P.H), np.abs(Y))
+        absM = oracle.spmm(P.row_ptr, P.col, np.abs(P.M), np.abs(Y))
+        for sub in range(3):
+            HY, MY = rt.spmm(dev(Y, dt), precision, sub)
+            assert np.all(np.abs(host(HY) - refH) <= eps * absH + 1e-300)
+            assert np.all(np.abs(host(MY) - refM) <= eps * absM + 1e-300)
+    rt.close()
+
+
 def test_philox_known_answers(ctx, ff):
     """Known-answer vectors of Philox-4x32-10 (Salmon et al., SC'11, Random123 distribution)."""
     import os
