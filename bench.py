@@ -49,27 +49,97 @@ def run_step(ff, ctx, dev_in, n, h, k, precision, tol, max_iter, use_graph=False
     return dict(total=t2 - t0, build=t1 - t0, solve=t2 - t1, ev=ev, res=res, info=info, A=A, W=W)
 
 
-def spmm_rate(ff, ctx, A, n, m, reps=20):
-    """Average duration of the FP32 fused SpMM launch (events on the context's stream)."""
+KERNEL_SRC = os.path.join(ROOT, "paper_2605_29318_amd", "csrc", "k_rowtile.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "spmm_rowtile_ellipsoids1m_k32_hbm_traffic.txt")
+
+
+def kernel_source_hash():
+    import hashlib
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def spmm_setup(ff, ctx, A, n, m):
+    """The eigensolver's FP32 SpMM as it runs in the iteration: the row-tile copy of
+    [H, M] and the launch shape the solver selects, on the W slice of an [n][3m] block."""
     import torch
-    stream = ctx.stream
+    nnz = int(A.col.numel())
+    v = ff.spmm_variant_selected(ctx, n, nnz, m, 1)
+    names = ff.spmm_variant_names()
+    base = [i for i, nm in enumerate(names) if nm.startswith("rowtile")][0]
+    if v < base:
+        raise RuntimeError(f"selected SpMM variant {names[v]} is not a row-tile variant")
+    rt = ff.RowTiles(ctx, n, A.row_ptr, A.col, A.H, A.M, precision=1)
     Y = torch.randn((n, 3 * m), dtype=torch.float32, device="cuda")
     HY = torch.empty_like(Y)
     MY = torch.empty_like(Y)
-    Yv = Y[:, m:2 * m]
-    out = (HY[:, m:2 * m], MY[:, m:2 * m])
-    ff.spmm_hm(ctx, A.row_ptr, A.col, A.H, A.M, A.hm32, Yv, 1, out=out)
+    return rt, v - base, names[v], Y[:, m:2 * m], (HY[:, m:2 * m], MY[:, m:2 * m])
+
+
+def spmm_rate(ff, ctx, A, n, m, reps=20):
+    """Average duration of the FP32 fused SpMM launch (HIP events on the context's stream)."""
+    import torch
+    rt, sub, name, Yv, out = spmm_setup(ff, ctx, A, n, m)
+    stream = ctx.stream
+    rt.spmm(Yv, 1, sub, out=out)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(reps):
-        ff.spmm_hm(ctx, A.row_ptr, A.col, A.H, A.M, A.hm32, Yv, 1, out=out)
+        rt.spmm(Yv, 1, sub, out=out)
     e1.record(stream)
     e1.synchronize()
     ms = e0.elapsed_time(e1) / reps
     nnz = int(A.col.numel())
+    # algorithmic bytes of the product, independent of the storage format: FP32 H and M
+    # values and an int32 column per nonzero, the row pointers, Y read once, HY and MY written
     alg_bytes = nnz * 12 + 8 * (n + 1) + 4 * n * m + 8 * n * m
-    return ms, alg_bytes
+    ntiles, entries = rt.info()
+    rt.close()
+    return ms, alg_bytes, name, entries
+
+
+def measured_traffic():
+    """HBM bytes per SpMM launch from the committed counter summary (FETCH_SIZE and
+    WRITE_SIZE passes, each scaled by the same counter on a copy of known size), or
+    None when the summary is missing or was taken on another version of the kernel."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def spmm_only(args):
+    """Counter-collection helper: the SpMM launches of the benchmark workload and an
+    elementwise kernel that reads and writes 1 GiB (the counters' calibration)."""
+    import numpy as np
+    import torch
+    from paper_2605_29318_amd import freeform as ff
+    from paper_2605_29318_amd import synth
+    c = synth.ellipsoid_union(n=args.n, seed=3, hetero=True, k=args.k, mc_samples=4_000_000)
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), device="cuda")
+    ctx = ff.Context(0)
+    A = ff.assemble_cloud(ctx, dev(c.xyz), dev(c.vol), dev(c.lam), dev(c.mu), c.h)
+    m = args.k if args.k % 8 == 0 else ((args.k + 7) // 8) * 8
+    rt, sub, name, Yv, out = spmm_setup(ff, ctx, A, c.n, m)
+    for _ in range(args.steps):
+        rt.spmm(Yv, 1, sub, out=out)
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")     # 1 GiB
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    log(f"[bench] spmm-only: {args.steps} launches of {name}, 3 calibration passes over 1 GiB")
+    rt.close()
+    ctx.close()
 
 
 def cpu_baseline(n_sample, k, iters, gpu_iters, n_full):
@@ -111,11 +181,16 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--graph", action="store_true")
+    ap.add_argument("--spmm-only", action="store_true",
+                    help="run only the SpMM launches and a 1 GiB calibration kernel (for counter passes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1).", file=sys.stderr)
         sys.exit(2)
+    if args.spmm_only:
+        spmm_only(args)
+        return
 
     import numpy as np
     import torch
@@ -158,10 +233,11 @@ def main():
         log(f"[bench] fp64 step: {r64['total']:.3f} s, iters {r64['info']['iters_fp64']}")
 
     m = args.k if args.k % 8 == 0 else ((args.k + 7) // 8) * 8
-    spmm_ms, alg_bytes = spmm_rate(ff, ctx, A, c.n, m)
-    variant = ff.spmm_variant_names()[ff.spmm_variant_selected(ctx, c.n, nnz, m, 1)]
+    spmm_ms, alg_bytes, variant, entries = spmm_rate(ff, ctx, A, c.n, m)
     achieved = alg_bytes / (spmm_ms * 1e-3) / 1e9
-    log(f"[bench] spmm fp32: {spmm_ms:.3f} ms, {achieved:.0f} GB/s algorithmic")
+    traffic = measured_traffic()
+    log(f"[bench] spmm fp32 ({variant}): {spmm_ms:.3f} ms, {achieved:.0f} GB/s algorithmic, "
+        f"{entries} row-tile entries for {nnz} nonzeros")
 
     cpu = None
     if not args.no_cpu:
@@ -195,8 +271,8 @@ def main():
         "speedup_vs_fp64": (round(fp64["seconds"] / (ms_per_step / 1e3), 3) if fp64 else None),
         "spmm_gbps": round(achieved, 1),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "fused [H,M] Y SpMM, FP32, m=%d, variant %s" % (m, variant),
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": "spmm_rt_kernel (fused [H,M] Y on the row-tile copy, FP32, m=%d, %s)" % (m, variant),
                      "bytes_per_launch": alg_bytes, "launch_ms": round(spmm_ms, 4)},
         "cpu_baseline": cpu,
     }

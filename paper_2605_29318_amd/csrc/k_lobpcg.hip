@@ -1516,6 +1516,7 @@ static const char *kVariantNames[] = {"waves4_unroll2_xcd", "waves4_unroll4_xcd"
                                       "rowtile4_waves4_batch4_occ4"};
 constexpr int kNumVariants = 16;
 constexpr int kRowTileBase = 13;               // variants from here on run on the row-tile copy
+constexpr int kCsrVariant = 11;                // fastest variant on the CSR itself
 constexpr int kDefaultVariant = 14;    // fastest untuned choice on 10^5-10^6-row RKPM matrices (row tiles)
 
 inline int rt_spmm(ff_ctx *ctx, hipStream_t st, const rt::RTView &v, int sub, int m, const float *Y, int64_t ldy,
@@ -1972,6 +1973,9 @@ int solve(ff_ctx *ctx, int n_obj, const int64_t *obj_off, const int64_t *row_ptr
     s.var32 = lookup_variant(ctx, s.N, nnz, m, 1);
     s.var64 = lookup_variant(ctx, s.N, nnz, m, 0);
     {
+        // the mixed path's FP64 phase is normally the certification alone: it keeps the CSR
+        // (kCsrVariant) rather than paying for an FP64 row-tile copy
+        if (p->precision == 1 && s.var64 >= kRowTileBase) s.var64 = kCsrVariant;
         const int want32 = p->precision == 1 && s.var32 >= kRowTileBase, want64 = s.var64 >= kRowTileBase;
         if (want32 || want64) {
             int rc0 = rt::build_ws(ctx, s.st, s.N, row_ptr, col, H, M, want32, want64, &s.rtv);
