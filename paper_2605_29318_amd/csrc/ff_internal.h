@@ -27,6 +27,7 @@ enum WsSlot {
     WS_DINV, WS_DINV32, WS_NORMS, WS_CHUNKS, WS_GCHUNKS, WS_OBJ, WS_SIGN, WS_TUNE,
     WS_MLP0, WS_MLP1, WS_MLP2, WS_MLP3, WS_MLP4, WS_MLP5, WS_MLP6, WS_MLP7,
     WS_RT_CNT, WS_RT_PTR, WS_RT_COL, WS_RT_VAL32, WS_RT_VAL64,   // row-tile SpMM copies
+    WS_CHEB0, WS_CHEB1, WS_CHEB2, WS_CHEB3, WS_CHEB4,             // Chebyshev-Jacobi work
     WS_COUNT
 };
 

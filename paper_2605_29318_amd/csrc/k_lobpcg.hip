@@ -1491,6 +1491,134 @@ __global__ void diag_inv_bs_kernel(int64_t n, const int64_t *row_ptr, const int3
     d32[r] = (float)v;
 }
 
+// ---------------------------------------------------------------------------
+// Chebyshev-Jacobi preconditioner: z = q(A) D^-1 r with A = D^-1 H, D = diag(H),
+// q the Chebyshev semi-iteration polynomial of degree d for A z = D^-1 r on
+// [a, b] (b an upper bound of the spectrum of A, a = b / 30). q(x) > 0 on
+// (0, b], so the preconditioner is SPD there. Per object: coef[0] = 1 / theta,
+// coef[2s - 1], coef[2s] the step-s factors of dz (rho_s rho_{s-1}) and of r
+// (2 rho_s / delta), theta = (a + b) / 2, delta = (b - a) / 2.
+// ---------------------------------------------------------------------------
+
+constexpr int kChebCoef = 16;                  // per-object coefficient stride (degree <= 8)
+
+// Gershgorin bound of D^-1/2 H D^-1/2 per row: sum_j |H_ij| / sqrt(H_ii H_jj), one wavefront per row
+__global__ void gersh_row_kernel(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *H,
+                                 const double *dinv, double *g) {
+    const int lane = threadIdx.x & 63;
+    const int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (r >= n) return;
+    double s = 0.0;
+    for (int64_t e = row_ptr[r] + lane; e < row_ptr[r + 1]; e += 64) s += fabs(H[e]) * sqrt(dinv[col[e]]);
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d, 64);
+    if (lane == 0) g[r] = s * sqrt(dinv[r]);
+}
+
+// per chunk: max of g over its rows, and for the 8 power-iteration columns y^T H y and y^T D y
+__global__ void __launch_bounds__(256) cheb_chunk_kernel(const GChunk *chunks, const double *g, const double *Y,
+                                                         const double *HY, const double *dinv, double *part) {
+    const GChunk ch = chunks[blockIdx.x];
+    const int t = threadIdx.x;
+    const int c = t & 7, rr = t >> 3;              // 32 row lanes x 8 columns
+    double gm = 0.0, num = 0.0, den = 0.0;
+    for (int64_t r = ch.r0 + rr; r < ch.r0 + ch.len; r += 32) {
+        if (Y) {
+            const double y = Y[r * 8 + c];
+            num += y * HY[r * 8 + c];
+            den += y * y / dinv[r];
+        }
+        if (c == 0) gm = fmax(gm, g[r]);
+    }
+    __shared__ double red[3][256];
+    red[0][t] = gm;
+    red[1][t] = num;
+    red[2][t] = den;
+    __syncthreads();
+    if (t < 8) {
+        double a = 0.0, b = 0.0, m = 0.0;
+        for (int q = 0; q < 32; ++q) {
+            m = fmax(m, red[0][q * 8 + t]);
+            a += red[1][q * 8 + t];
+            b += red[2][q * 8 + t];
+        }
+        part[(size_t)blockIdx.x * 17 + 1 + t] = a;
+        part[(size_t)blockIdx.x * 17 + 9 + t] = b;
+        if (t == 0) part[(size_t)blockIdx.x * 17] = m;   // the row maxima live in the c == 0 lanes
+    }
+}
+
+// per object: sums over its chunks (ascending) -> out[o][17] (Gershgorin max, 8 numerators, 8 denominators)
+__global__ void cheb_obj_kernel(int n_obj, const int *gfirst, const int *gcount, const double *part, double *out) {
+    const int o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= n_obj) return;
+    double v[17];
+    for (int q = 0; q < 17; ++q) v[q] = 0.0;
+    for (int c = gfirst[o]; c < gfirst[o] + gcount[o]; ++c) {
+        v[0] = fmax(v[0], part[(size_t)c * 17]);
+        for (int q = 1; q < 17; ++q) v[q] += part[(size_t)c * 17 + q];
+    }
+    for (int q = 0; q < 17; ++q) out[(size_t)o * 17 + q] = v[q];
+}
+
+// one power step y <- D^-1 H y / gersh(obj): the factor keeps the block bounded without normalisation
+template <typename T>
+__global__ void power_step_kernel(int64_t n, const int *row_obj, const double *objv, const T *HY, const T *dinv,
+                                  T *Y) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * 8) return;
+    const int64_t r = t >> 3;
+    Y[t] = (T)((double)dinv[r] * (double)HY[t] / objv[(size_t)row_obj[r] * 17]);
+}
+
+template <typename T>
+__global__ void to_f64_kernel(int64_t count, const T *a, double *b) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < count) b[t] = (double)a[t];
+}
+template <typename T>
+__global__ void from_f64_kernel(int64_t count, const double *a, T *b) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < count) b[t] = (T)a[t];
+}
+
+// z0: R <- W (= D^-1 r, written by resid_kernel), dz = W / theta, W <- dz
+template <typename T>
+__global__ void cheb_init_kernel(int64_t n, int m, int64_t ld, const int *row_obj, const int *obj_status,
+                                 const double *coef, T *S, T *Rb, T *DZ) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * m) return;
+    const int64_t r = t / m;
+    const int c = (int)(t - r * m);
+    const int o = row_obj[r];
+    if (obj_status[o] != 0) return;
+    T *w = S + r * ld + m + c;
+    const double v = (double)*w;
+    const double dz = v * coef[(size_t)o * kChebCoef];
+    Rb[t] = (T)v;
+    DZ[t] = (T)dz;
+    *w = (T)dz;
+}
+
+// step s: R -= D^-1 H dz, dz = f1 dz + f2 R, W += dz
+template <typename T>
+__global__ void cheb_step_kernel(int64_t n, int m, int64_t ld, int step, const int *row_obj, const int *obj_status,
+                                 const double *coef, const T *dinv, const T *HD, T *S, T *Rb, T *DZ) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * m) return;
+    const int64_t r = t / m;
+    const int c = (int)(t - r * m);
+    const int o = row_obj[r];
+    if (obj_status[o] != 0) return;
+    const double f1 = coef[(size_t)o * kChebCoef + 2 * step - 1], f2 = coef[(size_t)o * kChebCoef + 2 * step];
+    const double rv = (double)Rb[t] - (double)dinv[r] * (double)HD[t];
+    const double dz = f1 * (double)DZ[t] + f2 * rv;
+    Rb[t] = (T)rv;
+    DZ[t] = (T)dz;
+    T *w = S + r * ld + m + c;
+    *w = (T)((double)*w + dz);
+}
+
 __global__ void row_obj_kernel(int64_t N, const int64_t *obj_off, int n_obj, int *row_obj) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= N) return;
@@ -1587,6 +1715,9 @@ struct Solver {
     int var32 = 0, var64 = 0;
     rt::RTView rtv;                                // row-tile copy when a row-tile variant is selected
     bool jacobi = false;
+    int cheb = 0;                                  // Chebyshev-Jacobi degree (0: plain Jacobi or none)
+    double *cheb_coef = nullptr;                   // [n_obj][kChebCoef]
+    void *cheb_r = nullptr, *cheb_dz = nullptr, *cheb_hd = nullptr, *cheb_md = nullptr;   // [N][m] work blocks
     int *status = nullptr, *width = nullptr, *info = nullptr, *iters = nullptr, *row_obj = nullptr;
     int *ufirst = nullptr, *ucount = nullptr, *gfirst = nullptr, *gcount = nullptr;
     int64_t *obj_off = nullptr;
@@ -1718,6 +1849,27 @@ int stage_resid(Solver &s, T *S, T *HS, T *MS, double tol, int stall) {
     return FF_OK;
 }
 
+// W <- q(D^-1 H) D^-1 R (the resid stage left D^-1 R in W)
+template <typename T>
+int stage_precond(Solver &s, T *S) {
+    if (s.cheb < 2) return FF_OK;
+    const int64_t cnt = s.N * s.m;
+    const int64_t ld = 3 * (int64_t)s.m;
+    T *Rb = (T *)s.cheb_r, *DZ = (T *)s.cheb_dz, *HD = (T *)s.cheb_hd, *MD = (T *)s.cheb_md;
+    hipLaunchKernelGGL(cheb_init_kernel<T>, dim3(grid_for(cnt, 256)), dim3(256), 0, s.st, s.N, s.m, ld, s.row_obj,
+                       s.status, s.cheb_coef, S, Rb, DZ);
+    FF_CHECK_LAUNCH(s.ctx);
+    for (int step = 1; step < s.cheb; ++step) {
+        int rc = launch_spmm<T>(s.ctx, s.st, sizeof(T) == 4 ? s.var32 : s.var64, s.N, s.row_ptr, s.col, hm_of<T>(s),
+                                DZ, s.m, HD, MD, s.m, s.m, s.row_obj, s.status, &s.rtv);
+        if (rc) return rc;
+        hipLaunchKernelGGL(cheb_step_kernel<T>, dim3(grid_for(cnt, 256)), dim3(256), 0, s.st, s.N, s.m, ld, step,
+                           s.row_obj, s.status, s.cheb_coef, dinv_of<T>(s), HD, S, Rb, DZ);
+        FF_CHECK_LAUNCH(s.ctx);
+    }
+    return FF_OK;
+}
+
 // X-only Rayleigh-Ritz: images of X, M-orthonormalise and diagonalise
 template <typename T>
 int init_block(Solver &s, T *S, T *HS, T *MS, double tau) {
@@ -1729,10 +1881,93 @@ int init_block(Solver &s, T *S, T *HS, T *MS, double tau) {
     return set_width(s, 2 * s.m, 1);
 }
 
+// Chebyshev-Jacobi set-up: per object, the Gershgorin bound g of D^-1/2 H D^-1/2 and
+// the largest Rayleigh quotient of D^-1 H after 30 steps of power iteration on 8
+// seeded vectors (in the working precision); b = min(1.1 x quotient, g), a = b / 30.
+template <typename T>
+int cheb_setup(Solver &s, int degree, uint64_t seed) {
+    ff_ctx *ctx = s.ctx;
+    const int64_t N = s.N;
+    const int n_obj = s.n_obj;
+    const size_t blk = (size_t)N * s.m * sizeof(double);
+    s.cheb_r = ws_get(ctx, WS_CHEB0, blk);
+    s.cheb_dz = ws_get(ctx, WS_CHEB1, blk);
+    s.cheb_hd = ws_get(ctx, WS_CHEB2, blk);
+    s.cheb_md = ws_get(ctx, WS_CHEB3, blk);
+    double *aux = (double *)ws_get(ctx, WS_CHEB4, ((size_t)n_obj * (kChebCoef + 17) + (size_t)s.ng * 17 + N) *
+                                                      sizeof(double));
+    if (!s.cheb_r || !s.cheb_dz || !s.cheb_hd || !s.cheb_md || !aux) return FF_ERR_OOM;
+    s.cheb_coef = aux;
+    double *objv = aux + (size_t)n_obj * kChebCoef, *part = objv + (size_t)n_obj * 17, *grow = part + (size_t)s.ng * 17;
+    const int var = sizeof(T) == 4 ? s.var32 : s.var64;
+    // Gershgorin bounds
+    hipLaunchKernelGGL(gersh_row_kernel, dim3(grid_for(N, 4)), dim3(256), 0, s.st, N, s.row_ptr, s.col, s.H, s.dinv64,
+                       grow);
+    hipLaunchKernelGGL(cheb_chunk_kernel, dim3(s.ng), dim3(256), 0, s.st, s.gch, grow, (const double *)nullptr,
+                       (const double *)nullptr, s.dinv64, part);
+    hipLaunchKernelGGL(cheb_obj_kernel, dim3(grid_for(n_obj, 64)), dim3(64), 0, s.st, n_obj, s.gfirst, s.gcount, part,
+                       objv);
+    FF_CHECK_LAUNCH(ctx);
+    // power iteration on 8 columns: Y in cheb_r, HY in cheb_hd, MY in cheb_md (stride 8)
+    T *Y = (T *)s.cheb_r, *HY = (T *)s.cheb_hd, *MY = (T *)s.cheb_md;
+    double *Yd = (double *)s.cheb_dz;
+    hipLaunchKernelGGL(philox_block_kernel, dim3(grid_for((N * 8 + 3) / 4, 256)), dim3(256), 0, s.st, N * 8,
+                       seed ^ 0x9e3779b97f4a7c15ull, Yd);
+    hipLaunchKernelGGL(from_f64_kernel<T>, dim3(grid_for(N * 8, 256)), dim3(256), 0, s.st, N * 8, (const double *)Yd, Y);
+    FF_CHECK_LAUNCH(ctx);
+    int rc;
+    for (int it = 0; it < 30; ++it) {
+        if ((rc = launch_spmm<T>(ctx, s.st, var, N, s.row_ptr, s.col, hm_of<T>(s), Y, 8, HY, MY, 8, 8, s.row_obj,
+                                 s.status, &s.rtv)))
+            return rc;
+        hipLaunchKernelGGL(power_step_kernel<T>, dim3(grid_for(N * 8, 256)), dim3(256), 0, s.st, N, s.row_obj, objv,
+                           HY, dinv_of<T>(s), Y);
+        FF_CHECK_LAUNCH(ctx);
+    }
+    if ((rc = launch_spmm<T>(ctx, s.st, var, N, s.row_ptr, s.col, hm_of<T>(s), Y, 8, HY, MY, 8, 8, s.row_obj,
+                             s.status, &s.rtv)))
+        return rc;
+    double *HYd = (double *)s.cheb_md;            // MY is no longer needed
+    hipLaunchKernelGGL(to_f64_kernel<T>, dim3(grid_for(N * 8, 256)), dim3(256), 0, s.st, N * 8, (const T *)Y, Yd);
+    hipLaunchKernelGGL(to_f64_kernel<T>, dim3(grid_for(N * 8, 256)), dim3(256), 0, s.st, N * 8, (const T *)HY, HYd);
+    hipLaunchKernelGGL(cheb_chunk_kernel, dim3(s.ng), dim3(256), 0, s.st, s.gch, grow, (const double *)Yd,
+                       (const double *)HYd, s.dinv64, part);
+    hipLaunchKernelGGL(cheb_obj_kernel, dim3(grid_for(n_obj, 64)), dim3(64), 0, s.st, n_obj, s.gfirst, s.gcount, part,
+                       objv);
+    FF_CHECK_LAUNCH(ctx);
+    std::vector<double> hv((size_t)n_obj * 17), coef((size_t)n_obj * kChebCoef, 0.0);
+    FF_HIP(ctx, hipMemcpyAsync(hv.data(), objv, hv.size() * sizeof(double), hipMemcpyDeviceToHost, s.st));
+    FF_HIP(ctx, hipStreamSynchronize(s.st));
+    for (int o = 0; o < n_obj; ++o) {
+        const double *v = hv.data() + (size_t)o * 17;
+        double lam = 0.0;
+        for (int j = 0; j < 8; ++j)
+            if (v[9 + j] > 0.0) lam = std::max(lam, v[1 + j] / v[9 + j]);
+        const double g = v[0] > 0.0 ? v[0] : 1.0;
+        const double b = (lam > 0.0 && lam == lam) ? std::min(1.1 * lam, g) : g;
+        const double a = b / 30.0, theta = 0.5 * (a + b), delta = 0.5 * (b - a), sigma = theta / delta;
+        double *c = coef.data() + (size_t)o * kChebCoef;
+        c[0] = 1.0 / theta;
+        double rho_prev = 1.0 / sigma;
+        for (int step = 1; step < degree; ++step) {
+            const double rho = 1.0 / (2.0 * sigma - rho_prev);
+            c[2 * step - 1] = rho * rho_prev;
+            c[2 * step] = 2.0 * rho / delta;
+            rho_prev = rho;
+        }
+        if (ctx->verbose) fprintf(stderr, "[freeform] object %d: Gershgorin %.4g, power estimate %.4g, b %.4g\n", o, g, lam, b);
+    }
+    FF_HIP(ctx, hipMemcpyAsync(s.cheb_coef, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice, s.st));
+    FF_HIP(ctx, hipStreamSynchronize(s.st));
+    s.cheb = degree;
+    return FF_OK;
+}
+
 template <typename T>
 int body(Solver &s, T *S, T *HS, T *MS, double tol, int stall, double tau) {
     int rc;
     if ((rc = stage_resid<T>(s, S, HS, MS, tol, stall))) return rc;
+    if ((rc = stage_precond<T>(s, S))) return rc;
     if ((rc = stage_spmm<T>(s, S, HS, MS, 1))) return rc;
     if ((rc = stage_gram_rr<T>(s, S, HS, MS, tau))) return rc;
     if ((rc = stage_update<T>(s, S, HS, MS, 1))) return rc;
@@ -1897,7 +2132,7 @@ int setup(Solver &s, const ff_eig_params *p) {
     hipLaunchKernelGGL(rownorm_obj_kernel, dim3(grid_for(n_obj, 64)), dim3(64), 0, s.st, n_obj, s.ufirst, s.ucount,
                        s.rpart, s.norms);
     FF_CHECK_LAUNCH(ctx);
-    s.jacobi = p->precond == 1;
+    s.jacobi = p->precond == 1 || p->precond == 2;
     if (s.jacobi) {
         s.dinv64 = (double *)ws_get(ctx, WS_DINV, (size_t)s.N * sizeof(double));
         s.dinv32 = (float *)ws_get(ctx, WS_DINV32, (size_t)s.N * sizeof(float));
@@ -1936,6 +2171,9 @@ int solve(ff_ctx *ctx, int n_obj, const int64_t *obj_off, const int64_t *row_ptr
     FF_REQUIRE(ctx, p->precision == 0 || p->precision == 1, "precision must be 0 or 1");
     FF_REQUIRE(ctx, p->precision == 0 || hm32, "mixed precision needs the FP32 copies (hm32)");
     FF_REQUIRE(ctx, p->tol > 0.0 && p->max_iter >= 0, "bad tolerance or iteration cap");
+    FF_REQUIRE(ctx, p->precond >= 0 && p->precond <= 2, "precond must be 0, 1 or 2");
+    FF_REQUIRE(ctx, p->precond != 2 || p->precond_degree == 0 || (p->precond_degree >= 2 && p->precond_degree <= 8),
+               "Chebyshev degree %d must be 0 (default 4) or in [2, 8]", p->precond_degree);
     int m = p->block > 0 ? p->block : ((p->k + 7) / 8) * 8;
     FF_REQUIRE(ctx, m >= p->k && m % 8 == 0 && m >= 8 && m <= 64, "block %d: needs k <= m <= 64, m multiple of 8", m);
     Solver s;
@@ -1984,6 +2222,11 @@ int solve(ff_ctx *ctx, int n_obj, const int64_t *obj_off, const int64_t *row_ptr
     }
     int rc = setup(s, p);
     if (rc) return rc;
+    if (p->precond == 2) {
+        const int degree = p->precond_degree > 0 ? p->precond_degree : 4;
+        rc = p->precision == 1 ? cheb_setup<float>(s, degree, p->seed) : cheb_setup<double>(s, degree, p->seed);
+        if (rc) return rc;
+    }
     const int check_every = p->check_every > 0 ? p->check_every : 10;
     const double tau32 = 1e-5, tau64 = 1e-13;
     constexpr int kStall32 = 200;

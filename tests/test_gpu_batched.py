@@ -48,13 +48,14 @@ def batch(oracle, ctx, ff):
     return clouds, parts, refs
 
 
-@pytest.mark.parametrize("precision,graph", [(0, False), (1, False), (1, True)])
-def test_batched_matches_oracle(batch, oracle, ctx, ff, precision, graph):
+@pytest.mark.parametrize("precision,graph,precond", [(0, False, 1), (1, False, 1), (1, True, 1), (1, True, 2),
+                                                     (0, False, 2)])
+def test_batched_matches_oracle(batch, oracle, ctx, ff, precision, graph, precond):
     clouds, parts, refs = batch
     k = 16
     off, rp, col, H, M, hm = ff.concat_objects(parts)
     lam, W, res, infos, rc = ff.eigenmodes_batched(ctx, off, rp, col, H, M, hm, k=k, precision=precision,
-                                                   tol=1e-8, max_iter=8000, use_graph=graph)
+                                                   tol=1e-8, max_iter=8000, use_graph=graph, precond=precond)
     assert rc == 0
     Wh = W.cpu().numpy()
     for o, (P, wd, Vd) in enumerate(refs):

@@ -227,20 +227,21 @@ def _check_modes(oracle, P, lam, W, res, k, rel_tol, sin_tol, resid_tol):
     assert np.all(W[idx, np.arange(k)] > 0)
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_eigenmodes_cube(oracle, ctx, ff, precision):
+@pytest.mark.parametrize("precision,precond,degree", [(0, 1, 0), (1, 1, 0), (0, 2, 0), (1, 2, 3), (1, 2, 8)])
+def test_eigenmodes_cube(oracle, ctx, ff, precision, precond, degree):
     c = synth.cube_lattice()
     P = oracle.pipeline(c)
     A = ff.assemble_cloud(ctx, dev(c.xyz), dev(c.vol), dev(c.lam), dev(c.mu), c.h)
     k = 8
     lam, W, res, info = ff.eigenmodes(ctx, c.n, A.row_ptr, A.col, A.H, A.M, A.hm32, k=k, precision=precision,
-                                      tol=1e-8 if precision == 0 else 1e-6, max_iter=4000)
+                                      tol=1e-8 if precision == 0 else 1e-6, max_iter=4000, precond=precond,
+                                      precond_degree=degree)
     _check_modes(oracle, P, lam, host(W), res, k, 1e-8 if precision == 0 else 1e-5,
                  1e-6 if precision == 0 else 1e-3, 1e-8 if precision == 0 else 1e-6)
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_eigenmodes_random_hetero(oracle, ctx, ff, precision):
+@pytest.mark.parametrize("precision,precond", [(0, 1), (1, 1), (0, 2), (1, 2)])
+def test_eigenmodes_random_hetero(oracle, ctx, ff, precision, precond):
     """i.i.d. random particles give cond(M) ~ 2e7: a backward-error residual of 1e-6
     leaves ~3e-4 eigenvalue error even in exact FP64, so parity is checked at 1e-8
     (where the oracle's own solve is accurate to ~4e-8)."""
@@ -249,7 +250,7 @@ def test_eigenmodes_random_hetero(oracle, ctx, ff, precision):
     A = ff.assemble_cloud(ctx, dev(c.xyz), dev(c.vol), dev(c.lam), dev(c.mu), c.h)
     k = 16
     lam, W, res, info = ff.eigenmodes(ctx, c.n, A.row_ptr, A.col, A.H, A.M, A.hm32, k=k, precision=precision,
-                                      tol=1e-8, max_iter=8000)
+                                      tol=1e-8, max_iter=8000, precond=precond)
     _check_modes(oracle, P, lam, host(W), res, k, 1e-5, 1e-3, 1e-8)
 
 
@@ -262,6 +263,16 @@ def test_eigenmodes_given_start_block(oracle, ctx, ff):
     lam, W, res, info = ff.eigenmodes(ctx, c.n, A.row_ptr, A.col, A.H, A.M, A.hm32, k=8, precision=0, tol=1e-8,
                                       X0=dev(X0[perm]))
     _check_modes(oracle, P, lam, host(W), res, 8, 1e-8, 1e-6, 1e-8)
+
+
+def test_chebyshev_degree_is_validated(ctx, ff):
+    c = synth.cube_lattice()
+    A = ff.assemble_cloud(ctx, dev(c.xyz), dev(c.vol), dev(c.lam), dev(c.mu), c.h)
+    for bad in (1, 9, -2):
+        with pytest.raises(ff.FFError):
+            ff.eigenmodes(ctx, c.n, A.row_ptr, A.col, A.H, A.M, A.hm32, k=8, precond=2, precond_degree=bad)
+    with pytest.raises(ff.FFError):
+        ff.eigenmodes(ctx, c.n, A.row_ptr, A.col, A.H, A.M, A.hm32, k=8, precond=3)
 
 
 def test_not_converged_still_returns(ctx, ff):
