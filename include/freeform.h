@@ -278,7 +278,10 @@ int rayleigh_ritz(ff_ctx *ctx, int w, int m, const double *G, double tau, double
  *   both. Device memory owned by the handle until rowtiles_destroy (destroy it
  *   before its context). The CSR may be freed afterwards.
  * spmm_rowtiles: [HY, MY] = [H, M] Y as spmm_hm, on the copy; sub selects a
- *   launch shape (0 .. 2).
+ *   launch shape (0 .. 2). With MY NULL only HY = H Y is formed, the product
+ *   the Chebyshev-Jacobi preconditioner of eigenmodes runs: at precision 1 it
+ *   accumulates in FP32 (an approximate operator is all a preconditioner
+ *   needs), at precision 0 in FP64.
  */
 typedef struct ff_rowtiles ff_rowtiles;
 int rowtiles_build(ff_ctx *ctx, int64_t n, const int64_t *row_ptr, const int32_t *col, const double *H,

@@ -24,6 +24,7 @@ namespace lob {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
 
 __device__ inline int xcd_remap(int b, int nb) {
     // consecutive workgroups are dealt round-robin to the 8 XCDs; give each
@@ -589,6 +590,117 @@ __global__ void __launch_bounds__(256) update_kernel(const UChunk *chunks, const
                     ax[t] = mfma(av_, bx, ax[t]);
                     if (write_p) ap[t] = mfma(av_, bp, ap[t]);
                 }
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                if (t >= nct) break;
+                const int c = t * 16 + li;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int64_t row = rt + MfmaAcc<T>::row(lk, v);
+                    if (row >= rend || c >= m) continue;
+                    Arr[row * ld + c] = ax[t][v];
+                    if (write_p) Arr[row * ld + 2 * m + c] = ap[t][v];
+                }
+            }
+        }
+    }
+}
+
+// Block update with whole-row fragment loads. MFMA sums over k in any order, so
+// the k index of lane group lk at sub-step s of super-step kb is taken as
+// kb * 4VK + lk * VK + s (VK = 16 / sizeof(T)): each lane then reads VK
+// consecutive entries of its row with one 16-byte load; the loads of the next
+// four super-steps are in flight during the MFMAs of these. C and C_p' sit in LDS
+// in fragment order ([kb][t][lane][s]), so a lane's VK B values are one 16-byte
+// LDS read and a wave's reads cover consecutive addresses.
+template <typename T> struct UVec;
+template <> struct UVec<float> { typedef f32x4 type; static constexpr int n = 4; };
+template <> struct UVec<double> { typedef f64x2 type; static constexpr int n = 2; };
+
+template <typename T> __host__ __device__ inline int upd_nkb(int w) { return (w + 4 * UVec<T>::n - 1) / (4 * UVec<T>::n); }
+
+template <typename T>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) update_frag_kernel(const UChunk *chunks, const int *obj_status, const int *width,
+                                                          T *S, T *HS, T *MS, int64_t ld, int m, int wmax,
+                                                          const T *C, const T *Cp, int write_p) {
+    typedef typename MfmaAcc<T>::type Acc;
+    typedef typename UVec<T>::type V;
+    constexpr int VK = UVec<T>::n, kGrp = sizeof(T) == 8 ? 2 : 4;
+    const UChunk ch = chunks[blockIdx.x];
+    if (obj_status[ch.obj] != 0) return;
+    const int w = width[ch.obj];
+    const int nkb = upd_nkb<T>(w), nct = (m + 15) >> 4;
+    extern __shared__ __align__(16) char smem[];
+    const T *Co = C + (size_t)ch.obj * wmax * m;
+    const T *Cpo = Cp + (size_t)ch.obj * wmax * m;
+    T *Cf = (T *)smem;
+    T *Cpf = Cf + (size_t)nkb * nct * 64 * VK;
+    for (int idx = threadIdx.x; idx < nkb * nct * 64 * VK; idx += 256) {
+        const int sv = idx % VK, l = (idx / VK) & 63, rest = idx / (64 * VK);
+        const int t = rest % nct, kb = rest / nct;
+        const int k = kb * 4 * VK + (l >> 4) * VK + sv, c = t * 16 + (l & 15);
+        const bool in = k < w && c < m;
+        Cf[idx] = in ? Co[(size_t)k * m + c] : (T)0;
+        Cpf[idx] = (in && write_p) ? Cpo[(size_t)k * m + c] : (T)0;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int64_t rend = ch.r0 + ch.len;
+    for (int64_t rt = ch.r0 + 16 * wv; rt < rend; rt += 64) {
+        const int64_t arow = rt + li;
+        const bool av = arow < rend;
+        for (int a = 0; a < 3; ++a) {
+            T *Arr = a == 0 ? S : (a == 1 ? HS : MS);
+            const T *rowp = Arr + arow * ld;
+            // groups of kGrp super-steps; the next group's loads are issued before this group's MFMAs
+            auto load_group = [&](int g0, V (&A)[kGrp]) {
+#pragma unroll
+                for (int u = 0; u < kGrp; ++u) {
+                    const int kb = g0 + u, k0 = kb * 4 * VK + lk * VK;
+                    V x = V{};
+                    if (kb < nkb) {
+                        if (av && k0 + VK <= w) {
+                            x = *(const V *)(rowp + k0);
+                        } else {
+#pragma unroll
+                            for (int q = 0; q < VK; ++q) x[q] = (av && k0 + q < w) ? rowp[k0 + q] : (T)0;
+                        }
+                    }
+                    A[u] = x;
+                }
+            };
+            Acc ax[4], ap[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                ax[t] = Acc{0, 0, 0, 0};
+                ap[t] = Acc{0, 0, 0, 0};
+            }
+            V cur[kGrp], nxt[kGrp];
+            load_group(0, cur);
+            for (int g0 = 0; g0 < nkb; g0 += kGrp) {
+                load_group(g0 + kGrp, nxt);
+#pragma unroll
+                for (int u = 0; u < kGrp; ++u) {
+                    const int kb = g0 + u;
+                    if (kb >= nkb) continue;
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        if (t >= nct) continue;
+                        const size_t f = ((size_t)(kb * nct + t) * 64 + lane) * VK;
+                        const V bx = *(const V *)(Cf + f);
+#pragma unroll
+                        for (int q = 0; q < VK; ++q) ax[t] = mfma(cur[u][q], bx[q], ax[t]);
+                        if (write_p) {
+                            const V bp = *(const V *)(Cpf + f);
+#pragma unroll
+                            for (int q = 0; q < VK; ++q) ap[t] = mfma(cur[u][q], bp[q], ap[t]);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < kGrp; ++u) cur[u] = nxt[u];
             }
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
@@ -1691,6 +1803,26 @@ int launch_spmm(ff_ctx *ctx, hipStream_t st, int variant, int64_t nrows, const i
     return FF_OK;
 }
 
+// HY = H Y alone (the preconditioner and the spectrum estimate): the row-tile
+// H-only kernel where the solver runs a row-tile variant, else the fused
+// product with MY written to the scratch block MS.
+inline int rt_spmm_h(ff_ctx *ctx, hipStream_t st, const rt::RTView &v, int sub, int m, const float *Y, int64_t ldy,
+                     float *HY, int64_t ldo, const int *row_obj, const int *status) {
+    return rt::spmm_h32(ctx, st, v, sub, m, Y, ldy, HY, ldo, row_obj, status);
+}
+inline int rt_spmm_h(ff_ctx *ctx, hipStream_t st, const rt::RTView &v, int sub, int m, const double *Y, int64_t ldy,
+                     double *HY, int64_t ldo, const int *row_obj, const int *status) {
+    return rt::spmm_h64(ctx, st, v, sub, m, Y, ldy, HY, ldo, row_obj, status);
+}
+template <typename T>
+int launch_spmm_h(ff_ctx *ctx, hipStream_t st, int variant, int64_t nrows, const int64_t *row_ptr, const int32_t *col,
+                  HMPair<T> hm, const T *Y, int64_t ldy, T *HY, T *MS, int64_t ldo, int m, const int *row_obj,
+                  const int *status, const rt::RTView *rtv) {
+    if (variant >= kRowTileBase && rtv && (sizeof(T) == 4 ? rtv->v32 != nullptr : rtv->v64 != nullptr))
+        return rt_spmm_h(ctx, st, *rtv, variant - kRowTileBase, m, Y, ldy, HY, ldo, row_obj, status);
+    return launch_spmm<T>(ctx, st, variant, nrows, row_ptr, col, hm, Y, ldy, HY, MS, ldo, m, row_obj, status, rtv);
+}
+
 template <typename T> struct Prec;
 template <> struct Prec<float> {
     typedef float CT;
@@ -1753,6 +1885,14 @@ template <typename T> inline int update_c_in_lds(int wmax, int m) {
 }
 template <typename T> inline size_t update_shmem(int wmax, int m) {
     return update_c_in_lds<T>(wmax, m) ? (size_t)2 * ((wmax + 3) & ~3) * ((m + 15) & ~15) * sizeof(T) : 0;
+}
+// the fragment-order kernel: 16-byte row loads need 16-byte aligned rows (ld = 3m), at most
+// four 16-column tiles (m <= 64), and its LDS copies within 128 KB
+template <typename T> inline size_t update_frag_shmem(int wmax, int m) {
+    return (size_t)2 * upd_nkb<T>(wmax) * 4 * UVec<T>::n * ((m + 15) & ~15) * sizeof(T);
+}
+template <typename T> inline int update_frag_ok(int wmax, int m) {
+    return (3 * (size_t)m * sizeof(T)) % 16 == 0 && m <= 64 && update_frag_shmem<T>(wmax, m) <= 128 * 1024;
 }
 
 int set_width(Solver &s, int w, int only_active) {
@@ -1828,6 +1968,13 @@ int stage_gram_rr(Solver &s, T *S, T *HS, T *MS, double tau) {
 
 template <typename T>
 int stage_update(Solver &s, T *S, T *HS, T *MS, int write_p) {
+    if (update_frag_ok<T>(s.wmax, s.m)) {
+        hipLaunchKernelGGL(update_frag_kernel<T>, dim3(s.nu), dim3(256), update_frag_shmem<T>(s.wmax, s.m), s.st,
+                           s.uch, s.status, s.width, S, HS, MS, (int64_t)3 * s.m, s.m, s.wmax,
+                           (const T *)cw_of<T>(s), (const T *)cpw_of<T>(s), write_p);
+        FF_CHECK_LAUNCH(s.ctx);
+        return FF_OK;
+    }
     hipLaunchKernelGGL(update_kernel<T>, dim3(s.nu), dim3(256), update_shmem<T>(s.wmax, s.m), s.st, s.uch, s.status,
                        s.width, S, HS, MS, (int64_t)3 * s.m, s.m, s.wmax, (const T *)cw_of<T>(s),
                        (const T *)cpw_of<T>(s), write_p, update_c_in_lds<T>(s.wmax, s.m));
@@ -1860,8 +2007,8 @@ int stage_precond(Solver &s, T *S) {
                        s.status, s.cheb_coef, S, Rb, DZ);
     FF_CHECK_LAUNCH(s.ctx);
     for (int step = 1; step < s.cheb; ++step) {
-        int rc = launch_spmm<T>(s.ctx, s.st, sizeof(T) == 4 ? s.var32 : s.var64, s.N, s.row_ptr, s.col, hm_of<T>(s),
-                                DZ, s.m, HD, MD, s.m, s.m, s.row_obj, s.status, &s.rtv);
+        int rc = launch_spmm_h<T>(s.ctx, s.st, sizeof(T) == 4 ? s.var32 : s.var64, s.N, s.row_ptr, s.col, hm_of<T>(s),
+                                  DZ, s.m, HD, MD, s.m, s.m, s.row_obj, s.status, &s.rtv);
         if (rc) return rc;
         hipLaunchKernelGGL(cheb_step_kernel<T>, dim3(grid_for(cnt, 256)), dim3(256), 0, s.st, s.N, s.m, ld, step,
                            s.row_obj, s.status, s.cheb_coef, dinv_of<T>(s), HD, S, Rb, DZ);
@@ -1917,15 +2064,15 @@ int cheb_setup(Solver &s, int degree, uint64_t seed) {
     FF_CHECK_LAUNCH(ctx);
     int rc;
     for (int it = 0; it < 30; ++it) {
-        if ((rc = launch_spmm<T>(ctx, s.st, var, N, s.row_ptr, s.col, hm_of<T>(s), Y, 8, HY, MY, 8, 8, s.row_obj,
-                                 s.status, &s.rtv)))
+        if ((rc = launch_spmm_h<T>(ctx, s.st, var, N, s.row_ptr, s.col, hm_of<T>(s), Y, 8, HY, MY, 8, 8, s.row_obj,
+                                   s.status, &s.rtv)))
             return rc;
         hipLaunchKernelGGL(power_step_kernel<T>, dim3(grid_for(N * 8, 256)), dim3(256), 0, s.st, N, s.row_obj, objv,
                            HY, dinv_of<T>(s), Y);
         FF_CHECK_LAUNCH(ctx);
     }
-    if ((rc = launch_spmm<T>(ctx, s.st, var, N, s.row_ptr, s.col, hm_of<T>(s), Y, 8, HY, MY, 8, 8, s.row_obj,
-                             s.status, &s.rtv)))
+    if ((rc = launch_spmm_h<T>(ctx, s.st, var, N, s.row_ptr, s.col, hm_of<T>(s), Y, 8, HY, MY, 8, 8, s.row_obj,
+                               s.status, &s.rtv)))
         return rc;
     double *HYd = (double *)s.cheb_md;            // MY is no longer needed
     hipLaunchKernelGGL(to_f64_kernel<T>, dim3(grid_for(N * 8, 256)), dim3(256), 0, s.st, N * 8, (const T *)Y, Yd);
@@ -2145,6 +2292,14 @@ int setup(Solver &s, const ff_eig_params *p) {
                                     (int)update_shmem<double>(wmax, m)));
     FF_HIP(ctx, hipFuncSetAttribute((const void *)update_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)update_shmem<float>(wmax, m)));
+    if (update_frag_ok<double>(wmax, m))
+        FF_HIP(ctx, hipFuncSetAttribute((const void *)update_frag_kernel<double>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)update_frag_shmem<double>(wmax, m)));
+    if (update_frag_ok<float>(wmax, m))
+        FF_HIP(ctx, hipFuncSetAttribute((const void *)update_frag_kernel<float>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)update_frag_shmem<float>(wmax, m)));
     int rc = gram_prepare(ctx);
     return rc ? rc : rr_prepare(ctx, wmax);
 }

@@ -37,6 +37,12 @@ int spmm32(ff_ctx *ctx, hipStream_t st, const RTView &v, int sub, int m, const f
            float *MY, int64_t ldo, const int *row_obj, const int *status);
 int spmm64(ff_ctx *ctx, hipStream_t st, const RTView &v, int sub, int m, const double *Y, int64_t ldy, double *HY,
            double *MY, int64_t ldo, const int *row_obj, const int *status);
+// HY = H Y alone, for the preconditioner: FP32 accumulation on the FP32 copy,
+// FP64 on the FP64 copy.
+int spmm_h32(ff_ctx *ctx, hipStream_t st, const RTView &v, int sub, int m, const float *Y, int64_t ldy, float *HY,
+             int64_t ldo, const int *row_obj, const int *status);
+int spmm_h64(ff_ctx *ctx, hipStream_t st, const RTView &v, int sub, int m, const double *Y, int64_t ldy, double *HY,
+             int64_t ldo, const int *row_obj, const int *status);
 
 }  // namespace rt
 }  // namespace ff

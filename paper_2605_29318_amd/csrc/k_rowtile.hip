@@ -100,29 +100,38 @@ template <typename T> struct Vec;
 template <> struct Vec<float> { typedef float4 type; static constexpr int n = 4; };
 template <> struct Vec<double> { typedef double2 type; static constexpr int n = 2; };
 
-// FP64 accumulators (a product of two FP32 numbers is exact in FP64)
-struct Acc4 { double v[4]; };
-__device__ inline void acc_fma(Acc4 &a, float h, const float4 &x) {
+// Accumulators: FP64 for the products of the eigensolver (a product of two FP32
+// numbers is exact in FP64), FP32 for the H-only products of the preconditioner.
+template <typename A> struct Acc4 { A v[4]; };
+__device__ inline void acc_fma(Acc4<double> &a, float h, const float4 &x) {
     const double d = (double)h;
     a.v[0] += d * (double)x.x;
     a.v[1] += d * (double)x.y;
     a.v[2] += d * (double)x.z;
     a.v[3] += d * (double)x.w;
 }
-__device__ inline void acc_fma(Acc4 &a, double h, const double2 &x) {
+__device__ inline void acc_fma(Acc4<float> &a, float h, const float4 &x) {
+    a.v[0] = fmaf(h, x.x, a.v[0]);
+    a.v[1] = fmaf(h, x.y, a.v[1]);
+    a.v[2] = fmaf(h, x.z, a.v[2]);
+    a.v[3] = fmaf(h, x.w, a.v[3]);
+}
+__device__ inline void acc_fma(Acc4<double> &a, double h, const double2 &x) {
     a.v[0] += h * x.x;
     a.v[1] += h * x.y;
 }
-__device__ inline void acc_store(float *p, const Acc4 &a) {
+template <typename A>
+__device__ inline void acc_store(float *p, const Acc4<A> &a) {
     *(float4 *)p = make_float4((float)a.v[0], (float)a.v[1], (float)a.v[2], (float)a.v[3]);
 }
-__device__ inline void acc_store(double *p, const Acc4 &a) { *(double2 *)p = make_double2(a.v[0], a.v[1]); }
+__device__ inline void acc_store(double *p, const Acc4<double> &a) { *(double2 *)p = make_double2(a.v[0], a.v[1]); }
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // Chunk of 64 union entries: column and the eight values of entry l in lane l.
-template <typename T> struct Chunk;
-template <> struct Chunk<float> {
+// With kHM false only the H values are loaded and staged (stride 4 in LDS).
+template <typename T, bool kHM> struct Chunk;
+template <bool kHM> struct Chunk<float, kHM> {
     int32_t j;
     f32x4 a, b;                                    // H rows 0..3, M rows 0..3
     __device__ void load(const int32_t *tcol, const float *tval, int64_t e, bool in) {
@@ -131,31 +140,36 @@ template <> struct Chunk<float> {
         if (in) {
             j = __builtin_nontemporal_load(tcol + e);
             a = __builtin_nontemporal_load((const f32x4 *)(tval + e * 8));
-            b = __builtin_nontemporal_load((const f32x4 *)(tval + e * 8 + 4));
+            if (kHM) b = __builtin_nontemporal_load((const f32x4 *)(tval + e * 8 + 4));
         }
     }
     __device__ void stage(float *sv, int lane) const {
-        *(f32x4 *)(sv + lane * 8) = a;
-        *(f32x4 *)(sv + lane * 8 + 4) = b;
+        if (kHM) {
+            *(f32x4 *)(sv + lane * 8) = a;
+            *(f32x4 *)(sv + lane * 8 + 4) = b;
+        } else {
+            *(f32x4 *)(sv + lane * 4) = a;
+        }
     }
 };
 typedef double f64x2 __attribute__((ext_vector_type(2)));
-template <> struct Chunk<double> {
+template <bool kHM> struct Chunk<double, kHM> {
+    static constexpr int NQ = kHM ? 4 : 2;
     int32_t j;
-    f64x2 v[4];
+    f64x2 v[NQ];
     __device__ void load(const int32_t *tcol, const double *tval, int64_t e, bool in) {
         j = 0;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) v[q] = f64x2{0.0, 0.0};
+        for (int q = 0; q < NQ; ++q) v[q] = f64x2{0.0, 0.0};
         if (in) {
             j = __builtin_nontemporal_load(tcol + e);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) v[q] = __builtin_nontemporal_load((const f64x2 *)(tval + e * 8 + 2 * q));
+            for (int q = 0; q < NQ; ++q) v[q] = __builtin_nontemporal_load((const f64x2 *)(tval + e * 8 + 2 * q));
         }
     }
     __device__ void stage(double *sv, int lane) const {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) *(f64x2 *)(sv + lane * 8 + 2 * q) = v[q];
+        for (int q = 0; q < NQ; ++q) *(f64x2 *)(sv + lane * 2 * NQ + 2 * q) = v[q];
     }
 };
 
@@ -166,14 +180,16 @@ template <> struct Chunk<double> {
 // group that needs it by a cross-lane shuffle. Lanes form groups of
 // G = m / VN; group g takes entries g, g + NG, ... of the chunk; each lane holds
 // VN columns of the gathered row of Y and accumulates all four rows of the tile
-// in FP64; the groups are summed at the end.
-template <typename T, int kWaves, int kBatch, int kOcc>
+// in FP64; the groups are summed at the end. With kHM false the kernel forms
+// H Y alone (MY is not touched), accumulating in A.
+template <typename T, typename A, bool kHM, int kWaves, int kBatch, int kOcc>
 __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(kOcc, 8)))
 spmm_rt_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int32_t *tcol, const T *tval, const T *Y,
                int64_t ldy, T *HY, T *MY, int64_t ldo, int m, const int *row_obj, const int *obj_status) {
     typedef typename Vec<T>::type V;
     constexpr int VN = Vec<T>::n;
-    __shared__ __align__(16) T svals[kWaves][64 * 8];
+    constexpr int NV = kHM ? 8 : 4;                // staged values per entry
+    __shared__ __align__(16) T svals[kWaves][64 * NV];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t t = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kWaves + wv;
     if (t >= ntiles) return;
@@ -193,12 +209,16 @@ spmm_rt_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int32_t
     const int steps = (64 + NG - 1) / NG;
     T *sv = svals[wv];
     const int64_t e0 = tptr[t], e1 = tptr[t + 1];
-    Acc4 aH[kTileRows], aM[kTileRows];
+    Acc4<A> aH[kTileRows], aM[kHM ? kTileRows : 1];
 #pragma unroll
     for (int i = 0; i < kTileRows; ++i)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) aH[i].v[q] = aM[i].v[q] = 0.0;
-    Chunk<T> nxt;
+        for (int q = 0; q < 4; ++q) aH[i].v[q] = 0;
+#pragma unroll
+    for (int i = 0; i < (kHM ? kTileRows : 1); ++i)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) aM[i].v[q] = 0;
+    Chunk<T, kHM> nxt;
     nxt.load(tcol, tval, e0 + lane, e0 + lane < e1);
     for (int64_t base = e0; base < e1; base += 64) {
         const int cnt = (int)(e1 - base < 64 ? e1 - base : 64);
@@ -224,11 +244,11 @@ spmm_rt_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int32_t
                 const int src = (s0 + u) * NG + g;
                 const bool ok = on && (s0 + u < steps) && src < cnt;
                 if (ok) {
-                    const T *vv = sv + src * 8;
+                    const T *vv = sv + src * NV;
 #pragma unroll
                     for (int i = 0; i < kTileRows; ++i) {
                         acc_fma(aH[i], vv[i], x[u]);
-                        acc_fma(aM[i], vv[4 + i], x[u]);
+                        if (kHM) acc_fma(aM[i], vv[4 + i], x[u]);
                     }
                 }
             }
@@ -241,22 +261,22 @@ spmm_rt_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int32_t
 #pragma unroll
                 for (int q = 0; q < VN; ++q) {
                     aH[i].v[q] += __shfl_xor(aH[i].v[q], d, 64);
-                    aM[i].v[q] += __shfl_xor(aM[i].v[q], d, 64);
+                    if (kHM) aM[i].v[q] += __shfl_xor(aM[i].v[q], d, 64);
                 }
     } else {
-        __shared__ double red[kWaves][2][4][64];
+        __shared__ A red[kWaves][2][4][64];
 #pragma unroll
         for (int i = 0; i < kTileRows; ++i) {
             for (int q = 0; q < VN; ++q) {
                 red[wv][0][q][lane] = aH[i].v[q];
-                red[wv][1][q][lane] = aM[i].v[q];
+                if (kHM) red[wv][1][q][lane] = aM[i].v[q];
             }
             __builtin_amdgcn_wave_barrier();
             if (g == 0)
                 for (int tt = 1; tt < NG; ++tt)
                     for (int q = 0; q < VN; ++q) {
                         aH[i].v[q] += red[wv][0][q][tt * G + c];
-                        aM[i].v[q] += red[wv][1][q][tt * G + c];
+                        if (kHM) aM[i].v[q] += red[wv][1][q][tt * G + c];
                     }
             __builtin_amdgcn_wave_barrier();
         }
@@ -266,18 +286,18 @@ spmm_rt_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int32_t
         for (int i = 0; i < kTileRows; ++i)
             if (act[i]) {
                 acc_store(HY + (r0 + i) * ldo + c * VN, aH[i]);
-                acc_store(MY + (r0 + i) * ldo + c * VN, aM[i]);
+                if (kHM) acc_store(MY + (r0 + i) * ldo + c * VN, aM[kHM ? i : 0]);
             }
     }
 }
 
-template <typename T>
+template <typename T, typename A = double, bool kHM = true>
 int launch(ff_ctx *ctx, hipStream_t st, const RTView &v, const T *tval, int sub, int m, const T *Y, int64_t ldy,
            T *HY, T *MY, int64_t ldo, const int *row_obj, const int *status) {
     // each lane holds one 16-byte access of the gathered row (narrower loads cost the texture unit as many cycles)
-#define FF_RT(W, B, O)                                                                                       \
-    hipLaunchKernelGGL((spmm_rt_kernel<T, W, B, O>), dim3(grid_for(v.ntiles, W)), dim3(64 * W), 0, st, v.n, \
-                       v.ntiles, v.tptr, v.tcol, tval, Y, ldy, HY, MY, ldo, m, row_obj, status)
+#define FF_RT(W, B, O)                                                                                      \
+    hipLaunchKernelGGL((spmm_rt_kernel<T, A, kHM, W, B, O>), dim3(grid_for(v.ntiles, W)), dim3(64 * W), 0, st, \
+                       v.n, v.ntiles, v.tptr, v.tcol, tval, Y, ldy, HY, MY, ldo, m, row_obj, status)
     switch (sub) {
         case 1: FF_RT(2, 8, 1); break;
         case 2: FF_RT(4, 4, 4); break;
@@ -297,6 +317,16 @@ int spmm64(ff_ctx *ctx, hipStream_t st, const RTView &v, int sub, int m, const d
            double *MY, int64_t ldo, const int *row_obj, const int *status) {
     FF_REQUIRE(ctx, v.v64 != nullptr, "row tiles have no FP64 values");
     return launch<double>(ctx, st, v, v.v64, sub, m, Y, ldy, HY, MY, ldo, row_obj, status);
+}
+int spmm_h32(ff_ctx *ctx, hipStream_t st, const RTView &v, int sub, int m, const float *Y, int64_t ldy, float *HY,
+             int64_t ldo, const int *row_obj, const int *status) {
+    FF_REQUIRE(ctx, v.v32 != nullptr, "row tiles have no FP32 values");
+    return launch<float, float, false>(ctx, st, v, v.v32, sub, m, Y, ldy, HY, nullptr, ldo, row_obj, status);
+}
+int spmm_h64(ff_ctx *ctx, hipStream_t st, const RTView &v, int sub, int m, const double *Y, int64_t ldy, double *HY,
+             int64_t ldo, const int *row_obj, const int *status) {
+    FF_REQUIRE(ctx, v.v64 != nullptr, "row tiles have no FP64 values");
+    return launch<double, double, false>(ctx, st, v, v.v64, sub, m, Y, ldy, HY, nullptr, ldo, row_obj, status);
 }
 
 // tile pointers and the number of union entries (host), in caller-provided memory
@@ -430,13 +460,18 @@ int rowtiles_info(const ff_rowtiles *rt, int64_t *ntiles, int64_t *entries) {
 int spmm_rowtiles(ff_ctx *ctx, const ff_rowtiles *rt, int precision, int m, const void *Y, int64_t ld_y, void *HY,
                   void *MY, int64_t ld_out, int sub) {
     if (!ctx || !rt) return FF_ERR_INVALID_ARG;
-    FF_REQUIRE(ctx, Y && HY && MY, "required pointer is NULL");
+    FF_REQUIRE(ctx, Y && HY, "required pointer is NULL");
     FF_REQUIRE(ctx, precision == 0 || precision == 1, "precision must be 0 or 1");
     const int vn = precision ? 4 : 2;
     FF_REQUIRE(ctx, m > 0 && m % vn == 0 && m / vn <= 64, "block width %d not supported", m);
     FF_REQUIRE(ctx, ld_y >= m && ld_out >= m && ld_y % vn == 0 && ld_out % vn == 0, "bad leading dimension");
     FF_REQUIRE(ctx, sub >= 0 && sub < rt::kSubs, "launch shape %d out of range", sub);
     FF_HIP(ctx, hipSetDevice(ctx->device));
+    if (!MY)
+        return precision ? rt::spmm_h32(ctx, ctx->stream, rt->v, sub, m, (const float *)Y, ld_y, (float *)HY, ld_out,
+                                        nullptr, nullptr)
+                         : rt::spmm_h64(ctx, ctx->stream, rt->v, sub, m, (const double *)Y, ld_y, (double *)HY,
+                                        ld_out, nullptr, nullptr);
     if (precision)
         return rt::spmm32(ctx, ctx->stream, rt->v, sub, m, (const float *)Y, ld_y, (float *)HY, (float *)MY, ld_out,
                           nullptr, nullptr);

@@ -337,16 +337,19 @@ class RowTiles:
         lib().rowtiles_info(self.h, ctypes.byref(nt), ctypes.byref(ne))
         return nt.value, ne.value
 
-    def spmm(self, Y, precision: int, sub: int = 0, out=None):
+    def spmm(self, Y, precision: int, sub: int = 0, out=None, h_only: bool = False):
+        """[HY, MY] = [H, M] Y; with h_only, (HY, None) from the preconditioner's product."""
         import torch
         n, m = Y.shape
         if out is None:
             HY = torch.empty_like(Y)
-            MY = torch.empty_like(Y)
+            MY = None if h_only else torch.empty_like(Y)
         else:
             HY, MY = out
-        self.ctx.check(lib().spmm_rowtiles(self.ctx.h, self.h, precision, m, _p(Y), Y.stride(0), _p(HY), _p(MY),
-                                           HY.stride(0), sub))
+            if h_only:
+                MY = None
+        self.ctx.check(lib().spmm_rowtiles(self.ctx.h, self.h, precision, m, _p(Y), Y.stride(0), _p(HY),
+                                           None if MY is None else _p(MY), HY.stride(0), sub))
         return HY, MY
 
     def close(self):

@@ -188,6 +188,13 @@ def test_rowtiles_spmm(oracle, ctx, ff, precision):
             HY, MY = rt.spmm(dev(Y, dt), precision, sub)
             assert np.all(np.abs(host(HY) - refH) <= eps * absH + 1e-300)
             assert np.all(np.abs(host(MY) - refM) <= eps * absM + 1e-300)
+            # H alone (the preconditioner's product): FP32 accumulation at precision 1, whose
+            # longest chain of roundings is a lane group's share of a tile (at most 4 rows / 8)
+            # plus the three cross-group additions and the rounding of the values and of Y
+            HO, none = rt.spmm(dev(Y, dt), precision, sub, h_only=True)
+            assert none is None
+            eps_h = (4 * rl.max() // 8 + 6) * 2.0 ** -24 if precision else 1e-13
+            assert np.all(np.abs(host(HO) - refH) <= eps_h * absH + 1e-300)
     rt.close()
 
 
