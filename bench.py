@@ -12,8 +12,10 @@ per-particle E log-uniform in [1e4, 1e6] Pa and nu uniform in [0.3, 0.48],
 support radius 2.5 x mean spacing, k = 32 (constant mode included).
 
 Also reported (same JSON line): the plain FP64 path on the same object, the
-fused SpMM's achieved HBM rate against the MI355X peak (HIP events on the
-solver's stream), and the FP64 CPU oracle timed on a bounded sample.
+per-stage device times of the timed solve (HIP events the library records on
+its stream), the achieved HBM rate of the dominant kernel (the Chebyshev step:
+H-only product fused with the preconditioner's vector update) against the
+MI355X peak, and the FP64 CPU oracle timed on a bounded sample.
 """
 from __future__ import annotations
 
@@ -28,6 +30,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "s to 32 eigenmodes @1M particles (resid≤1e-6), mixed vs FP64; SpMM GB/s"
 HBM_PEAK_GBS = 8000.0
+PRECOND = 2            # Chebyshev-Jacobi
+PRECOND_DEGREE = 0     # library default
 
 
 def log(*a):
@@ -43,14 +47,16 @@ def run_step(ff, ctx, dev_in, n, h, k, precision, tol, max_iter, use_graph=False
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ev, W, res, info = ff.eigenmodes(ctx, n, A.row_ptr, A.col, A.H, A.M, A.hm32, k=k, precision=precision,
-                                     tol=tol, max_iter=max_iter, use_graph=use_graph, allow_unconverged=True)
+                                     tol=tol, max_iter=max_iter, use_graph=use_graph, allow_unconverged=True,
+                                     precond=PRECOND, precond_degree=PRECOND_DEGREE)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     return dict(total=t2 - t0, build=t1 - t0, solve=t2 - t1, ev=ev, res=res, info=info, A=A, W=W)
 
 
 KERNEL_SRC = os.path.join(ROOT, "paper_2605_29318_amd", "csrc", "k_rowtile.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "spmm_rowtile_ellipsoids1m_k32_hbm_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cheb_step_ellipsoids1m_k32_hbm_traffic.txt")
+DOMINANT = "spmm_rt_h8_kernel<true"
 
 
 def kernel_source_hash():
@@ -58,49 +64,23 @@ def kernel_source_hash():
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
-def spmm_setup(ff, ctx, A, n, m):
-    """The eigensolver's FP32 SpMM as it runs in the iteration: the row-tile copy of
-    [H, M] and the launch shape the solver selects, on the W slice of an [n][3m] block."""
-    import torch
-    nnz = int(A.col.numel())
-    v = ff.spmm_variant_selected(ctx, n, nnz, m, 1)
-    names = ff.spmm_variant_names()
-    base = [i for i, nm in enumerate(names) if nm.startswith("rowtile")][0]
-    if v < base:
-        raise RuntimeError(f"selected SpMM variant {names[v]} is not a row-tile variant")
-    rt = ff.RowTiles(ctx, n, A.row_ptr, A.col, A.H, A.M, precision=1)
-    Y = torch.randn((n, 3 * m), dtype=torch.float32, device="cuda")
-    HY = torch.empty_like(Y)
-    MY = torch.empty_like(Y)
-    return rt, v - base, names[v], Y[:, m:2 * m], (HY[:, m:2 * m], MY[:, m:2 * m])
+def cheb_step_bytes(nnz, n, m):
+    """Algorithmic HBM bytes of one Chebyshev step launch (FP32, m columns), independent of
+    the storage format: the FP32 H value and int32 column of every nonzero, the row
+    pointers, D^-1 and the row's object index, the gathered block DZ read once, R read and
+    written, the next DZ written, W read and written."""
+    return nnz * 8 + 8 * (n + 1) + n * (4 + 4) + n * m * 4 * (1 + 2 + 1 + 2)
 
 
-def spmm_rate(ff, ctx, A, n, m, reps=20):
-    """Average duration of the FP32 fused SpMM launch (HIP events on the context's stream)."""
-    import torch
-    rt, sub, name, Yv, out = spmm_setup(ff, ctx, A, n, m)
-    stream = ctx.stream
-    rt.spmm(Yv, 1, sub, out=out)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(reps):
-        rt.spmm(Yv, 1, sub, out=out)
-    e1.record(stream)
-    e1.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    nnz = int(A.col.numel())
-    # algorithmic bytes of the product, independent of the storage format: FP32 H and M
-    # values and an int32 column per nonzero, the row pointers, Y read once, HY and MY written
-    alg_bytes = nnz * 12 + 8 * (n + 1) + 4 * n * m + 8 * n * m
-    ntiles, entries = rt.info()
-    rt.close()
-    return ms, alg_bytes, name, entries
+def spmm_hm_bytes(nnz, n, m):
+    """Algorithmic HBM bytes of one fused [H, M] Y launch (FP32): H, M values and a column
+    per nonzero, the row pointers, Y read once, HY and MY written."""
+    return nnz * 12 + 8 * (n + 1) + 4 * n * m + 8 * n * m
 
 
 def measured_traffic():
-    """HBM bytes per SpMM launch from the committed counter summary (FETCH_SIZE and
-    WRITE_SIZE passes, each scaled by the same counter on a copy of known size), or
+    """HBM bytes per Chebyshev step launch from the committed counter summary (FETCH_SIZE
+    and WRITE_SIZE passes, each scaled by the same counter on a copy of known size), or
     None when the summary is missing or was taken on another version of the kernel."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
@@ -117,9 +97,10 @@ def measured_traffic():
         return None
 
 
-def spmm_only(args):
-    """Counter-collection helper: the SpMM launches of the benchmark workload and an
-    elementwise kernel that reads and writes 1 GiB (the counters' calibration)."""
+def counters_run(args):
+    """Counter-collection helper: a short solve of the benchmark workload (its Chebyshev
+    step and SpMM launches) and an elementwise kernel that reads and writes 1 GiB (the
+    counters' calibration)."""
     import numpy as np
     import torch
     from paper_2605_29318_amd import freeform as ff
@@ -128,17 +109,14 @@ def spmm_only(args):
     dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), device="cuda")
     ctx = ff.Context(0)
     A = ff.assemble_cloud(ctx, dev(c.xyz), dev(c.vol), dev(c.lam), dev(c.mu), c.h)
-    m = args.k if args.k % 8 == 0 else ((args.k + 7) // 8) * 8
-    rt, sub, name, Yv, out = spmm_setup(ff, ctx, A, c.n, m)
-    for _ in range(args.steps):
-        rt.spmm(Yv, 1, sub, out=out)
+    ff.eigenmodes(ctx, c.n, A.row_ptr, A.col, A.H, A.M, A.hm32, k=args.k, precision=1, tol=args.tol,
+                  max_iter=args.steps, allow_unconverged=True, precond=PRECOND, precond_degree=PRECOND_DEGREE)
     src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")     # 1 GiB
     dst = torch.empty_like(src)
     for _ in range(3):
         torch.mul(src, 1.0, out=dst)
     torch.cuda.synchronize()
-    log(f"[bench] spmm-only: {args.steps} launches of {name}, 3 calibration passes over 1 GiB")
-    rt.close()
+    log(f"[bench] counters: {args.steps} solver iterations, 3 calibration passes over 1 GiB")
     ctx.close()
 
 
@@ -164,8 +142,10 @@ def cpu_baseline(n_sample, k, iters, gpu_iters, n_full):
     est = build * scale + per_iter * scale * gpu_iters
     return dict(value=round(est, 2), unit="s", cores=os.cpu_count(), kind="oracle",
                 sample=(f"oracle binning+neighbours+RKPM+assembly on {n_sample} particles of the same recipe "
-                        f"({build:.2f} s) and {iters} FP64 LOBPCG iterations ({per_iter*1e3:.1f} ms/iter), "
-                        f"scaled linearly to {n_full} particles and {gpu_iters} iterations"),
+                        f"({build:.2f} s) and {iters} FP64 Jacobi-preconditioned LOBPCG iterations "
+                        f"({per_iter*1e3:.1f} ms/iter), scaled linearly to {n_full} particles and the GPU's "
+                        f"{gpu_iters} iterations (a lower bound: each GPU iteration also applies the "
+                        f"Chebyshev polynomial, the oracle's applies diag(H)^-1)"),
                 measured_s=round(t3 - t0, 2))
 
 
@@ -181,15 +161,15 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--graph", action="store_true")
-    ap.add_argument("--spmm-only", action="store_true",
-                    help="run only the SpMM launches and a 1 GiB calibration kernel (for counter passes)")
+    ap.add_argument("--counters", action="store_true",
+                    help="run a short solve (--steps iterations) and a 1 GiB calibration kernel (for counter passes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1).", file=sys.stderr)
         sys.exit(2)
-    if args.spmm_only:
-        spmm_only(args)
+    if args.counters:
+        counters_run(args)
         return
 
     import numpy as np
@@ -211,6 +191,7 @@ def main():
     torch.cuda.synchronize()
     times = []
     last = None
+    ctx.set_stage_timing(True)
     t_start = time.perf_counter()
     for s in range(args.steps):
         last = run_step(ff, ctx, dev_in, c.n, c.h, args.k, 1, args.tol, args.max_iter, args.graph)
@@ -219,6 +200,8 @@ def main():
             f"iters {last['info']['iters_fp32']}+{last['info']['iters_fp64']}, max resid {last['res'].max():.2e}")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
+    stages = ctx.stage_times()          # of the last timed solve
+    ctx.set_stage_timing(False)
     ms_per_step = 1e3 * wall / args.steps
     A = last["A"]
     nnz = int(A.col.numel())
@@ -233,11 +216,19 @@ def main():
         log(f"[bench] fp64 step: {r64['total']:.3f} s, iters {r64['info']['iters_fp64']}")
 
     m = args.k if args.k % 8 == 0 else ((args.k + 7) // 8) * 8
-    spmm_ms, alg_bytes, variant, entries = spmm_rate(ff, ctx, A, c.n, m)
-    achieved = alg_bytes / (spmm_ms * 1e-3) / 1e9
+    cheb_ms, cheb_n = stages["precond_product"]
+    spmm_ms, spmm_n = stages["spmm"]
+    cheb_avg = cheb_ms / max(cheb_n, 1)
+    spmm_avg = spmm_ms / max(spmm_n, 1)
+    cheb_alg = cheb_step_bytes(nnz, c.n, m)
+    spmm_alg = spmm_hm_bytes(nnz, c.n, m)
+    achieved = cheb_alg / (cheb_avg * 1e-3) / 1e9
+    spmm_gbps = spmm_alg / (spmm_avg * 1e-3) / 1e9
     traffic = measured_traffic()
-    log(f"[bench] spmm fp32 ({variant}): {spmm_ms:.3f} ms, {achieved:.0f} GB/s algorithmic, "
-        f"{entries} row-tile entries for {nnz} nonzeros")
+    log(f"[bench] stage times of the last solve (ms, launches): "
+        + ", ".join(f"{k} {v[0]:.1f}/{v[1]}" for k, v in stages.items()))
+    log(f"[bench] chebyshev step: {cheb_avg:.3f} ms/launch, {achieved:.0f} GB/s algorithmic; "
+        f"fused [H,M] spmm: {spmm_avg:.3f} ms/launch, {spmm_gbps:.0f} GB/s")
 
     cpu = None
     if not args.no_cpu:
@@ -261,7 +252,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "ellipsoids1m_hetero", "particles": c.n, "k": args.k, "tol": args.tol,
                    "nnz": nnz, "nnz_per_row": round(nnz / c.n, 1), "h": round(c.h, 6),
-                   "precond": "jacobi", "graph": bool(args.graph)},
+                   "precond": "chebyshev-jacobi", "precond_degree": PRECOND_DEGREE or 4,
+                   "graph": bool(args.graph)},
         "build_s": round(last["build"], 4),
         "solve_s": round(last["solve"], 4),
         "iters": {"fp32": info["iters_fp32"], "fp64": info["iters_fp64"]},
@@ -269,11 +261,17 @@ def main():
         "converged": bool(info["converged"]),
         "fp64": fp64,
         "speedup_vs_fp64": (round(fp64["seconds"] / (ms_per_step / 1e3), 3) if fp64 else None),
-        "spmm_gbps": round(achieved, 1),
+        "spmm_gbps": round(spmm_gbps, 1),
+        "stages_ms": {k: round(v[0], 2) for k, v in stages.items()},
+        "stage_launches": {k: int(v[1]) for k, v in stages.items()},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "spmm_rt_kernel (fused [H,M] Y on the row-tile copy, FP32, m=%d, %s)" % (m, variant),
-                     "bytes_per_launch": alg_bytes, "launch_ms": round(spmm_ms, 4)},
+                     "kernel": "spmm_rt_h8_kernel<true> (Chebyshev step: H-only product on the row-tile copy "
+                               "fused with the step's vector update, FP32, m=%d)" % m,
+                     "bytes_per_launch": cheb_alg, "launch_ms": round(cheb_avg, 4),
+                     "share_of_solve": round(cheb_ms / max(stages["total"][0], 1e-9), 3)},
+        "spmm_hm": {"achieved": round(spmm_gbps, 1), "unit": "GB/s", "bytes_per_launch": spmm_alg,
+                    "launch_ms": round(spmm_avg, 4)},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -53,9 +53,30 @@ typedef enum {
 int ff_ctx_create(ff_ctx **ctx, int device, void *hip_stream);
 void ff_ctx_destroy(ff_ctx *ctx);
 const char *ff_last_error(const ff_ctx *ctx);
-/* Elapsed device time of named stages of the last eigenmodes call, in ms (host out). */
-int ff_ctx_stage_times(const ff_ctx *ctx, double *spmm_ms, double *gram_ms, double *rr_ms,
-                       double *update_ms, double *total_ms);
+/*
+ * Per-stage device time of eigenmodes / eigenmodes_batched. With timing on
+ * (ff_ctx_set_stage_timing(ctx, 1); off by default), the solver brackets each
+ * stage of every iteration with HIP events on its stream (not inside a
+ * captured hipGraph: with use_graph only FF_STAGE_TOTAL is filled) and sums
+ * their elapsed times when the call ends. ff_ctx_stage_times copies the last
+ * call's sums: ms[s] (milliseconds) and launches[s] (kernel launches of the
+ * stage's main kernel, for per-launch averages), s < min(n, FF_STAGE_COUNT);
+ * either array may be NULL. Returns FF_STAGE_COUNT.
+ */
+typedef enum {
+    FF_STAGE_SPMM = 0,         /* fused [H, M] products of the iteration and of the refreshes */
+    FF_STAGE_PRECOND_PRODUCT,  /* Chebyshev steps: H-only products fused with the step's update */
+    FF_STAGE_PRECOND_OTHER,    /* Chebyshev start (copy of D^-1 r, first term) */
+    FF_STAGE_GRAM,             /* Gram products and their reduction */
+    FF_STAGE_RR,               /* Rayleigh-Ritz */
+    FF_STAGE_UPDATE,           /* block update */
+    FF_STAGE_RESID,            /* residual block, norms, convergence flags */
+    FF_STAGE_TOTAL,            /* the whole call, host clock */
+    FF_STAGE_COUNT
+} ff_stage;
+int ff_ctx_set_stage_timing(ff_ctx *ctx, int enable);
+int ff_ctx_stage_times(const ff_ctx *ctx, int n, double *ms, int64_t *launches);
+const char *ff_stage_name(int stage);
 
 /* Uniform cell grid of edge h over the node bounding box. */
 typedef struct {
@@ -169,7 +190,8 @@ typedef struct {
     int use_graph;      /* 1 = replay one captured hipGraph per iteration (a call on the null
                            stream runs on a private stream of the context) */
     int refresh_every;  /* recompute HX, MX explicitly every this many iterations (0 = auto) */
-    int precond_degree; /* Chebyshev degree d for precond = 2 (0 = 4; 2..8); d - 1 products with H per iteration */
+    int precond_degree; /* Chebyshev degree d for precond = 2 (0 = default 4; 2..16); d - 1 products with H per
+                           iteration */
 } ff_eig_params;
 
 typedef struct {
@@ -275,13 +297,17 @@ int rayleigh_ritz(ff_ctx *ctx, int w, int m, const double *G, double tau, double
  *
  * rowtiles_build: from the FP64 CSR of assemble_HM (rows with ascending
  *   columns); precision 1 keeps FP32 values (rounded from H, M), 0 FP64, 2
- *   both. Device memory owned by the handle until rowtiles_destroy (destroy it
+ *   both; 3 keeps only H, in FP32, in tiles of eight rows (the copy the
+ *   Chebyshev-Jacobi preconditioner of eigenmodes runs on; M may be NULL).
+ *   Device memory owned by the handle until rowtiles_destroy (destroy it
  *   before its context). The CSR may be freed afterwards.
  * spmm_rowtiles: [HY, MY] = [H, M] Y as spmm_hm, on the copy; sub selects a
  *   launch shape (0 .. 2). With MY NULL only HY = H Y is formed, the product
  *   the Chebyshev-Jacobi preconditioner of eigenmodes runs: at precision 1 it
  *   accumulates in FP32 (an approximate operator is all a preconditioner
- *   needs), at precision 0 in FP64.
+ *   needs), at precision 0 in FP64. A handle built with precision 3 takes
+ *   only this form, at precision 1, with m % 8 == 0, 8 <= m <= 64 and leading
+ *   dimensions that are multiples of 4.
  */
 typedef struct ff_rowtiles ff_rowtiles;
 int rowtiles_build(ff_ctx *ctx, int64_t n, const int64_t *row_ptr, const int32_t *col, const double *H,

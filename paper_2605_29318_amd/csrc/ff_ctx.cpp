@@ -60,6 +60,52 @@ void *pinned_get(ff_ctx *ctx, size_t bytes) {
     return p;
 }
 
+void timing_reset(ff_ctx *ctx) {
+    ctx->ev_used = 0;
+    ctx->marks.clear();
+    for (int i = 0; i < FF_STAGE_COUNT; ++i) {
+        ctx->stage_ms[i] = 0.0;
+        ctx->stage_launches[i] = 0;
+    }
+}
+
+int timing_event(ff_ctx *ctx, hipStream_t st) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
+        (void)hipGetLastError();
+        return -1;
+    }
+    if (ctx->ev_used == ctx->ev_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) {
+            (void)hipGetLastError();
+            return -1;
+        }
+        ctx->ev_pool.push_back(e);
+    }
+    const int idx = (int)ctx->ev_used;
+    if (hipEventRecord(ctx->ev_pool[idx], st) != hipSuccess) {
+        (void)hipGetLastError();
+        return -1;
+    }
+    ++ctx->ev_used;
+    return idx;
+}
+
+void timing_collect(ff_ctx *ctx) {
+    for (const auto &mk : ctx->marks) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, ctx->ev_pool[mk[2]], ctx->ev_pool[mk[3]]) != hipSuccess) {
+            (void)hipGetLastError();
+            continue;
+        }
+        ctx->stage_ms[mk[0]] += ms;
+        ctx->stage_launches[mk[0]] += mk[1];
+    }
+    ctx->marks.clear();
+    ctx->ev_used = 0;
+}
+
 }  // namespace ff
 
 extern "C" {
@@ -91,6 +137,7 @@ void ff_ctx_destroy(ff_ctx *ctx) {
         if (ctx->ws[i]) (void)hipFree(ctx->ws[i]);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     if (ctx->graph_stream) (void)hipStreamDestroy(ctx->graph_stream);
+    for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     delete ctx;
 }
 
@@ -98,15 +145,25 @@ const char *ff_last_error(const ff_ctx *ctx) {
     return ctx ? ctx->last_error.c_str() : "null context";
 }
 
-int ff_ctx_stage_times(const ff_ctx *ctx, double *spmm_ms, double *gram_ms, double *rr_ms,
-                       double *update_ms, double *total_ms) {
+int ff_ctx_set_stage_timing(ff_ctx *ctx, int enable) {
     if (!ctx) return FF_ERR_INVALID_ARG;
-    if (spmm_ms) *spmm_ms = ctx->stage_ms[0];
-    if (gram_ms) *gram_ms = ctx->stage_ms[1];
-    if (rr_ms) *rr_ms = ctx->stage_ms[2];
-    if (update_ms) *update_ms = ctx->stage_ms[3];
-    if (total_ms) *total_ms = ctx->stage_ms[4];
+    ctx->timing = enable != 0;
     return FF_OK;
+}
+
+int ff_ctx_stage_times(const ff_ctx *ctx, int n, double *ms, int64_t *launches) {
+    if (!ctx || n < 0) return FF_ERR_INVALID_ARG;
+    for (int i = 0; i < n && i < FF_STAGE_COUNT; ++i) {
+        if (ms) ms[i] = ctx->stage_ms[i];
+        if (launches) launches[i] = ctx->stage_launches[i];
+    }
+    return FF_STAGE_COUNT;
+}
+
+const char *ff_stage_name(int stage) {
+    static const char *names[FF_STAGE_COUNT] = {"spmm", "precond_product", "precond_other", "gram",
+                                                "rayleigh_ritz", "update", "resid", "total"};
+    return stage >= 0 && stage < FF_STAGE_COUNT ? names[stage] : "";
 }
 
 }  // extern "C"

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdint>
@@ -28,6 +29,7 @@ enum WsSlot {
     WS_MLP0, WS_MLP1, WS_MLP2, WS_MLP3, WS_MLP4, WS_MLP5, WS_MLP6, WS_MLP7,
     WS_RT_CNT, WS_RT_PTR, WS_RT_COL, WS_RT_VAL32, WS_RT_VAL64,   // row-tile SpMM copies
     WS_CHEB0, WS_CHEB1, WS_CHEB2, WS_CHEB3, WS_CHEB4,             // Chebyshev-Jacobi work
+    WS_RT8_CNT, WS_RT8_PTR, WS_RT8_COL, WS_RT8_VAL,               // eight-row H-only tile copy
     WS_COUNT
 };
 
@@ -42,7 +44,12 @@ struct ff_ctx {
     void *pinned = nullptr;          // small pinned host staging area
     size_t pinned_size = 0;
     std::unordered_map<std::string, int> tuned;   // SpMM shape key -> variant
-    double stage_ms[5] = {0, 0, 0, 0, 0};
+    int timing = 0;                               // per-stage HIP-event timing of the solver
+    std::vector<hipEvent_t> ev_pool;              // reusable timing events
+    size_t ev_used = 0;
+    std::vector<std::array<int, 4>> marks;        // stage, launches, start event, end event
+    double stage_ms[FF_STAGE_COUNT] = {};
+    int64_t stage_launches[FF_STAGE_COUNT] = {};
     int verbose = 0;                 // FF_VERBOSE=1: residual trace on stderr
     hipStream_t graph_stream = nullptr;   // private stream for graph capture
 };
@@ -50,6 +57,31 @@ struct ff_ctx {
 namespace ff {
 
 int set_error(ff_ctx *ctx, int code, const char *fmt, ...);
+
+// Stage timing: timing_reset at the start of a solve, StageMark around each
+// stage (records a start and an end event on the stream when timing is on and
+// the stream is not being captured), timing_collect after the final
+// synchronisation (sums the marks' elapsed times into stage_ms).
+void timing_reset(ff_ctx *ctx);
+void timing_collect(ff_ctx *ctx);
+int timing_event(ff_ctx *ctx, hipStream_t st);
+struct StageMark {
+    ff_ctx *ctx;
+    hipStream_t st;
+    int stage, launches, e0 = -1;
+    StageMark(ff_ctx *c, hipStream_t s, int stg, int n = 1) : ctx(c), st(s), stage(stg), launches(n) {
+        if (ctx->timing) e0 = timing_event(ctx, st);
+    }
+    void end() {
+        if (e0 < 0) return;
+        const int e1 = timing_event(ctx, st);
+        if (e1 >= 0) ctx->marks.push_back({stage, launches, e0, e1});
+        e0 = -1;
+    }
+    ~StageMark() { end(); }
+    StageMark(const StageMark &) = delete;
+    StageMark &operator=(const StageMark &) = delete;
+};
 
 // Grow-only device buffer for a workspace slot; returns nullptr on failure
 // (and records FF_ERR_OOM in the context).

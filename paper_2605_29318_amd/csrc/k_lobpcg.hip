@@ -1612,7 +1612,8 @@ __global__ void diag_inv_bs_kernel(int64_t n, const int64_t *row_ptr, const int3
 // (2 rho_s / delta), theta = (a + b) / 2, delta = (b - a) / 2.
 // ---------------------------------------------------------------------------
 
-constexpr int kChebCoef = 16;                  // per-object coefficient stride (degree <= 8)
+constexpr int kChebCoef = 32;                  // per-object coefficient stride (degree <= 16)
+constexpr int kChebDefault = 4;                // degree when the caller passes 0
 
 // Gershgorin bound of D^-1/2 H D^-1/2 per row: sum_j |H_ij| / sqrt(H_ii H_jj), one wavefront per row
 __global__ void gersh_row_kernel(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *H,
@@ -1814,6 +1815,14 @@ inline int rt_spmm_h(ff_ctx *ctx, hipStream_t st, const rt::RTView &v, int sub, 
                      double *HY, int64_t ldo, const int *row_obj, const int *status) {
     return rt::spmm_h64(ctx, st, v, sub, m, Y, ldy, HY, ldo, row_obj, status);
 }
+inline int rt_cheb_step(ff_ctx *ctx, hipStream_t st, const rt::RTView &v, int sub, int m, const float *DZ, int64_t ld,
+                        const int *row_obj, const int *status, const rt::ChebStep<float> &cs) {
+    return rt::cheb_step32(ctx, st, v, sub, m, DZ, ld, row_obj, status, cs);
+}
+inline int rt_cheb_step(ff_ctx *ctx, hipStream_t st, const rt::RTView &v, int sub, int m, const double *DZ, int64_t ld,
+                        const int *row_obj, const int *status, const rt::ChebStep<double> &cs) {
+    return rt::cheb_step64(ctx, st, v, sub, m, DZ, ld, row_obj, status, cs);
+}
 template <typename T>
 int launch_spmm_h(ff_ctx *ctx, hipStream_t st, int variant, int64_t nrows, const int64_t *row_ptr, const int32_t *col,
                   HMPair<T> hm, const T *Y, int64_t ldy, T *HY, T *MS, int64_t ldo, int m, const int *row_obj,
@@ -1846,6 +1855,7 @@ struct Solver {
     int m = 0, k = 0, wmax = 0;
     int var32 = 0, var64 = 0;
     rt::RTView rtv;                                // row-tile copy when a row-tile variant is selected
+    rt::RT8View rt8;                               // eight-row H-only copy for the FP32 preconditioner
     bool jacobi = false;
     int cheb = 0;                                  // Chebyshev-Jacobi degree (0: plain Jacobi or none)
     double *cheb_coef = nullptr;                   // [n_obj][kChebCoef]
@@ -1904,6 +1914,7 @@ int set_width(Solver &s, int w, int only_active) {
 
 template <typename T>
 int stage_spmm(Solver &s, T *S, T *HS, T *MS, int slot) {
+    StageMark mark(s.ctx, s.st, FF_STAGE_SPMM);
     const int64_t ld = 3 * (int64_t)s.m;
     return launch_spmm<T>(s.ctx, s.st, sizeof(T) == 4 ? s.var32 : s.var64, s.N, s.row_ptr, s.col, hm_of<T>(s),
                           S + slot * s.m, ld, HS + slot * s.m, MS + slot * s.m, ld, s.m, s.row_obj, s.status,
@@ -1954,6 +1965,7 @@ int rr_prepare(ff_ctx *ctx, int wmax) {
 
 template <typename T>
 int stage_gram_rr(Solver &s, T *S, T *HS, T *MS, double tau) {
+    StageMark mark(s.ctx, s.st, FF_STAGE_GRAM);
     const int T16 = (s.wmax + 15) / 16, nsup = (T16 + 5) / 6;
     hipLaunchKernelGGL((gram_kernel<T, T>), dim3(s.ng, nsup * nsup), dim3(512), gram_shmem_bytes<T>(), s.st, s.gch,
                        s.status, s.width, S, HS, MS, (int64_t)3 * s.m, s.wmax, s.gpart, 1);
@@ -1962,12 +1974,15 @@ int stage_gram_rr(Solver &s, T *S, T *HS, T *MS, double tau) {
     hipLaunchKernelGGL(gram_reduce_kernel, dim3(grid_for(per2, 256), s.n_obj), dim3(256), 0, s.st, s.status, s.width,
                        s.gfirst, s.gcount, s.gpart, s.wmax, s.G);
     FF_CHECK_LAUNCH(s.ctx);
+    mark.end();
+    StageMark rr_mark(s.ctx, s.st, FF_STAGE_RR);
     return launch_rr<typename Prec<T>::CT>(s.ctx, s.st, s.n_obj, s.status, s.width, s.G, s.wmax, s.m, tau, s.rrscr,
                                            s.C, cw_of<T>(s), s.Cp, cpw_of<T>(s), s.theta, s.info);
 }
 
 template <typename T>
 int stage_update(Solver &s, T *S, T *HS, T *MS, int write_p) {
+    StageMark mark(s.ctx, s.st, FF_STAGE_UPDATE);
     if (update_frag_ok<T>(s.wmax, s.m)) {
         hipLaunchKernelGGL(update_frag_kernel<T>, dim3(s.nu), dim3(256), update_frag_shmem<T>(s.wmax, s.m), s.st,
                            s.uch, s.status, s.width, S, HS, MS, (int64_t)3 * s.m, s.m, s.wmax,
@@ -1984,6 +1999,7 @@ int stage_update(Solver &s, T *S, T *HS, T *MS, int write_p) {
 
 template <typename T>
 int stage_resid(Solver &s, T *S, T *HS, T *MS, double tol, int stall) {
+    StageMark mark(s.ctx, s.st, FF_STAGE_RESID);
     hipLaunchKernelGGL(resid_kernel<T>, dim3(s.ng), dim3(256), 0, s.st, s.gch, s.status, S, (const T *)HS,
                        (const T *)MS, (int64_t)3 * s.m, s.m, s.theta, s.jacobi ? dinv_of<T>(s) : (const T *)nullptr,
                        s.rpart);
@@ -2003,11 +2019,53 @@ int stage_precond(Solver &s, T *S) {
     const int64_t cnt = s.N * s.m;
     const int64_t ld = 3 * (int64_t)s.m;
     T *Rb = (T *)s.cheb_r, *DZ = (T *)s.cheb_dz, *HD = (T *)s.cheb_hd, *MD = (T *)s.cheb_md;
-    hipLaunchKernelGGL(cheb_init_kernel<T>, dim3(grid_for(cnt, 256)), dim3(256), 0, s.st, s.N, s.m, ld, s.row_obj,
-                       s.status, s.cheb_coef, S, Rb, DZ);
-    FF_CHECK_LAUNCH(s.ctx);
+    {
+        StageMark mark(s.ctx, s.st, FF_STAGE_PRECOND_OTHER);
+        hipLaunchKernelGGL(cheb_init_kernel<T>, dim3(grid_for(cnt, 256)), dim3(256), 0, s.st, s.N, s.m, ld,
+                           s.row_obj, s.status, s.cheb_coef, S, Rb, DZ);
+        FF_CHECK_LAUNCH(s.ctx);
+    }
+    StageMark mark(s.ctx, s.st, FF_STAGE_PRECOND_PRODUCT, s.cheb - 1);
+    const int var = sizeof(T) == 4 ? s.var32 : s.var64;
+    if (sizeof(T) == 4 && s.rt8.vh) {
+        T *buf[2] = {DZ, HD};
+        for (int step = 1; step < s.cheb; ++step) {
+            rt::ChebStep<float> cs;
+            cs.coef = s.cheb_coef;
+            cs.stride = kChebCoef;
+            cs.step = step;
+            cs.dinv = (const float *)dinv_of<T>(s);
+            cs.R = (float *)Rb;
+            cs.dz_out = (float *)buf[step & 1];
+            cs.W = (float *)(S + s.m);
+            cs.ldw = ld;
+            const int rc = rt::cheb_step_t8(s.ctx, s.st, s.rt8, 0, s.m, (const float *)buf[(step - 1) & 1], s.m,
+                                            s.row_obj, s.status, cs);
+            if (rc) return rc;
+        }
+        return FF_OK;
+    }
+    if (var >= kRowTileBase && (sizeof(T) == 4 ? s.rtv.v32 != nullptr : s.rtv.v64 != nullptr)) {
+        // fused: each step's product writes the next DZ into the other buffer
+        T *buf[2] = {DZ, HD};
+        for (int step = 1; step < s.cheb; ++step) {
+            rt::ChebStep<T> cs;
+            cs.coef = s.cheb_coef;
+            cs.stride = kChebCoef;
+            cs.step = step;
+            cs.dinv = dinv_of<T>(s);
+            cs.R = Rb;
+            cs.dz_out = buf[step & 1];
+            cs.W = S + s.m;
+            cs.ldw = ld;
+            const int rc = rt_cheb_step(s.ctx, s.st, s.rtv, var - kRowTileBase, s.m, buf[(step - 1) & 1], s.m,
+                                        s.row_obj, s.status, cs);
+            if (rc) return rc;
+        }
+        return FF_OK;
+    }
     for (int step = 1; step < s.cheb; ++step) {
-        int rc = launch_spmm_h<T>(s.ctx, s.st, sizeof(T) == 4 ? s.var32 : s.var64, s.N, s.row_ptr, s.col, hm_of<T>(s),
+        int rc = launch_spmm_h<T>(s.ctx, s.st, var, s.N, s.row_ptr, s.col, hm_of<T>(s),
                                   DZ, s.m, HD, MD, s.m, s.m, s.row_obj, s.status, &s.rtv);
         if (rc) return rc;
         hipLaunchKernelGGL(cheb_step_kernel<T>, dim3(grid_for(cnt, 256)), dim3(256), 0, s.st, s.N, s.m, ld, step,
@@ -2063,17 +2121,19 @@ int cheb_setup(Solver &s, int degree, uint64_t seed) {
     hipLaunchKernelGGL(from_f64_kernel<T>, dim3(grid_for(N * 8, 256)), dim3(256), 0, s.st, N * 8, (const double *)Yd, Y);
     FF_CHECK_LAUNCH(ctx);
     int rc;
+    auto hprod = [&]() -> int {
+        if (sizeof(T) == 4 && s.rt8.vh)
+            return rt::spmm_h_t8(ctx, s.st, s.rt8, 0, 8, (const float *)Y, 8, (float *)HY, 8, s.row_obj, s.status);
+        return launch_spmm_h<T>(ctx, s.st, var, N, s.row_ptr, s.col, hm_of<T>(s), Y, 8, HY, MY, 8, 8, s.row_obj,
+                                s.status, &s.rtv);
+    };
     for (int it = 0; it < 30; ++it) {
-        if ((rc = launch_spmm_h<T>(ctx, s.st, var, N, s.row_ptr, s.col, hm_of<T>(s), Y, 8, HY, MY, 8, 8, s.row_obj,
-                                   s.status, &s.rtv)))
-            return rc;
+        if ((rc = hprod())) return rc;
         hipLaunchKernelGGL(power_step_kernel<T>, dim3(grid_for(N * 8, 256)), dim3(256), 0, s.st, N, s.row_obj, objv,
                            HY, dinv_of<T>(s), Y);
         FF_CHECK_LAUNCH(ctx);
     }
-    if ((rc = launch_spmm_h<T>(ctx, s.st, var, N, s.row_ptr, s.col, hm_of<T>(s), Y, 8, HY, MY, 8, 8, s.row_obj,
-                               s.status, &s.rtv)))
-        return rc;
+    if ((rc = hprod())) return rc;
     double *HYd = (double *)s.cheb_md;            // MY is no longer needed
     hipLaunchKernelGGL(to_f64_kernel<T>, dim3(grid_for(N * 8, 256)), dim3(256), 0, s.st, N * 8, (const T *)Y, Yd);
     hipLaunchKernelGGL(to_f64_kernel<T>, dim3(grid_for(N * 8, 256)), dim3(256), 0, s.st, N * 8, (const T *)HY, HYd);
@@ -2320,6 +2380,7 @@ int solve(ff_ctx *ctx, int n_obj, const int64_t *obj_off, const int64_t *row_ptr
           const double *M, const float *hm32, const ff_eig_params *p, const double *X0, double *eigval, double *W,
           double *resid, ff_eig_info *info) {
     auto t_start = std::chrono::steady_clock::now();
+    timing_reset(ctx);
     FF_REQUIRE(ctx, p != nullptr && row_ptr && col && H && M && eigval && W && resid, "required pointer is NULL");
     FF_REQUIRE(ctx, n_obj >= 1 && obj_off, "bad object list");
     FF_REQUIRE(ctx, p->k >= 1, "k must be >= 1");
@@ -2327,8 +2388,8 @@ int solve(ff_ctx *ctx, int n_obj, const int64_t *obj_off, const int64_t *row_ptr
     FF_REQUIRE(ctx, p->precision == 0 || hm32, "mixed precision needs the FP32 copies (hm32)");
     FF_REQUIRE(ctx, p->tol > 0.0 && p->max_iter >= 0, "bad tolerance or iteration cap");
     FF_REQUIRE(ctx, p->precond >= 0 && p->precond <= 2, "precond must be 0, 1 or 2");
-    FF_REQUIRE(ctx, p->precond != 2 || p->precond_degree == 0 || (p->precond_degree >= 2 && p->precond_degree <= 8),
-               "Chebyshev degree %d must be 0 (default 4) or in [2, 8]", p->precond_degree);
+    FF_REQUIRE(ctx, p->precond != 2 || p->precond_degree == 0 || (p->precond_degree >= 2 && p->precond_degree <= 16),
+               "Chebyshev degree %d must be 0 (default %d) or in [2, 16]", p->precond_degree, kChebDefault);
     int m = p->block > 0 ? p->block : ((p->k + 7) / 8) * 8;
     FF_REQUIRE(ctx, m >= p->k && m % 8 == 0 && m >= 8 && m <= 64, "block %d: needs k <= m <= 64, m multiple of 8", m);
     Solver s;
@@ -2378,7 +2439,12 @@ int solve(ff_ctx *ctx, int n_obj, const int64_t *obj_off, const int64_t *row_ptr
     int rc = setup(s, p);
     if (rc) return rc;
     if (p->precond == 2) {
-        const int degree = p->precond_degree > 0 ? p->precond_degree : 4;
+        const int degree = p->precond_degree > 0 ? p->precond_degree : kChebDefault;
+        // the FP32 preconditioner's products run on tiles of eight rows when the block shape allows
+        if (p->precision == 1 && s.var32 >= kRowTileBase && rt::t8_ok(s.m, s.m, s.m)) {
+            rc = rt::build_t8_ws(ctx, s.st, s.N, row_ptr, col, H, &s.rt8);
+            if (rc) return rc;
+        }
         rc = p->precision == 1 ? cheb_setup<float>(s, degree, p->seed) : cheb_setup<double>(s, degree, p->seed);
         if (rc) return rc;
     }
@@ -2486,7 +2552,9 @@ int solve(ff_ctx *ctx, int n_obj, const int64_t *obj_off, const int64_t *row_ptr
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
     if (info)
         for (int o = 0; o < n_obj; ++o) info[o].seconds = secs;
-    ctx->stage_ms[4] = secs * 1e3;
+    timing_collect(ctx);
+    ctx->stage_ms[FF_STAGE_TOTAL] = secs * 1e3;
+    ctx->stage_launches[FF_STAGE_TOTAL] = 1;
     if (broke && !all_conv) return set_error(ctx, FF_ERR_BREAKDOWN, "Rayleigh-Ritz basis lost rank");
     if (!all_conv)
         return set_error(ctx, FF_ERR_NOT_CONVERGED, "max residual %.3e above tol %.3e after %d + %d iterations", worst,

@@ -20,8 +20,8 @@ struct RTView {
     int64_t n = 0, ntiles = 0, entries = 0;
     const int64_t *tptr = nullptr;   // [ntiles + 1]
     const int32_t *tcol = nullptr;   // [entries]
-    const float *v32 = nullptr;      // [entries][8]: H of rows 0..3, M of rows 0..3 (FP32 copies)
-    const double *v64 = nullptr;     // [entries][8] (FP64)
+    const float *v32 = nullptr;      // [2][entries][4]: H of rows 0..3 per entry, then M likewise (FP32 copies)
+    const double *v64 = nullptr;     // [2][entries][4] (FP64)
 };
 
 // Build the tile structure and the value copies asked for (want32 / want64)
@@ -37,6 +37,41 @@ int spmm32(ff_ctx *ctx, hipStream_t st, const RTView &v, int sub, int m, const f
            float *MY, int64_t ldo, const int *row_obj, const int *status);
 int spmm64(ff_ctx *ctx, hipStream_t st, const RTView &v, int sub, int m, const double *Y, int64_t ldy, double *HY,
            double *MY, int64_t ldo, const int *row_obj, const int *status);
+// One step of the Chebyshev-Jacobi preconditioner fused into the H-only
+// product of DZ (rows of object o use coef[o * stride + 2 step - 1] = f1 and
+// coef[o * stride + 2 step] = f2): R -= D^-1 H DZ, DZ' = f1 DZ + f2 R, W += DZ'.
+// R, DZ and dz_out share the leading dimension of DZ; dz_out must not alias DZ
+// (other tiles still gather it).
+template <typename T> struct ChebStep {
+    const double *coef = nullptr;
+    int stride = 0, step = 0;
+    const T *dinv = nullptr;
+    T *R = nullptr, *dz_out = nullptr, *W = nullptr;
+    int64_t ldw = 0;
+};
+int cheb_step32(ff_ctx *ctx, hipStream_t st, const RTView &v, int sub, int m, const float *DZ, int64_t ld,
+                const int *row_obj, const int *status, const ChebStep<float> &cs);
+int cheb_step64(ff_ctx *ctx, hipStream_t st, const RTView &v, int sub, int m, const double *DZ, int64_t ld,
+                const int *row_obj, const int *status, const ChebStep<double> &cs);
+
+// H-only FP32 copy in tiles of eight rows (the preconditioner's products):
+// vh[entry][8] holds the H values of the tile's eight rows.
+constexpr int kTile8 = 8;
+struct RT8View {
+    int64_t n = 0, ntiles = 0, entries = 0;
+    const int64_t *tptr = nullptr;   // [ntiles + 1]
+    const int32_t *tcol = nullptr;   // [entries]
+    const float *vh = nullptr;       // [entries][8]
+};
+int build_t8_ws(ff_ctx *ctx, hipStream_t st, int64_t n, const int64_t *row_ptr, const int32_t *col, const double *H,
+                RT8View *out);
+// block widths the eight-row kernels take: m % 8 == 0, 8 <= m <= 64, 16-byte aligned rows
+bool t8_ok(int m, int64_t ldy, int64_t ldo);
+int spmm_h_t8(ff_ctx *ctx, hipStream_t st, const RT8View &v, int sub, int m, const float *Y, int64_t ldy, float *HY,
+              int64_t ldo, const int *row_obj, const int *status);
+int cheb_step_t8(ff_ctx *ctx, hipStream_t st, const RT8View &v, int sub, int m, const float *DZ, int64_t ld,
+                 const int *row_obj, const int *status, const ChebStep<float> &cs);
+
 // HY = H Y alone, for the preconditioner: FP32 accumulation on the FP32 copy,
 // FP64 on the FP64 copy.
 int spmm_h32(ff_ctx *ctx, hipStream_t st, const RTView &v, int sub, int m, const float *Y, int64_t ldy, float *HY,

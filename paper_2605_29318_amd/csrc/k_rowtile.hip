@@ -6,7 +6,9 @@
 struct ff_rowtiles {
     int device = 0;
     hipStream_t stream = nullptr;                  // the context's stream, kept for destruction
+    int eight = 0;                                 // 1: the H-only copy in tiles of eight rows (v8)
     ff::rt::RTView v;
+    ff::rt::RT8View v8;
     void *mem[4] = {nullptr, nullptr, nullptr, nullptr};
 };
 
@@ -27,38 +29,41 @@ __device__ inline int xcd_remap(int b, int nb) {
 // building the tile copy: one thread per tile merges its (sorted) rows
 // ---------------------------------------------------------------------------
 
-struct Merge4 {
-    int64_t p[kTileRows], e[kTileRows];
-    int32_t h[kTileRows];
+template <int R> struct Merge {
+    int64_t p[R], e[R];
+    int32_t h[R];
 };
 
-__device__ inline void merge_init(Merge4 &s, int64_t nrows, int64_t r0, const int64_t *row_ptr, const int32_t *col) {
+template <int R>
+__device__ inline void merge_init(Merge<R> &s, int64_t nrows, int64_t r0, const int64_t *row_ptr, const int32_t *col) {
 #pragma unroll
-    for (int i = 0; i < kTileRows; ++i) {
+    for (int i = 0; i < R; ++i) {
         const bool in = r0 + i < nrows;
         s.p[i] = in ? row_ptr[r0 + i] : 0;
         s.e[i] = in ? row_ptr[r0 + i + 1] : 0;
         s.h[i] = s.p[i] < s.e[i] ? col[s.p[i]] : INT_MAX;
     }
 }
-__device__ inline int32_t merge_head(const Merge4 &s) {
+template <int R>
+__device__ inline int32_t merge_head(const Merge<R> &s) {
     int32_t c = s.h[0];
 #pragma unroll
-    for (int i = 1; i < kTileRows; ++i) c = min(c, s.h[i]);
+    for (int i = 1; i < R; ++i) c = min(c, s.h[i]);
     return c;
 }
 
+template <int R>
 __global__ void rt_count_kernel(int64_t nrows, int64_t ntiles, const int64_t *row_ptr, const int32_t *col,
                                 int64_t *cnt) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= ntiles) return;
-    Merge4 s;
-    merge_init(s, nrows, t * kTileRows, row_ptr, col);
+    Merge<R> s;
+    merge_init(s, nrows, t * R, row_ptr, col);
     int64_t k = 0;
     for (int32_t cur = merge_head(s); cur != INT_MAX; cur = merge_head(s)) {
         ++k;
 #pragma unroll
-        for (int i = 0; i < kTileRows; ++i)
+        for (int i = 0; i < R; ++i)
             if (s.h[i] == cur) {
                 ++s.p[i];
                 s.h[i] = s.p[i] < s.e[i] ? col[s.p[i]] : INT_MAX;
@@ -67,23 +72,47 @@ __global__ void rt_count_kernel(int64_t nrows, int64_t ntiles, const int64_t *ro
     cnt[t] = k;
 }
 
+// H-only FP32 copy in tiles of R rows: vh[entry][R]
+template <int R>
+__global__ void rt_fill_h_kernel(int64_t nrows, int64_t ntiles, const int64_t *row_ptr, const int32_t *col,
+                                 const double *H, const int64_t *tptr, int32_t *tcol, float *vh) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntiles) return;
+    Merge<R> s;
+    merge_init(s, nrows, t * R, row_ptr, col);
+    int64_t o = tptr[t];
+    for (int32_t cur = merge_head(s); cur != INT_MAX; cur = merge_head(s), ++o) {
+        tcol[o] = cur;
+        float *v = vh + o * R;
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const bool hit = s.h[i] == cur;
+            v[i] = hit ? (float)H[s.p[i]] : 0.f;
+            if (hit) {
+                ++s.p[i];
+                s.h[i] = s.p[i] < s.e[i] ? col[s.p[i]] : INT_MAX;
+            }
+        }
+    }
+}
+
 template <typename T>
 __global__ void rt_fill_kernel(int64_t nrows, int64_t ntiles, const int64_t *row_ptr, const int32_t *col,
                                const double *H, const double *M, const int64_t *tptr, int32_t *tcol, T *tval,
-                               int write_col) {
+                               int64_t entries, int write_col) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= ntiles) return;
-    Merge4 s;
+    Merge<kTileRows> s;
     merge_init(s, nrows, t * kTileRows, row_ptr, col);
     int64_t o = tptr[t];
     for (int32_t cur = merge_head(s); cur != INT_MAX; cur = merge_head(s), ++o) {
         if (write_col) tcol[o] = cur;
-        T *v = tval + o * 8;
+        T *vh = tval + o * 4, *vm = tval + (entries + o) * 4;
 #pragma unroll
         for (int i = 0; i < kTileRows; ++i) {
             const bool hit = s.h[i] == cur;
-            v[i] = hit ? (T)H[s.p[i]] : (T)0;
-            v[4 + i] = hit ? (T)M[s.p[i]] : (T)0;
+            vh[i] = hit ? (T)H[s.p[i]] : (T)0;
+            vm[i] = hit ? (T)M[s.p[i]] : (T)0;
             if (hit) {
                 ++s.p[i];
                 s.h[i] = s.p[i] < s.e[i] ? col[s.p[i]] : INT_MAX;
@@ -99,6 +128,14 @@ __global__ void rt_fill_kernel(int64_t nrows, int64_t ntiles, const int64_t *row
 template <typename T> struct Vec;
 template <> struct Vec<float> { typedef float4 type; static constexpr int n = 4; };
 template <> struct Vec<double> { typedef double2 type; static constexpr int n = 2; };
+__device__ inline float vget(const float4 &v, int q) { return q == 0 ? v.x : q == 1 ? v.y : q == 2 ? v.z : v.w; }
+__device__ inline double vget(const double2 &v, int q) { return q == 0 ? v.x : v.y; }
+__device__ inline void vset(float4 &v, int q, float x) {
+    if (q == 0) v.x = x; else if (q == 1) v.y = x; else if (q == 2) v.z = x; else v.w = x;
+}
+__device__ inline void vset(double2 &v, int q, double x) {
+    if (q == 0) v.x = x; else v.y = x;
+}
 
 // Accumulators: FP64 for the products of the eigensolver (a product of two FP32
 // numbers is exact in FP64), FP32 for the H-only products of the preconditioner.
@@ -134,13 +171,13 @@ template <typename T, bool kHM> struct Chunk;
 template <bool kHM> struct Chunk<float, kHM> {
     int32_t j;
     f32x4 a, b;                                    // H rows 0..3, M rows 0..3
-    __device__ void load(const int32_t *tcol, const float *tval, int64_t e, bool in) {
+    __device__ void load(const int32_t *tcol, const float *th, const float *tm, int64_t e, bool in) {
         j = 0;
         a = b = f32x4{0.f, 0.f, 0.f, 0.f};
         if (in) {
             j = __builtin_nontemporal_load(tcol + e);
-            a = __builtin_nontemporal_load((const f32x4 *)(tval + e * 8));
-            if (kHM) b = __builtin_nontemporal_load((const f32x4 *)(tval + e * 8 + 4));
+            a = __builtin_nontemporal_load((const f32x4 *)(th + e * 4));
+            if (kHM) b = __builtin_nontemporal_load((const f32x4 *)(tm + e * 4));
         }
     }
     __device__ void stage(float *sv, int lane) const {
@@ -157,14 +194,15 @@ template <bool kHM> struct Chunk<double, kHM> {
     static constexpr int NQ = kHM ? 4 : 2;
     int32_t j;
     f64x2 v[NQ];
-    __device__ void load(const int32_t *tcol, const double *tval, int64_t e, bool in) {
+    __device__ void load(const int32_t *tcol, const double *th, const double *tm, int64_t e, bool in) {
         j = 0;
 #pragma unroll
         for (int q = 0; q < NQ; ++q) v[q] = f64x2{0.0, 0.0};
         if (in) {
             j = __builtin_nontemporal_load(tcol + e);
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) v[q] = __builtin_nontemporal_load((const f64x2 *)(tval + e * 8 + 2 * q));
+            for (int q = 0; q < NQ; ++q)
+                v[q] = __builtin_nontemporal_load((const f64x2 *)((q < 2 ? th : tm) + e * 4 + 2 * (q & 1)));
         }
     }
     __device__ void stage(double *sv, int lane) const {
@@ -173,19 +211,64 @@ template <bool kHM> struct Chunk<double, kHM> {
     }
 };
 
+// One 64-entry chunk of a tile: stage its values in LDS, request the chunk two
+// ahead into the same registers, then gather and accumulate.
+template <typename T, typename A, bool kHM, int kBatch>
+__device__ __forceinline__ void rt_chunk(Chunk<T, kHM> &ch, int64_t base, int64_t e1, const int32_t *tcol,
+                                         const T *tval_h, const T *tval_m, T *sv, int lane, bool on, int g, int c,
+                                         int NG, int steps, const T *Y, int64_t ldy, Acc4<A> (&aH)[kTileRows],
+                                         Acc4<A> (&aM)[kHM ? kTileRows : 1]) {
+    typedef typename Vec<T>::type V;
+    constexpr int VN = Vec<T>::n;
+    constexpr int NV = kHM ? 8 : 4;
+    const int cnt = (int)(e1 - base < 64 ? e1 - base : 64);
+    const int32_t jc = ch.j;
+    __builtin_amdgcn_wave_barrier();
+    ch.stage(sv, lane);
+    __builtin_amdgcn_wave_barrier();
+    ch.load(tcol, tval_h, tval_m, base + 128 + lane, base + 128 + lane < e1);
+    for (int s0 = 0; s0 < steps; s0 += kBatch) {
+        V x[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int src = (s0 + u) * NG + g;
+            const int32_t j = __shfl(jc, src < 64 ? src : 63, 64);
+            const bool ok = on && (s0 + u < steps) && src < cnt;
+            if (ok)
+                x[u] = *(const V *)(Y + (int64_t)j * ldy + c * VN);
+            else
+                x[u] = V{};
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int src = (s0 + u) * NG + g;
+            const bool ok = on && (s0 + u < steps) && src < cnt;
+            if (ok) {
+                const T *vv = sv + src * NV;
+#pragma unroll
+                for (int i = 0; i < kTileRows; ++i) {
+                    acc_fma(aH[i], vv[i], x[u]);
+                    if (kHM) acc_fma(aM[i], vv[4 + i], x[u]);
+                }
+            }
+        }
+    }
+}
+
 // One wavefront per tile. The wave reads 64 union entries (column and eight
-// values) with one coalesced load per lane, prefetches the next 64 while it
-// works on these, keeps the values in a wave-private LDS area (each lane group
+// values) with one coalesced load per lane, keeps the next two chunks of 64 in
+// flight while it works on one, keeps the values in a wave-private LDS area (each lane group
 // reads its entry's values as a broadcast) and hands each column to the lane
 // group that needs it by a cross-lane shuffle. Lanes form groups of
 // G = m / VN; group g takes entries g, g + NG, ... of the chunk; each lane holds
 // VN columns of the gathered row of Y and accumulates all four rows of the tile
 // in FP64; the groups are summed at the end. With kHM false the kernel forms
 // H Y alone (MY is not touched), accumulating in A.
-template <typename T, typename A, bool kHM, int kWaves, int kBatch, int kOcc>
+template <typename T, typename A, bool kHM, bool kEpi, int kWaves, int kBatch, int kOcc>
 __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(kOcc, 8)))
-spmm_rt_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int32_t *tcol, const T *tval, const T *Y,
-               int64_t ldy, T *HY, T *MY, int64_t ldo, int m, const int *row_obj, const int *obj_status) {
+spmm_rt_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int32_t *tcol, const T *tval_h,
+               const T *tval_m, const T *Y, int64_t ldy, T *HY, T *MY, int64_t ldo, int m, const int *row_obj,
+               const int *obj_status, ChebStep<T> cs) {
     typedef typename Vec<T>::type V;
     constexpr int VN = Vec<T>::n;
     constexpr int NV = kHM ? 8 : 4;                // staged values per entry
@@ -218,41 +301,15 @@ spmm_rt_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int32_t
     for (int i = 0; i < (kHM ? kTileRows : 1); ++i)
 #pragma unroll
         for (int q = 0; q < 4; ++q) aM[i].v[q] = 0;
-    Chunk<T, kHM> nxt;
-    nxt.load(tcol, tval, e0 + lane, e0 + lane < e1);
-    for (int64_t base = e0; base < e1; base += 64) {
-        const int cnt = (int)(e1 - base < 64 ? e1 - base : 64);
-        const int32_t jc = nxt.j;
-        __builtin_amdgcn_wave_barrier();
-        nxt.stage(sv, lane);
-        __builtin_amdgcn_wave_barrier();
-        nxt.load(tcol, tval, base + 64 + lane, base + 64 + lane < e1);
-        for (int s0 = 0; s0 < steps; s0 += kBatch) {
-            V x[kBatch];
-#pragma unroll
-            for (int u = 0; u < kBatch; ++u) {
-                const int src = (s0 + u) * NG + g;
-                const int32_t j = __shfl(jc, src < 64 ? src : 63, 64);
-                const bool ok = on && (s0 + u < steps) && src < cnt;
-                if (ok)
-                    x[u] = *(const V *)(Y + (int64_t)j * ldy + c * VN);
-                else
-                    x[u] = V{};
-            }
-#pragma unroll
-            for (int u = 0; u < kBatch; ++u) {
-                const int src = (s0 + u) * NG + g;
-                const bool ok = on && (s0 + u < steps) && src < cnt;
-                if (ok) {
-                    const T *vv = sv + src * NV;
-#pragma unroll
-                    for (int i = 0; i < kTileRows; ++i) {
-                        acc_fma(aH[i], vv[i], x[u]);
-                        if (kHM) acc_fma(aM[i], vv[4 + i], x[u]);
-                    }
-                }
-            }
-        }
+    // two chunks in flight: chunk k + 2 is requested as soon as chunk k is staged
+    Chunk<T, kHM> ca, cb;
+    ca.load(tcol, tval_h, tval_m, e0 + lane, e0 + lane < e1);
+    cb.load(tcol, tval_h, tval_m, e0 + 64 + lane, e0 + 64 + lane < e1);
+    for (int64_t base = e0; base < e1; base += 128) {
+        rt_chunk<T, A, kHM, kBatch>(ca, base, e1, tcol, tval_h, tval_m, sv, lane, on, g, c, NG, steps, Y, ldy, aH, aM);
+        if (base + 64 < e1)
+            rt_chunk<T, A, kHM, kBatch>(cb, base + 64, e1, tcol, tval_h, tval_m, sv, lane, on, g, c, NG, steps, Y, ldy,
+                                        aH, aM);
     }
     if ((64 % G) == 0) {
 #pragma unroll
@@ -281,23 +338,206 @@ spmm_rt_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int32_t
             __builtin_amdgcn_wave_barrier();
         }
     }
-    if (g == 0) {
+    // after the butterfly every lane holds the sums and lane group i < 4 stores row i;
+    // otherwise group 0 stores all four rows
+    const bool all = (64 % G) == 0;
+    if (all ? g < kTileRows : g == 0) {
 #pragma unroll
-        for (int i = 0; i < kTileRows; ++i)
-            if (act[i]) {
-                acc_store(HY + (r0 + i) * ldo + c * VN, aH[i]);
-                if (kHM) acc_store(MY + (r0 + i) * ldo + c * VN, aM[kHM ? i : 0]);
+        for (int i = 0; i < kTileRows; ++i) {
+            if (all && i != g) continue;
+            if (!act[i]) continue;
+            const int64_t r = r0 + i;
+            if (kEpi) {
+                // Chebyshev step on the row: r -= D^-1 H dz, dz' = f1 dz + f2 r, w += dz'
+                const int o = row_obj[r];
+                const double f1 = cs.coef[(size_t)o * cs.stride + 2 * cs.step - 1];
+                const double f2 = cs.coef[(size_t)o * cs.stride + 2 * cs.step];
+                const double dv = (double)cs.dinv[r];
+                const V rv0 = *(const V *)(cs.R + r * ldo + c * VN);
+                const V dz0 = *(const V *)(Y + r * ldy + c * VN);
+                const V w0 = *(const V *)(cs.W + r * cs.ldw + c * VN);
+                V rv1, dz1, w1;
+#pragma unroll
+                for (int q = 0; q < VN; ++q) {
+                    const double rv = (double)vget(rv0, q) - dv * (double)(T)aH[i].v[q];
+                    const double dz = f1 * (double)vget(dz0, q) + f2 * rv;
+                    vset(rv1, q, (T)rv);
+                    vset(dz1, q, (T)dz);
+                    vset(w1, q, (T)((double)vget(w0, q) + dz));
+                }
+                *(V *)(cs.R + r * ldo + c * VN) = rv1;
+                *(V *)(cs.dz_out + r * ldo + c * VN) = dz1;
+                *(V *)(cs.W + r * cs.ldw + c * VN) = w1;
+            } else {
+                acc_store(HY + r * ldo + c * VN, aH[i]);
+                if (kHM) acc_store(MY + r * ldo + c * VN, aM[kHM ? i : 0]);
             }
+        }
     }
 }
 
-template <typename T, typename A = double, bool kHM = true>
+template <int kBatch>
+__device__ __forceinline__ void h8_chunk(Chunk<float, false> &ch, int64_t base, int64_t e1, const int32_t *tcol,
+                                         const float *tval_h, float *sv, int lane, int g, int c, int NG, int steps,
+                                         const float *Y, int64_t ldy, float (&acc)[kTileRows][8]) {
+    const int cnt = (int)(e1 - base < 64 ? e1 - base : 64);
+    const int32_t jc = ch.j;
+    __builtin_amdgcn_wave_barrier();
+    ch.stage(sv, lane);
+    __builtin_amdgcn_wave_barrier();
+    ch.load(tcol, tval_h, nullptr, base + 128 + lane, base + 128 + lane < e1);
+    for (int s0 = 0; s0 < steps; s0 += kBatch) {
+        f32x4 x[kBatch][2];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int src = (s0 + u) * NG + g;
+            const int32_t j = __shfl(jc, src < 64 ? src : 63, 64);
+            const bool ok = (s0 + u < steps) && src < cnt;
+            x[u][0] = x[u][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+            if (ok) {
+                const float *yp = Y + (int64_t)j * ldy + c * 8;
+                x[u][0] = *(const f32x4 *)yp;
+                x[u][1] = *(const f32x4 *)(yp + 4);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int src = (s0 + u) * NG + g;
+            if ((s0 + u < steps) && src < cnt) {
+                const f32x4 hv = *(const f32x4 *)(sv + src * 4);
+#pragma unroll
+                for (int i = 0; i < kTileRows; ++i)
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) acc[i][q] = fmaf(hv[i], x[u][q >> 2][q & 3], acc[i][q]);
+            }
+        }
+    }
+}
+
+// H-only FP32 product (FP32 accumulation) with eight columns per lane: two
+// 16-byte pieces of each gathered row, so the per-entry work that does not
+// scale with the columns (column shuffle, value read, address) is spread over
+// twice the FMAs of the four-column kernel. Needs m % 8 == 0 and 64 % (m / 8)
+// == 0; after the butterfly every lane holds the sums and lane group i stores
+// row i. With kEpi the Chebyshev step replaces the store; its operands for the
+// lane group's row are loaded before the product so their latency is hidden.
+template <bool kEpi, int kWaves, int kBatch, int kOcc>
+__global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(kOcc, 8)))
+spmm_rt_h8_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int32_t *tcol, const float *tval_h,
+                  const float *Y, int64_t ldy, float *HY, int64_t ldo, int m, const int *row_obj,
+                  const int *obj_status, ChebStep<float> cs) {
+    __shared__ __align__(16) float svals[kWaves][64 * 4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t t = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kWaves + wv;
+    if (t >= ntiles) return;
+    const int64_t r0 = t * kTileRows;
+    bool act[kTileRows];
+    bool any = false;
+#pragma unroll
+    for (int i = 0; i < kTileRows; ++i) {
+        act[i] = r0 + i < nrows && (!obj_status || obj_status[row_obj[r0 + i]] == 0);
+        any = any || act[i];
+    }
+    if (!any) return;
+    const int G = m >> 3, NG = 64 / G;
+    const int g = lane / G, c = lane - g * G;
+    const int steps = NG < 64 ? 64 / NG : 1;
+    const bool mine = g < kTileRows && act[g < kTileRows ? g : 0];
+    const int64_t rme = r0 + (g < kTileRows ? g : 0);
+    f32x4 er[2], ez[2], ew[2];
+    if (kEpi && mine) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            er[h] = *(const f32x4 *)(cs.R + rme * ldo + c * 8 + 4 * h);
+            ez[h] = *(const f32x4 *)(Y + rme * ldy + c * 8 + 4 * h);
+            ew[h] = *(const f32x4 *)(cs.W + rme * cs.ldw + c * 8 + 4 * h);
+        }
+    }
+    float *sv = svals[wv];
+    const int64_t e0 = tptr[t], e1 = tptr[t + 1];
+    float acc[kTileRows][8];
+#pragma unroll
+    for (int i = 0; i < kTileRows; ++i)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[i][q] = 0.f;
+    Chunk<float, false> ca, cb;
+    ca.load(tcol, tval_h, nullptr, e0 + lane, e0 + lane < e1);
+    cb.load(tcol, tval_h, nullptr, e0 + 64 + lane, e0 + 64 + lane < e1);
+    for (int64_t base = e0; base < e1; base += 128) {
+        h8_chunk<kBatch>(ca, base, e1, tcol, tval_h, sv, lane, g, c, NG, steps, Y, ldy, acc);
+        if (base + 64 < e1) h8_chunk<kBatch>(cb, base + 64, e1, tcol, tval_h, sv, lane, g, c, NG, steps, Y, ldy, acc);
+    }
+#pragma unroll
+    for (int i = 0; i < kTileRows; ++i)
+        for (int d = G; d < 64; d <<= 1)
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc[i][q] += __shfl_xor(acc[i][q], d, 64);
+    if (!mine) return;
+    float a8[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        a8[q] = acc[0][q];
+#pragma unroll
+        for (int i = 1; i < kTileRows; ++i)
+            if (g == i) a8[q] = acc[i][q];
+    }
+    if (kEpi) {
+        // Chebyshev step on the row: r -= D^-1 H dz, dz' = f1 dz + f2 r, w += dz'
+        const int o = row_obj[rme];
+        const double f1 = cs.coef[(size_t)o * cs.stride + 2 * cs.step - 1];
+        const double f2 = cs.coef[(size_t)o * cs.stride + 2 * cs.step];
+        const double dv = (double)cs.dinv[rme];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            f32x4 rv1, dz1, w1;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double rv = (double)er[h][q] - dv * (double)a8[4 * h + q];
+                const double dz = f1 * (double)ez[h][q] + f2 * rv;
+                rv1[q] = (float)rv;
+                dz1[q] = (float)dz;
+                w1[q] = (float)((double)ew[h][q] + dz);
+            }
+            *(f32x4 *)(cs.R + rme * ldo + c * 8 + 4 * h) = rv1;
+            *(f32x4 *)(cs.dz_out + rme * ldo + c * 8 + 4 * h) = dz1;
+            *(f32x4 *)(cs.W + rme * cs.ldw + c * 8 + 4 * h) = w1;
+        }
+    } else {
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+            *(f32x4 *)(HY + rme * ldo + c * 8 + 4 * h) =
+                f32x4{a8[4 * h], a8[4 * h + 1], a8[4 * h + 2], a8[4 * h + 3]};
+    }
+}
+
+inline bool h8_ok(int m, int64_t ldy, int64_t ldo) {
+    return m % 8 == 0 && m <= 512 && 64 % (m / 8) == 0 && ldy % 4 == 0 && ldo % 4 == 0;
+}
+
+template <bool kEpi>
+int launch_h8(ff_ctx *ctx, hipStream_t st, const RTView &v, int sub, int m, const float *Y, int64_t ldy, float *HY,
+              int64_t ldo, const int *row_obj, const int *status, const ChebStep<float> &cs) {
+#define FF_RT8(W, B, O)                                                                                     \
+    hipLaunchKernelGGL((spmm_rt_h8_kernel<kEpi, W, B, O>), dim3(grid_for(v.ntiles, W)), dim3(64 * W), 0, st, \
+                       v.n, v.ntiles, v.tptr, v.tcol, v.v32, Y, ldy, HY, ldo, m, row_obj, status, cs)
+    switch (sub) {
+        case 1: FF_RT8(2, 4, 1); break;
+        case 2: FF_RT8(4, 2, 4); break;
+        default: FF_RT8(4, 4, 1); break;
+    }
+#undef FF_RT8
+    FF_CHECK_LAUNCH(ctx);
+    return FF_OK;
+}
+
+template <typename T, typename A = double, bool kHM = true, bool kEpi = false>
 int launch(ff_ctx *ctx, hipStream_t st, const RTView &v, const T *tval, int sub, int m, const T *Y, int64_t ldy,
-           T *HY, T *MY, int64_t ldo, const int *row_obj, const int *status) {
+           T *HY, T *MY, int64_t ldo, const int *row_obj, const int *status, ChebStep<T> cs = ChebStep<T>{}) {
     // each lane holds one 16-byte access of the gathered row (narrower loads cost the texture unit as many cycles)
-#define FF_RT(W, B, O)                                                                                      \
-    hipLaunchKernelGGL((spmm_rt_kernel<T, A, kHM, W, B, O>), dim3(grid_for(v.ntiles, W)), dim3(64 * W), 0, st, \
-                       v.n, v.ntiles, v.tptr, v.tcol, tval, Y, ldy, HY, MY, ldo, m, row_obj, status)
+#define FF_RT(W, B, O)                                                                                             \
+    hipLaunchKernelGGL((spmm_rt_kernel<T, A, kHM, kEpi, W, B, O>), dim3(grid_for(v.ntiles, W)), dim3(64 * W), 0, st, \
+                       v.n, v.ntiles, v.tptr, v.tcol, tval, tval + 4 * v.entries, Y, ldy, HY, MY, ldo, m, row_obj,  \
+                       status, cs)
     switch (sub) {
         case 1: FF_RT(2, 8, 1); break;
         case 2: FF_RT(4, 4, 4); break;
@@ -321,6 +561,8 @@ int spmm64(ff_ctx *ctx, hipStream_t st, const RTView &v, int sub, int m, const d
 int spmm_h32(ff_ctx *ctx, hipStream_t st, const RTView &v, int sub, int m, const float *Y, int64_t ldy, float *HY,
              int64_t ldo, const int *row_obj, const int *status) {
     FF_REQUIRE(ctx, v.v32 != nullptr, "row tiles have no FP32 values");
+    if (h8_ok(m, ldy, ldo))
+        return launch_h8<false>(ctx, st, v, sub, m, Y, ldy, HY, ldo, row_obj, status, ChebStep<float>{});
     return launch<float, float, false>(ctx, st, v, v.v32, sub, m, Y, ldy, HY, nullptr, ldo, row_obj, status);
 }
 int spmm_h64(ff_ctx *ctx, hipStream_t st, const RTView &v, int sub, int m, const double *Y, int64_t ldy, double *HY,
@@ -328,11 +570,27 @@ int spmm_h64(ff_ctx *ctx, hipStream_t st, const RTView &v, int sub, int m, const
     FF_REQUIRE(ctx, v.v64 != nullptr, "row tiles have no FP64 values");
     return launch<double, double, false>(ctx, st, v, v.v64, sub, m, Y, ldy, HY, nullptr, ldo, row_obj, status);
 }
+int cheb_step32(ff_ctx *ctx, hipStream_t st, const RTView &v, int sub, int m, const float *DZ, int64_t ld,
+                const int *row_obj, const int *status, const ChebStep<float> &cs) {
+    FF_REQUIRE(ctx, v.v32 != nullptr && row_obj != nullptr, "row tiles have no FP32 values");
+    if (h8_ok(m, ld, ld) && cs.ldw % 4 == 0)
+        return launch_h8<true>(ctx, st, v, sub, m, DZ, ld, nullptr, ld, row_obj, status, cs);
+    return launch<float, float, false, true>(ctx, st, v, v.v32, sub, m, DZ, ld, nullptr, nullptr, ld, row_obj, status,
+                                             cs);
+}
+int cheb_step64(ff_ctx *ctx, hipStream_t st, const RTView &v, int sub, int m, const double *DZ, int64_t ld,
+                const int *row_obj, const int *status, const ChebStep<double> &cs) {
+    FF_REQUIRE(ctx, v.v64 != nullptr && row_obj != nullptr, "row tiles have no FP64 values");
+    return launch<double, double, false, true>(ctx, st, v, v.v64, sub, m, DZ, ld, nullptr, nullptr, ld, row_obj,
+                                               status, cs);
+}
 
 // tile pointers and the number of union entries (host), in caller-provided memory
+template <int R = kTileRows>
 static int build_ptr(ff_ctx *ctx, hipStream_t st, int64_t n, const int64_t *row_ptr, const int32_t *col,
                      int64_t *cnt, int64_t *tptr, int64_t ntiles, int64_t *entries) {
-    hipLaunchKernelGGL(rt_count_kernel, dim3(grid_for(ntiles, 256)), dim3(256), 0, st, n, ntiles, row_ptr, col, cnt);
+    hipLaunchKernelGGL(rt_count_kernel<R>, dim3(grid_for(ntiles, 256)), dim3(256), 0, st, n, ntiles, row_ptr, col,
+                       cnt);
     FF_CHECK_LAUNCH(ctx);
     int rc = scan_exclusive_i64(ctx, cnt, tptr, ntiles);
     if (rc) return rc;
@@ -345,13 +603,14 @@ static int build_ptr(ff_ctx *ctx, hipStream_t st, int64_t n, const int64_t *row_
 }
 
 static int fill(ff_ctx *ctx, hipStream_t st, int64_t n, int64_t ntiles, const int64_t *row_ptr, const int32_t *col,
-                const double *H, const double *M, const int64_t *tptr, int32_t *tcol, float *v32, double *v64) {
+                const double *H, const double *M, const int64_t *tptr, int64_t entries, int32_t *tcol, float *v32,
+                double *v64) {
     if (v32)
         hipLaunchKernelGGL(rt_fill_kernel<float>, dim3(grid_for(ntiles, 256)), dim3(256), 0, st, n, ntiles, row_ptr,
-                           col, H, M, tptr, tcol, v32, 1);
+                           col, H, M, tptr, tcol, v32, entries, 1);
     if (v64)
         hipLaunchKernelGGL(rt_fill_kernel<double>, dim3(grid_for(ntiles, 256)), dim3(256), 0, st, n, ntiles, row_ptr,
-                           col, H, M, tptr, tcol, v64, v32 ? 0 : 1);
+                           col, H, M, tptr, tcol, v64, entries, v32 ? 0 : 1);
     FF_CHECK_LAUNCH(ctx);
     return FF_OK;
 }
@@ -373,7 +632,7 @@ int build_ws(ff_ctx *ctx, hipStream_t st, int64_t n, const int64_t *row_ptr, con
                                             (size_t)std::max<int64_t>(entries, 1) * 8 * sizeof(double))
                          : nullptr;
     if (!tcol || (want32 && !v32) || (want64 && !v64)) return FF_ERR_OOM;
-    if ((rc = fill(ctx, st, n, ntiles, row_ptr, col, H, M, tptr, tcol, v32, v64))) return rc;
+    if ((rc = fill(ctx, st, n, ntiles, row_ptr, col, H, M, tptr, entries, tcol, v32, v64))) return rc;
     out->n = n;
     out->ntiles = ntiles;
     out->entries = entries;
@@ -381,6 +640,224 @@ int build_ws(ff_ctx *ctx, hipStream_t st, int64_t n, const int64_t *row_ptr, con
     out->tcol = tcol;
     out->v32 = v32;
     out->v64 = v64;
+    return FF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// The preconditioner's H-only product on tiles of eight rows
+// ---------------------------------------------------------------------------
+//
+// Eight rows per tile cut the gathered rows of the block from 0.39 to 0.23 per
+// nonzero on the benchmark's clouds (the H values grow from 1.55 to 1.86 slots
+// per nonzero): the product gathers about 40% fewer bytes through the caches.
+// Same scheme as the eight-column kernel: lane groups of G = m / 8 lanes take
+// entries of a 64-entry chunk, each lane accumulates 8 rows x 8 columns in
+// FP32, the groups are summed by a butterfly, and lane group i stores row i.
+struct Chunk8 {
+    int32_t j;
+    f32x4 a, b;                                    // H rows 0..3 and 4..7
+    __device__ void load(const int32_t *tcol, const float *vh, int64_t e, bool in) {
+        j = 0;
+        a = b = f32x4{0.f, 0.f, 0.f, 0.f};
+        if (in) {
+            j = __builtin_nontemporal_load(tcol + e);
+            a = __builtin_nontemporal_load((const f32x4 *)(vh + e * 8));
+            b = __builtin_nontemporal_load((const f32x4 *)(vh + e * 8 + 4));
+        }
+    }
+    __device__ void stage(float *sv, int lane) const {
+        *(f32x4 *)(sv + lane * 8) = a;
+        *(f32x4 *)(sv + lane * 8 + 4) = b;
+    }
+};
+
+template <int kBatch>
+__device__ __forceinline__ void t8_chunk(Chunk8 &ch, int64_t base, int64_t e1, const int32_t *tcol, const float *vh,
+                                         float *sv, int lane, int g, int c, int NG, int steps, const float *Y,
+                                         int64_t ldy, float (&acc)[kTile8][8]) {
+    const int cnt = (int)(e1 - base < 64 ? e1 - base : 64);
+    const int32_t jc = ch.j;
+    __builtin_amdgcn_wave_barrier();
+    ch.stage(sv, lane);
+    __builtin_amdgcn_wave_barrier();
+    ch.load(tcol, vh, base + 128 + lane, base + 128 + lane < e1);
+    for (int s0 = 0; s0 < steps; s0 += kBatch) {
+        f32x4 x[kBatch][2];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int src = (s0 + u) * NG + g;
+            const int32_t j = __shfl(jc, src < 64 ? src : 63, 64);
+            const bool ok = (s0 + u < steps) && src < cnt;
+            x[u][0] = x[u][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+            if (ok) {
+                const float *yp = Y + (int64_t)j * ldy + c * 8;
+                x[u][0] = *(const f32x4 *)yp;
+                x[u][1] = *(const f32x4 *)(yp + 4);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int src = (s0 + u) * NG + g;
+            if ((s0 + u < steps) && src < cnt) {
+                const f32x4 h0 = *(const f32x4 *)(sv + src * 8), h1 = *(const f32x4 *)(sv + src * 8 + 4);
+#pragma unroll
+                for (int i = 0; i < kTile8; ++i) {
+                    const float hv = i < 4 ? h0[i & 3] : h1[i & 3];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) acc[i][q] = fmaf(hv, x[u][q >> 2][q & 3], acc[i][q]);
+                }
+            }
+        }
+    }
+}
+
+template <bool kEpi, int kWaves, int kBatch, int kOcc>
+__global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(kOcc, 8)))
+spmm_t8_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int32_t *tcol, const float *vh,
+               const float *Y, int64_t ldy, float *HY, int64_t ldo, int m, const int *row_obj, const int *obj_status,
+               ChebStep<float> cs) {
+    __shared__ __align__(16) float svals[kWaves][64 * 8];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t t = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kWaves + wv;
+    if (t >= ntiles) return;
+    const int64_t r0 = t * kTile8;
+    const int G = m >> 3, NG = 64 / G;             // NG >= 8 (m <= 64)
+    const int g = lane / G, c = lane - g * G;
+    const int steps = 64 / NG;
+    const int64_t rme = r0 + (g < kTile8 ? g : 0);
+    const bool mine = g < kTile8 && rme < nrows && (!obj_status || obj_status[row_obj[rme]] == 0);
+    bool any = false;
+#pragma unroll
+    for (int i = 0; i < kTile8; ++i)
+        any = any || (r0 + i < nrows && (!obj_status || obj_status[row_obj[r0 + i]] == 0));
+    if (!any) return;
+    f32x4 er[2], ez[2], ew[2];
+    if (kEpi && mine) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            er[h] = *(const f32x4 *)(cs.R + rme * ldo + c * 8 + 4 * h);
+            ez[h] = *(const f32x4 *)(Y + rme * ldy + c * 8 + 4 * h);
+            ew[h] = *(const f32x4 *)(cs.W + rme * cs.ldw + c * 8 + 4 * h);
+        }
+    }
+    float *sv = svals[wv];
+    const int64_t e0 = tptr[t], e1 = tptr[t + 1];
+    float acc[kTile8][8];
+#pragma unroll
+    for (int i = 0; i < kTile8; ++i)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[i][q] = 0.f;
+    Chunk8 ca, cb;
+    ca.load(tcol, vh, e0 + lane, e0 + lane < e1);
+    cb.load(tcol, vh, e0 + 64 + lane, e0 + 64 + lane < e1);
+    for (int64_t base = e0; base < e1; base += 128) {
+        t8_chunk<kBatch>(ca, base, e1, tcol, vh, sv, lane, g, c, NG, steps, Y, ldy, acc);
+        if (base + 64 < e1) t8_chunk<kBatch>(cb, base + 64, e1, tcol, vh, sv, lane, g, c, NG, steps, Y, ldy, acc);
+    }
+#pragma unroll
+    for (int i = 0; i < kTile8; ++i)
+        for (int d = G; d < 64; d <<= 1)
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc[i][q] += __shfl_xor(acc[i][q], d, 64);
+    if (!mine) return;
+    float a8[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        a8[q] = acc[0][q];
+#pragma unroll
+        for (int i = 1; i < kTile8; ++i)
+            if (g == i) a8[q] = acc[i][q];
+    }
+    if (kEpi) {
+        const int o = row_obj[rme];
+        const double f1 = cs.coef[(size_t)o * cs.stride + 2 * cs.step - 1];
+        const double f2 = cs.coef[(size_t)o * cs.stride + 2 * cs.step];
+        const double dv = (double)cs.dinv[rme];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            f32x4 rv1, dz1, w1;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double rv = (double)er[h][q] - dv * (double)a8[4 * h + q];
+                const double dz = f1 * (double)ez[h][q] + f2 * rv;
+                rv1[q] = (float)rv;
+                dz1[q] = (float)dz;
+                w1[q] = (float)((double)ew[h][q] + dz);
+            }
+            *(f32x4 *)(cs.R + rme * ldo + c * 8 + 4 * h) = rv1;
+            *(f32x4 *)(cs.dz_out + rme * ldo + c * 8 + 4 * h) = dz1;
+            *(f32x4 *)(cs.W + rme * cs.ldw + c * 8 + 4 * h) = w1;
+        }
+    } else {
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+            *(f32x4 *)(HY + rme * ldo + c * 8 + 4 * h) =
+                f32x4{a8[4 * h], a8[4 * h + 1], a8[4 * h + 2], a8[4 * h + 3]};
+    }
+}
+
+bool t8_ok(int m, int64_t ldy, int64_t ldo) {
+    return m % 8 == 0 && m >= 8 && m <= 64 && 64 % (m / 8) == 0 && ldy % 4 == 0 && ldo % 4 == 0;
+}
+
+template <bool kEpi>
+int launch_t8(ff_ctx *ctx, hipStream_t st, const RT8View &v, int sub, int m, const float *Y, int64_t ldy, float *HY,
+              int64_t ldo, const int *row_obj, const int *status, const ChebStep<float> &cs) {
+#define FF_T8(W, B, O)                                                                                  \
+    hipLaunchKernelGGL((spmm_t8_kernel<kEpi, W, B, O>), dim3(grid_for(v.ntiles, W)), dim3(64 * W), 0, st, \
+                       v.n, v.ntiles, v.tptr, v.tcol, v.vh, Y, ldy, HY, ldo, m, row_obj, status, cs)
+    switch (sub) {
+        case 1: FF_T8(4, 2, 1); break;
+        case 2: FF_T8(2, 4, 1); break;
+        default: FF_T8(2, 2, 1); break;
+    }
+#undef FF_T8
+    FF_CHECK_LAUNCH(ctx);
+    return FF_OK;
+}
+
+int spmm_h_t8(ff_ctx *ctx, hipStream_t st, const RT8View &v, int sub, int m, const float *Y, int64_t ldy, float *HY,
+              int64_t ldo, const int *row_obj, const int *status) {
+    FF_REQUIRE(ctx, v.vh != nullptr && t8_ok(m, ldy, ldo), "eight-row tiles: bad copy or block shape (m = %d)", m);
+    return launch_t8<false>(ctx, st, v, sub, m, Y, ldy, HY, ldo, row_obj, status, ChebStep<float>{});
+}
+
+int cheb_step_t8(ff_ctx *ctx, hipStream_t st, const RT8View &v, int sub, int m, const float *DZ, int64_t ld,
+                 const int *row_obj, const int *status, const ChebStep<float> &cs) {
+    FF_REQUIRE(ctx, v.vh != nullptr && row_obj != nullptr && t8_ok(m, ld, ld) && cs.ldw % 4 == 0,
+               "eight-row tiles: bad copy or block shape (m = %d)", m);
+    return launch_t8<true>(ctx, st, v, sub, m, DZ, ld, nullptr, ld, row_obj, status, cs);
+}
+
+static int fill_t8(ff_ctx *ctx, hipStream_t st, int64_t n, int64_t ntiles, const int64_t *row_ptr,
+                   const int32_t *col, const double *H, const int64_t *tptr, int32_t *tcol, float *vh) {
+    hipLaunchKernelGGL(rt_fill_h_kernel<kTile8>, dim3(grid_for(ntiles, 256)), dim3(256), 0, st, n, ntiles, row_ptr,
+                       col, H, tptr, tcol, vh);
+    FF_CHECK_LAUNCH(ctx);
+    return FF_OK;
+}
+
+int build_t8_ws(ff_ctx *ctx, hipStream_t st, int64_t n, const int64_t *row_ptr, const int32_t *col, const double *H,
+                RT8View *out) {
+    FF_REQUIRE(ctx, n > 0 && row_ptr && col && H && out, "bad arguments");
+    const int64_t ntiles = (n + kTile8 - 1) / kTile8;
+    int64_t *cnt = (int64_t *)ws_get(ctx, WS_RT8_CNT, (size_t)(ntiles + 1) * sizeof(int64_t));
+    int64_t *tptr = (int64_t *)ws_get(ctx, WS_RT8_PTR, (size_t)(ntiles + 1) * sizeof(int64_t));
+    if (!cnt || !tptr) return FF_ERR_OOM;
+    int64_t entries = 0;
+    int rc = build_ptr<kTile8>(ctx, st, n, row_ptr, col, cnt, tptr, ntiles, &entries);
+    if (rc) return rc;
+    const size_t ne = (size_t)std::max<int64_t>(entries, 1);
+    int32_t *tcol = (int32_t *)ws_get(ctx, WS_RT8_COL, ne * sizeof(int32_t));
+    float *vh = (float *)ws_get(ctx, WS_RT8_VAL, ne * kTile8 * sizeof(float));
+    if (!tcol || !vh) return FF_ERR_OOM;
+    if ((rc = fill_t8(ctx, st, n, ntiles, row_ptr, col, H, tptr, tcol, vh))) return rc;
+    out->n = n;
+    out->ntiles = ntiles;
+    out->entries = entries;
+    out->tptr = tptr;
+    out->tcol = tcol;
+    out->vh = vh;
     return FF_OK;
 }
 
@@ -395,13 +872,56 @@ int rowtiles_build(ff_ctx *ctx, int64_t n, const int64_t *row_ptr, const int32_t
                    const double *M, int precision, ff_rowtiles **out) {
     if (!ctx || !out) return FF_ERR_INVALID_ARG;
     *out = nullptr;
-    FF_REQUIRE(ctx, n > 0 && row_ptr && col && H && M, "bad arguments");
-    FF_REQUIRE(ctx, precision >= 0 && precision <= 2, "precision must be 0 (FP64), 1 (FP32) or 2 (both)");
+    FF_REQUIRE(ctx, n > 0 && row_ptr && col && H && (M || precision == 3), "bad arguments");
+    FF_REQUIRE(ctx, precision >= 0 && precision <= 3,
+               "precision must be 0 (FP64), 1 (FP32), 2 (both) or 3 (FP32 H only, eight-row tiles)");
     FF_HIP(ctx, hipSetDevice(ctx->device));
     hipStream_t st = ctx->stream;
     ff_rowtiles *h = new ff_rowtiles();
     h->device = ctx->device;
     h->stream = ctx->stream;
+    if (precision == 3) {
+        h->eight = 1;
+        const int64_t nt8 = (n + rt::kTile8 - 1) / rt::kTile8;
+        int64_t *cnt8 = nullptr, *tptr8 = nullptr;
+        int rc8 = FF_OK;
+        if (hipMalloc((void **)&cnt8, (size_t)(nt8 + 1) * sizeof(int64_t)) != hipSuccess ||
+            hipMalloc((void **)&tptr8, (size_t)(nt8 + 1) * sizeof(int64_t)) != hipSuccess) {
+            (void)hipGetLastError();
+            rc8 = set_error(ctx, FF_ERR_OOM, "row-tile allocation failed");
+        }
+        h->mem[0] = tptr8;
+        int64_t ent8 = 0;
+        if (!rc8) rc8 = rt::build_ptr<rt::kTile8>(ctx, st, n, row_ptr, col, cnt8, tptr8, nt8, &ent8);
+        if (cnt8) (void)hipFree(cnt8);
+        int32_t *tcol8 = nullptr;
+        float *vh = nullptr;
+        if (!rc8) {
+            const size_t ne = (size_t)std::max<int64_t>(ent8, 1);
+            if (hipMalloc((void **)&tcol8, ne * sizeof(int32_t)) != hipSuccess ||
+                hipMalloc((void **)&vh, ne * rt::kTile8 * sizeof(float)) != hipSuccess) {
+                (void)hipGetLastError();
+                rc8 = set_error(ctx, FF_ERR_OOM, "row-tile allocation of %lld entries failed", (long long)ent8);
+            }
+            h->mem[1] = tcol8;
+            h->mem[2] = vh;
+        }
+        if (!rc8) rc8 = rt::fill_t8(ctx, st, n, nt8, row_ptr, col, H, tptr8, tcol8, vh);
+        if (!rc8 && hipStreamSynchronize(st) != hipSuccess)
+            rc8 = set_error(ctx, FF_ERR_HIP, "row-tile build failed");
+        if (rc8) {
+            rowtiles_destroy(h);
+            return rc8;
+        }
+        h->v8.n = n;
+        h->v8.ntiles = nt8;
+        h->v8.entries = ent8;
+        h->v8.tptr = tptr8;
+        h->v8.tcol = tcol8;
+        h->v8.vh = vh;
+        *out = h;
+        return FF_OK;
+    }
     const int64_t ntiles = (n + rt::kTileRows - 1) / rt::kTileRows;
     auto alloc = [&](int slot, size_t bytes) -> void * {
         void *p = nullptr;
@@ -433,7 +953,7 @@ int rowtiles_build(ff_ctx *ctx, int64_t n, const int64_t *row_ptr, const int32_t
         if (!tcol || (precision != 0 && !v32) || (precision != 1 && !v64))
             rc = set_error(ctx, FF_ERR_OOM, "row-tile allocation of %lld entries failed", (long long)entries);
     }
-    if (!rc) rc = rt::fill(ctx, st, n, ntiles, row_ptr, col, H, M, tptr, tcol, v32, v64);
+    if (!rc) rc = rt::fill(ctx, st, n, ntiles, row_ptr, col, H, M, tptr, entries, tcol, v32, v64);
     if (!rc && hipStreamSynchronize(st) != hipSuccess) rc = set_error(ctx, FF_ERR_HIP, "row-tile build failed");
     if (rc) {
         rowtiles_destroy(h);
@@ -452,8 +972,8 @@ int rowtiles_build(ff_ctx *ctx, int64_t n, const int64_t *row_ptr, const int32_t
 
 int rowtiles_info(const ff_rowtiles *rt, int64_t *ntiles, int64_t *entries) {
     if (!rt) return FF_ERR_INVALID_ARG;
-    if (ntiles) *ntiles = rt->v.ntiles;
-    if (entries) *entries = rt->v.entries;
+    if (ntiles) *ntiles = rt->eight ? rt->v8.ntiles : rt->v.ntiles;
+    if (entries) *entries = rt->eight ? rt->v8.entries : rt->v.entries;
     return FF_OK;
 }
 
@@ -462,6 +982,15 @@ int spmm_rowtiles(ff_ctx *ctx, const ff_rowtiles *rt, int precision, int m, cons
     if (!ctx || !rt) return FF_ERR_INVALID_ARG;
     FF_REQUIRE(ctx, Y && HY, "required pointer is NULL");
     FF_REQUIRE(ctx, precision == 0 || precision == 1, "precision must be 0 or 1");
+    if (rt->eight) {
+        FF_REQUIRE(ctx, precision == 1 && !MY, "the eight-row copy forms H Y alone in FP32 (MY must be NULL)");
+        FF_REQUIRE(ctx, rt::t8_ok(m, ld_y, ld_out) && ld_y >= m && ld_out >= m,
+                   "block width %d / leading dimensions not supported by the eight-row kernel", m);
+        FF_REQUIRE(ctx, sub >= 0 && sub < rt::kSubs, "launch shape %d out of range", sub);
+        FF_HIP(ctx, hipSetDevice(ctx->device));
+        return rt::spmm_h_t8(ctx, ctx->stream, rt->v8, sub, m, (const float *)Y, ld_y, (float *)HY, ld_out, nullptr,
+                             nullptr);
+    }
     const int vn = precision ? 4 : 2;
     FF_REQUIRE(ctx, m > 0 && m % vn == 0 && m / vn <= 64, "block width %d not supported", m);
     FF_REQUIRE(ctx, ld_y >= m && ld_out >= m && ld_y % vn == 0 && ld_out % vn == 0, "bad leading dimension");

@@ -75,7 +75,9 @@ def lib():
         "ff_ctx_create": (i32, [P(vp), i32, vp]),
         "ff_ctx_destroy": (None, [vp]),
         "ff_last_error": (ctypes.c_char_p, [vp]),
-        "ff_ctx_stage_times": (i32, [vp, P(f64), P(f64), P(f64), P(f64), P(f64)]),
+        "ff_ctx_set_stage_timing": (i32, [vp, i32]),
+        "ff_ctx_stage_times": (i32, [vp, i32, P(f64), P(i64)]),
+        "ff_stage_name": (ctypes.c_char_p, [i32]),
         "build_neighbors": (i32, [vp, i64, vp, i64, vp, f64, P(ff_grid), vp, vp, vp, i64, vp, vp, i64,
                                   P(i64)]),
         "rkpm_shape": (i32, [vp, i64, vp, i64, vp, vp, vp, i64, f64, i32, vp, vp, vp, P(i64)]),
@@ -140,6 +142,21 @@ class Context:
     def check(self, rc: int):
         if rc != 0:
             raise FFError(rc, lib().ff_last_error(self.h).decode())
+
+    def set_stage_timing(self, enable: bool):
+        """Per-stage HIP-event timing of the eigensolver (off by default)."""
+        self.check(lib().ff_ctx_set_stage_timing(self.h, int(bool(enable))))
+
+    def stage_times(self):
+        """{stage name: (milliseconds, launches)} of the last eigenmodes call."""
+        L = lib()
+        n = L.ff_ctx_stage_times(self.h, 0, None, None)
+        if n < 0:
+            self.check(n)
+        ms = (ctypes.c_double * n)()
+        la = (ctypes.c_int64 * n)()
+        L.ff_ctx_stage_times(self.h, n, ms, la)
+        return {L.ff_stage_name(i).decode(): (ms[i], la[i]) for i in range(n)}
 
     def close(self):
         if self.h:

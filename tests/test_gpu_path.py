@@ -198,6 +198,37 @@ def test_rowtiles_spmm(oracle, ctx, ff, precision):
     rt.close()
 
 
+def test_rowtiles_eight_row_h_copy(oracle, ctx, ff):
+    """The preconditioner's H-only copy in tiles of eight rows (ragged last tile): H Y in
+    FP32 accumulation, every launch shape and the block widths the kernel takes; other
+    forms are rejected."""
+    c = synth.random_cloud(2503, seed=29, hetero=True)
+    P = oracle.pipeline(c)
+    A = ff.assemble_cloud(ctx, dev(c.xyz), dev(c.vol), dev(c.lam), dev(c.mu), c.h)
+    rt = ff.RowTiles(ctx, A.n, A.row_ptr, A.col, A.H, A.M, precision=3)
+    ntiles, entries = rt.info()
+    assert ntiles == (c.n + 7) // 8
+    rl = np.diff(P.row_ptr)
+    assert rl.max() <= entries <= rl.sum()
+    # longest rounding chain: a lane group's share of a tile's entries (at most 8 rows, at
+    # least 8 groups), the butterfly's additions, the rounding of the values and of Y
+    eps = (rl.max() + 8) * 2.0 ** -24
+    for m in (8, 16, 32, 64):
+        Y = np.random.default_rng(m).standard_normal((c.n, m))
+        refH = oracle.spmm(P.row_ptr, P.col, P.H, Y)
+        absH = oracle.spmm(P.row_ptr, P.col, np.abs(P.H), np.abs(Y))
+        for sub in range(3):
+            HO, none = rt.spmm(dev(Y, torch.float32), 1, sub, h_only=True)
+            assert none is None
+            assert np.all(np.abs(host(HO) - refH) <= eps * absH + 1e-300), (m, sub)
+    Y = dev(np.ones((c.n, 24)), torch.float32)
+    with pytest.raises(ff.FFError):
+        rt.spmm(Y, 1, 0, h_only=True)                      # 24 / 8 = 3 does not divide 64
+    with pytest.raises(ff.FFError):
+        rt.spmm(dev(np.ones((c.n, 32)), torch.float32), 1, 0)   # MY requested
+    rt.close()
+
+
 def test_philox_known_answers(ctx, ff):
     """Known-answer vectors of Philox-4x32-10 (Salmon et al., SC'11, Random123 distribution)."""
     import os
@@ -275,7 +306,7 @@ def test_eigenmodes_given_start_block(oracle, ctx, ff):
 def test_chebyshev_degree_is_validated(ctx, ff):
     c = synth.cube_lattice()
     A = ff.assemble_cloud(ctx, dev(c.xyz), dev(c.vol), dev(c.lam), dev(c.mu), c.h)
-    for bad in (1, 9, -2):
+    for bad in (1, 17, -2):
         with pytest.raises(ff.FFError):
             ff.eigenmodes(ctx, c.n, A.row_ptr, A.col, A.H, A.M, A.hm32, k=8, precond=2, precond_degree=bad)
     with pytest.raises(ff.FFError):
@@ -289,3 +320,29 @@ def test_not_converged_still_returns(ctx, ff):
                                       max_iter=3, allow_unconverged=True)
     assert info["status"] == ff.FF_ERR_NOT_CONVERGED
     assert np.all(np.isfinite(lam)) and np.all(res > 0)
+
+
+def test_stage_timing(ctx, ff):
+    """Per-stage HIP-event times: off by default (only the total), on they cover every
+    stage, the Chebyshev products count degree - 1 launches per body pass, and the
+    stage sums stay within the call's wall time."""
+    c = synth.cube_lattice()
+    A = ff.assemble_cloud(ctx, dev(c.xyz), dev(c.vol), dev(c.lam), dev(c.mu), c.h)
+    run = lambda: ff.eigenmodes(ctx, c.n, A.row_ptr, A.col, A.H, A.M, A.hm32, k=8, precision=1, tol=1e-6,
+                                precond=2, precond_degree=3)
+    run()
+    st = ctx.stage_times()
+    assert set(st) == {"spmm", "precond_product", "precond_other", "gram", "rayleigh_ritz", "update", "resid",
+                       "total"}
+    assert all(v == (0.0, 0) for k, v in st.items() if k != "total") and st["total"][0] > 0
+    ctx.set_stage_timing(True)
+    try:
+        lam, W, res, info = run()
+        st = ctx.stage_times()
+    finally:
+        ctx.set_stage_timing(False)
+    its = info["iters_fp32"] + info["iters_fp64"]
+    for k in ("spmm", "precond_product", "precond_other", "gram", "rayleigh_ritz", "update", "resid"):
+        assert st[k][0] > 0 and st[k][1] > 0, k
+    assert st["precond_product"][1] % 2 == 0 and st["precond_product"][1] >= 2 * its
+    assert sum(v[0] for k, v in st.items() if k != "total") <= st["total"][0] * 1.01
