@@ -190,7 +190,7 @@ typedef struct {
     int use_graph;      /* 1 = replay one captured hipGraph per iteration (a call on the null
                            stream runs on a private stream of the context) */
     int refresh_every;  /* recompute HX, MX explicitly every this many iterations (0 = auto) */
-    int precond_degree; /* Chebyshev degree d for precond = 2 (0 = default 4; 2..16); d - 1 products with H per
+    int precond_degree; /* Chebyshev degree d for precond = 2 (0 = default 8; 2..16); d - 1 products with H per
                            iteration */
 } ff_eig_params;
 
@@ -297,17 +297,20 @@ int rayleigh_ritz(ff_ctx *ctx, int w, int m, const double *G, double tau, double
  *
  * rowtiles_build: from the FP64 CSR of assemble_HM (rows with ascending
  *   columns); precision 1 keeps FP32 values (rounded from H, M), 0 FP64, 2
- *   both; 3 keeps only H, in FP32, in tiles of eight rows (the copy the
- *   Chebyshev-Jacobi preconditioner of eigenmodes runs on; M may be NULL).
+ *   both; 3 and 4 keep only H, in FP32, in tiles of eight and of sixteen
+ *   rows (the copies the Chebyshev-Jacobi preconditioner of eigenmodes runs
+ *   on: sixteen rows on MFMA where the block width allows, eight rows
+ *   otherwise; M may be NULL).
  *   Device memory owned by the handle until rowtiles_destroy (destroy it
  *   before its context). The CSR may be freed afterwards.
  * spmm_rowtiles: [HY, MY] = [H, M] Y as spmm_hm, on the copy; sub selects a
  *   launch shape (0 .. 2). With MY NULL only HY = H Y is formed, the product
  *   the Chebyshev-Jacobi preconditioner of eigenmodes runs: at precision 1 it
  *   accumulates in FP32 (an approximate operator is all a preconditioner
- *   needs), at precision 0 in FP64. A handle built with precision 3 takes
- *   only this form, at precision 1, with m % 8 == 0, 8 <= m <= 64 and leading
- *   dimensions that are multiples of 4.
+ *   needs), at precision 0 in FP64. A handle built with precision 3 or 4
+ *   takes only this form, at precision 1, with leading dimensions that are
+ *   multiples of 4 and m % 8 == 0, 8 <= m <= 64, 64 % (m / 8) == 0 (eight
+ *   rows) or m in {4, 8, 12, 16, 32, 64} (sixteen rows).
  */
 typedef struct ff_rowtiles ff_rowtiles;
 int rowtiles_build(ff_ctx *ctx, int64_t n, const int64_t *row_ptr, const int32_t *col, const double *H,

@@ -29,7 +29,8 @@ enum WsSlot {
     WS_MLP0, WS_MLP1, WS_MLP2, WS_MLP3, WS_MLP4, WS_MLP5, WS_MLP6, WS_MLP7,
     WS_RT_CNT, WS_RT_PTR, WS_RT_COL, WS_RT_VAL32, WS_RT_VAL64,   // row-tile SpMM copies
     WS_CHEB0, WS_CHEB1, WS_CHEB2, WS_CHEB3, WS_CHEB4,             // Chebyshev-Jacobi work
-    WS_RT8_CNT, WS_RT8_PTR, WS_RT8_COL, WS_RT8_VAL,               // eight-row H-only tile copy
+    WS_RT8_CNT, WS_RT8_PTR, WS_RT8_COL, WS_RT8_VAL, WS_RT8_VALM,  // eight-row tile copy (H, and M)
+    WS_RT16_CNT, WS_RT16_PTR, WS_RT16_COL, WS_RT16_VAL,           // sixteen-row H-only tile copy
     WS_COUNT
 };
 

@@ -1613,7 +1613,7 @@ __global__ void diag_inv_bs_kernel(int64_t n, const int64_t *row_ptr, const int3
 // ---------------------------------------------------------------------------
 
 constexpr int kChebCoef = 32;                  // per-object coefficient stride (degree <= 16)
-constexpr int kChebDefault = 4;                // degree when the caller passes 0
+constexpr int kChebDefault = 8;                // degree when the caller passes 0
 
 // Gershgorin bound of D^-1/2 H D^-1/2 per row: sum_j |H_ij| / sqrt(H_ii H_jj), one wavefront per row
 __global__ void gersh_row_kernel(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *H,
@@ -1754,11 +1754,14 @@ static const char *kVariantNames[] = {"waves4_unroll2_xcd", "waves4_unroll4_xcd"
                                       "chunk64_waves4_batch4", "chunk64_waves2_batch8_occ6",
                                       "chunk64_waves4_batch4_occ8", "chunk64_waves2_batch16",
                                       "rowtile4_waves4_batch4", "rowtile4_waves2_batch8",
-                                      "rowtile4_waves4_batch4_occ4"};
-constexpr int kNumVariants = 16;
-constexpr int kRowTileBase = 13;               // variants from here on run on the row-tile copy
+                                      "rowtile4_waves4_batch4_occ4", "rowtile8_mfma64_waves4_batch8",
+                                      "rowtile8_mfma64_waves2_batch8", "rowtile8_mfma64_waves4_batch4_occ6"};
+constexpr int kNumVariants = 19;
+constexpr int kRowTileBase = 13;               // variants from here on run on a row-tile copy
+constexpr int kRowTile8Base = 16;              // from here on: the eight-row [H, M] copy on FP64 MFMA (FP32 blocks)
 constexpr int kCsrVariant = 11;                // fastest variant on the CSR itself
-constexpr int kDefaultVariant = 14;    // fastest untuned choice on 10^5-10^6-row RKPM matrices (row tiles)
+constexpr int kDefaultVariant64 = 14;  // fastest untuned FP64 choice on 10^5-10^6-row RKPM matrices (row tiles)
+constexpr int kDefaultVariant32 = 16;  // fastest untuned FP32 choice (eight-row tiles, MFMA)
 
 inline int rt_spmm(ff_ctx *ctx, hipStream_t st, const rt::RTView &v, int sub, int m, const float *Y, int64_t ldy,
                    float *HY, float *MY, int64_t ldo, const int *row_obj, const int *status) {
@@ -1769,10 +1772,23 @@ inline int rt_spmm(ff_ctx *ctx, hipStream_t st, const rt::RTView &v, int sub, in
     return rt::spmm64(ctx, st, v, sub, m, Y, ldy, HY, MY, ldo, row_obj, status);
 }
 
+inline int rt_hm8(ff_ctx *ctx, hipStream_t st, const rt::RT8View &v, int sub, int m, const float *Y, int64_t ldy,
+                  float *HY, float *MY, int64_t ldo, const int *row_obj, const int *status) {
+    return rt::spmm_hm8(ctx, st, v, sub, m, Y, ldy, HY, MY, ldo, row_obj, status);
+}
+inline int rt_hm8(ff_ctx *ctx, hipStream_t, const rt::RT8View &, int, int, const double *, int64_t, double *,
+                  double *, int64_t, const int *, const int *) {
+    return set_error(ctx, FF_ERR_INVALID_ARG, "the eight-row MFMA SpMM variants take FP32 blocks only");
+}
+
 template <typename T>
 int launch_spmm(ff_ctx *ctx, hipStream_t st, int variant, int64_t nrows, const int64_t *row_ptr, const int32_t *col,
                 HMPair<T> hm, const T *Y, int64_t ldy, T *HY, T *MY, int64_t ldo, int m, const int *row_obj,
-                const int *status, const rt::RTView *rtv) {
+                const int *status, const rt::RTView *rtv, const rt::RT8View *rt8 = nullptr) {
+    if (variant >= kRowTile8Base) {
+        FF_REQUIRE(ctx, rt8 != nullptr && rt8->vm != nullptr, "eight-row SpMM variant without an eight-row copy");
+        return rt_hm8(ctx, st, *rt8, variant - kRowTile8Base, m, Y, ldy, HY, MY, ldo, row_obj, status);
+    }
     if (variant >= kRowTileBase) {
         FF_REQUIRE(ctx, rtv != nullptr, "row-tile SpMM variant without a row-tile copy");
         return rt_spmm(ctx, st, *rtv, variant - kRowTileBase, m, Y, ldy, HY, MY, ldo, row_obj, status);
@@ -1826,10 +1842,12 @@ inline int rt_cheb_step(ff_ctx *ctx, hipStream_t st, const rt::RTView &v, int su
 template <typename T>
 int launch_spmm_h(ff_ctx *ctx, hipStream_t st, int variant, int64_t nrows, const int64_t *row_ptr, const int32_t *col,
                   HMPair<T> hm, const T *Y, int64_t ldy, T *HY, T *MS, int64_t ldo, int m, const int *row_obj,
-                  const int *status, const rt::RTView *rtv) {
-    if (variant >= kRowTileBase && rtv && (sizeof(T) == 4 ? rtv->v32 != nullptr : rtv->v64 != nullptr))
+                  const int *status, const rt::RTView *rtv, const rt::RT8View *rt8 = nullptr) {
+    if (variant >= kRowTileBase && variant < kRowTile8Base && rtv &&
+        (sizeof(T) == 4 ? rtv->v32 != nullptr : rtv->v64 != nullptr))
         return rt_spmm_h(ctx, st, *rtv, variant - kRowTileBase, m, Y, ldy, HY, ldo, row_obj, status);
-    return launch_spmm<T>(ctx, st, variant, nrows, row_ptr, col, hm, Y, ldy, HY, MS, ldo, m, row_obj, status, rtv);
+    return launch_spmm<T>(ctx, st, variant, nrows, row_ptr, col, hm, Y, ldy, HY, MS, ldo, m, row_obj, status, rtv,
+                          rt8);
 }
 
 template <typename T> struct Prec;
@@ -1856,6 +1874,7 @@ struct Solver {
     int var32 = 0, var64 = 0;
     rt::RTView rtv;                                // row-tile copy when a row-tile variant is selected
     rt::RT8View rt8;                               // eight-row H-only copy for the FP32 preconditioner
+    rt::RT16View rt16;                             // sixteen-row H-only copy (MFMA form), preferred
     bool jacobi = false;
     int cheb = 0;                                  // Chebyshev-Jacobi degree (0: plain Jacobi or none)
     double *cheb_coef = nullptr;                   // [n_obj][kChebCoef]
@@ -1918,7 +1937,7 @@ int stage_spmm(Solver &s, T *S, T *HS, T *MS, int slot) {
     const int64_t ld = 3 * (int64_t)s.m;
     return launch_spmm<T>(s.ctx, s.st, sizeof(T) == 4 ? s.var32 : s.var64, s.N, s.row_ptr, s.col, hm_of<T>(s),
                           S + slot * s.m, ld, HS + slot * s.m, MS + slot * s.m, ld, s.m, s.row_obj, s.status,
-                          &s.rtv);
+                          &s.rtv, &s.rt8);
 }
 
 // the four Rayleigh-Ritz stages on every active object (LDS limits set by rr_prepare)
@@ -2027,7 +2046,7 @@ int stage_precond(Solver &s, T *S) {
     }
     StageMark mark(s.ctx, s.st, FF_STAGE_PRECOND_PRODUCT, s.cheb - 1);
     const int var = sizeof(T) == 4 ? s.var32 : s.var64;
-    if (sizeof(T) == 4 && s.rt8.vh) {
+    if (sizeof(T) == 4 && ((s.rt8.vh && rt::t8_ok(s.m, s.m, s.m)) || s.rt16.vh)) {
         T *buf[2] = {DZ, HD};
         for (int step = 1; step < s.cheb; ++step) {
             rt::ChebStep<float> cs;
@@ -2039,8 +2058,11 @@ int stage_precond(Solver &s, T *S) {
             cs.dz_out = (float *)buf[step & 1];
             cs.W = (float *)(S + s.m);
             cs.ldw = ld;
-            const int rc = rt::cheb_step_t8(s.ctx, s.st, s.rt8, 0, s.m, (const float *)buf[(step - 1) & 1], s.m,
-                                            s.row_obj, s.status, cs);
+            const int rc = s.rt16.vh ? rt::cheb_step_t16(s.ctx, s.st, s.rt16, 0, s.m,
+                                                         (const float *)buf[(step - 1) & 1], s.m, s.row_obj, s.status,
+                                                         cs)
+                                     : rt::cheb_step_t8(s.ctx, s.st, s.rt8, 0, s.m, (const float *)buf[(step - 1) & 1],
+                                                        s.m, s.row_obj, s.status, cs);
             if (rc) return rc;
         }
         return FF_OK;
@@ -2066,7 +2088,7 @@ int stage_precond(Solver &s, T *S) {
     }
     for (int step = 1; step < s.cheb; ++step) {
         int rc = launch_spmm_h<T>(s.ctx, s.st, var, s.N, s.row_ptr, s.col, hm_of<T>(s),
-                                  DZ, s.m, HD, MD, s.m, s.m, s.row_obj, s.status, &s.rtv);
+                                  DZ, s.m, HD, MD, s.m, s.m, s.row_obj, s.status, &s.rtv, &s.rt8);
         if (rc) return rc;
         hipLaunchKernelGGL(cheb_step_kernel<T>, dim3(grid_for(cnt, 256)), dim3(256), 0, s.st, s.N, s.m, ld, step,
                            s.row_obj, s.status, s.cheb_coef, dinv_of<T>(s), HD, S, Rb, DZ);
@@ -2122,10 +2144,12 @@ int cheb_setup(Solver &s, int degree, uint64_t seed) {
     FF_CHECK_LAUNCH(ctx);
     int rc;
     auto hprod = [&]() -> int {
-        if (sizeof(T) == 4 && s.rt8.vh)
+        if (sizeof(T) == 4 && s.rt16.vh)
+            return rt::spmm_h_t16(ctx, s.st, s.rt16, 0, 8, (const float *)Y, 8, (float *)HY, 8, s.row_obj, s.status);
+        if (sizeof(T) == 4 && s.rt8.vh)       // the power steps run at m = 8, which the eight-row kernel takes
             return rt::spmm_h_t8(ctx, s.st, s.rt8, 0, 8, (const float *)Y, 8, (float *)HY, 8, s.row_obj, s.status);
         return launch_spmm_h<T>(ctx, s.st, var, N, s.row_ptr, s.col, hm_of<T>(s), Y, 8, HY, MY, 8, 8, s.row_obj,
-                                s.status, &s.rtv);
+                                s.status, &s.rtv, &s.rt8);
     };
     for (int it = 0; it < 30; ++it) {
         if ((rc = hprod())) return rc;
@@ -2373,7 +2397,7 @@ std::string tune_key(int64_t n, int64_t nnz, int m, int precision) {
 
 int lookup_variant(ff_ctx *ctx, int64_t n, int64_t nnz, int m, int precision) {
     auto it = ctx->tuned.find(tune_key(n, nnz, m, precision));
-    return it == ctx->tuned.end() ? kDefaultVariant : it->second;
+    return it == ctx->tuned.end() ? (precision ? kDefaultVariant32 : kDefaultVariant64) : it->second;
 }
 
 int solve(ff_ctx *ctx, int n_obj, const int64_t *obj_off, const int64_t *row_ptr, const int32_t *col, const double *H,
@@ -2430,9 +2454,18 @@ int solve(ff_ctx *ctx, int n_obj, const int64_t *obj_off, const int64_t *row_ptr
         // the mixed path's FP64 phase is normally the certification alone: it keeps the CSR
         // (kCsrVariant) rather than paying for an FP64 row-tile copy
         if (p->precision == 1 && s.var64 >= kRowTileBase) s.var64 = kCsrVariant;
-        const int want32 = p->precision == 1 && s.var32 >= kRowTileBase, want64 = s.var64 >= kRowTileBase;
+        // the FP64 blocks never take the eight-row MFMA variants (FP32 only); nor do block widths they lack
+        if (s.var64 >= kRowTile8Base) s.var64 = kDefaultVariant64;
+        if (s.var32 >= kRowTile8Base && !rt::hm8_ok(m, 3 * (int64_t)m, 3 * (int64_t)m)) s.var32 = kDefaultVariant64;
+        const int want32 = p->precision == 1 && s.var32 >= kRowTileBase && s.var32 < kRowTile8Base,
+                  want64 = s.var64 >= kRowTileBase;
         if (want32 || want64) {
             int rc0 = rt::build_ws(ctx, s.st, s.N, row_ptr, col, H, M, want32, want64, &s.rtv);
+            if (rc0) return rc0;
+        }
+        if (p->precision == 1 && s.var32 >= kRowTile8Base) {
+            // one eight-row copy with H and M serves the fused products and the preconditioner
+            int rc0 = rt::build_t8_ws(ctx, s.st, s.N, row_ptr, col, H, &s.rt8, M);
             if (rc0) return rc0;
         }
     }
@@ -2441,8 +2474,13 @@ int solve(ff_ctx *ctx, int n_obj, const int64_t *obj_off, const int64_t *row_ptr
     if (p->precond == 2) {
         const int degree = p->precond_degree > 0 ? p->precond_degree : kChebDefault;
         // the FP32 preconditioner's products run on tiles of eight rows when the block shape allows
+        // (the sixteen-row MFMA form measured slower than the eight-row one: 1.38 against 1.23 ms per
+        // product at 1M particles, m = 32; it serves the widths the eight-row kernel does not take)
         if (p->precision == 1 && s.var32 >= kRowTileBase && rt::t8_ok(s.m, s.m, s.m)) {
-            rc = rt::build_t8_ws(ctx, s.st, s.N, row_ptr, col, H, &s.rt8);
+            if (!s.rt8.vh) rc = rt::build_t8_ws(ctx, s.st, s.N, row_ptr, col, H, &s.rt8);
+            if (rc) return rc;
+        } else if (p->precision == 1 && s.var32 >= kRowTileBase && rt::t16_ok(s.m, s.m, s.m)) {
+            rc = rt::build_t16_ws(ctx, s.st, s.N, row_ptr, col, H, &s.rt16);
             if (rc) return rc;
         }
         rc = p->precision == 1 ? cheb_setup<float>(s, degree, p->seed) : cheb_setup<double>(s, degree, p->seed);
@@ -2606,7 +2644,14 @@ extern "C" int spmm_hm(ff_ctx *ctx, int64_t n, const int64_t *row_ptr, const int
     FF_REQUIRE(ctx, v >= 0 && v < kNumVariants, "variant %d out of range", v);
     // a row-tile variant builds its copy of the matrix for this call (rowtiles_build keeps one)
     rt::RTView view;
-    if (v >= kRowTileBase) {
+    rt::RT8View view8;
+    if (v >= kRowTile8Base) {
+        FF_REQUIRE(ctx, precision == 1, "variant %d (%s) takes FP32 blocks only", v, kVariantNames[v]);
+        FF_REQUIRE(ctx, H && M, "row-tile variants need H and M");
+        FF_REQUIRE(ctx, rt::hm8_ok(m, ld_y, ld_out), "variant %d takes m in {4, 8, 12, 16, 32, 64}, m = %d", v, m);
+        int rc = rt::build_t8_ws(ctx, ctx->stream, n, row_ptr, col, H, &view8, M);
+        if (rc) return rc;
+    } else if (v >= kRowTileBase) {
         FF_REQUIRE(ctx, H && M, "row-tile variants need H and M");
         int rc = rt::build_ws(ctx, ctx->stream, n, row_ptr, col, H, M, precision, !precision, &view);
         if (rc) return rc;
@@ -2615,7 +2660,7 @@ extern "C" int spmm_hm(ff_ctx *ctx, int64_t n, const int64_t *row_ptr, const int
         FF_REQUIRE(ctx, hm32 != nullptr || v >= kRowTileBase, "hm32 is NULL");
         return launch_spmm<float>(ctx, ctx->stream, v, n, row_ptr, col, HMPair<float>{(const float2 *)hm32},
                                   (const float *)Y, ld_y, (float *)HY, (float *)MY, ld_out, m, nullptr, nullptr,
-                                  &view);
+                                  &view, &view8);
     }
     FF_REQUIRE(ctx, H && M, "H or M is NULL");
     return launch_spmm<double>(ctx, ctx->stream, v, n, row_ptr, col, HMPair<double>{H, M}, (const double *)Y, ld_y,
@@ -2679,19 +2724,26 @@ extern "C" int spmm_autotune(ff_ctx *ctx, int64_t n, const int64_t *row_ptr, con
     int best = 0;
     double bms = 1e30;
     rt::RTView view;
-    int have_view = 0;
+    rt::RT8View view8;
+    int have_view = 0, have_view8 = 0;
     for (int v = 0; v < kNumVariants; ++v) {
-        if (v >= kRowTileBase && !have_view) {
+        if (v >= kRowTile8Base && (!precision || !rt::hm8_ok(m, m, m))) continue;
+        if (v >= kRowTileBase && v < kRowTile8Base && !have_view) {
             int rc0 = rt::build_ws(ctx, ctx->stream, n, row_ptr, col, H, M, precision, !precision, &view);
             if (rc0) return rc0;
             have_view = 1;
+        }
+        if (v >= kRowTile8Base && !have_view8) {
+            int rc0 = rt::build_t8_ws(ctx, ctx->stream, n, row_ptr, col, H, &view8, M);
+            if (rc0) return rc0;
+            have_view8 = 1;
         }
         auto run = [&]() -> int {
             if (precision)
                 return launch_spmm<float>(ctx, ctx->stream, v, n, row_ptr, col,
                                           HMPair<float>{(const float2 *)hm32}, (const float *)buf, m,
                                           (float *)(buf + (size_t)n * m * esz), (float *)(buf + 2 * (size_t)n * m * esz),
-                                          m, m, nullptr, nullptr, &view);
+                                          m, m, nullptr, nullptr, &view, &view8);
             return launch_spmm<double>(ctx, ctx->stream, v, n, row_ptr, col, HMPair<double>{H, M},
                                        (const double *)buf, m, (double *)(buf + (size_t)n * m * esz),
                                        (double *)(buf + 2 * (size_t)n * m * esz), m, m, nullptr, nullptr, &view);

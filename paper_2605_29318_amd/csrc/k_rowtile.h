@@ -57,20 +57,46 @@ int cheb_step64(ff_ctx *ctx, hipStream_t st, const RTView &v, int sub, int m, co
 // H-only FP32 copy in tiles of eight rows (the preconditioner's products):
 // vh[entry][8] holds the H values of the tile's eight rows.
 constexpr int kTile8 = 8;
+constexpr int kHSubs = 3;            // launch shapes of the H-only kernels
 struct RT8View {
     int64_t n = 0, ntiles = 0, entries = 0;
     const int64_t *tptr = nullptr;   // [ntiles + 1]
     const int32_t *tcol = nullptr;   // [entries]
     const float *vh = nullptr;       // [entries][8]
+    const float *vm = nullptr;       // [entries][8] M values, when built with M
 };
 int build_t8_ws(ff_ctx *ctx, hipStream_t st, int64_t n, const int64_t *row_ptr, const int32_t *col, const double *H,
-                RT8View *out);
+                RT8View *out, const double *M = nullptr);
 // block widths the eight-row kernels take: m % 8 == 0, 8 <= m <= 64, 16-byte aligned rows
 bool t8_ok(int m, int64_t ldy, int64_t ldo);
 int spmm_h_t8(ff_ctx *ctx, hipStream_t st, const RT8View &v, int sub, int m, const float *Y, int64_t ldy, float *HY,
               int64_t ldo, const int *row_obj, const int *status);
 int cheb_step_t8(ff_ctx *ctx, hipStream_t st, const RT8View &v, int sub, int m, const float *DZ, int64_t ld,
                  const int *row_obj, const int *status, const ChebStep<float> &cs);
+
+// H-only FP32 copy in tiles of sixteen rows, for the MFMA form of the
+// preconditioner's products: vh[entry][16].
+constexpr int kTile16 = 16;
+struct RT16View {
+    int64_t n = 0, ntiles = 0, entries = 0;
+    const int64_t *tptr = nullptr;   // [ntiles + 1]
+    const int32_t *tcol = nullptr;   // [entries]
+    const float *vh = nullptr;       // [entries][16]
+};
+int build_t16_ws(ff_ctx *ctx, hipStream_t st, int64_t n, const int64_t *row_ptr, const int32_t *col, const double *H,
+                 RT16View *out);
+// block widths the sixteen-row kernels take: m in {4, 8, 12, 16, 32, 64}, 16-byte aligned rows
+bool t16_ok(int m, int64_t ldy, int64_t ldo);
+int spmm_h_t16(ff_ctx *ctx, hipStream_t st, const RT16View &v, int sub, int m, const float *Y, int64_t ldy, float *HY,
+               int64_t ldo, const int *row_obj, const int *status);
+int cheb_step_t16(ff_ctx *ctx, hipStream_t st, const RT16View &v, int sub, int m, const float *DZ, int64_t ld,
+                  const int *row_obj, const int *status, const ChebStep<float> &cs);
+
+// [HY, MY] = [H, M] Y (FP32 blocks, FP64 accumulation on FP64 MFMA) on an
+// eight-row copy built with M; m in {4, 8, 12, 16, 32, 64}; sub 0..2.
+bool hm8_ok(int m, int64_t ldy, int64_t ldo);
+int spmm_hm8(ff_ctx *ctx, hipStream_t st, const RT8View &v, int sub, int m, const float *Y, int64_t ldy, float *HY,
+             float *MY, int64_t ldo, const int *row_obj, const int *status);
 
 // HY = H Y alone, for the preconditioner: FP32 accumulation on the FP32 copy,
 // FP64 on the FP64 copy.

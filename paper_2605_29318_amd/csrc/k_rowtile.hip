@@ -6,9 +6,10 @@
 struct ff_rowtiles {
     int device = 0;
     hipStream_t stream = nullptr;                  // the context's stream, kept for destruction
-    int eight = 0;                                 // 1: the H-only copy in tiles of eight rows (v8)
+    int hrows = 0;                                 // 8 or 16: an H-only copy in tiles of that many rows
     ff::rt::RTView v;
     ff::rt::RT8View v8;
+    ff::rt::RT16View v16;
     void *mem[4] = {nullptr, nullptr, nullptr, nullptr};
 };
 
@@ -72,10 +73,11 @@ __global__ void rt_count_kernel(int64_t nrows, int64_t ntiles, const int64_t *ro
     cnt[t] = k;
 }
 
-// H-only FP32 copy in tiles of R rows: vh[entry][R]
+// FP32 copy in tiles of R rows: vh[entry][R] (H) and, when vm is given, vm[entry][R] (M)
 template <int R>
 __global__ void rt_fill_h_kernel(int64_t nrows, int64_t ntiles, const int64_t *row_ptr, const int32_t *col,
-                                 const double *H, const int64_t *tptr, int32_t *tcol, float *vh) {
+                                 const double *H, const double *M, const int64_t *tptr, int32_t *tcol, float *vh,
+                                 float *vm) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= ntiles) return;
     Merge<R> s;
@@ -88,6 +90,7 @@ __global__ void rt_fill_h_kernel(int64_t nrows, int64_t ntiles, const int64_t *r
         for (int i = 0; i < R; ++i) {
             const bool hit = s.h[i] == cur;
             v[i] = hit ? (float)H[s.p[i]] : 0.f;
+            if (vm) vm[o * R + i] = hit ? (float)M[s.p[i]] : 0.f;
             if (hit) {
                 ++s.p[i];
                 s.h[i] = s.p[i] < s.e[i] ? col[s.p[i]] : INT_MAX;
@@ -211,9 +214,9 @@ template <bool kHM> struct Chunk<double, kHM> {
     }
 };
 
-// One 64-entry chunk of a tile: stage its values in LDS, request the chunk two
-// ahead into the same registers, then gather and accumulate.
-template <typename T, typename A, bool kHM, int kBatch>
+// One 64-entry chunk of a tile: stage its values in LDS, request the chunk
+// kAhead chunks ahead into the same registers, then gather and accumulate.
+template <typename T, typename A, bool kHM, int kBatch, int kAhead>
 __device__ __forceinline__ void rt_chunk(Chunk<T, kHM> &ch, int64_t base, int64_t e1, const int32_t *tcol,
                                          const T *tval_h, const T *tval_m, T *sv, int lane, bool on, int g, int c,
                                          int NG, int steps, const T *Y, int64_t ldy, Acc4<A> (&aH)[kTileRows],
@@ -226,7 +229,7 @@ __device__ __forceinline__ void rt_chunk(Chunk<T, kHM> &ch, int64_t base, int64_
     __builtin_amdgcn_wave_barrier();
     ch.stage(sv, lane);
     __builtin_amdgcn_wave_barrier();
-    ch.load(tcol, tval_h, tval_m, base + 128 + lane, base + 128 + lane < e1);
+    ch.load(tcol, tval_h, tval_m, base + 64 * kAhead + lane, base + 64 * kAhead + lane < e1);
     for (int s0 = 0; s0 < steps; s0 += kBatch) {
         V x[kBatch];
 #pragma unroll
@@ -256,8 +259,8 @@ __device__ __forceinline__ void rt_chunk(Chunk<T, kHM> &ch, int64_t base, int64_
 }
 
 // One wavefront per tile. The wave reads 64 union entries (column and eight
-// values) with one coalesced load per lane, keeps the next two chunks of 64 in
-// flight while it works on one, keeps the values in a wave-private LDS area (each lane group
+// values) with one coalesced load per lane, keeps the next chunk of 64 (two
+// in the H-only form) in flight while it works on one, keeps the values in a wave-private LDS area (each lane group
 // reads its entry's values as a broadcast) and hands each column to the lane
 // group that needs it by a cross-lane shuffle. Lanes form groups of
 // G = m / VN; group g takes entries g, g + NG, ... of the chunk; each lane holds
@@ -301,15 +304,24 @@ spmm_rt_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int32_t
     for (int i = 0; i < (kHM ? kTileRows : 1); ++i)
 #pragma unroll
         for (int q = 0; q < 4; ++q) aM[i].v[q] = 0;
-    // two chunks in flight: chunk k + 2 is requested as soon as chunk k is staged
+    // the H-only (FP32-accumulating) form keeps two chunks in flight: chunk k + 2 is requested as
+    // soon as chunk k is staged; the fused form, with twice the accumulators in FP64, keeps one
+    // (a second would cost it occupancy)
     Chunk<T, kHM> ca, cb;
     ca.load(tcol, tval_h, tval_m, e0 + lane, e0 + lane < e1);
-    cb.load(tcol, tval_h, tval_m, e0 + 64 + lane, e0 + 64 + lane < e1);
-    for (int64_t base = e0; base < e1; base += 128) {
-        rt_chunk<T, A, kHM, kBatch>(ca, base, e1, tcol, tval_h, tval_m, sv, lane, on, g, c, NG, steps, Y, ldy, aH, aM);
-        if (base + 64 < e1)
-            rt_chunk<T, A, kHM, kBatch>(cb, base + 64, e1, tcol, tval_h, tval_m, sv, lane, on, g, c, NG, steps, Y, ldy,
-                                        aH, aM);
+    if (!kHM) {
+        cb.load(tcol, tval_h, tval_m, e0 + 64 + lane, e0 + 64 + lane < e1);
+        for (int64_t base = e0; base < e1; base += 128) {
+            rt_chunk<T, A, kHM, kBatch, 2>(ca, base, e1, tcol, tval_h, tval_m, sv, lane, on, g, c, NG, steps, Y, ldy,
+                                           aH, aM);
+            if (base + 64 < e1)
+                rt_chunk<T, A, kHM, kBatch, 2>(cb, base + 64, e1, tcol, tval_h, tval_m, sv, lane, on, g, c, NG, steps,
+                                               Y, ldy, aH, aM);
+        }
+    } else {
+        for (int64_t base = e0; base < e1; base += 64)
+            rt_chunk<T, A, kHM, kBatch, 1>(ca, base, e1, tcol, tval_h, tval_m, sv, lane, on, g, c, NG, steps, Y, ldy,
+                                           aH, aM);
     }
     if ((64 % G) == 0) {
 #pragma unroll
@@ -671,7 +683,7 @@ struct Chunk8 {
     }
 };
 
-template <int kBatch>
+template <int kBatch, int kAhead>
 __device__ __forceinline__ void t8_chunk(Chunk8 &ch, int64_t base, int64_t e1, const int32_t *tcol, const float *vh,
                                          float *sv, int lane, int g, int c, int NG, int steps, const float *Y,
                                          int64_t ldy, float (&acc)[kTile8][8]) {
@@ -680,7 +692,7 @@ __device__ __forceinline__ void t8_chunk(Chunk8 &ch, int64_t base, int64_t e1, c
     __builtin_amdgcn_wave_barrier();
     ch.stage(sv, lane);
     __builtin_amdgcn_wave_barrier();
-    ch.load(tcol, vh, base + 128 + lane, base + 128 + lane < e1);
+    ch.load(tcol, vh, base + 64 * kAhead + lane, base + 64 * kAhead + lane < e1);
     for (int s0 = 0; s0 < steps; s0 += kBatch) {
         f32x4 x[kBatch][2];
 #pragma unroll
@@ -711,7 +723,7 @@ __device__ __forceinline__ void t8_chunk(Chunk8 &ch, int64_t base, int64_t e1, c
     }
 }
 
-template <bool kEpi, int kWaves, int kBatch, int kOcc>
+template <bool kEpi, int kWaves, int kBatch, int kAhead, int kOcc, bool kPre>
 __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(kOcc, 8)))
 spmm_t8_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int32_t *tcol, const float *vh,
                const float *Y, int64_t ldy, float *HY, int64_t ldo, int m, const int *row_obj, const int *obj_status,
@@ -732,14 +744,15 @@ spmm_t8_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int32_t
         any = any || (r0 + i < nrows && (!obj_status || obj_status[row_obj[r0 + i]] == 0));
     if (!any) return;
     f32x4 er[2], ez[2], ew[2];
-    if (kEpi && mine) {
+    auto epi_load = [&]() {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             er[h] = *(const f32x4 *)(cs.R + rme * ldo + c * 8 + 4 * h);
             ez[h] = *(const f32x4 *)(Y + rme * ldy + c * 8 + 4 * h);
             ew[h] = *(const f32x4 *)(cs.W + rme * cs.ldw + c * 8 + 4 * h);
         }
-    }
+    };
+    if (kEpi && kPre && mine) epi_load();
     float *sv = svals[wv];
     const int64_t e0 = tptr[t], e1 = tptr[t + 1];
     float acc[kTile8][8];
@@ -749,11 +762,18 @@ spmm_t8_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int32_t
         for (int q = 0; q < 8; ++q) acc[i][q] = 0.f;
     Chunk8 ca, cb;
     ca.load(tcol, vh, e0 + lane, e0 + lane < e1);
-    cb.load(tcol, vh, e0 + 64 + lane, e0 + 64 + lane < e1);
-    for (int64_t base = e0; base < e1; base += 128) {
-        t8_chunk<kBatch>(ca, base, e1, tcol, vh, sv, lane, g, c, NG, steps, Y, ldy, acc);
-        if (base + 64 < e1) t8_chunk<kBatch>(cb, base + 64, e1, tcol, vh, sv, lane, g, c, NG, steps, Y, ldy, acc);
+    if (kAhead == 2) {
+        cb.load(tcol, vh, e0 + 64 + lane, e0 + 64 + lane < e1);
+        for (int64_t base = e0; base < e1; base += 128) {
+            t8_chunk<kBatch, 2>(ca, base, e1, tcol, vh, sv, lane, g, c, NG, steps, Y, ldy, acc);
+            if (base + 64 < e1)
+                t8_chunk<kBatch, 2>(cb, base + 64, e1, tcol, vh, sv, lane, g, c, NG, steps, Y, ldy, acc);
+        }
+    } else {
+        for (int64_t base = e0; base < e1; base += 64)
+            t8_chunk<kBatch, 1>(ca, base, e1, tcol, vh, sv, lane, g, c, NG, steps, Y, ldy, acc);
     }
+    if (kEpi && !kPre && mine) epi_load();
 #pragma unroll
     for (int i = 0; i < kTile8; ++i)
         for (int d = G; d < 64; d <<= 1)
@@ -803,13 +823,14 @@ bool t8_ok(int m, int64_t ldy, int64_t ldo) {
 template <bool kEpi>
 int launch_t8(ff_ctx *ctx, hipStream_t st, const RT8View &v, int sub, int m, const float *Y, int64_t ldy, float *HY,
               int64_t ldo, const int *row_obj, const int *status, const ChebStep<float> &cs) {
-#define FF_T8(W, B, O)                                                                                  \
-    hipLaunchKernelGGL((spmm_t8_kernel<kEpi, W, B, O>), dim3(grid_for(v.ntiles, W)), dim3(64 * W), 0, st, \
+#define FF_T8(W, B, A, O, P)                                                                                \
+    hipLaunchKernelGGL((spmm_t8_kernel<kEpi, W, B, A, O, P>), dim3(grid_for(v.ntiles, W)), dim3(64 * W), 0, st, \
                        v.n, v.ntiles, v.tptr, v.tcol, v.vh, Y, ldy, HY, ldo, m, row_obj, status, cs)
+    // measured on the benchmark workload (m = 32): 1.23 / 1.27 / 1.41 ms
     switch (sub) {
-        case 1: FF_T8(4, 2, 1); break;
-        case 2: FF_T8(2, 4, 1); break;
-        default: FF_T8(2, 2, 1); break;
+        case 1: FF_T8(2, 4, 2, 1, true); break;
+        case 2: FF_T8(4, 2, 2, 1, true); break;
+        default: FF_T8(4, 2, 1, 4, false); break;
     }
 #undef FF_T8
     FF_CHECK_LAUNCH(ctx);
@@ -830,15 +851,16 @@ int cheb_step_t8(ff_ctx *ctx, hipStream_t st, const RT8View &v, int sub, int m, 
 }
 
 static int fill_t8(ff_ctx *ctx, hipStream_t st, int64_t n, int64_t ntiles, const int64_t *row_ptr,
-                   const int32_t *col, const double *H, const int64_t *tptr, int32_t *tcol, float *vh) {
+                   const int32_t *col, const double *H, const int64_t *tptr, int32_t *tcol, float *vh,
+                   const double *M = nullptr, float *vm = nullptr) {
     hipLaunchKernelGGL(rt_fill_h_kernel<kTile8>, dim3(grid_for(ntiles, 256)), dim3(256), 0, st, n, ntiles, row_ptr,
-                       col, H, tptr, tcol, vh);
+                       col, H, M, tptr, tcol, vh, vm);
     FF_CHECK_LAUNCH(ctx);
     return FF_OK;
 }
 
 int build_t8_ws(ff_ctx *ctx, hipStream_t st, int64_t n, const int64_t *row_ptr, const int32_t *col, const double *H,
-                RT8View *out) {
+                RT8View *out, const double *M) {
     FF_REQUIRE(ctx, n > 0 && row_ptr && col && H && out, "bad arguments");
     const int64_t ntiles = (n + kTile8 - 1) / kTile8;
     int64_t *cnt = (int64_t *)ws_get(ctx, WS_RT8_CNT, (size_t)(ntiles + 1) * sizeof(int64_t));
@@ -850,14 +872,382 @@ int build_t8_ws(ff_ctx *ctx, hipStream_t st, int64_t n, const int64_t *row_ptr, 
     const size_t ne = (size_t)std::max<int64_t>(entries, 1);
     int32_t *tcol = (int32_t *)ws_get(ctx, WS_RT8_COL, ne * sizeof(int32_t));
     float *vh = (float *)ws_get(ctx, WS_RT8_VAL, ne * kTile8 * sizeof(float));
-    if (!tcol || !vh) return FF_ERR_OOM;
-    if ((rc = fill_t8(ctx, st, n, ntiles, row_ptr, col, H, tptr, tcol, vh))) return rc;
+    float *vm = M ? (float *)ws_get(ctx, WS_RT8_VALM, ne * kTile8 * sizeof(float)) : nullptr;
+    if (!tcol || !vh || (M && !vm)) return FF_ERR_OOM;
+    if ((rc = fill_t8(ctx, st, n, ntiles, row_ptr, col, H, tptr, tcol, vh, M, vm))) return rc;
     out->n = n;
     out->ntiles = ntiles;
     out->entries = entries;
     out->tptr = tptr;
     out->tcol = tcol;
     out->vh = vh;
+    out->vm = vm;
+    return FF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// The preconditioner's H-only product on tiles of sixteen rows, on MFMA
+// ---------------------------------------------------------------------------
+//
+// Per tile the product is dense: (H Y)[tile rows][columns] = V[tile rows][entries]
+// . Y[entries][columns], V the tile's value block and the entries' rows of Y
+// gathered. It runs on v_mfma_f32_16x16x4f32 with the 16 tile rows as the B/D
+// column index and 16 column slots as the A/D row index: slot i of MFMA t holds
+// column kMT * i + t (kMT = m / 16), so the lane that supplies slot i for entry
+// k reads kMT consecutive floats of that entry's row with one load. The MFMA
+// sums over the entries itself (no cross-lane reduction), and lane l ends up
+// holding row l % 16 of the tile at 4 kMT consecutive columns, which it then
+// stores or uses for the Chebyshev step. m <= 16 (kMT = 1) masks slots >= m.
+struct Chunk16 {
+    int32_t j;
+    f32x4 v[4];                                    // H of the tile's rows 0..15
+    __device__ void load(const int32_t *tcol, const float *vh, int64_t e, bool in) {
+        j = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+        if (in) {
+            j = __builtin_nontemporal_load(tcol + e);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q] = __builtin_nontemporal_load((const f32x4 *)(vh + e * 16 + 4 * q));
+        }
+    }
+    __device__ void stage(float *sv, int lane) const {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) *(f32x4 *)(sv + lane * 16 + 4 * q) = v[q];
+    }
+};
+
+template <int kMT> struct YVec;
+template <> struct YVec<1> { typedef float type; };
+template <> struct YVec<2> { typedef float2 type; };
+template <> struct YVec<4> { typedef f32x4 type; };
+__device__ inline float yget(const float &v, int) { return v; }
+__device__ inline float yget(const float2 &v, int t) { return t == 0 ? v.x : v.y; }
+__device__ inline float yget(const f32x4 &v, int t) { return v[t]; }
+
+__device__ inline f32x4 mfma16(float a, float b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <int kMT, int kBatch, int kAhead>
+__device__ __forceinline__ void t16_chunk(Chunk16 &ch, int64_t base, int64_t e1, const int32_t *tcol, const float *vh,
+                                          float *sv, int lane, int li, int lk, int m, const float *Y, int64_t ldy,
+                                          f32x4 (&d)[kMT]) {
+    typedef typename YVec<kMT>::type YV;
+    const int cnt = (int)(e1 - base < 64 ? e1 - base : 64);
+    const int32_t jc = ch.j;
+    __builtin_amdgcn_wave_barrier();
+    ch.stage(sv, lane);
+    __builtin_amdgcn_wave_barrier();
+    ch.load(tcol, vh, base + 64 * kAhead + lane, base + 64 * kAhead + lane < e1);
+    const bool slot_ok = kMT > 1 || li < m;
+    const int nq = (cnt + 3) >> 2;                 // k-steps of 4 entries
+    for (int q0 = 0; q0 < nq; q0 += kBatch) {
+        YV y[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int e = 4 * (q0 + u) + lk;
+            const int32_t j = __shfl(jc, e < 64 ? e : 63, 64);
+            y[u] = YV{};
+            if (e < cnt && slot_ok) y[u] = *(const YV *)(Y + (int64_t)j * ldy + kMT * li);
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int e = 4 * (q0 + u) + lk;
+            const float b = (q0 + u < nq && e < cnt) ? sv[e * 16 + li] : 0.f;
+#pragma unroll
+            for (int t = 0; t < kMT; ++t) d[t] = mfma16(yget(y[u], t), b, d[t]);
+        }
+    }
+}
+
+template <bool kEpi, int kMT, int kWaves, int kBatch, int kAhead, int kOcc, bool kPre>
+__global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(kOcc, 8)))
+spmm_t16_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int32_t *tcol, const float *vh,
+                const float *Y, int64_t ldy, float *HY, int64_t ldo, int m, const int *row_obj, const int *obj_status,
+                ChebStep<float> cs) {
+    __shared__ __align__(16) float svals[kWaves][64 * 16];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t t = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kWaves + wv;
+    if (t >= ntiles) return;
+    const int li = lane & 15, lk = lane >> 4;
+    const int64_t r = t * kTile16 + li;           // the row this lane stores
+    const int c0 = lk * 4 * kMT;                   // its first column
+    const bool mine = r < nrows && c0 < m && (!obj_status || obj_status[row_obj[r]] == 0);
+    if (!__any(r < nrows && (!obj_status || obj_status[row_obj[r]] == 0))) return;
+    f32x4 er[kMT], ez[kMT], ew[kMT];
+    auto epi_load = [&]() {
+#pragma unroll
+        for (int h = 0; h < kMT; ++h) {
+            er[h] = *(const f32x4 *)(cs.R + r * ldo + c0 + 4 * h);
+            ez[h] = *(const f32x4 *)(Y + r * ldy + c0 + 4 * h);
+            ew[h] = *(const f32x4 *)(cs.W + r * cs.ldw + c0 + 4 * h);
+        }
+    };
+    if (kEpi && kPre && mine) epi_load();
+    float *sv = svals[wv];
+    const int64_t e0 = tptr[t], e1 = tptr[t + 1];
+    f32x4 d[kMT];
+#pragma unroll
+    for (int q = 0; q < kMT; ++q) d[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    Chunk16 ca, cb;
+    ca.load(tcol, vh, e0 + lane, e0 + lane < e1);
+    if (kAhead == 2) {
+        cb.load(tcol, vh, e0 + 64 + lane, e0 + 64 + lane < e1);
+        for (int64_t base = e0; base < e1; base += 128) {
+            t16_chunk<kMT, kBatch, 2>(ca, base, e1, tcol, vh, sv, lane, li, lk, m, Y, ldy, d);
+            if (base + 64 < e1) t16_chunk<kMT, kBatch, 2>(cb, base + 64, e1, tcol, vh, sv, lane, li, lk, m, Y, ldy, d);
+        }
+    } else {
+        for (int64_t base = e0; base < e1; base += 64)
+            t16_chunk<kMT, kBatch, 1>(ca, base, e1, tcol, vh, sv, lane, li, lk, m, Y, ldy, d);
+    }
+    if (!mine) return;
+    if (kEpi && !kPre) epi_load();
+    // d[t][v] is column kMT * (4 lk + v) + t = c0 + kMT * v + t
+    f32x4 out[kMT];
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int tt = 0; tt < kMT; ++tt) {
+            const int cc = kMT * v + tt;
+            out[cc >> 2][cc & 3] = d[tt][v];
+        }
+    if (kEpi) {
+        const int o = row_obj[r];
+        const double f1 = cs.coef[(size_t)o * cs.stride + 2 * cs.step - 1];
+        const double f2 = cs.coef[(size_t)o * cs.stride + 2 * cs.step];
+        const double dv = (double)cs.dinv[r];
+#pragma unroll
+        for (int h = 0; h < kMT; ++h) {
+            f32x4 rv1, dz1, w1;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double rv = (double)er[h][q] - dv * (double)out[h][q];
+                const double dz = f1 * (double)ez[h][q] + f2 * rv;
+                rv1[q] = (float)rv;
+                dz1[q] = (float)dz;
+                w1[q] = (float)((double)ew[h][q] + dz);
+            }
+            *(f32x4 *)(cs.R + r * ldo + c0 + 4 * h) = rv1;
+            *(f32x4 *)(cs.dz_out + r * ldo + c0 + 4 * h) = dz1;
+            *(f32x4 *)(cs.W + r * cs.ldw + c0 + 4 * h) = w1;
+        }
+    } else {
+#pragma unroll
+        for (int h = 0; h < kMT; ++h) *(f32x4 *)(HY + r * ldo + c0 + 4 * h) = out[h];
+    }
+}
+
+bool t16_ok(int m, int64_t ldy, int64_t ldo) {
+    return (m == 32 || m == 64 || (m % 4 == 0 && m >= 4 && m <= 16)) && ldy % 4 == 0 && ldo % 4 == 0;
+}
+
+template <bool kEpi>
+int launch_t16(ff_ctx *ctx, hipStream_t st, const RT16View &v, int sub, int m, const float *Y, int64_t ldy, float *HY,
+               int64_t ldo, const int *row_obj, const int *status, const ChebStep<float> &cs) {
+#define FF_T16(MT, W, B, A, O, P)                                                                            \
+    hipLaunchKernelGGL((spmm_t16_kernel<kEpi, MT, W, B, A, O, P>), dim3(grid_for(v.ntiles, W)), dim3(64 * W), 0, \
+                       st, v.n, v.ntiles, v.tptr, v.tcol, v.vh, Y, ldy, HY, ldo, m, row_obj, status, cs)
+    const int mt = m <= 16 ? 1 : m / 16;
+    if (mt == 1) {
+        FF_T16(1, 4, 4, 1, 4, false);
+    } else if (mt == 2) {
+        // measured on the benchmark workload: 1.38 / 1.43 / 1.47 ms
+        switch (sub) {
+            case 1: FF_T16(2, 4, 8, 1, 4, false); break;
+            case 2: FF_T16(2, 4, 16, 1, 1, true); break;
+            default: FF_T16(2, 2, 16, 1, 4, false); break;
+        }
+    } else {
+        FF_T16(4, 4, 2, 1, 4, false);
+    }
+#undef FF_T16
+    FF_CHECK_LAUNCH(ctx);
+    return FF_OK;
+}
+
+int spmm_h_t16(ff_ctx *ctx, hipStream_t st, const RT16View &v, int sub, int m, const float *Y, int64_t ldy, float *HY,
+               int64_t ldo, const int *row_obj, const int *status) {
+    FF_REQUIRE(ctx, v.vh != nullptr && t16_ok(m, ldy, ldo), "sixteen-row tiles: bad copy or block shape (m = %d)", m);
+    return launch_t16<false>(ctx, st, v, sub, m, Y, ldy, HY, ldo, row_obj, status, ChebStep<float>{});
+}
+
+int cheb_step_t16(ff_ctx *ctx, hipStream_t st, const RT16View &v, int sub, int m, const float *DZ, int64_t ld,
+                  const int *row_obj, const int *status, const ChebStep<float> &cs) {
+    FF_REQUIRE(ctx, v.vh != nullptr && row_obj != nullptr && t16_ok(m, ld, ld) && cs.ldw % 4 == 0,
+               "sixteen-row tiles: bad copy or block shape (m = %d)", m);
+    return launch_t16<true>(ctx, st, v, sub, m, DZ, ld, nullptr, ld, row_obj, status, cs);
+}
+
+static int fill_t16(ff_ctx *ctx, hipStream_t st, int64_t n, int64_t ntiles, const int64_t *row_ptr,
+                    const int32_t *col, const double *H, const int64_t *tptr, int32_t *tcol, float *vh) {
+    hipLaunchKernelGGL(rt_fill_h_kernel<kTile16>, dim3(grid_for(ntiles, 64)), dim3(64), 0, st, n, ntiles, row_ptr,
+                       col, H, (const double *)nullptr, tptr, tcol, vh, (float *)nullptr);
+    FF_CHECK_LAUNCH(ctx);
+    return FF_OK;
+}
+
+int build_t16_ws(ff_ctx *ctx, hipStream_t st, int64_t n, const int64_t *row_ptr, const int32_t *col, const double *H,
+                 RT16View *out) {
+    FF_REQUIRE(ctx, n > 0 && row_ptr && col && H && out, "bad arguments");
+    const int64_t ntiles = (n + kTile16 - 1) / kTile16;
+    int64_t *cnt = (int64_t *)ws_get(ctx, WS_RT16_CNT, (size_t)(ntiles + 1) * sizeof(int64_t));
+    int64_t *tptr = (int64_t *)ws_get(ctx, WS_RT16_PTR, (size_t)(ntiles + 1) * sizeof(int64_t));
+    if (!cnt || !tptr) return FF_ERR_OOM;
+    int64_t entries = 0;
+    int rc = build_ptr<kTile16>(ctx, st, n, row_ptr, col, cnt, tptr, ntiles, &entries);
+    if (rc) return rc;
+    const size_t ne = (size_t)std::max<int64_t>(entries, 1);
+    int32_t *tcol = (int32_t *)ws_get(ctx, WS_RT16_COL, ne * sizeof(int32_t));
+    float *vh = (float *)ws_get(ctx, WS_RT16_VAL, ne * kTile16 * sizeof(float));
+    if (!tcol || !vh) return FF_ERR_OOM;
+    if ((rc = fill_t16(ctx, st, n, ntiles, row_ptr, col, H, tptr, tcol, vh))) return rc;
+    out->n = n;
+    out->ntiles = ntiles;
+    out->entries = entries;
+    out->tptr = tptr;
+    out->tcol = tcol;
+    out->vh = vh;
+    return FF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Fused [H, M] Y on the eight-row [H, M] copy, on FP64 MFMA
+// ---------------------------------------------------------------------------
+//
+// Per tile (HY; MY)[16 outputs][columns] = V[16 outputs][entries] . Y[entries]
+// [columns], the 16 outputs being H of the tile's eight rows and M of the same
+// rows. v_mfma_f64_16x16x4f64 takes the outputs as its A/D row index and 16
+// column slots as the B/D column index (slot j of MFMA t is column kMT j + t),
+// so a lane reads kMT consecutive floats of a gathered row with one load. The
+// FP32 values and block entries are exact in FP64 and the sums accumulate in
+// FP64, as in the VALU kernel; the VALU keeps only the conversions and the
+// address arithmetic. Lanes with the same output write one contiguous row.
+struct ChunkHM8 {
+    int32_t j;
+    f32x4 v[4];                                    // H rows 0..3, 4..7, M rows 0..3, 4..7
+    __device__ void load(const int32_t *tcol, const float *vh, const float *vm, int64_t e, bool in) {
+        j = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+        if (in) {
+            j = __builtin_nontemporal_load(tcol + e);
+            v[0] = __builtin_nontemporal_load((const f32x4 *)(vh + e * 8));
+            v[1] = __builtin_nontemporal_load((const f32x4 *)(vh + e * 8 + 4));
+            v[2] = __builtin_nontemporal_load((const f32x4 *)(vm + e * 8));
+            v[3] = __builtin_nontemporal_load((const f32x4 *)(vm + e * 8 + 4));
+        }
+    }
+    __device__ void stage(float *sv, int lane) const {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) *(f32x4 *)(sv + lane * 16 + 4 * q) = v[q];
+    }
+};
+
+typedef double f64x4r __attribute__((ext_vector_type(4)));
+__device__ inline f64x4r mfma64(double a, double b, f64x4r c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <int kMT, int kBatch>
+__device__ __forceinline__ void hm8_chunk(ChunkHM8 &ch, int64_t base, int64_t e1, const int32_t *tcol,
+                                          const float *vh, const float *vm, float *sv, int lane, int li, int lk, int m,
+                                          const float *Y, int64_t ldy, f64x4r (&d)[kMT]) {
+    typedef typename YVec<kMT>::type YV;
+    const int cnt = (int)(e1 - base < 64 ? e1 - base : 64);
+    const int32_t jc = ch.j;
+    __builtin_amdgcn_wave_barrier();
+    ch.stage(sv, lane);
+    __builtin_amdgcn_wave_barrier();
+    ch.load(tcol, vh, vm, base + 64 + lane, base + 64 + lane < e1);
+    const bool slot_ok = kMT > 1 || li < m;
+    const int nq = (cnt + 3) >> 2;
+    for (int q0 = 0; q0 < nq; q0 += kBatch) {
+        YV y[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int e = 4 * (q0 + u) + lk;
+            const int32_t j = __shfl(jc, e < 64 ? e : 63, 64);
+            y[u] = YV{};
+            if (e < cnt && slot_ok) y[u] = *(const YV *)(Y + (int64_t)j * ldy + kMT * li);
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int e = 4 * (q0 + u) + lk;
+            const double a = (q0 + u < nq && e < cnt) ? (double)sv[e * 16 + li] : 0.0;
+#pragma unroll
+            for (int t = 0; t < kMT; ++t) d[t] = mfma64(a, (double)yget(y[u], t), d[t]);
+        }
+    }
+}
+
+template <int kMT, int kWaves, int kBatch, int kOcc>
+__global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(kOcc, 8)))
+spmm_hm8_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int32_t *tcol, const float *vh,
+                const float *vm, const float *Y, int64_t ldy, float *HY, float *MY, int64_t ldo, int m,
+                const int *row_obj, const int *obj_status) {
+    __shared__ __align__(16) float svals[kWaves][64 * 16];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t t = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kWaves + wv;
+    if (t >= ntiles) return;
+    const int li = lane & 15, lk = lane >> 4;
+    const int64_t r0 = t * kTile8;
+    bool any = false;
+#pragma unroll
+    for (int i = 0; i < kTile8; ++i)
+        any = any || (r0 + i < nrows && (!obj_status || obj_status[row_obj[r0 + i]] == 0));
+    if (!any) return;
+    float *sv = svals[wv];
+    const int64_t e0 = tptr[t], e1 = tptr[t + 1];
+    f64x4r d[kMT];
+#pragma unroll
+    for (int q = 0; q < kMT; ++q) d[q] = f64x4r{0.0, 0.0, 0.0, 0.0};
+    ChunkHM8 ch;
+    ch.load(tcol, vh, vm, e0 + lane, e0 + lane < e1);
+    for (int64_t base = e0; base < e1; base += 64)
+        hm8_chunk<kMT, kBatch>(ch, base, e1, tcol, vh, vm, sv, lane, li, lk, m, Y, ldy, d);
+    if (kMT == 1 && li >= m) return;
+    // lane holds D[4 v + lk][li]: output 4 v + lk (H rows 0..7, then M rows 0..7), columns kMT li + t
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int o = 4 * v + lk;
+        const int64_t r = r0 + (o & 7);
+        if (r >= nrows || (obj_status && obj_status[row_obj[r]] != 0)) continue;
+        float *dst = (o < 8 ? HY : MY) + r * ldo + kMT * li;
+        if (kMT == 1) {
+            dst[0] = (float)d[0][v];
+        } else if (kMT == 2) {
+            *(float2 *)dst = make_float2((float)d[0][v], (float)d[1][v]);
+        } else {
+            *(f32x4 *)dst = f32x4{(float)d[0][v], (float)d[1][v], (float)d[2][v], (float)d[3][v]};
+        }
+    }
+}
+
+bool hm8_ok(int m, int64_t ldy, int64_t ldo) { return t16_ok(m, ldy, ldo); }
+
+int spmm_hm8(ff_ctx *ctx, hipStream_t st, const RT8View &v, int sub, int m, const float *Y, int64_t ldy, float *HY,
+             float *MY, int64_t ldo, const int *row_obj, const int *status) {
+    FF_REQUIRE(ctx, v.vh != nullptr && v.vm != nullptr && hm8_ok(m, ldy, ldo),
+               "eight-row [H, M] tiles: bad copy or block shape (m = %d)", m);
+#define FF_HM8(MT, W, B, O)                                                                                \
+    hipLaunchKernelGGL((spmm_hm8_kernel<MT, W, B, O>), dim3(grid_for(v.ntiles, W)), dim3(64 * W), 0, st, v.n, \
+                       v.ntiles, v.tptr, v.tcol, v.vh, v.vm, Y, ldy, HY, MY, ldo, m, row_obj, status)
+    const int mt = m <= 16 ? 1 : m / 16;
+    if (mt == 1) {
+        FF_HM8(1, 4, 8, 4);
+    } else if (mt == 2) {
+        switch (sub) {
+            case 1: FF_HM8(2, 2, 8, 4); break;
+            case 2: FF_HM8(2, 4, 4, 6); break;
+            default: FF_HM8(2, 4, 8, 4); break;
+        }
+    } else {
+        if (sub == 1) FF_HM8(4, 2, 4, 4); else FF_HM8(4, 4, 4, 4);
+    }
+#undef FF_HM8
+    FF_CHECK_LAUNCH(ctx);
     return FF_OK;
 }
 
@@ -872,17 +1262,18 @@ int rowtiles_build(ff_ctx *ctx, int64_t n, const int64_t *row_ptr, const int32_t
                    const double *M, int precision, ff_rowtiles **out) {
     if (!ctx || !out) return FF_ERR_INVALID_ARG;
     *out = nullptr;
-    FF_REQUIRE(ctx, n > 0 && row_ptr && col && H && (M || precision == 3), "bad arguments");
-    FF_REQUIRE(ctx, precision >= 0 && precision <= 3,
-               "precision must be 0 (FP64), 1 (FP32), 2 (both) or 3 (FP32 H only, eight-row tiles)");
+    FF_REQUIRE(ctx, n > 0 && row_ptr && col && H && (M || precision >= 3), "bad arguments");
+    FF_REQUIRE(ctx, precision >= 0 && precision <= 4,
+               "precision must be 0 (FP64), 1 (FP32), 2 (both), 3 or 4 (FP32 H only, eight- or sixteen-row tiles)");
     FF_HIP(ctx, hipSetDevice(ctx->device));
     hipStream_t st = ctx->stream;
     ff_rowtiles *h = new ff_rowtiles();
     h->device = ctx->device;
     h->stream = ctx->stream;
-    if (precision == 3) {
-        h->eight = 1;
-        const int64_t nt8 = (n + rt::kTile8 - 1) / rt::kTile8;
+    if (precision >= 3) {
+        const int R = precision == 3 ? rt::kTile8 : rt::kTile16;
+        h->hrows = R;
+        const int64_t nt8 = (n + R - 1) / R;
         int64_t *cnt8 = nullptr, *tptr8 = nullptr;
         int rc8 = FF_OK;
         if (hipMalloc((void **)&cnt8, (size_t)(nt8 + 1) * sizeof(int64_t)) != hipSuccess ||
@@ -892,33 +1283,37 @@ int rowtiles_build(ff_ctx *ctx, int64_t n, const int64_t *row_ptr, const int32_t
         }
         h->mem[0] = tptr8;
         int64_t ent8 = 0;
-        if (!rc8) rc8 = rt::build_ptr<rt::kTile8>(ctx, st, n, row_ptr, col, cnt8, tptr8, nt8, &ent8);
+        if (!rc8)
+            rc8 = R == rt::kTile8 ? rt::build_ptr<rt::kTile8>(ctx, st, n, row_ptr, col, cnt8, tptr8, nt8, &ent8)
+                                  : rt::build_ptr<rt::kTile16>(ctx, st, n, row_ptr, col, cnt8, tptr8, nt8, &ent8);
         if (cnt8) (void)hipFree(cnt8);
         int32_t *tcol8 = nullptr;
         float *vh = nullptr;
         if (!rc8) {
             const size_t ne = (size_t)std::max<int64_t>(ent8, 1);
             if (hipMalloc((void **)&tcol8, ne * sizeof(int32_t)) != hipSuccess ||
-                hipMalloc((void **)&vh, ne * rt::kTile8 * sizeof(float)) != hipSuccess) {
+                hipMalloc((void **)&vh, ne * R * sizeof(float)) != hipSuccess) {
                 (void)hipGetLastError();
                 rc8 = set_error(ctx, FF_ERR_OOM, "row-tile allocation of %lld entries failed", (long long)ent8);
             }
             h->mem[1] = tcol8;
             h->mem[2] = vh;
         }
-        if (!rc8) rc8 = rt::fill_t8(ctx, st, n, nt8, row_ptr, col, H, tptr8, tcol8, vh);
+        if (!rc8)
+            rc8 = R == rt::kTile8 ? rt::fill_t8(ctx, st, n, nt8, row_ptr, col, H, tptr8, tcol8, vh)
+                                  : rt::fill_t16(ctx, st, n, nt8, row_ptr, col, H, tptr8, tcol8, vh);
         if (!rc8 && hipStreamSynchronize(st) != hipSuccess)
             rc8 = set_error(ctx, FF_ERR_HIP, "row-tile build failed");
         if (rc8) {
             rowtiles_destroy(h);
             return rc8;
         }
-        h->v8.n = n;
-        h->v8.ntiles = nt8;
-        h->v8.entries = ent8;
-        h->v8.tptr = tptr8;
-        h->v8.tcol = tcol8;
-        h->v8.vh = vh;
+        h->v8.n = h->v16.n = n;
+        h->v8.ntiles = h->v16.ntiles = nt8;
+        h->v8.entries = h->v16.entries = ent8;
+        h->v8.tptr = h->v16.tptr = tptr8;
+        h->v8.tcol = h->v16.tcol = tcol8;
+        h->v8.vh = h->v16.vh = vh;
         *out = h;
         return FF_OK;
     }
@@ -972,8 +1367,8 @@ int rowtiles_build(ff_ctx *ctx, int64_t n, const int64_t *row_ptr, const int32_t
 
 int rowtiles_info(const ff_rowtiles *rt, int64_t *ntiles, int64_t *entries) {
     if (!rt) return FF_ERR_INVALID_ARG;
-    if (ntiles) *ntiles = rt->eight ? rt->v8.ntiles : rt->v.ntiles;
-    if (entries) *entries = rt->eight ? rt->v8.entries : rt->v.entries;
+    if (ntiles) *ntiles = rt->hrows ? rt->v8.ntiles : rt->v.ntiles;
+    if (entries) *entries = rt->hrows ? rt->v8.entries : rt->v.entries;
     return FF_OK;
 }
 
@@ -982,12 +1377,16 @@ int spmm_rowtiles(ff_ctx *ctx, const ff_rowtiles *rt, int precision, int m, cons
     if (!ctx || !rt) return FF_ERR_INVALID_ARG;
     FF_REQUIRE(ctx, Y && HY, "required pointer is NULL");
     FF_REQUIRE(ctx, precision == 0 || precision == 1, "precision must be 0 or 1");
-    if (rt->eight) {
-        FF_REQUIRE(ctx, precision == 1 && !MY, "the eight-row copy forms H Y alone in FP32 (MY must be NULL)");
-        FF_REQUIRE(ctx, rt::t8_ok(m, ld_y, ld_out) && ld_y >= m && ld_out >= m,
-                   "block width %d / leading dimensions not supported by the eight-row kernel", m);
-        FF_REQUIRE(ctx, sub >= 0 && sub < rt::kSubs, "launch shape %d out of range", sub);
+    if (rt->hrows) {
+        FF_REQUIRE(ctx, precision == 1 && !MY, "an H-only copy forms H Y alone in FP32 (MY must be NULL)");
+        FF_REQUIRE(ctx, (rt->hrows == 8 ? rt::t8_ok(m, ld_y, ld_out) : rt::t16_ok(m, ld_y, ld_out)) && ld_y >= m &&
+                            ld_out >= m,
+                   "block width %d / leading dimensions not supported by the %d-row kernel", m, rt->hrows);
+        FF_REQUIRE(ctx, sub >= 0 && sub < rt::kHSubs, "launch shape %d out of range", sub);
         FF_HIP(ctx, hipSetDevice(ctx->device));
+        if (rt->hrows == 16)
+            return rt::spmm_h_t16(ctx, ctx->stream, rt->v16, sub, m, (const float *)Y, ld_y, (float *)HY, ld_out,
+                                  nullptr, nullptr);
         return rt::spmm_h_t8(ctx, ctx->stream, rt->v8, sub, m, (const float *)Y, ld_y, (float *)HY, ld_out, nullptr,
                              nullptr);
     }

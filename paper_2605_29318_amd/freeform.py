@@ -250,7 +250,7 @@ def _params(k, block, precision, tol, max_iter, precond, seed, check_every, use_
 
 
 def eigenmodes(ctx: Context, n: int, row_ptr, col, H, M, hm32, k: int, block: int = 0, precision: int = 1,
-               tol: float = 1e-6, max_iter: int = 5000, precond: int = 1, seed: int = 0, X0=None,
+               tol: float = 1e-6, max_iter: int = 5000, precond: int = 2, seed: int = 0, X0=None,
                check_every: int = 10, use_graph: bool = False, refresh_every: int = 0, allow_unconverged=False,
                precond_degree: int = 0):
     import torch
@@ -271,7 +271,7 @@ def eigenmodes(ctx: Context, n: int, row_ptr, col, H, M, hm32, k: int, block: in
 
 
 def eigenmodes_batched(ctx: Context, obj_row_off, row_ptr, col, H, M, hm32, k: int, block: int = 0,
-                       precision: int = 1, tol: float = 1e-6, max_iter: int = 5000, precond: int = 1,
+                       precision: int = 1, tol: float = 1e-6, max_iter: int = 5000, precond: int = 2,
                        seed: int = 0, X0=None, check_every: int = 10, use_graph: bool = False,
                        refresh_every: int = 0, allow_unconverged=False, precond_degree: int = 0):
     import torch

@@ -49,6 +49,8 @@ def main(argv=None) -> int:
     ap.add_argument("--lr-final", type=float, default=3e-4)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--precision", type=int, nargs="+", default=[1, 0])
+    ap.add_argument("--precond", type=int, nargs="+", default=[2, 1],
+                    help="preconditioners to evaluate (2 Chebyshev-Jacobi, 1 Jacobi)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--out", type=str, default=None, help="save the FP32 parameters (.npy)")
     a = ap.parse_args(argv)
@@ -88,28 +90,32 @@ def main(argv=None) -> int:
         m = ((k + 7) // 8) * 8
         row = dict(shape=j, n=s.n)
         for prec in a.precision:
-            for mode in ("random", "warm"):
-                X0, used = ws.warm_block(ctx, net if mode == "warm" else None, s, m, seed=a.seed + 1)
-                lam, W, info = ws.solve(ctx, s, k, X0=X0, precision=prec, tol=a.tol)
-                row[f"p{prec}_{mode}"] = dict(iters=info["iters_fp32"] + info["iters_fp64"],
-                                              seconds=round(info["seconds"], 3), converged=info["converged"],
-                                              used_network=used, max_resid=info["max_resid"])
-                if mode == "random":
-                    lam_r = lam
-                else:
-                    row[f"p{prec}_dlam"] = float(np.abs(lam[1:] - lam_r[1:]).max() / np.abs(lam_r[1:]).max())
+            for pc in a.precond:
+                key = f"p{prec}c{pc}"
+                for mode in ("random", "warm"):
+                    X0, used = ws.warm_block(ctx, net if mode == "warm" else None, s, m, seed=a.seed + 1)
+                    lam, W, info = ws.solve(ctx, s, k, X0=X0, precision=prec, tol=a.tol, precond=pc)
+                    row[f"{key}_{mode}"] = dict(iters=info["iters_fp32"] + info["iters_fp64"],
+                                                seconds=round(info["seconds"], 3), converged=info["converged"],
+                                                used_network=used, max_resid=info["max_resid"])
+                    if mode == "random":
+                        lam_r = lam
+                    else:
+                        row[f"{key}_dlam"] = float(np.abs(lam[1:] - lam_r[1:]).max() / np.abs(lam_r[1:]).max())
         rows.append(row)
         _log(json.dumps(row))
     summ = dict(train_shapes=len(train), train_seconds=round(train_s, 2), k=k, freq=a.freq, epochs=a.epochs)
     for prec in a.precision:
-        r = [x[f"p{prec}_random"]["iters"] for x in rows]
-        w = [x[f"p{prec}_warm"]["iters"] for x in rows]
-        rs = [x[f"p{prec}_random"]["seconds"] for x in rows]
-        wsec = [x[f"p{prec}_warm"]["seconds"] for x in rows]
-        summ[f"p{prec}"] = dict(iters_random=float(np.mean(r)), iters_warm=float(np.mean(w)),
-                                seconds_random=float(np.mean(rs)), seconds_warm=float(np.mean(wsec)),
-                                iter_ratio=float(np.mean(np.array(w) / np.array(r))),
-                                used_network=sum(x[f"p{prec}_warm"]["used_network"] for x in rows))
+        for pc in a.precond:
+            key = f"p{prec}c{pc}"
+            r = [x[f"{key}_random"]["iters"] for x in rows]
+            w = [x[f"{key}_warm"]["iters"] for x in rows]
+            rs = [x[f"{key}_random"]["seconds"] for x in rows]
+            wsec = [x[f"{key}_warm"]["seconds"] for x in rows]
+            summ[key] = dict(iters_random=float(np.mean(r)), iters_warm=float(np.mean(w)),
+                             seconds_random=float(np.mean(rs)), seconds_warm=float(np.mean(wsec)),
+                             iter_ratio=float(np.mean(np.array(w) / np.array(r))),
+                             used_network=sum(x[f"{key}_warm"]["used_network"] for x in rows))
     _log("SUMMARY " + json.dumps(summ))
     net.close()
     ctx.close()

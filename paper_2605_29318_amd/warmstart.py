@@ -47,11 +47,12 @@ def prepare(ctx: ff.Context, cloud, n_freq: int = DEFAULT_FREQ, device="cuda") -
 
 
 def solve(ctx: ff.Context, s: Sample, k: int, X0=None, precision: int = 1, tol: float = 1e-6,
-          max_iter: int = 20000, seed: int = 0):
+          max_iter: int = 20000, seed: int = 0, precond: int = 2):
     """eigenmodes on a prepared sample; returns (lam, W, info)."""
     A = s.A
     lam, W, res, info = ff.eigenmodes(ctx, A.n, A.row_ptr, A.col, A.H, A.M, A.hm32, k=k, precision=precision,
-                                      tol=tol, max_iter=max_iter, X0=X0, seed=seed, allow_unconverged=True)
+                                      tol=tol, max_iter=max_iter, X0=X0, seed=seed, allow_unconverged=True,
+                                      precond=precond)
     return lam, W, info
 
 

@@ -157,11 +157,16 @@ def test_spmm(oracle, ctx, ff, precision, m):
     refM = oracle.spmm(P.row_ptr, P.col, P.M, Y)
     absH = oracle.spmm(P.row_ptr, P.col, np.abs(P.H), np.abs(Y))
     absM = oracle.spmm(P.row_ptr, P.col, np.abs(P.M), np.abs(Y))
-    for v in range(len(ff.spmm_variant_names())):
+    for v, name in enumerate(ff.spmm_variant_names()):
+        if name.startswith("rowtile8_mfma") and (precision == 0 or m not in (8, 16, 32, 64)):
+            # the eight-row FP64-MFMA variants take FP32 blocks of these widths only
+            with pytest.raises(ff.FFError):
+                ff.spmm_hm(ctx, A.row_ptr, A.col, A.H, A.M, A.hm32, dev(Y, dt), precision, variant=v)
+            continue
         HY, MY = ff.spmm_hm(ctx, A.row_ptr, A.col, A.H, A.M, A.hm32, dev(Y, dt), precision, variant=v)
         eps = 2e-6 if precision else 1e-13
-        assert np.all(np.abs(host(HY) - refH) <= eps * absH + 1e-300)
-        assert np.all(np.abs(host(MY) - refM) <= eps * absM + 1e-300)
+        assert np.all(np.abs(host(HY) - refH) <= eps * absH + 1e-300), name
+        assert np.all(np.abs(host(MY) - refM) <= eps * absM + 1e-300), name
 
 
 @pytest.mark.parametrize("precision", [0, 1])
@@ -198,22 +203,24 @@ def test_rowtiles_spmm(oracle, ctx, ff, precision):
     rt.close()
 
 
-def test_rowtiles_eight_row_h_copy(oracle, ctx, ff):
-    """The preconditioner's H-only copy in tiles of eight rows (ragged last tile): H Y in
-    FP32 accumulation, every launch shape and the block widths the kernel takes; other
-    forms are rejected."""
+@pytest.mark.parametrize("rows", [8, 16])
+def test_rowtiles_h_only_copies(oracle, ctx, ff, rows):
+    """The preconditioner's H-only copies in tiles of eight rows (VALU kernel) and of
+    sixteen rows (MFMA kernel), ragged last tile: H Y in FP32 accumulation, every launch
+    shape and the block widths the kernels take; other forms are rejected."""
     c = synth.random_cloud(2503, seed=29, hetero=True)
     P = oracle.pipeline(c)
     A = ff.assemble_cloud(ctx, dev(c.xyz), dev(c.vol), dev(c.lam), dev(c.mu), c.h)
-    rt = ff.RowTiles(ctx, A.n, A.row_ptr, A.col, A.H, A.M, precision=3)
+    rt = ff.RowTiles(ctx, A.n, A.row_ptr, A.col, A.H, A.M, precision=3 if rows == 8 else 4)
     ntiles, entries = rt.info()
-    assert ntiles == (c.n + 7) // 8
+    assert ntiles == (c.n + rows - 1) // rows
     rl = np.diff(P.row_ptr)
     assert rl.max() <= entries <= rl.sum()
-    # longest rounding chain: a lane group's share of a tile's entries (at most 8 rows, at
-    # least 8 groups), the butterfly's additions, the rounding of the values and of Y
-    eps = (rl.max() + 8) * 2.0 ** -24
-    for m in (8, 16, 32, 64):
+    # longest rounding chain: the entries one accumulator sums (a lane group's share of a
+    # tile, at most rows x the longest row over 8 groups, or a whole tile's union in the
+    # MFMA), the butterfly's additions, the rounding of the values and of Y
+    eps = ((rl.max() if rows == 8 else 16 * rl.max()) + 8) * 2.0 ** -24
+    for m in ((8, 16, 32, 64) if rows == 8 else (4, 8, 12, 16, 32, 64)):
         Y = np.random.default_rng(m).standard_normal((c.n, m))
         refH = oracle.spmm(P.row_ptr, P.col, P.H, Y)
         absH = oracle.spmm(P.row_ptr, P.col, np.abs(P.H), np.abs(Y))
@@ -223,7 +230,7 @@ def test_rowtiles_eight_row_h_copy(oracle, ctx, ff):
             assert np.all(np.abs(host(HO) - refH) <= eps * absH + 1e-300), (m, sub)
     Y = dev(np.ones((c.n, 24)), torch.float32)
     with pytest.raises(ff.FFError):
-        rt.spmm(Y, 1, 0, h_only=True)                      # 24 / 8 = 3 does not divide 64
+        rt.spmm(Y, 1, 0, h_only=True)                      # a width neither kernel takes
     with pytest.raises(ff.FFError):
         rt.spmm(dev(np.ones((c.n, 32)), torch.float32), 1, 0)   # MY requested
     rt.close()

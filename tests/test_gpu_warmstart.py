@@ -48,7 +48,7 @@ def test_training_lowers_the_loss(env):
     assert last < first - 0.5, (first, last)
 
 
-def test_warm_start_reaches_the_same_eigenpairs_in_fewer_iterations(env):
+def _ratios(env, precond):
     ff, ws, ctx, net, train, tests, log = env
     m = K
     ratios = []
@@ -58,7 +58,7 @@ def test_warm_start_reaches_the_same_eigenpairs_in_fewer_iterations(env):
         its = {}
         for mode in ("random", "warm"):
             X0, used = ws.warm_block(ctx, net if mode == "warm" else None, s, m, seed=1, fallback=False)
-            lam, W, info = ws.solve(ctx, s, K, X0=X0, precision=1, tol=1e-6)
+            lam, W, info = ws.solve(ctx, s, K, X0=X0, precision=1, tol=1e-6, precond=precond)
             assert info["converged"] == 1 and info["max_resid"] <= 1e-6
             # Ritz values bound the eigenvalues from above; residual 1e-6 allowed at most 1.1e-4 of lambda_max on these shapes
             assert np.all(lam[1:] >= ref[1:] * (1 - 1e-7))
@@ -66,8 +66,24 @@ def test_warm_start_reaches_the_same_eigenpairs_in_fewer_iterations(env):
             assert np.abs(lam[1:] - ref[1:]).max() <= 1e-3 * ref[1:].max()
             its[mode] = info["iters_fp32"] + info["iters_fp64"]
         ratios.append(its["warm"] / its["random"])
-    print("warm/random iteration ratios", ratios)
+    print("precond", precond, "warm/random iteration ratios", ratios)
+    return ratios
+
+
+def test_warm_start_reaches_the_same_eigenpairs_in_fewer_iterations(env):
+    """With the Jacobi preconditioner (several hundred iterations from a random start)
+    the network's block saves iterations."""
+    ratios = _ratios(env, precond=1)
     assert np.mean(ratios) < 1.0, ratios
+
+
+def test_warm_start_with_chebyshev_preconditioner(env):
+    """With the default Chebyshev-Jacobi preconditioner convergence takes a few dozen
+    iterations from any start and the network's block gains nothing measurable
+    (measured mean ratio 1.01 on these shapes); it must still reach the same
+    eigenpairs and cost no more than a few iterations."""
+    ratios = _ratios(env, precond=2)
+    assert np.mean(ratios) <= 1.15, ratios
 
 
 def test_fallback_keeps_the_block_with_the_lower_ritz_sum(env):
