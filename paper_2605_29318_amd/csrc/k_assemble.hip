@@ -55,12 +55,18 @@ __device__ inline int wave_sum_i32(int v) {
 // Runs of candidate columns for row k; returns the window size (sum of run lengths).
 __device__ int64_t build_window(int64_t k, const int64_t *cs, GridI g, Win *win) {
     const int lane = threadIdx.x & 63;
-    int64_t lo = 0, hi = g.ncell - 1;           // last cell c with cs[c] <= k
-    while (lo < hi) {
-        int64_t mid = (lo + hi + 1) >> 1;
-        if (cs[mid] <= k) lo = mid; else hi = mid - 1;
+    // last cell c with cs[c] <= k, by a 64-way search (cs is non-decreasing and cs[0] = 0 <= k)
+    int64_t lo = 0, hi = g.ncell - 1;
+    while (hi - lo >= 64) {
+        const int64_t step = (hi - lo + 64) / 64;
+        const int64_t probe = lo + lane * step;
+        const uint64_t ok = __ballot(probe <= hi && cs[probe] <= k);
+        const int last = 63 - __clzll(ok);
+        lo += last * step;
+        hi = lo + step - 1 < hi ? lo + step - 1 : hi;
     }
-    const int64_t c = lo;
+    const uint64_t okf = __ballot(lo + lane <= hi && cs[lo + lane] <= k);
+    const int64_t c = lo + (63 - __clzll(okf));
     const int64_t cx = c % g.d[0], cy = (c / g.d[0]) % g.d[1], cz = c / (g.d[0] * g.d[1]);
     int64_t start = 0, len = 0;
     if (lane < 25) {
@@ -110,19 +116,55 @@ __device__ inline int64_t global_of(int x, const Win *w) {
     return w->start[lo] + (int64_t)(x - w->base[lo]);
 }
 
-// mark the columns of row k in the bitmap
+// mark the columns of row k in the bitmap. The row's transpose entries (i, and
+// the range of N(i)) are read by the lanes in one pass; the neighbour ids of
+// entry j + 1 are requested before entry j is marked.
 __device__ inline void mark_row(int64_t k, const int64_t *nt_off, const int2 *nt, const int64_t *off,
                                 const int32_t *ids, const Win *win, uint32_t *bm, int nwords) {
     const int lane = threadIdx.x & 63;
     for (int w = lane; w < nwords; w += 64) bm[w] = 0u;
     __builtin_amdgcn_wave_barrier();
     const int64_t a = nt_off[k], b = nt_off[k + 1];
-    for (int64_t e = a; e < b; ++e) {
-        const int64_t i = nt[e].x;
-        const int64_t f1 = off[i + 1];
-        for (int64_t f = off[i] + lane; f < f1; f += 64) {
-            const int x = local_of(ids[f], win);
-            if (x >= 0 && x < win->base[win->nr]) atomicOr(&bm[x >> 5], 1u << (x & 31));
+    const int wend = win->base[win->nr];
+    for (int64_t e0 = a; e0 < b; e0 += 64) {
+        const int cnt = (int)(b - e0 < 64 ? b - e0 : 64);
+        int64_t f0 = 0, f1 = 0;
+        if (lane < cnt) {
+            const int64_t i = nt[e0 + lane].x;
+            f0 = off[i];
+            f1 = off[i + 1];
+        }
+        int32_t idA = -1, idB = -1;
+        {
+            const int64_t s0 = __shfl(f0, 0, 64), s1 = __shfl(f1, 0, 64);
+            if (s0 + lane < s1) idA = ids[s0 + lane];
+        }
+        for (int j = 0; j < cnt; j += 2) {
+            int64_t s0, s1;
+            if (j + 1 < cnt) {
+                s0 = __shfl(f0, j + 1, 64);
+                s1 = __shfl(f1, j + 1, 64);
+                idB = s0 + lane < s1 ? ids[s0 + lane] : -1;
+            }
+            s0 = __shfl(f0, j, 64);
+            s1 = __shfl(f1, j, 64);
+            for (int64_t f = s0 + lane; f < s1; f += 64) {
+                const int32_t id = f == s0 + lane ? idA : ids[f];
+                const int x = local_of(id, win);
+                if (x >= 0 && x < wend) atomicOr(&bm[x >> 5], 1u << (x & 31));
+            }
+            if (j + 1 >= cnt) break;
+            if (j + 2 < cnt) {
+                const int64_t t0 = __shfl(f0, j + 2, 64), t1 = __shfl(f1, j + 2, 64);
+                idA = t0 + lane < t1 ? ids[t0 + lane] : -1;
+            }
+            s0 = __shfl(f0, j + 1, 64);
+            s1 = __shfl(f1, j + 1, 64);
+            for (int64_t f = s0 + lane; f < s1; f += 64) {
+                const int32_t id = f == s0 + lane ? idB : ids[f];
+                const int x = local_of(id, win);
+                if (x >= 0 && x < wend) atomicOr(&bm[x >> 5], 1u << (x & 31));
+            }
         }
     }
     __builtin_amdgcn_wave_barrier();
@@ -149,20 +191,43 @@ __global__ void __launch_bounds__(256) nt_fill_kernel(const int64_t *off, const 
     }
 }
 
+// NT(k) in ascending i (the i are distinct within a list): one wavefront per
+// node copies its list to LDS and writes each entry at its rank; lists longer
+// than kSortMax fall back to an insertion sort by one lane.
+constexpr int kSortMax = 1024;
 __global__ void __launch_bounds__(256) nt_sort_kernel(const int64_t *nt_off, int64_t n, int2 *nt,
                                                       unsigned long long *empty_node) {
-    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ int2 buf[4][kSortMax];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     if (k >= n) return;
     const int64_t a = nt_off[k], b = nt_off[k + 1];
-    if (a == b) atomicMin(empty_node, (unsigned long long)k);
-    for (int64_t j = a + 1; j < b; ++j) {
-        const int2 v = nt[j];
-        int64_t t = j - 1;
-        while (t >= a && nt[t].x > v.x) {
-            nt[t + 1] = nt[t];
-            --t;
-        }
-        nt[t + 1] = v;
+    const int64_t cnt = b - a;
+    if (cnt == 0) {
+        if (lane == 0) atomicMin(empty_node, (unsigned long long)k);
+        return;
+    }
+    if (cnt > kSortMax) {
+        if (lane == 0)
+            for (int64_t j = a + 1; j < b; ++j) {
+                const int2 v = nt[j];
+                int64_t t = j - 1;
+                while (t >= a && nt[t].x > v.x) {
+                    nt[t + 1] = nt[t];
+                    --t;
+                }
+                nt[t + 1] = v;
+            }
+        return;
+    }
+    int2 *bw = buf[wv];
+    for (int t = lane; t < cnt; t += 64) bw[t] = nt[a + t];
+    __builtin_amdgcn_wave_barrier();
+    for (int t = lane; t < cnt; t += 64) {
+        const int2 v = bw[t];
+        int r = 0;
+        for (int u = 0; u < cnt; ++u) r += bw[u].x < v.x;
+        nt[a + r] = v;
     }
 }
 
@@ -255,27 +320,84 @@ __global__ void __launch_bounds__(256) num_kernel(int64_t n, const int64_t *cs, 
     }
     __builtin_amdgcn_wave_barrier();
 
+    // the row's transpose entries: i, the range of N(i), grad phi_k(X_i), phi_k(X_i) and the
+    // weights, read by the lanes in one pass; entry j + 1's neighbour data is requested
+    // before entry j is accumulated. Entries are accumulated in ascending i, each term as
+    // written, so every entry is the same ordered sum on every run.
     const int64_t a = nt_off[k], b = nt_off[k + 1];
-    for (int64_t e = a; e < b; ++e) {
-        const int2 ent = nt[e];
-        const int64_t i = ent.x;
-        const int64_t ek = off[i] + ent.y;
-        const double gk0 = dphi[3 * ek], gk1 = dphi[3 * ek + 1], gk2 = dphi[3 * ek + 2];
-        const double pk = phi[ek];
-        const int64_t ii = perm ? (int64_t)perm[i] : i;
-        const double wi = vol[ii] * (lam[ii] + 4.0 * mu[ii]);
-        const double mi = rho ? vol[ii] * rho[ii] : vol[ii];
-        const int64_t f1 = off[i + 1];
-        for (int64_t f = off[i] + lane; f < f1; f += 64) {
-            const int x = local_of(ids[f], win);
-            if (x < 0 || x >= win->base[win->nr]) continue;
-            const uint32_t word = bm[x >> 5];
-            const int r = pre[x >> 5] + __popc(word & ((1u << (x & 31)) - 1u));
-            const double dot = ((gk0 * dphi[3 * f]) + (gk1 * dphi[3 * f + 1])) + (gk2 * dphi[3 * f + 2]);
-            aH[r] += wi * dot;
-            aM[r] += mi * (pk * phi[f]);
+    const int wend = win->base[win->nr];
+    for (int64_t e0 = a; e0 < b; e0 += 64) {
+        const int cnt = (int)(b - e0 < 64 ? b - e0 : 64);
+        int64_t f0 = 0, f1 = 0;
+        double q0 = 0.0, q1 = 0.0, q2 = 0.0, qp = 0.0, qw = 0.0, qm = 0.0;
+        if (lane < cnt) {
+            const int2 ent = nt[e0 + lane];
+            const int64_t i = ent.x;
+            f0 = off[i];
+            f1 = off[i + 1];
+            const int64_t ek = f0 + ent.y;
+            q0 = dphi[3 * ek];
+            q1 = dphi[3 * ek + 1];
+            q2 = dphi[3 * ek + 2];
+            qp = phi[ek];
+            const int64_t ii = perm ? (int64_t)perm[i] : i;
+            qw = vol[ii] * (lam[ii] + 4.0 * mu[ii]);
+            qm = rho ? vol[ii] * rho[ii] : vol[ii];
         }
-        __builtin_amdgcn_wave_barrier();
+        // first 64 neighbours of an entry, requested ahead
+        struct Pre { int32_t id; double d0, d1, d2, p; };
+        auto fetch = [&](int j, Pre &P) {
+            const int64_t s0 = __shfl(f0, j, 64), s1 = __shfl(f1, j, 64);
+            const int64_t f = s0 + lane;
+            P.id = -1;
+            P.d0 = P.d1 = P.d2 = P.p = 0.0;
+            if (f < s1) {
+                P.id = ids[f];
+                P.d0 = dphi[3 * f];
+                P.d1 = dphi[3 * f + 1];
+                P.d2 = dphi[3 * f + 2];
+                P.p = phi[f];
+            }
+        };
+        auto accumulate = [&](int j, const Pre &P) {
+            const int64_t s0 = __shfl(f0, j, 64), s1 = __shfl(f1, j, 64);
+            const double gk0 = __shfl(q0, j, 64), gk1 = __shfl(q1, j, 64), gk2 = __shfl(q2, j, 64);
+            const double pk = __shfl(qp, j, 64), wi = __shfl(qw, j, 64), mi = __shfl(qm, j, 64);
+            for (int64_t f = s0 + lane; f < s1; f += 64) {
+                int32_t id;
+                double d0, d1, d2, pf;
+                if (f == s0 + lane) {
+                    id = P.id;
+                    d0 = P.d0;
+                    d1 = P.d1;
+                    d2 = P.d2;
+                    pf = P.p;
+                } else {
+                    id = ids[f];
+                    d0 = dphi[3 * f];
+                    d1 = dphi[3 * f + 1];
+                    d2 = dphi[3 * f + 2];
+                    pf = phi[f];
+                }
+                const int x = local_of(id, win);
+                if (x < 0 || x >= wend) continue;
+                const uint32_t word = bm[x >> 5];
+                const int r = pre[x >> 5] + __popc(word & ((1u << (x & 31)) - 1u));
+                const double dot = ((gk0 * d0) + (gk1 * d1)) + (gk2 * d2);
+                aH[r] += wi * dot;
+                aM[r] += mi * (pk * pf);
+            }
+            __builtin_amdgcn_wave_barrier();
+        };
+        Pre PA, PB;
+        fetch(0, PA);
+        for (int j = 0; j < cnt; j += 2) {
+            if (j + 1 < cnt) fetch(j + 1, PB);
+            accumulate(j, PA);
+            if (j + 1 >= cnt) break;
+            if (j + 2 < cnt) fetch(j + 2, PA);
+            accumulate(j + 1, PB);
+        }
     }
     for (int t = lane; t < len; t += 64) {
         const double h = aH[t], m = aM[t];
@@ -337,7 +459,7 @@ extern "C" int assemble_HM(ff_ctx *ctx, int64_t n, int64_t q, const int64_t *nbr
     hipLaunchKernelGGL(nt_fill_kernel, dim3(grid_for(q, 256)), dim3(256), 0, st, nbr_off, nbr_id, q, nt_off, cursor,
                        nt);
     FF_CHECK_LAUNCH(ctx);
-    hipLaunchKernelGGL(nt_sort_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, nt_off, n, nt, empty_node);
+    hipLaunchKernelGGL(nt_sort_kernel, dim3(grid_for(n, 4)), dim3(256), 0, st, nt_off, n, nt, empty_node);
     FF_CHECK_LAUNCH(ctx);
 
     GridI g;
