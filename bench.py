@@ -4,7 +4,9 @@ One step is the whole subspace-construction path on one synthetic object:
 cell binning and neighbour lists, RKPM shape functions, assembly of H and M,
 and the mixed-precision LOBPCG (FP32 products, FP64 Rayleigh-Ritz, FP64
 certification) to residual 1e-6. Inputs are generated on the host once and
-are resident in HBM before the timed region.
+are resident in HBM before the timed region. Step s starts the eigensolver
+from the seeded random block of seed s (the iteration count depends on the
+start), so the reported time is a mean over starts.
 
 Workload: 1,000,000 particles drawn uniformly inside a seeded union of 20
 random ellipsoids (semi-axes U(0.05, 0.4)) clipped to the unit box,
@@ -38,7 +40,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_step(ff, ctx, dev_in, n, h, k, precision, tol, max_iter, use_graph=False):
+def run_step(ff, ctx, dev_in, n, h, k, precision, tol, max_iter, use_graph=False, seed=0):
     import torch
     xyz, vol, lam, mu = dev_in
     torch.cuda.synchronize()
@@ -48,7 +50,7 @@ def run_step(ff, ctx, dev_in, n, h, k, precision, tol, max_iter, use_graph=False
     t1 = time.perf_counter()
     ev, W, res, info = ff.eigenmodes(ctx, n, A.row_ptr, A.col, A.H, A.M, A.hm32, k=k, precision=precision,
                                      tol=tol, max_iter=max_iter, use_graph=use_graph, allow_unconverged=True,
-                                     precond=PRECOND, precond_degree=PRECOND_DEGREE)
+                                     precond=PRECOND, precond_degree=PRECOND_DEGREE, seed=seed)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     return dict(total=t2 - t0, build=t1 - t0, solve=t2 - t1, ev=ev, res=res, info=info, A=A, W=W)
@@ -152,7 +154,7 @@ def cpu_baseline(n_sample, k, iters, gpu_iters, n_full):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--k", type=int, default=32)
@@ -185,7 +187,7 @@ def main():
     ctx = ff.Context(0)
 
     for w in range(args.warmup):
-        r = run_step(ff, ctx, dev_in, c.n, c.h, args.k, 1, args.tol, args.max_iter, args.graph)
+        r = run_step(ff, ctx, dev_in, c.n, c.h, args.k, 1, args.tol, args.max_iter, args.graph, seed=1000 + w)
         log(f"[bench] warmup {w}: {r['total']:.3f} s (build {r['build']:.3f}, solve {r['solve']:.3f}), "
             f"iters {r['info']['iters_fp32']}+{r['info']['iters_fp64']}")
     torch.cuda.synchronize()
@@ -193,9 +195,13 @@ def main():
     last = None
     ctx.set_stage_timing(True)
     t_start = time.perf_counter()
+    step_iters = []
     for s in range(args.steps):
-        last = run_step(ff, ctx, dev_in, c.n, c.h, args.k, 1, args.tol, args.max_iter, args.graph)
+        # step s starts LOBPCG from the seeded random block of seed s: the iteration count of a
+        # solve depends on its start (the last pair's convergence), so the steps average over starts
+        last = run_step(ff, ctx, dev_in, c.n, c.h, args.k, 1, args.tol, args.max_iter, args.graph, seed=s)
         times.append(last["total"])
+        step_iters.append(last["info"]["iters_fp32"] + last["info"]["iters_fp64"])
         log(f"[bench] step {s}: {last['total']:.3f} s (build {last['build']:.3f}, solve {last['solve']:.3f}), "
             f"iters {last['info']['iters_fp32']}+{last['info']['iters_fp64']}, max resid {last['res'].max():.2e}")
     torch.cuda.synchronize()
@@ -208,7 +214,8 @@ def main():
 
     fp64 = None
     if not args.no_fp64:
-        r64 = run_step(ff, ctx, dev_in, c.n, c.h, args.k, 0, args.tol, args.max_iter, args.graph)
+        r64 = run_step(ff, ctx, dev_in, c.n, c.h, args.k, 0, args.tol, args.max_iter, args.graph,
+                       seed=args.steps - 1)
         rel = np.abs(last["ev"][1:] - r64["ev"][1:]) / np.abs(r64["ev"][1:])
         fp64 = dict(seconds=round(r64["total"], 3), iters=r64["info"]["iters_fp64"],
                     max_resid=float(r64["res"].max()), converged=bool(r64["info"]["converged"]),
@@ -232,7 +239,7 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        gpu_iters = last["info"]["iters_fp32"] + last["info"]["iters_fp64"]
+        gpu_iters = int(round(sum(step_iters) / len(step_iters)))
         cpu = cpu_baseline(50_000, args.k, 10, gpu_iters, c.n)
         log(f"[bench] cpu baseline: {cpu}")
 
@@ -257,6 +264,8 @@ def main():
         "build_s": round(last["build"], 4),
         "solve_s": round(last["solve"], 4),
         "iters": {"fp32": info["iters_fp32"], "fp64": info["iters_fp64"]},
+        "iters_per_step": step_iters,
+        "start_seeds": list(range(args.steps)),
         "max_resid": float(last["res"].max()),
         "converged": bool(info["converged"]),
         "fp64": fp64,

@@ -98,8 +98,12 @@ typedef struct {
  *             points are the nodes themselves, in sorted order (q must be n)
  *  grid       host out: the cell grid
  *  perm       [n] device out: perm[j] = original index of sorted node j.
- *             Nodes are sorted by cell id (z, y, x with x fastest), ties by
- *             original index (a stable counting sort).
+ *             Nodes are sorted by cell id (z, y, x with x fastest), then by
+ *             the Morton code of their sub-cell (each axis of the cell split
+ *             in 4: s_a = clamp(floor((t_a - q_a) * 4), 0, 3), t_a = (x_a -
+ *             o_a) / h, q_a the cell coordinate; bits interleaved x, y, z from
+ *             the lowest), ties by original index. Consecutive sorted nodes
+ *             are then spatially close, which the SpMM's row tiles exploit.
  *  xyz_sorted [n][3] device out: xyz[perm[j]]
  *  cell_start [n_cells + 1] device out, or NULL on the sizing call: sorted
  *             nodes of cell c are cell_start[c] .. cell_start[c+1]-1

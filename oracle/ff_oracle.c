@@ -12,7 +12,8 @@
  * point decides (cell index, neighbour predicate) are reproducible.
  *
  * Steps and the passages they follow:
- *   orc_grid / orc_bin      uniform cell list (the paper has none; cell size = support radius)
+ *   orc_grid / orc_bin      uniform cell list (the paper has none; cell size = support radius),
+ *                           nodes ordered by cell, then by a Morton code of 4x4x4 sub-cells
  *   orc_neighbors           support of the compact kernel: d^2 < h^2
  *   orc_neighbors_brute     the same predicate by exhaustive search (pin)
  *   orc_rkpm                RKPM shape functions and gradients, Sec. 3.2 Eq. (7)-(11)
@@ -71,22 +72,52 @@ static int64_t cell_of(const double *p, const double *o, double h, const int64_t
     return (cz * D[1] + cy) * D[0] + cx;
 }
 
-/* Stable counting sort of the nodes by cell id (x fastest):
+/* sub-cell index of a node inside its cell along one axis: the cell split in 4,
+ * s_a = min(max(floor((t_a - q_a) * 4), 0), 3) with t_a = (x_a - o_a)/h and q_a the
+ * (clamped) cell coordinate */
+static int64_t sub_coord(double x, double o, double h, int64_t D)
+{
+    double t = (x - o) / h;
+    double q = floor(t);
+    if (q < 0.0) q = 0.0;
+    if (q > (double)(D - 1)) q = (double)(D - 1);
+    double s = floor((t - q) * 4.0);
+    if (s < 0.0) s = 0.0;
+    if (s > 3.0) s = 3.0;
+    return (int64_t)s;
+}
+
+/* Morton code of the node's sub-cell: the three 2-bit sub-cell indices
+ * interleaved, x in the lowest bit of each triple */
+static int64_t subcell_code(const double *p, const double *o, double h, const int64_t *D)
+{
+    int64_t sx = sub_coord(p[0], o[0], h, D[0]);
+    int64_t sy = sub_coord(p[1], o[1], h, D[1]);
+    int64_t sz = sub_coord(p[2], o[2], h, D[2]);
+    int64_t code = 0;
+    for (int b = 0; b < 2; ++b)
+        code |= (((sx >> b) & 1) << (3 * b)) | (((sy >> b) & 1) << (3 * b + 1)) | (((sz >> b) & 1) << (3 * b + 2));
+    return code;
+}
+
+/* Stable counting sort of the nodes by (cell id (x fastest), sub-cell code):
  * perm[j] = original index of the j-th node in sorted order,
- * cell_start[c] .. cell_start[c+1]-1 = the sorted nodes of cell c. */
+ * cell_start[c] .. cell_start[c+1]-1 = the sorted nodes of cell c, in ascending
+ * sub-cell code, then original index. */
 int orc_bin(int64_t n, const double *xyz, double h, const double *origin, const int64_t *dims,
             int32_t *perm, int64_t *cell_start)
 {
     int64_t ncell = dims[0] * dims[1] * dims[2];
-    int64_t *cursor = (int64_t *)calloc((size_t)ncell + 1, sizeof(int64_t));
+    int64_t nkey = ncell * 64;
+    int64_t *cursor = (int64_t *)calloc((size_t)nkey + 1, sizeof(int64_t));
     int64_t *key = (int64_t *)malloc((size_t)n * sizeof(int64_t));
     if (!cursor || !key) { free(cursor); free(key); return ORC_ERR_ARG; }
     for (int64_t i = 0; i < n; ++i) {
-        key[i] = cell_of(xyz + 3 * i, origin, h, dims);
+        key[i] = cell_of(xyz + 3 * i, origin, h, dims) * 64 + subcell_code(xyz + 3 * i, origin, h, dims);
         cursor[key[i] + 1] += 1;
     }
-    for (int64_t c = 0; c < ncell; ++c) cursor[c + 1] += cursor[c];
-    memcpy(cell_start, cursor, (size_t)(ncell + 1) * sizeof(int64_t));
+    for (int64_t c = 0; c < nkey; ++c) cursor[c + 1] += cursor[c];
+    for (int64_t c = 0; c <= ncell; ++c) cell_start[c] = cursor[c * 64];
     for (int64_t i = 0; i < n; ++i) perm[cursor[key[i]]++] = (int32_t)i;
     free(cursor);
     free(key);

@@ -104,7 +104,8 @@ def grid(xyz, h):
 
 
 def bin_nodes(xyz, h):
-    """Stable counting sort of the nodes by cell. Returns perm, cell_start, origin, dims."""
+    """Counting sort of the nodes by (cell, Morton code of the 4x4x4 sub-cell, original
+    index). Returns perm, cell_start, origin, dims."""
     xyz = _c(xyz, np.float64)
     origin, dims = grid(xyz, h)
     n = xyz.shape[0]

@@ -2264,9 +2264,16 @@ int run_phase(Solver &s, T *S, T *HS, T *MS, int max_iters, double tol, int stal
             std::vector<double> rs((size_t)s.m);
             if (hipMemcpy(rs.data(), s.res, rs.size() * sizeof(double), hipMemcpyDeviceToHost) == hipSuccess) {
                 double mx = 0.0;
-                for (int j = 0; j < s.k; ++j) mx = std::max(mx, rs[j]);
-                fprintf(stderr, "[freeform] %s it %d: object 0 max resid %.3e status %d\n",
-                        sizeof(T) == 4 ? "fp32" : "fp64", it, mx, hstat[0]);
+                int jmax = 0, above = 0;
+                for (int j = 0; j < s.k; ++j) {
+                    if (rs[j] > mx) {
+                        mx = rs[j];
+                        jmax = j;
+                    }
+                    above += rs[j] > tol;
+                }
+                fprintf(stderr, "[freeform] %s it %d: object 0 max resid %.3e (pair %d, %d above tol) status %d\n",
+                        sizeof(T) == 4 ? "fp32" : "fp64", it, mx, jmax, above, hstat[0]);
             }
         }
         if (all) break;

@@ -207,8 +207,24 @@ __device__ inline int64_t axis_cell(double x, double o, double h, int64_t D) {
     return (int64_t)t;
 }
 
+// Sub-cell index along one axis: the cell split in 4, s = clamp(floor((t - q) * 4), 0, 3)
+// with t = (x - o)/h and q the clamped cell coordinate (t - q and the product are exact).
+__device__ inline int axis_sub(double x, double o, double h, int64_t D) {
+    const double t = (x - o) / h;
+    double q = floor(t);
+    q = q < 0.0 ? 0.0 : q;
+    const double top = (double)(D - 1);
+    q = q > top ? top : q;
+    double s = floor((t - q) * 4.0);
+    s = s < 0.0 ? 0.0 : (s > 3.0 ? 3.0 : s);
+    return (int)s;
+}
+
+// Cell of each node and the Morton code (x lowest) of its 4x4x4 sub-cell: nodes
+// are ordered by cell, then sub-cell, so consecutive rows are spatially compact
+// (the SpMM's row tiles share more columns).
 __global__ void __launch_bounds__(256) cell_key_kernel(const double *xyz, int64_t n, GridDev g, int32_t *key,
-                                                       int32_t *count) {
+                                                       int32_t *count, int32_t *sub) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int64_t cx = axis_cell(xyz[3 * i + 0], g.o[0], g.h, g.d[0]);
@@ -216,11 +232,19 @@ __global__ void __launch_bounds__(256) cell_key_kernel(const double *xyz, int64_
     int64_t cz = axis_cell(xyz[3 * i + 2], g.o[2], g.h, g.d[2]);
     int32_t c = (int32_t)((cz * g.d[1] + cy) * g.d[0] + cx);
     key[i] = c;
+    const int sx = axis_sub(xyz[3 * i + 0], g.o[0], g.h, g.d[0]);
+    const int sy = axis_sub(xyz[3 * i + 1], g.o[1], g.h, g.d[1]);
+    const int sz = axis_sub(xyz[3 * i + 2], g.o[2], g.h, g.d[2]);
+    int code = 0;
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+        code |= (((sx >> b) & 1) << (3 * b)) | (((sy >> b) & 1) << (3 * b + 1)) | (((sz >> b) & 1) << (3 * b + 2));
+    sub[i] = code;
     atomicAdd(&count[c], 1);
 }
 
 // Unordered placement into the cell's slot range; the per-cell sort below
-// restores the stable (cell, original index) order deterministically.
+// restores the (cell, sub-cell code, original index) order deterministically.
 __global__ void __launch_bounds__(256) cell_scatter_kernel(const int32_t *key, int64_t n, const int64_t *cell_start,
                                                            int32_t *cursor, int32_t *perm) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -231,7 +255,7 @@ __global__ void __launch_bounds__(256) cell_scatter_kernel(const int32_t *key, i
 }
 
 __global__ void __launch_bounds__(256) cell_sort_kernel(const int64_t *cell_start, int64_t ncell, int32_t *perm,
-                                                        int *too_full) {
+                                                        const int32_t *sub, int *too_full) {
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncell) return;
     int64_t a = cell_start[c], b = cell_start[c + 1];
@@ -240,9 +264,10 @@ __global__ void __launch_bounds__(256) cell_sort_kernel(const int64_t *cell_star
         return;
     }
     for (int64_t j = a + 1; j < b; ++j) {
-        int32_t v = perm[j];
+        const int32_t v = perm[j];
+        const int64_t kv = ((int64_t)sub[v] << 32) | (uint32_t)v;
         int64_t t = j - 1;
-        while (t >= a && perm[t] > v) {
+        while (t >= a && (((int64_t)sub[perm[t]] << 32) | (uint32_t)perm[t]) > kv) {
             perm[t + 1] = perm[t];
             --t;
         }
@@ -383,16 +408,18 @@ extern "C" int build_neighbors(ff_ctx *ctx, int64_t n, const double *xyz, int64_
     int32_t *key = (int32_t *)ws_get(ctx, WS_KEYS, (size_t)n * sizeof(int32_t));
     int32_t *count = (int32_t *)ws_get(ctx, WS_COUNTS, (size_t)(ncell > q ? ncell : q) * sizeof(int32_t));
     int32_t *cursor = (int32_t *)ws_get(ctx, WS_CURSOR, (size_t)ncell * sizeof(int32_t));
-    if (!key || !count || !cursor) return FF_ERR_OOM;
+    int32_t *sub = (int32_t *)ws_get(ctx, WS_SUBCELL, (size_t)n * sizeof(int32_t));
+    if (!key || !count || !cursor || !sub) return FF_ERR_OOM;
     FF_HIP(ctx, hipMemsetAsync(count, 0, (size_t)ncell * sizeof(int32_t), st));
     FF_HIP(ctx, hipMemsetAsync(cursor, 0, (size_t)ncell * sizeof(int32_t), st));
-    hipLaunchKernelGGL(cell_key_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, xyz, n, g, key, count);
+    hipLaunchKernelGGL(cell_key_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, xyz, n, g, key, count, sub);
     FF_CHECK_LAUNCH(ctx);
     int rc = scan_exclusive_i32_to_i64(ctx, count, cs, ncell);
     if (rc) return rc;
     hipLaunchKernelGGL(cell_scatter_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, key, n, cs, cursor, perm);
     FF_CHECK_LAUNCH(ctx);
-    hipLaunchKernelGGL(cell_sort_kernel, dim3(grid_for(ncell, 256)), dim3(256), 0, st, cs, ncell, perm, flag + 2);
+    hipLaunchKernelGGL(cell_sort_kernel, dim3(grid_for(ncell, 256)), dim3(256), 0, st, cs, ncell, perm, sub,
+                       flag + 2);
     FF_CHECK_LAUNCH(ctx);
     hipLaunchKernelGGL(gather_xyz_kernel, dim3(grid_for(3 * n, 256)), dim3(256), 0, st, xyz, perm, n, xyz_sorted);
     FF_CHECK_LAUNCH(ctx);

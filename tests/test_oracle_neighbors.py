@@ -1,7 +1,8 @@
 """Pins of the oracle's cell binning and neighbour lists (CPU only).
 
 Binning is checked against the definition of a cell (a box of edge h from the
-origin) and of a stable sort; the cell-list neighbour search is checked
+origin), of its 4x4x4 sub-cells and of the (cell, sub-cell Morton code, original
+index) order; the cell-list neighbour search is checked
 against exhaustive search and against scipy's KD-tree.
 """
 import numpy as np
@@ -20,7 +21,7 @@ def _clouds():
 
 
 @pytest.mark.parametrize("ci", range(4))
-def test_binning_is_stable_cell_sort(oracle, ci):
+def test_binning_orders_by_cell_and_subcell(oracle, ci):
     c = list(_clouds())[ci]
     perm, cs, origin, dims = oracle.bin_nodes(c.xyz, c.h)
     n = c.n
@@ -42,10 +43,21 @@ def test_binning_is_stable_cell_sort(oracle, ci):
     assert np.all((x < hi + eps) | last)
     # the grid just covers the nodes
     assert np.all(origin + (dims - 1) * c.h <= c.xyz.max(axis=0) + eps)
-    # stable: inside a cell the original indices ascend
+    # inside a cell: ascending Morton code of the 4x4x4 sub-cell, ties by original index;
+    # each node lies in its sub-cell's box (the last sub-cell of a clamped axis is closed)
+    t = (c.xyz[perm] - origin) / c.h
+    q = np.clip(np.floor(t), 0, dims - 1)
+    sub = np.clip(np.floor((t - q) * 4.0), 0, 3).astype(np.int64)
+    code = np.zeros(n, dtype=np.int64)
+    for b in range(2):
+        for a in range(3):
+            code |= ((sub[:, a] >> b) & 1) << (3 * b + a)
+    slo = lo + sub * (c.h / 4)
+    assert np.all(x >= slo - eps)
+    assert np.all((x < slo + c.h / 4 + eps) | (sub == 3))
     for a, b in zip(cs[:-1], cs[1:]):
-        seg = perm[a:b]
-        assert np.all(np.diff(seg) > 0)
+        key = code[a:b] * (n + 1) + perm[a:b]
+        assert np.all(np.diff(key) > 0)
 
 
 @pytest.mark.parametrize("ci", range(4))
