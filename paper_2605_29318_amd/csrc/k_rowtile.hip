@@ -693,16 +693,18 @@ __device__ __forceinline__ void t8_chunk(Chunk8 &ch, int64_t base, int64_t e1, c
     ch.stage(sv, lane);
     __builtin_amdgcn_wave_barrier();
     ch.load(tcol, vh, base + 64 * kAhead + lane, base + 64 * kAhead + lane < e1);
+    (void)cnt;
+    // entries past the chunk's end have column 0 and zero values: their loads are valid and
+    // add nothing, so the loads carry no per-lane condition (a conditional load into a
+    // register the previous step loaded makes the wave wait for every load in flight)
     for (int s0 = 0; s0 < steps; s0 += kBatch) {
         f32x4 x[kBatch][2];
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
-            const int src = (s0 + u) * NG + g;
-            const int32_t j = __shfl(jc, src < 64 ? src : 63, 64);
-            const bool ok = (s0 + u < steps) && src < cnt;
-            x[u][0] = x[u][1] = f32x4{0.f, 0.f, 0.f, 0.f};
-            if (ok) {
-                const float *yp = Y + (int64_t)j * ldy + c * 8;
+            if (s0 + u < steps) {
+                const int src = (s0 + u) * NG + g;
+                const uint32_t j = (uint32_t)__shfl(jc, src, 64);
+                const float *yp = Y + (size_t)(j * (uint32_t)ldy) + c * 8;
                 x[u][0] = *(const f32x4 *)yp;
                 x[u][1] = *(const f32x4 *)(yp + 4);
             }
@@ -710,7 +712,7 @@ __device__ __forceinline__ void t8_chunk(Chunk8 &ch, int64_t base, int64_t e1, c
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
             const int src = (s0 + u) * NG + g;
-            if ((s0 + u < steps) && src < cnt) {
+            if (s0 + u < steps) {
                 const f32x4 h0 = *(const f32x4 *)(sv + src * 8), h1 = *(const f32x4 *)(sv + src * 8 + 4);
 #pragma unroll
                 for (int i = 0; i < kTile8; ++i) {
@@ -826,20 +828,25 @@ int launch_t8(ff_ctx *ctx, hipStream_t st, const RT8View &v, int sub, int m, con
 #define FF_T8(W, B, A, O, P)                                                                                \
     hipLaunchKernelGGL((spmm_t8_kernel<kEpi, W, B, A, O, P>), dim3(grid_for(v.ntiles, W)), dim3(64 * W), 0, st, \
                        v.n, v.ntiles, v.tptr, v.tcol, v.vh, Y, ldy, HY, ldo, m, row_obj, status, cs)
-    // measured on the benchmark workload (m = 32): 1.23 / 1.27 / 1.41 ms
+    // H-only product on the benchmark workload (m = 32): 1.18 / 1.24 ms for the first two
     switch (sub) {
-        case 1: FF_T8(2, 4, 2, 1, true); break;
-        case 2: FF_T8(4, 2, 2, 1, true); break;
-        default: FF_T8(4, 2, 1, 4, false); break;
+        case 1: FF_T8(4, 2, 2, 1, true); break;
+        case 2: FF_T8(4, 2, 1, 1, false); break;
+        default: FF_T8(2, 4, 2, 1, true); break;
     }
 #undef FF_T8
     FF_CHECK_LAUNCH(ctx);
     return FF_OK;
 }
 
+// the gathers index rows with 32-bit offsets
+inline bool off32_ok(int64_t n, int64_t ld) { return n * ld < ((int64_t)1 << 32); }
+
 int spmm_h_t8(ff_ctx *ctx, hipStream_t st, const RT8View &v, int sub, int m, const float *Y, int64_t ldy, float *HY,
               int64_t ldo, const int *row_obj, const int *status) {
     FF_REQUIRE(ctx, v.vh != nullptr && t8_ok(m, ldy, ldo), "eight-row tiles: bad copy or block shape (m = %d)", m);
+    FF_REQUIRE(ctx, off32_ok(v.n, ldy), "block of %lld rows x %lld too large for 32-bit row offsets", (long long)v.n,
+               (long long)ldy);
     return launch_t8<false>(ctx, st, v, sub, m, Y, ldy, HY, ldo, row_obj, status, ChebStep<float>{});
 }
 
@@ -847,6 +854,8 @@ int cheb_step_t8(ff_ctx *ctx, hipStream_t st, const RT8View &v, int sub, int m, 
                  const int *row_obj, const int *status, const ChebStep<float> &cs) {
     FF_REQUIRE(ctx, v.vh != nullptr && row_obj != nullptr && t8_ok(m, ld, ld) && cs.ldw % 4 == 0,
                "eight-row tiles: bad copy or block shape (m = %d)", m);
+    FF_REQUIRE(ctx, off32_ok(v.n, ld), "block of %lld rows x %lld too large for 32-bit row offsets", (long long)v.n,
+               (long long)ld);
     return launch_t8<true>(ctx, st, v, sub, m, DZ, ld, nullptr, ld, row_obj, status, cs);
 }
 
@@ -1161,23 +1170,28 @@ __device__ __forceinline__ void hm8_chunk(ChunkHM8 &ch, int64_t base, int64_t e1
     ch.stage(sv, lane);
     __builtin_amdgcn_wave_barrier();
     ch.load(tcol, vh, vm, base + 64 + lane, base + 64 + lane < e1);
-    const bool slot_ok = kMT > 1 || li < m;
+    // entries past the chunk's end have column 0 and zero values, and a masked slot (m < 16)
+    // reads column 0: every load is valid, so none carries a per-lane condition
+    const int col = kMT * (kMT > 1 || li < m ? li : 0);
     const int nq = (cnt + 3) >> 2;
     for (int q0 = 0; q0 < nq; q0 += kBatch) {
         YV y[kBatch];
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
-            const int e = 4 * (q0 + u) + lk;
-            const int32_t j = __shfl(jc, e < 64 ? e : 63, 64);
-            y[u] = YV{};
-            if (e < cnt && slot_ok) y[u] = *(const YV *)(Y + (int64_t)j * ldy + kMT * li);
+            if (q0 + u < nq) {
+                const int e = 4 * (q0 + u) + lk;
+                const uint32_t j = (uint32_t)__shfl(jc, e, 64);
+                y[u] = *(const YV *)(Y + (size_t)(j * (uint32_t)ldy) + col);
+            }
         }
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
-            const int e = 4 * (q0 + u) + lk;
-            const double a = (q0 + u < nq && e < cnt) ? (double)sv[e * 16 + li] : 0.0;
+            if (q0 + u < nq) {
+                const int e = 4 * (q0 + u) + lk;
+                const double a = (double)sv[e * 16 + li];
 #pragma unroll
-            for (int t = 0; t < kMT; ++t) d[t] = mfma64(a, (double)yget(y[u], t), d[t]);
+                for (int t = 0; t < kMT; ++t) d[t] = mfma64(a, (double)yget(y[u], t), d[t]);
+            }
         }
     }
 }
@@ -1231,6 +1245,8 @@ int spmm_hm8(ff_ctx *ctx, hipStream_t st, const RT8View &v, int sub, int m, cons
              float *MY, int64_t ldo, const int *row_obj, const int *status) {
     FF_REQUIRE(ctx, v.vh != nullptr && v.vm != nullptr && hm8_ok(m, ldy, ldo),
                "eight-row [H, M] tiles: bad copy or block shape (m = %d)", m);
+    FF_REQUIRE(ctx, off32_ok(v.n, ldy), "block of %lld rows x %lld too large for 32-bit row offsets", (long long)v.n,
+               (long long)ldy);
 #define FF_HM8(MT, W, B, O)                                                                                \
     hipLaunchKernelGGL((spmm_hm8_kernel<MT, W, B, O>), dim3(grid_for(v.ntiles, W)), dim3(64 * W), 0, st, v.n, \
                        v.ntiles, v.tptr, v.tcol, v.vh, v.vm, Y, ldy, HY, MY, ldo, m, row_obj, status)
