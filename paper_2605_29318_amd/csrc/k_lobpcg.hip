@@ -1614,6 +1614,8 @@ __global__ void diag_inv_bs_kernel(int64_t n, const int64_t *row_ptr, const int3
 
 constexpr int kChebCoef = 32;                  // per-object coefficient stride (degree <= 16)
 constexpr int kChebDefault = 8;                // degree when the caller passes 0
+constexpr int kChebT8Sub = 1;                  // launch shape of the fused step (fewer registers than the
+                                               // H-only product's default with the step's operands live)
 
 // Gershgorin bound of D^-1/2 H D^-1/2 per row: sum_j |H_ij| / sqrt(H_ii H_jj), one wavefront per row
 __global__ void gersh_row_kernel(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *H,
@@ -2061,8 +2063,9 @@ int stage_precond(Solver &s, T *S) {
             const int rc = s.rt16.vh ? rt::cheb_step_t16(s.ctx, s.st, s.rt16, 0, s.m,
                                                          (const float *)buf[(step - 1) & 1], s.m, s.row_obj, s.status,
                                                          cs)
-                                     : rt::cheb_step_t8(s.ctx, s.st, s.rt8, 0, s.m, (const float *)buf[(step - 1) & 1],
-                                                        s.m, s.row_obj, s.status, cs);
+                                     : rt::cheb_step_t8(s.ctx, s.st, s.rt8, kChebT8Sub, s.m,
+                                                        (const float *)buf[(step - 1) & 1], s.m, s.row_obj, s.status,
+                                                        cs);
             if (rc) return rc;
         }
         return FF_OK;
