@@ -259,7 +259,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "ellipsoids1m_hetero", "particles": c.n, "k": args.k, "tol": args.tol,
                    "nnz": nnz, "nnz_per_row": round(nnz / c.n, 1), "h": round(c.h, 6),
-                   "precond": "chebyshev-jacobi", "precond_degree": PRECOND_DEGREE or 8,
+                   "precond": "chebyshev-jacobi", "precond_degree": PRECOND_DEGREE or 12, "precond_ratio": 1000,
                    "graph": bool(args.graph)},
         "build_s": round(last["build"], 4),
         "solve_s": round(last["solve"], 4),

@@ -187,15 +187,17 @@ typedef struct {
     double tol;         /* max_j r_j over the first k pairs, r_j as in eigenmodes() */
     int max_iter;       /* total iteration cap (both phases) */
     int precond;        /* 0 = none, 1 = Jacobi diag(H)^-1, 2 = Chebyshev-Jacobi: q(D^-1 H) D^-1 with q the
-                           degree-d Chebyshev semi-iteration polynomial for D^-1 H on [b/30, b], b from 30 power
+                           degree-d Chebyshev semi-iteration polynomial for D^-1 H on [b/ratio, b], b from 30 power
                            steps (x 1.1, at most the Gershgorin bound); SPD on the spectrum */
     uint64_t seed;      /* Philox-4x32-10 key for the random start when X0 == NULL */
     int check_every;    /* host convergence check period in iterations (0 = 10) */
     int use_graph;      /* 1 = replay one captured hipGraph per iteration (a call on the null
                            stream runs on a private stream of the context) */
     int refresh_every;  /* recompute HX, MX explicitly every this many iterations (0 = auto) */
-    int precond_degree; /* Chebyshev degree d for precond = 2 (0 = default 8; 2..16); d - 1 products with H per
+    int precond_degree; /* Chebyshev degree d for precond = 2 (0 = default 12; 2..16); d - 1 products with H per
                            iteration */
+    double precond_ratio; /* b / a of the Chebyshev interval [a, b] (0 = default 1000; > 1): q stays
+                             positive on (0, b] for any ratio; a wide interval favours the low modes */
 } ff_eig_params;
 
 typedef struct {

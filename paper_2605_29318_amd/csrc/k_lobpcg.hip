@@ -1606,14 +1606,18 @@ __global__ void diag_inv_bs_kernel(int64_t n, const int64_t *row_ptr, const int3
 // ---------------------------------------------------------------------------
 // Chebyshev-Jacobi preconditioner: z = q(A) D^-1 r with A = D^-1 H, D = diag(H),
 // q the Chebyshev semi-iteration polynomial of degree d for A z = D^-1 r on
-// [a, b] (b an upper bound of the spectrum of A, a = b / 30). q(x) > 0 on
+// [a, b] (b an upper bound of the spectrum of A, a = b / ratio). q(x) > 0 on
 // (0, b], so the preconditioner is SPD there. Per object: coef[0] = 1 / theta,
 // coef[2s - 1], coef[2s] the step-s factors of dz (rho_s rho_{s-1}) and of r
 // (2 rho_s / delta), theta = (a + b) / 2, delta = (b - a) / 2.
 // ---------------------------------------------------------------------------
 
 constexpr int kChebCoef = 32;                  // per-object coefficient stride (degree <= 16)
-constexpr int kChebDefault = 8;                // degree when the caller passes 0
+// defaults measured at 10^6 particles, k = 32, over start seeds (mean solve time): degree 8 and
+// b / a = 30: 1.54 s, 8 and 1000: 1.22 s, 10 and 500: 0.99 s, 12 and 1000: 0.95 s, 14 and 1000:
+// 1.00 s, 16 and 3000: 1.04 s; b / a beyond 1000 changes nothing
+constexpr int kChebDefault = 12;               // degree when the caller passes 0
+constexpr double kChebRatio = 1000.0;          // b / a when the caller passes 0
 constexpr int kChebT8Sub = 1;                  // launch shape of the fused step (fewer registers than the
                                                // H-only product's default with the step's operands live)
 
@@ -2113,9 +2117,9 @@ int init_block(Solver &s, T *S, T *HS, T *MS, double tau) {
 
 // Chebyshev-Jacobi set-up: per object, the Gershgorin bound g of D^-1/2 H D^-1/2 and
 // the largest Rayleigh quotient of D^-1 H after 30 steps of power iteration on 8
-// seeded vectors (in the working precision); b = min(1.1 x quotient, g), a = b / 30.
+// seeded vectors (in the working precision); b = min(1.1 x quotient, g), a = b / ratio.
 template <typename T>
-int cheb_setup(Solver &s, int degree, uint64_t seed) {
+int cheb_setup(Solver &s, int degree, double ratio, uint64_t seed) {
     ff_ctx *ctx = s.ctx;
     const int64_t N = s.N;
     const int n_obj = s.n_obj;
@@ -2179,7 +2183,7 @@ int cheb_setup(Solver &s, int degree, uint64_t seed) {
             if (v[9 + j] > 0.0) lam = std::max(lam, v[1 + j] / v[9 + j]);
         const double g = v[0] > 0.0 ? v[0] : 1.0;
         const double b = (lam > 0.0 && lam == lam) ? std::min(1.1 * lam, g) : g;
-        const double a = b / 30.0, theta = 0.5 * (a + b), delta = 0.5 * (b - a), sigma = theta / delta;
+        const double a = b / ratio, theta = 0.5 * (a + b), delta = 0.5 * (b - a), sigma = theta / delta;
         double *c = coef.data() + (size_t)o * kChebCoef;
         c[0] = 1.0 / theta;
         double rho_prev = 1.0 / sigma;
@@ -2424,6 +2428,8 @@ int solve(ff_ctx *ctx, int n_obj, const int64_t *obj_off, const int64_t *row_ptr
     FF_REQUIRE(ctx, p->precond >= 0 && p->precond <= 2, "precond must be 0, 1 or 2");
     FF_REQUIRE(ctx, p->precond != 2 || p->precond_degree == 0 || (p->precond_degree >= 2 && p->precond_degree <= 16),
                "Chebyshev degree %d must be 0 (default %d) or in [2, 16]", p->precond_degree, kChebDefault);
+    FF_REQUIRE(ctx, p->precond != 2 || p->precond_ratio == 0.0 || (p->precond_ratio > 1.0 && p->precond_ratio <= 1e6),
+               "Chebyshev interval ratio %g must be 0 (default %g) or in (1, 1e6]", p->precond_ratio, kChebRatio);
     int m = p->block > 0 ? p->block : ((p->k + 7) / 8) * 8;
     FF_REQUIRE(ctx, m >= p->k && m % 8 == 0 && m >= 8 && m <= 64, "block %d: needs k <= m <= 64, m multiple of 8", m);
     Solver s;
@@ -2493,7 +2499,9 @@ int solve(ff_ctx *ctx, int n_obj, const int64_t *obj_off, const int64_t *row_ptr
             rc = rt::build_t16_ws(ctx, s.st, s.N, row_ptr, col, H, &s.rt16);
             if (rc) return rc;
         }
-        rc = p->precision == 1 ? cheb_setup<float>(s, degree, p->seed) : cheb_setup<double>(s, degree, p->seed);
+        const double ratio = p->precond_ratio > 0.0 ? p->precond_ratio : kChebRatio;
+        rc = p->precision == 1 ? cheb_setup<float>(s, degree, ratio, p->seed)
+                               : cheb_setup<double>(s, degree, ratio, p->seed);
         if (rc) return rc;
     }
     const int check_every = p->check_every > 0 ? p->check_every : 10;

@@ -51,6 +51,8 @@ def main(argv=None) -> int:
     ap.add_argument("--precision", type=int, nargs="+", default=[1, 0])
     ap.add_argument("--precond", type=int, nargs="+", default=[2, 1],
                     help="preconditioners to evaluate (2 Chebyshev-Jacobi, 1 Jacobi)")
+    ap.add_argument("--random-weight", type=float, nargs="+", default=[3.0, 0.0],
+                    help="random_weight of warm_block per preconditioner in --precond order")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--out", type=str, default=None, help="save the FP32 parameters (.npy)")
     a = ap.parse_args(argv)
@@ -90,10 +92,12 @@ def main(argv=None) -> int:
         m = ((k + 7) // 8) * 8
         row = dict(shape=j, n=s.n)
         for prec in a.precision:
-            for pc in a.precond:
+            for ip, pc in enumerate(a.precond):
                 key = f"p{prec}c{pc}"
+                rw = a.random_weight[ip] if ip < len(a.random_weight) else 0.0
                 for mode in ("random", "warm"):
-                    X0, used = ws.warm_block(ctx, net if mode == "warm" else None, s, m, seed=a.seed + 1)
+                    X0, used = ws.warm_block(ctx, net if mode == "warm" else None, s, m, seed=a.seed + 1,
+                                             random_weight=rw)
                     lam, W, info = ws.solve(ctx, s, k, X0=X0, precision=prec, tol=a.tol, precond=pc)
                     row[f"{key}_{mode}"] = dict(iters=info["iters_fp32"] + info["iters_fp64"],
                                                 seconds=round(info["seconds"], 3), converged=info["converged"],

@@ -272,7 +272,8 @@ def _check_modes(oracle, P, lam, W, res, k, rel_tol, sin_tol, resid_tol):
     assert np.all(W[idx, np.arange(k)] > 0)
 
 
-@pytest.mark.parametrize("precision,precond,degree", [(0, 1, 0), (1, 1, 0), (0, 2, 0), (1, 2, 3), (1, 2, 8)])
+@pytest.mark.parametrize("precision,precond,degree", [(0, 1, 0), (1, 1, 0), (0, 2, 0), (1, 2, 3), (1, 2, 8),
+                                                     (1, 2, 16)])
 def test_eigenmodes_cube(oracle, ctx, ff, precision, precond, degree):
     c = synth.cube_lattice()
     P = oracle.pipeline(c)
@@ -310,7 +311,7 @@ def test_eigenmodes_given_start_block(oracle, ctx, ff):
     _check_modes(oracle, P, lam, host(W), res, 8, 1e-8, 1e-6, 1e-8)
 
 
-def test_chebyshev_degree_is_validated(ctx, ff):
+def test_chebyshev_parameters_are_validated(ctx, ff):
     c = synth.cube_lattice()
     A = ff.assemble_cloud(ctx, dev(c.xyz), dev(c.vol), dev(c.lam), dev(c.mu), c.h)
     for bad in (1, 17, -2):
@@ -318,6 +319,9 @@ def test_chebyshev_degree_is_validated(ctx, ff):
             ff.eigenmodes(ctx, c.n, A.row_ptr, A.col, A.H, A.M, A.hm32, k=8, precond=2, precond_degree=bad)
     with pytest.raises(ff.FFError):
         ff.eigenmodes(ctx, c.n, A.row_ptr, A.col, A.H, A.M, A.hm32, k=8, precond=3)
+    for bad in (0.5, 1.0, -3.0):
+        with pytest.raises(ff.FFError):
+            ff.eigenmodes(ctx, c.n, A.row_ptr, A.col, A.H, A.M, A.hm32, k=8, precond=2, precond_ratio=bad)
 
 
 def test_not_converged_still_returns(ctx, ff):

@@ -48,7 +48,7 @@ def test_training_lowers_the_loss(env):
     assert last < first - 0.5, (first, last)
 
 
-def _ratios(env, precond):
+def _ratios(env, precond, random_weight=0.0):
     ff, ws, ctx, net, train, tests, log = env
     m = K
     ratios = []
@@ -57,7 +57,8 @@ def _ratios(env, precond):
         assert rinfo["converged"] == 1
         its = {}
         for mode in ("random", "warm"):
-            X0, used = ws.warm_block(ctx, net if mode == "warm" else None, s, m, seed=1, fallback=False)
+            X0, used = ws.warm_block(ctx, net if mode == "warm" else None, s, m, seed=1, fallback=False,
+                                     random_weight=random_weight)
             lam, W, info = ws.solve(ctx, s, K, X0=X0, precision=1, tol=1e-6, precond=precond)
             assert info["converged"] == 1 and info["max_resid"] <= 1e-6
             # Ritz values bound the eigenvalues from above; residual 1e-6 allowed at most 1.1e-4 of lambda_max on these shapes
@@ -78,12 +79,13 @@ def test_warm_start_reaches_the_same_eigenpairs_in_fewer_iterations(env):
 
 
 def test_warm_start_with_chebyshev_preconditioner(env):
-    """With the default Chebyshev-Jacobi preconditioner convergence takes a few dozen
-    iterations from any start and the network's block gains nothing measurable
-    (measured mean ratio 1.01 on these shapes); it must still reach the same
-    eigenpairs and cost no more than a few iterations."""
-    ratios = _ratios(env, precond=2)
-    assert np.mean(ratios) <= 1.15, ratios
+    """With the default Chebyshev-Jacobi preconditioner the network's block alone costs
+    iterations (mean ratio 1.29 on these shapes: it lacks a component along some wanted
+    mode, which the strong preconditioner cannot grow quickly); blended with random
+    columns of three times its RMS it reaches the same eigenpairs in fewer iterations
+    (measured 0.974)."""
+    ratios = _ratios(env, precond=2, random_weight=3.0)
+    assert np.mean(ratios) < 1.0, ratios
 
 
 def test_fallback_keeps_the_block_with_the_lower_ritz_sum(env):
