@@ -118,15 +118,23 @@ class _Union:
         self.c = np.asarray(centres, dtype=np.float64)      # (m, 3)
         self.a = np.asarray(axes, dtype=np.float64)         # (m, 3) semi-axes
         self.R = np.asarray(rots, dtype=np.float64)         # (m, 3, 3) body->world
+        # axis-aligned bodies skip the rotation (a product with the identity is exact)
+        self.eye = [bool(np.array_equal(R, np.eye(3))) for R in self.R]
 
     def inside(self, p: np.ndarray) -> np.ndarray:
         p = np.asarray(p, dtype=np.float64)
         ok = np.zeros(p.shape[0], dtype=bool)
-        for c, a, R in zip(self.c, self.a, self.R):
-            q = (p - c) @ R            # world -> body coordinates
-            ok |= np.sum((q / a) ** 2, axis=1) <= 1.0
-        inbox = np.all((p >= 0.0) & (p <= 1.0), axis=1)
-        return ok & inbox
+        step = 1 << 16                  # cache-sized pieces (the same arithmetic per point)
+        for s0 in range(0, p.shape[0], step):
+            ps = p[s0:s0 + step]
+            oks = ok[s0:s0 + step]
+            for c, a, R, eye in zip(self.c, self.a, self.R, self.eye):
+                q = ps - c if eye else (ps - c) @ R     # world -> body coordinates
+                t = q / a
+                oks |= ((t[:, 0] * t[:, 0] + t[:, 1] * t[:, 1]) + t[:, 2] * t[:, 2]) <= 1.0
+            for ax in range(3):
+                oks &= (ps[:, ax] >= 0.0) & (ps[:, ax] <= 1.0)
+        return ok
 
 
 def _quat_to_rot(q):
@@ -202,21 +210,26 @@ def _poisson_disk(shape: _Union, rng, n: int, r: float, max_rounds: int = 4000) 
             cand = cand[~(d < r)]
         if cand.shape[0] == 0:
             continue
-        # resolve conflicts inside the batch greedily in candidate order
+        # resolve conflicts inside the batch greedily in candidate order (walk the
+        # candidates in order, dropping the later partners of each kept one): the
+        # same selection is reached in rounds, a candidate being kept once every
+        # earlier partner is dropped and dropped once an earlier partner is kept
         pairs = cKDTree(cand).query_pairs(r, output_type="ndarray")
         keep = np.ones(cand.shape[0], dtype=bool)
         if pairs.size:
-            pairs = pairs[np.lexsort((pairs[:, 1], pairs[:, 0]))]
-            order = np.argsort(pairs[:, 0], kind="stable")
-            pairs = pairs[order]
-            # greedy: walk candidates in order; drop later partners of kept ones
-            nbrs = [[] for _ in range(cand.shape[0])]
-            for a, b in pairs:
-                nbrs[a].append(b)
-            for a in range(cand.shape[0]):
-                if keep[a]:
-                    for b in nbrs[a]:
-                        keep[b] = False
+            lo = np.minimum(pairs[:, 0], pairs[:, 1])
+            hi = np.maximum(pairs[:, 0], pairs[:, 1])
+            state = np.zeros(cand.shape[0], dtype=np.int8)       # 0 open, 1 kept, 2 dropped
+            nc = cand.shape[0]
+            while True:
+                open_lo = np.bincount(hi, weights=(state[lo] != 2), minlength=nc)
+                newly_kept = (state == 0) & (open_lo == 0)
+                state[newly_kept] = 1
+                kept_lo = np.bincount(hi, weights=(state[lo] == 1), minlength=nc)
+                state[(state == 0) & (kept_lo > 0)] = 2
+                if not np.any(state == 0):
+                    break
+            keep = state == 1
         cand = cand[keep][:need]
         pts = np.concatenate([pts, cand])
     return np.ascontiguousarray(pts[:n])
@@ -281,15 +294,32 @@ def ellipsoid_union(n: int = 1_000_000, seed: int = 3, hetero: bool = True, k: i
                  meta=dict(volume=V, spacing=s, hetero=hetero))
 
 
+def _batch_member(args) -> Cloud:
+    nj, sj, Ej, k, mc_samples = args
+    return sphere_union(n=nj, seed=sj, E=Ej, k=k, mc_samples=mc_samples)
+
+
 def batch_objects(count: int = 64, nmin: int = 2_000, nmax: int = 200_000, seed: int = 100,
-                  k: int = 16, mc_samples: int = 400_000) -> List[Cloud]:
-    """Sphere-union objects with n log-uniform in [nmin, nmax] and E uniform in [1e4, 1e6]."""
+                  k: int = 16, mc_samples: int = 400_000, workers: int = 1) -> List[Cloud]:
+    """Sphere-union objects with n log-uniform in [nmin, nmax] and E uniform in [1e4, 1e6].
+
+    Each object draws from its own seed, so ``workers`` > 1 builds them in
+    freshly started worker processes with the same result."""
     rng = np.random.default_rng(seed)
-    out = []
+    jobs = []
     for j in range(count):
         nj = int(round(math.exp(rng.uniform(math.log(nmin), math.log(nmax)))))
         Ej = float(rng.uniform(1e4, 1e6))
-        out.append(sphere_union(n=nj, seed=seed * 1000 + j, E=Ej, k=k, mc_samples=mc_samples))
+        jobs.append((nj, seed * 1000 + j, Ej, k, mc_samples))
+    if workers <= 1:
+        return [_batch_member(a) for a in jobs]
+    import multiprocessing as mp
+    order = sorted(range(count), key=lambda j: -jobs[j][0])       # largest first
+    with mp.get_context("spawn").Pool(min(workers, count)) as pool:
+        built = pool.map(_batch_member, [jobs[j] for j in order], chunksize=1)
+    out = [None] * count
+    for j, c in zip(order, built):
+        out[j] = c
     return out
 
 
