@@ -58,7 +58,6 @@ def run_step(ff, ctx, dev_in, n, h, k, precision, tol, max_iter, use_graph=False
 
 KERNEL_SRC = os.path.join(ROOT, "paper_2605_29318_amd", "csrc", "k_rowtile.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cheb_step_ellipsoids1m_k32_hbm_traffic.txt")
-DOMINANT = "spmm_rt_h8_kernel<true"
 
 
 def kernel_source_hash():
@@ -66,12 +65,13 @@ def kernel_source_hash():
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
-def cheb_step_bytes(nnz, n, m):
-    """Algorithmic HBM bytes of one Chebyshev step launch (FP32, m columns), independent of
-    the storage format: the FP32 H value and int32 column of every nonzero, the row
-    pointers, D^-1 and the row's object index, the gathered block DZ read once, R read and
-    written, the next DZ written, W read and written."""
-    return nnz * 8 + 8 * (n + 1) + n * (4 + 4) + n * m * 4 * (1 + 2 + 1 + 2)
+def cheb_step_bytes(nnz, n, m, value_bytes=2):
+    """Algorithmic HBM bytes of one Chebyshev step launch (FP32 blocks, m columns),
+    independent of the tiling: the H value (binary16 by default, value_bytes) and int32
+    column of every nonzero, the row pointers, D^-1 and the row's object index, the
+    gathered block DZ read once, R read and written, the next DZ written, W read and
+    written."""
+    return nnz * (value_bytes + 4) + 8 * (n + 1) + n * (4 + 4) + n * m * 4 * (1 + 2 + 1 + 2)
 
 
 def spmm_hm_bytes(nnz, n, m):
@@ -260,6 +260,7 @@ def main():
         "config": {"workload": "ellipsoids1m_hetero", "particles": c.n, "k": args.k, "tol": args.tol,
                    "nnz": nnz, "nnz_per_row": round(nnz / c.n, 1), "h": round(c.h, 6),
                    "precond": "chebyshev-jacobi", "precond_degree": PRECOND_DEGREE or 12, "precond_ratio": 1000,
+                   "precond_values": "fp16",
                    "graph": bool(args.graph)},
         "build_s": round(last["build"], 4),
         "solve_s": round(last["solve"], 4),
@@ -275,8 +276,9 @@ def main():
         "stage_launches": {k: int(v[1]) for k, v in stages.items()},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "spmm_t8_kernel<true> (Chebyshev step: H-only product on the eight-row tile copy "
-                               "fused with the step's vector update, FP32, m=%d)" % m,
+                     "kernel": "spmm_t8_kernel<_Float16, true> (Chebyshev step: H-only product on the eight-row "
+                               "tile copy of H in binary16, FP32 accumulation, fused with the step's vector "
+                               "update, m=%d)" % m,
                      "bytes_per_launch": cheb_alg, "launch_ms": round(cheb_avg, 4),
                      "share_of_solve": round(cheb_ms / max(stages["total"][0], 1e-9), 3)},
         "spmm_hm": {"achieved": round(spmm_gbps, 1), "unit": "GB/s", "bytes_per_launch": spmm_alg,

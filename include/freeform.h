@@ -198,6 +198,9 @@ typedef struct {
                            iteration */
     double precond_ratio; /* b / a of the Chebyshev interval [a, b] (0 = default 1000; > 1): q stays
                              positive on (0, b] for any ratio; a wide interval favours the low modes */
+    int precond_values; /* storage of H in the Chebyshev products of the mixed path's eight-row kernel:
+                           0 = default (FP16), 1 = FP32, 2 = binary16 scaled by a power of two (see
+                           rowtiles_build precision 5); the products accumulate in FP32 either way */
 } ff_eig_params;
 
 typedef struct {
@@ -306,17 +309,23 @@ int rayleigh_ritz(ff_ctx *ctx, int w, int m, const double *G, double tau, double
  *   both; 3 and 4 keep only H, in FP32, in tiles of eight and of sixteen
  *   rows (the copies the Chebyshev-Jacobi preconditioner of eigenmodes runs
  *   on: sixteen rows on MFMA where the block width allows, eight rows
- *   otherwise; M may be NULL).
+ *   otherwise; M may be NULL); 5 keeps H in eight-row tiles in binary16:
+ *   each value is the FP32 value times 2^e, rounded to nearest even, with e
+ *   chosen so the largest |H| lands in [2^14, 2^15), and the product scales
+ *   its FP32 sums by 2^-e (the preconditioner's default storage: half the
+ *   bytes per value, relative error 2^-11 per value).
  *   Device memory owned by the handle until rowtiles_destroy (destroy it
  *   before its context). The CSR may be freed afterwards.
  * spmm_rowtiles: [HY, MY] = [H, M] Y as spmm_hm, on the copy; sub selects a
  *   launch shape (0 .. 2). With MY NULL only HY = H Y is formed, the product
  *   the Chebyshev-Jacobi preconditioner of eigenmodes runs: at precision 1 it
  *   accumulates in FP32 (an approximate operator is all a preconditioner
- *   needs), at precision 0 in FP64. A handle built with precision 3 or 4
+ *   needs), at precision 0 in FP64. A handle built with precision 3, 4 or 5
  *   takes only this form, at precision 1, with leading dimensions that are
  *   multiples of 4 and m % 8 == 0, 8 <= m <= 64, 64 % (m / 8) == 0 (eight
- *   rows) or m in {4, 8, 12, 16, 32, 64} (sixteen rows).
+ *   rows) or m in {4, 8, 12, 16, 32, 64} (sixteen rows). Errors: invalid
+ *   arguments and unsupported shapes return FF_ERR_INVALID_ARG, a
+ *   non-finite H at precision 5 likewise.
  */
 typedef struct ff_rowtiles ff_rowtiles;
 int rowtiles_build(ff_ctx *ctx, int64_t n, const int64_t *row_ptr, const int32_t *col, const double *H,

@@ -2430,6 +2430,8 @@ int solve(ff_ctx *ctx, int n_obj, const int64_t *obj_off, const int64_t *row_ptr
                "Chebyshev degree %d must be 0 (default %d) or in [2, 16]", p->precond_degree, kChebDefault);
     FF_REQUIRE(ctx, p->precond != 2 || p->precond_ratio == 0.0 || (p->precond_ratio > 1.0 && p->precond_ratio <= 1e6),
                "Chebyshev interval ratio %g must be 0 (default %g) or in (1, 1e6]", p->precond_ratio, kChebRatio);
+    FF_REQUIRE(ctx, p->precond_values >= 0 && p->precond_values <= 2,
+               "precond_values %d must be 0 (default FP16), 1 (FP32) or 2 (FP16)", p->precond_values);
     int m = p->block > 0 ? p->block : ((p->k + 7) / 8) * 8;
     FF_REQUIRE(ctx, m >= p->k && m % 8 == 0 && m >= 8 && m <= 64, "block %d: needs k <= m <= 64, m multiple of 8", m);
     Solver s;
@@ -2494,6 +2496,8 @@ int solve(ff_ctx *ctx, int n_obj, const int64_t *obj_off, const int64_t *row_ptr
         // product at 1M particles, m = 32; it serves the widths the eight-row kernel does not take)
         if (p->precision == 1 && s.var32 >= kRowTileBase && rt::t8_ok(s.m, s.m, s.m)) {
             if (!s.rt8.vh) rc = rt::build_t8_ws(ctx, s.st, s.N, row_ptr, col, H, &s.rt8);
+            // H in binary16 for these products: 1.86 value slots per nonzero at 2 bytes instead of 4
+            if (!rc && p->precond_values != 1) rc = rt::build_t8_half(ctx, s.st, &s.rt8);
             if (rc) return rc;
         } else if (p->precision == 1 && s.var32 >= kRowTileBase && rt::t16_ok(s.m, s.m, s.m)) {
             rc = rt::build_t16_ws(ctx, s.st, s.N, row_ptr, col, H, &s.rt16);

@@ -64,9 +64,15 @@ struct RT8View {
     const int32_t *tcol = nullptr;   // [entries]
     const float *vh = nullptr;       // [entries][8]
     const float *vm = nullptr;       // [entries][8] M values, when built with M
+    // FP16 copy of H scaled by 2^e (largest magnitude in [2^14, 2^15)); hscale = 2^-e. When present the
+    // H-only products (spmm_h_t8, cheb_step_t8) read it instead of vh
+    const uint16_t *vh16 = nullptr;  // [entries][8] binary16 bits
+    float hscale = 1.f;
 };
 int build_t8_ws(ff_ctx *ctx, hipStream_t st, int64_t n, const int64_t *row_ptr, const int32_t *col, const double *H,
                 RT8View *out, const double *M = nullptr);
+// adds the FP16 copy of vh to a built view (vh16 storage: entries * 8 halves at out16, or the workspace)
+int build_t8_half(ff_ctx *ctx, hipStream_t st, RT8View *v, uint16_t *out16 = nullptr);
 // block widths the eight-row kernels take: m % 8 == 0, 8 <= m <= 64, 16-byte aligned rows
 bool t8_ok(int m, int64_t ldy, int64_t ldo);
 int spmm_h_t8(ff_ctx *ctx, hipStream_t st, const RT8View &v, int sub, int m, const float *Y, int64_t ldy, float *HY,

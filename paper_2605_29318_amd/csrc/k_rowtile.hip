@@ -2,6 +2,8 @@
 #include "k_rowtile.h"
 
 #include <climits>
+#include <cmath>
+#include <cstring>
 
 struct ff_rowtiles {
     int device = 0;
@@ -167,6 +169,7 @@ __device__ inline void acc_store(float *p, const Acc4<A> &a) {
 __device__ inline void acc_store(double *p, const Acc4<double> &a) { *(double2 *)p = make_double2(a.v[0], a.v[1]); }
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
 // Chunk of 64 union entries: column and the eight values of entry l in lane l.
 // With kHM false only the H values are loaded and staged (stride 4 in LDS).
@@ -665,7 +668,8 @@ int build_ws(ff_ctx *ctx, hipStream_t st, int64_t n, const int64_t *row_ptr, con
 // Same scheme as the eight-column kernel: lane groups of G = m / 8 lanes take
 // entries of a 64-entry chunk, each lane accumulates 8 rows x 8 columns in
 // FP32, the groups are summed by a butterfly, and lane group i stores row i.
-struct Chunk8 {
+template <typename V> struct Chunk8;
+template <> struct Chunk8<float> {
     int32_t j;
     f32x4 a, b;                                    // H rows 0..3 and 4..7
     __device__ void load(const int32_t *tcol, const float *vh, int64_t e, bool in) {
@@ -682,9 +686,27 @@ struct Chunk8 {
         *(f32x4 *)(sv + lane * 8 + 4) = b;
     }
 };
+// the FP16 copy: one 16-byte load per entry, widened to FP32 as it is staged
+template <> struct Chunk8<_Float16> {
+    int32_t j;
+    f32x4 a;                                       // H rows 0..7 as eight binary16 values
+    __device__ void load(const int32_t *tcol, const _Float16 *vh, int64_t e, bool in) {
+        j = 0;
+        a = f32x4{0.f, 0.f, 0.f, 0.f};
+        if (in) {
+            j = __builtin_nontemporal_load(tcol + e);
+            a = __builtin_nontemporal_load((const f32x4 *)(vh + e * 8));
+        }
+    }
+    __device__ void stage(float *sv, int lane) const {
+        const f16x8 h = __builtin_bit_cast(f16x8, a);
+        *(f32x4 *)(sv + lane * 8) = f32x4{(float)h[0], (float)h[1], (float)h[2], (float)h[3]};
+        *(f32x4 *)(sv + lane * 8 + 4) = f32x4{(float)h[4], (float)h[5], (float)h[6], (float)h[7]};
+    }
+};
 
-template <int kBatch, int kAhead>
-__device__ __forceinline__ void t8_chunk(Chunk8 &ch, int64_t base, int64_t e1, const int32_t *tcol, const float *vh,
+template <typename V, int kBatch, int kAhead>
+__device__ __forceinline__ void t8_chunk(Chunk8<V> &ch, int64_t base, int64_t e1, const int32_t *tcol, const V *vh,
                                          float *sv, int lane, int g, int c, int NG, int steps, const float *Y,
                                          int64_t ldy, float (&acc)[kTile8][8]) {
     const int cnt = (int)(e1 - base < 64 ? e1 - base : 64);
@@ -725,9 +747,9 @@ __device__ __forceinline__ void t8_chunk(Chunk8 &ch, int64_t base, int64_t e1, c
     }
 }
 
-template <bool kEpi, int kWaves, int kBatch, int kAhead, int kOcc, bool kPre>
+template <typename V, bool kEpi, int kWaves, int kBatch, int kAhead, int kOcc, bool kPre>
 __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(kOcc, 8)))
-spmm_t8_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int32_t *tcol, const float *vh,
+spmm_t8_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int32_t *tcol, const V *vh, float vscale,
                const float *Y, int64_t ldy, float *HY, int64_t ldo, int m, const int *row_obj, const int *obj_status,
                ChebStep<float> cs) {
     __shared__ __align__(16) float svals[kWaves][64 * 8];
@@ -762,18 +784,18 @@ spmm_t8_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int32_t
     for (int i = 0; i < kTile8; ++i)
 #pragma unroll
         for (int q = 0; q < 8; ++q) acc[i][q] = 0.f;
-    Chunk8 ca, cb;
+    Chunk8<V> ca, cb;
     ca.load(tcol, vh, e0 + lane, e0 + lane < e1);
     if (kAhead == 2) {
         cb.load(tcol, vh, e0 + 64 + lane, e0 + 64 + lane < e1);
         for (int64_t base = e0; base < e1; base += 128) {
-            t8_chunk<kBatch, 2>(ca, base, e1, tcol, vh, sv, lane, g, c, NG, steps, Y, ldy, acc);
+            t8_chunk<V, kBatch, 2>(ca, base, e1, tcol, vh, sv, lane, g, c, NG, steps, Y, ldy, acc);
             if (base + 64 < e1)
-                t8_chunk<kBatch, 2>(cb, base + 64, e1, tcol, vh, sv, lane, g, c, NG, steps, Y, ldy, acc);
+                t8_chunk<V, kBatch, 2>(cb, base + 64, e1, tcol, vh, sv, lane, g, c, NG, steps, Y, ldy, acc);
         }
     } else {
         for (int64_t base = e0; base < e1; base += 64)
-            t8_chunk<kBatch, 1>(ca, base, e1, tcol, vh, sv, lane, g, c, NG, steps, Y, ldy, acc);
+            t8_chunk<V, kBatch, 1>(ca, base, e1, tcol, vh, sv, lane, g, c, NG, steps, Y, ldy, acc);
     }
     if (kEpi && !kPre && mine) epi_load();
 #pragma unroll
@@ -794,7 +816,7 @@ spmm_t8_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int32_t
         const int o = row_obj[rme];
         const double f1 = cs.coef[(size_t)o * cs.stride + 2 * cs.step - 1];
         const double f2 = cs.coef[(size_t)o * cs.stride + 2 * cs.step];
-        const double dv = (double)cs.dinv[rme];
+        const double dv = (double)cs.dinv[rme] * (double)vscale;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             f32x4 rv1, dz1, w1;
@@ -813,8 +835,8 @@ spmm_t8_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int32_t
     } else {
 #pragma unroll
         for (int h = 0; h < 2; ++h)
-            *(f32x4 *)(HY + rme * ldo + c * 8 + 4 * h) =
-                f32x4{a8[4 * h], a8[4 * h + 1], a8[4 * h + 2], a8[4 * h + 3]};
+            *(f32x4 *)(HY + rme * ldo + c * 8 + 4 * h) = f32x4{a8[4 * h] * vscale, a8[4 * h + 1] * vscale,
+                                                                a8[4 * h + 2] * vscale, a8[4 * h + 3] * vscale};
     }
 }
 
@@ -825,14 +847,23 @@ bool t8_ok(int m, int64_t ldy, int64_t ldo) {
 template <bool kEpi>
 int launch_t8(ff_ctx *ctx, hipStream_t st, const RT8View &v, int sub, int m, const float *Y, int64_t ldy, float *HY,
               int64_t ldo, const int *row_obj, const int *status, const ChebStep<float> &cs) {
-#define FF_T8(W, B, A, O, P)                                                                                \
-    hipLaunchKernelGGL((spmm_t8_kernel<kEpi, W, B, A, O, P>), dim3(grid_for(v.ntiles, W)), dim3(64 * W), 0, st, \
-                       v.n, v.ntiles, v.tptr, v.tcol, v.vh, Y, ldy, HY, ldo, m, row_obj, status, cs)
-    // H-only product on the benchmark workload (m = 32): 1.18 / 1.24 ms for the first two
-    switch (sub) {
-        case 1: FF_T8(4, 2, 2, 1, true); break;
-        case 2: FF_T8(4, 2, 1, 1, false); break;
-        default: FF_T8(2, 4, 2, 1, true); break;
+#define FF_T8(VT, VP, SC, W, B, A, O, P)                                                                          \
+    hipLaunchKernelGGL((spmm_t8_kernel<VT, kEpi, W, B, A, O, P>), dim3(grid_for(v.ntiles, W)), dim3(64 * W), 0, st, \
+                       v.n, v.ntiles, v.tptr, v.tcol, VP, SC, Y, ldy, HY, ldo, m, row_obj, status, cs)
+    // H-only product on the benchmark workload (m = 32, FP32 values): 1.18 / 1.24 ms for the first two
+    if (v.vh16) {
+        const _Float16 *vp = (const _Float16 *)v.vh16;
+        switch (sub) {
+            case 1: FF_T8(_Float16, vp, v.hscale, 4, 2, 2, 1, true); break;
+            case 2: FF_T8(_Float16, vp, v.hscale, 4, 2, 1, 1, false); break;
+            default: FF_T8(_Float16, vp, v.hscale, 2, 4, 2, 1, true); break;
+        }
+    } else {
+        switch (sub) {
+            case 1: FF_T8(float, v.vh, 1.f, 4, 2, 2, 1, true); break;
+            case 2: FF_T8(float, v.vh, 1.f, 4, 2, 1, 1, false); break;
+            default: FF_T8(float, v.vh, 1.f, 2, 4, 2, 1, true); break;
+        }
     }
 #undef FF_T8
     FF_CHECK_LAUNCH(ctx);
@@ -844,7 +875,8 @@ inline bool off32_ok(int64_t n, int64_t ld) { return n * ld < ((int64_t)1 << 32)
 
 int spmm_h_t8(ff_ctx *ctx, hipStream_t st, const RT8View &v, int sub, int m, const float *Y, int64_t ldy, float *HY,
               int64_t ldo, const int *row_obj, const int *status) {
-    FF_REQUIRE(ctx, v.vh != nullptr && t8_ok(m, ldy, ldo), "eight-row tiles: bad copy or block shape (m = %d)", m);
+    FF_REQUIRE(ctx, (v.vh != nullptr || v.vh16 != nullptr) && t8_ok(m, ldy, ldo),
+               "eight-row tiles: bad copy or block shape (m = %d)", m);
     FF_REQUIRE(ctx, off32_ok(v.n, ldy), "block of %lld rows x %lld too large for 32-bit row offsets", (long long)v.n,
                (long long)ldy);
     return launch_t8<false>(ctx, st, v, sub, m, Y, ldy, HY, ldo, row_obj, status, ChebStep<float>{});
@@ -852,7 +884,7 @@ int spmm_h_t8(ff_ctx *ctx, hipStream_t st, const RT8View &v, int sub, int m, con
 
 int cheb_step_t8(ff_ctx *ctx, hipStream_t st, const RT8View &v, int sub, int m, const float *DZ, int64_t ld,
                  const int *row_obj, const int *status, const ChebStep<float> &cs) {
-    FF_REQUIRE(ctx, v.vh != nullptr && row_obj != nullptr && t8_ok(m, ld, ld) && cs.ldw % 4 == 0,
+    FF_REQUIRE(ctx, (v.vh != nullptr || v.vh16 != nullptr) && row_obj != nullptr && t8_ok(m, ld, ld) && cs.ldw % 4 == 0,
                "eight-row tiles: bad copy or block shape (m = %d)", m);
     FF_REQUIRE(ctx, off32_ok(v.n, ld), "block of %lld rows x %lld too large for 32-bit row offsets", (long long)v.n,
                (long long)ld);
@@ -891,6 +923,70 @@ int build_t8_ws(ff_ctx *ctx, hipStream_t st, int64_t n, const int64_t *row_ptr, 
     out->tcol = tcol;
     out->vh = vh;
     out->vm = vm;
+    return FF_OK;
+}
+
+// largest |v| over n4 groups of four FP32 values, as the bit pattern of a non-negative float
+// (those order as unsigned integers, so one atomic max per wavefront combines them)
+__global__ void absmax_f32_kernel(int64_t n4, const float *v, uint32_t *out) {
+    float a = 0.f;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += (int64_t)gridDim.x * blockDim.x) {
+        const f32x4 x = __builtin_nontemporal_load((const f32x4 *)v + i);
+        a = fmaxf(a, fmaxf(fmaxf(fabsf(x[0]), fabsf(x[1])), fmaxf(fabsf(x[2]), fabsf(x[3]))));
+    }
+    for (int d = 32; d >= 1; d >>= 1) a = fmaxf(a, __shfl_xor(a, d, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(a));
+}
+
+// out[i] = binary16(scale * v[i]), eight values per thread; scale is a power of two, so the only
+// rounding is the one to binary16 (to nearest even)
+__global__ void to_half_kernel(int64_t n8, const float *v, float scale, f32x4 *out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n8) return;
+    const f32x4 a = __builtin_nontemporal_load((const f32x4 *)v + 2 * i);
+    const f32x4 b = __builtin_nontemporal_load((const f32x4 *)v + 2 * i + 1);
+    f16x8 h;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        h[q] = (_Float16)(a[q] * scale);
+        h[4 + q] = (_Float16)(b[q] * scale);
+    }
+    out[i] = __builtin_bit_cast(f32x4, h);
+}
+
+int build_t8_half(ff_ctx *ctx, hipStream_t st, RT8View *v, uint16_t *out16) {
+    FF_REQUIRE(ctx, v != nullptr && v->vh != nullptr && v->entries >= 0, "FP16 tile copy needs a built FP32 copy");
+    const int64_t n8 = v->entries;                 // one group of eight values per entry
+    uint32_t *mx = (uint32_t *)ws_get(ctx, WS_RT8_MAX, 256);
+    if (!out16) out16 = (uint16_t *)ws_get(ctx, WS_RT8_VAL16, (size_t)std::max<int64_t>(n8, 1) * 8 * 2);
+    uint32_t *hbuf = (uint32_t *)pinned_get(ctx, 64);
+    if (!mx || !out16 || !hbuf) return FF_ERR_OOM;
+    FF_HIP(ctx, hipMemsetAsync(mx, 0, sizeof(uint32_t), st));
+    if (n8 > 0) {
+        const int64_t blocks = std::min<int64_t>(grid_for(2 * n8, 256), 8192);
+        hipLaunchKernelGGL(absmax_f32_kernel, dim3(blocks), dim3(256), 0, st, 2 * n8, v->vh, mx);
+        FF_CHECK_LAUNCH(ctx);
+    }
+    FF_HIP(ctx, hipMemcpyAsync(hbuf, mx, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    FF_HIP(ctx, hipStreamSynchronize(st));
+    float amax;
+    std::memcpy(&amax, hbuf, sizeof(float));
+    FF_REQUIRE(ctx, std::isfinite(amax), "non-finite value in H");
+    // scale 2^e puts the largest magnitude in [2^14, 2^15): binary16 holds it with room to spare, and the
+    // relative rounding error stays 2^-11 down to 2^-29 of it (below that subnormal, then zero)
+    int e = 0;
+    if (amax > 0.f) {
+        int p;
+        (void)std::frexp(amax, &p);                // amax in [2^(p-1), 2^p)
+        e = std::max(-126, std::min(126, 15 - p));
+    }
+    if (n8 > 0) {
+        hipLaunchKernelGGL(to_half_kernel, dim3(grid_for(n8, 256)), dim3(256), 0, st, n8, v->vh,
+                           std::ldexp(1.f, e), (f32x4 *)out16);
+        FF_CHECK_LAUNCH(ctx);
+    }
+    v->vh16 = out16;
+    v->hscale = std::ldexp(1.f, -e);
     return FF_OK;
 }
 
@@ -1279,15 +1375,16 @@ int rowtiles_build(ff_ctx *ctx, int64_t n, const int64_t *row_ptr, const int32_t
     if (!ctx || !out) return FF_ERR_INVALID_ARG;
     *out = nullptr;
     FF_REQUIRE(ctx, n > 0 && row_ptr && col && H && (M || precision >= 3), "bad arguments");
-    FF_REQUIRE(ctx, precision >= 0 && precision <= 4,
-               "precision must be 0 (FP64), 1 (FP32), 2 (both), 3 or 4 (FP32 H only, eight- or sixteen-row tiles)");
+    FF_REQUIRE(ctx, precision >= 0 && precision <= 5,
+               "precision must be 0 (FP64), 1 (FP32), 2 (both), 3 or 4 (FP32 H only, eight- or sixteen-row tiles) "
+               "or 5 (H only in FP16, eight-row tiles)");
     FF_HIP(ctx, hipSetDevice(ctx->device));
     hipStream_t st = ctx->stream;
     ff_rowtiles *h = new ff_rowtiles();
     h->device = ctx->device;
     h->stream = ctx->stream;
     if (precision >= 3) {
-        const int R = precision == 3 ? rt::kTile8 : rt::kTile16;
+        const int R = precision == 4 ? rt::kTile16 : rt::kTile8;
         h->hrows = R;
         const int64_t nt8 = (n + R - 1) / R;
         int64_t *cnt8 = nullptr, *tptr8 = nullptr;
@@ -1318,18 +1415,27 @@ int rowtiles_build(ff_ctx *ctx, int64_t n, const int64_t *row_ptr, const int32_t
         if (!rc8)
             rc8 = R == rt::kTile8 ? rt::fill_t8(ctx, st, n, nt8, row_ptr, col, H, tptr8, tcol8, vh)
                                   : rt::fill_t16(ctx, st, n, nt8, row_ptr, col, H, tptr8, tcol8, vh);
-        if (!rc8 && hipStreamSynchronize(st) != hipSuccess)
-            rc8 = set_error(ctx, FF_ERR_HIP, "row-tile build failed");
-        if (rc8) {
-            rowtiles_destroy(h);
-            return rc8;
-        }
         h->v8.n = h->v16.n = n;
         h->v8.ntiles = h->v16.ntiles = nt8;
         h->v8.entries = h->v16.entries = ent8;
         h->v8.tptr = h->v16.tptr = tptr8;
         h->v8.tcol = h->v16.tcol = tcol8;
         h->v8.vh = h->v16.vh = vh;
+        if (!rc8 && precision == 5) {
+            uint16_t *v16 = nullptr;
+            if (hipMalloc((void **)&v16, (size_t)std::max<int64_t>(ent8, 1) * rt::kTile8 * 2) != hipSuccess) {
+                (void)hipGetLastError();
+                rc8 = set_error(ctx, FF_ERR_OOM, "row-tile allocation of %lld entries failed", (long long)ent8);
+            }
+            h->mem[3] = v16;
+            if (!rc8) rc8 = rt::build_t8_half(ctx, st, &h->v8, v16);
+        }
+        if (!rc8 && hipStreamSynchronize(st) != hipSuccess)
+            rc8 = set_error(ctx, FF_ERR_HIP, "row-tile build failed");
+        if (rc8) {
+            rowtiles_destroy(h);
+            return rc8;
+        }
         *out = h;
         return FF_OK;
     }

@@ -47,7 +47,8 @@ class ff_eig_params(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int), ("block", ctypes.c_int), ("precision", ctypes.c_int),
                 ("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("precond", ctypes.c_int),
                 ("seed", ctypes.c_uint64), ("check_every", ctypes.c_int), ("use_graph", ctypes.c_int),
-                ("refresh_every", ctypes.c_int), ("precond_degree", ctypes.c_int), ("precond_ratio", ctypes.c_double)]
+                ("refresh_every", ctypes.c_int), ("precond_degree", ctypes.c_int), ("precond_ratio", ctypes.c_double),
+                ("precond_values", ctypes.c_int)]
 
 
 class ff_eig_info(ctypes.Structure):
@@ -244,18 +245,18 @@ def assemble_HM(ctx: Context, n: int, nbr_off, nbr_id, phi, dphi, vol, lam, mu, 
 
 
 def _params(k, block, precision, tol, max_iter, precond, seed, check_every, use_graph, refresh_every,
-            precond_degree=0, precond_ratio=0.0):
+            precond_degree=0, precond_ratio=0.0, precond_values=0):
     return ff_eig_params(k, block, precision, tol, max_iter, precond, seed, check_every, int(use_graph),
-                         refresh_every, precond_degree, float(precond_ratio))
+                         refresh_every, precond_degree, float(precond_ratio), precond_values)
 
 
 def eigenmodes(ctx: Context, n: int, row_ptr, col, H, M, hm32, k: int, block: int = 0, precision: int = 1,
                tol: float = 1e-6, max_iter: int = 5000, precond: int = 2, seed: int = 0, X0=None,
                check_every: int = 10, use_graph: bool = False, refresh_every: int = 0, allow_unconverged=False,
-               precond_degree: int = 0, precond_ratio: float = 0.0):
+               precond_degree: int = 0, precond_ratio: float = 0.0, precond_values: int = 0):
     import torch
     p = _params(k, block, precision, tol, max_iter, precond, seed, check_every, use_graph, refresh_every,
-                precond_degree, precond_ratio)
+                precond_degree, precond_ratio, precond_values)
     lam = np.zeros(k)
     res = np.zeros(k)
     W = torch.empty((n, k), dtype=torch.float64, device=H.device)
@@ -274,13 +275,13 @@ def eigenmodes_batched(ctx: Context, obj_row_off, row_ptr, col, H, M, hm32, k: i
                        precision: int = 1, tol: float = 1e-6, max_iter: int = 5000, precond: int = 2,
                        seed: int = 0, X0=None, check_every: int = 10, use_graph: bool = False,
                        refresh_every: int = 0, allow_unconverged=False, precond_degree: int = 0,
-                       precond_ratio: float = 0.0):
+                       precond_ratio: float = 0.0, precond_values: int = 0):
     import torch
     off = np.ascontiguousarray(obj_row_off, dtype=np.int64)
     n_obj = len(off) - 1
     N = int(off[-1])
     p = _params(k, block, precision, tol, max_iter, precond, seed, check_every, use_graph, refresh_every,
-                precond_degree, precond_ratio)
+                precond_degree, precond_ratio, precond_values)
     lam = np.zeros((n_obj, k))
     res = np.zeros((n_obj, k))
     W = torch.empty((N, k), dtype=torch.float64, device=H.device)

@@ -236,6 +236,49 @@ def test_rowtiles_h_only_copies(oracle, ctx, ff, rows):
     rt.close()
 
 
+def _fp16_storage(H):
+    """H as the FP16 tile copy stores it (rowtiles_build precision 5): FP32 rounding, scale
+    2^e with the largest magnitude in [2^14, 2^15), binary16 rounding to nearest even."""
+    h32 = H.astype(np.float32)
+    amax = float(np.abs(h32).max())
+    e = 15 - int(np.frexp(amax)[1]) if amax > 0 else 0
+    q = (h32.astype(np.float64) * 2.0 ** e).astype(np.float16)
+    assert np.all(np.isfinite(q))
+    return q.astype(np.float64) * 2.0 ** -e, e
+
+
+def test_rowtiles_fp16_copy(oracle, ctx, ff):
+    """The preconditioner's default copy: H in binary16 (scaled by a power of two) in
+    tiles of eight rows, ragged last tile. Against H as stored it obeys the same FP32
+    accumulation bound as the FP32 copy; against the exact H each value adds at most
+    2^-11 relative (or half a subnormal step)."""
+    c = synth.random_cloud(2503, seed=29, hetero=True)
+    P = oracle.pipeline(c)
+    A = ff.assemble_cloud(ctx, dev(c.xyz), dev(c.vol), dev(c.lam), dev(c.mu), c.h)
+    rt = ff.RowTiles(ctx, A.n, A.row_ptr, A.col, A.H, None, precision=5)
+    ntiles, entries = rt.info()
+    assert ntiles == (c.n + 7) // 8
+    Hq, e = _fp16_storage(P.H)
+    rl = np.diff(P.row_ptr)
+    eps = (rl.max() + 8) * 2.0 ** -24
+    for m in (8, 16, 32, 64):
+        Y = np.random.default_rng(m).standard_normal((c.n, m))
+        refq = oracle.spmm(P.row_ptr, P.col, Hq, Y)
+        absq = oracle.spmm(P.row_ptr, P.col, np.abs(Hq), np.abs(Y))
+        ref = oracle.spmm(P.row_ptr, P.col, P.H, Y)
+        absH = oracle.spmm(P.row_ptr, P.col, np.abs(P.H), np.abs(Y))
+        absY = oracle.spmm(P.row_ptr, P.col, np.ones_like(P.H), np.abs(Y))
+        for sub in range(3):
+            HO, none = rt.spmm(dev(Y, torch.float32), 1, sub, h_only=True)
+            assert none is None
+            HO = host(HO)
+            assert np.all(np.abs(HO - refq) <= eps * absq + 1e-300), (m, sub)
+            assert np.all(np.abs(HO - ref) <= (2.0 ** -11 + 2 * eps) * absH + 2.0 ** (-24 - e) * absY), (m, sub)
+    rt.close()
+    with pytest.raises(ff.FFError):
+        ff.RowTiles(ctx, A.n, A.row_ptr, A.col, A.H, None, precision=6)
+
+
 def test_philox_known_answers(ctx, ff):
     """Known-answer vectors of Philox-4x32-10 (Salmon et al., SC'11, Random123 distribution)."""
     import os
@@ -272,16 +315,17 @@ def _check_modes(oracle, P, lam, W, res, k, rel_tol, sin_tol, resid_tol):
     assert np.all(W[idx, np.arange(k)] > 0)
 
 
-@pytest.mark.parametrize("precision,precond,degree", [(0, 1, 0), (1, 1, 0), (0, 2, 0), (1, 2, 3), (1, 2, 8),
-                                                     (1, 2, 16)])
-def test_eigenmodes_cube(oracle, ctx, ff, precision, precond, degree):
+@pytest.mark.parametrize("precision,precond,degree,values", [(0, 1, 0, 0), (1, 1, 0, 0), (0, 2, 0, 0), (1, 2, 3, 0),
+                                                            (1, 2, 8, 0), (1, 2, 16, 0), (1, 2, 0, 1),
+                                                            (1, 2, 0, 2)])
+def test_eigenmodes_cube(oracle, ctx, ff, precision, precond, degree, values):
     c = synth.cube_lattice()
     P = oracle.pipeline(c)
     A = ff.assemble_cloud(ctx, dev(c.xyz), dev(c.vol), dev(c.lam), dev(c.mu), c.h)
     k = 8
     lam, W, res, info = ff.eigenmodes(ctx, c.n, A.row_ptr, A.col, A.H, A.M, A.hm32, k=k, precision=precision,
                                       tol=1e-8 if precision == 0 else 1e-6, max_iter=4000, precond=precond,
-                                      precond_degree=degree)
+                                      precond_degree=degree, precond_values=values)
     _check_modes(oracle, P, lam, host(W), res, k, 1e-8 if precision == 0 else 1e-5,
                  1e-6 if precision == 0 else 1e-3, 1e-8 if precision == 0 else 1e-6)
 
@@ -322,6 +366,9 @@ def test_chebyshev_parameters_are_validated(ctx, ff):
     for bad in (0.5, 1.0, -3.0):
         with pytest.raises(ff.FFError):
             ff.eigenmodes(ctx, c.n, A.row_ptr, A.col, A.H, A.M, A.hm32, k=8, precond=2, precond_ratio=bad)
+    for bad in (-1, 3):
+        with pytest.raises(ff.FFError):
+            ff.eigenmodes(ctx, c.n, A.row_ptr, A.col, A.H, A.M, A.hm32, k=8, precond=2, precond_values=bad)
 
 
 def test_not_converged_still_returns(ctx, ff):
