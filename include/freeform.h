@@ -198,9 +198,14 @@ typedef struct {
                            iteration */
     double precond_ratio; /* b / a of the Chebyshev interval [a, b] (0 = default 1000; > 1): q stays
                              positive on (0, b] for any ratio; a wide interval favours the low modes */
-    int precond_values; /* storage of H in the Chebyshev products of the mixed path's eight-row kernel:
-                           0 = default (FP16), 1 = FP32, 2 = binary16 scaled by a power of two (see
-                           rowtiles_build precision 5); the products accumulate in FP32 either way */
+    int precond_values; /* number formats of the Chebyshev products of the mixed path (eight-row tiles):
+                           1 = H and the iterate in FP32 (FP32 VALU); 2 = H in binary16 scaled by a
+                           power of two (rowtiles_build precision 5), iterate FP32 (FP32 VALU); 3 = H
+                           and the iterate in binary16 on the matrix cores (rowtiles_build precision 6;
+                           block width 32 or 64), each column of the preconditioner's input scaled by
+                           the inverse of its largest magnitude per object (the output's span is
+                           unchanged); 0 = default: 3 where the width allows, else 2. Products
+                           accumulate in FP32 in every case */
 } ff_eig_params;
 
 typedef struct {
@@ -312,8 +317,10 @@ int rayleigh_ritz(ff_ctx *ctx, int w, int m, const double *G, double tau, double
  *   otherwise; M may be NULL); 5 keeps H in eight-row tiles in binary16:
  *   each value is the FP32 value times 2^e, rounded to nearest even, with e
  *   chosen so the largest |H| lands in [2^14, 2^15), and the product scales
- *   its FP32 sums by 2^-e (the preconditioner's default storage: half the
- *   bytes per value, relative error 2^-11 per value).
+ *   its FP32 sums by 2^-e (half the bytes per value, relative error 2^-11
+ *   per value); 6 keeps the values of 5 in K-blocks of 16 union entries,
+ *   [kblock][8 rows][16 entries], for the matrix-core products (the
+ *   preconditioner's default form at block widths 32 and 64).
  *   Device memory owned by the handle until rowtiles_destroy (destroy it
  *   before its context). The CSR may be freed afterwards.
  * spmm_rowtiles: [HY, MY] = [H, M] Y as spmm_hm, on the copy; sub selects a
@@ -323,7 +330,10 @@ int rayleigh_ritz(ff_ctx *ctx, int w, int m, const double *G, double tau, double
  *   needs), at precision 0 in FP64. A handle built with precision 3, 4 or 5
  *   takes only this form, at precision 1, with leading dimensions that are
  *   multiples of 4 and m % 8 == 0, 8 <= m <= 64, 64 % (m / 8) == 0 (eight
- *   rows) or m in {4, 8, 12, 16, 32, 64} (sixteen rows). Errors: invalid
+ *   rows) or m in {4, 8, 12, 16, 32, 64} (sixteen rows). A handle built
+ *   with precision 6 also takes precision 2: Y in binary16 ([n][m] with
+ *   ld_y == m, m 32 or 64), HY = H Y in FP32, accumulated in FP32 on
+ *   v_mfma_f32_16x16x16_f16 (MY NULL). Errors: invalid
  *   arguments and unsupported shapes return FF_ERR_INVALID_ARG, a
  *   non-finite H at precision 5 likewise.
  */

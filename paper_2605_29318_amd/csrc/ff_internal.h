@@ -31,6 +31,8 @@ enum WsSlot {
     WS_CHEB0, WS_CHEB1, WS_CHEB2, WS_CHEB3, WS_CHEB4,             // Chebyshev-Jacobi work
     WS_RT8_CNT, WS_RT8_PTR, WS_RT8_COL, WS_RT8_VAL, WS_RT8_VALM,  // eight-row tile copy (H, and M)
     WS_RT8_VAL16, WS_RT8_MAX,                                     // its FP16 copy of H and |H| max
+    WS_RTQ_CNT, WS_RTQ_PTR, WS_RTQ_VAL,                           // K-blocked FP16 copy (matrix cores)
+    WS_CHEBQ,                                                     // column maxima of the scaled recurrence
     WS_RT16_CNT, WS_RT16_PTR, WS_RT16_COL, WS_RT16_VAL,           // sixteen-row H-only tile copy
     WS_SUBCELL,                                                   // sub-cell codes of the binning
     WS_COUNT

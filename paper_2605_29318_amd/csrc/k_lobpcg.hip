@@ -441,14 +441,16 @@ __global__ void __launch_bounds__(256) gram_reduce_kernel(const int *obj_status,
 template <typename T>
 __global__ void __launch_bounds__(256) resid_kernel(const UChunk *chunks, const int *obj_status, T *S, const T *HS,
                                                     const T *MS, int64_t ld, int m, const double *theta,
-                                                    const T *dinv, double *rpart) {
+                                                    const T *dinv, double *rpart, float *wpart) {
     const UChunk ch = chunks[blockIdx.x];
     if (obj_status[ch.obj] != 0) return;
     const int rows_per = 256 / m;
     const int t = threadIdx.x;
     const int rr = t / m, c = t - (t / m) * m;
     __shared__ double red[2][256];
+    __shared__ float wred[256];
     double r2 = 0.0, x2 = 0.0;
+    float wmax = 0.f;
     if (rr < rows_per) {
         const double th = theta[(size_t)ch.obj * m + c];
         for (int64_t r = ch.r0 + rr; r < ch.r0 + ch.len; r += rows_per) {
@@ -456,20 +458,26 @@ __global__ void __launch_bounds__(256) resid_kernel(const UChunk *chunks, const 
             const double R = (double)HS[r * ld + c] - th * (double)MS[r * ld + c];
             r2 += R * R;
             x2 += x * x;
-            S[r * ld + m + c] = (T)(dinv ? R * (double)dinv[r] : R);
+            const T w = (T)(dinv ? R * (double)dinv[r] : R);
+            S[r * ld + m + c] = w;
+            wmax = fmaxf(wmax, fabsf((float)w));
         }
     }
     red[0][t] = r2;
     red[1][t] = x2;
+    wred[t] = wmax;
     __syncthreads();
     if (t < m) {
         double a = 0.0, b = 0.0;
+        float w = 0.f;
         for (int q = 0; q < rows_per; ++q) {
             a += red[0][q * m + t];
             b += red[1][q * m + t];
+            w = fmaxf(w, wred[q * m + t]);
         }
         rpart[(size_t)blockIdx.x * 2 * m + t] = a;
         rpart[(size_t)blockIdx.x * 2 * m + m + t] = b;
+        if (wpart) wpart[(size_t)blockIdx.x * m + t] = w;
     }
 }
 
@@ -1719,6 +1727,39 @@ __global__ void cheb_init_kernel(int64_t n, int m, int64_t ld, const int *row_ob
     *w = (T)dz;
 }
 
+// The binary16 recurrence of the matrix-core steps starts from s W per object o and column c,
+// s = 1 / max_rows |W[., c]| (1 for a zero column): the preconditioner is linear, so this scales
+// column c of its output by s, which leaves the span the Rayleigh-Ritz step works on unchanged,
+// and it keeps the iterates inside the binary16 range whatever the residuals' magnitude.
+__global__ void colmax_obj_kernel(int n_obj, const int *obj_status, const int *cfirst, const int *ccount,
+                                  const float *wpart, int m, float *cmax) {
+    const int o = blockIdx.x, c = threadIdx.x;
+    if (o >= n_obj || c >= m || obj_status[o] != 0) return;
+    float v = 0.f;
+    for (int i = 0; i < ccount[o]; ++i) v = fmaxf(v, wpart[(size_t)(cfirst[o] + i) * m + c]);
+    cmax[(size_t)o * m + c] = v;
+}
+
+// z0 of the binary16 recurrence: R <- s W, dz = binary16(s W / theta), W <- dz
+__global__ void cheb_init_q_kernel(int64_t n, int m, int64_t ld, const int *row_obj, const int *obj_status,
+                                   const double *coef, const float *cmax, float *S, float *Rb, _Float16 *DZ) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * m) return;
+    const int64_t r = t / m;
+    const int c = (int)(t - r * m);
+    const int o = row_obj[r];
+    if (obj_status[o] != 0) return;
+    float *w = S + r * ld + m + c;
+    const float mx = cmax[(size_t)o * m + c];
+    const double v = (double)*w * (mx > 0.f ? 1.0 / (double)mx : 1.0);
+    double dz = v * coef[(size_t)o * kChebCoef];
+    dz = dz > 65504.0 ? 65504.0 : (dz < -65504.0 ? -65504.0 : dz);
+    const _Float16 h = (_Float16)(float)dz;
+    Rb[t] = (float)v;
+    DZ[t] = h;
+    *w = (float)h;
+}
+
 // step s: R -= D^-1 H dz, dz = f1 dz + f2 R, W += dz
 template <typename T>
 __global__ void cheb_step_kernel(int64_t n, int m, int64_t ld, int step, const int *row_obj, const int *obj_status,
@@ -1881,6 +1922,9 @@ struct Solver {
     rt::RTView rtv;                                // row-tile copy when a row-tile variant is selected
     rt::RT8View rt8;                               // eight-row H-only copy for the FP32 preconditioner
     rt::RT16View rt16;                             // sixteen-row H-only copy (MFMA form), preferred
+    rt::RTQView rtq;                               // K-blocked binary16 copy: matrix-core Chebyshev steps
+    bool q_on = false;                             // the FP32 preconditioner runs the matrix-core steps
+    float *wpart = nullptr, *cmax = nullptr;       // [chunks][m], [n_obj][m] column maxima of D^-1 R
     bool jacobi = false;
     int cheb = 0;                                  // Chebyshev-Jacobi degree (0: plain Jacobi or none)
     double *cheb_coef = nullptr;                   // [n_obj][kChebCoef]
@@ -2027,7 +2071,7 @@ int stage_resid(Solver &s, T *S, T *HS, T *MS, double tol, int stall) {
     StageMark mark(s.ctx, s.st, FF_STAGE_RESID);
     hipLaunchKernelGGL(resid_kernel<T>, dim3(s.ng), dim3(256), 0, s.st, s.gch, s.status, S, (const T *)HS,
                        (const T *)MS, (int64_t)3 * s.m, s.m, s.theta, s.jacobi ? dinv_of<T>(s) : (const T *)nullptr,
-                       s.rpart);
+                       s.rpart, sizeof(T) == 4 && s.q_on ? s.wpart : (float *)nullptr);
     FF_CHECK_LAUNCH(s.ctx);
     hipLaunchKernelGGL(norms_kernel, dim3(s.n_obj), dim3(1024), 0, s.st, s.status, s.gfirst, s.gcount, s.rpart, s.m,
                        s.k, s.theta, s.norms, tol, stall, s.res, s.track);
@@ -2044,6 +2088,34 @@ int stage_precond(Solver &s, T *S) {
     const int64_t cnt = s.N * s.m;
     const int64_t ld = 3 * (int64_t)s.m;
     T *Rb = (T *)s.cheb_r, *DZ = (T *)s.cheb_dz, *HD = (T *)s.cheb_hd, *MD = (T *)s.cheb_md;
+    if (sizeof(T) == 4 && s.q_on) {
+        // binary16 iterate in the DZ buffer (two [N][m] halves), scaled start
+        uint16_t *q16[2] = {(uint16_t *)s.cheb_dz, (uint16_t *)s.cheb_dz + s.N * s.m};
+        {
+            StageMark mark(s.ctx, s.st, FF_STAGE_PRECOND_OTHER);
+            hipLaunchKernelGGL(colmax_obj_kernel, dim3(s.n_obj), dim3(64), 0, s.st, s.n_obj, s.status, s.gfirst,
+                               s.gcount, s.wpart, s.m, s.cmax);
+            FF_CHECK_LAUNCH(s.ctx);
+            hipLaunchKernelGGL(cheb_init_q_kernel, dim3(grid_for(cnt, 256)), dim3(256), 0, s.st, s.N, s.m, ld,
+                               s.row_obj, s.status, s.cheb_coef, s.cmax, (float *)S, (float *)Rb, (_Float16 *)q16[0]);
+            FF_CHECK_LAUNCH(s.ctx);
+        }
+        StageMark mark(s.ctx, s.st, FF_STAGE_PRECOND_PRODUCT, s.cheb - 1);
+        for (int step = 1; step < s.cheb; ++step) {
+            rt::ChebStepQ cs;
+            cs.coef = s.cheb_coef;
+            cs.stride = kChebCoef;
+            cs.step = step;
+            cs.dinv = (const float *)dinv_of<T>(s);
+            cs.R = (float *)Rb;
+            cs.W = (float *)(S + s.m);
+            cs.ldw = ld;
+            cs.dz_out = q16[step & 1];
+            const int rc = rt::cheb_step_tq(s.ctx, s.st, s.rtq, s.m, q16[(step - 1) & 1], s.row_obj, s.status, cs);
+            if (rc) return rc;
+        }
+        return FF_OK;
+    }
     {
         StageMark mark(s.ctx, s.st, FF_STAGE_PRECOND_OTHER);
         hipLaunchKernelGGL(cheb_init_kernel<T>, dim3(grid_for(cnt, 256)), dim3(256), 0, s.st, s.N, s.m, ld,
@@ -2430,8 +2502,9 @@ int solve(ff_ctx *ctx, int n_obj, const int64_t *obj_off, const int64_t *row_ptr
                "Chebyshev degree %d must be 0 (default %d) or in [2, 16]", p->precond_degree, kChebDefault);
     FF_REQUIRE(ctx, p->precond != 2 || p->precond_ratio == 0.0 || (p->precond_ratio > 1.0 && p->precond_ratio <= 1e6),
                "Chebyshev interval ratio %g must be 0 (default %g) or in (1, 1e6]", p->precond_ratio, kChebRatio);
-    FF_REQUIRE(ctx, p->precond_values >= 0 && p->precond_values <= 2,
-               "precond_values %d must be 0 (default FP16), 1 (FP32) or 2 (FP16)", p->precond_values);
+    FF_REQUIRE(ctx, p->precond_values >= 0 && p->precond_values <= 3,
+               "precond_values %d must be 0 (default), 1 (FP32), 2 (binary16 H) or 3 (binary16 H and iterate)",
+               p->precond_values);
     int m = p->block > 0 ? p->block : ((p->k + 7) / 8) * 8;
     FF_REQUIRE(ctx, m >= p->k && m % 8 == 0 && m >= 8 && m <= 64, "block %d: needs k <= m <= 64, m multiple of 8", m);
     Solver s;
@@ -2496,8 +2569,20 @@ int solve(ff_ctx *ctx, int n_obj, const int64_t *obj_off, const int64_t *row_ptr
         // product at 1M particles, m = 32; it serves the widths the eight-row kernel does not take)
         if (p->precision == 1 && s.var32 >= kRowTileBase && rt::t8_ok(s.m, s.m, s.m)) {
             if (!s.rt8.vh) rc = rt::build_t8_ws(ctx, s.st, s.N, row_ptr, col, H, &s.rt8);
-            // H in binary16 for these products: 1.86 value slots per nonzero at 2 bytes instead of 4
-            if (!rc && p->precond_values != 1) rc = rt::build_t8_half(ctx, s.st, &s.rt8);
+            // H in binary16 for these products: 1.75 value slots per nonzero at 2 bytes instead of 4;
+            // with the iterate in binary16 too (block widths 32 and 64) the products run on the matrix
+            // cores, otherwise on the FP32 VALU
+            const bool q = p->precond_values == 3 || (p->precond_values == 0 && rt::tq_ok(s.m));
+            FF_REQUIRE(ctx, !q || rt::tq_ok(s.m), "binary16 iterate needs block width 32 or 64 (m = %d)", s.m);
+            if (!rc && q) {
+                rc = rt::build_tq(ctx, s.st, s.rt8, &s.rtq);
+                s.wpart = (float *)ws_get(ctx, WS_CHEBQ, ((size_t)s.ng + s.n_obj) * s.m * sizeof(float));
+                if (!rc && !s.wpart) rc = FF_ERR_OOM;
+                s.cmax = s.wpart + (size_t)s.ng * s.m;
+                s.q_on = rc == FF_OK;
+            } else if (!rc && p->precond_values != 1) {
+                rc = rt::build_t8_half(ctx, s.st, &s.rt8);
+            }
             if (rc) return rc;
         } else if (p->precision == 1 && s.var32 >= kRowTileBase && rt::t16_ok(s.m, s.m, s.m)) {
             rc = rt::build_t16_ws(ctx, s.st, s.N, row_ptr, col, H, &s.rt16);

@@ -80,6 +80,43 @@ int spmm_h_t8(ff_ctx *ctx, hipStream_t st, const RT8View &v, int sub, int m, con
 int cheb_step_t8(ff_ctx *ctx, hipStream_t st, const RT8View &v, int sub, int m, const float *DZ, int64_t ld,
                  const int *row_obj, const int *status, const ChebStep<float> &cs);
 
+// The preconditioner's Chebyshev step on the matrix cores: H of the eight-row
+// tiles in binary16 (scaled by 2^e as vh16), cut into K-blocks of 16 union
+// entries, vq[kblock][8 rows][16 entries] (zero past a tile's last entry), and
+// the iterate DZ in binary16, [rows][m]; products accumulate in FP32 on
+// v_mfma_f32_16x16x16_f16.
+struct RTQView {
+    int64_t n = 0, ntiles = 0, nkb = 0;
+    const int64_t *tptr = nullptr;   // [ntiles + 1] union entries of the eight-row copy
+    const int32_t *tcol = nullptr;   // [entries]
+    const int64_t *kptr = nullptr;   // [ntiles + 1] first K-block of each tile
+    const uint16_t *vq = nullptr;    // [nkb][8][16] binary16 bits
+    float hscale = 1.f;              // 2^-e
+};
+// builds the K-blocked copy from the FP32 values of a built eight-row copy into workspace slots;
+// build_tq_ptr (tile K-block pointers kptr[ntiles + 1], cnt[ntiles + 1] scratch, their total nkb)
+// and build_tq_fill (nkb * 128 binary16 values) do the same into the caller's storage
+int build_tq(ff_ctx *ctx, hipStream_t st, const RT8View &v8, RTQView *out);
+int build_tq_ptr(ff_ctx *ctx, hipStream_t st, const RT8View &v8, int64_t *kptr, int64_t *cnt, int64_t *nkb);
+int build_tq_fill(ff_ctx *ctx, hipStream_t st, const RT8View &v8, const int64_t *kptr, int64_t nkb, uint16_t *vq,
+                  RTQView *out);
+// block widths the matrix-core kernels take: m in {32, 64}
+bool tq_ok(int m);
+// one Chebyshev step, binary16 iterate: R -= D^-1 H DZ, DZ' = f1 DZ + f2 R (stored in binary16),
+// W += DZ'; DZ and dz_out are [rows][m], R has leading dimension m, W ldw
+struct ChebStepQ {
+    const double *coef = nullptr;
+    int stride = 0, step = 0;
+    const float *dinv = nullptr;
+    float *R = nullptr, *W = nullptr;
+    uint16_t *dz_out = nullptr;
+    int64_t ldw = 0;
+};
+int cheb_step_tq(ff_ctx *ctx, hipStream_t st, const RTQView &v, int m, const uint16_t *DZ, const int *row_obj,
+                 const int *status, const ChebStepQ &cs);
+// HY = H Y (Y binary16 [rows][m], HY FP32 with leading dimension ldo)
+int spmm_h_tq(ff_ctx *ctx, hipStream_t st, const RTQView &v, int m, const uint16_t *Y, float *HY, int64_t ldo);
+
 // H-only FP32 copy in tiles of sixteen rows, for the MFMA form of the
 // preconditioner's products: vh[entry][16].
 constexpr int kTile16 = 16;

@@ -12,7 +12,8 @@ struct ff_rowtiles {
     ff::rt::RTView v;
     ff::rt::RT8View v8;
     ff::rt::RT16View v16;
-    void *mem[4] = {nullptr, nullptr, nullptr, nullptr};
+    ff::rt::RTQView vq;                            // K-blocked binary16 copy (precision 6)
+    void *mem[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
 };
 
 namespace ff {
@@ -954,17 +955,17 @@ __global__ void to_half_kernel(int64_t n8, const float *v, float scale, f32x4 *o
     out[i] = __builtin_bit_cast(f32x4, h);
 }
 
-int build_t8_half(ff_ctx *ctx, hipStream_t st, RT8View *v, uint16_t *out16) {
-    FF_REQUIRE(ctx, v != nullptr && v->vh != nullptr && v->entries >= 0, "FP16 tile copy needs a built FP32 copy");
-    const int64_t n8 = v->entries;                 // one group of eight values per entry
+// the exponent e of the binary16 copies: 2^e puts the largest |vh| in [2^14, 2^15), so binary16 holds
+// it with room to spare and the relative rounding error stays 2^-11 down to 2^-29 of it (below that
+// subnormal, then zero); synchronises the stream once
+static int half_exponent(ff_ctx *ctx, hipStream_t st, const float *vh, int64_t n8, int *e_out) {
     uint32_t *mx = (uint32_t *)ws_get(ctx, WS_RT8_MAX, 256);
-    if (!out16) out16 = (uint16_t *)ws_get(ctx, WS_RT8_VAL16, (size_t)std::max<int64_t>(n8, 1) * 8 * 2);
     uint32_t *hbuf = (uint32_t *)pinned_get(ctx, 64);
-    if (!mx || !out16 || !hbuf) return FF_ERR_OOM;
+    if (!mx || !hbuf) return FF_ERR_OOM;
     FF_HIP(ctx, hipMemsetAsync(mx, 0, sizeof(uint32_t), st));
     if (n8 > 0) {
         const int64_t blocks = std::min<int64_t>(grid_for(2 * n8, 256), 8192);
-        hipLaunchKernelGGL(absmax_f32_kernel, dim3(blocks), dim3(256), 0, st, 2 * n8, v->vh, mx);
+        hipLaunchKernelGGL(absmax_f32_kernel, dim3(blocks), dim3(256), 0, st, 2 * n8, vh, mx);
         FF_CHECK_LAUNCH(ctx);
     }
     FF_HIP(ctx, hipMemcpyAsync(hbuf, mx, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
@@ -972,14 +973,24 @@ int build_t8_half(ff_ctx *ctx, hipStream_t st, RT8View *v, uint16_t *out16) {
     float amax;
     std::memcpy(&amax, hbuf, sizeof(float));
     FF_REQUIRE(ctx, std::isfinite(amax), "non-finite value in H");
-    // scale 2^e puts the largest magnitude in [2^14, 2^15): binary16 holds it with room to spare, and the
-    // relative rounding error stays 2^-11 down to 2^-29 of it (below that subnormal, then zero)
     int e = 0;
     if (amax > 0.f) {
         int p;
         (void)std::frexp(amax, &p);                // amax in [2^(p-1), 2^p)
         e = std::max(-126, std::min(126, 15 - p));
     }
+    *e_out = e;
+    return FF_OK;
+}
+
+int build_t8_half(ff_ctx *ctx, hipStream_t st, RT8View *v, uint16_t *out16) {
+    FF_REQUIRE(ctx, v != nullptr && v->vh != nullptr && v->entries >= 0, "FP16 tile copy needs a built FP32 copy");
+    const int64_t n8 = v->entries;                 // one group of eight values per entry
+    if (!out16) out16 = (uint16_t *)ws_get(ctx, WS_RT8_VAL16, (size_t)std::max<int64_t>(n8, 1) * 8 * 2);
+    if (!out16) return FF_ERR_OOM;
+    int e = 0;
+    int rc = half_exponent(ctx, st, v->vh, n8, &e);
+    if (rc) return rc;
     if (n8 > 0) {
         hipLaunchKernelGGL(to_half_kernel, dim3(grid_for(n8, 256)), dim3(256), 0, st, n8, v->vh,
                            std::ldexp(1.f, e), (f32x4 *)out16);
@@ -988,6 +999,239 @@ int build_t8_half(ff_ctx *ctx, hipStream_t st, RT8View *v, uint16_t *out16) {
     v->vh16 = out16;
     v->hscale = std::ldexp(1.f, -e);
     return FF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// The preconditioner's Chebyshev step on the matrix cores (binary16 operands)
+// ---------------------------------------------------------------------------
+//
+// Per tile, (H DZ)^T [columns][8 rows] = DZ^T [columns][entries] . V^T [entries]
+// [rows] on v_mfma_f32_16x16x16_f16: 16 columns of the block form the A/D row
+// index, 16 union entries the contraction index, the tile's rows the B/D column
+// index (8 of its 16 slots carry rows, the other 8 are never stored). A lane's
+// A operand holds one column of four consecutive entries, i.e. four different
+// gathered rows of DZ: the wave loads the K-block's 16 rows of DZ with 16-byte
+// loads, stages them in LDS and reads the fragments back column-wise. The B
+// operand is read straight from the K-blocked copy (8 bytes per lane). Lane l
+// ends up with rows l % 16 (< 8 kept) at columns 16 cb + 4 (l / 16) + 0..3.
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+
+__global__ void tq_count_kernel(int64_t ntiles, const int64_t *tptr, int64_t *cnt) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < ntiles) cnt[t] = (tptr[t + 1] - tptr[t] + 15) / 16;
+}
+
+// one 64-thread block per tile; K-block kb holds the tile's entries 16 kb .. 16 kb + 15: thread s
+// takes values s and s + 64 of the block's 128 (entry-major in vh, so the reads are contiguous)
+// and writes them to [row][entry]
+__global__ void __launch_bounds__(64) tq_fill_kernel(int64_t ntiles, const int64_t *tptr, const int64_t *kptr,
+                                                    const float *vh, float scale, _Float16 *vq) {
+    const int64_t t = blockIdx.x;
+    if (t >= ntiles) return;
+    const int64_t e0 = tptr[t], e1 = tptr[t + 1], k0 = kptr[t], nk = kptr[t + 1] - k0;
+    for (int64_t kb = 0; kb < nk; ++kb) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int s = threadIdx.x + 64 * h;
+            const int k = s >> 3, r = s & 7;
+            const int64_t e = e0 + 16 * kb + k;
+            const float v = e < e1 ? vh[e * kTile8 + r] * scale : 0.f;
+            vq[(k0 + kb) * 128 + r * 16 + k] = (_Float16)v;
+        }
+    }
+}
+
+// K-block pointers of the tiles (kptr[ntiles + 1]; cnt[ntiles + 1] scratch) and their total
+int build_tq_ptr(ff_ctx *ctx, hipStream_t st, const RT8View &v8, int64_t *kptr, int64_t *cnt, int64_t *nkb) {
+    FF_REQUIRE(ctx, v8.vh != nullptr && v8.tptr != nullptr && v8.ntiles > 0 && kptr && cnt && nkb,
+               "K-blocked copy needs a built eight-row FP32 copy");
+    hipLaunchKernelGGL(tq_count_kernel, dim3(grid_for(v8.ntiles, 256)), dim3(256), 0, st, v8.ntiles, v8.tptr, cnt);
+    FF_CHECK_LAUNCH(ctx);
+    int rc = scan_exclusive_i64(ctx, cnt, kptr, v8.ntiles);
+    if (rc) return rc;
+    int64_t *h = (int64_t *)pinned_get(ctx, 64);
+    if (!h) return FF_ERR_OOM;
+    FF_HIP(ctx, hipMemcpyAsync(h, kptr + v8.ntiles, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    FF_HIP(ctx, hipStreamSynchronize(st));
+    *nkb = h[0];
+    return FF_OK;
+}
+
+// the binary16 values into vq (nkb * 128 halves), scaled as the eight-row binary16 copy
+int build_tq_fill(ff_ctx *ctx, hipStream_t st, const RT8View &v8, const int64_t *kptr, int64_t nkb, uint16_t *vq,
+                  RTQView *out) {
+    FF_REQUIRE(ctx, out && vq && kptr, "bad arguments");
+    int e = 0;
+    int rc = half_exponent(ctx, st, v8.vh, v8.entries, &e);
+    if (rc) return rc;
+    hipLaunchKernelGGL(tq_fill_kernel, dim3(v8.ntiles), dim3(64), 0, st, v8.ntiles, v8.tptr, kptr, v8.vh,
+                       std::ldexp(1.f, e), (_Float16 *)vq);
+    FF_CHECK_LAUNCH(ctx);
+    out->n = v8.n;
+    out->ntiles = v8.ntiles;
+    out->nkb = nkb;
+    out->tptr = v8.tptr;
+    out->tcol = v8.tcol;
+    out->kptr = kptr;
+    out->vq = vq;
+    out->hscale = std::ldexp(1.f, -e);
+    return FF_OK;
+}
+
+int build_tq(ff_ctx *ctx, hipStream_t st, const RT8View &v8, RTQView *out) {
+    const int64_t ntiles = v8.ntiles;
+    int64_t *kptr = (int64_t *)ws_get(ctx, WS_RTQ_PTR, (size_t)(ntiles + 1) * sizeof(int64_t));
+    int64_t *cnt = (int64_t *)ws_get(ctx, WS_RTQ_CNT, (size_t)(ntiles + 1) * sizeof(int64_t));
+    if (!kptr || !cnt) return FF_ERR_OOM;
+    int64_t nkb = 0;
+    int rc = build_tq_ptr(ctx, st, v8, kptr, cnt, &nkb);
+    if (rc) return rc;
+    uint16_t *vq = (uint16_t *)ws_get(ctx, WS_RTQ_VAL, (size_t)std::max<int64_t>(nkb, 1) * 128 * 2);
+    if (!vq) return FF_ERR_OOM;
+    return build_tq_fill(ctx, st, v8, kptr, nkb, vq, out);
+}
+
+bool tq_ok(int m) { return m == 32 || m == 64; }
+
+template <int kMB, bool kEpi, int kWaves, int kOcc>
+__global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(kOcc, 8)))
+spmm_tq_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int32_t *tcol, const int64_t *kptr,
+               const _Float16 *vq, float vscale, const _Float16 *Y, float *HY, int64_t ldo, const int *row_obj,
+               const int *obj_status, ChebStepQ cs) {
+    constexpr int m = 16 * kMB;
+    constexpr int kPieces = m / 8;                 // 16-byte pieces of a binary16 row of the block
+    constexpr int kRowsPer = 64 / kPieces;         // rows one wave-wide load covers (16 or 8)
+    constexpr int kLoads = 16 / kRowsPer;          // loads per K-block (1 or 2)
+    constexpr int kStride = 2 * m + 16;            // LDS row stride in bytes: the four entry quads of a
+                                                   // fragment read fall on different banks
+    __shared__ __align__(16) unsigned char ys[kWaves][16 * kStride];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t t = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kWaves + wv;
+    if (t >= ntiles) return;
+    const int64_t r0 = t * kTile8;
+    const int rr = lane & 15, quad = lane >> 4;
+    const int64_t rme = r0 + (rr & 7);
+    const bool mine = rr < 8 && rme < nrows && (!obj_status || obj_status[row_obj[rme]] == 0);
+    bool any = false;
+#pragma unroll
+    for (int i = 0; i < kTile8; ++i)
+        any = any || (r0 + i < nrows && (!obj_status || obj_status[row_obj[r0 + i]] == 0));
+    if (!any) return;
+    const int64_t e0 = tptr[t], e1 = tptr[t + 1], k0 = kptr[t];
+    const int nk = (int)(kptr[t + 1] - k0);
+    const int piece = lane % kPieces, slot = lane / kPieces;
+    unsigned char *sy = ys[wv];
+    // entries past the tile's end read its last column (their values are zero), so every load is
+    // unconditional
+    auto col_of = [&](int kb, int i) -> uint32_t {
+        const int64_t e = e0 + 16 * kb + slot + kRowsPer * i;
+        return (uint32_t)tcol[e < e1 ? e : e1 - 1];
+    };
+    auto load_y = [&](uint32_t j) -> f32x4 {
+        return *(const f32x4 *)(Y + (size_t)(j * (uint32_t)m) + piece * 8);
+    };
+    auto load_v = [&](int kb) -> f16x4 {
+        return __builtin_nontemporal_load((const f16x4 *)(vq + (k0 + kb) * 128 + (rr & 7) * 16 + 4 * quad));
+    };
+    f32x4 acc[kMB];
+#pragma unroll
+    for (int cb = 0; cb < kMB; ++cb) acc[cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (nk > 0) {
+        f32x4 yc[kLoads];
+        uint32_t jn[kLoads];
+#pragma unroll
+        for (int i = 0; i < kLoads; ++i) yc[i] = load_y(col_of(0, i));
+        f16x4 bc = load_v(0);
+#pragma unroll
+        for (int i = 0; i < kLoads; ++i) jn[i] = col_of(nk > 1 ? 1 : 0, i);
+        for (int kb = 0; kb < nk; ++kb) {
+            // K-block kb + 1's rows (their columns are loaded), kb + 2's columns; the last pass reloads
+            // its own block, unused
+            const int kb1 = kb + 1 < nk ? kb + 1 : kb, kb2 = kb + 2 < nk ? kb + 2 : kb1;
+            f32x4 yn[kLoads];
+#pragma unroll
+            for (int i = 0; i < kLoads; ++i) yn[i] = load_y(jn[i]);
+            const f16x4 bn = load_v(kb1);
+#pragma unroll
+            for (int i = 0; i < kLoads; ++i) jn[i] = col_of(kb2, i);
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int i = 0; i < kLoads; ++i) *(f32x4 *)(sy + (slot + kRowsPer * i) * kStride + piece * 16) = yc[i];
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int cb = 0; cb < kMB; ++cb) {
+                f16x4 a;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) a[q] = *(const _Float16 *)(sy + (4 * quad + q) * kStride + (16 * cb + rr) * 2);
+                acc[cb] = __builtin_amdgcn_mfma_f32_16x16x16f16(a, bc, acc[cb], 0, 0, 0);
+            }
+#pragma unroll
+            for (int i = 0; i < kLoads; ++i) yc[i] = yn[i];
+            bc = bn;
+        }
+    }
+    if (!mine) return;
+    if (kEpi) {
+        const int o = row_obj[rme];
+        const double f1 = cs.coef[(size_t)o * cs.stride + 2 * cs.step - 1];
+        const double f2 = cs.coef[(size_t)o * cs.stride + 2 * cs.step];
+        const double dv = (double)cs.dinv[rme] * (double)vscale;
+        _Float16 *dzo = (_Float16 *)cs.dz_out;
+#pragma unroll
+        for (int cb = 0; cb < kMB; ++cb) {
+            const int c0 = 16 * cb + 4 * quad;
+            float *rp = cs.R + rme * m + c0, *wp = cs.W + rme * cs.ldw + c0;
+            const f32x4 er = *(const f32x4 *)rp, ew = *(const f32x4 *)wp;
+            const f16x4 ez = *(const f16x4 *)(Y + rme * m + c0);
+            f32x4 rv1, w1;
+            f16x4 dz1;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double rv = (double)er[q] - dv * (double)acc[cb][q];
+                double dz = f1 * (double)(float)ez[q] + f2 * rv;
+                dz = dz > 65504.0 ? 65504.0 : (dz < -65504.0 ? -65504.0 : dz);   // binary16 range
+                rv1[q] = (float)rv;
+                dz1[q] = (_Float16)(float)dz;
+                w1[q] = (float)((double)ew[q] + (double)(float)dz1[q]);
+            }
+            *(f32x4 *)rp = rv1;
+            *(f16x4 *)(dzo + rme * m + c0) = dz1;
+            *(f32x4 *)wp = w1;
+        }
+    } else {
+#pragma unroll
+        for (int cb = 0; cb < kMB; ++cb)
+            *(f32x4 *)(HY + rme * ldo + 16 * cb + 4 * quad) = acc[cb] * vscale;
+    }
+}
+
+template <bool kEpi>
+static int launch_tq(ff_ctx *ctx, hipStream_t st, const RTQView &v, int m, const uint16_t *Y, float *HY,
+                     int64_t ldo, const int *row_obj, const int *status, const ChebStepQ &cs) {
+    FF_REQUIRE(ctx, v.vq != nullptr && tq_ok(m), "matrix-core Chebyshev step: no K-blocked copy or m = %d", m);
+    FF_REQUIRE(ctx, v.n * (int64_t)m < ((int64_t)1 << 32), "block of %lld rows x %d too large for 32-bit offsets",
+               (long long)v.n, m);
+    const _Float16 *vq = (const _Float16 *)v.vq, *y = (const _Float16 *)Y;
+#define FF_TQ(MB, W, O)                                                                                        \
+    hipLaunchKernelGGL((spmm_tq_kernel<MB, kEpi, W, O>), dim3(grid_for(v.ntiles, W)), dim3(64 * W), 0, st, v.n, \
+                       v.ntiles, v.tptr, v.tcol, v.kptr, vq, v.hscale, y, HY, ldo, row_obj, status, cs)
+    if (m == 32) FF_TQ(2, 4, 4);
+    else FF_TQ(4, 4, 4);
+#undef FF_TQ
+    FF_CHECK_LAUNCH(ctx);
+    return FF_OK;
+}
+
+int cheb_step_tq(ff_ctx *ctx, hipStream_t st, const RTQView &v, int m, const uint16_t *DZ, const int *row_obj,
+                 const int *status, const ChebStepQ &cs) {
+    FF_REQUIRE(ctx, DZ && row_obj && cs.R && cs.W && cs.dz_out && cs.dinv && cs.coef && cs.ldw % 4 == 0,
+               "matrix-core Chebyshev step: bad arguments");
+    return launch_tq<true>(ctx, st, v, m, DZ, nullptr, 0, row_obj, status, cs);
+}
+
+int spmm_h_tq(ff_ctx *ctx, hipStream_t st, const RTQView &v, int m, const uint16_t *Y, float *HY, int64_t ldo) {
+    FF_REQUIRE(ctx, Y && HY && ldo >= m && ldo % 4 == 0, "matrix-core product: bad arguments");
+    return launch_tq<false>(ctx, st, v, m, Y, HY, ldo, nullptr, nullptr, ChebStepQ{});
 }
 
 // ---------------------------------------------------------------------------
@@ -1375,9 +1619,9 @@ int rowtiles_build(ff_ctx *ctx, int64_t n, const int64_t *row_ptr, const int32_t
     if (!ctx || !out) return FF_ERR_INVALID_ARG;
     *out = nullptr;
     FF_REQUIRE(ctx, n > 0 && row_ptr && col && H && (M || precision >= 3), "bad arguments");
-    FF_REQUIRE(ctx, precision >= 0 && precision <= 5,
-               "precision must be 0 (FP64), 1 (FP32), 2 (both), 3 or 4 (FP32 H only, eight- or sixteen-row tiles) "
-               "or 5 (H only in FP16, eight-row tiles)");
+    FF_REQUIRE(ctx, precision >= 0 && precision <= 6,
+               "precision must be 0 (FP64), 1 (FP32), 2 (both), 3 or 4 (FP32 H only, eight- or sixteen-row tiles), "
+               "5 (H only in binary16, eight-row tiles) or 6 (5 in K-blocks for the matrix cores)");
     FF_HIP(ctx, hipSetDevice(ctx->device));
     hipStream_t st = ctx->stream;
     ff_rowtiles *h = new ff_rowtiles();
@@ -1429,6 +1673,27 @@ int rowtiles_build(ff_ctx *ctx, int64_t n, const int64_t *row_ptr, const int32_t
             }
             h->mem[3] = v16;
             if (!rc8) rc8 = rt::build_t8_half(ctx, st, &h->v8, v16);
+        }
+        if (!rc8 && precision == 6) {
+            int64_t *kp = nullptr, *kc = nullptr, nkb = 0;
+            if (hipMalloc((void **)&kp, (size_t)(nt8 + 1) * sizeof(int64_t)) != hipSuccess ||
+                hipMalloc((void **)&kc, (size_t)(nt8 + 1) * sizeof(int64_t)) != hipSuccess) {
+                (void)hipGetLastError();
+                rc8 = set_error(ctx, FF_ERR_OOM, "row-tile allocation failed");
+            }
+            h->mem[4] = kp;
+            if (!rc8) rc8 = rt::build_tq_ptr(ctx, st, h->v8, kp, kc, &nkb);
+            if (kc) {
+                (void)hipStreamSynchronize(st);
+                (void)hipFree(kc);
+            }
+            uint16_t *vq = nullptr;
+            if (!rc8 && hipMalloc((void **)&vq, (size_t)std::max<int64_t>(nkb, 1) * 128 * 2) != hipSuccess) {
+                (void)hipGetLastError();
+                rc8 = set_error(ctx, FF_ERR_OOM, "row-tile allocation of %lld K-blocks failed", (long long)nkb);
+            }
+            h->mem[5] = vq;
+            if (!rc8) rc8 = rt::build_tq_fill(ctx, st, h->v8, kp, nkb, vq, &h->vq);
         }
         if (!rc8 && hipStreamSynchronize(st) != hipSuccess)
             rc8 = set_error(ctx, FF_ERR_HIP, "row-tile build failed");
@@ -1498,7 +1763,14 @@ int spmm_rowtiles(ff_ctx *ctx, const ff_rowtiles *rt, int precision, int m, cons
                   void *MY, int64_t ld_out, int sub) {
     if (!ctx || !rt) return FF_ERR_INVALID_ARG;
     FF_REQUIRE(ctx, Y && HY, "required pointer is NULL");
-    FF_REQUIRE(ctx, precision == 0 || precision == 1, "precision must be 0 or 1");
+    if (precision == 2) {
+        FF_REQUIRE(ctx, rt->vq.vq != nullptr && !MY, "binary16 blocks need a handle built with precision 6, MY NULL");
+        FF_REQUIRE(ctx, rt::tq_ok(m) && ld_y == m && ld_out >= m && ld_out % 4 == 0,
+                   "binary16 products take m in {32, 64}, ld_y == m, ld_out >= m and a multiple of 4");
+        FF_HIP(ctx, hipSetDevice(ctx->device));
+        return rt::spmm_h_tq(ctx, ctx->stream, rt->vq, m, (const uint16_t *)Y, (float *)HY, ld_out);
+    }
+    FF_REQUIRE(ctx, precision == 0 || precision == 1, "precision must be 0, 1 or 2");
     if (rt->hrows) {
         FF_REQUIRE(ctx, precision == 1 && !MY, "an H-only copy forms H Y alone in FP32 (MY must be NULL)");
         FF_REQUIRE(ctx, (rt->hrows == 8 ? rt::t8_ok(m, ld_y, ld_out) : rt::t16_ok(m, ld_y, ld_out)) && ld_y >= m &&

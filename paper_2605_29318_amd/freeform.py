@@ -357,11 +357,16 @@ class RowTiles:
         return nt.value, ne.value
 
     def spmm(self, Y, precision: int, sub: int = 0, out=None, h_only: bool = False):
-        """[HY, MY] = [H, M] Y; with h_only, (HY, None) from the preconditioner's product."""
+        """[HY, MY] = [H, M] Y; with h_only, (HY, None) from the preconditioner's product.
+        precision 2 takes a binary16 Y (a handle built with precision 6) and returns HY in FP32."""
         import torch
         n, m = Y.shape
+        if precision == 2:
+            if Y.dtype != torch.float16:
+                raise TypeError("precision 2 takes a float16 block")
+            h_only = True
         if out is None:
-            HY = torch.empty_like(Y)
+            HY = torch.empty_like(Y, dtype=torch.float32) if precision == 2 else torch.empty_like(Y)
             MY = None if h_only else torch.empty_like(Y)
         else:
             HY, MY = out

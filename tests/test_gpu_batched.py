@@ -73,6 +73,27 @@ def test_batched_matches_oracle(batch, oracle, ctx, ff, precision, graph, precon
     assert len(set(its)) > 1
 
 
+@pytest.mark.parametrize("graph", [False, True])
+def test_batched_matrix_core_chebyshev(batch, oracle, ctx, ff, graph):
+    """k = 32: the Chebyshev steps run on the matrix cores (binary16 H and iterate), each
+    object's columns scaled by their own maxima; objects finish at different iterations
+    and are masked while the rest go on."""
+    clouds, parts, refs = batch
+    k = 32
+    off, rp, col, H, M, hm = ff.concat_objects(parts)
+    lam, W, res, infos, rc = ff.eigenmodes_batched(ctx, off, rp, col, H, M, hm, k=k, precision=1, tol=1e-8,
+                                                   max_iter=8000, use_graph=graph, precond=2, precond_values=3)
+    assert rc == 0
+    Wh = W.cpu().numpy()
+    for o, (P, wd, Vd) in enumerate(refs):
+        assert infos[o]["converged"] == 1 and infos[o]["graph"] == int(graph)
+        assert np.abs(lam[o, 1:20] - wd[1:20]).max() / wd[1:20].min() <= 1e-5
+        Wo = Wh[off[o]:off[o + 1]]
+        assert oracle.residuals(P.Hs(), P.Ms(), lam[o], Wo).max() <= 2e-8
+        assert np.abs(Wo.T @ (P.Ms() @ Wo) - np.eye(k)).max() <= 1e-6
+        assert np.all(np.diff(lam[o]) >= -1e-9 * abs(lam[o, -1]))
+
+
 def test_batched_equals_single_object_solves(batch, ctx, ff):
     clouds, parts, refs = batch
     k = 16

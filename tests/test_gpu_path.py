@@ -276,7 +276,47 @@ def test_rowtiles_fp16_copy(oracle, ctx, ff):
             assert np.all(np.abs(HO - ref) <= (2.0 ** -11 + 2 * eps) * absH + 2.0 ** (-24 - e) * absY), (m, sub)
     rt.close()
     with pytest.raises(ff.FFError):
-        ff.RowTiles(ctx, A.n, A.row_ptr, A.col, A.H, None, precision=6)
+        ff.RowTiles(ctx, A.n, A.row_ptr, A.col, A.H, None, precision=7)
+
+
+def test_rowtiles_fp16_kblocked_matrix_core(oracle, ctx, ff):
+    """The matrix-core product: H in binary16 K-blocks (rowtiles_build precision 6),
+    a binary16 block Y, FP32 sums on v_mfma_f32_16x16x16_f16, ragged last tile and
+    tiles whose entry count is not a multiple of 16. Against H as stored (and Y exactly,
+    being binary16) the FP32 accumulation bound holds; against the exact H each value
+    adds at most 2^-11 relative."""
+    c = synth.random_cloud(2503, seed=29, hetero=True)
+    P = oracle.pipeline(c)
+    A = ff.assemble_cloud(ctx, dev(c.xyz), dev(c.vol), dev(c.lam), dev(c.mu), c.h)
+    rt = ff.RowTiles(ctx, A.n, A.row_ptr, A.col, A.H, None, precision=6)
+    Hq, e = _fp16_storage(P.H)
+    rl = np.diff(P.row_ptr)
+    eps = (8 * rl.max() + 8) * 2.0 ** -24
+    for m in (32, 64):
+        Y = np.random.default_rng(m).standard_normal((c.n, m)).astype(np.float16).astype(np.float64)
+        refq = oracle.spmm(P.row_ptr, P.col, Hq, Y)
+        absq = oracle.spmm(P.row_ptr, P.col, np.abs(Hq), np.abs(Y))
+        ref = oracle.spmm(P.row_ptr, P.col, P.H, Y)
+        absH = oracle.spmm(P.row_ptr, P.col, np.abs(P.H), np.abs(Y))
+        absY = oracle.spmm(P.row_ptr, P.col, np.ones_like(P.H), np.abs(Y))
+        HO, none = rt.spmm(dev(Y, torch.float16), 2)
+        assert none is None and HO.dtype == torch.float32
+        HO = host(HO)
+        assert np.all(np.abs(HO - refq) <= eps * absq + 1e-300), m
+        assert np.all(np.abs(HO - ref) <= (2.0 ** -11 + 2 * eps) * absH + 2.0 ** (-24 - e) * absY), m
+        # the FP32 forms of the same handle agree with the binary16 one to the stored values' rounding
+        HF, _ = rt.spmm(dev(Y, torch.float32), 1, h_only=True)
+        assert np.all(np.abs(host(HF) - ref) <= 2 * eps * absH + 1e-300), m
+    for m in (16, 48):
+        with pytest.raises(ff.FFError):
+            rt.spmm(dev(np.ones((c.n, m)), torch.float16), 2)
+    with pytest.raises(ff.FFError):      # binary16 products need the K-blocked copy
+        rt5 = ff.RowTiles(ctx, A.n, A.row_ptr, A.col, A.H, None, precision=5)
+        try:
+            rt5.spmm(dev(np.ones((c.n, 32)), torch.float16), 2)
+        finally:
+            rt5.close()
+    rt.close()
 
 
 def test_philox_known_answers(ctx, ff):
@@ -344,6 +384,22 @@ def test_eigenmodes_random_hetero(oracle, ctx, ff, precision, precond):
     _check_modes(oracle, P, lam, host(W), res, k, 1e-5, 1e-3, 1e-8)
 
 
+@pytest.mark.parametrize("values", [1, 2, 3])
+def test_eigenmodes_chebyshev_number_formats(oracle, ctx, ff, values):
+    """k = 32 (the benchmark's block width): the Chebyshev-Jacobi products with H and the
+    iterate in FP32 (1), H in binary16 (2), and both in binary16 on the matrix cores (3,
+    the default at this width, with per-column scaling of the recurrence); the converged
+    eigenpairs meet the same bounds in every case."""
+    c = synth.random_cloud(2500, seed=33, hetero=True)
+    P = oracle.pipeline(c)
+    A = ff.assemble_cloud(ctx, dev(c.xyz), dev(c.vol), dev(c.lam), dev(c.mu), c.h)
+    k = 32
+    lam, W, res, info = ff.eigenmodes(ctx, c.n, A.row_ptr, A.col, A.H, A.M, A.hm32, k=k, precision=1, tol=1e-8,
+                                      max_iter=8000, precond=2, precond_values=values)
+    assert info["converged"] == 1
+    _check_modes(oracle, P, lam, host(W), res, k, 1e-5, 1e-3, 1e-8)
+
+
 def test_eigenmodes_given_start_block(oracle, ctx, ff):
     c = synth.cube_lattice()
     P = oracle.pipeline(c)
@@ -366,7 +422,7 @@ def test_chebyshev_parameters_are_validated(ctx, ff):
     for bad in (0.5, 1.0, -3.0):
         with pytest.raises(ff.FFError):
             ff.eigenmodes(ctx, c.n, A.row_ptr, A.col, A.H, A.M, A.hm32, k=8, precond=2, precond_ratio=bad)
-    for bad in (-1, 3):
+    for bad in (-1, 4, 3):        # 3 needs block width 32 or 64
         with pytest.raises(ff.FFError):
             ff.eigenmodes(ctx, c.n, A.row_ptr, A.col, A.H, A.M, A.hm32, k=8, precond=2, precond_values=bad)
 
