@@ -71,6 +71,8 @@ typedef enum {
     FF_STAGE_RR,               /* Rayleigh-Ritz */
     FF_STAGE_UPDATE,           /* block update */
     FF_STAGE_RESID,            /* residual block, norms, convergence flags */
+    FF_STAGE_FP64_PHASE,       /* mixed path: the FP64 phase as a whole (certifying Rayleigh-Ritz and any
+                                  FP64 iterations); the stages above then cover the FP32 phase alone */
     FF_STAGE_TOTAL,            /* the whole call, host clock */
     FF_STAGE_COUNT
 } ff_stage;

@@ -161,8 +161,9 @@ int ff_ctx_stage_times(const ff_ctx *ctx, int n, double *ms, int64_t *launches) 
 }
 
 const char *ff_stage_name(int stage) {
-    static const char *names[FF_STAGE_COUNT] = {"spmm", "precond_product", "precond_other", "gram",
-                                                "rayleigh_ritz", "update", "resid", "total"};
+    static const char *names[FF_STAGE_COUNT] = {"spmm",          "precond_product", "precond_other", "gram",
+                                                "rayleigh_ritz", "update",          "resid",         "fp64_phase",
+                                                "total"};
     return stage >= 0 && stage < FF_STAGE_COUNT ? names[stage] : "";
 }
 

@@ -50,6 +50,7 @@ struct ff_ctx {
     size_t pinned_size = 0;
     std::unordered_map<std::string, int> tuned;   // SpMM shape key -> variant
     int timing = 0;                               // per-stage HIP-event timing of the solver
+    int timing_mute = 0;                          // stage marks inside a region timed as one stage
     std::vector<hipEvent_t> ev_pool;              // reusable timing events
     size_t ev_used = 0;
     std::vector<std::array<int, 4>> marks;        // stage, launches, start event, end event
@@ -75,7 +76,7 @@ struct StageMark {
     hipStream_t st;
     int stage, launches, e0 = -1;
     StageMark(ff_ctx *c, hipStream_t s, int stg, int n = 1) : ctx(c), st(s), stage(stg), launches(n) {
-        if (ctx->timing) e0 = timing_event(ctx, st);
+        if (ctx->timing && !ctx->timing_mute) e0 = timing_event(ctx, st);
     }
     void end() {
         if (e0 < 0) return;
@@ -86,6 +87,15 @@ struct StageMark {
     ~StageMark() { end(); }
     StageMark(const StageMark &) = delete;
     StageMark &operator=(const StageMark &) = delete;
+};
+// while alive (and on), StageMarks inside record nothing: an enclosing mark times the region as one stage
+struct TimingMute {
+    ff_ctx *ctx;
+    int prev;
+    TimingMute(ff_ctx *c, bool on) : ctx(c), prev(c->timing_mute) { if (on) ctx->timing_mute = 1; }
+    ~TimingMute() { ctx->timing_mute = prev; }
+    TimingMute(const TimingMute &) = delete;
+    TimingMute &operator=(const TimingMute &) = delete;
 };
 
 // Grow-only device buffer for a workspace slot; returns nullptr on failure

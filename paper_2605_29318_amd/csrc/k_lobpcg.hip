@@ -1628,6 +1628,7 @@ constexpr int kChebDefault = 12;               // degree when the caller passes 
 constexpr double kChebRatio = 1000.0;          // b / a when the caller passes 0
 constexpr int kChebT8Sub = 1;                  // launch shape of the fused step (fewer registers than the
                                                // H-only product's default with the step's operands live)
+constexpr int kChebTqSub = 0;                  // launch shape of the matrix-core Chebyshev step
 
 // Gershgorin bound of D^-1/2 H D^-1/2 per row: sum_j |H_ij| / sqrt(H_ii H_jj), one wavefront per row
 __global__ void gersh_row_kernel(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *H,
@@ -2111,7 +2112,8 @@ int stage_precond(Solver &s, T *S) {
             cs.W = (float *)(S + s.m);
             cs.ldw = ld;
             cs.dz_out = q16[step & 1];
-            const int rc = rt::cheb_step_tq(s.ctx, s.st, s.rtq, s.m, q16[(step - 1) & 1], s.row_obj, s.status, cs);
+            const int rc = rt::cheb_step_tq(s.ctx, s.st, s.rtq, kChebTqSub, s.m, q16[(step - 1) & 1], s.row_obj,
+                                            s.status, cs);
             if (rc) return rc;
         }
         return FF_OK;
@@ -2636,13 +2638,19 @@ int solve(ff_ctx *ctx, int n_obj, const int64_t *obj_off, const int64_t *row_ptr
                            (const double *)X0d, (int64_t)m, S64, (int64_t)3 * m);
         FF_CHECK_LAUNCH(ctx);
     }
-    // FP64: Rayleigh-Ritz on X with the FP64 matrices (the certification), then iterate if needed
-    if ((rc = reset_status(s, 0))) return rc;
-    if ((rc = init_block<double>(s, S64, HS64, MS64, tau64))) return rc;
-    const int left = std::max(0, p->max_iter - it32);
-    if ((rc = run_phase<double>(s, S64, HS64, MS64, left + 1, p->tol, 0, tau64, check_every, use_graph,
-                                s.refresh64, &it64)))
-        return rc;
+    // FP64: Rayleigh-Ritz on X with the FP64 matrices (the certification), then iterate if needed. In the
+    // mixed path this phase is timed as one stage, so the per-stage figures describe the FP32 iterations
+    // (its passes after every object has converged launch kernels that return at once)
+    {
+        StageMark phase(ctx, s.st, FF_STAGE_FP64_PHASE);
+        TimingMute mute(ctx, p->precision == 1);
+        if ((rc = reset_status(s, 0))) return rc;
+        if ((rc = init_block<double>(s, S64, HS64, MS64, tau64))) return rc;
+        const int left = std::max(0, p->max_iter - it32);
+        if ((rc = run_phase<double>(s, S64, HS64, MS64, left + 1, p->tol, 0, tau64, check_every, use_graph,
+                                    s.refresh64, &it64)))
+            return rc;
+    }
     if (it64 > 0) it64 -= 0;
 
     // outputs: eigenvalues, residuals, sign-fixed vectors

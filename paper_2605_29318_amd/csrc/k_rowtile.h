@@ -112,10 +112,13 @@ struct ChebStepQ {
     uint16_t *dz_out = nullptr;
     int64_t ldw = 0;
 };
-int cheb_step_tq(ff_ctx *ctx, hipStream_t st, const RTQView &v, int m, const uint16_t *DZ, const int *row_obj,
-                 const int *status, const ChebStepQ &cs);
+// sub selects a launch shape (waves per block, K-blocks in flight), 0 .. kTqSubs - 1
+constexpr int kTqSubs = 5;
+int cheb_step_tq(ff_ctx *ctx, hipStream_t st, const RTQView &v, int sub, int m, const uint16_t *DZ,
+                 const int *row_obj, const int *status, const ChebStepQ &cs);
 // HY = H Y (Y binary16 [rows][m], HY FP32 with leading dimension ldo)
-int spmm_h_tq(ff_ctx *ctx, hipStream_t st, const RTQView &v, int m, const uint16_t *Y, float *HY, int64_t ldo);
+int spmm_h_tq(ff_ctx *ctx, hipStream_t st, const RTQView &v, int sub, int m, const uint16_t *Y, float *HY,
+              int64_t ldo);
 
 // H-only FP32 copy in tiles of sixteen rows, for the MFMA form of the
 // preconditioner's products: vh[entry][16].

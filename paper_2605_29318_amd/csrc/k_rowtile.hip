@@ -33,6 +33,9 @@ __device__ inline int xcd_remap(int b, int nb) {
 // building the tile copy: one thread per tile merges its (sorted) rows
 // ---------------------------------------------------------------------------
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
 template <int R> struct Merge {
     int64_t p[R], e[R];
     int32_t h[R];
@@ -57,10 +60,7 @@ __device__ inline int32_t merge_head(const Merge<R> &s) {
 }
 
 template <int R>
-__global__ void rt_count_kernel(int64_t nrows, int64_t ntiles, const int64_t *row_ptr, const int32_t *col,
-                                int64_t *cnt) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= ntiles) return;
+__device__ int64_t merge_count(int64_t nrows, int64_t t, const int64_t *row_ptr, const int32_t *col) {
     Merge<R> s;
     merge_init(s, nrows, t * R, row_ptr, col);
     int64_t k = 0;
@@ -73,16 +73,13 @@ __global__ void rt_count_kernel(int64_t nrows, int64_t ntiles, const int64_t *ro
                 s.h[i] = s.p[i] < s.e[i] ? col[s.p[i]] : INT_MAX;
             }
     }
-    cnt[t] = k;
+    return k;
 }
 
-// FP32 copy in tiles of R rows: vh[entry][R] (H) and, when vm is given, vm[entry][R] (M)
+// FP32 copy of tile t in tiles of R rows: vh[entry][R] (H) and, when vm is given, vm[entry][R] (M)
 template <int R>
-__global__ void rt_fill_h_kernel(int64_t nrows, int64_t ntiles, const int64_t *row_ptr, const int32_t *col,
-                                 const double *H, const double *M, const int64_t *tptr, int32_t *tcol, float *vh,
-                                 float *vm) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= ntiles) return;
+__device__ void merge_fill(int64_t nrows, int64_t t, const int64_t *row_ptr, const int32_t *col, const double *H,
+                           const double *M, const int64_t *tptr, int32_t *tcol, float *vh, float *vm) {
     Merge<R> s;
     merge_init(s, nrows, t * R, row_ptr, col);
     int64_t o = tptr[t];
@@ -98,6 +95,171 @@ __global__ void rt_fill_h_kernel(int64_t nrows, int64_t ntiles, const int64_t *r
                 ++s.p[i];
                 s.h[i] = s.p[i] < s.e[i] ? col[s.p[i]] : INT_MAX;
             }
+        }
+    }
+}
+
+template <int R>
+__global__ void rt_count_kernel(int64_t nrows, int64_t ntiles, const int64_t *row_ptr, const int32_t *col,
+                                int64_t *cnt) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntiles) return;
+    cnt[t] = merge_count<R>(nrows, t, row_ptr, col);
+}
+
+// ---------------------------------------------------------------------------
+// building the eight- and sixteen-row copies: one workgroup per tile
+// ---------------------------------------------------------------------------
+//
+// A tile's union holds each column of its rows once. The entry (row r, column c) represents c
+// in the union when no earlier row of the tile holds c. With G the exclusive prefix count of
+// representatives over the tile's entries in row order, c's union slot is the number of
+// representatives with a smaller column: the sum over rows q of G[start q + lower_bound(q, c)]
+// - G[start q]. Each representative writes its slot, the column and the R values (zero where a
+// row lacks it), so every slot is written once and the copy equals the serial merge's. The
+// column lists sit in LDS (cap entries per tile); a larger tile takes the serial merge.
+constexpr int kUnionCap = 6144;                   // entries per tile held in LDS (49 KB with G)
+constexpr int kUnionThreads = 256;
+
+template <int R>
+__global__ void tile_entries_max_kernel(int64_t nrows, int64_t ntiles, const int64_t *row_ptr, int *mx) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int v = 0;
+    if (t < ntiles) {
+        const int64_t r1 = (t + 1) * R < nrows ? (t + 1) * R : nrows;
+        const int64_t e = row_ptr[r1] - row_ptr[t * R];
+        v = e < INT_MAX ? (int)e : INT_MAX;
+    }
+    for (int d = 32; d >= 1; d >>= 1) v = max(v, __shfl_xor(v, d, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(mx, v);
+}
+
+__device__ inline int lower_bound_lds(const int32_t *a, int len, int32_t c) {
+    int lo = 0, hi = len;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a[mid] < c)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+template <int R, bool kFill>
+__global__ void __launch_bounds__(kUnionThreads) tile_union_kernel(int64_t nrows, int64_t ntiles,
+                                                                   const int64_t *row_ptr, const int32_t *col,
+                                                                   int cap, int64_t *cnt, const double *H,
+                                                                   const double *M, const int64_t *tptr,
+                                                                   int32_t *tcol, float *vh, float *vm) {
+    extern __shared__ __align__(16) int32_t lds[];
+    int32_t *lcol = lds;                           // [cap] the rows' columns, row after row
+    int32_t *G = lds + cap;                        // [cap + 1] representative flags, then their prefix
+    __shared__ int rs[R + 1];                      // row starts in lcol
+    __shared__ int64_t gs[R];                      // row starts in the CSR
+    __shared__ int wsum[kUnionThreads / 64];
+    const int64_t t = blockIdx.x;
+    if (t >= ntiles) return;
+    const int tid = threadIdx.x;
+    const int64_t r0 = t * R;
+    if (tid == 0) {
+        int acc = 0;
+        for (int r = 0; r < R; ++r) {
+            const bool in = r0 + r < nrows;
+            const int64_t b = in ? row_ptr[r0 + r] : 0, e = in ? row_ptr[r0 + r + 1] : 0;
+            gs[r] = b;
+            rs[r] = acc;
+            acc += (int)(e - b);
+        }
+        rs[R] = acc;
+    }
+    __syncthreads();
+    const int E = rs[R];
+    if (E > cap) {
+        if (tid == 0) {
+            if (kFill)
+                merge_fill<R>(nrows, t, row_ptr, col, H, M, tptr, tcol, vh, vm);
+            else
+                cnt[t] = merge_count<R>(nrows, t, row_ptr, col);
+        }
+        return;
+    }
+    auto row_of = [&](int x) {
+        int r = 0;
+        while (r + 1 < R && rs[r + 1] <= x) ++r;
+        return r;
+    };
+    for (int x = tid; x < E; x += kUnionThreads) {
+        const int r = row_of(x);
+        lcol[x] = col[gs[r] + (x - rs[r])];
+    }
+    __syncthreads();
+    // representatives over a contiguous chunk per thread, then a workgroup-wide exclusive scan
+    const int per = (E + kUnionThreads - 1) / kUnionThreads;
+    const int x0 = min(E, tid * per), x1 = min(E, x0 + per);
+    int local = 0;
+    for (int x = x0, r = x0 < E ? row_of(x0) : 0; x < x1; ++x) {
+        while (x >= rs[r + 1]) ++r;
+        const int32_t c = lcol[x];
+        bool rep = true;
+        for (int q = 0; q < r && rep; ++q) {
+            const int len = rs[q + 1] - rs[q];
+            const int lb = lower_bound_lds(lcol + rs[q], len, c);
+            rep = !(lb < len && lcol[rs[q] + lb] == c);
+        }
+        G[x] = rep ? 1 : 0;
+        local += rep ? 1 : 0;
+    }
+    const int lane = tid & 63, wv = tid >> 6;
+    int incl = local;
+    for (int d = 1; d < 64; d <<= 1) {
+        const int u = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += u;
+    }
+    if (lane == 63) wsum[wv] = incl;
+    __syncthreads();
+    int run = incl - local, U = 0;
+    for (int w = 0; w < kUnionThreads / 64; ++w) {
+        if (w < wv) run += wsum[w];
+        U += wsum[w];
+    }
+    for (int x = x0; x < x1; ++x) {
+        const int f = G[x];
+        G[x] = run;
+        run += f;
+    }
+    if (tid == 0) G[E] = U;
+    __syncthreads();
+    if (!kFill) {
+        if (tid == 0) cnt[t] = U;
+        return;
+    }
+    const int64_t o = tptr[t];
+    for (int x = tid; x < E; x += kUnionThreads) {
+        if (G[x + 1] == G[x]) continue;            // not a representative
+        const int r = row_of(x);
+        const int32_t c = lcol[x];
+        int rank = G[x] - G[rs[r]];
+        float v[R], w[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const int len = rs[q + 1] - rs[q];
+            int lb;
+            if (q == r) {
+                lb = x - rs[r];
+            } else {
+                lb = lower_bound_lds(lcol + rs[q], len, c);
+                rank += G[rs[q] + lb] - G[rs[q]];
+            }
+            const bool hit = lb < len && lcol[rs[q] + lb] == c;
+            v[q] = hit ? (float)H[gs[q] + lb] : 0.f;
+            w[q] = hit && vm ? (float)M[gs[q] + lb] : 0.f;
+        }
+        tcol[o + rank] = c;
+#pragma unroll
+        for (int q = 0; q < R; q += 4) {
+            *(f32x4 *)(vh + (o + rank) * R + q) = f32x4{v[q], v[q + 1], v[q + 2], v[q + 3]};
+            if (vm) *(f32x4 *)(vm + (o + rank) * R + q) = f32x4{w[q], w[q + 1], w[q + 2], w[q + 3]};
         }
     }
 }
@@ -169,8 +331,6 @@ __device__ inline void acc_store(float *p, const Acc4<A> &a) {
 }
 __device__ inline void acc_store(double *p, const Acc4<double> &a) { *(double2 *)p = make_double2(a.v[0], a.v[1]); }
 
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
 // Chunk of 64 union entries: column and the eight values of entry l in lane l.
 // With kHM false only the H values are loaded and staged (stride 4 in LDS).
@@ -618,6 +778,46 @@ static int build_ptr(ff_ctx *ctx, hipStream_t st, int64_t n, const int64_t *row_
     return FF_OK;
 }
 
+// the eight- and sixteen-row copies: the LDS cap of the workgroup-per-tile kernels (the largest
+// tile's entry count, at most kUnionCap), tile pointers and the number of union entries (host)
+template <int R>
+static int build_ptr_union(ff_ctx *ctx, hipStream_t st, int64_t n, const int64_t *row_ptr, const int32_t *col,
+                           int64_t *cnt, int64_t *tptr, int64_t ntiles, int64_t *entries, int *cap) {
+    int *mx0 = (int *)ws_get(ctx, WS_RT8_MAX, 256);
+    int64_t *h = (int64_t *)pinned_get(ctx, 64);
+    if (!mx0 || !h) return FF_ERR_OOM;
+    int *mx = mx0 + 1;                             // word 0 serves the binary16 copies' |H| maximum
+    FF_HIP(ctx, hipMemsetAsync(mx, 0, sizeof(int), st));
+    hipLaunchKernelGGL(tile_entries_max_kernel<R>, dim3(grid_for(ntiles, 256)), dim3(256), 0, st, n, ntiles, row_ptr,
+                       mx);
+    FF_CHECK_LAUNCH(ctx);
+    FF_HIP(ctx, hipMemcpyAsync(h, mx, sizeof(int), hipMemcpyDeviceToHost, st));
+    FF_HIP(ctx, hipStreamSynchronize(st));
+    *cap = std::min(*(int *)h, kUnionCap);
+    hipLaunchKernelGGL((tile_union_kernel<R, false>), dim3(ntiles), dim3(kUnionThreads),
+                       (size_t)(2 * *cap + 1) * sizeof(int32_t), st, n, ntiles, row_ptr, col, *cap, cnt,
+                       (const double *)nullptr, (const double *)nullptr, (const int64_t *)nullptr, (int32_t *)nullptr,
+                       (float *)nullptr, (float *)nullptr);
+    FF_CHECK_LAUNCH(ctx);
+    int rc = scan_exclusive_i64(ctx, cnt, tptr, ntiles);
+    if (rc) return rc;
+    FF_HIP(ctx, hipMemcpyAsync(h, tptr + ntiles, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    FF_HIP(ctx, hipStreamSynchronize(st));
+    *entries = h[0];
+    return FF_OK;
+}
+
+template <int R>
+static int fill_union(ff_ctx *ctx, hipStream_t st, int64_t n, int64_t ntiles, const int64_t *row_ptr,
+                      const int32_t *col, int cap, const double *H, const int64_t *tptr, int32_t *tcol, float *vh,
+                      const double *M = nullptr, float *vm = nullptr) {
+    hipLaunchKernelGGL((tile_union_kernel<R, true>), dim3(ntiles), dim3(kUnionThreads),
+                       (size_t)(2 * cap + 1) * sizeof(int32_t), st, n, ntiles, row_ptr, col, cap, (int64_t *)nullptr,
+                       H, M, tptr, tcol, vh, vm);
+    FF_CHECK_LAUNCH(ctx);
+    return FF_OK;
+}
+
 static int fill(ff_ctx *ctx, hipStream_t st, int64_t n, int64_t ntiles, const int64_t *row_ptr, const int32_t *col,
                 const double *H, const double *M, const int64_t *tptr, int64_t entries, int32_t *tcol, float *v32,
                 double *v64) {
@@ -892,15 +1092,6 @@ int cheb_step_t8(ff_ctx *ctx, hipStream_t st, const RT8View &v, int sub, int m, 
     return launch_t8<true>(ctx, st, v, sub, m, DZ, ld, nullptr, ld, row_obj, status, cs);
 }
 
-static int fill_t8(ff_ctx *ctx, hipStream_t st, int64_t n, int64_t ntiles, const int64_t *row_ptr,
-                   const int32_t *col, const double *H, const int64_t *tptr, int32_t *tcol, float *vh,
-                   const double *M = nullptr, float *vm = nullptr) {
-    hipLaunchKernelGGL(rt_fill_h_kernel<kTile8>, dim3(grid_for(ntiles, 256)), dim3(256), 0, st, n, ntiles, row_ptr,
-                       col, H, M, tptr, tcol, vh, vm);
-    FF_CHECK_LAUNCH(ctx);
-    return FF_OK;
-}
-
 int build_t8_ws(ff_ctx *ctx, hipStream_t st, int64_t n, const int64_t *row_ptr, const int32_t *col, const double *H,
                 RT8View *out, const double *M) {
     FF_REQUIRE(ctx, n > 0 && row_ptr && col && H && out, "bad arguments");
@@ -909,14 +1100,15 @@ int build_t8_ws(ff_ctx *ctx, hipStream_t st, int64_t n, const int64_t *row_ptr, 
     int64_t *tptr = (int64_t *)ws_get(ctx, WS_RT8_PTR, (size_t)(ntiles + 1) * sizeof(int64_t));
     if (!cnt || !tptr) return FF_ERR_OOM;
     int64_t entries = 0;
-    int rc = build_ptr<kTile8>(ctx, st, n, row_ptr, col, cnt, tptr, ntiles, &entries);
+    int cap = 0;
+    int rc = build_ptr_union<kTile8>(ctx, st, n, row_ptr, col, cnt, tptr, ntiles, &entries, &cap);
     if (rc) return rc;
     const size_t ne = (size_t)std::max<int64_t>(entries, 1);
     int32_t *tcol = (int32_t *)ws_get(ctx, WS_RT8_COL, ne * sizeof(int32_t));
     float *vh = (float *)ws_get(ctx, WS_RT8_VAL, ne * kTile8 * sizeof(float));
     float *vm = M ? (float *)ws_get(ctx, WS_RT8_VALM, ne * kTile8 * sizeof(float)) : nullptr;
     if (!tcol || !vh || (M && !vm)) return FF_ERR_OOM;
-    if ((rc = fill_t8(ctx, st, n, ntiles, row_ptr, col, H, tptr, tcol, vh, M, vm))) return rc;
+    if ((rc = fill_union<kTile8>(ctx, st, n, ntiles, row_ptr, col, cap, H, tptr, tcol, vh, M, vm))) return rc;
     out->n = n;
     out->ntiles = ntiles;
     out->entries = entries;
@@ -1093,7 +1285,7 @@ int build_tq(ff_ctx *ctx, hipStream_t st, const RT8View &v8, RTQView *out) {
 
 bool tq_ok(int m) { return m == 32 || m == 64; }
 
-template <int kMB, bool kEpi, int kWaves, int kOcc>
+template <int kMB, bool kEpi, int kWaves, int kOcc, int kD>
 __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(kOcc, 8)))
 spmm_tq_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int32_t *tcol, const int64_t *kptr,
                const _Float16 *vq, float vscale, const _Float16 *Y, float *HY, int64_t ldo, const int *row_obj,
@@ -1137,37 +1329,48 @@ spmm_tq_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int32_t
 #pragma unroll
     for (int cb = 0; cb < kMB; ++cb) acc[cb] = f32x4{0.f, 0.f, 0.f, 0.f};
     if (nk > 0) {
-        f32x4 yc[kLoads];
+        // a ring of kD K-blocks: kD - 1 in flight while one is multiplied. The passes of a partial
+        // last round reload the tile's last block and multiply a zero B operand.
+        f32x4 y[kD][kLoads];
+        f16x4 b[kD];
         uint32_t jn[kLoads];
 #pragma unroll
-        for (int i = 0; i < kLoads; ++i) yc[i] = load_y(col_of(0, i));
-        f16x4 bc = load_v(0);
+        for (int d = 0; d < kD - 1; ++d) {
+            const int kb = d < nk ? d : nk - 1;
 #pragma unroll
-        for (int i = 0; i < kLoads; ++i) jn[i] = col_of(nk > 1 ? 1 : 0, i);
-        for (int kb = 0; kb < nk; ++kb) {
-            // K-block kb + 1's rows (their columns are loaded), kb + 2's columns; the last pass reloads
-            // its own block, unused
-            const int kb1 = kb + 1 < nk ? kb + 1 : kb, kb2 = kb + 2 < nk ? kb + 2 : kb1;
-            f32x4 yn[kLoads];
+            for (int i = 0; i < kLoads; ++i) y[d][i] = load_y(col_of(kb, i));
+            b[d] = load_v(kb);
+        }
 #pragma unroll
-            for (int i = 0; i < kLoads; ++i) yn[i] = load_y(jn[i]);
-            const f16x4 bn = load_v(kb1);
+        for (int i = 0; i < kLoads; ++i) jn[i] = col_of(kD - 1 < nk ? kD - 1 : nk - 1, i);
+        for (int kb0 = 0; kb0 < nk; kb0 += kD) {
 #pragma unroll
-            for (int i = 0; i < kLoads; ++i) jn[i] = col_of(kb2, i);
-            __builtin_amdgcn_wave_barrier();
+            for (int d = 0; d < kD; ++d) {
+                const int kb = kb0 + d;
+                // block kb + kD - 1's rows (their columns are loaded), then block kb + kD's columns
+                const int si = (d + kD - 1) % kD;
+                const int kbi = kb + kD - 1 < nk ? kb + kD - 1 : nk - 1;
 #pragma unroll
-            for (int i = 0; i < kLoads; ++i) *(f32x4 *)(sy + (slot + kRowsPer * i) * kStride + piece * 16) = yc[i];
-            __builtin_amdgcn_wave_barrier();
+                for (int i = 0; i < kLoads; ++i) y[si][i] = load_y(jn[i]);
+                b[si] = load_v(kbi);
+                const int kbn = kb + kD < nk ? kb + kD : nk - 1;
 #pragma unroll
-            for (int cb = 0; cb < kMB; ++cb) {
-                f16x4 a;
+                for (int i = 0; i < kLoads; ++i) jn[i] = col_of(kbn, i);
+                __builtin_amdgcn_wave_barrier();
 #pragma unroll
-                for (int q = 0; q < 4; ++q) a[q] = *(const _Float16 *)(sy + (4 * quad + q) * kStride + (16 * cb + rr) * 2);
-                acc[cb] = __builtin_amdgcn_mfma_f32_16x16x16f16(a, bc, acc[cb], 0, 0, 0);
+                for (int i = 0; i < kLoads; ++i)
+                    *(f32x4 *)(sy + (slot + kRowsPer * i) * kStride + piece * 16) = y[d][i];
+                __builtin_amdgcn_wave_barrier();
+                const f16x4 bv = kb < nk ? b[d] : f16x4{0, 0, 0, 0};
+#pragma unroll
+                for (int cb = 0; cb < kMB; ++cb) {
+                    f16x4 a;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        a[q] = *(const _Float16 *)(sy + (4 * quad + q) * kStride + (16 * cb + rr) * 2);
+                    acc[cb] = __builtin_amdgcn_mfma_f32_16x16x16f16(a, bv, acc[cb], 0, 0, 0);
+                }
             }
-#pragma unroll
-            for (int i = 0; i < kLoads; ++i) yc[i] = yn[i];
-            bc = bn;
         }
     }
     if (!mine) return;
@@ -1206,32 +1409,49 @@ spmm_tq_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int32_t
 }
 
 template <bool kEpi>
-static int launch_tq(ff_ctx *ctx, hipStream_t st, const RTQView &v, int m, const uint16_t *Y, float *HY,
+static int launch_tq(ff_ctx *ctx, hipStream_t st, const RTQView &v, int sub, int m, const uint16_t *Y, float *HY,
                      int64_t ldo, const int *row_obj, const int *status, const ChebStepQ &cs) {
     FF_REQUIRE(ctx, v.vq != nullptr && tq_ok(m), "matrix-core Chebyshev step: no K-blocked copy or m = %d", m);
+    FF_REQUIRE(ctx, sub >= 0 && sub < kTqSubs, "launch shape %d out of range", sub);
     FF_REQUIRE(ctx, v.n * (int64_t)m < ((int64_t)1 << 32), "block of %lld rows x %d too large for 32-bit offsets",
                (long long)v.n, m);
     const _Float16 *vq = (const _Float16 *)v.vq, *y = (const _Float16 *)Y;
-#define FF_TQ(MB, W, O)                                                                                        \
-    hipLaunchKernelGGL((spmm_tq_kernel<MB, kEpi, W, O>), dim3(grid_for(v.ntiles, W)), dim3(64 * W), 0, st, v.n, \
+    // (waves per block, occupancy floor, K-blocks in the ring); product alone at 1M particles, m = 32 / 64:
+    // 0.607 / 0.888, 0.610 / 0.887, 0.656 / 0.962, 0.631 / 0.889, 0.612 / 0.892 ms. Eight consecutive tiles
+    // per workgroup share most gathered rows in the CU's cache.
+#define FF_TQ(MB, W, O, D)                                                                                        \
+    hipLaunchKernelGGL((spmm_tq_kernel<MB, kEpi, W, O, D>), dim3(grid_for(v.ntiles, W)), dim3(64 * W), 0, st, v.n, \
                        v.ntiles, v.tptr, v.tcol, v.kptr, vq, v.hscale, y, HY, ldo, row_obj, status, cs)
-    if (m == 32) FF_TQ(2, 4, 4);
-    else FF_TQ(4, 4, 4);
+#define FF_TQ_SHAPES(MB)                   \
+    switch (sub) {                         \
+        case 1: FF_TQ(MB, 8, 4, 3); break; \
+        case 2: FF_TQ(MB, 4, 4, 2); break; \
+        case 3: FF_TQ(MB, 4, 4, 3); break; \
+        case 4: FF_TQ(MB, 16, 4, 2); break; \
+        default: FF_TQ(MB, 8, 4, 2); break; \
+    }
+    if (m == 32) {
+        FF_TQ_SHAPES(2)
+    } else {
+        FF_TQ_SHAPES(4)
+    }
+#undef FF_TQ_SHAPES
 #undef FF_TQ
     FF_CHECK_LAUNCH(ctx);
     return FF_OK;
 }
 
-int cheb_step_tq(ff_ctx *ctx, hipStream_t st, const RTQView &v, int m, const uint16_t *DZ, const int *row_obj,
-                 const int *status, const ChebStepQ &cs) {
+int cheb_step_tq(ff_ctx *ctx, hipStream_t st, const RTQView &v, int sub, int m, const uint16_t *DZ,
+                 const int *row_obj, const int *status, const ChebStepQ &cs) {
     FF_REQUIRE(ctx, DZ && row_obj && cs.R && cs.W && cs.dz_out && cs.dinv && cs.coef && cs.ldw % 4 == 0,
                "matrix-core Chebyshev step: bad arguments");
-    return launch_tq<true>(ctx, st, v, m, DZ, nullptr, 0, row_obj, status, cs);
+    return launch_tq<true>(ctx, st, v, sub, m, DZ, nullptr, 0, row_obj, status, cs);
 }
 
-int spmm_h_tq(ff_ctx *ctx, hipStream_t st, const RTQView &v, int m, const uint16_t *Y, float *HY, int64_t ldo) {
+int spmm_h_tq(ff_ctx *ctx, hipStream_t st, const RTQView &v, int sub, int m, const uint16_t *Y, float *HY,
+              int64_t ldo) {
     FF_REQUIRE(ctx, Y && HY && ldo >= m && ldo % 4 == 0, "matrix-core product: bad arguments");
-    return launch_tq<false>(ctx, st, v, m, Y, HY, ldo, nullptr, nullptr, ChebStepQ{});
+    return launch_tq<false>(ctx, st, v, sub, m, Y, HY, ldo, nullptr, nullptr, ChebStepQ{});
 }
 
 // ---------------------------------------------------------------------------
@@ -1429,14 +1649,6 @@ int cheb_step_t16(ff_ctx *ctx, hipStream_t st, const RT16View &v, int sub, int m
     return launch_t16<true>(ctx, st, v, sub, m, DZ, ld, nullptr, ld, row_obj, status, cs);
 }
 
-static int fill_t16(ff_ctx *ctx, hipStream_t st, int64_t n, int64_t ntiles, const int64_t *row_ptr,
-                    const int32_t *col, const double *H, const int64_t *tptr, int32_t *tcol, float *vh) {
-    hipLaunchKernelGGL(rt_fill_h_kernel<kTile16>, dim3(grid_for(ntiles, 64)), dim3(64), 0, st, n, ntiles, row_ptr,
-                       col, H, (const double *)nullptr, tptr, tcol, vh, (float *)nullptr);
-    FF_CHECK_LAUNCH(ctx);
-    return FF_OK;
-}
-
 int build_t16_ws(ff_ctx *ctx, hipStream_t st, int64_t n, const int64_t *row_ptr, const int32_t *col, const double *H,
                  RT16View *out) {
     FF_REQUIRE(ctx, n > 0 && row_ptr && col && H && out, "bad arguments");
@@ -1445,13 +1657,14 @@ int build_t16_ws(ff_ctx *ctx, hipStream_t st, int64_t n, const int64_t *row_ptr,
     int64_t *tptr = (int64_t *)ws_get(ctx, WS_RT16_PTR, (size_t)(ntiles + 1) * sizeof(int64_t));
     if (!cnt || !tptr) return FF_ERR_OOM;
     int64_t entries = 0;
-    int rc = build_ptr<kTile16>(ctx, st, n, row_ptr, col, cnt, tptr, ntiles, &entries);
+    int cap = 0;
+    int rc = build_ptr_union<kTile16>(ctx, st, n, row_ptr, col, cnt, tptr, ntiles, &entries, &cap);
     if (rc) return rc;
     const size_t ne = (size_t)std::max<int64_t>(entries, 1);
     int32_t *tcol = (int32_t *)ws_get(ctx, WS_RT16_COL, ne * sizeof(int32_t));
     float *vh = (float *)ws_get(ctx, WS_RT16_VAL, ne * kTile16 * sizeof(float));
     if (!tcol || !vh) return FF_ERR_OOM;
-    if ((rc = fill_t16(ctx, st, n, ntiles, row_ptr, col, H, tptr, tcol, vh))) return rc;
+    if ((rc = fill_union<kTile16>(ctx, st, n, ntiles, row_ptr, col, cap, H, tptr, tcol, vh))) return rc;
     out->n = n;
     out->ntiles = ntiles;
     out->entries = entries;
@@ -1640,9 +1853,11 @@ int rowtiles_build(ff_ctx *ctx, int64_t n, const int64_t *row_ptr, const int32_t
         }
         h->mem[0] = tptr8;
         int64_t ent8 = 0;
+        int cap8 = 0;
         if (!rc8)
-            rc8 = R == rt::kTile8 ? rt::build_ptr<rt::kTile8>(ctx, st, n, row_ptr, col, cnt8, tptr8, nt8, &ent8)
-                                  : rt::build_ptr<rt::kTile16>(ctx, st, n, row_ptr, col, cnt8, tptr8, nt8, &ent8);
+            rc8 = R == rt::kTile8
+                      ? rt::build_ptr_union<rt::kTile8>(ctx, st, n, row_ptr, col, cnt8, tptr8, nt8, &ent8, &cap8)
+                      : rt::build_ptr_union<rt::kTile16>(ctx, st, n, row_ptr, col, cnt8, tptr8, nt8, &ent8, &cap8);
         if (cnt8) (void)hipFree(cnt8);
         int32_t *tcol8 = nullptr;
         float *vh = nullptr;
@@ -1657,8 +1872,9 @@ int rowtiles_build(ff_ctx *ctx, int64_t n, const int64_t *row_ptr, const int32_t
             h->mem[2] = vh;
         }
         if (!rc8)
-            rc8 = R == rt::kTile8 ? rt::fill_t8(ctx, st, n, nt8, row_ptr, col, H, tptr8, tcol8, vh)
-                                  : rt::fill_t16(ctx, st, n, nt8, row_ptr, col, H, tptr8, tcol8, vh);
+            rc8 = R == rt::kTile8 ? rt::fill_union<rt::kTile8>(ctx, st, n, nt8, row_ptr, col, cap8, H, tptr8, tcol8, vh)
+                                  : rt::fill_union<rt::kTile16>(ctx, st, n, nt8, row_ptr, col, cap8, H, tptr8, tcol8,
+                                                                vh);
         h->v8.n = h->v16.n = n;
         h->v8.ntiles = h->v16.ntiles = nt8;
         h->v8.entries = h->v16.entries = ent8;
@@ -1768,7 +1984,8 @@ int spmm_rowtiles(ff_ctx *ctx, const ff_rowtiles *rt, int precision, int m, cons
         FF_REQUIRE(ctx, rt::tq_ok(m) && ld_y == m && ld_out >= m && ld_out % 4 == 0,
                    "binary16 products take m in {32, 64}, ld_y == m, ld_out >= m and a multiple of 4");
         FF_HIP(ctx, hipSetDevice(ctx->device));
-        return rt::spmm_h_tq(ctx, ctx->stream, rt->vq, m, (const uint16_t *)Y, (float *)HY, ld_out);
+        FF_REQUIRE(ctx, sub >= 0 && sub < rt::kTqSubs, "launch shape %d out of range", sub);
+        return rt::spmm_h_tq(ctx, ctx->stream, rt->vq, sub, m, (const uint16_t *)Y, (float *)HY, ld_out);
     }
     FF_REQUIRE(ctx, precision == 0 || precision == 1, "precision must be 0, 1 or 2");
     if (rt->hrows) {
