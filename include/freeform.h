@@ -195,7 +195,8 @@ typedef struct {
     int check_every;    /* host convergence check period in iterations (0 = 10) */
     int use_graph;      /* 1 = replay one captured hipGraph per iteration (a call on the null
                            stream runs on a private stream of the context) */
-    int refresh_every;  /* recompute HX, MX explicitly every this many iterations (0 = auto) */
+    int refresh_every;  /* recompute the images of X and P explicitly every this many iterations (0 = auto:
+                           30 in the FP32 phase, 20 in FP64) */
     int precond_degree; /* Chebyshev degree d for precond = 2 (0 = default 12; 2..16); d - 1 products with H per
                            iteration */
     double precond_ratio; /* b / a of the Chebyshev interval [a, b] (0 = default 1000; > 1): q stays

@@ -916,8 +916,8 @@ __device__ inline void rr_gemm(const double *X, const double *Y, int transX, int
 // instructions rather than generic ones)
 template <bool kLds>
 __global__ void __launch_bounds__(kRRThreads) rr_tridiag_kernel(int *obj_status, const int *width, const double *G,
-                                                                int wmax, int m, double tau, double *scratch,
-                                                                int *info) {
+                                                                int wmax, int m, double tau, double pmin,
+                                                                double *scratch, int *info) {
     constexpr bool use_lds = kLds;
     const int o = blockIdx.x;
     if (obj_status[o] != 0) return;
@@ -963,7 +963,10 @@ __global__ void __launch_bounds__(kRRThreads) rr_tridiag_kernel(int *obj_status,
     //    and scales the previous row, which nothing reads any more.
     for (int j = 0; j < w; ++j) {
         const double piv = B[(size_t)j * wmax + j];
-        const bool kj = sc[j] > 0.0 && piv > tau;
+        // a P column (j >= 2m) whose squared M-norm is below pmin is dropped as well: its images are
+        // implicit updates whose absolute rounding error is set by the X terms, so once P has shrunk to
+        // that level the direction is noise to the Rayleigh-Ritz step
+        const bool kj = sc[j] > 0.0 && piv > tau && (j < 2 * m || sc[j] * sc[j] * pmin <= 1.0);
         if (tid == 0) {
             keep[j] = kj;
             dl[j] = kj ? sqrt(piv) : 0.0;
@@ -1941,7 +1944,7 @@ struct Solver {
     UChunk *uch = nullptr;
     GChunk *gch = nullptr;
     int nu = 0, ng = 0;
-    int refresh32 = 30, refresh64 = 0;
+    int refresh32 = 30, refresh64 = 20;
     int total_iters = 0;
     int graph_used = 0;
 };
@@ -1994,14 +1997,15 @@ int stage_spmm(Solver &s, T *S, T *HS, T *MS, int slot) {
 // the four Rayleigh-Ritz stages on every active object (LDS limits set by rr_prepare)
 template <typename CT>
 int launch_rr(ff_ctx *ctx, hipStream_t st, int n_obj, int *status, const int *width, const double *G, int wmax, int m,
-              double tau, double *scratch, double *C, CT *Cw, double *Cp, CT *Cpw, double *theta, int *info) {
+              double tau, double *scratch, double *C, CT *Cw, double *Cp, CT *Cpw, double *theta, int *info,
+              double pmin = 0.0) {
     const int lds = rr_use_lds(wmax), vlds = rr_vec_lds(wmax);
     if (lds)
         hipLaunchKernelGGL(rr_tridiag_kernel<true>, dim3(n_obj), dim3(kRRThreads), rr_shmem_bytes(wmax, 1), st, status,
-                           width, G, wmax, m, tau, scratch, info);
+                           width, G, wmax, m, tau, pmin, scratch, info);
     else
         hipLaunchKernelGGL(rr_tridiag_kernel<false>, dim3(n_obj), dim3(kRRThreads), rr_shmem_bytes(wmax, 0), st,
-                           status, width, G, wmax, m, tau, scratch, info);
+                           status, width, G, wmax, m, tau, pmin, scratch, info);
     hipLaunchKernelGGL(rr_eig_kernel, dim3(m, n_obj), dim3(64), 0, st, status, wmax, m, scratch);
     if (vlds)
         hipLaunchKernelGGL(rr_vec_kernel<true>, dim3(m, n_obj), dim3(64), rr_vec_shmem_bytes(wmax, 1), st, status,
@@ -2046,8 +2050,10 @@ int stage_gram_rr(Solver &s, T *S, T *HS, T *MS, double tau) {
     FF_CHECK_LAUNCH(s.ctx);
     mark.end();
     StageMark rr_mark(s.ctx, s.st, FF_STAGE_RR);
+    // P columns below an M-norm of 1e-6 (FP32) or 1e-12 (FP64) leave the basis
     return launch_rr<typename Prec<T>::CT>(s.ctx, s.st, s.n_obj, s.status, s.width, s.G, s.wmax, s.m, tau, s.rrscr,
-                                           s.C, cw_of<T>(s), s.Cp, cpw_of<T>(s), s.theta, s.info);
+                                           s.C, cw_of<T>(s), s.Cp, cpw_of<T>(s), s.theta, s.info,
+                                           sizeof(T) == 4 ? 1e-12 : 1e-24);
 }
 
 template <typename T>
@@ -2289,7 +2295,7 @@ int body(Solver &s, T *S, T *HS, T *MS, double tol, int stall, double tau) {
 // Iterate until every object has left the active state or max_iters is spent.
 template <typename T>
 int run_phase(Solver &s, T *S, T *HS, T *MS, int max_iters, double tol, int stall, double tau, int check_every,
-              int use_graph, int refresh, int *done_iters) {
+              int use_graph, int refresh, int *done_iters, int first_check = 0) {
     int it = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -2316,7 +2322,7 @@ int run_phase(Solver &s, T *S, T *HS, T *MS, int max_iters, double tol, int stal
         }
     }
     while (it < max_iters) {
-        const int steps = std::min(check_every, max_iters - it);
+        const int steps = std::min(it == 0 && first_check > 0 ? first_check : check_every, max_iters - it);
         for (int j = 0; j < steps; ++j) {
             if (refresh > 0 && it > 0 && it % refresh == 0) {
                 // recompute the images of X and P so the recurrences do not drift
@@ -2578,6 +2584,8 @@ int solve(ff_ctx *ctx, int n_obj, const int64_t *obj_off, const int64_t *row_ptr
             FF_REQUIRE(ctx, !q || rt::tq_ok(s.m), "binary16 iterate needs block width 32 or 64 (m = %d)", s.m);
             if (!rc && q) {
                 rc = rt::build_tq(ctx, s.st, s.rt8, &s.rtq);
+                // the power steps of the interval estimate (eight columns) read the binary16 copy too
+                if (!rc) rc = rt::build_t8_half(ctx, s.st, &s.rt8);
                 s.wpart = (float *)ws_get(ctx, WS_CHEBQ, ((size_t)s.ng + s.n_obj) * s.m * sizeof(float));
                 if (!rc && !s.wpart) rc = FF_ERR_OOM;
                 s.cmax = s.wpart + (size_t)s.ng * s.m;
@@ -2647,8 +2655,9 @@ int solve(ff_ctx *ctx, int n_obj, const int64_t *obj_off, const int64_t *row_ptr
         if ((rc = reset_status(s, 0))) return rc;
         if ((rc = init_block<double>(s, S64, HS64, MS64, tau64))) return rc;
         const int left = std::max(0, p->max_iter - it32);
+        // after the FP32 phase the first FP64 pass normally certifies every pair: check right after it
         if ((rc = run_phase<double>(s, S64, HS64, MS64, left + 1, p->tol, 0, tau64, check_every, use_graph,
-                                    s.refresh64, &it64)))
+                                    s.refresh64, &it64, p->precision == 1 ? 1 : 0)))
             return rc;
     }
     if (it64 > 0) it64 -= 0;
