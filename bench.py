@@ -65,13 +65,12 @@ def kernel_source_hash():
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
-def cheb_step_bytes(nnz, n, m, value_bytes=2):
-    """Algorithmic HBM bytes of one Chebyshev step launch (FP32 blocks, m columns),
-    independent of the tiling: the H value (binary16 by default, value_bytes) and int32
-    column of every nonzero, the row pointers, D^-1 and the row's object index, the
-    gathered block DZ read once, R read and written, the next DZ written, W read and
-    written."""
-    return nnz * (value_bytes + 4) + 8 * (n + 1) + n * (4 + 4) + n * m * 4 * (1 + 2 + 1 + 2)
+def cheb_step_bytes(nnz, n, m, value_bytes=2, iter_bytes=2):
+    """Algorithmic HBM bytes of one Chebyshev step launch (m columns), independent of the
+    tiling: the H value (binary16, value_bytes) and int32 column of every nonzero, the row
+    pointers, D^-1 and the row's object index, the iterate DZ (binary16, iter_bytes) read
+    once and the next one written, R (FP32) read and written, W (FP32) read and written."""
+    return nnz * (value_bytes + 4) + 8 * (n + 1) + n * (4 + 4) + n * m * (2 * iter_bytes + 4 * 4)
 
 
 def spmm_hm_bytes(nnz, n, m):
@@ -97,6 +96,25 @@ def measured_traffic():
         return float(vals["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def stream_copy_gbps():
+    """Achievable HBM bandwidth on this device: a 1 GiB device-to-device copy (reads and writes
+    1 GiB), mean of 10 after 3 untimed, timed with events on torch's stream."""
+    import torch
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 10
+    del src, dst
+    return 2 * (1 << 30) / (ms * 1e-3) / 1e9
 
 
 def counters_run(args):
@@ -163,6 +181,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--graph", action="store_true")
+    ap.add_argument("--no-k64", action="store_true", help="skip the k = 64 solve of the large-object configuration")
     ap.add_argument("--counters", action="store_true",
                     help="run a short solve (--steps iterations) and a 1 GiB calibration kernel (for counter passes)")
     args = ap.parse_args()
@@ -222,6 +241,18 @@ def main():
                     mixed_vs_fp64_eig_rel_diff=float(rel.max()))
         log(f"[bench] fp64 step: {r64['total']:.3f} s, iters {r64['info']['iters_fp64']}")
 
+    k64 = None
+    if not args.no_k64 and args.k == 32:
+        # the large-object configuration asks for 64 modes of the same object (mixed path, start seed 0)
+        r = run_step(ff, ctx, dev_in, c.n, c.h, 64, 1, args.tol, args.max_iter, args.graph, seed=0)
+        k64 = dict(seconds=round(r["total"], 3), build_s=round(r["build"], 4), solve_s=round(r["solve"], 4),
+                   iters=r["info"]["iters_fp32"] + r["info"]["iters_fp64"], max_resid=float(r["res"].max()),
+                   converged=bool(r["info"]["converged"]))
+        log(f"[bench] k = 64 step: {r['total']:.3f} s, iters {r['info']['iters_fp32']}+{r['info']['iters_fp64']}")
+        del r
+    copy_gbps = stream_copy_gbps()
+    log(f"[bench] stream copy (1 GiB, device to device): {copy_gbps:.0f} GB/s")
+
     m = args.k if args.k % 8 == 0 else ((args.k + 7) // 8) * 8
     cheb_ms, cheb_n = stages["precond_product"]
     spmm_ms, spmm_n = stages["spmm"]
@@ -260,7 +291,7 @@ def main():
         "config": {"workload": "ellipsoids1m_hetero", "particles": c.n, "k": args.k, "tol": args.tol,
                    "nnz": nnz, "nnz_per_row": round(nnz / c.n, 1), "h": round(c.h, 6),
                    "precond": "chebyshev-jacobi", "precond_degree": PRECOND_DEGREE or 12, "precond_ratio": 1000,
-                   "precond_values": "fp16",
+                   "precond_values": "fp16 H and iterate (matrix cores)",
                    "graph": bool(args.graph)},
         "build_s": round(last["build"], 4),
         "solve_s": round(last["solve"], 4),
@@ -271,14 +302,16 @@ def main():
         "converged": bool(info["converged"]),
         "fp64": fp64,
         "speedup_vs_fp64": (round(fp64["seconds"] / (ms_per_step / 1e3), 3) if fp64 else None),
+        "k64": k64,
+        "stream_copy_gbps": round(copy_gbps, 1),
         "spmm_gbps": round(spmm_gbps, 1),
         "stages_ms": {k: round(v[0], 2) for k, v in stages.items()},
         "stage_launches": {k: int(v[1]) for k, v in stages.items()},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "spmm_t8_kernel<_Float16, true> (Chebyshev step: H-only product on the eight-row "
-                               "tile copy of H in binary16, FP32 accumulation, fused with the step's vector "
-                               "update, m=%d)" % m,
+                     "kernel": "spmm_tq_kernel<%d, true> (Chebyshev step on the matrix cores: binary16 H in "
+                               "K-blocks of the eight-row tiles times the binary16 iterate, FP32 accumulation on "
+                               "v_mfma_f32_16x16x16_f16, fused with the step's vector update, m=%d)" % (m // 16, m),
                      "bytes_per_launch": cheb_alg, "launch_ms": round(cheb_avg, 4),
                      "share_of_solve": round(cheb_ms / max(stages["total"][0], 1e-9), 3)},
         "spmm_hm": {"achieved": round(spmm_gbps, 1), "unit": "GB/s", "bytes_per_launch": spmm_alg,

@@ -170,6 +170,11 @@ int rkpm_shape(ff_ctx *ctx, int64_t n, const double *xyz_sorted, int64_t q, cons
  *  col, H, M    [nnz_cap] device out, or NULL on the sizing call
  *  hm32         [nnz_cap][2] device out or NULL: FP32 copies (H, M) interleaved
  *  nnz          host out
+ * The sizing call (col NULL) fills row_ptr and nnz and keeps its symbolic
+ * state (transposed lists, row lengths) in the context; the next call on the
+ * context, if it passes the same nbr_off, nbr_id, grid dimensions,
+ * cell_start, row_ptr and sizes (compared by address and value, the arrays
+ * left unmodified in between), reuses that state instead of recomputing it.
  * Errors: FF_ERR_INVALID_ARG (a node with no quadrature point in its support,
  * a row longer than 2048 or a window of more than 16384 candidate nodes),
  * FF_ERR_CAPACITY.

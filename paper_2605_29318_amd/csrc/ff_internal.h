@@ -57,6 +57,12 @@ struct ff_ctx {
     double stage_ms[FF_STAGE_COUNT] = {};
     int64_t stage_launches[FF_STAGE_COUNT] = {};
     int verbose = 0;                 // FF_VERBOSE=1: residual trace on stderr
+    // symbolic state of assemble_HM's sizing call, reused by a matching next call
+    bool asm_valid = false;
+    const void *asm_ptr[4] = {};
+    int64_t asm_size[5] = {};
+    int64_t asm_nnz = 0;
+    int asm_rowmax = 0;
     hipStream_t graph_stream = nullptr;   // private stream for graph capture
 };
 

@@ -435,58 +435,85 @@ extern "C" int assemble_HM(ff_ctx *ctx, int64_t n, int64_t q, const int64_t *nbr
     int64_t total = 0;
     int64_t *host = (int64_t *)pinned_get(ctx, 4096);
     if (!host) return FF_ERR_OOM;
-    FF_HIP(ctx, hipMemcpyAsync(host, nbr_off + q, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    FF_HIP(ctx, hipStreamSynchronize(st));
-    total = host[0];
-
-    // transpose
-    int32_t *cnt = (int32_t *)ws_get(ctx, WS_COUNTS, (size_t)n * sizeof(int32_t));
-    int32_t *cursor = (int32_t *)ws_get(ctx, WS_CURSOR, (size_t)n * sizeof(int32_t));
-    int64_t *nt_off = (int64_t *)ws_get(ctx, WS_NT_OFF, (size_t)(n + 1) * sizeof(int64_t));
-    int2 *nt = (int2 *)ws_get(ctx, WS_NT, (size_t)(total > 0 ? total : 1) * sizeof(int2));
-    int32_t *rowlen = (int32_t *)ws_get(ctx, WS_ROWLEN, (size_t)n * sizeof(int32_t));
-    int *stats = (int *)ws_get(ctx, WS_ASM_FLAG, 64);
-    if (!cnt || !cursor || !nt_off || !nt || !rowlen || !stats) return FF_ERR_OOM;
-    unsigned long long *empty_node = (unsigned long long *)(stats + 4);
-    FF_HIP(ctx, hipMemsetAsync(cnt, 0, (size_t)n * sizeof(int32_t), st));
-    FF_HIP(ctx, hipMemsetAsync(cursor, 0, (size_t)n * sizeof(int32_t), st));
-    FF_HIP(ctx, hipMemsetAsync(stats, 0, 16, st));
-    FF_HIP(ctx, hipMemsetAsync(empty_node, 0xff, 8, st));
-    hipLaunchKernelGGL(nt_count_kernel, dim3(grid_for(total, 256)), dim3(256), 0, st, nbr_id, total, cnt);
-    FF_CHECK_LAUNCH(ctx);
-    int rc = scan_exclusive_i32_to_i64(ctx, cnt, nt_off, n);
-    if (rc) return rc;
-    hipLaunchKernelGGL(nt_fill_kernel, dim3(grid_for(q, 256)), dim3(256), 0, st, nbr_off, nbr_id, q, nt_off, cursor,
-                       nt);
-    FF_CHECK_LAUNCH(ctx);
-    hipLaunchKernelGGL(nt_sort_kernel, dim3(grid_for(n, 4)), dim3(256), 0, st, nt_off, n, nt, empty_node);
-    FF_CHECK_LAUNCH(ctx);
-
     GridI g;
     for (int a = 0; a < 3; ++a) g.d[a] = grid->dims[a];
     g.ncell = grid->n_cells;
-    hipLaunchKernelGGL(sym_kernel, dim3(grid_for(n, 4)), dim3(256), 0, st, n, cell_start, g, nt_off, nt, nbr_off,
-                       nbr_id, rowlen, stats);
-    FF_CHECK_LAUNCH(ctx);
-    rc = scan_exclusive_i32_to_i64(ctx, rowlen, row_ptr, n);
-    if (rc) return rc;
-    FF_HIP(ctx, hipMemcpyAsync(host, row_ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    FF_HIP(ctx, hipMemcpyAsync(host + 1, stats, 16, hipMemcpyDeviceToHost, st));
-    FF_HIP(ctx, hipMemcpyAsync(host + 3, empty_node, 8, hipMemcpyDeviceToHost, st));
-    FF_HIP(ctx, hipStreamSynchronize(st));
-    const int *hs = (const int *)(host + 1);
-    const unsigned long long en = (unsigned long long)host[3];
-    if (en != ~0ull)
-        return set_error(ctx, FF_ERR_INVALID_ARG, "node %llu has no quadrature point in its support", en);
-    FF_REQUIRE(ctx, hs[0] == 0, "a row's candidate window exceeds %d nodes; decrease h", kWinMax);
-    FF_REQUIRE(ctx, hs[1] <= kRowMax, "a row has %d entries (limit %d); decrease h", hs[1], kRowMax);
-    *nnz = host[0];
-    if (!col) return FF_OK;
-    if (nnz_cap < host[0])
-        return set_error(ctx, FF_ERR_CAPACITY, "CSR needs %lld entries, capacity %lld", (long long)host[0],
-                         (long long)nnz_cap);
+    // the sizing call's symbolic state, when this call follows it on the same arrays
+    const void *key_ptr[4] = {nbr_off, nbr_id, cell_start, row_ptr};
+    const int64_t key_size[5] = {n, q, grid->dims[0], grid->dims[1], grid->dims[2]};
+    bool reuse = col != nullptr && ctx->asm_valid;
+    for (int i = 0; i < 4 && reuse; ++i) reuse = ctx->asm_ptr[i] == key_ptr[i];
+    for (int i = 0; i < 5 && reuse; ++i) reuse = ctx->asm_size[i] == key_size[i];
+    ctx->asm_valid = false;
+    int64_t *nt_off = (int64_t *)ws_get(ctx, WS_NT_OFF, (size_t)(n + 1) * sizeof(int64_t));
+    if (!nt_off) return FF_ERR_OOM;
+    int2 *nt = nullptr;
+    int rowmax = 0;
+    if (reuse) {
+        nt = (int2 *)ctx->ws[WS_NT];
+        *nnz = ctx->asm_nnz;
+        rowmax = ctx->asm_rowmax;
+        if (nnz_cap < *nnz)
+            return set_error(ctx, FF_ERR_CAPACITY, "CSR needs %lld entries, capacity %lld", (long long)*nnz,
+                             (long long)nnz_cap);
+    } else {
+        FF_HIP(ctx, hipMemcpyAsync(host, nbr_off + q, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        FF_HIP(ctx, hipStreamSynchronize(st));
+        total = host[0];
 
-    const int rmax = ((hs[1] + 63) / 64) * 64;
+        // transpose
+        int32_t *cnt = (int32_t *)ws_get(ctx, WS_COUNTS, (size_t)n * sizeof(int32_t));
+        int32_t *cursor = (int32_t *)ws_get(ctx, WS_CURSOR, (size_t)n * sizeof(int32_t));
+        nt = (int2 *)ws_get(ctx, WS_NT, (size_t)(total > 0 ? total : 1) * sizeof(int2));
+        int32_t *rowlen = (int32_t *)ws_get(ctx, WS_ROWLEN, (size_t)n * sizeof(int32_t));
+        int *stats = (int *)ws_get(ctx, WS_ASM_FLAG, 64);
+        if (!cnt || !cursor || !nt_off || !nt || !rowlen || !stats) return FF_ERR_OOM;
+        unsigned long long *empty_node = (unsigned long long *)(stats + 4);
+        FF_HIP(ctx, hipMemsetAsync(cnt, 0, (size_t)n * sizeof(int32_t), st));
+        FF_HIP(ctx, hipMemsetAsync(cursor, 0, (size_t)n * sizeof(int32_t), st));
+        FF_HIP(ctx, hipMemsetAsync(stats, 0, 16, st));
+        FF_HIP(ctx, hipMemsetAsync(empty_node, 0xff, 8, st));
+        hipLaunchKernelGGL(nt_count_kernel, dim3(grid_for(total, 256)), dim3(256), 0, st, nbr_id, total, cnt);
+        FF_CHECK_LAUNCH(ctx);
+        int rc = scan_exclusive_i32_to_i64(ctx, cnt, nt_off, n);
+        if (rc) return rc;
+        hipLaunchKernelGGL(nt_fill_kernel, dim3(grid_for(q, 256)), dim3(256), 0, st, nbr_off, nbr_id, q, nt_off, cursor,
+                           nt);
+        FF_CHECK_LAUNCH(ctx);
+        hipLaunchKernelGGL(nt_sort_kernel, dim3(grid_for(n, 4)), dim3(256), 0, st, nt_off, n, nt, empty_node);
+        FF_CHECK_LAUNCH(ctx);
+
+        hipLaunchKernelGGL(sym_kernel, dim3(grid_for(n, 4)), dim3(256), 0, st, n, cell_start, g, nt_off, nt, nbr_off,
+                           nbr_id, rowlen, stats);
+        FF_CHECK_LAUNCH(ctx);
+        rc = scan_exclusive_i32_to_i64(ctx, rowlen, row_ptr, n);
+        if (rc) return rc;
+        FF_HIP(ctx, hipMemcpyAsync(host, row_ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        FF_HIP(ctx, hipMemcpyAsync(host + 1, stats, 16, hipMemcpyDeviceToHost, st));
+        FF_HIP(ctx, hipMemcpyAsync(host + 3, empty_node, 8, hipMemcpyDeviceToHost, st));
+        FF_HIP(ctx, hipStreamSynchronize(st));
+        const int *hs = (const int *)(host + 1);
+        const unsigned long long en = (unsigned long long)host[3];
+        if (en != ~0ull)
+            return set_error(ctx, FF_ERR_INVALID_ARG, "node %llu has no quadrature point in its support", en);
+        FF_REQUIRE(ctx, hs[0] == 0, "a row's candidate window exceeds %d nodes; decrease h", kWinMax);
+        FF_REQUIRE(ctx, hs[1] <= kRowMax, "a row has %d entries (limit %d); decrease h", hs[1], kRowMax);
+        *nnz = host[0];
+        rowmax = hs[1];
+        if (!col) {
+            ctx->asm_valid = true;
+            for (int i = 0; i < 4; ++i) ctx->asm_ptr[i] = key_ptr[i];
+            for (int i = 0; i < 5; ++i) ctx->asm_size[i] = key_size[i];
+            ctx->asm_nnz = host[0];
+            ctx->asm_rowmax = rowmax;
+            return FF_OK;
+        }
+        if (nnz_cap < host[0])
+            return set_error(ctx, FF_ERR_CAPACITY, "CSR needs %lld entries, capacity %lld", (long long)host[0],
+                             (long long)nnz_cap);
+    }
+
+    const int rmax = ((rowmax + 63) / 64) * 64;
     const int per_wave = (int)(((size_t)2 * rmax * sizeof(double) + sizeof(Win) + kWinWords * 8 + 255) & ~255);
     int waves = 4;
     while (waves > 1 && waves * per_wave > 64 * 1024) waves >>= 1;

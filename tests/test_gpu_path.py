@@ -107,6 +107,56 @@ def test_assembly_bitwise_symmetric_and_deterministic(case, ctx, ff):
     assert torch.equal(A.H, B.H) and torch.equal(A.M, B.M) and torch.equal(A.col, B.col)
 
 
+def test_assembly_sizing_state_reuse(oracle, ctx, ff):
+    """The sizing call keeps its symbolic state for the next call on the same arrays; any
+    other call in between (here the sizing of another object) makes the fill call recompute
+    it. Both routes give the oracle's CSR bit for bit."""
+    import ctypes
+    L = ff.lib()
+    objs = [synth.random_cloud(2100, seed=61, hetero=True), synth.cube_lattice()]
+    pre = []
+    for c in objs:
+        nb = ff.build_neighbors(ctx, dev(c.xyz), c.h)
+        phi, dphi, _ = ff.rkpm_shape(ctx, nb.xyz_sorted, nb.nbr_off, nb.nbr_id, c.h)
+        keep = (dev(c.vol), dev(c.lam), dev(c.mu))      # alive while their addresses are in use
+        row_ptr = torch.empty(c.n + 1, dtype=torch.int64, device="cuda")
+        args = (ctx.h, c.n, c.n, ff._p(nb.nbr_off), ff._p(nb.nbr_id), ff._p(phi), ff._p(dphi), ff._p(keep[0]),
+                ff._p(keep[1]), ff._p(keep[2]), None, ff._p(nb.perm), ctypes.byref(nb.grid), ff._p(nb.cell_start),
+                ff._p(row_ptr))
+        pre.append((c, nb, phi, dphi, keep, row_ptr, args))
+    def size(a):
+        nnz = ctypes.c_int64()
+        ctx.check(L.assemble_HM(*a, None, None, None, None, 0, ctypes.byref(nnz)))
+        return nnz.value
+    def fill(a, m):
+        col = torch.empty(m, dtype=torch.int32, device="cuda")
+        H = torch.empty(m, dtype=torch.float64, device="cuda")
+        M = torch.empty(m, dtype=torch.float64, device="cuda")
+        nnz = ctypes.c_int64()
+        ctx.check(L.assemble_HM(*a, ff._p(col), ff._p(H), ff._p(M), None, m, ctypes.byref(nnz)))
+        assert nnz.value == m
+        return col, H, M
+    (c0, _, _, _, _, rp0, a0), (c1, _, _, _, _, rp1, a1) = pre
+    m0 = size(a0)
+    m1 = size(a1)                         # replaces object 0's state
+    fresh = fill(a0, m0)                  # recomputes the symbolic phase
+    assert size(a0) == m0
+    reused = fill(a0, m0)                 # reuses it
+    P = oracle.pipeline(c0)
+    assert np.array_equal(host(rp0), P.row_ptr)
+    for col, H, M in (fresh, reused):
+        assert np.array_equal(host(col), P.col)
+        assert np.abs(host(H) - P.H).max() <= 1e-12 * np.abs(P.H).max()
+        assert np.abs(host(M) - P.M).max() <= 1e-12 * np.abs(P.M).max()
+    assert all(torch.equal(x, y) for x, y in zip(fresh, reused))
+    for sized in (False, True):              # a fill short of capacity is refused on either route
+        if sized:
+            size(a1)
+        with pytest.raises(ff.FFError) as ei:
+            fill(a1, m1 - 1)
+        assert ei.value.code == ff.FF_ERR_CAPACITY
+
+
 def test_separate_quadrature_points(oracle, ctx, ff):
     c = synth.random_cloud(2000, seed=14)
     rng = np.random.default_rng(3)
