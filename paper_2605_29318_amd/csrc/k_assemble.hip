@@ -34,6 +34,11 @@ struct Win {
     int32_t base[26];
     int32_t nr;
     int32_t pad;
+    // the same runs indexed by their (z, y) offset in the 5 x 5 window, (dz + 2) * 5 + (dy + 2):
+    // a node's slot follows from its cell's (z, y) without a search
+    int64_t s25[25];
+    int32_t b25[25];
+    int32_t cz, cy;
 };
 
 __device__ inline int wave_incl_scan_i32(int v) {
@@ -81,6 +86,14 @@ __device__ int64_t build_window(int64_t k, const int64_t *cs, GridI g, Win *win)
     }
     const int64_t lenc = len > (int64_t)kWinMax ? (int64_t)kWinMax + 1 : len;   // keep the scan in int range
     const int incl = wave_incl_scan_i32((int)lenc);
+    if (lane < 25) {
+        win->s25[lane] = start;
+        win->b25[lane] = incl - (int)lenc;
+    }
+    if (lane == 0) {
+        win->cz = (int32_t)cz;
+        win->cy = (int32_t)cy;
+    }
     const uint64_t mask = __ballot(len > 0);
     const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     if (len > 0) {
@@ -98,13 +111,12 @@ __device__ int64_t build_window(int64_t k, const int64_t *cs, GridI g, Win *win)
     return total;
 }
 
-__device__ inline int local_of(int64_t l, const Win *w) {
-    int lo = 0, hi = w->nr - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (w->start[mid] <= l) lo = mid; else hi = mid - 1;
-    }
-    return w->base[lo] + (int)(l - w->start[lo]);
+// slot of node l in the window, zy = (z << 16) | y of l's cell; -1 outside the 5 x 5 runs
+__device__ inline int local_of_zy(int64_t l, uint32_t zy, const Win *w) {
+    const int dz = (int)(zy >> 16) - w->cz + 2, dy = (int)(zy & 0xffffu) - w->cy + 2;
+    if ((unsigned)dz > 4u || (unsigned)dy > 4u) return -1;
+    const int run = dz * 5 + dy;
+    return w->b25[run] + (int)(l - w->s25[run]);
 }
 
 __device__ inline int64_t global_of(int x, const Win *w) {
@@ -120,7 +132,7 @@ __device__ inline int64_t global_of(int x, const Win *w) {
 // the range of N(i)) are read by the lanes in one pass; the neighbour ids of
 // entry j + 1 are requested before entry j is marked.
 __device__ inline void mark_row(int64_t k, const int64_t *nt_off, const int2 *nt, const int64_t *off,
-                                const int32_t *ids, const Win *win, uint32_t *bm, int nwords) {
+                                const int32_t *ids, const uint32_t *zys, const Win *win, uint32_t *bm, int nwords) {
     const int lane = threadIdx.x & 63;
     for (int w = lane; w < nwords; w += 64) bm[w] = 0u;
     __builtin_amdgcn_wave_barrier();
@@ -135,9 +147,13 @@ __device__ inline void mark_row(int64_t k, const int64_t *nt_off, const int2 *nt
             f1 = off[i + 1];
         }
         int32_t idA = -1, idB = -1;
+        uint32_t zA = 0, zB = 0;
         {
             const int64_t s0 = __shfl(f0, 0, 64), s1 = __shfl(f1, 0, 64);
-            if (s0 + lane < s1) idA = ids[s0 + lane];
+            if (s0 + lane < s1) {
+                idA = ids[s0 + lane];
+                zA = zys[s0 + lane];
+            }
         }
         for (int j = 0; j < cnt; j += 2) {
             int64_t s0, s1;
@@ -145,29 +161,46 @@ __device__ inline void mark_row(int64_t k, const int64_t *nt_off, const int2 *nt
                 s0 = __shfl(f0, j + 1, 64);
                 s1 = __shfl(f1, j + 1, 64);
                 idB = s0 + lane < s1 ? ids[s0 + lane] : -1;
+                zB = s0 + lane < s1 ? zys[s0 + lane] : 0u;
             }
             s0 = __shfl(f0, j, 64);
             s1 = __shfl(f1, j, 64);
             for (int64_t f = s0 + lane; f < s1; f += 64) {
-                const int32_t id = f == s0 + lane ? idA : ids[f];
-                const int x = local_of(id, win);
+                const bool first = f == s0 + lane;
+                const int32_t id = first ? idA : ids[f];
+                const int x = local_of_zy(id, first ? zA : zys[f], win);
                 if (x >= 0 && x < wend) atomicOr(&bm[x >> 5], 1u << (x & 31));
             }
             if (j + 1 >= cnt) break;
             if (j + 2 < cnt) {
                 const int64_t t0 = __shfl(f0, j + 2, 64), t1 = __shfl(f1, j + 2, 64);
                 idA = t0 + lane < t1 ? ids[t0 + lane] : -1;
+                zA = t0 + lane < t1 ? zys[t0 + lane] : 0u;
             }
             s0 = __shfl(f0, j + 1, 64);
             s1 = __shfl(f1, j + 1, 64);
             for (int64_t f = s0 + lane; f < s1; f += 64) {
-                const int32_t id = f == s0 + lane ? idB : ids[f];
-                const int x = local_of(id, win);
+                const bool first = f == s0 + lane;
+                const int32_t id = first ? idB : ids[f];
+                const int x = local_of_zy(id, first ? zB : zys[f], win);
                 if (x >= 0 && x < wend) atomicOr(&bm[x >> 5], 1u << (x & 31));
             }
         }
     }
     __builtin_amdgcn_wave_barrier();
+}
+
+// (z << 16) | y of each node's cell, then of each neighbour entry (aligned with the ids)
+__global__ void node_zy_kernel(int64_t ncell, const int64_t *cs, GridI g, uint32_t *zy) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncell) return;
+    const uint32_t v = (uint32_t)((c / ((int64_t)g.d[0] * g.d[1])) << 16) | (uint32_t)((c / g.d[0]) % g.d[1]);
+    for (int64_t j = cs[c]; j < cs[c + 1]; ++j) zy[j] = v;
+}
+
+__global__ void entry_zy_kernel(int64_t total, const int32_t *ids, const uint32_t *node_zy, uint32_t *zy) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < total) zy[e] = node_zy[ids[e]];
 }
 
 // ---------------------------------------------------------------------------
@@ -237,7 +270,7 @@ __global__ void __launch_bounds__(256) nt_sort_kernel(const int64_t *nt_off, int
 
 __global__ void __launch_bounds__(256) sym_kernel(int64_t n, const int64_t *cs, GridI g, const int64_t *nt_off,
                                                   const int2 *nt, const int64_t *off, const int32_t *ids,
-                                                  int32_t *rowlen, int *stats) {
+                                                  const uint32_t *zys, int32_t *rowlen, int *stats) {
     __shared__ Win wins[4];
     __shared__ uint32_t bms[4][kWinWords];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -254,7 +287,7 @@ __global__ void __launch_bounds__(256) sym_kernel(int64_t n, const int64_t *cs, 
         return;
     }
     const int nwords = (int)((W + 31) >> 5);
-    mark_row(k, nt_off, nt, off, ids, win, bm, nwords);
+    mark_row(k, nt_off, nt, off, ids, zys, win, bm, nwords);
     int c = 0;
     for (int w = lane; w < nwords; w += 64) c += __popc(bm[w]);
     c = wave_sum_i32(c);
@@ -270,6 +303,7 @@ __global__ void __launch_bounds__(256) sym_kernel(int64_t n, const int64_t *cs, 
 
 __global__ void __launch_bounds__(256) num_kernel(int64_t n, const int64_t *cs, GridI g, const int64_t *nt_off,
                                                   const int2 *nt, const int64_t *off, const int32_t *ids,
+                                                  const uint32_t *zys,
                                                   const double *phi, const double *dphi, const double *vol,
                                                   const double *lam, const double *mu, const double *rho,
                                                   const int32_t *perm, const int64_t *row_ptr, int32_t *col,
@@ -287,7 +321,7 @@ __global__ void __launch_bounds__(256) num_kernel(int64_t n, const int64_t *cs, 
 
     const int64_t W = build_window(k, cs, g, win);
     const int nwords = (int)((W + 31) >> 5);
-    mark_row(k, nt_off, nt, off, ids, win, bm, nwords);
+    mark_row(k, nt_off, nt, off, ids, zys, win, bm, nwords);
 
     // exclusive prefix of popcounts over the bitmap words
     int carry = 0;
@@ -345,14 +379,16 @@ __global__ void __launch_bounds__(256) num_kernel(int64_t n, const int64_t *cs, 
             qm = rho ? vol[ii] * rho[ii] : vol[ii];
         }
         // first 64 neighbours of an entry, requested ahead
-        struct Pre { int32_t id; double d0, d1, d2, p; };
+        struct Pre { int32_t id; uint32_t zy; double d0, d1, d2, p; };
         auto fetch = [&](int j, Pre &P) {
             const int64_t s0 = __shfl(f0, j, 64), s1 = __shfl(f1, j, 64);
             const int64_t f = s0 + lane;
             P.id = -1;
+            P.zy = 0u;
             P.d0 = P.d1 = P.d2 = P.p = 0.0;
             if (f < s1) {
                 P.id = ids[f];
+                P.zy = zys[f];
                 P.d0 = dphi[3 * f];
                 P.d1 = dphi[3 * f + 1];
                 P.d2 = dphi[3 * f + 2];
@@ -365,21 +401,24 @@ __global__ void __launch_bounds__(256) num_kernel(int64_t n, const int64_t *cs, 
             const double pk = __shfl(qp, j, 64), wi = __shfl(qw, j, 64), mi = __shfl(qm, j, 64);
             for (int64_t f = s0 + lane; f < s1; f += 64) {
                 int32_t id;
+                uint32_t zy;
                 double d0, d1, d2, pf;
                 if (f == s0 + lane) {
                     id = P.id;
+                    zy = P.zy;
                     d0 = P.d0;
                     d1 = P.d1;
                     d2 = P.d2;
                     pf = P.p;
                 } else {
                     id = ids[f];
+                    zy = zys[f];
                     d0 = dphi[3 * f];
                     d1 = dphi[3 * f + 1];
                     d2 = dphi[3 * f + 2];
                     pf = phi[f];
                 }
-                const int x = local_of(id, win);
+                const int x = local_of_zy(id, zy, win);
                 if (x < 0 || x >= wend) continue;
                 const uint32_t word = bm[x >> 5];
                 const int r = pre[x >> 5] + __popc(word & ((1u << (x & 31)) - 1u));
@@ -448,9 +487,13 @@ extern "C" int assemble_HM(ff_ctx *ctx, int64_t n, int64_t q, const int64_t *nbr
     int64_t *nt_off = (int64_t *)ws_get(ctx, WS_NT_OFF, (size_t)(n + 1) * sizeof(int64_t));
     if (!nt_off) return FF_ERR_OOM;
     int2 *nt = nullptr;
+    uint32_t *zys = nullptr;                       // (z << 16) | y of each neighbour entry's cell
     int rowmax = 0;
+    FF_REQUIRE(ctx, grid->dims[1] < 65536 && grid->dims[2] < 65536, "grid of %d x %d x %d cells too large",
+               grid->dims[0], grid->dims[1], grid->dims[2]);
     if (reuse) {
         nt = (int2 *)ctx->ws[WS_NT];
+        zys = (uint32_t *)ctx->ws[WS_ZYE];
         *nnz = ctx->asm_nnz;
         rowmax = ctx->asm_rowmax;
         if (nnz_cap < *nnz)
@@ -465,6 +508,17 @@ extern "C" int assemble_HM(ff_ctx *ctx, int64_t n, int64_t q, const int64_t *nbr
         int32_t *cnt = (int32_t *)ws_get(ctx, WS_COUNTS, (size_t)n * sizeof(int32_t));
         int32_t *cursor = (int32_t *)ws_get(ctx, WS_CURSOR, (size_t)n * sizeof(int32_t));
         nt = (int2 *)ws_get(ctx, WS_NT, (size_t)(total > 0 ? total : 1) * sizeof(int2));
+        uint32_t *node_zy = (uint32_t *)ws_get(ctx, WS_ZYN, (size_t)n * sizeof(uint32_t));
+        zys = (uint32_t *)ws_get(ctx, WS_ZYE, (size_t)(total > 0 ? total : 1) * sizeof(uint32_t));
+        if (!node_zy || !zys) return FF_ERR_OOM;
+        hipLaunchKernelGGL(node_zy_kernel, dim3(grid_for(g.ncell, 256)), dim3(256), 0, st, (int64_t)g.ncell,
+                           cell_start, g, node_zy);
+        FF_CHECK_LAUNCH(ctx);
+        if (total > 0) {
+            hipLaunchKernelGGL(entry_zy_kernel, dim3(grid_for(total, 256)), dim3(256), 0, st, total, nbr_id, node_zy,
+                               zys);
+            FF_CHECK_LAUNCH(ctx);
+        }
         int32_t *rowlen = (int32_t *)ws_get(ctx, WS_ROWLEN, (size_t)n * sizeof(int32_t));
         int *stats = (int *)ws_get(ctx, WS_ASM_FLAG, 64);
         if (!cnt || !cursor || !nt_off || !nt || !rowlen || !stats) return FF_ERR_OOM;
@@ -484,7 +538,7 @@ extern "C" int assemble_HM(ff_ctx *ctx, int64_t n, int64_t q, const int64_t *nbr
         FF_CHECK_LAUNCH(ctx);
 
         hipLaunchKernelGGL(sym_kernel, dim3(grid_for(n, 4)), dim3(256), 0, st, n, cell_start, g, nt_off, nt, nbr_off,
-                           nbr_id, rowlen, stats);
+                           nbr_id, zys, rowlen, stats);
         FF_CHECK_LAUNCH(ctx);
         rc = scan_exclusive_i32_to_i64(ctx, rowlen, row_ptr, n);
         if (rc) return rc;
@@ -519,8 +573,8 @@ extern "C" int assemble_HM(ff_ctx *ctx, int64_t n, int64_t q, const int64_t *nbr
     while (waves > 1 && waves * per_wave > 64 * 1024) waves >>= 1;
     const size_t shmem = (size_t)waves * per_wave;
     hipLaunchKernelGGL(num_kernel, dim3(grid_for(n, waves)), dim3(64 * waves), shmem, st, n, cell_start, g, nt_off,
-                       nt, nbr_off, nbr_id, phi, dphi, vol, lam, mu, rho, perm, row_ptr, col, H, M, hm32, rmax,
-                       per_wave);
+                       nt, nbr_off, nbr_id, zys, phi, dphi, vol, lam, mu, rho, perm, row_ptr, col, H, M, hm32,
+                       rmax, per_wave);
     FF_CHECK_LAUNCH(ctx);
     return FF_OK;
 }
