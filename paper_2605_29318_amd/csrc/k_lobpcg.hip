@@ -1735,33 +1735,48 @@ __global__ void cheb_init_kernel(int64_t n, int m, int64_t ld, const int *row_ob
 // s = 1 / max_rows |W[., c]| (1 for a zero column): the preconditioner is linear, so this scales
 // column c of its output by s, which leaves the span the Rayleigh-Ritz step works on unchanged,
 // and it keeps the iterates inside the binary16 range whatever the residuals' magnitude.
+// one wavefront per (column, object): lanes stride the object's chunks, then a butterfly max
 __global__ void colmax_obj_kernel(int n_obj, const int *obj_status, const int *cfirst, const int *ccount,
                                   const float *wpart, int m, float *cmax) {
-    const int o = blockIdx.x, c = threadIdx.x;
+    const int c = blockIdx.x, o = blockIdx.y, lane = threadIdx.x;
     if (o >= n_obj || c >= m || obj_status[o] != 0) return;
     float v = 0.f;
-    for (int i = 0; i < ccount[o]; ++i) v = fmaxf(v, wpart[(size_t)(cfirst[o] + i) * m + c]);
-    cmax[(size_t)o * m + c] = v;
+    for (int i = lane; i < ccount[o]; i += 64) v = fmaxf(v, wpart[(size_t)(cfirst[o] + i) * m + c]);
+    for (int d = 32; d >= 1; d >>= 1) v = fmaxf(v, __shfl_xor(v, d, 64));
+    if (lane == 0) cmax[(size_t)o * m + c] = v;
 }
 
-// z0 of the binary16 recurrence: R <- s W, dz = binary16(s W / theta), W <- dz
+// z0 of the binary16 recurrence: R <- s W, dz = binary16(s W / theta), W <- dz; four columns per
+// thread (m is a multiple of 16 on this path)
 __global__ void cheb_init_q_kernel(int64_t n, int m, int64_t ld, const int *row_obj, const int *obj_status,
                                    const double *coef, const float *cmax, float *S, float *Rb, _Float16 *DZ) {
+    typedef float f32x4_t __attribute__((ext_vector_type(4)));
+    typedef _Float16 f16x4_t __attribute__((ext_vector_type(4)));
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n * m) return;
-    const int64_t r = t / m;
-    const int c = (int)(t - r * m);
+    const int mq = m >> 2;
+    if (t >= n * mq) return;
+    const int64_t r = t / mq;
+    const int c = 4 * (int)(t - r * mq);
     const int o = row_obj[r];
     if (obj_status[o] != 0) return;
-    float *w = S + r * ld + m + c;
-    const float mx = cmax[(size_t)o * m + c];
-    const double v = (double)*w * (mx > 0.f ? 1.0 / (double)mx : 1.0);
-    double dz = v * coef[(size_t)o * kChebCoef];
-    dz = dz > 65504.0 ? 65504.0 : (dz < -65504.0 ? -65504.0 : dz);
-    const _Float16 h = (_Float16)(float)dz;
-    Rb[t] = (float)v;
-    DZ[t] = h;
-    *w = (float)h;
+    f32x4_t *w = (f32x4_t *)(S + r * ld + m + c);
+    const f32x4_t wv = *w;
+    const double th = coef[(size_t)o * kChebCoef];
+    f32x4_t rv, wo;
+    f16x4_t h;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const float mx = cmax[(size_t)o * m + c + q];
+        const double v = (double)wv[q] * (mx > 0.f ? 1.0 / (double)mx : 1.0);
+        double dz = v * th;
+        dz = dz > 65504.0 ? 65504.0 : (dz < -65504.0 ? -65504.0 : dz);
+        h[q] = (_Float16)(float)dz;
+        rv[q] = (float)v;
+        wo[q] = (float)h[q];
+    }
+    *(f32x4_t *)(Rb + r * m + c) = rv;
+    *(f16x4_t *)(DZ + r * m + c) = h;
+    *w = wo;
 }
 
 // step s: R -= D^-1 H dz, dz = f1 dz + f2 R, W += dz
@@ -2100,10 +2115,10 @@ int stage_precond(Solver &s, T *S) {
         uint16_t *q16[2] = {(uint16_t *)s.cheb_dz, (uint16_t *)s.cheb_dz + s.N * s.m};
         {
             StageMark mark(s.ctx, s.st, FF_STAGE_PRECOND_OTHER);
-            hipLaunchKernelGGL(colmax_obj_kernel, dim3(s.n_obj), dim3(64), 0, s.st, s.n_obj, s.status, s.gfirst,
+            hipLaunchKernelGGL(colmax_obj_kernel, dim3(s.m, s.n_obj), dim3(64), 0, s.st, s.n_obj, s.status, s.gfirst,
                                s.gcount, s.wpart, s.m, s.cmax);
             FF_CHECK_LAUNCH(s.ctx);
-            hipLaunchKernelGGL(cheb_init_q_kernel, dim3(grid_for(cnt, 256)), dim3(256), 0, s.st, s.N, s.m, ld,
+            hipLaunchKernelGGL(cheb_init_q_kernel, dim3(grid_for(cnt / 4, 256)), dim3(256), 0, s.st, s.N, s.m, ld,
                                s.row_obj, s.status, s.cheb_coef, s.cmax, (float *)S, (float *)Rb, (_Float16 *)q16[0]);
             FF_CHECK_LAUNCH(s.ctx);
         }
