@@ -42,6 +42,14 @@ __device__ inline int xcd_remap(int b, int nb) {
 template <typename T> struct Vec;
 template <> struct Vec<float> { typedef float4 type; static constexpr int n = 4; };
 template <> struct Vec<double> { typedef double2 type; static constexpr int n = 2; };
+__device__ inline float vget(const float4 &a, int i) { return i == 0 ? a.x : i == 1 ? a.y : i == 2 ? a.z : a.w; }
+__device__ inline double vget(const double2 &a, int i) { return i == 0 ? a.x : a.y; }
+__device__ inline void vset(float4 &a, int i, float v) {
+    if (i == 0) a.x = v; else if (i == 1) a.y = v; else if (i == 2) a.z = v; else a.w = v;
+}
+__device__ inline void vset(double2 &a, int i, double v) {
+    if (i == 0) a.x = v; else a.y = v;
+}
 
 template <typename T> struct HMPair;
 template <> struct HMPair<float> {
@@ -417,21 +425,31 @@ gram_kernel(const GChunk *chunks, const int *obj_status, const int *width, const
 }
 
 // G[o][p][i][j] = sum over the object's chunks (ascending) of part[c][p][i][j]
+// 256 threads: 16 consecutive outputs x 16 parts; part pp sums the chunks c = pp (mod 16) in ascending
+// order, then the 16 part sums are added in order: a fixed order, so the result is deterministic
 __global__ void __launch_bounds__(256) gram_reduce_kernel(const int *obj_status, const int *width,
                                                           const int *gfirst, const int *gcount, const double *part,
                                                           int wmax, double *G) {
     const int o = blockIdx.y;
     if (obj_status[o] != 0) return;
+    __shared__ double red[16][17];
     const int w = width[o];
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // over 2 * wmax * wmax
+    const int q = threadIdx.x & 15, pp = threadIdx.x >> 4;
+    const int64_t idx = (int64_t)blockIdx.x * 16 + q;   // over 2 * wmax * wmax
     const int64_t per = (int64_t)wmax * wmax;
-    if (idx >= 2 * per) return;
     const int i = (int)((idx % per) / wmax), j = (int)(idx % wmax);
-    if (i >= w || j >= w) return;
+    const bool live = idx < 2 * per && i < w && j < w;
     const int c0 = gfirst[o], nc = gcount[o];
     double s = 0.0;
-    for (int c = 0; c < nc; ++c) s += part[(size_t)(c0 + c) * 2 * per + idx];
-    G[(size_t)o * 2 * per + idx] = s;
+    if (live)
+        for (int c = pp; c < nc; c += 16) s += part[(size_t)(c0 + c) * 2 * per + idx];
+    red[pp][q] = s;
+    __syncthreads();
+    if (pp == 0 && live) {
+        double t = 0.0;
+        for (int u = 0; u < 16; ++u) t += red[u][q];
+        G[(size_t)o * 2 * per + idx] = t;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -442,30 +460,53 @@ template <typename T>
 __global__ void __launch_bounds__(256) resid_kernel(const UChunk *chunks, const int *obj_status, T *S, const T *HS,
                                                     const T *MS, int64_t ld, int m, const double *theta,
                                                     const T *dinv, double *rpart, float *wpart) {
+    // VN consecutive columns per thread (16-byte loads; m is a multiple of 4), rows_per rows per pass
+    typedef typename Vec<T>::type V;
+    constexpr int VN = Vec<T>::n;
     const UChunk ch = chunks[blockIdx.x];
     if (obj_status[ch.obj] != 0) return;
-    const int rows_per = 256 / m;
+    const int mv = m / VN;
+    const int rows_per = 256 / mv;
     const int t = threadIdx.x;
-    const int rr = t / m, c = t - (t / m) * m;
-    __shared__ double red[2][256];
-    __shared__ float wred[256];
-    double r2 = 0.0, x2 = 0.0;
-    float wmax = 0.f;
+    const int rr = t / mv, c = (t - (t / mv) * mv) * VN;
+    __shared__ double red[2][256 * VN];
+    __shared__ float wred[256 * VN];
+    double r2[VN], x2[VN], th[VN];
+    float wmax[VN];
+#pragma unroll
+    for (int v = 0; v < VN; ++v) {
+        r2[v] = x2[v] = 0.0;
+        wmax[v] = 0.f;
+    }
     if (rr < rows_per) {
-        const double th = theta[(size_t)ch.obj * m + c];
+#pragma unroll
+        for (int v = 0; v < VN; ++v) th[v] = theta[(size_t)ch.obj * m + c + v];
         for (int64_t r = ch.r0 + rr; r < ch.r0 + ch.len; r += rows_per) {
-            const double x = (double)S[r * ld + c];
-            const double R = (double)HS[r * ld + c] - th * (double)MS[r * ld + c];
-            r2 += R * R;
-            x2 += x * x;
-            const T w = (T)(dinv ? R * (double)dinv[r] : R);
-            S[r * ld + m + c] = w;
-            wmax = fmaxf(wmax, fabsf((float)w));
+            const V xs = *(const V *)(S + r * ld + c), hs = *(const V *)(HS + r * ld + c),
+                    ms = *(const V *)(MS + r * ld + c);
+            const double dv = dinv ? (double)dinv[r] : 1.0;
+            V wv;
+#pragma unroll
+            for (int v = 0; v < VN; ++v) {
+                const double x = (double)vget(xs, v);
+                const double R = (double)vget(hs, v) - th[v] * (double)vget(ms, v);
+                r2[v] += R * R;
+                x2[v] += x * x;
+                const T w = (T)(dinv ? R * dv : R);
+                vset(wv, v, w);
+                wmax[v] = fmaxf(wmax[v], fabsf((float)w));
+            }
+            *(V *)(S + r * ld + m + c) = wv;
         }
     }
-    red[0][t] = r2;
-    red[1][t] = x2;
-    wred[t] = wmax;
+    if (rr < rows_per) {
+#pragma unroll
+        for (int v = 0; v < VN; ++v) {
+            red[0][rr * m + c + v] = r2[v];
+            red[1][rr * m + c + v] = x2[v];
+            wred[rr * m + c + v] = wmax[v];
+        }
+    }
     __syncthreads();
     if (t < m) {
         double a = 0.0, b = 0.0;
@@ -1821,10 +1862,11 @@ static const char *kVariantNames[] = {"waves4_unroll2_xcd", "waves4_unroll4_xcd"
                                       "chunk64_waves4_batch4_occ8", "chunk64_waves2_batch16",
                                       "rowtile4_waves4_batch4", "rowtile4_waves2_batch8",
                                       "rowtile4_waves4_batch4_occ4", "rowtile8_mfma64_waves4_batch8",
-                                      "rowtile8_mfma64_waves2_batch8", "rowtile8_mfma64_waves4_batch4_occ6"};
-constexpr int kNumVariants = 19;
+                                      "rowtile8_mfma64_waves2_batch8", "rowtile8_mfma64_waves4_batch4_occ6",
+                                      "rowtile8_mfma32x64_waves4_batch8", "rowtile8_mfma32x64_waves2_batch8"};
+constexpr int kNumVariants = 21;
 constexpr int kRowTileBase = 13;               // variants from here on run on a row-tile copy
-constexpr int kRowTile8Base = 16;              // from here on: the eight-row [H, M] copy on FP64 MFMA (FP32 blocks)
+constexpr int kRowTile8Base = 16;              // from here on: the eight-row [H, M] copy on MFMA (FP32 blocks)
 constexpr int kCsrVariant = 11;                // fastest variant on the CSR itself
 constexpr int kDefaultVariant64 = 14;  // fastest untuned FP64 choice on 10^5-10^6-row RKPM matrices (row tiles)
 constexpr int kDefaultVariant32 = 16;  // fastest untuned FP32 choice (eight-row tiles, MFMA)
@@ -2060,7 +2102,7 @@ int stage_gram_rr(Solver &s, T *S, T *HS, T *MS, double tau) {
                        s.status, s.width, S, HS, MS, (int64_t)3 * s.m, s.wmax, s.gpart, 1);
     FF_CHECK_LAUNCH(s.ctx);
     const int64_t per2 = 2 * (int64_t)s.wmax * s.wmax;
-    hipLaunchKernelGGL(gram_reduce_kernel, dim3(grid_for(per2, 256), s.n_obj), dim3(256), 0, s.st, s.status, s.width,
+    hipLaunchKernelGGL(gram_reduce_kernel, dim3(grid_for(per2, 16), s.n_obj), dim3(256), 0, s.st, s.status, s.width,
                        s.gfirst, s.gcount, s.gpart, s.wmax, s.G);
     FF_CHECK_LAUNCH(s.ctx);
     mark.end();
@@ -2898,6 +2940,7 @@ extern "C" int spmm_autotune(ff_ctx *ctx, int64_t n, const int64_t *row_ptr, con
         float ms = 0.f;
         FF_HIP(ctx, hipEventElapsedTime(&ms, e0, e1));
         const double per = ms / reps;
+        if (ctx->verbose) fprintf(stderr, "[freeform] autotune %s: %.3f ms\n", kVariantNames[v], per);
         if (per < bms) {
             bms = per;
             best = v;
@@ -2990,7 +3033,7 @@ extern "C" int gram_hm(ff_ctx *ctx, int64_t n, int w, int precision, const void 
                            (const double *)MS, ld, w, part, vec_ok);
     FF_CHECK_LAUNCH(ctx);
     const int64_t per2 = 2 * (int64_t)w * w;
-    hipLaunchKernelGGL(gram_reduce_kernel, dim3(grid_for(per2, 256), 1), dim3(256), 0, st, ints, ints + 1, ints + 2,
+    hipLaunchKernelGGL(gram_reduce_kernel, dim3(grid_for(per2, 16), 1), dim3(256), 0, st, ints, ints + 1, ints + 2,
                        ints + 3, part, w, G);
     FF_CHECK_LAUNCH(ctx);
     FF_HIP(ctx, hipStreamSynchronize(st));

@@ -1712,7 +1712,7 @@ __device__ inline f64x4r mfma64(double a, double b, f64x4r c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-template <int kMT, int kBatch>
+template <int kMT, int kBatch, bool kF32>
 __device__ __forceinline__ void hm8_chunk(ChunkHM8 &ch, int64_t base, int64_t e1, const int32_t *tcol,
                                           const float *vh, const float *vm, float *sv, int lane, int li, int lk, int m,
                                           const float *Y, int64_t ldy, f64x4r (&d)[kMT]) {
@@ -1741,15 +1741,29 @@ __device__ __forceinline__ void hm8_chunk(ChunkHM8 &ch, int64_t base, int64_t e1
         for (int u = 0; u < kBatch; ++u) {
             if (q0 + u < nq) {
                 const int e = 4 * (q0 + u) + lk;
-                const double a = (double)sv[e * 16 + li];
+                if (kF32) {
+                    // each step of four entries on the FP32 matrix cores from a zero accumulator, its
+                    // sums added in FP64: a step rounds once at 2^-24 of its terms, the order of the
+                    // FP32 rounding of the stored values themselves
+                    const float a = sv[e * 16 + li];
 #pragma unroll
-                for (int t = 0; t < kMT; ++t) d[t] = mfma64(a, (double)yget(y[u], t), d[t]);
+                    for (int t = 0; t < kMT; ++t) {
+                        const f32x4 p = __builtin_amdgcn_mfma_f32_16x16x4f32(a, yget(y[u], t),
+                                                                            f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) d[t][v] += (double)p[v];
+                    }
+                } else {
+                    const double a = (double)sv[e * 16 + li];
+#pragma unroll
+                    for (int t = 0; t < kMT; ++t) d[t] = mfma64(a, (double)yget(y[u], t), d[t]);
+                }
             }
         }
     }
 }
 
-template <int kMT, int kWaves, int kBatch, int kOcc>
+template <int kMT, int kWaves, int kBatch, int kOcc, bool kF32>
 __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(kOcc, 8)))
 spmm_hm8_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int32_t *tcol, const float *vh,
                 const float *vm, const float *Y, int64_t ldy, float *HY, float *MY, int64_t ldo, int m,
@@ -1773,12 +1787,13 @@ spmm_hm8_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int32_
     ChunkHM8 ch;
     ch.load(tcol, vh, vm, e0 + lane, e0 + lane < e1);
     for (int64_t base = e0; base < e1; base += 64)
-        hm8_chunk<kMT, kBatch>(ch, base, e1, tcol, vh, vm, sv, lane, li, lk, m, Y, ldy, d);
+        hm8_chunk<kMT, kBatch, kF32>(ch, base, e1, tcol, vh, vm, sv, lane, li, lk, m, Y, ldy, d);
     if (kMT == 1 && li >= m) return;
-    // lane holds D[4 v + lk][li]: output 4 v + lk (H rows 0..7, then M rows 0..7), columns kMT li + t
+    // lane holds D[o][li] for v = 0..3 with o = 4 v + lk on the FP64 matrix cores and o = 4 lk + v on the
+    // FP32 ones (their result layouts differ); outputs o: H rows 0..7, then M rows 0..7; columns kMT li + t
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-        const int o = 4 * v + lk;
+        const int o = kF32 ? 4 * lk + v : 4 * v + lk;
         const int64_t r = r0 + (o & 7);
         if (r >= nrows || (obj_status && obj_status[row_obj[r]] != 0)) continue;
         float *dst = (o < 8 ? HY : MY) + r * ldo + kMT * li;
@@ -1800,20 +1815,28 @@ int spmm_hm8(ff_ctx *ctx, hipStream_t st, const RT8View &v, int sub, int m, cons
                "eight-row [H, M] tiles: bad copy or block shape (m = %d)", m);
     FF_REQUIRE(ctx, off32_ok(v.n, ldy), "block of %lld rows x %lld too large for 32-bit row offsets", (long long)v.n,
                (long long)ldy);
-#define FF_HM8(MT, W, B, O)                                                                                \
-    hipLaunchKernelGGL((spmm_hm8_kernel<MT, W, B, O>), dim3(grid_for(v.ntiles, W)), dim3(64 * W), 0, st, v.n, \
+#define FF_HM8(MT, W, B, O, F)                                                                                \
+    hipLaunchKernelGGL((spmm_hm8_kernel<MT, W, B, O, F>), dim3(grid_for(v.ntiles, W)), dim3(64 * W), 0, st, v.n, \
                        v.ntiles, v.tptr, v.tcol, v.vh, v.vm, Y, ldy, HY, MY, ldo, m, row_obj, status)
+    // sub 0..2: FP64 matrix cores; 3, 4: FP32 matrix cores with FP64 accumulation of each four-entry step
     const int mt = m <= 16 ? 1 : m / 16;
+    const bool f32 = sub >= 3;
     if (mt == 1) {
-        FF_HM8(1, 4, 8, 4);
+        if (f32) FF_HM8(1, 4, 8, 4, true); else FF_HM8(1, 4, 8, 4, false);
     } else if (mt == 2) {
         switch (sub) {
-            case 1: FF_HM8(2, 2, 8, 4); break;
-            case 2: FF_HM8(2, 4, 4, 6); break;
-            default: FF_HM8(2, 4, 8, 4); break;
+            case 1: FF_HM8(2, 2, 8, 4, false); break;
+            case 2: FF_HM8(2, 4, 4, 6, false); break;
+            case 3: FF_HM8(2, 4, 8, 4, true); break;
+            case 4: FF_HM8(2, 2, 8, 4, true); break;
+            default: FF_HM8(2, 4, 8, 4, false); break;
         }
     } else {
-        if (sub == 1) FF_HM8(4, 2, 4, 4); else FF_HM8(4, 4, 4, 4);
+        if (f32) {
+            if (sub == 4) FF_HM8(4, 2, 4, 4, true); else FF_HM8(4, 4, 4, 4, true);
+        } else {
+            if (sub == 1) FF_HM8(4, 2, 4, 4, false); else FF_HM8(4, 4, 4, 4, false);
+        }
     }
 #undef FF_HM8
     FF_CHECK_LAUNCH(ctx);
