@@ -186,7 +186,7 @@ def main():
                     help="run a short solve (--steps iterations) and a 1 GiB calibration kernel (for counter passes)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(run with --gpus 1).", file=sys.stderr)
         sys.exit(2)
     if args.counters:

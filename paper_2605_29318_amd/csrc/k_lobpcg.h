@@ -1,4 +1,4 @@
-// Row-chunk descriptors shared by the eigensolver kernels and their driver.
+// Row-chunk descriptors shared by the eigensolver kernels and their host code.
 #pragma once
 #include <cstdint>
 

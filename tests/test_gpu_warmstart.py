@@ -2,7 +2,7 @@
 by the library's own kernels on modes that eigenmodes computes for seeded
 ellipsoid-union shapes, then starts eigenmodes on held-out shapes.
 
-The converged answer is the judge: from the network's block the solver must
+The converged answer is the reference: from the network's block the solver must
 reach the same eigenpairs (eigenvalues against a tight FP64 solve, within the
 error the residual tolerance allows) and the residual tolerance itself. The
 gain is the number of iterations against a random start on the same shapes.
