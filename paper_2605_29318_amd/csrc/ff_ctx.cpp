@@ -125,6 +125,8 @@ int ff_ctx_create(ff_ctx **out, int device, void *hip_stream) {
     ctx->stream = (hipStream_t)hip_stream;
     const char *v = getenv("FF_VERBOSE");
     ctx->verbose = v && v[0] == '1';
+    // a cap on the LDS bitmap of the tile-copy build, so that its other paths can be exercised
+    if (const char *b = getenv("FF_UNION_BITS")) ctx->union_bits = atoi(b) < 0 ? 0 : atoi(b);
     *out = ctx;
     return FF_OK;
 }

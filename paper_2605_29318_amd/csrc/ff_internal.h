@@ -57,6 +57,7 @@ struct ff_ctx {
     double stage_ms[FF_STAGE_COUNT] = {};
     int64_t stage_launches[FF_STAGE_COUNT] = {};
     int verbose = 0;                 // FF_VERBOSE=1: residual trace on stderr
+    int union_bits = -1;             // FF_UNION_BITS: cap on the tile-copy build's bitmap words (-1: none)
     // symbolic state of assemble_HM's sizing call, reused by a matching next call
     bool asm_valid = false;
     const void *asm_ptr[4] = {};

@@ -118,20 +118,43 @@ __global__ void rt_count_kernel(int64_t nrows, int64_t ntiles, const int64_t *ro
 // - G[start q]. Each representative writes its slot, the column and the R values (zero where a
 // row lacks it), so every slot is written once and the copy equals the serial merge's. The
 // column lists sit in LDS (cap entries per tile); a larger tile takes the serial merge.
+//
+// The common case is faster still: a tile's columns lie in the range [cmin, cmax] of its rows' first
+// and last columns (its rows' two-hop neighbourhood, 2.6e3 words of 32 columns at the median on the
+// benchmark's clouds), so a bitmap of that range in LDS marks the union and a prefix popcount over
+// its words gives every column's slot directly. The tile's value block is then cleared and every
+// entry writes its own value into its slot and row (each slot's column is written by each of its
+// entries, the same value). Tiles whose range exceeds the bitmap take the path above.
 constexpr int kUnionCap = 6144;                   // entries per tile held in LDS (49 KB with G)
 constexpr int kUnionThreads = 256;
+constexpr int kUnionBitWords = 4096;              // bitmap words (32 KB with their prefix)
 
+// mx[0]: the largest entry count of a tile, mx[1]: the largest bitmap of a tile's column range in words
 template <int R>
-__global__ void tile_entries_max_kernel(int64_t nrows, int64_t ntiles, const int64_t *row_ptr, int *mx) {
+__global__ void tile_entries_max_kernel(int64_t nrows, int64_t ntiles, const int64_t *row_ptr, const int32_t *col,
+                                        int *mx) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int v = 0;
+    int v = 0, words = 0;
     if (t < ntiles) {
         const int64_t r1 = (t + 1) * R < nrows ? (t + 1) * R : nrows;
         const int64_t e = row_ptr[r1] - row_ptr[t * R];
         v = e < INT_MAX ? (int)e : INT_MAX;
+        int32_t lo = INT_MAX, hi = -1;
+        for (int64_t r = t * R; r < r1; ++r)
+            if (row_ptr[r + 1] > row_ptr[r]) {
+                lo = min(lo, col[row_ptr[r]]);
+                hi = max(hi, col[row_ptr[r + 1] - 1]);
+            }
+        if (hi >= lo) words = (int)(((int64_t)hi - lo) / 32 + 1);
     }
-    for (int d = 32; d >= 1; d >>= 1) v = max(v, __shfl_xor(v, d, 64));
-    if ((threadIdx.x & 63) == 0) atomicMax(mx, v);
+    for (int d = 32; d >= 1; d >>= 1) {
+        v = max(v, __shfl_xor(v, d, 64));
+        words = max(words, __shfl_xor(words, d, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(mx, v);
+        atomicMax(mx + 1, words);
+    }
 }
 
 __device__ inline int lower_bound_lds(const int32_t *a, int len, int32_t c) {
@@ -149,32 +172,103 @@ __device__ inline int lower_bound_lds(const int32_t *a, int len, int32_t c) {
 template <int R, bool kFill>
 __global__ void __launch_bounds__(kUnionThreads) tile_union_kernel(int64_t nrows, int64_t ntiles,
                                                                    const int64_t *row_ptr, const int32_t *col,
-                                                                   int cap, int64_t *cnt, const double *H,
-                                                                   const double *M, const int64_t *tptr,
-                                                                   int32_t *tcol, float *vh, float *vm) {
+                                                                   int cap, int bits, int64_t *cnt,
+                                                                   const double *H, const double *M,
+                                                                   const int64_t *tptr, int32_t *tcol, float *vh,
+                                                                   float *vm) {
     extern __shared__ __align__(16) int32_t lds[];
     int32_t *lcol = lds;                           // [cap] the rows' columns, row after row
     int32_t *G = lds + cap;                        // [cap + 1] representative flags, then their prefix
     __shared__ int rs[R + 1];                      // row starts in lcol
     __shared__ int64_t gs[R];                      // row starts in the CSR
     __shared__ int wsum[kUnionThreads / 64];
+    __shared__ int32_t crange[2];                  // first and last column of the tile
     const int64_t t = blockIdx.x;
     if (t >= ntiles) return;
     const int tid = threadIdx.x;
     const int64_t r0 = t * R;
     if (tid == 0) {
         int acc = 0;
+        int32_t lo = INT_MAX, hi = -1;
         for (int r = 0; r < R; ++r) {
             const bool in = r0 + r < nrows;
             const int64_t b = in ? row_ptr[r0 + r] : 0, e = in ? row_ptr[r0 + r + 1] : 0;
             gs[r] = b;
             rs[r] = acc;
             acc += (int)(e - b);
+            if (e > b) {
+                lo = min(lo, col[b]);
+                hi = max(hi, col[e - 1]);
+            }
         }
         rs[R] = acc;
+        crange[0] = lo;
+        crange[1] = hi;
     }
     __syncthreads();
     const int E = rs[R];
+    auto row_of = [&](int x) {
+        int r = 0;
+        while (r + 1 < R && rs[r + 1] <= x) ++r;
+        return r;
+    };
+    const int32_t cmin = crange[0];
+    const int nw = E > 0 ? (int)(((int64_t)crange[1] - cmin) / 32 + 1) : 0;
+    if (nw <= bits) {
+        uint32_t *bm = (uint32_t *)lds;            // [bits] the union's columns, relative to cmin
+        int32_t *pre = lds + bits;                 // [bits] set bits in the words before
+        for (int w = tid; w < nw; w += kUnionThreads) bm[w] = 0u;
+        __syncthreads();
+        for (int x = tid; x < E; x += kUnionThreads) {
+            const int r = row_of(x);
+            const int b = col[gs[r] + (x - rs[r])] - cmin;
+            atomicOr(&bm[b >> 5], 1u << (b & 31));
+        }
+        __syncthreads();
+        const int per = (nw + kUnionThreads - 1) / kUnionThreads;
+        const int w0 = min(nw, tid * per), w1 = min(nw, w0 + per);
+        int local = 0;
+        for (int w = w0; w < w1; ++w) local += __popc(bm[w]);
+        const int lane = tid & 63, wv = tid >> 6;
+        int incl = local;
+        for (int d = 1; d < 64; d <<= 1) {
+            const int u = __shfl_up(incl, d, 64);
+            if (lane >= d) incl += u;
+        }
+        if (lane == 63) wsum[wv] = incl;
+        __syncthreads();
+        int run = incl - local, U = 0;
+        for (int w = 0; w < kUnionThreads / 64; ++w) {
+            if (w < wv) run += wsum[w];
+            U += wsum[w];
+        }
+        for (int w = w0; w < w1; ++w) {
+            pre[w] = run;
+            run += __popc(bm[w]);
+        }
+        if (!kFill) {
+            if (tid == 0) cnt[t] = U;
+            return;
+        }
+        const int64_t o = tptr[t];
+        // clear the tile's values, then every entry writes its own; the barrier orders the two
+        for (int i = tid; i < U * R / 4; i += kUnionThreads) {
+            *(f32x4 *)(vh + o * R + 4 * i) = f32x4{0.f, 0.f, 0.f, 0.f};
+            if (vm) *(f32x4 *)(vm + o * R + 4 * i) = f32x4{0.f, 0.f, 0.f, 0.f};
+        }
+        __syncthreads();
+        for (int x = tid; x < E; x += kUnionThreads) {
+            const int r = row_of(x);
+            const int64_t g = gs[r] + (x - rs[r]);
+            const int32_t c = col[g];
+            const int b = c - cmin;
+            const int rank = pre[b >> 5] + __popc(bm[b >> 5] & ((1u << (b & 31)) - 1u));
+            tcol[o + rank] = c;
+            vh[(o + rank) * R + r] = (float)H[g];
+            if (vm) vm[(o + rank) * R + r] = (float)M[g];
+        }
+        return;
+    }
     if (E > cap) {
         if (tid == 0) {
             if (kFill)
@@ -184,11 +278,6 @@ __global__ void __launch_bounds__(kUnionThreads) tile_union_kernel(int64_t nrows
         }
         return;
     }
-    auto row_of = [&](int x) {
-        int r = 0;
-        while (r + 1 < R && rs[r + 1] <= x) ++r;
-        return r;
-    };
     for (int x = tid; x < E; x += kUnionThreads) {
         const int r = row_of(x);
         lcol[x] = col[gs[r] + (x - rs[r])];
@@ -782,22 +871,23 @@ static int build_ptr(ff_ctx *ctx, hipStream_t st, int64_t n, const int64_t *row_
 // tile's entry count, at most kUnionCap), tile pointers and the number of union entries (host)
 template <int R>
 static int build_ptr_union(ff_ctx *ctx, hipStream_t st, int64_t n, const int64_t *row_ptr, const int32_t *col,
-                           int64_t *cnt, int64_t *tptr, int64_t ntiles, int64_t *entries, int *cap) {
+                           int64_t *cnt, int64_t *tptr, int64_t ntiles, int64_t *entries, int *cap, int *bits) {
     int *mx0 = (int *)ws_get(ctx, WS_RT8_MAX, 256);
     int64_t *h = (int64_t *)pinned_get(ctx, 64);
     if (!mx0 || !h) return FF_ERR_OOM;
     int *mx = mx0 + 1;                             // word 0 serves the binary16 copies' |H| maximum
-    FF_HIP(ctx, hipMemsetAsync(mx, 0, sizeof(int), st));
+    FF_HIP(ctx, hipMemsetAsync(mx, 0, 2 * sizeof(int), st));
     hipLaunchKernelGGL(tile_entries_max_kernel<R>, dim3(grid_for(ntiles, 256)), dim3(256), 0, st, n, ntiles, row_ptr,
-                       mx);
+                       col, mx);
     FF_CHECK_LAUNCH(ctx);
-    FF_HIP(ctx, hipMemcpyAsync(h, mx, sizeof(int), hipMemcpyDeviceToHost, st));
+    FF_HIP(ctx, hipMemcpyAsync(h, mx, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
     FF_HIP(ctx, hipStreamSynchronize(st));
-    *cap = std::min(*(int *)h, kUnionCap);
-    hipLaunchKernelGGL((tile_union_kernel<R, false>), dim3(ntiles), dim3(kUnionThreads),
-                       (size_t)(2 * *cap + 1) * sizeof(int32_t), st, n, ntiles, row_ptr, col, *cap, cnt,
-                       (const double *)nullptr, (const double *)nullptr, (const int64_t *)nullptr, (int32_t *)nullptr,
-                       (float *)nullptr, (float *)nullptr);
+    *cap = std::min(((int *)h)[0], kUnionCap);
+    *bits = std::min(((int *)h)[1], ctx->union_bits >= 0 ? std::min(ctx->union_bits, kUnionBitWords) : kUnionBitWords);
+    const size_t lds = (size_t)std::max(2 * *cap + 1, 2 * *bits) * sizeof(int32_t);
+    hipLaunchKernelGGL((tile_union_kernel<R, false>), dim3(ntiles), dim3(kUnionThreads), lds, st, n, ntiles, row_ptr,
+                       col, *cap, *bits, cnt, (const double *)nullptr, (const double *)nullptr,
+                       (const int64_t *)nullptr, (int32_t *)nullptr, (float *)nullptr, (float *)nullptr);
     FF_CHECK_LAUNCH(ctx);
     int rc = scan_exclusive_i64(ctx, cnt, tptr, ntiles);
     if (rc) return rc;
@@ -809,11 +899,11 @@ static int build_ptr_union(ff_ctx *ctx, hipStream_t st, int64_t n, const int64_t
 
 template <int R>
 static int fill_union(ff_ctx *ctx, hipStream_t st, int64_t n, int64_t ntiles, const int64_t *row_ptr,
-                      const int32_t *col, int cap, const double *H, const int64_t *tptr, int32_t *tcol, float *vh,
-                      const double *M = nullptr, float *vm = nullptr) {
-    hipLaunchKernelGGL((tile_union_kernel<R, true>), dim3(ntiles), dim3(kUnionThreads),
-                       (size_t)(2 * cap + 1) * sizeof(int32_t), st, n, ntiles, row_ptr, col, cap, (int64_t *)nullptr,
-                       H, M, tptr, tcol, vh, vm);
+                      const int32_t *col, int cap, int bits, const double *H, const int64_t *tptr, int32_t *tcol,
+                      float *vh, const double *M = nullptr, float *vm = nullptr) {
+    const size_t lds = (size_t)std::max(2 * cap + 1, 2 * bits) * sizeof(int32_t);
+    hipLaunchKernelGGL((tile_union_kernel<R, true>), dim3(ntiles), dim3(kUnionThreads), lds, st, n, ntiles, row_ptr,
+                       col, cap, bits, (int64_t *)nullptr, H, M, tptr, tcol, vh, vm);
     FF_CHECK_LAUNCH(ctx);
     return FF_OK;
 }
@@ -1100,15 +1190,15 @@ int build_t8_ws(ff_ctx *ctx, hipStream_t st, int64_t n, const int64_t *row_ptr, 
     int64_t *tptr = (int64_t *)ws_get(ctx, WS_RT8_PTR, (size_t)(ntiles + 1) * sizeof(int64_t));
     if (!cnt || !tptr) return FF_ERR_OOM;
     int64_t entries = 0;
-    int cap = 0;
-    int rc = build_ptr_union<kTile8>(ctx, st, n, row_ptr, col, cnt, tptr, ntiles, &entries, &cap);
+    int cap = 0, bits = 0;
+    int rc = build_ptr_union<kTile8>(ctx, st, n, row_ptr, col, cnt, tptr, ntiles, &entries, &cap, &bits);
     if (rc) return rc;
     const size_t ne = (size_t)std::max<int64_t>(entries, 1);
     int32_t *tcol = (int32_t *)ws_get(ctx, WS_RT8_COL, ne * sizeof(int32_t));
     float *vh = (float *)ws_get(ctx, WS_RT8_VAL, ne * kTile8 * sizeof(float));
     float *vm = M ? (float *)ws_get(ctx, WS_RT8_VALM, ne * kTile8 * sizeof(float)) : nullptr;
     if (!tcol || !vh || (M && !vm)) return FF_ERR_OOM;
-    if ((rc = fill_union<kTile8>(ctx, st, n, ntiles, row_ptr, col, cap, H, tptr, tcol, vh, M, vm))) return rc;
+    if ((rc = fill_union<kTile8>(ctx, st, n, ntiles, row_ptr, col, cap, bits, H, tptr, tcol, vh, M, vm))) return rc;
     out->n = n;
     out->ntiles = ntiles;
     out->entries = entries;
@@ -1657,14 +1747,14 @@ int build_t16_ws(ff_ctx *ctx, hipStream_t st, int64_t n, const int64_t *row_ptr,
     int64_t *tptr = (int64_t *)ws_get(ctx, WS_RT16_PTR, (size_t)(ntiles + 1) * sizeof(int64_t));
     if (!cnt || !tptr) return FF_ERR_OOM;
     int64_t entries = 0;
-    int cap = 0;
-    int rc = build_ptr_union<kTile16>(ctx, st, n, row_ptr, col, cnt, tptr, ntiles, &entries, &cap);
+    int cap = 0, bits = 0;
+    int rc = build_ptr_union<kTile16>(ctx, st, n, row_ptr, col, cnt, tptr, ntiles, &entries, &cap, &bits);
     if (rc) return rc;
     const size_t ne = (size_t)std::max<int64_t>(entries, 1);
     int32_t *tcol = (int32_t *)ws_get(ctx, WS_RT16_COL, ne * sizeof(int32_t));
     float *vh = (float *)ws_get(ctx, WS_RT16_VAL, ne * kTile16 * sizeof(float));
     if (!tcol || !vh) return FF_ERR_OOM;
-    if ((rc = fill_union<kTile16>(ctx, st, n, ntiles, row_ptr, col, cap, H, tptr, tcol, vh))) return rc;
+    if ((rc = fill_union<kTile16>(ctx, st, n, ntiles, row_ptr, col, cap, bits, H, tptr, tcol, vh))) return rc;
     out->n = n;
     out->ntiles = ntiles;
     out->entries = entries;
@@ -1876,11 +1966,12 @@ int rowtiles_build(ff_ctx *ctx, int64_t n, const int64_t *row_ptr, const int32_t
         }
         h->mem[0] = tptr8;
         int64_t ent8 = 0;
-        int cap8 = 0;
+        int cap8 = 0, bits8 = 0;
         if (!rc8)
-            rc8 = R == rt::kTile8
-                      ? rt::build_ptr_union<rt::kTile8>(ctx, st, n, row_ptr, col, cnt8, tptr8, nt8, &ent8, &cap8)
-                      : rt::build_ptr_union<rt::kTile16>(ctx, st, n, row_ptr, col, cnt8, tptr8, nt8, &ent8, &cap8);
+            rc8 = R == rt::kTile8 ? rt::build_ptr_union<rt::kTile8>(ctx, st, n, row_ptr, col, cnt8, tptr8, nt8, &ent8,
+                                                                    &cap8, &bits8)
+                                  : rt::build_ptr_union<rt::kTile16>(ctx, st, n, row_ptr, col, cnt8, tptr8, nt8, &ent8,
+                                                                     &cap8, &bits8);
         if (cnt8) (void)hipFree(cnt8);
         int32_t *tcol8 = nullptr;
         float *vh = nullptr;
@@ -1895,9 +1986,9 @@ int rowtiles_build(ff_ctx *ctx, int64_t n, const int64_t *row_ptr, const int32_t
             h->mem[2] = vh;
         }
         if (!rc8)
-            rc8 = R == rt::kTile8 ? rt::fill_union<rt::kTile8>(ctx, st, n, nt8, row_ptr, col, cap8, H, tptr8, tcol8, vh)
-                                  : rt::fill_union<rt::kTile16>(ctx, st, n, nt8, row_ptr, col, cap8, H, tptr8, tcol8,
-                                                                vh);
+            rc8 = R == rt::kTile8
+                      ? rt::fill_union<rt::kTile8>(ctx, st, n, nt8, row_ptr, col, cap8, bits8, H, tptr8, tcol8, vh)
+                      : rt::fill_union<rt::kTile16>(ctx, st, n, nt8, row_ptr, col, cap8, bits8, H, tptr8, tcol8, vh);
         h->v8.n = h->v16.n = n;
         h->v8.ntiles = h->v16.ntiles = nt8;
         h->v8.entries = h->v16.entries = ent8;

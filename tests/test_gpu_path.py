@@ -253,18 +253,28 @@ def test_rowtiles_spmm(oracle, ctx, ff, precision):
     rt.close()
 
 
+@pytest.mark.parametrize("bitmap", [True, False])
 @pytest.mark.parametrize("rows,hf", [(8, 1.0), (16, 1.0), (8, 1.3)])
-def test_rowtiles_h_only_copies(oracle, ctx, ff, rows, hf):
+def test_rowtiles_h_only_copies(oracle, ctx, ff, rows, hf, bitmap):
     """The preconditioner's H-only copies in tiles of eight rows (VALU kernel) and of
     sixteen rows (MFMA kernel), ragged last tile: H Y in FP32 accumulation, every launch
     shape and the block widths the kernels take; other forms are rejected. The copies are
-    built one workgroup per tile with the rows' columns in LDS, tiles beyond its capacity
-    by the serial merge: the sixteen-row tiles of this cloud and the eight-row tiles at a
-    1.3x support radius (up to 7766 entries per tile) take both paths."""
+    built one workgroup per tile: from a bitmap of the tile's column range in LDS, or
+    (FF_UNION_BITS=0, as for a range beyond the bitmap) from the rows' columns in LDS by
+    binary search, tiles beyond that capacity by the serial merge: the sixteen-row tiles of
+    this cloud and the eight-row tiles at a 1.3x support radius (up to 7766 entries per
+    tile) take both of the latter."""
+    import os
     c = synth.random_cloud(2503, seed=29, hetero=True)
     c.h *= hf
     P = oracle.pipeline(c)
     A = ff.assemble_cloud(ctx, dev(c.xyz), dev(c.vol), dev(c.lam), dev(c.mu), c.h)
+    if not bitmap:
+        os.environ["FF_UNION_BITS"] = "0"
+        try:
+            ctx = ff.Context(0)
+        finally:
+            del os.environ["FF_UNION_BITS"]
     rt = ff.RowTiles(ctx, A.n, A.row_ptr, A.col, A.H, A.M, precision=3 if rows == 8 else 4)
     ntiles, entries = rt.info()
     assert ntiles == (c.n + rows - 1) // rows
@@ -288,6 +298,8 @@ def test_rowtiles_h_only_copies(oracle, ctx, ff, rows, hf):
     with pytest.raises(ff.FFError):
         rt.spmm(dev(np.ones((c.n, 32)), torch.float32), 1, 0)   # MY requested
     rt.close()
+    if not bitmap:
+        ctx.close()
 
 
 def _fp16_storage(H):
