@@ -188,7 +188,7 @@ int assemble_HM(ff_ctx *ctx, int64_t n, int64_t q, const int64_t *nbr_off, const
 /* Eigensolver parameters. */
 typedef struct {
     int k;              /* eigenpairs wanted, constant mode included (>= 1) */
-    int block;          /* block width m >= k (0 = choose); multiple of 4, <= 64 */
+    int block;          /* block width m >= k (0 = k rounded up to a multiple of 8); a multiple of 8, <= 64 */
     int precision;      /* 0 = FP64 throughout; 1 = mixed: FP32 products, FP64 Rayleigh-Ritz,
                            then FP64 certification and FP64 iterations if needed */
     double tol;         /* max_j r_j over the first k pairs, r_j as in eigenmodes() */
