@@ -309,9 +309,10 @@ def main():
         "stage_launches": {k: int(v[1]) for k, v in stages.items()},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "spmm_tq_kernel<%d, true> (Chebyshev step on the matrix cores: binary16 H in "
+                     "kernel": "spmm_tq_sb_kernel<%d, true> (Chebyshev step on the matrix cores: binary16 H in "
                                "K-blocks of the eight-row tiles times the binary16 iterate, FP32 accumulation on "
-                               "v_mfma_f32_16x16x16_f16, fused with the step's vector update, m=%d)" % (m // 16, m),
+                               "v_mfma_f32_16x16x16_f16, loads pipelined a super-block of four K-blocks ahead, "
+                               "fused with the step's vector update, m=%d)" % (m // 16, m),
                      "bytes_per_launch": cheb_alg, "launch_ms": round(cheb_avg, 4),
                      "share_of_solve": round(cheb_ms / max(stages["total"][0], 1e-9), 3)},
         "spmm_hm": {"achieved": round(spmm_gbps, 1), "unit": "GB/s", "bytes_per_launch": spmm_alg,

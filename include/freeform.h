@@ -341,8 +341,11 @@ int rayleigh_ritz(ff_ctx *ctx, int w, int m, const double *G, double tau, double
  *   rows) or m in {4, 8, 12, 16, 32, 64} (sixteen rows). A handle built
  *   with precision 6 also takes precision 2: Y in binary16 ([n][m] with
  *   ld_y == m, m 32 or 64), HY = H Y in FP32, accumulated in FP32 on
- *   v_mfma_f32_16x16x16_f16 (MY NULL); its launch shapes are sub 0 .. 4
- *   (waves per workgroup and K-blocks in flight). Errors: invalid
+ *   v_mfma_f32_16x16x16_f16 (MY NULL); its launch shapes are sub 0 .. 7
+ *   (0 .. 4: a ring of K-blocks, by waves per workgroup and K-blocks in
+ *   flight; 5 .. 7: super-blocks of four K-blocks, the next one's loads
+ *   issued before the current one is multiplied), all with the same
+ *   summation order. Errors: invalid
  *   arguments and unsupported shapes return FF_ERR_INVALID_ARG, a
  *   non-finite H at precision 5 likewise.
  */

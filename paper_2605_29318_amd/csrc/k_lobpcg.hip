@@ -1672,7 +1672,9 @@ constexpr int kChebDefault = 12;               // degree when the caller passes 
 constexpr double kChebRatio = 1000.0;          // b / a when the caller passes 0
 constexpr int kChebT8Sub = 1;                  // launch shape of the fused step (fewer registers than the
                                                // H-only product's default with the step's operands live)
-constexpr int kChebTqSub = 0;                  // launch shape of the matrix-core Chebyshev step
+// launch shape of the matrix-core Chebyshev step: the super-block pipelined kernel, eight waves per
+// workgroup at m = 32, four at m = 64
+inline int cheb_tq_sub(int m) { return m == 32 ? 5 : 6; }
 
 // Gershgorin bound of D^-1/2 H D^-1/2 per row: sum_j |H_ij| / sqrt(H_ii H_jj), one wavefront per row
 __global__ void gersh_row_kernel(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *H,
@@ -2175,7 +2177,7 @@ int stage_precond(Solver &s, T *S) {
             cs.W = (float *)(S + s.m);
             cs.ldw = ld;
             cs.dz_out = q16[step & 1];
-            const int rc = rt::cheb_step_tq(s.ctx, s.st, s.rtq, kChebTqSub, s.m, q16[(step - 1) & 1], s.row_obj,
+            const int rc = rt::cheb_step_tq(s.ctx, s.st, s.rtq, cheb_tq_sub(s.m), s.m, q16[(step - 1) & 1], s.row_obj,
                                             s.status, cs);
             if (rc) return rc;
         }

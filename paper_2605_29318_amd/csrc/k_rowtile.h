@@ -113,7 +113,7 @@ struct ChebStepQ {
     int64_t ldw = 0;
 };
 // sub selects a launch shape (waves per block, K-blocks in flight), 0 .. kTqSubs - 1
-constexpr int kTqSubs = 5;
+constexpr int kTqSubs = 8;
 int cheb_step_tq(ff_ctx *ctx, hipStream_t st, const RTQView &v, int sub, int m, const uint16_t *DZ,
                  const int *row_obj, const int *status, const ChebStepQ &cs);
 // HY = H Y (Y binary16 [rows][m], HY FP32 with leading dimension ldo)

@@ -1498,6 +1498,152 @@ spmm_tq_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int32_t
     }
 }
 
+// The same product with the gathers pipelined a super-block of four K-blocks (64 union entries) ahead.
+// Vector loads retire in order, so in the ring above the wait for a K-block's columns also waits for
+// every gather issued before them and at most one or two K-blocks of gathers are in flight. Here each
+// lane loads one column of a super-block (coalesced, two super-blocks ahead) and the lanes that
+// gather a row take its column from that lane by a cross-lane read; the gathers and value loads of
+// super-block s + 1 are issued before super-block s is multiplied. The four K-blocks of a super-block
+// use separate LDS buffers.
+template <int kMB, bool kEpi, int kWaves, int kOcc>
+__global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(kOcc, 8)))
+spmm_tq_sb_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int32_t *tcol, const int64_t *kptr,
+                  const _Float16 *vq, float vscale, const _Float16 *Y, float *HY, int64_t ldo, const int *row_obj,
+                  const int *obj_status, ChebStepQ cs) {
+    constexpr int m = 16 * kMB;
+    constexpr int kPieces = m / 8;                 // 16-byte pieces of a binary16 row of the block
+    constexpr int kRowsPer = 64 / kPieces;         // rows one wave-wide load covers (16 or 8)
+    constexpr int kLoads = 16 / kRowsPer;          // loads per K-block (1 or 2)
+    constexpr int kStride = 2 * m + 16;            // LDS row stride in bytes
+    constexpr int kQ = 4;                          // K-blocks per super-block
+    __shared__ __align__(16) unsigned char ys[kWaves][kQ][16 * kStride];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t t = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kWaves + wv;
+    if (t >= ntiles) return;
+    const int64_t r0 = t * kTile8;
+    const int rr = lane & 15, quad = lane >> 4;
+    const int64_t rme = r0 + (rr & 7);
+    const bool mine = rr < 8 && rme < nrows && (!obj_status || obj_status[row_obj[rme]] == 0);
+    bool any = false;
+#pragma unroll
+    for (int i = 0; i < kTile8; ++i)
+        any = any || (r0 + i < nrows && (!obj_status || obj_status[row_obj[r0 + i]] == 0));
+    if (!any) return;
+    const int64_t e0 = tptr[t], e1 = tptr[t + 1], k0 = kptr[t];
+    const int nk = (int)(kptr[t + 1] - k0);
+    const int ns = (nk + kQ - 1) / kQ;
+    const int piece = lane % kPieces, slot = lane / kPieces;
+    // entries past the tile's end read its last column (their values are zero)
+    auto cols_of = [&](int s) -> int {
+        const int64_t e = e0 + 64 * (int64_t)s + lane;
+        return tcol[e < e1 ? e : e1 - 1];
+    };
+    const _Float16 *vb = vq + k0 * 128 + (rr & 7) * 16 + 4 * quad;   // this lane's values in the tile's K-blocks
+    // the gathers of a super-block, then its value loads (consumed in that order); whole: all four
+    // K-blocks lie inside the tile
+    auto issue = [&](int s, int cols, f32x4 (&y)[kQ][kLoads], f16x4 (&b)[kQ], bool whole) {
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int q = 0; q < kQ; ++q)
+#pragma unroll
+            for (int i = 0; i < kLoads; ++i) {
+                const uint32_t j = (uint32_t)__shfl(cols, 16 * q + slot + kRowsPer * i, 64);
+                y[q][i] = *(const f32x4 *)(Y + (size_t)(j * (uint32_t)m) + piece * 8);
+            }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) {
+            const int kb = whole || kQ * s + q < nk ? kQ * s + q : nk - 1;
+            b[q] = __builtin_nontemporal_load((const f16x4 *)(vb + kb * 128));
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    f32x4 acc[kMB];
+#pragma unroll
+    for (int cb = 0; cb < kMB; ++cb) acc[cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // multiplies super-block s; full: all four of its K-blocks lie inside the tile
+    auto consume = [&](int s, const f32x4 (&y)[kQ][kLoads], const f16x4 (&b)[kQ], bool full) {
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int q = 0; q < kQ; ++q)
+#pragma unroll
+            for (int i = 0; i < kLoads; ++i)
+                *(f32x4 *)(&ys[wv][q][0] + (slot + kRowsPer * i) * kStride + piece * 16) = y[q][i];
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) {
+            if (!full && kQ * s + q >= nk) break;
+            const unsigned char *sy = &ys[wv][q][0];
+#pragma unroll
+            for (int cb = 0; cb < kMB; ++cb) {
+                f16x4 a;
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    a[u] = *(const _Float16 *)(sy + (4 * quad + u) * kStride + (16 * cb + rr) * 2);
+                acc[cb] = __builtin_amdgcn_mfma_f32_16x16x16f16(a, b[q], acc[cb], 0, 0, 0);
+            }
+        }
+    };
+    if (nk > 0) {
+        f32x4 ya[kQ][kLoads], yb[kQ][kLoads];
+        f16x4 ba[kQ], bb[kQ];
+        const int c0 = cols_of(0);
+        int c1 = cols_of(ns > 1 ? 1 : 0);
+        issue(0, c0, ya, ba, ns > 1);
+        int s = 0;
+        // steady state: super-blocks s and s + 1 are whole, s + 2 exists
+        for (; s + 2 < ns; s += 2) {
+            const int c2 = cols_of(s + 2);
+            issue(s + 1, c1, yb, bb, true);
+            consume(s, ya, ba, true);
+            c1 = cols_of(s + 3 < ns ? s + 3 : ns - 1);
+            issue(s + 2, c2, ya, ba, false);
+            consume(s + 1, yb, bb, true);
+        }
+        // the last one or two super-blocks
+        if (s + 1 < ns) {
+            issue(s + 1, c1, yb, bb, false);
+            consume(s, ya, ba, true);
+            consume(s + 1, yb, bb, false);
+        } else {
+            consume(s, ya, ba, false);
+        }
+    }
+    if (!mine) return;
+    if (kEpi) {
+        const int o = row_obj[rme];
+        const double f1 = cs.coef[(size_t)o * cs.stride + 2 * cs.step - 1];
+        const double f2 = cs.coef[(size_t)o * cs.stride + 2 * cs.step];
+        const double dv = (double)cs.dinv[rme] * (double)vscale;
+        _Float16 *dzo = (_Float16 *)cs.dz_out;
+#pragma unroll
+        for (int cb = 0; cb < kMB; ++cb) {
+            const int c0 = 16 * cb + 4 * quad;
+            float *rp = cs.R + rme * m + c0, *wp = cs.W + rme * cs.ldw + c0;
+            const f32x4 er = *(const f32x4 *)rp, ew = *(const f32x4 *)wp;
+            const f16x4 ez = *(const f16x4 *)(Y + rme * m + c0);
+            f32x4 rv1, w1;
+            f16x4 dz1;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double rv = (double)er[q] - dv * (double)acc[cb][q];
+                double dz = f1 * (double)(float)ez[q] + f2 * rv;
+                dz = dz > 65504.0 ? 65504.0 : (dz < -65504.0 ? -65504.0 : dz);   // binary16 range
+                rv1[q] = (float)rv;
+                dz1[q] = (_Float16)(float)dz;
+                w1[q] = (float)((double)ew[q] + (double)(float)dz1[q]);
+            }
+            *(f32x4 *)rp = rv1;
+            *(f16x4 *)(dzo + rme * m + c0) = dz1;
+            *(f32x4 *)wp = w1;
+        }
+    } else {
+#pragma unroll
+        for (int cb = 0; cb < kMB; ++cb)
+            *(f32x4 *)(HY + rme * ldo + 16 * cb + 4 * quad) = acc[cb] * vscale;
+    }
+}
+
 template <bool kEpi>
 static int launch_tq(ff_ctx *ctx, hipStream_t st, const RTQView &v, int sub, int m, const uint16_t *Y, float *HY,
                      int64_t ldo, const int *row_obj, const int *status, const ChebStepQ &cs) {
@@ -1506,11 +1652,16 @@ static int launch_tq(ff_ctx *ctx, hipStream_t st, const RTQView &v, int sub, int
     FF_REQUIRE(ctx, v.n * (int64_t)m < ((int64_t)1 << 32), "block of %lld rows x %d too large for 32-bit offsets",
                (long long)v.n, m);
     const _Float16 *vq = (const _Float16 *)v.vq, *y = (const _Float16 *)Y;
-    // (waves per block, occupancy floor, K-blocks in the ring); product alone at 1M particles, m = 32 / 64:
-    // 0.607 / 0.888, 0.610 / 0.887, 0.656 / 0.962, 0.631 / 0.889, 0.612 / 0.892 ms. Eight consecutive tiles
-    // per workgroup share most gathered rows in the CU's cache.
+    // Ring shapes 0 .. 4 (waves per block, occupancy floor, K-blocks in the ring); product alone at 1M
+    // particles, m = 32 / 64: 0.607 / 0.888, 0.610 / 0.887, 0.656 / 0.962, 0.631 / 0.889, 0.612 / 0.892 ms.
+    // Super-block shapes 5 .. 7 (waves per block, occupancy floor), measured in one run with shape 0 at
+    // 0.622 / 0.897 ms: 0.551 / 0.863, 0.561 / 0.825, 0.552 / 0.864 ms. Eight consecutive tiles per
+    // workgroup share most gathered rows in the CU's cache.
 #define FF_TQ(MB, W, O, D)                                                                                        \
     hipLaunchKernelGGL((spmm_tq_kernel<MB, kEpi, W, O, D>), dim3(grid_for(v.ntiles, W)), dim3(64 * W), 0, st, v.n, \
+                       v.ntiles, v.tptr, v.tcol, v.kptr, vq, v.hscale, y, HY, ldo, row_obj, status, cs)
+#define FF_TQS(MB, W, O)                                                                                       \
+    hipLaunchKernelGGL((spmm_tq_sb_kernel<MB, kEpi, W, O>), dim3(grid_for(v.ntiles, W)), dim3(64 * W), 0, st, v.n, \
                        v.ntiles, v.tptr, v.tcol, v.kptr, vq, v.hscale, y, HY, ldo, row_obj, status, cs)
 #define FF_TQ_SHAPES(MB)                   \
     switch (sub) {                         \
@@ -1518,6 +1669,9 @@ static int launch_tq(ff_ctx *ctx, hipStream_t st, const RTQView &v, int sub, int
         case 2: FF_TQ(MB, 4, 4, 2); break; \
         case 3: FF_TQ(MB, 4, 4, 3); break; \
         case 4: FF_TQ(MB, 16, 4, 2); break; \
+        case 5: FF_TQS(MB, 8, 2); break;   \
+        case 6: FF_TQS(MB, 4, 2); break;   \
+        case 7: FF_TQS(MB, 8, MB == 2 ? 5 : 3); break; \
         default: FF_TQ(MB, 8, 4, 2); break; \
     }
     if (m == 32) {
@@ -1526,6 +1680,7 @@ static int launch_tq(ff_ctx *ctx, hipStream_t st, const RTQView &v, int sub, int
         FF_TQ_SHAPES(4)
     }
 #undef FF_TQ_SHAPES
+#undef FF_TQS
 #undef FF_TQ
     FF_CHECK_LAUNCH(ctx);
     return FF_OK;
