@@ -1865,13 +1865,17 @@ static const char *kVariantNames[] = {"waves4_unroll2_xcd", "waves4_unroll4_xcd"
                                       "rowtile4_waves4_batch4", "rowtile4_waves2_batch8",
                                       "rowtile4_waves4_batch4_occ4", "rowtile8_mfma64_waves4_batch8",
                                       "rowtile8_mfma64_waves2_batch8", "rowtile8_mfma64_waves4_batch4_occ6",
-                                      "rowtile8_mfma32x64_waves4_batch8", "rowtile8_mfma32x64_waves2_batch8"};
-constexpr int kNumVariants = 21;
+                                      "rowtile8_mfma32x64_waves4_batch8", "rowtile8_mfma32x64_waves2_batch8",
+                                      "rowtile8_mfma64_pipelined_waves4", "rowtile8_mfma32x64_pipelined_waves4",
+                                      "rowtile8_mfma64_pipelined_waves2"};
+constexpr int kNumVariants = 24;
 constexpr int kRowTileBase = 13;               // variants from here on run on a row-tile copy
 constexpr int kRowTile8Base = 16;              // from here on: the eight-row [H, M] copy on MFMA (FP32 blocks)
 constexpr int kCsrVariant = 11;                // fastest variant on the CSR itself
 constexpr int kDefaultVariant64 = 14;  // fastest untuned FP64 choice on 10^5-10^6-row RKPM matrices (row tiles)
 constexpr int kDefaultVariant32 = 16;  // fastest untuned FP32 choice (eight-row tiles, MFMA)
+constexpr int kDefaultVariant32m32 = 23;  // at m = 32: the pipelined kernel, two waves per workgroup (1.72 ms
+                                          // against 1.85-1.89 ms for the others at 10^6 rows)
 
 inline int rt_spmm(ff_ctx *ctx, hipStream_t st, const rt::RTView &v, int sub, int m, const float *Y, int64_t ldy,
                    float *HY, float *MY, int64_t ldo, const int *row_obj, const int *status) {
@@ -2550,7 +2554,8 @@ std::string tune_key(int64_t n, int64_t nnz, int m, int precision) {
 
 int lookup_variant(ff_ctx *ctx, int64_t n, int64_t nnz, int m, int precision) {
     auto it = ctx->tuned.find(tune_key(n, nnz, m, precision));
-    return it == ctx->tuned.end() ? (precision ? kDefaultVariant32 : kDefaultVariant64) : it->second;
+    if (it != ctx->tuned.end()) return it->second;
+    return precision ? (m == 32 ? kDefaultVariant32m32 : kDefaultVariant32) : kDefaultVariant64;
 }
 
 int solve(ff_ctx *ctx, int n_obj, const int64_t *obj_off, const int64_t *row_ptr, const int32_t *col, const double *H,

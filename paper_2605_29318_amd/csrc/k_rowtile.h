@@ -139,7 +139,9 @@ int cheb_step_t16(ff_ctx *ctx, hipStream_t st, const RT16View &v, int sub, int m
                   const int *row_obj, const int *status, const ChebStep<float> &cs);
 
 // [HY, MY] = [H, M] Y (FP32 blocks, FP64 accumulation on FP64 MFMA) on an
-// eight-row copy built with M; m in {4, 8, 12, 16, 32, 64}; sub 0..2.
+// eight-row copy built with M; m in {4, 8, 12, 16, 32, 64}; sub 0 .. kHm8Subs - 1 (3, 4 and 6 take
+// four-entry steps on the FP32 matrix cores, each added in FP64; 5, 6 and 7 pipeline the loads).
+constexpr int kHm8Subs = 8;
 bool hm8_ok(int m, int64_t ldy, int64_t ldo);
 int spmm_hm8(ff_ctx *ctx, hipStream_t st, const RT8View &v, int sub, int m, const float *Y, int64_t ldy, float *HY,
              float *MY, int64_t ldo, const int *row_obj, const int *status);

@@ -2052,6 +2052,148 @@ spmm_hm8_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int32_
     }
 }
 
+// The same product with its loads pipelined. Vector loads retire in order, so above the wait for a
+// batch's gathers also waits for the next chunk's columns and values, issued just before them. Here
+// a chunk's columns and values are loaded two batches ahead of their use and each batch of eight
+// quads (32 entries) is gathered while the previous one is multiplied:
+//   chunk c: stage values(c) in LDS; gather batch 2c+1; multiply batch 2c; gather batch 2c+2
+//   (columns of chunk c+1); load columns and values of chunk c+2; multiply batch 2c+1.
+// The MFMA sequence (entries in order, one accumulator per column group) is that of the kernel above.
+template <int kMT, int kWaves, int kOcc, bool kF32>
+__global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(kOcc, 8)))
+spmm_hm8p_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int32_t *tcol, const float *vh,
+                 const float *vm, const float *Y, int64_t ldy, float *HY, float *MY, int64_t ldo, int m,
+                 const int *row_obj, const int *obj_status) {
+    typedef typename YVec<kMT>::type YV;
+    constexpr int kB = 8;                          // quads (of four entries) per batch
+    __shared__ __align__(16) float svals[kWaves][64 * 16];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t t = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kWaves + wv;
+    if (t >= ntiles) return;
+    const int li = lane & 15, lk = lane >> 4;
+    const int64_t r0 = t * kTile8;
+    bool any = false;
+#pragma unroll
+    for (int i = 0; i < kTile8; ++i)
+        any = any || (r0 + i < nrows && (!obj_status || obj_status[row_obj[r0 + i]] == 0));
+    if (!any) return;
+    float *sv = svals[wv];
+    const int64_t e0 = tptr[t], e1 = tptr[t + 1];
+    const int nch = (int)((e1 - e0 + 63) >> 6);
+    const int col = kMT * (kMT > 1 || li < m ? li : 0);
+    f64x4r d[kMT];
+#pragma unroll
+    for (int q = 0; q < kMT; ++q) d[q] = f64x4r{0.0, 0.0, 0.0, 0.0};
+    // quads of chunk c: entries past the tile's end have column 0 and zero values
+    auto nquads = [&](int c) __attribute__((always_inline)) -> int {
+        const int64_t cnt = e1 - e0 - 64 * (int64_t)c;
+        return cnt >= 64 ? 16 : (int)((cnt + 3) >> 2);
+    };
+    // a chunk's columns and values without a branch: the index is clamped to the tile's last entry and
+    // the lanes past the end take column 0 and zero values where they are used (staging, gathers), so
+    // that no instruction touches the loaded registers before then
+    struct Chunk {
+        int32_t j;
+        f32x4 v[4];
+        bool in;
+    };
+    auto load_chunk = [&](Chunk &ch, int c) __attribute__((always_inline)) {
+        const int64_t e = e0 + 64 * (int64_t)c + lane;
+        ch.in = e < e1;
+        const int64_t ec = ch.in ? e : e1 - 1;
+        __builtin_amdgcn_sched_barrier(0);
+        ch.j = __builtin_nontemporal_load(tcol + ec);
+        ch.v[0] = __builtin_nontemporal_load((const f32x4 *)(vh + ec * 8));
+        ch.v[1] = __builtin_nontemporal_load((const f32x4 *)(vh + ec * 8 + 4));
+        ch.v[2] = __builtin_nontemporal_load((const f32x4 *)(vm + ec * 8));
+        ch.v[3] = __builtin_nontemporal_load((const f32x4 *)(vm + ec * 8 + 4));
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    auto stage = [&](const Chunk &ch) __attribute__((always_inline)) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            *(f32x4 *)(sv + lane * 16 + 4 * q) = ch.in ? ch.v[q] : f32x4{0.f, 0.f, 0.f, 0.f};
+    };
+    // batch h (0 or 1) of a chunk whose columns are jc; every quad is gathered (past the end: row 0)
+    auto gather = [&](YV (&y)[kB], const Chunk &ch, int h) __attribute__((always_inline)) {
+        const int32_t jc = ch.in ? ch.j : 0;
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < kB; ++u) {
+            const uint32_t j = (uint32_t)__shfl(jc, 4 * (kB * h + u) + lk, 64);
+            y[u] = *(const YV *)(Y + (size_t)(j * (uint32_t)ldy) + col);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    // the quads below nq (all of them when full)
+    auto multiply = [&](const YV (&y)[kB], int h, int nq, bool full) __attribute__((always_inline)) {
+#pragma unroll
+        for (int u = 0; u < kB; ++u) {
+            if (full || kB * h + u < nq) {
+                const int e = 4 * (kB * h + u) + lk;
+                if (kF32) {
+                    const float a = sv[e * 16 + li];
+#pragma unroll
+                    for (int tt = 0; tt < kMT; ++tt) {
+                        const f32x4 p = __builtin_amdgcn_mfma_f32_16x16x4f32(a, yget(y[u], tt),
+                                                                            f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) d[tt][v] += (double)p[v];
+                    }
+                } else {
+                    const double a = (double)sv[e * 16 + li];
+#pragma unroll
+                    for (int tt = 0; tt < kMT; ++tt) d[tt] = mfma64(a, (double)yget(y[u], tt), d[tt]);
+                }
+            }
+        }
+    };
+    // chunk c: cur holds its columns and values, nxt those of chunk c + 1; cur is then reloaded with
+    // chunk c + 2. steady: chunk c is whole and chunks c + 1 and c + 2 exist (no branch)
+    YV ya[kB], yb[kB];
+    auto step = [&](int c, Chunk &cur, Chunk &nxt, bool steady) __attribute__((always_inline)) {
+        const int nq = steady ? 16 : nquads(c);
+        __builtin_amdgcn_wave_barrier();
+        stage(cur);
+        __builtin_amdgcn_wave_barrier();
+        if (steady || nq > kB) gather(yb, cur, 1);
+        multiply(ya, 0, nq, steady);
+        if (steady || c + 1 < nch) gather(ya, nxt, 0);
+        if (steady || c + 2 < nch) load_chunk(cur, c + 2);
+        if (steady || nq > kB) multiply(yb, 1, nq, steady);
+    };
+    if (nch > 0) {
+        Chunk pa, pb;
+        load_chunk(pa, 0);
+        if (nch > 1) load_chunk(pb, 1);
+        gather(ya, pa, 0);
+        int c = 0;
+        for (; c + 3 < nch; c += 2) {
+            step(c, pa, pb, true);
+            step(c + 1, pb, pa, true);
+        }
+        // the last one to three chunks
+        step(c, pa, pb, false);
+        if (c + 1 < nch) step(c + 1, pb, pa, false);
+        if (c + 2 < nch) step(c + 2, pa, pb, false);
+    }
+    if (kMT == 1 && li >= m) return;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int o = kF32 ? 4 * lk + v : 4 * v + lk;
+        const int64_t r = r0 + (o & 7);
+        if (r >= nrows || (obj_status && obj_status[row_obj[r]] != 0)) continue;
+        float *dst = (o < 8 ? HY : MY) + r * ldo + kMT * li;
+        if (kMT == 1) {
+            dst[0] = (float)d[0][v];
+        } else if (kMT == 2) {
+            *(float2 *)dst = make_float2((float)d[0][v], (float)d[1][v]);
+        } else {
+            *(f32x4 *)dst = f32x4{(float)d[0][v], (float)d[1][v], (float)d[2][v], (float)d[3][v]};
+        }
+    }
+}
+
 bool hm8_ok(int m, int64_t ldy, int64_t ldo) { return t16_ok(m, ldy, ldo); }
 
 int spmm_hm8(ff_ctx *ctx, hipStream_t st, const RT8View &v, int sub, int m, const float *Y, int64_t ldy, float *HY,
@@ -2063,8 +2205,29 @@ int spmm_hm8(ff_ctx *ctx, hipStream_t st, const RT8View &v, int sub, int m, cons
 #define FF_HM8(MT, W, B, O, F)                                                                                \
     hipLaunchKernelGGL((spmm_hm8_kernel<MT, W, B, O, F>), dim3(grid_for(v.ntiles, W)), dim3(64 * W), 0, st, v.n, \
                        v.ntiles, v.tptr, v.tcol, v.vh, v.vm, Y, ldy, HY, MY, ldo, m, row_obj, status)
-    // sub 0..2: FP64 matrix cores; 3, 4: FP32 matrix cores with FP64 accumulation of each four-entry step
+#define FF_HM8P(MT, W, O, F)                                                                                  \
+    hipLaunchKernelGGL((spmm_hm8p_kernel<MT, W, O, F>), dim3(grid_for(v.ntiles, W)), dim3(64 * W), 0, st, v.n, \
+                       v.ntiles, v.tptr, v.tcol, v.vh, v.vm, Y, ldy, HY, MY, ldo, m, row_obj, status)
+    // sub 0..2: FP64 matrix cores; 3, 4: FP32 matrix cores with FP64 accumulation of each four-entry step;
+    // 5, 6: the pipelined kernel on the FP64 and the FP32 matrix cores; 7: the former with two waves per
+    // workgroup at m = 32 (as 5 at other widths)
+    FF_REQUIRE(ctx, sub >= 0 && sub < kHm8Subs, "launch shape %d out of range", sub);
     const int mt = m <= 16 ? 1 : m / 16;
+    if (sub >= 5) {
+        const bool f32p = sub == 6;
+        if (mt == 1) {
+            if (f32p) FF_HM8P(1, 4, 2, true); else FF_HM8P(1, 4, 2, false);
+        } else if (mt == 2) {
+            if (sub == 7) FF_HM8P(2, 2, 2, false);
+            else if (f32p) FF_HM8P(2, 4, 2, true);
+            else FF_HM8P(2, 4, 2, false);
+        } else {
+            if (f32p) FF_HM8P(4, 4, 2, true); else FF_HM8P(4, 4, 2, false);
+        }
+        FF_CHECK_LAUNCH(ctx);
+        return FF_OK;
+    }
+#undef FF_HM8P
     const bool f32 = sub >= 3;
     if (mt == 1) {
         if (f32) FF_HM8(1, 4, 8, 4, true); else FF_HM8(1, 4, 8, 4, false);

@@ -207,6 +207,7 @@ def test_spmm(oracle, ctx, ff, precision, m):
     refM = oracle.spmm(P.row_ptr, P.col, P.M, Y)
     absH = oracle.spmm(P.row_ptr, P.col, np.abs(P.H), np.abs(Y))
     absM = oracle.spmm(P.row_ptr, P.col, np.abs(P.M), np.abs(Y))
+    out = {}
     for v, name in enumerate(ff.spmm_variant_names()):
         if name.startswith("rowtile8_mfma") and (precision == 0 or m not in (8, 16, 32, 64)):
             # the eight-row FP64-MFMA variants take FP32 blocks of these widths only
@@ -217,6 +218,13 @@ def test_spmm(oracle, ctx, ff, precision, m):
         eps = 2e-6 if precision else 1e-13
         assert np.all(np.abs(host(HY) - refH) <= eps * absH + 1e-300), name
         assert np.all(np.abs(host(MY) - refM) <= eps * absM + 1e-300), name
+        out[name] = (host(HY), host(MY))
+    # the pipelined eight-row kernels issue the same matrix-core steps in the same order
+    for a, b in (("rowtile8_mfma64_pipelined_waves4", "rowtile8_mfma64_waves4_batch8"),
+                 ("rowtile8_mfma64_pipelined_waves2", "rowtile8_mfma64_waves4_batch8"),
+                 ("rowtile8_mfma32x64_pipelined_waves4", "rowtile8_mfma32x64_waves4_batch8")):
+        if a in out:
+            assert np.array_equal(out[a][0], out[b][0]) and np.array_equal(out[a][1], out[b][1]), (a, m)
 
 
 @pytest.mark.parametrize("precision", [0, 1])
