@@ -321,6 +321,70 @@ def _fp16_storage(H):
     return q.astype(np.float64) * 2.0 ** -e, e
 
 
+def _banded_csr(seed=5):
+    """A CSR whose row bands grow along the rows, so that eight-row tiles hold from a few to
+    several hundred union entries: rows 0-999 reach at most 4 columns either side, rows
+    1000-1399 40-59, rows 1400-1799 60-89, rows 1800-2199 90-159, the rest 160-399; n = 3001
+    leaves a ragged last tile."""
+    rng = np.random.default_rng(seed)
+    n = 3001
+    band = np.concatenate([rng.integers(0, 5, 1000), rng.integers(40, 60, 400), rng.integers(60, 90, 400),
+                           rng.integers(90, 160, 400), rng.integers(160, 400, n - 2200)])
+    cols = [np.arange(max(0, i - b), min(n, i + b + 1)) for i, b in enumerate(band)]
+    row_ptr = np.concatenate([[0], np.cumsum([len(c) for c in cols])]).astype(np.int64)
+    col = np.concatenate(cols).astype(np.int32)
+    H = rng.standard_normal(len(col))
+    M = rng.uniform(0.1, 1.0, len(col))
+    E = np.array([len(np.unique(col[row_ptr[t]:row_ptr[min(t + 8, n)]])) for t in range(0, n, 8)])
+    return n, row_ptr, col, H, M, E
+
+
+def test_rowtile_kernels_short_tiles(oracle, ctx, ff):
+    """The pipelined product kernels on tiles of every length, including the shortest tails
+    (one and two chunks of 64 entries for the fused [H, M] product, one and two super-blocks
+    of four K-blocks for the binary16 product): against the plain CSR product of the oracle,
+    and bitwise against the unpipelined kernels."""
+    n, row_ptr, col, H, M, E = _banded_csr()
+    chunks, superblocks = set(((E + 63) // 64).tolist()), set((((E + 15) // 16 + 3) // 4).tolist())
+    assert {1, 2, 3, 4, 5} <= chunks and {1, 2, 3, 4, 5} <= superblocks
+    rp, cl, Hd, Md = dev(row_ptr, torch.int64), dev(col, torch.int32), dev(H), dev(M)
+    hm32 = torch.stack([Hd.float(), Md.float()], dim=1).reshape(-1).contiguous()
+    names = ff.spmm_variant_names()
+    for m in (8, 32, 64):
+        Y = np.random.default_rng(m).standard_normal((n, m))
+        refH, refM = oracle.spmm(row_ptr, col, H, Y), oracle.spmm(row_ptr, col, M, Y)
+        absH = oracle.spmm(row_ptr, col, np.abs(H), np.abs(Y))
+        absM = oracle.spmm(row_ptr, col, np.abs(M), np.abs(Y))
+        out = {}
+        for v, name in enumerate(names):
+            if not name.startswith("rowtile8_mfma"):
+                continue
+            HY, MY = ff.spmm_hm(ctx, rp, cl, Hd, Md, hm32, dev(Y, torch.float32), 1, variant=v)
+            HY, MY = host(HY), host(MY)
+            assert np.all(np.abs(HY - refH) <= 2e-6 * absH + 1e-300), (name, m)
+            assert np.all(np.abs(MY - refM) <= 2e-6 * absM + 1e-300), (name, m)
+            out[name] = (HY, MY)
+        for a, b in (("rowtile8_mfma64_pipelined_waves4", "rowtile8_mfma64_waves4_batch8"),
+                     ("rowtile8_mfma64_pipelined_waves2", "rowtile8_mfma64_waves4_batch8"),
+                     ("rowtile8_mfma32x64_pipelined_waves4", "rowtile8_mfma32x64_waves4_batch8")):
+            assert np.array_equal(out[a][0], out[b][0]) and np.array_equal(out[a][1], out[b][1]), (a, m)
+    rt = ff.RowTiles(ctx, n, rp, cl, Hd, None, precision=6)
+    Hq, _ = _fp16_storage(H)
+    rl = np.diff(row_ptr)
+    eps = (8 * rl.max() + 8) * 2.0 ** -24
+    for m in (32, 64):
+        Y = np.random.default_rng(m).standard_normal((n, m)).astype(np.float16).astype(np.float64)
+        refq = oracle.spmm(row_ptr, col, Hq, Y)
+        absq = oracle.spmm(row_ptr, col, np.abs(Hq), np.abs(Y))
+        HO, _ = rt.spmm(dev(Y, torch.float16), 2, 0)
+        HO = host(HO)
+        assert np.all(np.abs(HO - refq) <= eps * absq + 1e-300), m
+        for sub in range(1, 8):
+            HS, _ = rt.spmm(dev(Y, torch.float16), 2, sub)
+            assert np.array_equal(host(HS), HO), (m, sub)
+    rt.close()
+
+
 def test_rowtiles_fp16_copy(oracle, ctx, ff):
     """The preconditioner's default copy: H in binary16 (scaled by a power of two) in
     tiles of eight rows, ragged last tile. Against H as stored it obeys the same FP32
