@@ -171,7 +171,9 @@ int rkpm_shape(ff_ctx *ctx, int64_t n, const double *xyz_sorted, int64_t q, cons
  *  hm32         [nnz_cap][2] device out or NULL: FP32 copies (H, M) interleaved
  *  nnz          host out
  * The sizing call (col NULL) fills row_ptr and nnz and keeps its symbolic
- * state (transposed lists, row lengths) in the context; the next call on the
+ * state (transposed lists, row lengths, and each row's column bitmap over its
+ * candidate window, 2 KiB per row up to 8 GiB, which the numeric pass then
+ * reads instead of rebuilding) in the context; the next call on the
  * context, if it passes the same nbr_off, nbr_id, grid dimensions,
  * cell_start, row_ptr and sizes (compared by address and value, the arrays
  * left unmodified in between), reuses that state instead of recomputing it.

@@ -127,6 +127,9 @@ int ff_ctx_create(ff_ctx **out, int device, void *hip_stream) {
     ctx->verbose = v && v[0] == '1';
     // a cap on the LDS bitmap of the tile-copy build, so that its other paths can be exercised
     if (const char *b = getenv("FF_UNION_BITS")) ctx->union_bits = atoi(b) < 0 ? 0 : atoi(b);
+    // a cap on the row bitmaps the assembly's symbolic pass keeps, so that the numeric pass's own
+    // marking can be exercised
+    if (const char *b = getenv("FF_ASM_BITMAP_BYTES")) ctx->asm_bm_cap = atoll(b) < 0 ? 0 : atoll(b);
     *out = ctx;
     return FF_OK;
 }

@@ -21,7 +21,7 @@ namespace ff {
 // Workspace slots: each names one reusable device buffer owned by the context.
 enum WsSlot {
     WS_BBOX = 0, WS_KEYS, WS_COUNTS, WS_CURSOR, WS_CELLS, WS_SCAN, WS_FLAG,
-    WS_NT_OFF, WS_NT, WS_ROWLEN, WS_ASM_FLAG, WS_ZYN, WS_ZYE,
+    WS_NT_OFF, WS_NT, WS_ROWLEN, WS_ASM_FLAG, WS_ZYN, WS_ZYE, WS_ASM_BM,
     WS_S0, WS_S1, WS_HS0, WS_HS1, WS_MS0, WS_MS1,            // working precision blocks
     WS_D0, WS_D1, WS_HD0, WS_HD1, WS_MD0, WS_MD1,            // FP64 blocks of the mixed path
     WS_GPART, WS_G, WS_C, WS_C32, WS_THETA, WS_RPART, WS_RES, WS_STATE, WS_RRSCR,
@@ -64,6 +64,8 @@ struct ff_ctx {
     int64_t asm_size[5] = {};
     int64_t asm_nnz = 0;
     int asm_rowmax = 0;
+    bool asm_bm = false;             // the sizing call kept its row bitmaps (workspace slot WS_ASM_BM)
+    int64_t asm_bm_cap = -1;         // FF_ASM_BITMAP_BYTES: cap on that store (-1: the built-in 8 GiB)
     hipStream_t graph_stream = nullptr;   // private stream for graph capture
 };
 

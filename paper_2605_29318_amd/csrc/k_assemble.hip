@@ -22,6 +22,7 @@ namespace {
 
 constexpr int kWinMax = 16384;                 // candidate nodes per row window
 constexpr int kWinWords = kWinMax / 32;
+constexpr size_t kBitmapBytes = (size_t)8 << 30;  // largest store of the symbolic pass's row bitmaps
 constexpr int kRowMax = 2048;                  // entries per row
 
 struct GridI {
@@ -270,7 +271,7 @@ __global__ void __launch_bounds__(256) nt_sort_kernel(const int64_t *nt_off, int
 
 __global__ void __launch_bounds__(256) sym_kernel(int64_t n, const int64_t *cs, GridI g, const int64_t *nt_off,
                                                   const int2 *nt, const int64_t *off, const int32_t *ids,
-                                                  const uint32_t *zys, int32_t *rowlen, int *stats) {
+                                                  const uint32_t *zys, int32_t *rowlen, int *stats, uint32_t *bm_out) {
     __shared__ Win wins[4];
     __shared__ uint32_t bms[4][kWinWords];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -290,6 +291,8 @@ __global__ void __launch_bounds__(256) sym_kernel(int64_t n, const int64_t *cs, 
     mark_row(k, nt_off, nt, off, ids, zys, win, bm, nwords);
     int c = 0;
     for (int w = lane; w < nwords; w += 64) c += __popc(bm[w]);
+    if (bm_out)                                    // kept for the numeric pass (row stride kWinWords)
+        for (int w = lane; w < nwords; w += 64) bm_out[k * kWinWords + w] = bm[w];
     c = wave_sum_i32(c);
     if (lane == 0) {
         rowlen[k] = c;
@@ -307,7 +310,8 @@ __global__ void __launch_bounds__(256) num_kernel(int64_t n, const int64_t *cs, 
                                                   const double *phi, const double *dphi, const double *vol,
                                                   const double *lam, const double *mu, const double *rho,
                                                   const int32_t *perm, const int64_t *row_ptr, int32_t *col,
-                                                  double *H, double *M, float *hm32, int rmax, int per_wave) {
+                                                  double *H, double *M, float *hm32, int rmax, int per_wave,
+                                                  const uint32_t *bm_in) {
     extern __shared__ __align__(16) char smem[];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -321,7 +325,12 @@ __global__ void __launch_bounds__(256) num_kernel(int64_t n, const int64_t *cs, 
 
     const int64_t W = build_window(k, cs, g, win);
     const int nwords = (int)((W + 31) >> 5);
-    mark_row(k, nt_off, nt, off, ids, zys, win, bm, nwords);
+    if (bm_in) {                                   // the symbolic pass's bitmap of this row
+        for (int w = lane; w < nwords; w += 64) bm[w] = bm_in[k * kWinWords + w];
+        __builtin_amdgcn_wave_barrier();
+    } else {
+        mark_row(k, nt_off, nt, off, ids, zys, win, bm, nwords);
+    }
 
     // exclusive prefix of popcounts over the bitmap words
     int carry = 0;
@@ -491,9 +500,13 @@ extern "C" int assemble_HM(ff_ctx *ctx, int64_t n, int64_t q, const int64_t *nbr
     int rowmax = 0;
     FF_REQUIRE(ctx, grid->dims[1] < 65536 && grid->dims[2] < 65536, "grid of %d x %d x %d cells too large",
                grid->dims[0], grid->dims[1], grid->dims[2]);
+    // each row's column bitmap from the symbolic pass, so that the numeric pass need not mark it again
+    // (kWinWords words per row; left out beyond kBitmapBytes, where the numeric pass marks it itself)
+    uint32_t *bm = nullptr;
     if (reuse) {
         nt = (int2 *)ctx->ws[WS_NT];
         zys = (uint32_t *)ctx->ws[WS_ZYE];
+        bm = ctx->asm_bm ? (uint32_t *)ctx->ws[WS_ASM_BM] : nullptr;
         *nnz = ctx->asm_nnz;
         rowmax = ctx->asm_rowmax;
         if (nnz_cap < *nnz)
@@ -537,8 +550,13 @@ extern "C" int assemble_HM(ff_ctx *ctx, int64_t n, int64_t q, const int64_t *nbr
         hipLaunchKernelGGL(nt_sort_kernel, dim3(grid_for(n, 4)), dim3(256), 0, st, nt_off, n, nt, empty_node);
         FF_CHECK_LAUNCH(ctx);
 
+        const size_t bm_bytes = (size_t)n * kWinWords * sizeof(uint32_t);
+        if (bm_bytes <= (ctx->asm_bm_cap >= 0 ? (size_t)ctx->asm_bm_cap : kBitmapBytes)) {
+            bm = (uint32_t *)ws_get(ctx, WS_ASM_BM, bm_bytes);
+            if (!bm) ctx->last_error.clear();          // without it the numeric pass marks the rows itself
+        }
         hipLaunchKernelGGL(sym_kernel, dim3(grid_for(n, 4)), dim3(256), 0, st, n, cell_start, g, nt_off, nt, nbr_off,
-                           nbr_id, zys, rowlen, stats);
+                           nbr_id, zys, rowlen, stats, bm);
         FF_CHECK_LAUNCH(ctx);
         rc = scan_exclusive_i32_to_i64(ctx, rowlen, row_ptr, n);
         if (rc) return rc;
@@ -560,6 +578,7 @@ extern "C" int assemble_HM(ff_ctx *ctx, int64_t n, int64_t q, const int64_t *nbr
             for (int i = 0; i < 5; ++i) ctx->asm_size[i] = key_size[i];
             ctx->asm_nnz = host[0];
             ctx->asm_rowmax = rowmax;
+            ctx->asm_bm = bm != nullptr;
             return FF_OK;
         }
         if (nnz_cap < host[0])
@@ -574,7 +593,7 @@ extern "C" int assemble_HM(ff_ctx *ctx, int64_t n, int64_t q, const int64_t *nbr
     const size_t shmem = (size_t)waves * per_wave;
     hipLaunchKernelGGL(num_kernel, dim3(grid_for(n, waves)), dim3(64 * waves), shmem, st, n, cell_start, g, nt_off,
                        nt, nbr_off, nbr_id, zys, phi, dphi, vol, lam, mu, rho, perm, row_ptr, col, H, M, hm32,
-                       rmax, per_wave);
+                       rmax, per_wave, bm);
     FF_CHECK_LAUNCH(ctx);
     return FF_OK;
 }

@@ -157,6 +157,27 @@ def test_assembly_sizing_state_reuse(oracle, ctx, ff):
         assert ei.value.code == ff.FF_ERR_CAPACITY
 
 
+def test_assembly_without_stored_bitmaps(oracle, ctx, ff):
+    """The numeric pass reads each row's column bitmap kept by the symbolic pass, or, where
+    that store would be too large (FF_ASM_BITMAP_BYTES=0 here), marks the rows itself: the
+    same CSR bit for bit, and the oracle's."""
+    import os
+    c = synth.random_cloud(2100, seed=61, hetero=True)
+    A = ff.assemble_cloud(ctx, dev(c.xyz), dev(c.vol), dev(c.lam), dev(c.mu), c.h)
+    os.environ["FF_ASM_BITMAP_BYTES"] = "0"
+    try:
+        ctx2 = ff.Context(0)
+    finally:
+        del os.environ["FF_ASM_BITMAP_BYTES"]
+    B = ff.assemble_cloud(ctx2, dev(c.xyz), dev(c.vol), dev(c.lam), dev(c.mu), c.h)
+    for x, y in ((A.row_ptr, B.row_ptr), (A.col, B.col), (A.H, B.H), (A.M, B.M)):
+        assert torch.equal(x, y)
+    P = oracle.pipeline(c)
+    assert np.array_equal(host(B.col), P.col)
+    assert np.abs(host(B.H) - P.H).max() <= 1e-12 * np.abs(P.H).max()
+    ctx2.close()
+
+
 def test_separate_quadrature_points(oracle, ctx, ff):
     c = synth.random_cloud(2000, seed=14)
     rng = np.random.default_rng(3)
