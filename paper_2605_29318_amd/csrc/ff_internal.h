@@ -64,6 +64,7 @@ struct ff_ctx {
     int64_t asm_size[5] = {};
     int64_t asm_nnz = 0;
     int asm_rowmax = 0;
+    int asm_wwords = 0;              // largest row window of that call, in bitmap words
     bool asm_bm = false;             // the sizing call kept its row bitmaps (workspace slot WS_ASM_BM)
     int64_t asm_bm_cap = -1;         // FF_ASM_BITMAP_BYTES: cap on that store (-1: the built-in 8 GiB)
     hipStream_t graph_stream = nullptr;   // private stream for graph capture

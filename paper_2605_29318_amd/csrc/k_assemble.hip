@@ -23,6 +23,7 @@ namespace {
 constexpr int kWinMax = 16384;                 // candidate nodes per row window
 constexpr int kWinWords = kWinMax / 32;
 constexpr size_t kBitmapBytes = (size_t)8 << 30;  // largest store of the symbolic pass's row bitmaps
+constexpr int kLdsPerCu = 160 * 1024;
 constexpr int kRowMax = 2048;                  // entries per row
 
 struct GridI {
@@ -293,6 +294,7 @@ __global__ void __launch_bounds__(256) sym_kernel(int64_t n, const int64_t *cs, 
     for (int w = lane; w < nwords; w += 64) c += __popc(bm[w]);
     if (bm_out)                                    // kept for the numeric pass (row stride kWinWords)
         for (int w = lane; w < nwords; w += 64) bm_out[k * kWinWords + w] = bm[w];
+    if (lane == 0) atomicMax(&stats[2], nwords);
     c = wave_sum_i32(c);
     if (lane == 0) {
         rowlen[k] = c;
@@ -311,7 +313,7 @@ __global__ void __launch_bounds__(256) num_kernel(int64_t n, const int64_t *cs, 
                                                   const double *lam, const double *mu, const double *rho,
                                                   const int32_t *perm, const int64_t *row_ptr, int32_t *col,
                                                   double *H, double *M, float *hm32, int rmax, int per_wave,
-                                                  const uint32_t *bm_in) {
+                                                  int wwords, const uint32_t *bm_in) {
     extern __shared__ __align__(16) char smem[];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -321,7 +323,7 @@ __global__ void __launch_bounds__(256) num_kernel(int64_t n, const int64_t *cs, 
     double *aM = aH + rmax;
     Win *win = (Win *)(aM + rmax);
     uint32_t *bm = (uint32_t *)(win + 1);
-    int32_t *pre = (int32_t *)(bm + kWinWords);
+    int32_t *pre = (int32_t *)(bm + wwords);       // wwords: the largest row window, in bitmap words
 
     const int64_t W = build_window(k, cs, g, win);
     const int nwords = (int)((W + 31) >> 5);
@@ -497,7 +499,7 @@ extern "C" int assemble_HM(ff_ctx *ctx, int64_t n, int64_t q, const int64_t *nbr
     if (!nt_off) return FF_ERR_OOM;
     int2 *nt = nullptr;
     uint32_t *zys = nullptr;                       // (z << 16) | y of each neighbour entry's cell
-    int rowmax = 0;
+    int rowmax = 0, wwords = 0;
     FF_REQUIRE(ctx, grid->dims[1] < 65536 && grid->dims[2] < 65536, "grid of %d x %d x %d cells too large",
                grid->dims[0], grid->dims[1], grid->dims[2]);
     // each row's column bitmap from the symbolic pass, so that the numeric pass need not mark it again
@@ -509,6 +511,7 @@ extern "C" int assemble_HM(ff_ctx *ctx, int64_t n, int64_t q, const int64_t *nbr
         bm = ctx->asm_bm ? (uint32_t *)ctx->ws[WS_ASM_BM] : nullptr;
         *nnz = ctx->asm_nnz;
         rowmax = ctx->asm_rowmax;
+        wwords = ctx->asm_wwords;
         if (nnz_cap < *nnz)
             return set_error(ctx, FF_ERR_CAPACITY, "CSR needs %lld entries, capacity %lld", (long long)*nnz,
                              (long long)nnz_cap);
@@ -572,12 +575,14 @@ extern "C" int assemble_HM(ff_ctx *ctx, int64_t n, int64_t q, const int64_t *nbr
         FF_REQUIRE(ctx, hs[1] <= kRowMax, "a row has %d entries (limit %d); decrease h", hs[1], kRowMax);
         *nnz = host[0];
         rowmax = hs[1];
+        wwords = hs[2];
         if (!col) {
             ctx->asm_valid = true;
             for (int i = 0; i < 4; ++i) ctx->asm_ptr[i] = key_ptr[i];
             for (int i = 0; i < 5; ++i) ctx->asm_size[i] = key_size[i];
             ctx->asm_nnz = host[0];
             ctx->asm_rowmax = rowmax;
+            ctx->asm_wwords = wwords;
             ctx->asm_bm = bm != nullptr;
             return FF_OK;
         }
@@ -587,13 +592,19 @@ extern "C" int assemble_HM(ff_ctx *ctx, int64_t n, int64_t q, const int64_t *nbr
     }
 
     const int rmax = ((rowmax + 63) / 64) * 64;
-    const int per_wave = (int)(((size_t)2 * rmax * sizeof(double) + sizeof(Win) + kWinWords * 8 + 255) & ~255);
-    int waves = 4;
-    while (waves > 1 && waves * per_wave > 64 * 1024) waves >>= 1;
+    // LDS per wave: the row's FP64 accumulators, the window, its bitmap and prefix sized to the largest
+    // window; waves per workgroup (4, 2 or 1, at most 64 KiB) for the most waves per CU
+    const int per_wave = (int)(((size_t)2 * rmax * sizeof(double) + sizeof(Win) + (size_t)wwords * 8 + 255) & ~255);
+    int waves = 1, best = 0;
+    for (int w = 4; w >= 1; w >>= 1) {
+        if (w * per_wave > 64 * 1024) continue;
+        const int per_cu = w * std::min(kLdsPerCu / (w * per_wave), 32 / w);
+        if (per_cu > best) best = per_cu, waves = w;
+    }
     const size_t shmem = (size_t)waves * per_wave;
     hipLaunchKernelGGL(num_kernel, dim3(grid_for(n, waves)), dim3(64 * waves), shmem, st, n, cell_start, g, nt_off,
                        nt, nbr_off, nbr_id, zys, phi, dphi, vol, lam, mu, rho, perm, row_ptr, col, H, M, hm32,
-                       rmax, per_wave, bm);
+                       rmax, per_wave, wwords, bm);
     FF_CHECK_LAUNCH(ctx);
     return FF_OK;
 }
