@@ -294,11 +294,15 @@ __global__ void __launch_bounds__(256) sym_kernel(int64_t n, const int64_t *cs, 
     for (int w = lane; w < nwords; w += 64) c += __popc(bm[w]);
     if (bm_out)                                    // kept for the numeric pass (row stride kWinWords)
         for (int w = lane; w < nwords; w += 64) bm_out[k * kWinWords + w] = bm[w];
-    if (lane == 0) atomicMax(&stats[2], nwords);
+    // maxima over the rows: the atomic only when a plain read shows a smaller value (the maxima only
+    // grow, so a stale read costs an atomic, never a missed update); a million contended atomics on
+    // one address cost about as much as the pass itself
+    if (lane == 0 && nwords > __hip_atomic_load(&stats[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        atomicMax(&stats[2], nwords);
     c = wave_sum_i32(c);
     if (lane == 0) {
         rowlen[k] = c;
-        atomicMax(&stats[1], c);
+        if (c > __hip_atomic_load(&stats[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(&stats[1], c);
     }
 }
 
