@@ -393,63 +393,55 @@ __global__ void __launch_bounds__(256) num_kernel(int64_t n, const int64_t *cs, 
             qw = vol[ii] * (lam[ii] + 4.0 * mu[ii]);
             qm = rho ? vol[ii] * rho[ii] : vol[ii];
         }
-        // first 64 neighbours of an entry, requested ahead
-        struct Pre { int32_t id; uint32_t zy; double d0, d1, d2, p; };
-        auto fetch = [&](int j, Pre &P) {
+        // first 128 neighbours of an entry, requested ahead without a branch: lanes past the end of
+        // N(i) (never empty: it holds k) load its last neighbour, which accumulate() does not use; the
+        // scheduling barriers keep the loads together and their first use in accumulate()
+        struct Pre { int32_t id[2]; uint32_t zy[2]; double d0[2], d1[2], d2[2], p[2]; };
+        auto fetch = [&](int j, Pre &P) __attribute__((always_inline)) {
             const int64_t s0 = __shfl(f0, j, 64), s1 = __shfl(f1, j, 64);
-            const int64_t f = s0 + lane;
-            P.id = -1;
-            P.zy = 0u;
-            P.d0 = P.d1 = P.d2 = P.p = 0.0;
-            if (f < s1) {
-                P.id = ids[f];
-                P.zy = zys[f];
-                P.d0 = dphi[3 * f];
-                P.d1 = dphi[3 * f + 1];
-                P.d2 = dphi[3 * f + 2];
-                P.p = phi[f];
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {                 // neighbours lane and 64 + lane
+                const int64_t f = s0 + 64 * h + lane < s1 ? s0 + 64 * h + lane : s1 - 1;
+                P.id[h] = ids[f];
+                P.zy[h] = zys[f];
+                P.d0[h] = dphi[3 * f];
+                P.d1[h] = dphi[3 * f + 1];
+                P.d2[h] = dphi[3 * f + 2];
+                P.p[h] = phi[f];
             }
+            __builtin_amdgcn_sched_barrier(0);
         };
         auto accumulate = [&](int j, const Pre &P) {
             const int64_t s0 = __shfl(f0, j, 64), s1 = __shfl(f1, j, 64);
             const double gk0 = __shfl(q0, j, 64), gk1 = __shfl(q1, j, 64), gk2 = __shfl(q2, j, 64);
             const double pk = __shfl(qp, j, 64), wi = __shfl(qw, j, 64), mi = __shfl(qm, j, 64);
-            for (int64_t f = s0 + lane; f < s1; f += 64) {
-                int32_t id;
-                uint32_t zy;
-                double d0, d1, d2, pf;
-                if (f == s0 + lane) {
-                    id = P.id;
-                    zy = P.zy;
-                    d0 = P.d0;
-                    d1 = P.d1;
-                    d2 = P.d2;
-                    pf = P.p;
-                } else {
-                    id = ids[f];
-                    zy = zys[f];
-                    d0 = dphi[3 * f];
-                    d1 = dphi[3 * f + 1];
-                    d2 = dphi[3 * f + 2];
-                    pf = phi[f];
-                }
+            auto term = [&](int32_t id, uint32_t zy, double d0, double d1, double d2, double pf)
+                            __attribute__((always_inline)) {
                 const int x = local_of_zy(id, zy, win);
-                if (x < 0 || x >= wend) continue;
+                if (x < 0 || x >= wend) return;
                 const uint32_t word = bm[x >> 5];
                 const int r = pre[x >> 5] + __popc(word & ((1u << (x & 31)) - 1u));
                 const double dot = ((gk0 * d0) + (gk1 * d1)) + (gk2 * d2);
                 aH[r] += wi * dot;
                 aM[r] += mi * (pk * pf);
-            }
+            };
+#pragma unroll
+            for (int h = 0; h < 2; ++h)                  // the first 128, requested ahead
+                if (s0 + 64 * h + lane < s1) term(P.id[h], P.zy[h], P.d0[h], P.d1[h], P.d2[h], P.p[h]);
+            for (int64_t f = s0 + 128 + lane; f < s1; f += 64)           // the rest of a longer N(i)
+                term(ids[f], zys[f], dphi[3 * f], dphi[3 * f + 1], dphi[3 * f + 2], phi[f]);
             __builtin_amdgcn_wave_barrier();
         };
+        // entry j + 1's neighbours are requested before entry j is accumulated (the last entry's
+        // are requested again at the end rather than behind a branch)
         Pre PA, PB;
         fetch(0, PA);
         for (int j = 0; j < cnt; j += 2) {
-            if (j + 1 < cnt) fetch(j + 1, PB);
+            fetch(j + 1 < cnt ? j + 1 : cnt - 1, PB);
             accumulate(j, PA);
             if (j + 1 >= cnt) break;
-            if (j + 2 < cnt) fetch(j + 2, PA);
+            fetch(j + 2 < cnt ? j + 2 : cnt - 1, PA);
             accumulate(j + 1, PB);
         }
     }
