@@ -187,23 +187,33 @@ __global__ void __launch_bounds__(kUnionThreads) tile_union_kernel(int64_t nrows
     if (t >= ntiles) return;
     const int tid = threadIdx.x;
     const int64_t r0 = t * R;
-    if (tid == 0) {
-        int acc = 0;
+    if (tid < 64) {                                // lane r reads row r's range and end columns at once
+        const bool in = tid < R && r0 + tid < nrows;
+        const int64_t b = in ? row_ptr[r0 + tid] : 0, e = in ? row_ptr[r0 + tid + 1] : 0;
+        const int len = (int)(e - b);
         int32_t lo = INT_MAX, hi = -1;
-        for (int r = 0; r < R; ++r) {
-            const bool in = r0 + r < nrows;
-            const int64_t b = in ? row_ptr[r0 + r] : 0, e = in ? row_ptr[r0 + r + 1] : 0;
-            gs[r] = b;
-            rs[r] = acc;
-            acc += (int)(e - b);
-            if (e > b) {
-                lo = min(lo, col[b]);
-                hi = max(hi, col[e - 1]);
-            }
+        if (e > b) {
+            lo = col[b];
+            hi = col[e - 1];
         }
-        rs[R] = acc;
-        crange[0] = lo;
-        crange[1] = hi;
+        int incl = len;                            // row starts: inclusive scan over the R lanes
+        for (int d = 1; d < R; d <<= 1) {
+            const int u = __shfl_up(incl, d, 64);
+            if (tid >= d) incl += u;
+        }
+        for (int d = 1; d < 64; d <<= 1) {
+            lo = min(lo, __shfl_xor(lo, d, 64));
+            hi = max(hi, __shfl_xor(hi, d, 64));
+        }
+        if (tid < R) {
+            gs[tid] = b;
+            rs[tid] = incl - len;
+        }
+        if (tid == R - 1) rs[R] = incl;
+        if (tid == 0) {
+            crange[0] = lo;
+            crange[1] = hi;
+        }
     }
     __syncthreads();
     const int E = rs[R];
@@ -219,10 +229,22 @@ __global__ void __launch_bounds__(kUnionThreads) tile_union_kernel(int64_t nrows
         int32_t *pre = lds + bits;                 // [bits] set bits in the words before
         for (int w = tid; w < nw; w += kUnionThreads) bm[w] = 0u;
         __syncthreads();
-        for (int x = tid; x < E; x += kUnionThreads) {
-            const int r = row_of(x);
-            const int b = col[gs[r] + (x - rs[r])] - cmin;
-            atomicOr(&bm[b >> 5], 1u << (b & 31));
+        // four entries per thread per pass, their columns loaded before any is used (an index past
+        // E reads entry E - 1 and marks nothing)
+        for (int x0 = tid; x0 < E; x0 += 4 * kUnionThreads) {
+            int32_t c[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int x = min(x0 + u * kUnionThreads, E - 1);
+                const int r = row_of(x);
+                c[u] = col[gs[r] + (x - rs[r])];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (x0 + u * kUnionThreads < E) {
+                    const int b = c[u] - cmin;
+                    atomicOr(&bm[b >> 5], 1u << (b & 31));
+                }
         }
         __syncthreads();
         const int per = (nw + kUnionThreads - 1) / kUnionThreads;
@@ -257,15 +279,28 @@ __global__ void __launch_bounds__(kUnionThreads) tile_union_kernel(int64_t nrows
             if (vm) *(f32x4 *)(vm + o * R + 4 * i) = f32x4{0.f, 0.f, 0.f, 0.f};
         }
         __syncthreads();
-        for (int x = tid; x < E; x += kUnionThreads) {
-            const int r = row_of(x);
-            const int64_t g = gs[r] + (x - rs[r]);
-            const int32_t c = col[g];
-            const int b = c - cmin;
-            const int rank = pre[b >> 5] + __popc(bm[b >> 5] & ((1u << (b & 31)) - 1u));
-            tcol[o + rank] = c;
-            vh[(o + rank) * R + r] = (float)H[g];
-            if (vm) vm[(o + rank) * R + r] = (float)M[g];
+        for (int x0 = tid; x0 < E; x0 += 4 * kUnionThreads) {   // as above: loads first
+            int32_t c[4];
+            double hv[4], mv[4];
+            int rr[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int x = min(x0 + u * kUnionThreads, E - 1);
+                rr[u] = row_of(x);
+                const int64_t g = gs[rr[u]] + (x - rs[rr[u]]);
+                c[u] = col[g];
+                hv[u] = H[g];
+                mv[u] = vm ? M[g] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (x0 + u * kUnionThreads < E) {
+                    const int b = c[u] - cmin;
+                    const int rank = pre[b >> 5] + __popc(bm[b >> 5] & ((1u << (b & 31)) - 1u));
+                    tcol[o + rank] = c[u];
+                    vh[(o + rank) * R + rr[u]] = (float)hv[u];
+                    if (vm) vm[(o + rank) * R + rr[u]] = (float)mv[u];
+                }
         }
         return;
     }
