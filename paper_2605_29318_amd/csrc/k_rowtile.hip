@@ -1124,6 +1124,31 @@ spmm_t8_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int32_t
             t8_chunk<V, kBatch, 1>(ca, base, e1, tcol, vh, sv, lane, g, c, NG, steps, Y, ldy, acc);
     }
     if (kEpi && !kPre && mine) epi_load();
+    if (!kEpi && G == 1) {
+        // m = 8: the sum over the 64 lanes as a reduce-scatter. Step d (1, 2, .., 32, the order of the
+        // butterfly below) halves each lane's set, the lanes with bit d set keeping the upper half, so
+        // every element is the butterfly's sum bit for bit (the same pairs in the same order); lane l
+        // ends with element k = bit-reverse6(l) of the 8 x 8 block, row k / 8 and column k % 8
+        float v[64];
+#pragma unroll
+        for (int i = 0; i < kTile8; ++i)
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[8 * i + q] = acc[i][q];
+#pragma unroll
+        for (int st = 0, h = 32; st < 6; ++st, h >>= 1) {
+            const int d = 1 << st;
+            const bool up = (lane & d) != 0;
+#pragma unroll
+            for (int k = 0; k < h; ++k) {
+                const float keep = up ? v[k + h] : v[k], send = up ? v[k] : v[k + h];
+                v[k] = keep + __shfl_xor(send, d, 64);
+            }
+        }
+        const int k = (int)(__builtin_bitreverse32((uint32_t)lane) >> 26);
+        const int64_t r = r0 + (k >> 3);
+        if (r < nrows && (!obj_status || obj_status[row_obj[r]] == 0)) HY[r * ldo + (k & 7)] = v[0] * vscale;
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < kTile8; ++i)
         for (int d = G; d < 64; d <<= 1)
