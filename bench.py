@@ -65,12 +65,16 @@ def kernel_source_hash():
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
-def cheb_step_bytes(nnz, n, m, value_bytes=2, iter_bytes=2):
+def cheb_step_bytes(nnz, n, m, value_bytes=2, iter_bytes=2, degree=12):
     """Algorithmic HBM bytes of one Chebyshev step launch (m columns), independent of the
-    tiling: the H value (binary16, value_bytes) and int32 column of every nonzero, the row
-    pointers, D^-1 and the row's object index, the iterate DZ (binary16, iter_bytes) read
-    once and the next one written, R (FP32) read and written, W (FP32) read and written."""
-    return nnz * (value_bytes + 4) + 8 * (n + 1) + n * (4 + 4) + n * m * (2 * iter_bytes + 4 * 4)
+    tiling, averaged over the degree - 1 steps of one application: the H value (binary16,
+    value_bytes) and int32 column of every nonzero, the row pointers, D^-1 and the row's
+    object index, the iterate DZ (binary16, iter_bytes) read once and the next one written,
+    R (FP32) read and written, and W (FP32) read and written at ceil((degree - 1) / 2) of the
+    steps (every second step adds two iterates, the last step its own when the count is odd)."""
+    steps = degree - 1
+    w_frac = ((steps + 1) // 2) / steps
+    return nnz * (value_bytes + 4) + 8 * (n + 1) + n * (4 + 4) + n * m * (2 * iter_bytes + 8 + 8 * w_frac)
 
 
 def spmm_hm_bytes(nnz, n, m):
@@ -258,7 +262,7 @@ def main():
     spmm_ms, spmm_n = stages["spmm"]
     cheb_avg = cheb_ms / max(cheb_n, 1)
     spmm_avg = spmm_ms / max(spmm_n, 1)
-    cheb_alg = cheb_step_bytes(nnz, c.n, m)
+    cheb_alg = cheb_step_bytes(nnz, c.n, m, degree=PRECOND_DEGREE or 12)
     spmm_alg = spmm_hm_bytes(nnz, c.n, m)
     achieved = cheb_alg / (cheb_avg * 1e-3) / 1e9
     spmm_gbps = spmm_alg / (spmm_avg * 1e-3) / 1e9

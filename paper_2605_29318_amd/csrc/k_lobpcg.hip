@@ -2181,6 +2181,8 @@ int stage_precond(Solver &s, T *S) {
             cs.W = (float *)(S + s.m);
             cs.ldw = ld;
             cs.dz_out = q16[step & 1];
+            // W gathers two steps' iterates at every even step (and the last one's when it is odd)
+            cs.wmode = (step & 1) == 0 ? 2 : (step == s.cheb - 1 ? 1 : 0);
             const int rc = rt::cheb_step_tq(s.ctx, s.st, s.rtq, cheb_tq_sub(s.m), s.m, q16[(step - 1) & 1], s.row_obj,
                                             s.status, cs);
             if (rc) return rc;

@@ -103,7 +103,9 @@ int build_tq_fill(ff_ctx *ctx, hipStream_t st, const RT8View &v8, const int64_t 
 // block widths the matrix-core kernels take: m in {32, 64}
 bool tq_ok(int m);
 // one Chebyshev step, binary16 iterate: R -= D^-1 H DZ, DZ' = f1 DZ + f2 R (stored in binary16),
-// W += DZ'; DZ and dz_out are [rows][m], R has leading dimension m, W ldw
+// and by wmode: 1 W += DZ', 0 W untouched, 2 W += DZ + DZ' (the previous step's DZ' with this one's,
+// so that W is read and written every other step); DZ and dz_out are [rows][m], R has leading
+// dimension m, W ldw
 struct ChebStepQ {
     const double *coef = nullptr;
     int stride = 0, step = 0;
@@ -111,6 +113,7 @@ struct ChebStepQ {
     float *R = nullptr, *W = nullptr;
     uint16_t *dz_out = nullptr;
     int64_t ldw = 0;
+    int wmode = 1;
 };
 // sub selects a launch shape (waves per block, K-blocks in flight), 0 .. kTqSubs - 1
 constexpr int kTqSubs = 8;

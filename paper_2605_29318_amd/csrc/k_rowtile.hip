@@ -1534,7 +1534,8 @@ spmm_tq_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int32_t
         for (int cb = 0; cb < kMB; ++cb) {
             const int c0 = 16 * cb + 4 * quad;
             float *rp = cs.R + rme * m + c0, *wp = cs.W + rme * cs.ldw + c0;
-            const f32x4 er = *(const f32x4 *)rp, ew = *(const f32x4 *)wp;
+            const f32x4 er = *(const f32x4 *)rp;
+            const f32x4 ew = cs.wmode ? *(const f32x4 *)wp : f32x4{0.f, 0.f, 0.f, 0.f};
             const f16x4 ez = *(const f16x4 *)(Y + rme * m + c0);
             f32x4 rv1, w1;
             f16x4 dz1;
@@ -1545,11 +1546,12 @@ spmm_tq_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int32_t
                 dz = dz > 65504.0 ? 65504.0 : (dz < -65504.0 ? -65504.0 : dz);   // binary16 range
                 rv1[q] = (float)rv;
                 dz1[q] = (_Float16)(float)dz;
-                w1[q] = (float)((double)ew[q] + (double)(float)dz1[q]);
+                w1[q] = cs.wmode == 2 ? (float)(((double)ew[q] + (double)(float)ez[q]) + (double)(float)dz1[q])
+                                      : (float)((double)ew[q] + (double)(float)dz1[q]);
             }
             *(f32x4 *)rp = rv1;
             *(f16x4 *)(dzo + rme * m + c0) = dz1;
-            *(f32x4 *)wp = w1;
+            if (cs.wmode) *(f32x4 *)wp = w1;
         }
     } else {
 #pragma unroll
@@ -1680,7 +1682,8 @@ spmm_tq_sb_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int3
         for (int cb = 0; cb < kMB; ++cb) {
             const int c0 = 16 * cb + 4 * quad;
             float *rp = cs.R + rme * m + c0, *wp = cs.W + rme * cs.ldw + c0;
-            const f32x4 er = *(const f32x4 *)rp, ew = *(const f32x4 *)wp;
+            const f32x4 er = *(const f32x4 *)rp;
+            const f32x4 ew = cs.wmode ? *(const f32x4 *)wp : f32x4{0.f, 0.f, 0.f, 0.f};
             const f16x4 ez = *(const f16x4 *)(Y + rme * m + c0);
             f32x4 rv1, w1;
             f16x4 dz1;
@@ -1691,11 +1694,12 @@ spmm_tq_sb_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int3
                 dz = dz > 65504.0 ? 65504.0 : (dz < -65504.0 ? -65504.0 : dz);   // binary16 range
                 rv1[q] = (float)rv;
                 dz1[q] = (_Float16)(float)dz;
-                w1[q] = (float)((double)ew[q] + (double)(float)dz1[q]);
+                w1[q] = cs.wmode == 2 ? (float)(((double)ew[q] + (double)(float)ez[q]) + (double)(float)dz1[q])
+                                      : (float)((double)ew[q] + (double)(float)dz1[q]);
             }
             *(f32x4 *)rp = rv1;
             *(f16x4 *)(dzo + rme * m + c0) = dz1;
-            *(f32x4 *)wp = w1;
+            if (cs.wmode) *(f32x4 *)wp = w1;
         }
     } else {
 #pragma unroll
