@@ -1876,6 +1876,7 @@ constexpr int kDefaultVariant64 = 14;  // fastest untuned FP64 choice on 10^5-10
 constexpr int kDefaultVariant32 = 16;  // fastest untuned FP32 choice (eight-row tiles, MFMA)
 constexpr int kDefaultVariant32m32 = 23;  // at m = 32: the pipelined kernel, two waves per workgroup (1.72 ms
                                           // against 1.85-1.89 ms for the others at 10^6 rows)
+constexpr int kDefaultVariant32m64 = 17;  // at m = 64: two waves per workgroup (3.07 against 3.16 ms)
 
 inline int rt_spmm(ff_ctx *ctx, hipStream_t st, const rt::RTView &v, int sub, int m, const float *Y, int64_t ldy,
                    float *HY, float *MY, int64_t ldo, const int *row_obj, const int *status) {
@@ -2557,7 +2558,8 @@ std::string tune_key(int64_t n, int64_t nnz, int m, int precision) {
 int lookup_variant(ff_ctx *ctx, int64_t n, int64_t nnz, int m, int precision) {
     auto it = ctx->tuned.find(tune_key(n, nnz, m, precision));
     if (it != ctx->tuned.end()) return it->second;
-    return precision ? (m == 32 ? kDefaultVariant32m32 : kDefaultVariant32) : kDefaultVariant64;
+    return precision ? (m == 32 ? kDefaultVariant32m32 : m == 64 ? kDefaultVariant32m64 : kDefaultVariant32)
+                     : kDefaultVariant64;
 }
 
 int solve(ff_ctx *ctx, int n_obj, const int64_t *obj_off, const int64_t *row_ptr, const int32_t *col, const double *H,
