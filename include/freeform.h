@@ -49,7 +49,12 @@ typedef enum {
     FF_ERR_BREAKDOWN = -7         /* eigensolver basis lost rank beyond recovery */
 } ff_status;
 
-/* Context: binds a device and a stream (NULL = the device's null stream). */
+/* Context: binds a device and a stream (NULL = the device's null stream).
+ * Read once here from the environment: FF_VERBOSE=1 (progress on stderr);
+ * FF_UNION_BITS=n caps the LDS bitmap of the row-tile copy build at n words
+ * and FF_ASM_BITMAP_BYTES=n caps the row bitmaps assemble_HM keeps between
+ * its passes at n bytes, so that the other paths of both can be exercised
+ * (the results are the same either way). */
 int ff_ctx_create(ff_ctx **ctx, int device, void *hip_stream);
 void ff_ctx_destroy(ff_ctx *ctx);
 const char *ff_last_error(const ff_ctx *ctx);
