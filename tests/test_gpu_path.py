@@ -566,6 +566,22 @@ def test_eigenmodes_chebyshev_number_formats(oracle, ctx, ff, values):
     _check_modes(oracle, P, lam, host(W), res, k, 1e-5, 1e-3, 1e-8)
 
 
+@pytest.mark.parametrize("degree", [2, 3, 9])
+def test_eigenmodes_matrix_core_chebyshev_degrees(oracle, ctx, ff, degree):
+    """k = 32 on the matrix cores with step counts 1, 2 and 8: the block W takes the iterates of
+    two steps at every second step, and the last step's own when the count is odd, so a single
+    step, one pair and an even count (the last step adding two iterates) all reach the same
+    eigenpairs."""
+    c = synth.random_cloud(2500, seed=33, hetero=True)
+    P = oracle.pipeline(c)
+    A = ff.assemble_cloud(ctx, dev(c.xyz), dev(c.vol), dev(c.lam), dev(c.mu), c.h)
+    k = 32
+    lam, W, res, info = ff.eigenmodes(ctx, c.n, A.row_ptr, A.col, A.H, A.M, A.hm32, k=k, precision=1, tol=1e-8,
+                                      max_iter=8000, precond=2, precond_degree=degree, precond_values=3)
+    assert info["converged"] == 1
+    _check_modes(oracle, P, lam, host(W), res, k, 1e-5, 1e-3, 1e-8)
+
+
 @pytest.mark.parametrize("values,seed", [(1, 0), (2, 1), (3, 0), (3, 1)])
 def test_eigenmodes_stable_near_convergence(oracle, ctx, ff, values, seed):
     """k = 32 on the 1000-particle lattice, residual 1e-8: most pairs converge long before the
