@@ -13,8 +13,9 @@ Layers:
   * this file: the generalized eigenproblem of Eq. (15) - dense LAPACK
     ``eigh`` for small n, and an FP64 block LOBPCG (Knyazev 2001) with SVQB
     orthonormalisation (Stathopoulos & Wu 2002) and an optional Jacobi
-    preconditioner diag(H)^-1 for larger n - plus the
-    residual and subspace-angle metrics used to compare results.
+    (diag(H)^-1) or Chebyshev-Jacobi polynomial preconditioner for larger n -
+    plus the residual, subspace-angle and cluster metrics used to compare
+    results.
 """
 from __future__ import annotations
 
@@ -197,6 +198,7 @@ def assemble(n, off, ids, phi, dphi, vol, lam, mu, rho=None):
 
 
 def spmm(row_ptr, col, val, X):
+    """Y = A X for a CSR matrix given by its arrays (row-major blocks, threaded C loop)."""
     X = _c(X, np.float64)
     two = X.ndim == 2
     X2 = X if two else X[:, None]
@@ -209,6 +211,23 @@ def spmm(row_ptr, col, val, X):
 
 def norm_inf(row_ptr, val):
     return float(lib().orc_norm_inf(len(row_ptr) - 1, _c(row_ptr, np.int64), _c(val, np.float64)))
+
+
+def matmul(A, X):
+    """A @ X for a scipy CSR matrix, through the threaded C product of ``spmm`` (the same
+    definition as scipy's, one row at a time in storage order); other operands use ``@``."""
+    import scipy.sparse as sp
+    if not sp.isspmatrix_csr(A) and not isinstance(A, getattr(sp, "csr_array", ())):
+        return A @ X
+    arrs = getattr(A, "_orc_arrays", None)
+    if arrs is None:
+        arrs = (np.ascontiguousarray(A.indptr, dtype=np.int64), np.ascontiguousarray(A.indices, dtype=np.int32),
+                np.ascontiguousarray(A.data, dtype=np.float64))
+        try:
+            A._orc_arrays = arrs
+        except AttributeError:
+            pass
+    return spmm(arrs[0], arrs[1], arrs[2], X)
 
 
 def to_scipy(n, row_ptr, col, val):
@@ -292,7 +311,8 @@ def residuals(H, M, lam, W, normH=None, normM=None):
         normH = float(abs(H).sum(axis=1).max())
     if normM is None:
         normM = float(abs(M).sum(axis=1).max())
-    R = H @ W - (M @ W) * lam[None, :]
+    W = np.ascontiguousarray(W, dtype=np.float64)
+    R = matmul(H, W) - matmul(M, W) * lam[None, :]
     return np.linalg.norm(R, axis=0) / ((normH + np.abs(lam) * normM) * np.linalg.norm(W, axis=0))
 
 
@@ -308,31 +328,83 @@ def _svqb(S, MS, tau):
     return (Dinv[:, None] * U[:, keep]) / np.sqrt(s[keep])[None, :]
 
 
+def chebyshev_jacobi(H, degree=12, ratio=1000.0, upper=None, mul=None):
+    """Polynomial preconditioner T r = p(D^-1 H) D^-1 r, D = diag(H).
+
+    p is the Chebyshev semi-iteration for D^-1 H z = D^-1 r on the interval
+    [upper / ratio, upper] (Saad, "Iterative Methods for Sparse Linear Systems",
+    Chebyshev acceleration), started from z = 0 and stopped after ``degree``
+    updates of z, i.e. ``degree - 1`` products with H. p is positive on
+    (0, upper], so T is symmetric positive definite when ``upper`` bounds the
+    spectrum of D^-1 H; by default ``upper`` is 1.05 times the largest
+    eigenvalue of D^-1/2 H D^-1/2 from ARPACK. The eigenproblem's answer does
+    not depend on T, only the number of iterations does.
+    """
+    mul = matmul if mul is None else mul
+    d = np.asarray(H.diagonal(), dtype=np.float64)
+    if upper is None:
+        import scipy.sparse.linalg as sla
+        s = 1.0 / np.sqrt(d)
+        op = sla.LinearOperator(H.shape, dtype=np.float64,
+                                matvec=lambda v: s * mul(H, np.ascontiguousarray(s * np.ravel(v))))
+        lmax = float(sla.eigsh(op, k=1, which="LA", tol=1e-4, return_eigenvectors=False)[0])
+        upper = 1.05 * lmax
+    lo = upper / ratio
+    theta, delta = 0.5 * (upper + lo), 0.5 * (upper - lo)
+    sigma = theta / delta
+
+    def apply(R):
+        f = R / d[:, None]                     # right-hand side D^-1 r
+        z = np.zeros_like(f)
+        res = f.copy()                         # residual f - A z of the Chebyshev iteration
+        step = res / theta
+        rho = 1.0 / sigma
+        for j in range(degree):
+            z += step
+            if j == degree - 1:
+                break
+            res -= mul(H, step) / d[:, None]
+            rho_next = 1.0 / (2.0 * sigma - rho)
+            step = (rho_next * rho) * step + (2.0 * rho_next / delta) * res
+            rho = rho_next
+        return z
+
+    apply.upper = upper
+    return apply
+
+
 def lobpcg(H, M, X0, k=None, tol=1e-10, maxiter=5000, precond=None, normH=None, normM=None,
-           verbose=False):
+           verbose=False, mul=None):
     """Block LOBPCG (Knyazev 2001) in FP64 for the smallest eigenpairs of (H, M).
 
     Search space S = [X, W, P] with W the (optionally preconditioned) block
     residual and P the previous search direction; the Rayleigh-Ritz step is
     done in an M-orthonormal basis of S. Converged when the first k columns
-    satisfy the backward-error residual of ``residuals`` <= tol.
+    satisfy the backward-error residual of ``residuals`` <= tol. ``precond``
+    is None, "jacobi" (diag(H)^-1), "chebyshev" (``chebyshev_jacobi`` with its
+    defaults) or a callable R -> W. Products with H and M go through ``mul``
+    (default ``matmul``, the threaded C loop for CSR operands).
     """
+    mul = matmul if mul is None else mul
     X = np.array(X0, dtype=np.float64, copy=True)
     m = X.shape[1]
     if isinstance(precond, str):
-        if precond != "jacobi":
+        if precond == "jacobi":
+            dH = np.asarray(H.diagonal(), dtype=np.float64)
+            precond = (lambda R, d=dH: R / d[:, None])
+        elif precond == "chebyshev":
+            precond = chebyshev_jacobi(H, mul=mul)
+        else:
             raise ValueError(precond)
-        dH = np.asarray(H.diagonal(), dtype=np.float64)
-        precond = (lambda R, d=dH: R / d[:, None])
     k = m if k is None else k
     if normH is None:
         normH = float(abs(H).sum(axis=1).max())
     if normM is None:
         normM = float(abs(M).sum(axis=1).max())
-    MX = M @ X
+    MX = mul(M, X)
     T = _svqb(X, MX, 1e-14)
     X = X @ T
-    HX, MX = H @ X, M @ X
+    HX, MX = mul(H, X), mul(M, X)
     A = X.T @ HX
     th, Y = np.linalg.eigh(0.5 * (A + A.T))
     X, HX, MX = X @ Y, HX @ Y, MX @ Y
@@ -343,12 +415,12 @@ def lobpcg(H, M, X0, k=None, tol=1e-10, maxiter=5000, precond=None, normH=None, 
         R = HX - MX * th[None, :]
         res = np.linalg.norm(R, axis=0) / ((normH + np.abs(th) * normM) *
                                            np.linalg.norm(X, axis=0))
-        if verbose and it % 50 == 0:
-            print(it, res[:k].max())
+        if verbose and it % verbose == 0:
+            print(it, res[:k].max(), flush=True)
         if res[:k].max() <= tol:
             break
         W = R if precond is None else precond(R)
-        HW, MW = H @ W, M @ W
+        HW, MW = mul(H, W), mul(M, W)
         blocks = [X, W] + ([P] if P is not None else [])
         S = np.concatenate(blocks, axis=1)
         HS = np.concatenate([HX, HW] + ([HP] if P is not None else []), axis=1)
@@ -369,12 +441,14 @@ def lobpcg(H, M, X0, k=None, tol=1e-10, maxiter=5000, precond=None, normH=None, 
 
 def subspace_sines(Wa, Wb, M):
     """Sines of the principal angles between span(Wa) and span(Wb) in the M inner product."""
-    Ta = _svqb(Wa, M @ Wa, 1e-14)
+    Wa = np.ascontiguousarray(Wa, dtype=np.float64)
+    Wb = np.ascontiguousarray(Wb, dtype=np.float64)
+    Ta = _svqb(Wa, matmul(M, Wa), 1e-14)
     Qa = Wa @ Ta
-    Tb = _svqb(Wb, M @ Wb, 1e-14)
+    Tb = _svqb(Wb, matmul(M, Wb), 1e-14)
     Qb = Wb @ Tb
-    E = Qb - Qa @ (Qa.T @ (M @ Qb))
-    G = E.T @ (M @ E)
+    E = Qb - Qa @ (Qa.T @ matmul(M, Qb))
+    G = E.T @ matmul(M, E)
     s = np.linalg.eigvalsh(0.5 * (G + G.T))
     return np.sqrt(np.clip(s, 0.0, None))[::-1]
 

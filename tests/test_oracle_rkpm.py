@@ -133,3 +133,60 @@ def test_singular_moment_reported(oracle):
     with pytest.raises(oracle.SingularMoment) as ei:
         oracle.rkpm(qx, xs, off, ids, 0.25)
     assert ei.value.index == 0
+
+
+def test_gaussian_branch_reproduction_and_gradient(oracle):
+    """kernel 1 (Gaussian exp(-d^2/r^2), r = h/2, cut at d = h): the corrected functions
+    reproduce linear fields and their gradients to 1e-12, and the gradient matches central
+    finite differences at points none of whose nodes lies near the cut (where the raw
+    kernel jumps by e^-4 and the list would change)."""
+    c = synth.random_cloud(1500, seed=31)
+    xs, qx, off, ids = _prep(oracle, c)
+    phi, dphi = oracle.rkpm(qx, xs, off, ids, c.h, kernel=1)
+    q = qx.shape[0]
+    rows = np.repeat(np.arange(q), np.diff(off))
+    assert np.abs(np.bincount(rows, weights=phi, minlength=q) - 1.0).max() <= 1e-12
+    p = xs[ids]
+    for a in range(3):
+        assert np.abs(np.bincount(rows, weights=dphi[:, a], minlength=q)).max() * c.h <= 1e-12
+        lin = np.bincount(rows, weights=phi * p[:, a], minlength=q)
+        assert np.abs(lin - qx[:, a]).max() / c.h <= 1e-12
+        for s in range(3):
+            gl = np.bincount(rows, weights=dphi[:, s] * p[:, a], minlength=q)
+            assert np.abs(gl - (1.0 if a == s else 0.0)).max() <= 1e-12
+    # finite differences away from the cut
+    d = 1e-6 * c.h
+    sel = []
+    for i in range(0, q, 7):
+        nb = ids[off[i]:off[i + 1]]
+        dist = np.sqrt(np.sum((xs[nb] - qx[i]) ** 2, axis=1))
+        # no node inside the list within 1e-3 h of the cut, and none just outside it
+        near = np.sum((np.abs(np.sqrt(np.sum((xs - qx[i]) ** 2, axis=1)) - c.h) < 1e-3 * c.h))
+        if near == 0 and dist.max() < c.h:
+            sel.append(i)
+    sel = np.array(sel[:120])
+    assert len(sel) >= 60
+    sub_off = np.concatenate([[0], np.cumsum(np.diff(off)[sel])])
+    sub_ids = np.concatenate([ids[off[i]:off[i + 1]] for i in sel]).astype(np.int32)
+    ref_all = np.concatenate([dphi[off[i]:off[i + 1]] for i in sel])
+    for s in range(3):
+        e = np.zeros(3)
+        e[s] = d
+        pp, _ = oracle.rkpm(qx[sel] + e, xs, sub_off, sub_ids, c.h, kernel=1)
+        pm, _ = oracle.rkpm(qx[sel] - e, xs, sub_off, sub_ids, c.h, kernel=1)
+        fd = (pp - pm) / (2 * d)
+        assert np.abs(fd - ref_all[:, s]).max() <= 1e-6 * np.abs(ref_all).max()
+
+
+def test_gaussian_branch_shepard_shape(oracle):
+    """At an interior node of an unjittered lattice the corrected functions reduce to
+    Shepard's w_k / sum w, so phi_k / phi_self = exp(-4 z^2) with z = |p_k - X| / h."""
+    c = synth.cube_lattice(m=12, jitter=0.0)
+    xs, qx, off, ids = _prep(oracle, c)
+    phi, _ = oracle.rkpm(qx, xs, off, ids, c.h, kernel=1)
+    i = int(np.argmin(np.sum((qx - (np.array([0.6, 0.6, 0.6]) - 0.05)) ** 2, axis=1)))
+    nb = ids[off[i]:off[i + 1]]
+    ph = phi[off[i]:off[i + 1]]
+    z = np.sqrt(np.sum((xs[nb] - qx[i]) ** 2, axis=1)) / c.h
+    ratio = ph / ph[np.argmin(z)]
+    assert np.abs(ratio - np.exp(-4.0 * z * z)).max() <= 1e-12
