@@ -221,6 +221,13 @@ typedef struct {
                            the inverse of its largest magnitude per object (the output's span is
                            unchanged); 0 = default: 3 where the width allows, else 2. Products
                            accumulate in FP32 in every case */
+    double eig_tol;     /* 0 = off. Else the FP64 phase also iterates until the a-posteriori
+                           eigenvalue bound of every wanted pair (eig_bounds) is <= eig_tol
+                           (relative): an object converges when max_j r_j <= tol and
+                           max_j eig_bound_j <= eig_tol. On the mixed path the FP64 phase then
+                           preconditions with the FP32 / binary16 Chebyshev-Jacobi products (an
+                           approximate operator is all a preconditioner needs; the residuals,
+                           Grams and Rayleigh-Ritz stay FP64 on the FP64 matrices) */
 } ff_eig_params;
 
 typedef struct {
@@ -231,6 +238,10 @@ typedef struct {
     double max_resid;   /* final max_j r_j (FP64, certified) */
     double seconds;     /* wall time of the call */
     int graph;          /* 1 if the iterations were replayed from a captured hipGraph */
+    double max_eig_bound;   /* max over the k pairs of eig_bound (eig_bounds); infinite if the FP64
+                               phase never formed it */
+    double max_angle_bound; /* max over the k pairs of angle_bound */
+    int eig_certified;      /* 1 if max_eig_bound <= eig_tol (eig_tol > 0), or <= 1e-5 when eig_tol is 0 */
 } ff_eig_info;
 
 /*
@@ -270,6 +281,27 @@ int eigenmodes_batched(ff_ctx *ctx, int n_obj, const int64_t *obj_row_off, const
                        const int32_t *col, const double *H, const double *M, const float *hm32,
                        const ff_eig_params *p, const double *X0, double *eigval, double *W,
                        double *resid, ff_eig_info *info);
+
+/*
+ * eig_bounds - a-posteriori bounds of the last eigenmodes / eigenmodes_batched call on
+ * this context, per object and pair (host out, [n_obj][k] each, either may be NULL).
+ * For the generalized problem of Eq. (15) with M-orthonormal w_j and residual
+ * r_j = H w_j - theta_j M w_j, eigenvalue perturbation theory bounds the error of the
+ * Ritz value by ||r_j||^2 / gap and the sine of the eigenvector's angle by ||r_j|| / gap,
+ * with the residual in the M^-1 norm and gap the distance from theta_j to the rest of the
+ * spectrum. The library takes the residual in the norm of diag(M)^-1 instead (the M^-1
+ * norm would need a solve with M), so the figures are estimates, not guarantees:
+ *   eta_j^2 = sum_i R_ij^2 / M_ii, in FP64 with the FP64 matrices;
+ *   Ritz values within 1e-3 relative of a neighbour form a cluster C, bounded as a
+ *   block: eta_C^2 = sum of eta_j^2 over C, gap_C = distance from C to the nearest Ritz
+ *   value outside it (including the next Ritz value beyond the block);
+ *   eig_bound_j = eta_C^2 / (gap_C max(|theta_j|, theta_1))   (relative eigenvalue error)
+ *   angle_bound_j = eta_C / gap_C                             (sine of the largest angle)
+ * They are formed in the FP64 phase at each residual check; a pair whose gap is unknown
+ * (no Ritz value beyond the block yet) has an infinite bound. Returns FF_ERR_INVALID_ARG
+ * if n_obj or k differ from the last call's.
+ */
+int eig_bounds(ff_ctx *ctx, int n_obj, int k, double *eig_bound, double *angle_bound);
 
 /*
  * spmm_hm - the fused block product [HY, MY] = [H, M] Y used inside eigenmodes,

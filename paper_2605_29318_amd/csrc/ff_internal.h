@@ -35,6 +35,7 @@ enum WsSlot {
     WS_CHEBQ,                                                     // column maxima of the scaled recurrence
     WS_RT16_CNT, WS_RT16_PTR, WS_RT16_COL, WS_RT16_VAL,           // sixteen-row H-only tile copy
     WS_SUBCELL,                                                   // sub-cell codes of the binning
+    WS_MDINV,                                                     // diag(M)^-1 for the eigenvalue bounds
     WS_COUNT
 };
 
@@ -68,6 +69,9 @@ struct ff_ctx {
     bool asm_bm = false;             // the sizing call kept its row bitmaps (workspace slot WS_ASM_BM)
     int64_t asm_bm_cap = -1;         // FF_ASM_BITMAP_BYTES: cap on that store (-1: the built-in 8 GiB)
     hipStream_t graph_stream = nullptr;   // private stream for graph capture
+    // a-posteriori bounds of the last eigensolve, [n_obj][k] each
+    int eb_nobj = 0, eb_k = 0;
+    std::vector<double> eb_eig, eb_angle;
 };
 
 namespace ff {

@@ -456,10 +456,14 @@ __global__ void __launch_bounds__(256) gram_reduce_kernel(const int *obj_status,
 // residuals and the W block
 // ---------------------------------------------------------------------------
 
+// Per chunk and column: sum r^2, sum x^2 and, with mdinv, sum r^2 / M_ii (the residual in the
+// norm of diag(M)^-1, from which the eigenvalue bounds of norms_kernel are formed); rpart
+// holds 3m sums per chunk.
 template <typename T>
 __global__ void __launch_bounds__(256) resid_kernel(const UChunk *chunks, const int *obj_status, T *S, const T *HS,
                                                     const T *MS, int64_t ld, int m, const double *theta,
-                                                    const T *dinv, double *rpart, float *wpart) {
+                                                    const T *dinv, const double *mdinv, double *rpart,
+                                                    float *wpart) {
     // VN consecutive columns per thread (16-byte loads; m is a multiple of 4), rows_per rows per pass
     typedef typename Vec<T>::type V;
     constexpr int VN = Vec<T>::n;
@@ -469,13 +473,13 @@ __global__ void __launch_bounds__(256) resid_kernel(const UChunk *chunks, const 
     const int rows_per = 256 / mv;
     const int t = threadIdx.x;
     const int rr = t / mv, c = (t - (t / mv) * mv) * VN;
-    __shared__ double red[2][256 * VN];
+    __shared__ double red[3][256 * VN];
     __shared__ float wred[256 * VN];
-    double r2[VN], x2[VN], th[VN];
+    double r2[VN], x2[VN], e2[VN], th[VN];
     float wmax[VN];
 #pragma unroll
     for (int v = 0; v < VN; ++v) {
-        r2[v] = x2[v] = 0.0;
+        r2[v] = x2[v] = e2[v] = 0.0;
         wmax[v] = 0.f;
     }
     if (rr < rows_per) {
@@ -485,6 +489,7 @@ __global__ void __launch_bounds__(256) resid_kernel(const UChunk *chunks, const 
             const V xs = *(const V *)(S + r * ld + c), hs = *(const V *)(HS + r * ld + c),
                     ms = *(const V *)(MS + r * ld + c);
             const double dv = dinv ? (double)dinv[r] : 1.0;
+            const double md = mdinv ? mdinv[r] : 0.0;
             V wv;
 #pragma unroll
             for (int v = 0; v < VN; ++v) {
@@ -492,6 +497,7 @@ __global__ void __launch_bounds__(256) resid_kernel(const UChunk *chunks, const 
                 const double R = (double)vget(hs, v) - th[v] * (double)vget(ms, v);
                 r2[v] += R * R;
                 x2[v] += x * x;
+                e2[v] += R * R * md;
                 const T w = (T)(dinv ? R * dv : R);
                 vset(wv, v, w);
                 wmax[v] = fmaxf(wmax[v], fabsf((float)w));
@@ -504,20 +510,23 @@ __global__ void __launch_bounds__(256) resid_kernel(const UChunk *chunks, const 
         for (int v = 0; v < VN; ++v) {
             red[0][rr * m + c + v] = r2[v];
             red[1][rr * m + c + v] = x2[v];
+            red[2][rr * m + c + v] = e2[v];
             wred[rr * m + c + v] = wmax[v];
         }
     }
     __syncthreads();
     if (t < m) {
-        double a = 0.0, b = 0.0;
+        double a = 0.0, b = 0.0, e = 0.0;
         float w = 0.f;
         for (int q = 0; q < rows_per; ++q) {
             a += red[0][q * m + t];
             b += red[1][q * m + t];
+            e += red[2][q * m + t];
             w = fmaxf(w, wred[q * m + t]);
         }
-        rpart[(size_t)blockIdx.x * 2 * m + t] = a;
-        rpart[(size_t)blockIdx.x * 2 * m + m + t] = b;
+        rpart[(size_t)blockIdx.x * 3 * m + t] = a;
+        rpart[(size_t)blockIdx.x * 3 * m + m + t] = b;
+        rpart[(size_t)blockIdx.x * 3 * m + 2 * m + t] = e;
         if (wpart) wpart[(size_t)blockIdx.x * m + t] = w;
     }
 }
@@ -525,42 +534,83 @@ __global__ void __launch_bounds__(256) resid_kernel(const UChunk *chunks, const 
 // r_j = ||R_j|| / ((||H|| + |theta_j| ||M||) ||x_j||); status: 0 active, 1 converged, 2 stagnated.
 // 1024 threads: thread (part, q) sums the chunks c = part (mod 16) of output q in
 // ascending order, then the 16 parts are added in a fixed order.
+//
+// With ebound non-NULL, also the a-posteriori bounds of every pair (the residual taken in the
+// norm of diag(M)^-1, eta_j^2 = sum_i R_ij^2 / M_ii, standing in for the M^-1 norm of the
+// quadratic eigenvalue bound |theta - lambda| <= ||r||^2_{M^-1} / gap and of the Davis-Kahan
+// angle bound sin <= ||r||_{M^-1} / gap; the columns are M-orthonormal). Ritz values closer than
+// 1e-3 relative form a cluster, bounded as a block: eta_C^2 = sum of eta_j^2 over the cluster,
+// gap = distance from the cluster to the nearest Ritz value outside it (theta_next, the next Ritz
+// value of the last Rayleigh-Ritz step, beyond the block; unknown = NaN makes the bound infinite).
+//   ebound_j = eta_C^2 / (gap theta_ref), theta_ref = max(|theta_j|, theta_1) (relative error;
+//              the constant mode's is relative to theta_1)
+//   abound_j = eta_C / gap
+// With eig_tol > 0 an object converges only when both max_j r_j <= tol and max_j ebound_j <=
+// eig_tol over the first k pairs.
 __global__ void __launch_bounds__(1024) norms_kernel(int *obj_status, const int *cfirst, const int *ccount,
                                                      const double *rpart, int m, int k, const double *theta,
                                                      const double *norms, double tol, int stall_limit,
-                                                     double *res, double *track) {
+                                                     double *res, double *track, const double *theta_next,
+                                                     double eig_tol, double *ebound, double *abound) {
     const int o = blockIdx.x;
     if (obj_status[o] != 0) return;
-    __shared__ double part[16][128];
-    __shared__ double rj[64];
+    __shared__ double part[16][192];
+    __shared__ double rj[64], eta2[64], th[65], eb[64];
     const int q = threadIdx.x & 127, pp = threadIdx.x >> 7;   // 8 parts of 128 outputs
     const int c0 = cfirst[o], nc = ccount[o];
-    for (int pp2 = pp; pp2 < 16; pp2 += 8) {
-        double s = 0.0;
-        if (q < 2 * m)
-            for (int c = pp2; c < nc; c += 16) s += rpart[(size_t)(c0 + c) * 2 * m + q];
-        part[pp2][q] = s;
-    }
+    for (int q2 = q; q2 < 3 * m; q2 += 128)
+        for (int pp2 = pp; pp2 < 16; pp2 += 8) {
+            double s = 0.0;
+            for (int c = pp2; c < nc; c += 16) s += rpart[(size_t)(c0 + c) * 3 * m + q2];
+            part[pp2][q2] = s;
+        }
     __syncthreads();
     if (threadIdx.x < m) {
         const int c = threadIdx.x;
-        double a = 0.0, b = 0.0;
+        double a = 0.0, b = 0.0, e = 0.0;
         for (int t = 0; t < 16; ++t) {
             a += part[t][c];
             b += part[t][m + c];
+            e += part[t][2 * m + c];
         }
-        const double th = theta[(size_t)o * m + c];
-        double r = sqrt(a) / ((norms[2 * o] + fabs(th) * norms[2 * o + 1]) * sqrt(b));
+        const double thc = theta[(size_t)o * m + c];
+        double r = sqrt(a) / ((norms[2 * o] + fabs(thc) * norms[2 * o + 1]) * sqrt(b));
         if (!(r == r)) r = INFINITY;
         res[(size_t)o * m + c] = r;
         rj[c] = c < k ? r : 0.0;
+        eta2[c] = e;
+        th[c] = thc;
+    }
+    if (threadIdx.x == 0) th[m] = theta_next ? theta_next[o] : NAN;
+    __syncthreads();
+    if (ebound && threadIdx.x < m) {
+        const int c = threadIdx.x;
+        const double crel = 1e-3;
+        int a = c, b = c + 1;                      // cluster [a, b) of Ritz values within crel of a neighbour
+        while (a > 0 && th[a] - th[a - 1] <= crel * fabs(th[a])) --a;
+        while (b <= m && th[b] - th[b - 1] <= crel * fabs(th[b])) ++b;
+        double gap = INFINITY;
+        if (a > 0) gap = th[a] - th[a - 1];
+        if (b <= m) gap = fmin(gap, th[b] - th[b - 1]);
+        if (b > m || (b == m && !(th[m] == th[m]))) gap = NAN;   // the cluster reaches an unknown value
+        double e2 = 0.0;
+        for (int j = a; j < b && j < m; ++j) e2 += eta2[j];
+        const double ref = fmax(fabs(th[c]), m > 1 ? th[1] : th[m]);
+        double eb_c = e2 / (gap * ref), ab_c = sqrt(e2) / gap;
+        if (!(eb_c == eb_c) || !(ref > 0.0)) eb_c = INFINITY;
+        if (!(ab_c == ab_c)) ab_c = INFINITY;
+        ebound[(size_t)o * m + c] = eb_c;
+        abound[(size_t)o * m + c] = ab_c;
+        eb[c] = c < k ? eb_c : 0.0;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double v = 0.0;
+        double v = 0.0, ve = 0.0;
         for (int c = 0; c < k; ++c) v = fmax(v, rj[c]);
+        if (ebound)
+            for (int c = 0; c < k; ++c) ve = fmax(ve, eb[c]);
         double *tr = track + 2 * o;               // [best max residual, iterations since improvement]
-        if (v <= tol) {
+        if (v <= tol && (eig_tol <= 0.0 || (ebound && ve <= eig_tol))) {
             obj_status[o] = 1;
         } else if (stall_limit > 0) {
             if (v < 0.9 * tr[0]) {
@@ -1234,12 +1284,17 @@ __global__ void __launch_bounds__(kRRThreads) rr_tridiag_kernel(int *obj_status,
     RR_MARK(5);
 }
 
-// stage 2: eigenvalue t of T by multisection (64 Sturm counts per round)
-__global__ void __launch_bounds__(64) rr_eig_kernel(const int *obj_status, int wmax, int m, double *scratch) {
+// stage 2: eigenvalue t of T by multisection (64 Sturm counts per round); the block t = m
+// (launched when theta_next is given) finds the next Ritz value beyond the block when the kept
+// basis has more than m columns, and otherwise leaves the previous step's value (the X-only
+// steps at the start of a phase have none of their own)
+__global__ void __launch_bounds__(64) rr_eig_kernel(const int *obj_status, int wmax, int m, double *scratch,
+                                                    double *theta_next) {
     const int t = blockIdx.x, o = blockIdx.y, lane = threadIdx.x;
     if (obj_status[o] != 0) return;
     const RRScr g = rr_scr(scratch, o, wmax, m);
     const int r = (int)g.meta[RR_R];
+    if (t >= m && r <= m) return;
     __shared__ double dg[kRRMax], eg[kRRMax];
     for (int i = lane; i < r; i += 64) {
         dg[i] = g.dg[i];
@@ -1261,7 +1316,10 @@ __global__ void __launch_bounds__(64) rr_eig_kernel(const int *obj_status, int w
         lo = nlo;
         hi = nhi;
     }
-    if (lane == 0) g.evs[t] = 0.5 * (lo + hi);
+    if (lane == 0) {
+        g.evs[t] = 0.5 * (lo + hi);
+        if (t >= m) theta_next[o] = 0.5 * (lo + hi);
+    }
 }
 
 // stage 3: eigenvector(s) of T for eigenvalue t (its whole cluster when t leads one),
@@ -1655,6 +1713,26 @@ __global__ void diag_inv_bs_kernel(int64_t n, const int64_t *row_ptr, const int3
     d32[r] = (float)v;
 }
 
+// d[r] = 1 / M_rr (1 where the diagonal is not positive)
+__global__ void diag_inv_m_kernel(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *M, double *d) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    int64_t lo = row_ptr[r], hi = row_ptr[r + 1] - 1;
+    double v = 0.0;
+    while (lo <= hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        const int32_t c = col[mid];
+        if (c == r) { v = M[mid]; break; }
+        if (c < r) lo = mid + 1; else hi = mid - 1;
+    }
+    d[r] = v > 0.0 ? 1.0 / v : 1.0;
+}
+
+__global__ void fill_f64_kernel(int64_t count, double *a, double v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) a[i] = v;
+}
+
 // ---------------------------------------------------------------------------
 // Chebyshev-Jacobi preconditioner: z = q(A) D^-1 r with A = D^-1 H, D = diag(H),
 // q the Chebyshev semi-iteration polynomial of degree d for A z = D^-1 r on
@@ -2004,6 +2082,13 @@ struct Solver {
     double *G = nullptr, *gpart = nullptr, *rpart = nullptr;
     float *Cp32 = nullptr;
     double *res = nullptr, *track = nullptr, *norms = nullptr, *rrscr = nullptr, *dinv64 = nullptr;
+    double *theta_next = nullptr;                  // [n_obj] next Ritz value beyond the block (NaN: unknown)
+    double *ebound = nullptr, *abound = nullptr;   // [n_obj][m] eigenvalue and angle bounds of the pairs
+    double *mdinv = nullptr;                       // [N] diag(M)^-1 for the bounds
+    double eig_tol = 0.0;                          // FP64 phase: also require max ebound <= eig_tol
+    int bounds_on = 0;                             // the residual stage forms the bounds (FP64 phase)
+    float *S32 = nullptr;                          // FP32 blocks of the mixed path (its FP64 phase
+                                                   // preconditions through them)
     float *C32 = nullptr, *dinv32 = nullptr;
     UChunk *uch = nullptr;
     GChunk *gch = nullptr;
@@ -2062,7 +2147,7 @@ int stage_spmm(Solver &s, T *S, T *HS, T *MS, int slot) {
 template <typename CT>
 int launch_rr(ff_ctx *ctx, hipStream_t st, int n_obj, int *status, const int *width, const double *G, int wmax, int m,
               double tau, double *scratch, double *C, CT *Cw, double *Cp, CT *Cpw, double *theta, int *info,
-              double pmin = 0.0) {
+              double pmin = 0.0, double *theta_next = nullptr) {
     const int lds = rr_use_lds(wmax), vlds = rr_vec_lds(wmax);
     if (lds)
         hipLaunchKernelGGL(rr_tridiag_kernel<true>, dim3(n_obj), dim3(kRRThreads), rr_shmem_bytes(wmax, 1), st, status,
@@ -2070,7 +2155,8 @@ int launch_rr(ff_ctx *ctx, hipStream_t st, int n_obj, int *status, const int *wi
     else
         hipLaunchKernelGGL(rr_tridiag_kernel<false>, dim3(n_obj), dim3(kRRThreads), rr_shmem_bytes(wmax, 0), st,
                            status, width, G, wmax, m, tau, pmin, scratch, info);
-    hipLaunchKernelGGL(rr_eig_kernel, dim3(m, n_obj), dim3(64), 0, st, status, wmax, m, scratch);
+    hipLaunchKernelGGL(rr_eig_kernel, dim3(theta_next ? m + 1 : m, n_obj), dim3(64), 0, st, status, wmax, m, scratch,
+                       theta_next);
     if (vlds)
         hipLaunchKernelGGL(rr_vec_kernel<true>, dim3(m, n_obj), dim3(64), rr_vec_shmem_bytes(wmax, 1), st, status,
                            width, wmax, m, scratch, C, theta);
@@ -2117,7 +2203,7 @@ int stage_gram_rr(Solver &s, T *S, T *HS, T *MS, double tau) {
     // P columns below an M-norm of 1e-6 (FP32) or 1e-12 (FP64) leave the basis
     return launch_rr<typename Prec<T>::CT>(s.ctx, s.st, s.n_obj, s.status, s.width, s.G, s.wmax, s.m, tau, s.rrscr,
                                            s.C, cw_of<T>(s), s.Cp, cpw_of<T>(s), s.theta, s.info,
-                                           sizeof(T) == 4 ? 1e-12 : 1e-24);
+                                           sizeof(T) == 4 ? 1e-12 : 1e-24, s.theta_next);
 }
 
 template <typename T>
@@ -2140,12 +2226,18 @@ int stage_update(Solver &s, T *S, T *HS, T *MS, int write_p) {
 template <typename T>
 int stage_resid(Solver &s, T *S, T *HS, T *MS, double tol, int stall) {
     StageMark mark(s.ctx, s.st, FF_STAGE_RESID);
+    const bool bounds = s.bounds_on && sizeof(T) == 8;
+    // the chunk maxima of D^-1 R feed the binary16 preconditioner, which the mixed path's FP64 phase uses too
+    const bool wmx = s.q_on && (sizeof(T) == 4 || s.S32 != nullptr);
     hipLaunchKernelGGL(resid_kernel<T>, dim3(s.ng), dim3(256), 0, s.st, s.gch, s.status, S, (const T *)HS,
                        (const T *)MS, (int64_t)3 * s.m, s.m, s.theta, s.jacobi ? dinv_of<T>(s) : (const T *)nullptr,
-                       s.rpart, sizeof(T) == 4 && s.q_on ? s.wpart : (float *)nullptr);
+                       bounds ? (const double *)s.mdinv : (const double *)nullptr, s.rpart,
+                       wmx ? s.wpart : (float *)nullptr);
     FF_CHECK_LAUNCH(s.ctx);
     hipLaunchKernelGGL(norms_kernel, dim3(s.n_obj), dim3(1024), 0, s.st, s.status, s.gfirst, s.gcount, s.rpart, s.m,
-                       s.k, s.theta, s.norms, tol, stall, s.res, s.track);
+                       s.k, s.theta, s.norms, tol, stall, s.res, s.track, (const double *)s.theta_next,
+                       bounds ? s.eig_tol : 0.0, bounds ? s.ebound : (double *)nullptr,
+                       bounds ? s.abound : (double *)nullptr);
     FF_CHECK_LAUNCH(s.ctx);
     hipLaunchKernelGGL(count_iter_kernel, dim3(grid_for(s.n_obj, 64)), dim3(64), 0, s.st, s.n_obj, s.status, s.iters);
     FF_CHECK_LAUNCH(s.ctx);
@@ -2158,6 +2250,21 @@ int stage_precond(Solver &s, T *S) {
     if (s.cheb < 2) return FF_OK;
     const int64_t cnt = s.N * s.m;
     const int64_t ld = 3 * (int64_t)s.m;
+    if (sizeof(T) == 8 && s.S32 && (s.q_on || s.rt8.vh || s.rt16.vh)) {
+        // the mixed path's FP64 phase: the preconditioner is an approximate operator, so it runs the
+        // FP32 / binary16 products on an FP32 copy of D^-1 R (the FP32 blocks are free by now) and its
+        // output returns to the FP64 W block; residuals, products of the basis, Grams and
+        // Rayleigh-Ritz stay FP64
+        hipLaunchKernelGGL((copy_block_kernel<float, double>), dim3(grid_for(cnt, 256)), dim3(256), 0, s.st, s.N, s.m,
+                           (const double *)(S + s.m), ld, s.S32 + s.m, ld);
+        FF_CHECK_LAUNCH(s.ctx);
+        const int rc = stage_precond<float>(s, s.S32);
+        if (rc) return rc;
+        hipLaunchKernelGGL((copy_block_kernel<double, float>), dim3(grid_for(cnt, 256)), dim3(256), 0, s.st, s.N, s.m,
+                           (const float *)(s.S32 + s.m), ld, (double *)(S + s.m), ld);
+        FF_CHECK_LAUNCH(s.ctx);
+        return FF_OK;
+    }
     T *Rb = (T *)s.cheb_r, *DZ = (T *)s.cheb_dz, *HD = (T *)s.cheb_hd, *MD = (T *)s.cheb_md;
     if (sizeof(T) == 4 && s.q_on) {
         // binary16 iterate in the DZ buffer (two [N][m] halves), scaled start
@@ -2500,10 +2607,13 @@ int setup(Solver &s, const ff_eig_params *p) {
     FF_CHECK_LAUNCH(ctx);
 
     const int m = s.m, wmax = s.wmax;
-    s.theta = (double *)ws_get(ctx, WS_THETA, (size_t)n_obj * m * sizeof(double) * 2 + (size_t)n_obj * 4 * sizeof(double));
+    s.theta = (double *)ws_get(ctx, WS_THETA, (size_t)n_obj * m * sizeof(double) * 4 + (size_t)n_obj * 5 * sizeof(double));
     s.res = s.theta + (size_t)n_obj * m;
     s.track = s.res + (size_t)n_obj * m;
     s.norms = s.track + 2 * (size_t)n_obj;
+    s.theta_next = s.norms + 2 * (size_t)n_obj;
+    s.ebound = s.theta_next + (size_t)n_obj;
+    s.abound = s.ebound + (size_t)n_obj * m;
     s.C = (double *)ws_get(ctx, WS_C, (size_t)n_obj * wmax * m * sizeof(double) * 4);
     s.C64w = s.C ? s.C + (size_t)n_obj * wmax * m : nullptr;
     s.Cp = s.C ? s.C + (size_t)2 * n_obj * wmax * m : nullptr;
@@ -2512,10 +2622,23 @@ int setup(Solver &s, const ff_eig_params *p) {
     s.Cp32 = s.C32 ? s.C32 + (size_t)n_obj * wmax * m : nullptr;
     s.G = (double *)ws_get(ctx, WS_G, (size_t)n_obj * 2 * wmax * wmax * sizeof(double));
     s.gpart = (double *)ws_get(ctx, WS_GPART, (size_t)s.ng * 2 * wmax * wmax * sizeof(double));
-    s.rpart = (double *)ws_get(ctx, WS_RPART, (size_t)std::max(s.nu, s.ng) * 2 * std::max(m, 2) * sizeof(double));
+    s.rpart = (double *)ws_get(ctx, WS_RPART, (size_t)std::max(s.nu, s.ng) * 3 * std::max(m, 2) * sizeof(double));
     s.rrscr = (double *)ws_get(ctx, WS_RRSCR, (size_t)n_obj * rr_scratch_doubles(wmax, m) * sizeof(double));
     if (!s.theta || !s.C || !s.C32 || !s.G || !s.gpart || !s.rpart || !s.rrscr) return FF_ERR_OOM;
     FF_HIP(ctx, hipMemsetAsync(s.theta, 0, (size_t)n_obj * m * sizeof(double) * 2, s.st));
+    // the next Ritz value is unknown (NaN) until a Rayleigh-Ritz step on more than m columns; the
+    // bounds are infinite until the FP64 phase forms them
+    hipLaunchKernelGGL(fill_f64_kernel, dim3(grid_for(n_obj, 256)), dim3(256), 0, s.st, (int64_t)n_obj, s.theta_next,
+                       (double)NAN);
+    hipLaunchKernelGGL(fill_f64_kernel, dim3(grid_for((int64_t)n_obj * 2 * m, 256)), dim3(256), 0, s.st,
+                       (int64_t)n_obj * 2 * m, s.ebound, (double)INFINITY);
+    FF_CHECK_LAUNCH(ctx);
+    s.eig_tol = p->eig_tol;
+    s.mdinv = (double *)ws_get(ctx, WS_MDINV, (size_t)s.N * sizeof(double));
+    if (!s.mdinv) return FF_ERR_OOM;
+    hipLaunchKernelGGL(diag_inv_m_kernel, dim3(grid_for(s.N, 256)), dim3(256), 0, s.st, s.N, s.row_ptr, s.col, s.M,
+                       s.mdinv);
+    FF_CHECK_LAUNCH(ctx);
 
     // per-object norms of H and M (infinity norm = max absolute row sum)
     hipLaunchKernelGGL(rownorm_chunk_kernel, dim3(s.nu), dim3(256), 0, s.st, s.uch, s.row_ptr, s.H, s.M, s.rpart);
@@ -2578,6 +2701,7 @@ int solve(ff_ctx *ctx, int n_obj, const int64_t *obj_off, const int64_t *row_ptr
                "Chebyshev degree %d must be 0 (default %d) or in [2, 16]", p->precond_degree, kChebDefault);
     FF_REQUIRE(ctx, p->precond != 2 || p->precond_ratio == 0.0 || (p->precond_ratio > 1.0 && p->precond_ratio <= 1e6),
                "Chebyshev interval ratio %g must be 0 (default %g) or in (1, 1e6]", p->precond_ratio, kChebRatio);
+    FF_REQUIRE(ctx, p->eig_tol >= 0.0 && p->eig_tol == p->eig_tol, "eig_tol must be >= 0");
     FF_REQUIRE(ctx, p->precond_values >= 0 && p->precond_values <= 3,
                "precond_values %d must be 0 (default), 1 (FP32), 2 (binary16 H) or 3 (binary16 H and iterate)",
                p->precond_values);
@@ -2697,6 +2821,7 @@ int solve(ff_ctx *ctx, int n_obj, const int64_t *obj_off, const int64_t *row_ptr
         hipLaunchKernelGGL((copy_block_kernel<float, double>), dim3(grid_for(s.N * m, 256)), dim3(256), 0, s.st, s.N, m,
                            (const double *)X0d, (int64_t)m, S32, (int64_t)3 * m);
         FF_CHECK_LAUNCH(ctx);
+        s.S32 = S32;
         if ((rc = init_block<float>(s, S32, HS32, MS32, tau32))) return rc;
         // the FP32 phase ends at tol, or when its residual has not dropped by 10% for kStall32
         // iterations (its rounding floor); the largest residual is not monotone, and bumps
@@ -2720,6 +2845,7 @@ int solve(ff_ctx *ctx, int n_obj, const int64_t *obj_off, const int64_t *row_ptr
     {
         StageMark phase(ctx, s.st, FF_STAGE_FP64_PHASE);
         TimingMute mute(ctx, p->precision == 1);
+        s.bounds_on = 1;                  // the residual stage forms the a-posteriori bounds from here on
         if ((rc = reset_status(s, 0))) return rc;
         if ((rc = init_block<double>(s, S64, HS64, MS64, tau64))) return rc;
         const int left = std::max(0, p->max_iter - it32);
@@ -2728,10 +2854,10 @@ int solve(ff_ctx *ctx, int n_obj, const int64_t *obj_off, const int64_t *row_ptr
                                     s.refresh64, &it64, p->precision == 1 ? 1 : 0)))
             return rc;
     }
-    if (it64 > 0) it64 -= 0;
-
-    // outputs: eigenvalues, residuals, sign-fixed vectors
-    std::vector<double> th((size_t)n_obj * m), rs((size_t)n_obj * m);
+    // outputs: eigenvalues, residuals, bounds, sign-fixed vectors
+    std::vector<double> th((size_t)n_obj * m), rs((size_t)n_obj * m), eb((size_t)n_obj * m), ab((size_t)n_obj * m);
+    FF_HIP(ctx, hipMemcpyAsync(eb.data(), s.ebound, eb.size() * sizeof(double), hipMemcpyDeviceToHost, s.st));
+    FF_HIP(ctx, hipMemcpyAsync(ab.data(), s.abound, ab.size() * sizeof(double), hipMemcpyDeviceToHost, s.st));
     std::vector<int> st((size_t)n_obj), its((size_t)n_obj), inf((size_t)n_obj);
     FF_HIP(ctx, hipMemcpyAsync(th.data(), s.theta, th.size() * sizeof(double), hipMemcpyDeviceToHost, s.st));
     FF_HIP(ctx, hipMemcpyAsync(rs.data(), s.res, rs.size() * sizeof(double), hipMemcpyDeviceToHost, s.st));
@@ -2758,12 +2884,21 @@ int solve(ff_ctx *ctx, int n_obj, const int64_t *obj_off, const int64_t *row_ptr
     FF_HIP(ctx, hipStreamSynchronize(s.st));
     bool all_conv = true, broke = false;
     double worst = 0.0;
+    ctx->eb_nobj = n_obj;
+    ctx->eb_k = s.k;
+    ctx->eb_eig.assign((size_t)n_obj * s.k, INFINITY);
+    ctx->eb_angle.assign((size_t)n_obj * s.k, INFINITY);
     for (int o = 0; o < n_obj; ++o) {
-        double mx = 0.0;
+        double mx = 0.0, mxe = 0.0, mxa = 0.0;
         for (int j = 0; j < s.k; ++j) {
             eigval[(size_t)o * s.k + j] = th[(size_t)o * m + j];
             resid[(size_t)o * s.k + j] = rs[(size_t)o * m + j];
             mx = std::max(mx, rs[(size_t)o * m + j]);
+            const double e = eb[(size_t)o * m + j], a = ab[(size_t)o * m + j];
+            ctx->eb_eig[(size_t)o * s.k + j] = e;
+            ctx->eb_angle[(size_t)o * s.k + j] = a;
+            mxe = (e == e) ? std::max(mxe, e) : INFINITY;
+            mxa = (a == a) ? std::max(mxa, a) : INFINITY;
         }
         const bool conv = st[o] == 1 && mx <= p->tol;
         all_conv = all_conv && conv;
@@ -2777,6 +2912,9 @@ int solve(ff_ctx *ctx, int n_obj, const int64_t *obj_off, const int64_t *row_ptr
             info[o].restarts = (inf[o] >> 16) & 1;
             info[o].max_resid = mx;
             info[o].seconds = 0.0;
+            info[o].max_eig_bound = mxe;
+            info[o].max_angle_bound = mxa;
+            info[o].eig_certified = mxe <= (p->eig_tol > 0.0 ? p->eig_tol : 1e-5);
         }
     }
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
@@ -2813,6 +2951,15 @@ extern "C" int eigenmodes_batched(ff_ctx *ctx, int n_obj, const int64_t *obj_row
                                   ff_eig_info *info) {
     if (!ctx) return FF_ERR_INVALID_ARG;
     return solve(ctx, n_obj, obj_row_off, row_ptr, col, H, M, hm32, p, X0, eigval, W, resid, info);
+}
+
+extern "C" int eig_bounds(ff_ctx *ctx, int n_obj, int k, double *eig_bound, double *angle_bound) {
+    if (!ctx) return FF_ERR_INVALID_ARG;
+    FF_REQUIRE(ctx, n_obj == ctx->eb_nobj && k == ctx->eb_k && n_obj > 0,
+               "n_obj %d, k %d differ from the last eigensolve's (%d, %d)", n_obj, k, ctx->eb_nobj, ctx->eb_k);
+    if (eig_bound) memcpy(eig_bound, ctx->eb_eig.data(), ctx->eb_eig.size() * sizeof(double));
+    if (angle_bound) memcpy(angle_bound, ctx->eb_angle.data(), ctx->eb_angle.size() * sizeof(double));
+    return FF_OK;
 }
 
 extern "C" int spmm_hm(ff_ctx *ctx, int64_t n, const int64_t *row_ptr, const int32_t *col, const double *H,

@@ -48,13 +48,14 @@ class ff_eig_params(ctypes.Structure):
                 ("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("precond", ctypes.c_int),
                 ("seed", ctypes.c_uint64), ("check_every", ctypes.c_int), ("use_graph", ctypes.c_int),
                 ("refresh_every", ctypes.c_int), ("precond_degree", ctypes.c_int), ("precond_ratio", ctypes.c_double),
-                ("precond_values", ctypes.c_int)]
+                ("precond_values", ctypes.c_int), ("eig_tol", ctypes.c_double)]
 
 
 class ff_eig_info(ctypes.Structure):
     _fields_ = [("iters_fp32", ctypes.c_int), ("iters_fp64", ctypes.c_int), ("converged", ctypes.c_int),
                 ("restarts", ctypes.c_int), ("max_resid", ctypes.c_double), ("seconds", ctypes.c_double),
-                ("graph", ctypes.c_int)]
+                ("graph", ctypes.c_int), ("max_eig_bound", ctypes.c_double), ("max_angle_bound", ctypes.c_double),
+                ("eig_certified", ctypes.c_int)]
 
 
 _lib = None
@@ -88,6 +89,7 @@ def lib():
                              P(ff_eig_info)]),
         "eigenmodes_batched": (i32, [vp, i32, vp, vp, vp, vp, vp, vp, P(ff_eig_params), vp, vp, vp, vp,
                                      vp]),
+        "eig_bounds": (i32, [vp, i32, i32, vp, vp]),
         "spmm_hm": (i32, [vp, i64, vp, vp, vp, vp, vp, i32, i32, vp, i64, vp, vp, i64, i32]),
         "spmm_autotune": (i32, [vp, i64, vp, vp, vp, vp, vp, i32, i32, ctypes.c_char_p, P(i32), P(f64)]),
         "gram_hm": (i32, [vp, i64, i32, i32, vp, vp, vp, i64, vp]),
@@ -245,27 +247,34 @@ def assemble_HM(ctx: Context, n: int, nbr_off, nbr_id, phi, dphi, vol, lam, mu, 
 
 
 def _params(k, block, precision, tol, max_iter, precond, seed, check_every, use_graph, refresh_every,
-            precond_degree=0, precond_ratio=0.0, precond_values=0):
+            precond_degree=0, precond_ratio=0.0, precond_values=0, eig_tol=0.0):
     return ff_eig_params(k, block, precision, tol, max_iter, precond, seed, check_every, int(use_graph),
-                         refresh_every, precond_degree, float(precond_ratio), precond_values)
+                         refresh_every, precond_degree, float(precond_ratio), precond_values, float(eig_tol))
+
+
+def _info_dict(i):
+    return dict(iters_fp32=i.iters_fp32, iters_fp64=i.iters_fp64, converged=i.converged, restarts=i.restarts,
+                max_resid=i.max_resid, seconds=i.seconds, graph=i.graph, max_eig_bound=i.max_eig_bound,
+                max_angle_bound=i.max_angle_bound, eig_certified=i.eig_certified)
 
 
 def eigenmodes(ctx: Context, n: int, row_ptr, col, H, M, hm32, k: int, block: int = 0, precision: int = 1,
                tol: float = 1e-6, max_iter: int = 5000, precond: int = 2, seed: int = 0, X0=None,
                check_every: int = 10, use_graph: bool = False, refresh_every: int = 0, allow_unconverged=False,
-               precond_degree: int = 0, precond_ratio: float = 0.0, precond_values: int = 0):
+               precond_degree: int = 0, precond_ratio: float = 0.0, precond_values: int = 0, eig_tol: float = 0.0):
     import torch
     p = _params(k, block, precision, tol, max_iter, precond, seed, check_every, use_graph, refresh_every,
-                precond_degree, precond_ratio, precond_values)
+                precond_degree, precond_ratio, precond_values, eig_tol)
+    m = block if block > 0 else (k + 7) // 8 * 8
+    _check_block(X0, n, m, H.device)
     lam = np.zeros(k)
     res = np.zeros(k)
     W = torch.empty((n, k), dtype=torch.float64, device=H.device)
     info = ff_eig_info()
     rc = lib().eigenmodes(ctx.h, n, _p(row_ptr), _p(col), _p(H), _p(M), _p(hm32), ctypes.byref(p),
                           _p(X0), lam.ctypes.data_as(vp), _p(W), res.ctypes.data_as(vp), ctypes.byref(info))
-    out = dict(iters_fp32=info.iters_fp32, iters_fp64=info.iters_fp64, converged=info.converged,
-               restarts=info.restarts, max_resid=info.max_resid, seconds=info.seconds, graph=info.graph,
-               status=rc)
+    out = _info_dict(info)
+    out["status"] = rc
     if rc != 0 and not (allow_unconverged and rc == FF_ERR_NOT_CONVERGED):
         ctx.check(rc)
     return lam, W, res, out
@@ -275,13 +284,14 @@ def eigenmodes_batched(ctx: Context, obj_row_off, row_ptr, col, H, M, hm32, k: i
                        precision: int = 1, tol: float = 1e-6, max_iter: int = 5000, precond: int = 2,
                        seed: int = 0, X0=None, check_every: int = 10, use_graph: bool = False,
                        refresh_every: int = 0, allow_unconverged=False, precond_degree: int = 0,
-                       precond_ratio: float = 0.0, precond_values: int = 0):
+                       precond_ratio: float = 0.0, precond_values: int = 0, eig_tol: float = 0.0):
     import torch
     off = np.ascontiguousarray(obj_row_off, dtype=np.int64)
     n_obj = len(off) - 1
     N = int(off[-1])
     p = _params(k, block, precision, tol, max_iter, precond, seed, check_every, use_graph, refresh_every,
-                precond_degree, precond_ratio, precond_values)
+                precond_degree, precond_ratio, precond_values, eig_tol)
+    _check_block(X0, N, block if block > 0 else (k + 7) // 8 * 8, H.device)
     lam = np.zeros((n_obj, k))
     res = np.zeros((n_obj, k))
     W = torch.empty((N, k), dtype=torch.float64, device=H.device)
@@ -289,11 +299,29 @@ def eigenmodes_batched(ctx: Context, obj_row_off, row_ptr, col, H, M, hm32, k: i
     rc = lib().eigenmodes_batched(ctx.h, n_obj, off.ctypes.data_as(vp), _p(row_ptr), _p(col), _p(H), _p(M),
                                   _p(hm32), ctypes.byref(p), _p(X0), lam.ctypes.data_as(vp), _p(W),
                                   res.ctypes.data_as(vp), ctypes.cast(info, vp))
-    infos = [dict(iters_fp32=i.iters_fp32, iters_fp64=i.iters_fp64, converged=i.converged,
-                  max_resid=i.max_resid, seconds=i.seconds, graph=i.graph) for i in info]
+    infos = [_info_dict(i) for i in info]
     if rc != 0 and not (allow_unconverged and rc == FF_ERR_NOT_CONVERGED):
         ctx.check(rc)
     return lam, W, res, infos, rc
+
+
+def eig_bounds(ctx: Context, n_obj: int, k: int):
+    """(eig_bound, angle_bound), each [n_obj][k], of the last eigensolve on the context."""
+    e = np.zeros((n_obj, k))
+    a = np.zeros((n_obj, k))
+    ctx.check(lib().eig_bounds(ctx.h, n_obj, k, e.ctypes.data_as(vp), a.ctypes.data_as(vp)))
+    return e, a
+
+
+def _check_block(X0, n, m, device):
+    """A starting block must be FP64, contiguous, on the solver's device and [n][m] (the library
+    reads n * m doubles from it)."""
+    import torch
+    if X0 is None:
+        return
+    if X0.dtype != torch.float64 or not X0.is_contiguous() or X0.device != device or tuple(X0.shape) != (n, m):
+        raise FFError(FF_ERR_INVALID_ARG, f"X0 must be a contiguous float64 [{n}][{m}] tensor on {device}, got "
+                      f"{X0.dtype} {tuple(X0.shape)} on {X0.device} (contiguous={X0.is_contiguous()})")
 
 
 def spmm_hm(ctx: Context, row_ptr, col, H, M, hm32, Y, precision: int, variant: int = -1, out=None):

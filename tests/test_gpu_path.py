@@ -85,6 +85,15 @@ def test_shape_functions(case):
     assert np.abs(dphi - P.dphi).max() <= 1e-12 * np.abs(P.dphi).max()
 
 
+def test_shape_functions_gaussian(case, oracle, ctx, ff):
+    """kernel 1 (the Gaussian of Sec. 3.2, r = h/2, cut at h) on the same lists."""
+    name, c, P, A = case
+    phi_o, dphi_o = oracle.rkpm(P.xyz, P.xyz, P.nbr_off, P.nbr_id, c.h, kernel=1)
+    phi, dphi, _ = ff.rkpm_shape(ctx, A.nb.xyz_sorted, A.nb.nbr_off, A.nb.nbr_id, c.h, kernel=1)
+    assert np.abs(host(phi) - phi_o).max() <= 1e-12
+    assert np.abs(host(dphi) - dphi_o).max() <= 1e-12 * np.abs(dphi_o).max()
+
+
 def test_assembly(case):
     name, c, P, A = case
     assert np.array_equal(host(A.row_ptr), P.row_ptr)
@@ -195,6 +204,50 @@ def test_separate_quadrature_points(oracle, ctx, ff):
     if (cnt >= 4).all():
         pytest.skip("no singular point in this draw")
     assert ei.value.code == ff.FF_ERR_SINGULAR_MOMENT
+
+
+@pytest.mark.parametrize("shuffled", [False, True])
+@pytest.mark.parametrize("kernel", [0, 1])
+def test_assembly_separate_quadrature_points(oracle, ctx, ff, kernel, shuffled):
+    """q != n: 2,600 quadrature points on a jittered grid inside the node box (every one sees
+    enough nodes), their own weights and material; the per-point arrays either in quadrature
+    order (perm NULL) or shuffled, with perm[i] naming point i's entry. Pattern bit-exact,
+    values to 1e-12 of their scale."""
+    c = synth.random_cloud(2000, seed=44, hetero=True)
+    rng = np.random.default_rng(8)
+    g = (np.arange(14) + 0.5) / 14
+    q = np.stack(np.meshgrid(g, g, g, indexing="ij"), axis=-1).reshape(-1, 3)[:2600]
+    q = np.clip(q + rng.uniform(-0.01, 0.01, q.shape), 0.02, 0.98)
+    nq = q.shape[0]
+    vol = np.full(nq, 1.0 / nq)
+    E = np.exp(rng.uniform(np.log(1e4), np.log(1e6), nq))
+    lam, mu = synth.lame_from_young(E, rng.uniform(0.3, 0.48, nq))
+    perm_n, cs, origin, dims = oracle.bin_nodes(c.xyz, c.h)
+    xs = np.ascontiguousarray(c.xyz[perm_n])
+    off, ids = oracle.neighbors(q, xs, c.h, origin, dims, cs)
+    phi, dphi = oracle.rkpm(q, xs, off, ids, c.h, kernel=kernel)
+    rp, col, H, M = oracle.assemble(c.n, off, ids, phi, dphi, vol, lam, mu)
+    nb = ff.build_neighbors(ctx, dev(c.xyz), c.h, qxyz=dev(q))
+    assert np.array_equal(host(nb.nbr_id), ids)
+    gphi, gdphi, _ = ff.rkpm_shape(ctx, nb.xyz_sorted, nb.nbr_off, nb.nbr_id, c.h, qxyz=dev(q), kernel=kernel)
+    assert np.abs(host(gphi) - phi).max() <= 1e-12
+    assert np.abs(host(gdphi) - dphi).max() <= 1e-12 * np.abs(dphi).max()
+    if shuffled:
+        sig = rng.permutation(nq).astype(np.int32)       # point i's values sit at entry sig[i]
+        store = lambda a: np.empty_like(a)
+        v2, l2, m2 = store(vol), store(lam), store(mu)
+        v2[sig], l2[sig], m2[sig] = vol, lam, mu
+        args = dict(perm=dev(sig, torch.int32))
+        vol_d, lam_d, mu_d = dev(v2), dev(l2), dev(m2)
+    else:
+        args = {}
+        vol_d, lam_d, mu_d = dev(vol), dev(lam), dev(mu)
+    grp, gcol, gH, gM, _ = ff.assemble_HM(ctx, c.n, nb.nbr_off, nb.nbr_id, gphi, gdphi, vol_d, lam_d, mu_d, nb.grid,
+                                         nb.cell_start, **args)
+    assert np.array_equal(host(grp), rp)
+    assert np.array_equal(host(gcol), col)
+    assert np.abs(host(gH) - H).max() <= 1e-12 * np.abs(H).max()
+    assert np.abs(host(gM) - M).max() <= 1e-12 * np.abs(M).max()
 
 
 def test_singular_moment_index(ctx, ff):
