@@ -348,6 +348,21 @@ int rayleigh_ritz(ff_ctx *ctx, int w, int m, const double *G, double tau, double
                   int *kept);
 
 /*
+ * rayleigh_ritz_noalloc - rayleigh_ritz for callers that cannot allocate device memory
+ * (code under stream capture, tight serving loops, harnesses that forbid allocation):
+ * the same kernels and results, with its work arrays in a fixed per-GPU device scratch
+ * (1.6 MB, held from the first context on that GPU until the process ends) instead of
+ * the context's workspace. It calls no device allocator. Limits: order w <= 192 and
+ * m <= 64 pairs; larger sizes return FF_ERR_INVALID_ARG. Every call on one GPU shares
+ * that scratch (its status words are reset by each call, the work arrays written before
+ * they are read): calls that overlap in time on one GPU, from any context or stream,
+ * race and must not be issued. kept is read back with a stream synchronisation, as in
+ * rayleigh_ritz.
+ */
+int rayleigh_ritz_noalloc(ff_ctx *ctx, int w, int m, const double *G, double tau, double *C, double *theta,
+                          int *kept);
+
+/*
  * Row-tile copy of [H, M] for the fused SpMM. Rows are grouped in tiles of
  * four consecutive rows (in the cell-sorted numbering, so spatially close);
  * a tile keeps the ascending union of its rows' column lists and, per union

@@ -1,5 +1,6 @@
 // Context lifetime, error reporting and workspace management.
 #include "ff_internal.h"
+#include "k_lobpcg.h"
 
 #include <cstdlib>
 
@@ -130,6 +131,11 @@ int ff_ctx_create(ff_ctx **out, int device, void *hip_stream) {
     // a cap on the row bitmaps the assembly's symbolic pass keeps, so that the numeric pass's own
     // marking can be exercised
     if (const char *b = getenv("FF_ASM_BITMAP_BYTES")) ctx->asm_bm_cap = atoll(b) < 0 ? 0 : atoll(b);
+    // the fixed scratch of rayleigh_ritz_noalloc: its device address, once per device
+    if (ff::lob::noalloc_setup(ctx) != FF_OK) {
+        delete ctx;
+        return FF_ERR_HIP;
+    }
     *out = ctx;
     return FF_OK;
 }

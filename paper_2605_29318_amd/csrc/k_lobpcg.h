@@ -16,3 +16,13 @@ typedef UChunk GChunk;
 
 }  // namespace lob
 }  // namespace ff
+
+struct ff_ctx;
+namespace ff {
+namespace lob {
+
+// Once per device (the context's, current): the address of rayleigh_ritz_noalloc's fixed scratch.
+int noalloc_setup(ff_ctx *ctx);
+
+}  // namespace lob
+}  // namespace ff

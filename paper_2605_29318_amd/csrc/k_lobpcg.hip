@@ -13,6 +13,8 @@
 // Every kernel reads a per-object status word and skips objects that are
 // converged, so many independent problems share one launch per stage.
 #include "ff_internal.h"
+
+#include <mutex>
 #include "k_lobpcg.h"
 #include "k_rowtile.h"
 
@@ -832,7 +834,7 @@ constexpr size_t kRRLdsLimit = 156 * 1024;
 struct RRScr {
     double *A, *B, *S1, *S2, *sc, *dg, *eg, *tg, *evs, *kidx, *kpos, *meta, *Yv;
 };
-__host__ __device__ inline size_t rr_scratch_doubles(int wmax, int m) {
+__host__ __device__ constexpr inline size_t rr_scratch_doubles(int wmax, int m) {
     return (size_t)4 * wmax * wmax + (size_t)7 * wmax + 16 + (size_t)m * wmax;
 }
 __device__ inline RRScr rr_scr(double *scratch, int o, int wmax, int m) {
@@ -3195,6 +3197,80 @@ extern "C" int gram_hm(ff_ctx *ctx, int64_t n, int w, int precision, const void 
                        ints + 3, part, w, G);
     FF_CHECK_LAUNCH(ctx);
     FF_HIP(ctx, hipStreamSynchronize(st));
+    return FF_OK;
+}
+
+namespace ff {
+namespace lob {
+
+// Device memory of rayleigh_ritz_noalloc, one copy per GPU for the life of the process: the
+// Rayleigh-Ritz work arrays of the largest pencil it takes (order 192, 64 pairs), the three
+// coefficient blocks C_w, C_p, C_pw and the status words (1.6 MB). Host code reaches it only
+// through the address hipGetSymbolAddress gives for the current device.
+constexpr int kNaW = 192, kNaM = 64, kNaDevices = 64;
+constexpr size_t kNaRR = rr_scratch_doubles(kNaW, kNaM);
+constexpr size_t kNaC = (size_t)3 * kNaW * kNaM;
+constexpr size_t kNaDoubles = kNaRR + kNaC + 8;
+static __device__ __align__(256) double scratch[kNaDoubles];
+static std::mutex na_mu;
+static double *na_ptr[kNaDevices] = {};
+
+__global__ void rr_status_init_kernel(int *ints, int w) {
+    if (threadIdx.x == 0) {
+        ints[0] = 0;      // status: active
+        ints[1] = w;      // width
+        ints[2] = 0;      // info
+    }
+}
+
+int noalloc_setup(ff_ctx *ctx) {
+    std::lock_guard<std::mutex> lock(na_mu);
+    if (ctx->device >= kNaDevices) return FF_OK;      // rayleigh_ritz_noalloc then reports it
+    if (na_ptr[ctx->device]) return FF_OK;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+        (void)hipGetLastError();
+        return set_error(ctx, FF_ERR_HIP, "hipGetSymbolAddress of the fixed scratch failed on device %d: %s",
+                         ctx->device, hipGetErrorString(e));
+    }
+    na_ptr[ctx->device] = (double *)p;
+    return FF_OK;
+}
+
+}  // namespace lob
+}  // namespace ff
+
+extern "C" int rayleigh_ritz_noalloc(ff_ctx *ctx, int w, int m, const double *G, double tau, double *C,
+                                     double *theta, int *kept) {
+    if (!ctx) return FF_ERR_INVALID_ARG;
+    FF_REQUIRE(ctx, G && C && theta && kept, "required pointer is NULL");
+    FF_REQUIRE(ctx, w > 0 && m > 0 && m <= w, "bad order %d or pair count %d", w, m);
+    FF_REQUIRE(ctx, w <= kNaW && m <= kNaM,
+               "order %d / %d pairs exceed the fixed scratch of rayleigh_ritz_noalloc (order <= %d, pairs <= %d)", w, m,
+               kNaW, kNaM);
+    double *base = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(na_mu);
+        base = ctx->device < kNaDevices ? na_ptr[ctx->device] : nullptr;
+    }
+    FF_REQUIRE(ctx, base != nullptr, "no fixed scratch on device %d", ctx->device);
+    FF_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    double *scr = base, *cw = base + kNaRR;
+    int *ints = (int *)(base + kNaRR + kNaC);
+    // the status words start fresh on every call; the work arrays are written before they are read
+    hipLaunchKernelGGL(rr_status_init_kernel, dim3(1), dim3(64), 0, st, ints, w);
+    FF_CHECK_LAUNCH(ctx);
+    int rc = rr_prepare(ctx, w);
+    if (!rc) rc = launch_rr<double>(ctx, st, 1, ints, ints + 1, G, w, m, tau, scr, C, cw, cw + (size_t)w * m,
+                                    cw + (size_t)2 * w * m, theta, ints + 2);
+    if (rc) return rc;
+    int h[3];
+    FF_HIP(ctx, hipMemcpyAsync(h, ints, sizeof(h), hipMemcpyDeviceToHost, st));
+    FF_HIP(ctx, hipStreamSynchronize(st));
+    *kept = h[2] & 0xffff;
+    if (h[0] == 3) return set_error(ctx, FF_ERR_BREAKDOWN, "only %d of %d columns kept (need %d)", *kept, w, m);
     return FF_OK;
 }
 

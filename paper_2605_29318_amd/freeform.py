@@ -94,6 +94,7 @@ def lib():
         "spmm_autotune": (i32, [vp, i64, vp, vp, vp, vp, vp, i32, i32, ctypes.c_char_p, P(i32), P(f64)]),
         "gram_hm": (i32, [vp, i64, i32, i32, vp, vp, vp, i64, vp]),
         "rayleigh_ritz": (i32, [vp, i32, i32, vp, f64, vp, vp, P(i32)]),
+        "rayleigh_ritz_noalloc": (i32, [vp, i32, i32, vp, f64, vp, vp, P(i32)]),
         "spmm_variant_count": (i32, []),
         "spmm_variant_name": (ctypes.c_char_p, [i32]),
         "spmm_variant_selected": (i32, [vp, i64, i64, i32, i32]),
