@@ -131,6 +131,60 @@ int build_neighbors(ff_ctx *ctx, int64_t n, const double *xyz, int64_t q, const 
                     int64_t nbr_cap, int64_t *nbr_total);
 
 /*
+ * build_neighbors_radii - build_neighbors with a support radius per node: the pairs
+ * d^2 < R_j * R_j (same d^2 as build_neighbors) of the kernels of the paper's own
+ * construction (Supp. B.1, "RKPM construction"), whose Gaussians have a radius per
+ * centre. radius [n] device in, original node order, finite and positive; the cell
+ * grid's edge h is the largest radius (grid->h), so a point's neighbours lie in the
+ * 27 cells around it. Everything else as build_neighbors.
+ */
+int build_neighbors_radii(ff_ctx *ctx, int64_t n, const double *xyz, const double *radius, int64_t q,
+                          const double *qxyz, ff_grid *grid, int32_t *perm, double *xyz_sorted,
+                          int64_t *cell_start, int64_t cell_cap, int64_t *nbr_off, int32_t *nbr_id,
+                          int64_t nbr_cap, int64_t *nbr_total);
+
+/*
+ * fps_centers - farthest point sampling of K kernel centres among q integration points
+ * (Supp. B.1, "RKPM construction": the centres are spread evenly over the object).
+ * out_idx[0] = start; out_idx[t] = the point whose squared distance to its nearest
+ * already picked point is largest, ties to the lowest index; squared distances are
+ * ((dx*dx)+(dy*dy))+(dz*dz) in IEEE double, so the picks are exact.
+ *  qxyz    [q][3] device in;   out_idx [K] device out;
+ *  out_xyz [K][3] device out or NULL: the picked points, in pick order
+ * Errors: FF_ERR_INVALID_ARG (K outside [1, q], start outside [0, q), a non-finite point).
+ */
+int fps_centers(ff_ctx *ctx, int64_t q, const double *qxyz, int K, int64_t start, int32_t *out_idx,
+                double *out_xyz);
+
+/*
+ * kernel_radii - the radius of each centre's Gaussian (Supp. B.1: the smallest distance
+ * that reaches two other centres, i.e. the distance to the 2nd-nearest other centre),
+ * r_k = sqrt(second smallest d^2), and the support radius R_k = cut * r_k of the cut
+ * kernel of rkpm_shape_radii. centres [K][3] device in (K >= 3); r, R [K] device out.
+ */
+int kernel_radii(ff_ctx *ctx, int64_t K, const double *centres, double cut, double *r, double *R);
+
+/*
+ * rkpm_shape_radii - shape functions and gradients on the paper's own kernels: a
+ * Gaussian exp(-|X - p_k|^2 / r_k^2) per centre (Sec. 3.2), cut at |X - p_k| = cut r_k
+ * with its tangent in s = d^2/r_k^2 subtracted, so that value and slope vanish there:
+ *   w_k = exp(-s) - exp(-cut^2) (1 + cut^2 - s)   (s < cut^2, else 0).
+ * basis selects what is built on them (Sec. 3.2 and the comparison of its Fig. 3b):
+ *   0  plain RBF                phi_k = w_k
+ *   1  partition-of-unity RBF   phi_k = w_k / sum_j w_j
+ *   2  RKPM, linear basis       Eq. (7)-(11), in the shifted basis [1, (p_k - X)/h]
+ * with exact gradients in X. node_r [n]: each centre's r_k, sorted numbering, or in
+ * original order when perm (from build_neighbors_radii) is given; h: the scale of the
+ * shifted basis (any positive value gives the same phi in exact arithmetic; pass
+ * grid->h). Lists, layout and bad_index as rkpm_shape (bad_index also names a point
+ * whose kernel sum is zero for basis 1).
+ */
+int rkpm_shape_radii(ff_ctx *ctx, int64_t n, const double *xyz_sorted, const double *node_r,
+                     const int32_t *perm, int64_t q, const double *qxyz, const int64_t *nbr_off,
+                     const int32_t *nbr_id, int64_t nbr_total, double h, double cut, int basis,
+                     double *phi, double *dphi, int64_t *bad_index);
+
+/*
  * rkpm_shape - RKPM shape functions and gradients, Sec. 3.2 Eq. (7)-(11).
  *
  * For quadrature point X_i and each neighbour k in its list (linear basis

@@ -507,3 +507,235 @@ double orc_norm_inf(int64_t n, const int64_t *row_ptr, const double *val)
     }
     return best;
 }
+
+/* ------------------------------------------------------------------------ */
+/* The paper's own construction (Supp. B.1, "RKPM construction"):            */
+/* integration points, farthest-point-sampled centres, a Gaussian kernel     */
+/* per centre whose radius is the distance to its 2nd-nearest centre.        */
+/* ------------------------------------------------------------------------ */
+
+static double dist2(const double *a, const double *b)
+{
+    double dx = a[0] - b[0], dy = a[1] - b[1], dz = a[2] - b[2];
+    return ((dx * dx) + (dy * dy)) + (dz * dz);
+}
+
+/* Farthest point sampling: out[0] = start; out[t] = the point whose squared
+ * distance to its nearest already chosen point is largest (ties: lowest
+ * index). Requires 1 <= K <= q. */
+int orc_fps(int64_t q, const double *xyz, int64_t K, int64_t start, int32_t *out)
+{
+    if (K < 1 || K > q || start < 0 || start >= q) return ORC_ERR_ARG;
+    double *md = (double *)malloc((size_t)q * sizeof(double));
+    if (!md) return ORC_ERR_ARG;
+    for (int64_t i = 0; i < q; ++i) md[i] = INFINITY;
+    int64_t last = start;
+    out[0] = (int32_t)start;
+    for (int64_t t = 1; t < K; ++t) {
+        int64_t best = -1;
+        double bv = -1.0;
+        for (int64_t i = 0; i < q; ++i) {
+            double d = dist2(xyz + 3 * i, xyz + 3 * last);
+            if (d < md[i]) md[i] = d;
+            if (md[i] > bv) { bv = md[i]; best = i; }
+        }
+        out[t] = (int32_t)best;
+        last = best;
+    }
+    free(md);
+    return ORC_OK;
+}
+
+/* Per centre: r_k = distance to the 2nd-nearest other centre (the minimal
+ * distance that reaches two other centres), and the support radius
+ * R_k = cut * r_k of the truncated kernel. Requires K >= 3. */
+int orc_radii(int64_t K, const double *c, double cut, double *r, double *R)
+{
+    if (K < 3) return ORC_ERR_ARG;
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < K; ++k) {
+        double d1 = INFINITY, d2 = INFINITY;            /* two smallest squared distances */
+        for (int64_t j = 0; j < K; ++j) {
+            if (j == k) continue;
+            double d = dist2(c + 3 * k, c + 3 * j);
+            if (d < d1) { d2 = d1; d1 = d; }
+            else if (d < d2) d2 = d;
+        }
+        r[k] = sqrt(d2);
+        R[k] = cut * r[k];
+    }
+    return ORC_OK;
+}
+
+/* Neighbour lists with a support radius per node: N(X) = { k : d^2 < R_k R_k },
+ * over the 27 cells around X of the grid of edge h >= max R_k; ascending. */
+static int64_t scan_point_var(const double *X, const double *xyz_sorted, const double *R_sorted, double h,
+                              const double *origin, const int64_t *dims, const int64_t *cell_start, int32_t *out)
+{
+    int64_t c[3];
+    for (int a = 0; a < 3; ++a) c[a] = cell_coord(X[a], origin[a], h, dims[a]);
+    int64_t cnt = 0;
+    for (int64_t z = c[2] - 1; z <= c[2] + 1; ++z) {
+        if (z < 0 || z >= dims[2]) continue;
+        for (int64_t y = c[1] - 1; y <= c[1] + 1; ++y) {
+            if (y < 0 || y >= dims[1]) continue;
+            for (int64_t x = c[0] - 1; x <= c[0] + 1; ++x) {
+                if (x < 0 || x >= dims[0]) continue;
+                int64_t cell = (z * dims[1] + y) * dims[0] + x;
+                for (int64_t j = cell_start[cell]; j < cell_start[cell + 1]; ++j) {
+                    double Rj = R_sorted[j];
+                    if (dist2(X, xyz_sorted + 3 * j) < Rj * Rj) {
+                        if (out) out[cnt] = (int32_t)j;
+                        ++cnt;
+                    }
+                }
+            }
+        }
+    }
+    return cnt;
+}
+
+int64_t orc_neighbors_var(int64_t q, const double *qxyz, const double *xyz_sorted, const double *R_sorted,
+                          double h, const double *origin, const int64_t *dims, const int64_t *cell_start,
+                          int64_t *nbr_off, int32_t *nbr_id)
+{
+    if (!nbr_id) {
+        int64_t *cnt = nbr_off + 1;
+#pragma omp parallel for schedule(dynamic, 256)
+        for (int64_t i = 0; i < q; ++i)
+            cnt[i] = scan_point_var(qxyz + 3 * i, xyz_sorted, R_sorted, h, origin, dims, cell_start, NULL);
+        nbr_off[0] = 0;
+        for (int64_t i = 0; i < q; ++i) nbr_off[i + 1] += nbr_off[i];
+        return nbr_off[q];
+    }
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t i = 0; i < q; ++i)
+        scan_point_var(qxyz + 3 * i, xyz_sorted, R_sorted, h, origin, dims, cell_start, nbr_id + nbr_off[i]);
+    return nbr_off[q];
+}
+
+/* the same predicate by exhaustive search (pin) */
+int64_t orc_neighbors_var_brute(int64_t q, const double *qxyz, int64_t n, const double *xyz_sorted,
+                                const double *R_sorted, int64_t *nbr_off, int32_t *nbr_id)
+{
+    int64_t tot = 0;
+    nbr_off[0] = 0;
+    for (int64_t i = 0; i < q; ++i) {
+        for (int64_t j = 0; j < n; ++j)
+            if (dist2(qxyz + 3 * i, xyz_sorted + 3 * j) < R_sorted[j] * R_sorted[j]) {
+                if (nbr_id) nbr_id[tot] = (int32_t)j;
+                ++tot;
+            }
+        nbr_off[i + 1] = tot;
+    }
+    return tot;
+}
+
+/* Gaussian exp(-s), s = d^2/r^2 (Sec. 3.2), cut at s = c^2 with the tangent
+ * subtracted so that value and slope vanish there:
+ *   w(s) = exp(-s) - exp(-c^2) (1 + c^2 - s),   dw/ds = -exp(-s) + exp(-c^2)   (s < c^2)
+ * and 0 beyond; grad_X w = dw/ds * 2 (X - p) / r^2. */
+static void gauss_cut(double d2, double rk, double cut, double *w, double *g_over_r)
+{
+    double s = d2 / (rk * rk), c2 = cut * cut;
+    if (s < c2) {
+        double e = exp(-s), ec = exp(-c2);
+        *w = e - ec * (1.0 + c2 - s);
+        *g_over_r = (-e + ec) * 2.0 / (rk * rk);    /* grad = g_over_r * (X - p) */
+    } else {
+        *w = 0.0;
+        *g_over_r = 0.0;
+    }
+}
+
+/* Shape functions on the centres' kernels with three bases (Sec. 3.2, Fig. 3b):
+ *   basis 0  plain RBF:               phi_k = w_k
+ *   basis 1  partition-of-unity RBF:  phi_k = w_k / sum_j w_j
+ *   basis 2  RKPM, linear basis:      Eq. (7)-(11), evaluated as orc_rkpm in the
+ *            shifted basis [1, (p_k - X)/h] with h the given scale
+ * with exact gradients. r_sorted[k] is centre k's Gaussian radius. A singular
+ * moment matrix (basis 2) or an empty kernel sum (basis 1) reports the point. */
+int orc_rkpm_var(int64_t q, const double *qxyz, const double *xyz_sorted, const double *r_sorted,
+                 const int64_t *nbr_off, const int32_t *nbr_id, double h, double cut, int basis,
+                 double *phi, double *dphi, int64_t *bad_index)
+{
+    int64_t bad = -1;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < q; ++i) {
+        const double *X = qxyz + 3 * i;
+        double Mh[4][4] = {{0}}, dM[3][4][4] = {{{0}}}, S = 0.0, dS[3] = {0.0, 0.0, 0.0};
+        for (int64_t e = nbr_off[i]; e < nbr_off[i + 1]; ++e) {
+            int64_t k = nbr_id[e];
+            const double *p = xyz_sorted + 3 * k;
+            double rv[3] = {X[0] - p[0], X[1] - p[1], X[2] - p[2]};
+            double wt, go;
+            gauss_cut(dist2(X, p), r_sorted[k], cut, &wt, &go);
+            double g[3] = {go * rv[0], go * rv[1], go * rv[2]};
+            S += wt;
+            for (int s = 0; s < 3; ++s) dS[s] += g[s];
+            if (basis == 2) {
+                double P[4] = {1.0, -rv[0] / h, -rv[1] / h, -rv[2] / h};
+                for (int a = 0; a < 4; ++a)
+                    for (int b2 = 0; b2 < 4; ++b2) Mh[a][b2] += wt * P[a] * P[b2];
+                for (int s = 0; s < 3; ++s) {
+                    double dP[4] = {0.0, 0.0, 0.0, 0.0};
+                    dP[s + 1] = -1.0 / h;
+                    for (int a = 0; a < 4; ++a)
+                        for (int b2 = 0; b2 < 4; ++b2)
+                            dM[s][a][b2] += g[s] * P[a] * P[b2] + wt * (dP[a] * P[b2] + P[a] * dP[b2]);
+                }
+            }
+        }
+        double L[4][4], b[4] = {0}, db[3][4] = {{0}};
+        int ok = 1;
+        if (basis == 2) {
+            ok = chol4(Mh, L);
+            if (ok) {
+                double e1[4] = {1.0, 0.0, 0.0, 0.0};
+                chol4_solve(L, e1, b);
+                for (int s = 0; s < 3; ++s) {
+                    double t[4];
+                    for (int a = 0; a < 4; ++a) {
+                        t[a] = 0.0;
+                        for (int c = 0; c < 4; ++c) t[a] += dM[s][a][c] * b[c];
+                    }
+                    chol4_solve(L, t, db[s]);
+                    for (int a = 0; a < 4; ++a) db[s][a] = -db[s][a];
+                }
+            }
+        } else if (basis == 1) {
+            ok = S > 0.0;
+        }
+        if (!ok) {
+#pragma omp critical
+            { if (bad < 0 || i < bad) bad = i; }
+            continue;
+        }
+        for (int64_t e = nbr_off[i]; e < nbr_off[i + 1]; ++e) {
+            int64_t k = nbr_id[e];
+            const double *p = xyz_sorted + 3 * k;
+            double rv[3] = {X[0] - p[0], X[1] - p[1], X[2] - p[2]};
+            double wt, go;
+            gauss_cut(dist2(X, p), r_sorted[k], cut, &wt, &go);
+            if (basis == 0) {
+                phi[e] = wt;
+                for (int s = 0; s < 3; ++s) dphi[3 * e + s] = go * rv[s];
+            } else if (basis == 1) {
+                phi[e] = wt / S;
+                for (int s = 0; s < 3; ++s) dphi[3 * e + s] = go * rv[s] / S - wt * dS[s] / (S * S);
+            } else {
+                double P[4] = {1.0, -rv[0] / h, -rv[1] / h, -rv[2] / h};
+                double Pb = 0.0;
+                for (int a = 0; a < 4; ++a) Pb += P[a] * b[a];
+                phi[e] = wt * Pb;
+                for (int s = 0; s < 3; ++s) {
+                    double Pdb = 0.0;
+                    for (int a = 0; a < 4; ++a) Pdb += P[a] * db[s][a];
+                    dphi[3 * e + s] = go * rv[s] * Pb + wt * (-b[s + 1] / h) + wt * Pdb;
+                }
+            }
+        }
+    }
+    if (bad_index) *bad_index = bad;
+    return bad >= 0 ? ORC_ERR_SINGULAR : ORC_OK;
+}

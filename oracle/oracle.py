@@ -78,6 +78,18 @@ def lib():
         L.orc_spmm.restype = None
         L.orc_norm_inf.argtypes = [ctypes.c_int64, _i64p, _f64p]
         L.orc_norm_inf.restype = ctypes.c_double
+        L.orc_fps.argtypes = [ctypes.c_int64, _f64p, ctypes.c_int64, ctypes.c_int64, _i32p]
+        L.orc_fps.restype = ctypes.c_int
+        L.orc_radii.argtypes = [ctypes.c_int64, _f64p, ctypes.c_double, _f64p, _f64p]
+        L.orc_radii.restype = ctypes.c_int
+        L.orc_neighbors_var.argtypes = [ctypes.c_int64, _f64p, _f64p, _f64p, ctypes.c_double, _f64p, _i64p,
+                                        _i64p, _i64p, vp]
+        L.orc_neighbors_var.restype = ctypes.c_int64
+        L.orc_neighbors_var_brute.argtypes = [ctypes.c_int64, _f64p, ctypes.c_int64, _f64p, _f64p, _i64p, vp]
+        L.orc_neighbors_var_brute.restype = ctypes.c_int64
+        L.orc_rkpm_var.argtypes = [ctypes.c_int64, _f64p, _f64p, _f64p, _i64p, _i32p, ctypes.c_double,
+                                   ctypes.c_double, ctypes.c_int, _f64p, _f64p, ctypes.POINTER(ctypes.c_int64)]
+        L.orc_rkpm_var.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -281,6 +293,120 @@ def pipeline(cloud, use_rho: bool = False, kernel: int = 0) -> Problem:
     return Problem(cloud.n, cloud.h, perm, cs, origin, dims, xs, off, ids, phi, dphi,
                    np.ascontiguousarray(vol), np.ascontiguousarray(lam), np.ascontiguousarray(mu),
                    rho, rp, col, H, M)
+
+
+# ----------------------------------------------------------------------------
+# the paper's own construction (Supp. B.1 "RKPM construction"): integration points,
+# farthest-point-sampled centres, a Gaussian per centre whose radius reaches two other
+# centres; plain RBF, partition-of-unity RBF and RKPM bases (Sec. 3.2, Fig. 3b)
+# ----------------------------------------------------------------------------
+
+BASIS_RBF, BASIS_PU, BASIS_RKPM = 0, 1, 2
+
+
+def fps(xyz, K, start=0):
+    """Farthest point sampling of K of the points, from ``start``; ties to the lowest index."""
+    xyz = _c(xyz, np.float64)
+    out = np.zeros(int(K), dtype=np.int32)
+    if lib().orc_fps(xyz.shape[0], xyz, int(K), int(start), out) != 0:
+        raise ValueError("bad FPS arguments")
+    return out
+
+
+def radii(centres, cut=3.0):
+    """r_k = distance to the 2nd-nearest other centre; R_k = cut * r_k (support of the cut kernel)."""
+    c = _c(centres, np.float64)
+    r = np.zeros(c.shape[0])
+    R = np.zeros(c.shape[0])
+    if lib().orc_radii(c.shape[0], c, float(cut), r, R) != 0:
+        raise ValueError("need at least 3 centres")
+    return r, R
+
+
+def neighbors_var(qxyz, xyz_sorted, R_sorted, h, origin, dims, cell_start):
+    qxyz = _c(qxyz, np.float64)
+    q = qxyz.shape[0]
+    off = np.zeros(q + 1, dtype=np.int64)
+    args = (_c(xyz_sorted, np.float64), _c(R_sorted, np.float64), float(h), _c(origin, np.float64),
+            _c(dims, np.int64), _c(cell_start, np.int64), off)
+    tot = lib().orc_neighbors_var(q, qxyz, *args, None)
+    ids = np.zeros(max(tot, 1), dtype=np.int32)
+    lib().orc_neighbors_var(q, qxyz, *args, _ptr(ids))
+    return off, ids[:tot]
+
+
+def neighbors_var_brute(qxyz, xyz_sorted, R_sorted):
+    qxyz = _c(qxyz, np.float64)
+    xs = _c(xyz_sorted, np.float64)
+    q = qxyz.shape[0]
+    off = np.zeros(q + 1, dtype=np.int64)
+    tot = lib().orc_neighbors_var_brute(q, qxyz, xs.shape[0], xs, _c(R_sorted, np.float64), off, None)
+    ids = np.zeros(max(tot, 1), dtype=np.int32)
+    lib().orc_neighbors_var_brute(q, qxyz, xs.shape[0], xs, _c(R_sorted, np.float64), off, _ptr(ids))
+    return off, ids[:tot]
+
+
+def rkpm_var(qxyz, xyz_sorted, r_sorted, off, ids, h, cut=3.0, basis=BASIS_RKPM):
+    """phi, dphi on the centres' cut Gaussians for the given basis (0 RBF, 1 PU-RBF, 2 RKPM)."""
+    nnz = int(off[-1])
+    phi = np.zeros(max(nnz, 1))
+    dphi = np.zeros((max(nnz, 1), 3))
+    bad = ctypes.c_int64(-1)
+    rc = lib().orc_rkpm_var(len(off) - 1, _c(qxyz, np.float64), _c(xyz_sorted, np.float64),
+                            _c(r_sorted, np.float64), _c(off, np.int64), _c(ids, np.int32), float(h),
+                            float(cut), int(basis), phi, dphi, ctypes.byref(bad))
+    if rc != 0:
+        raise SingularMoment(bad.value)
+    return phi[:nnz], dphi[:nnz]
+
+
+@dataclass
+class PaperProblem:
+    """The paper's construction for one object, centres in sorted (cell) numbering."""
+    K: int
+    centre_idx: np.ndarray      # [K] FPS picks: indices into the integration points, in pick order
+    perm: np.ndarray            # [K] sorted centre j = pick perm[j]
+    xyz: np.ndarray             # [K][3] centres, sorted
+    r: np.ndarray               # [K] Gaussian radius, sorted
+    R: np.ndarray               # [K] support radius, sorted
+    h: float                    # cell edge = max R
+    origin: np.ndarray
+    dims: np.ndarray
+    cell_start: np.ndarray
+    qxyz: np.ndarray
+    nbr_off: np.ndarray
+    nbr_id: np.ndarray
+    phi: np.ndarray
+    dphi: np.ndarray
+    row_ptr: np.ndarray
+    col: np.ndarray
+    H: np.ndarray
+    M: np.ndarray
+
+    def Hs(self):
+        return to_scipy(self.K, self.row_ptr, self.col, self.H)
+
+    def Ms(self):
+        return to_scipy(self.K, self.row_ptr, self.col, self.M)
+
+
+def paper_pipeline(qxyz, vol, lam, mu, K, cut=3.0, basis=BASIS_RKPM, start=0, rho=None) -> PaperProblem:
+    """Supp. B.1: K centres by FPS over the integration points, r_k to the 2nd-nearest centre,
+    neighbour lists d^2 < R_k^2 on a grid of edge max R, shape functions (Sec. 3.2) and
+    H (Prop. 1), M (Eq. (14)) with the integration points as quadrature (weights vol)."""
+    qxyz = _c(qxyz, np.float64)
+    pick = fps(qxyz, K, start)
+    cen = qxyz[pick]
+    r, R = radii(cen, cut)
+    h = float(R.max())
+    perm, cs, origin, dims = bin_nodes(cen, h)
+    xs = np.ascontiguousarray(cen[perm])
+    rs, Rs = r[perm], R[perm]
+    off, ids = neighbors_var(qxyz, xs, Rs, h, origin, dims, cs)
+    phi, dphi = rkpm_var(qxyz, xs, rs, off, ids, h, cut, basis)
+    rp, col, H, M = assemble(K, off, ids, phi, dphi, vol, lam, mu, rho)
+    return PaperProblem(int(K), pick, perm, xs, rs, Rs, h, origin, dims, cs, qxyz, off, ids, phi, dphi,
+                        rp, col, H, M)
 
 
 # ----------------------------------------------------------------------------

@@ -26,6 +26,7 @@ SOURCES = [
     ("k_lobpcg.hip", False),
     ("k_mlp.hip", False),
     ("k_rowtile.hip", False),
+    ("k_paper.hip", True),
 ]
 
 COMMON = ["-x", "hip", "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",

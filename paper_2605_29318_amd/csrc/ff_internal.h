@@ -36,6 +36,7 @@ enum WsSlot {
     WS_RT16_CNT, WS_RT16_PTR, WS_RT16_COL, WS_RT16_VAL,           // sixteen-row H-only tile copy
     WS_SUBCELL,                                                   // sub-cell codes of the binning
     WS_MDINV,                                                     // diag(M)^-1 for the eigenvalue bounds
+    WS_FPS, WS_RADMAX,                                            // farthest point sampling, radius maxima
     WS_COUNT
 };
 

@@ -287,10 +287,13 @@ __global__ void __launch_bounds__(256) gather_xyz_kernel(const double *xyz, cons
 // neighbour lists: one wavefront per quadrature point, lanes over candidates
 // ---------------------------------------------------------------------------
 
+// With rad (support radius per node, original order, read through perm) the predicate is
+// d^2 < R_j R_j for sorted node j, else d^2 < h h.
 template <bool kFill>
 __global__ void __launch_bounds__(256) neighbor_kernel(const double *qxyz, int64_t q, const double *xs, GridDev g,
                                                        const int64_t *cell_start, const int64_t *off,
-                                                       int32_t *ids, int32_t *counts) {
+                                                       int32_t *ids, int32_t *counts, const double *rad,
+                                                       const int32_t *perm) {
     const int lane = threadIdx.x & 63;
     const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     if (i >= q) return;
@@ -315,7 +318,12 @@ __global__ void __launch_bounds__(256) neighbor_kernel(const double *qxyz, int64
                 if (j < j1) {
                     const double dx = X0 - xs[3 * j], dy = X1 - xs[3 * j + 1], dz = X2 - xs[3 * j + 2];
                     const double d2 = ((dx * dx) + (dy * dy)) + (dz * dz);
-                    hit = d2 < g.hh;
+                    if (rad) {
+                        const double Rj = rad[perm[j]];
+                        hit = d2 < Rj * Rj;
+                    } else {
+                        hit = d2 < g.hh;
+                    }
                 }
                 const uint64_t mask = __ballot(hit);
                 if (kFill && hit) ids[pos + __popcll(mask & below)] = (int32_t)j;
@@ -341,11 +349,72 @@ int scan_exclusive_i32_to_i64(ff_ctx *ctx, const int32_t *in, int64_t *out, int6
 
 using namespace ff;
 
+namespace {
+
+// largest radius per block and a flag for a radius that is not finite and positive
+__global__ void __launch_bounds__(256) radius_max_kernel(const double *rad, int64_t n, double *part, int *bad) {
+    __shared__ double s[256];
+    double m = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const double v = rad[i];
+        if (!(v > 0.0) || !isfinite(v)) atomicOr(bad, 1);
+        m = fmax(m, v);
+    }
+    s[threadIdx.x] = m;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) s[threadIdx.x] = fmax(s[threadIdx.x], s[threadIdx.x + st]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+int build_impl(ff_ctx *ctx, int64_t n, const double *xyz, int64_t q, const double *qxyz, double h,
+               const double *rad, ff_grid *grid, int32_t *perm, double *xyz_sorted, int64_t *cell_start,
+               int64_t cell_cap, int64_t *nbr_off, int32_t *nbr_id, int64_t nbr_cap, int64_t *nbr_total);
+
+}  // namespace
+
 extern "C" int build_neighbors(ff_ctx *ctx, int64_t n, const double *xyz, int64_t q, const double *qxyz,
                                double h, ff_grid *grid, int32_t *perm, double *xyz_sorted, int64_t *cell_start,
                                int64_t cell_cap, int64_t *nbr_off, int32_t *nbr_id, int64_t nbr_cap,
                                int64_t *nbr_total) {
     if (!ctx) return FF_ERR_INVALID_ARG;
+    return build_impl(ctx, n, xyz, q, qxyz, h, nullptr, grid, perm, xyz_sorted, cell_start, cell_cap, nbr_off,
+                      nbr_id, nbr_cap, nbr_total);
+}
+
+extern "C" int build_neighbors_radii(ff_ctx *ctx, int64_t n, const double *xyz, const double *radius, int64_t q,
+                                     const double *qxyz, ff_grid *grid, int32_t *perm, double *xyz_sorted,
+                                     int64_t *cell_start, int64_t cell_cap, int64_t *nbr_off, int32_t *nbr_id,
+                                     int64_t nbr_cap, int64_t *nbr_total) {
+    if (!ctx) return FF_ERR_INVALID_ARG;
+    FF_REQUIRE(ctx, radius != nullptr, "radius is NULL");
+    FF_REQUIRE(ctx, n > 0 && n < INT32_MAX, "n = %lld out of range", (long long)n);
+    FF_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    constexpr int kBlocks = 256;
+    double *part = (double *)ws_get(ctx, WS_RADMAX, kBlocks * sizeof(double) + 64);
+    int *flag = (int *)(part ? part + kBlocks : nullptr);
+    double *host = (double *)pinned_get(ctx, 4096);
+    if (!part || !host) return FF_ERR_OOM;
+    FF_HIP(ctx, hipMemsetAsync(flag, 0, sizeof(int), st));
+    hipLaunchKernelGGL(radius_max_kernel, dim3(kBlocks), dim3(256), 0, st, radius, n, part, flag);
+    FF_CHECK_LAUNCH(ctx);
+    FF_HIP(ctx, hipMemcpyAsync(host, part, kBlocks * sizeof(double) + sizeof(int), hipMemcpyDeviceToHost, st));
+    FF_HIP(ctx, hipStreamSynchronize(st));
+    FF_REQUIRE(ctx, ((const int *)(host + kBlocks))[0] == 0, "a support radius is not finite and positive");
+    double h = 0.0;
+    for (int b = 0; b < kBlocks; ++b) h = std::max(h, host[b]);
+    return build_impl(ctx, n, xyz, q, qxyz, h, radius, grid, perm, xyz_sorted, cell_start, cell_cap, nbr_off,
+                      nbr_id, nbr_cap, nbr_total);
+}
+
+namespace {
+
+int build_impl(ff_ctx *ctx, int64_t n, const double *xyz, int64_t q, const double *qxyz, double h,
+               const double *rad, ff_grid *grid, int32_t *perm, double *xyz_sorted, int64_t *cell_start,
+               int64_t cell_cap, int64_t *nbr_off, int32_t *nbr_id, int64_t nbr_cap, int64_t *nbr_total) {
     FF_REQUIRE(ctx, n > 0 && n < INT32_MAX, "n = %lld out of range", (long long)n);
     FF_REQUIRE(ctx, xyz && perm && xyz_sorted && nbr_off && grid && nbr_total, "required pointer is NULL");
     FF_REQUIRE(ctx, std::isfinite(h) && h > 0.0, "support radius h must be finite and positive");
@@ -428,7 +497,7 @@ extern "C" int build_neighbors(ff_ctx *ctx, int64_t n, const double *xyz, int64_
     const double *Q = qxyz ? qxyz : xyz_sorted;
     const unsigned nbq = grid_for(q, 4);   // 4 waves of 64 per block
     hipLaunchKernelGGL(neighbor_kernel<false>, dim3(nbq), dim3(256), 0, st, Q, q, xyz_sorted, g, cs,
-                       (const int64_t *)nullptr, (int32_t *)nullptr, count);
+                       (const int64_t *)nullptr, (int32_t *)nullptr, count, rad, (const int32_t *)perm);
     FF_CHECK_LAUNCH(ctx);
     rc = scan_exclusive_i32_to_i64(ctx, count, nbr_off, q);
     if (rc) return rc;
@@ -443,7 +512,9 @@ extern "C" int build_neighbors(ff_ctx *ctx, int64_t n, const double *xyz, int64_
         return set_error(ctx, FF_ERR_CAPACITY, "nbr_id needs %lld entries, capacity %lld", (long long)total,
                          (long long)nbr_cap);
     hipLaunchKernelGGL(neighbor_kernel<true>, dim3(nbq), dim3(256), 0, st, Q, q, xyz_sorted, g, cs, nbr_off,
-                       nbr_id, (int32_t *)nullptr);
+                       nbr_id, (int32_t *)nullptr, rad, (const int32_t *)perm);
     FF_CHECK_LAUNCH(ctx);
     return FF_OK;
 }
+
+}  // namespace

@@ -256,10 +256,188 @@ __global__ void __launch_bounds__(256) rkpm_kernel(const double *xs, const doubl
     }
 }
 
+// Gaussian exp(-s), s = d^2 / r^2, cut at s = c^2 with its tangent there subtracted (value and
+// slope vanish at the cut): w = exp(-s) - exp(-c^2) (1 + c^2 - s), grad w = go (X - p) with
+// go = 2 (exp(-c^2) - exp(-s)) / r^2; zero beyond the cut.
+__device__ inline void gauss_cut(double d2, double rk, double cut, double &w, double &go) {
+    const double s = d2 / (rk * rk), c2 = cut * cut;
+    if (s < c2) {
+        const double e = exp(-s), ec = exp(-c2);
+        w = e - ec * (1.0 + c2 - s);
+        go = (-e + ec) * 2.0 / (rk * rk);
+    } else {
+        w = 0.0;
+        go = 0.0;
+    }
+}
+
+// Shape functions on the centres' own Gaussians (radius r_k per node), one wavefront per
+// point as rkpm_kernel, for three bases (Sec. 3.2 and its Fig. 3b comparison):
+//   kBasis 0  plain RBF               phi_k = w_k
+//   kBasis 1  partition-of-unity RBF  phi_k = w_k / sum w
+//   kBasis 2  RKPM, linear basis      Eq. (7)-(11) in the shifted basis [1, (p - X)/h]
+template <int kBasis>
+__global__ void __launch_bounds__(256) rkpm_var_kernel(const double *xs, const double *rnode, const int32_t *perm,
+                                                       const double *qxyz, int64_t q, const int64_t *off,
+                                                       const int32_t *ids, double h, double cut, double *phi,
+                                                       double *dphi, unsigned long long *bad) {
+    const int lane = threadIdx.x & 63;
+    const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (i >= q) return;
+    const double X[3] = {qxyz[3 * i], qxyz[3 * i + 1], qxyz[3 * i + 2]};
+    const int64_t e0 = off[i], e1 = off[i + 1];
+    const double hinv = 1.0 / h;
+    constexpr int NS = kBasis == 2 ? kSyms : 1;
+    double S[NS], G[3][NS];
+#pragma unroll
+    for (int t = 0; t < NS; ++t) { S[t] = 0.0; G[0][t] = G[1][t] = G[2][t] = 0.0; }
+    if (kBasis > 0) {
+        for (int64_t e = e0 + lane; e < e1; e += 64) {
+            const int64_t k = ids[e];
+            const double r0 = X[0] - xs[3 * k], r1 = X[1] - xs[3 * k + 1], r2 = X[2] - xs[3 * k + 2];
+            const double d2 = ((r0 * r0) + (r1 * r1)) + (r2 * r2);
+            double w, go;
+            gauss_cut(d2, rnode[perm ? perm[k] : k], cut, w, go);
+            const double g[3] = {go * r0, go * r1, go * r2};
+            if (kBasis == 1) {
+                S[0] += w;
+                G[0][0] += g[0];
+                G[1][0] += g[1];
+                G[2][0] += g[2];
+            } else {
+                const double P[4] = {1.0, -r0 * hinv, -r1 * hinv, -r2 * hinv};
+                int t = 0;
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int b = a; b < 4; ++b, ++t) {
+                        const double pp = P[a] * P[b];
+                        S[t] += w * pp;
+                        G[0][t] += g[0] * pp;
+                        G[1][t] += g[1] * pp;
+                        G[2][t] += g[2] * pp;
+                    }
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < NS; ++t) {
+            S[t] = wave_sum(S[t]);
+            G[0][t] = wave_sum(G[0][t]);
+            G[1][t] = wave_sum(G[1][t]);
+            G[2][t] = wave_sum(G[2][t]);
+        }
+    }
+    double b[4] = {0.0, 0.0, 0.0, 0.0}, db[3][4] = {};
+    if (kBasis == 1 && !(S[0] > 0.0)) {
+        if (lane == 0) atomicMin(bad, (unsigned long long)i);
+        return;
+    }
+    if (kBasis == 2) {
+        double Mh[4][4], L[4][4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) Mh[a][c] = S[kBasis == 2 ? sym_index(a, c) : 0];
+        if (!chol4(Mh, L)) {
+            if (lane == 0) atomicMin(bad, (unsigned long long)i);
+            return;
+        }
+        const double e1v[4] = {1.0, 0.0, 0.0, 0.0};
+        chol4_solve(L, e1v, b);
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+            double dM[4][4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) dM[a][c] = G[s][kBasis == 2 ? sym_index(a, c) : 0];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                dM[s + 1][c] -= Mh[c][0] * hinv;
+                dM[c][s + 1] -= Mh[c][0] * hinv;
+            }
+            double t[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) t[a] = dM[a][0] * b[0] + dM[a][1] * b[1] + dM[a][2] * b[2] + dM[a][3] * b[3];
+            double x[4];
+            chol4_solve(L, t, x);
+#pragma unroll
+            for (int a = 0; a < 4; ++a) db[s][a] = -x[a];
+        }
+    }
+    for (int64_t e = e0 + lane; e < e1; e += 64) {
+        const int64_t k = ids[e];
+        const double r0 = X[0] - xs[3 * k], r1 = X[1] - xs[3 * k + 1], r2 = X[2] - xs[3 * k + 2];
+        const double d2 = ((r0 * r0) + (r1 * r1)) + (r2 * r2);
+        double w, go;
+        gauss_cut(d2, rnode[perm ? perm[k] : k], cut, w, go);
+        const double r[3] = {r0, r1, r2};
+        if (kBasis == 0) {
+            phi[e] = w;
+#pragma unroll
+            for (int s = 0; s < 3; ++s) dphi[3 * e + s] = go * r[s];
+        } else if (kBasis == 1) {
+            const double inv = 1.0 / S[0];
+            phi[e] = w * inv;
+#pragma unroll
+            for (int s = 0; s < 3; ++s) dphi[3 * e + s] = go * r[s] * inv - w * G[s][0] * (inv * inv);
+        } else {
+            const double P[4] = {1.0, -r0 * hinv, -r1 * hinv, -r2 * hinv};
+            const double Pb = P[0] * b[0] + P[1] * b[1] + P[2] * b[2] + P[3] * b[3];
+            phi[e] = w * Pb;
+#pragma unroll
+            for (int s = 0; s < 3; ++s) {
+                const double Pdb = P[0] * db[s][0] + P[1] * db[s][1] + P[2] * db[s][2] + P[3] * db[s][3];
+                dphi[3 * e + s] = (go * r[s]) * Pb - w * b[s + 1] * hinv + w * Pdb;
+            }
+        }
+    }
+}
+
 }  // namespace
 }  // namespace ff
 
 using namespace ff;
+
+extern "C" int rkpm_shape_radii(ff_ctx *ctx, int64_t n, const double *xyz_sorted, const double *node_r,
+                                const int32_t *perm, int64_t q, const double *qxyz, const int64_t *nbr_off,
+                                const int32_t *nbr_id, int64_t nbr_total, double h, double cut, int basis,
+                                double *phi, double *dphi, int64_t *bad_index) {
+    if (!ctx) return FF_ERR_INVALID_ARG;
+    FF_REQUIRE(ctx, n > 0 && q > 0, "empty input");
+    FF_REQUIRE(ctx, xyz_sorted && node_r && nbr_off && nbr_id && phi && dphi, "required pointer is NULL");
+    FF_REQUIRE(ctx, std::isfinite(h) && h > 0.0, "scale h must be finite and positive");
+    FF_REQUIRE(ctx, std::isfinite(cut) && cut > 0.0, "cut must be finite and positive");
+    FF_REQUIRE(ctx, basis >= 0 && basis <= 2, "basis must be 0 (RBF), 1 (partition-of-unity RBF) or 2 (RKPM)");
+    if (!qxyz) FF_REQUIRE(ctx, q == n, "qxyz == NULL requires q == n");
+    (void)nbr_total;
+    FF_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    unsigned long long *bad = (unsigned long long *)ws_get(ctx, WS_FLAG, 64);
+    unsigned long long *host = (unsigned long long *)pinned_get(ctx, 4096);
+    if (!bad || !host) return FF_ERR_OOM;
+    FF_HIP(ctx, hipMemsetAsync(bad, 0xff, sizeof(unsigned long long), st));
+    const double *Q = qxyz ? qxyz : xyz_sorted;
+    const dim3 grid(grid_for(q, 4)), block(256);
+    if (basis == 0)
+        hipLaunchKernelGGL(rkpm_var_kernel<0>, grid, block, 0, st, xyz_sorted, node_r, perm, Q, q, nbr_off, nbr_id, h,
+                           cut, phi, dphi, bad);
+    else if (basis == 1)
+        hipLaunchKernelGGL(rkpm_var_kernel<1>, grid, block, 0, st, xyz_sorted, node_r, perm, Q, q, nbr_off, nbr_id, h,
+                           cut, phi, dphi, bad);
+    else
+        hipLaunchKernelGGL(rkpm_var_kernel<2>, grid, block, 0, st, xyz_sorted, node_r, perm, Q, q, nbr_off, nbr_id, h,
+                           cut, phi, dphi, bad);
+    FF_CHECK_LAUNCH(ctx);
+    FF_HIP(ctx, hipMemcpyAsync(host, bad, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    FF_HIP(ctx, hipStreamSynchronize(st));
+    const int64_t b = (host[0] == ~0ull) ? -1 : (int64_t)host[0];
+    if (bad_index) *bad_index = b;
+    if (b >= 0)
+        return set_error(ctx, FF_ERR_SINGULAR_MOMENT, "%s at quadrature point %lld",
+                         basis == 2 ? "moment matrix not positive definite" : "kernel sum is zero", (long long)b);
+    return FF_OK;
+}
 
 extern "C" int rkpm_shape(ff_ctx *ctx, int64_t n, const double *xyz_sorted, int64_t q, const double *qxyz,
                           const int64_t *nbr_off, const int32_t *nbr_id, int64_t nbr_total, double h, int kernel,

@@ -83,6 +83,10 @@ def lib():
         "build_neighbors": (i32, [vp, i64, vp, i64, vp, f64, P(ff_grid), vp, vp, vp, i64, vp, vp, i64,
                                   P(i64)]),
         "rkpm_shape": (i32, [vp, i64, vp, i64, vp, vp, vp, i64, f64, i32, vp, vp, vp, P(i64)]),
+        "build_neighbors_radii": (i32, [vp, i64, vp, vp, i64, vp, P(ff_grid), vp, vp, vp, i64, vp, vp, i64, P(i64)]),
+        "fps_centers": (i32, [vp, i64, vp, i32, i64, vp, vp]),
+        "kernel_radii": (i32, [vp, i64, vp, f64, vp, vp]),
+        "rkpm_shape_radii": (i32, [vp, i64, vp, vp, vp, i64, vp, vp, vp, i64, f64, f64, i32, vp, vp, P(i64)]),
         "assemble_HM": (i32, [vp, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, P(ff_grid), vp, vp, vp,
                               vp, vp, vp, i64, P(i64)]),
         "eigenmodes": (i32, [vp, i64, vp, vp, vp, vp, vp, P(ff_eig_params), vp, vp, vp, vp,
@@ -225,6 +229,73 @@ def rkpm_shape(ctx: Context, xyz_sorted, nbr_off, nbr_id, h: float, qxyz=None, k
         e.bad_index = bad.value
         raise e
     return phi[:tot], dphi[:tot], feat
+
+
+def build_neighbors_radii(ctx: Context, xyz, radius, qxyz) -> Neighbors:
+    """Neighbour lists d^2 < R_j^2 with a support radius per node (original order)."""
+    import torch
+    dev = xyz.device
+    xyz = xyz.contiguous()
+    radius = radius.contiguous()
+    qxyz = qxyz.contiguous()
+    n, q = xyz.shape[0], qxyz.shape[0]
+    if radius.dtype != torch.float64 or radius.shape != (n,):
+        raise FFError(FF_ERR_INVALID_ARG, "radius must be float64 [n]")
+    grid = ff_grid()
+    perm = torch.empty(n, dtype=torch.int32, device=dev)
+    xs = torch.empty((n, 3), dtype=torch.float64, device=dev)
+    off = torch.empty(q + 1, dtype=torch.int64, device=dev)
+    tot = ctypes.c_int64()
+    L = lib()
+    ctx.check(L.build_neighbors_radii(ctx.h, n, _p(xyz), _p(radius), q, _p(qxyz), ctypes.byref(grid), _p(perm),
+                                      _p(xs), None, 0, _p(off), None, 0, ctypes.byref(tot)))
+    cs = torch.empty(grid.n_cells + 1, dtype=torch.int64, device=dev)
+    ids = torch.empty(max(tot.value, 1), dtype=torch.int32, device=dev)
+    ctx.check(L.build_neighbors_radii(ctx.h, n, _p(xyz), _p(radius), q, _p(qxyz), ctypes.byref(grid), _p(perm),
+                                      _p(xs), _p(cs), cs.numel(), _p(off), _p(ids), ids.numel(), ctypes.byref(tot)))
+    return Neighbors(grid, perm, xs, cs, off, ids[:tot.value])
+
+
+def fps_centers(ctx: Context, qxyz, K: int, start: int = 0):
+    """(indices [K] int32, centres [K][3]) of farthest point sampling over the points."""
+    import torch
+    qxyz = qxyz.contiguous()
+    idx = torch.empty(K, dtype=torch.int32, device=qxyz.device)
+    cen = torch.empty((K, 3), dtype=torch.float64, device=qxyz.device)
+    ctx.check(lib().fps_centers(ctx.h, qxyz.shape[0], _p(qxyz), K, start, _p(idx), _p(cen)))
+    return idx, cen
+
+
+def kernel_radii(ctx: Context, centres, cut: float = 3.0):
+    """(r, R): each centre's Gaussian radius (distance to its 2nd-nearest centre) and cut * r."""
+    import torch
+    centres = centres.contiguous()
+    K = centres.shape[0]
+    r = torch.empty(K, dtype=torch.float64, device=centres.device)
+    R = torch.empty(K, dtype=torch.float64, device=centres.device)
+    ctx.check(lib().kernel_radii(ctx.h, K, _p(centres), float(cut), _p(r), _p(R)))
+    return r, R
+
+
+def rkpm_shape_radii(ctx: Context, xyz_sorted, node_r, nbr_off, nbr_id, h: float, qxyz, cut: float = 3.0,
+                     basis: int = 2, perm=None):
+    import torch
+    dev = xyz_sorted.device
+    n = xyz_sorted.shape[0]
+    q = nbr_off.shape[0] - 1
+    tot = nbr_id.shape[0]
+    qxyz = qxyz.contiguous()
+    phi = torch.empty(max(tot, 1), dtype=torch.float64, device=dev)
+    dphi = torch.empty((max(tot, 1), 3), dtype=torch.float64, device=dev)
+    bad = ctypes.c_int64(-1)
+    rc = lib().rkpm_shape_radii(ctx.h, n, _p(xyz_sorted), _p(node_r.contiguous()), _p(perm), q, _p(qxyz),
+                                _p(nbr_off), _p(nbr_id), tot, float(h), float(cut), int(basis), _p(phi), _p(dphi),
+                                ctypes.byref(bad))
+    if rc != 0:
+        e = FFError(rc, lib().ff_last_error(ctx.h).decode())
+        e.bad_index = bad.value
+        raise e
+    return phi[:tot], dphi[:tot]
 
 
 def assemble_HM(ctx: Context, n: int, nbr_off, nbr_id, phi, dphi, vol, lam, mu, grid: ff_grid, cell_start,
@@ -558,6 +629,39 @@ def assemble_cloud(ctx: Context, xyz, vol, lam, mu, h: float, rho=None, features
     rp, col, H, M, hm32 = assemble_HM(ctx, n, nb.nbr_off, nb.nbr_id, phi, dphi, vol, lam, mu, nb.grid,
                                       nb.cell_start, rho=rho, perm=nb.perm)
     return Assembled(n, h, nb, phi, dphi, feat, rp, col, H, M, hm32)
+
+
+@dataclass
+class PaperAssembled:
+    """The paper's construction on the device (Supp. B.1): FPS centres, radii, lists, shape
+    functions, H and M in sorted centre numbering."""
+    K: int
+    pick: "object"
+    centres: "object"
+    r: "object"
+    R: "object"
+    nb: Neighbors
+    phi: "object"
+    dphi: "object"
+    row_ptr: "object"
+    col: "object"
+    H: "object"
+    M: "object"
+    hm32: "object"
+
+
+def paper_construction(ctx: Context, qxyz, vol, lam, mu, K: int, cut: float = 3.0, basis: int = 2,
+                       start: int = 0, rho=None) -> PaperAssembled:
+    """fps_centers -> kernel_radii -> build_neighbors_radii -> rkpm_shape_radii -> assemble_HM, with
+    the integration points as quadrature points (their arrays in their own order)."""
+    pick, cen = fps_centers(ctx, qxyz, K, start)
+    r, R = kernel_radii(ctx, cen, cut)
+    nb = build_neighbors_radii(ctx, cen, R, qxyz)
+    phi, dphi = rkpm_shape_radii(ctx, nb.xyz_sorted, r, nb.nbr_off, nb.nbr_id, nb.grid.h, qxyz, cut, basis,
+                                 perm=nb.perm)
+    rp, col, H, M, hm32 = assemble_HM(ctx, K, nb.nbr_off, nb.nbr_id, phi, dphi, vol, lam, mu, nb.grid,
+                                      nb.cell_start, rho=rho)
+    return PaperAssembled(K, pick, cen, r, R, nb, phi, dphi, rp, col, H, M, hm32)
 
 
 def concat_objects(parts):

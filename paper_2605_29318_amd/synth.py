@@ -323,6 +323,92 @@ def batch_objects(count: int = 64, nmin: int = 2_000, nmax: int = 200_000, seed:
     return out
 
 
+# ----------------------------------------------------------------------------
+# integration points of the paper's own construction (Supp. B.1): a uniform grid
+# over the bounding box, points outside the object rejected
+# ----------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class IntegrationSet:
+    """Grid integration points inside an object, their weights and material, and the number
+    of kernel centres to pick from them."""
+    name: str
+    xyz: np.ndarray          # (Q, 3) grid points inside the object, grid order (x fastest)
+    vol: np.ndarray          # (Q,) weight = grid cell volume
+    lam: np.ndarray
+    mu: np.ndarray
+    rho: np.ndarray
+    spacing: float
+    K: int                   # kernel centres to pick
+    k: int                   # eigenpairs wanted (constant mode included)
+    meta: dict = dataclasses.field(default_factory=dict)
+
+    @property
+    def q(self) -> int:
+        return int(self.xyz.shape[0])
+
+    def sha256(self) -> str:
+        m = hashlib.sha256()
+        for a in (self.xyz, self.vol, self.lam, self.mu, self.rho):
+            m.update(np.ascontiguousarray(a).tobytes())
+        m.update(np.int64(self.K).tobytes())
+        return m.hexdigest()
+
+
+def grid_inside(inside, lo, hi, spacing: float) -> np.ndarray:
+    """Cell centres lo + (i + 1/2) g of a uniform grid over the box [lo, hi] that pass the
+    inside test, x fastest."""
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    cnt = np.maximum(1, np.round((hi - lo) / spacing).astype(np.int64))
+    axes = [lo[a] + (np.arange(cnt[a]) + 0.5) * spacing for a in range(3)]
+    z, y, x = np.meshgrid(axes[2], axes[1], axes[0], indexing="ij")
+    p = np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1)
+    return np.ascontiguousarray(p[inside(p)])
+
+
+def _set(name, xyz, spacing, E, nu, rho, K, k, meta):
+    q = xyz.shape[0]
+    E = np.broadcast_to(np.asarray(E, dtype=np.float64), (q,)).copy()
+    nu = np.broadcast_to(np.asarray(nu, dtype=np.float64), (q,)).copy()
+    lam, mu = lame_from_young(E, nu)
+    return IntegrationSet(name, xyz, np.full(q, spacing ** 3), lam, mu, np.full(q, float(rho)), spacing, K, k,
+                          meta)
+
+
+def beam(spacing: float = 0.05, K: int = 1000, k: int = 17, E: float = 5e6, nu: float = 0.45,
+         rho: float = 1000.0, length: float = 5.0) -> IntegrationSet:
+    """The standard beam of Sec. 4: a length x 1 x 1 m cuboid (5 m by default), E = 5e6 Pa,
+    nu = 0.45, density 1000; every grid point of the box is inside."""
+    xyz = grid_inside(lambda p: np.ones(p.shape[0], dtype=bool), (0, 0, 0), (length, 1, 1), spacing)
+    return _set(f"beam{length:g}", xyz, spacing, E, nu, rho, K, k, dict(length=length))
+
+
+def layered_sphere(spacing: float = 0.025, K: int = 1000, k: int = 33, radius: float = 0.5,
+                   E_stiff: float = 1e6, E_soft: float = 1e4, nu: float = 0.45, rho: float = 1000.0,
+                   layers: int = 4) -> IntegrationSet:
+    """The heterogeneous sphere of the supplementary multi-layer test: concentric shells of equal
+    thickness, stiff and soft alternating from the centre outwards (stiff-soft-stiff-soft)."""
+    inside = lambda p: np.sum(p * p, axis=1) <= radius * radius
+    xyz = grid_inside(inside, (-radius,) * 3, (radius,) * 3, spacing)
+    shell = np.minimum((np.sqrt(np.sum(xyz * xyz, axis=1)) / radius * layers).astype(np.int64), layers - 1)
+    E = np.where(shell % 2 == 0, E_stiff, E_soft)
+    return _set("layered_sphere", xyz, spacing, E, nu, rho, K, k, dict(radius=radius, layers=layers))
+
+
+def ellipsoid_blob(spacing: float = 0.02, K: int = 1000, k: int = 33, seed: int = 3, E: float = 1e5,
+                   nu: float = 0.45, rho: float = 1000.0) -> IntegrationSet:
+    """An object of the kind the paper's datasets hold (a closed shape with an inside test),
+    here the seeded union of 20 ellipsoids of the large-object workload, on a grid."""
+    rng = np.random.default_rng(seed)
+    while True:
+        shape = _ellipsoid_union(rng, count=20)
+        if _mc_volume(shape, rng, 400_000) >= 0.05 and _connected(shape):
+            break
+    xyz = grid_inside(shape.inside, (0, 0, 0), (1, 1, 1), spacing)
+    return _set(f"ellipsoid_blob{seed}", xyz, spacing, E, nu, rho, K, k, dict(seed=seed))
+
+
 def initial_block(n: int, m: int, seed: int) -> np.ndarray:
     """Seeded starting block for the eigensolver, uniform in [-1, 1), row-major (n, m)."""
     rng = np.random.default_rng(seed)
