@@ -370,6 +370,36 @@ int spmm_hm(ff_ctx *ctx, int64_t n, const int64_t *row_ptr, const int32_t *col, 
             void *HY, void *MY, int64_t ld_out, int variant);
 
 /*
+ * Matrix-free products with H and M, without the assembled CSR. Prop. 1 (with the
+ * quadrature of Supp. C) and Eq. (14) write both as sums over the integration points:
+ *   H = G^T D G,  M = Phi^T V Phi,
+ * G [3q][n] the gradients grad phi_k(X_i), Phi [q][n] the values phi_k(X_i),
+ * D = diag(v_i (lambda_i + 4 mu_i)) per gradient component, V = diag(v_i [rho_i]). So
+ * [H Y, M Y] = [G^T (D (G Y)), Phi^T (V (Phi Y))] in two passes over the neighbour lists:
+ * a gather per integration point, then a sum per node over the points whose list holds
+ * it (ascending), each in a fixed order.
+ *
+ * mf_build: the lists, shape functions and per-point arrays exactly as assemble_HM takes
+ *   them (perm as there); keeps the transposed lists with phi and grad phi in that order,
+ *   and the per-point weights, in FP32 (precision 1) or FP64 (precision 0). It keeps
+ *   pointers to nbr_off and nbr_id, which must stay allocated and unchanged while the
+ *   handle is used. Destroy the handle before its context.
+ * mf_apply: HY = H Y and/or MY = M Y (either may be NULL) for Y [n][m], m in [1, 64],
+ *   float or double as the handle, row-major with leading dimensions ld_y, ld_out; FP32
+ *   accumulation at precision 1. Equal to the products with assemble_HM's matrices up to
+ *   rounding (the terms are associated differently).
+ * mf_interpolate: U [q][m] = Phi Y, the fields sum_k phi_k(X_i) Y_k at the integration
+ *   points (Sec. 3.2: the skinning weights W^j(X) = sum_k phi_k(X) c_k^j where Y = c).
+ */
+typedef struct ff_mf ff_mf;
+int mf_build(ff_ctx *ctx, int64_t n, int64_t q, const int64_t *nbr_off, const int32_t *nbr_id, const double *phi,
+             const double *dphi, const double *vol, const double *lam, const double *mu, const double *rho,
+             const int32_t *perm, int precision, ff_mf **out);
+int mf_apply(ff_ctx *ctx, ff_mf *mf, int m, const void *Y, int64_t ld_y, void *HY, void *MY, int64_t ld_out);
+int mf_interpolate(ff_ctx *ctx, const ff_mf *mf, int m, const void *Y, int64_t ld_y, void *U, int64_t ld_u);
+void mf_destroy(ff_mf *mf);
+
+/*
  * spmm_autotune - time every SpMM tile shape on the given matrix with hipEvents
  * and keep the fastest for matrices of this shape (n, nnz/row, m, precision);
  * results are cached in the JSON file at cache_path (NULL = no file).

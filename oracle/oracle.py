@@ -215,8 +215,11 @@ def spmm(row_ptr, col, val, X):
     two = X.ndim == 2
     X2 = X if two else X[:, None]
     X2 = np.ascontiguousarray(X2)
-    Y = np.zeros_like(X2)
-    lib().orc_spmm(len(row_ptr) - 1, _c(row_ptr, np.int64), _c(col, np.int32),
+    col = _c(col, np.int32)
+    if col.size and (int(col.max()) >= X2.shape[0] or int(col.min()) < 0):
+        raise ValueError("column index outside the block")
+    Y = np.zeros((len(row_ptr) - 1, X2.shape[1]))       # as many rows as the matrix (it may be rectangular)
+    lib().orc_spmm(len(row_ptr) - 1, _c(row_ptr, np.int64), col,
                    _c(val, np.float64), X2.shape[1], X2, Y)
     return Y if two else Y[:, 0]
 

@@ -27,6 +27,7 @@ SOURCES = [
     ("k_mlp.hip", False),
     ("k_rowtile.hip", False),
     ("k_paper.hip", True),
+    ("k_matfree.hip", False),
 ]
 
 COMMON = ["-x", "hip", "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",

@@ -37,6 +37,7 @@ enum WsSlot {
     WS_SUBCELL,                                                   // sub-cell codes of the binning
     WS_MDINV,                                                     // diag(M)^-1 for the eigenvalue bounds
     WS_FPS, WS_RADMAX,                                            // farthest point sampling, radius maxima
+    WS_MF,                                                        // matrix-free build: transposed entries
     WS_COUNT
 };
 

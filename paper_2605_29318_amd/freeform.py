@@ -106,6 +106,10 @@ def lib():
         "rowtiles_info": (i32, [vp, P(i64), P(i64)]),
         "spmm_rowtiles": (i32, [vp, vp, i32, i32, vp, i64, vp, vp, i64, i32]),
         "rowtiles_destroy": (None, [vp]),
+        "mf_build": (i32, [vp, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, i32, P(vp)]),
+        "mf_apply": (i32, [vp, vp, i32, vp, i64, vp, vp, i64]),
+        "mf_interpolate": (i32, [vp, vp, i32, vp, i64, vp, i64]),
+        "mf_destroy": (None, [vp]),
         "rand_block": (i32, [vp, i64, i32, ctypes.c_uint64, vp]),
         "philox4x32_10": (i32, [vp, i32, vp, vp, vp]),
         "mlp_param_count": (i32, [i32, i32]),
@@ -479,6 +483,61 @@ class RowTiles:
     def close(self):
         if self.h:
             lib().rowtiles_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class MatFree:
+    """Handle of the matrix-free products [H Y, M Y] = [G^T D G Y, Phi^T V Phi Y] (mf_build)."""
+
+    def __init__(self, ctx: Context, n: int, nbr_off, nbr_id, phi, dphi, vol, lam, mu, rho=None, perm=None,
+                 precision: int = 1):
+        self.ctx = ctx
+        self.h = None
+        self.n = n
+        self.q = nbr_off.shape[0] - 1
+        self.precision = precision
+        self._keep = (nbr_off, nbr_id)          # the handle reads these lists on every product
+        h = ctypes.c_void_p()
+        ctx.check(lib().mf_build(ctx.h, n, self.q, _p(nbr_off), _p(nbr_id), _p(phi), _p(dphi), _p(vol), _p(lam),
+                                 _p(mu), _p(rho), _p(perm), precision, ctypes.byref(h)))
+        self.h = h
+        ctx._children.add(self)
+
+    def apply(self, Y, h: bool = True, m: bool = True, out=None):
+        """(HY, MY) for Y [n][m] (float32 at precision 1, float64 at 0); either may be skipped."""
+        import torch
+        dt = torch.float32 if self.precision else torch.float64
+        if Y.dtype != dt or Y.shape[0] != self.n or Y.stride(1) != 1:
+            raise FFError(FF_ERR_INVALID_ARG, f"Y must be [{self.n}][m] {dt} with unit column stride")
+        k = Y.shape[1]
+        if out is None:
+            HY = torch.empty((self.n, k), dtype=dt, device=Y.device) if h else None
+            MY = torch.empty((self.n, k), dtype=dt, device=Y.device) if m else None
+        else:
+            HY, MY = out
+        ld = (HY if HY is not None else MY).stride(0)
+        self.ctx.check(lib().mf_apply(self.ctx.h, self.h, k, _p(Y), Y.stride(0), _p(HY), _p(MY), ld))
+        return HY, MY
+
+    def interpolate(self, Y):
+        """U [q][m] = Phi Y: the fields at the integration points."""
+        import torch
+        dt = torch.float32 if self.precision else torch.float64
+        if Y.dtype != dt or Y.shape[0] != self.n or Y.stride(1) != 1:
+            raise FFError(FF_ERR_INVALID_ARG, f"Y must be [{self.n}][m] {dt} with unit column stride")
+        U = torch.empty((self.q, Y.shape[1]), dtype=dt, device=Y.device)
+        self.ctx.check(lib().mf_interpolate(self.ctx.h, self.h, Y.shape[1], _p(Y), Y.stride(0), _p(U), U.stride(0)))
+        return U
+
+    def close(self):
+        if self.h:
+            lib().mf_destroy(self.h)
             self.h = None
 
     def __del__(self):

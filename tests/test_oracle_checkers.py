@@ -47,6 +47,22 @@ def test_spmm_matches_scipy(oracle, m):
     assert np.array_equal(oracle.matmul(A, X), Y)
 
 
+def test_spmm_rectangular(oracle):
+    """A q x n matrix (the lists of q integration points over n nodes) times an n x m block."""
+    rng = np.random.default_rng(2)
+    q, n, m = 50, 20, 3
+    rows = [np.sort(rng.choice(n, size=int(rng.integers(0, 6)), replace=False)) for _ in range(q)]
+    rp = np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int64)
+    col = np.concatenate(rows).astype(np.int32)
+    val = rng.standard_normal(col.size)
+    X = rng.standard_normal((n, m))
+    Y = oracle.spmm(rp, col, val, X)
+    assert Y.shape == (q, m)
+    assert np.abs(Y - sp.csr_matrix((val, col, rp), shape=(q, n)) @ X).max() <= 1e-14
+    with pytest.raises(ValueError):
+        oracle.spmm(rp, col, val, X[:5])
+
+
 def test_norm_inf_matches_definition(oracle):
     n = 250
     rp, col, val = _random_csr(n, seed=4, long_rows=(77,))
