@@ -130,3 +130,38 @@ def test_fps_edge_cases(oracle, ctx, ff):
         ff.fps_centers(ctx, dev(grid), 65, 0)
     with pytest.raises(ff.FFError):
         ff.kernel_radii(ctx, dev(grid[:2]))
+
+
+def test_first_mode_by_basis_on_the_gpu(oracle, ctx, ff):
+    """The comparison of Sec. 3.2 / Fig. 3b on the device path: on a 3 x 1 x 1 box the first
+    non-zero mode of RKPM is closest to the continuum one (eigenvalue (pi / 3)^2 (lambda + 4 mu),
+    shape cos(pi x / 3)), the plain RBF's farthest; the device's figures agree with the oracle's
+    (dense LAPACK on the oracle's matrices, fields from the oracle's lists)."""
+    import scipy.linalg as sl
+    S = synth.beam(spacing=0.1, K=220, length=3.0)
+    s = S.lam[0] + 4 * S.mu[0]
+    A_cos = np.stack([np.cos(np.pi * S.xyz[:, 0] / 3.0), np.ones(S.q)], 1)
+
+    def shape_err(u):
+        coef = np.linalg.lstsq(A_cos, u, rcond=None)[0]
+        return np.linalg.norm(u - A_cos @ coef) / np.linalg.norm(u - u.mean())
+
+    got, ref = {}, {}
+    for basis in (0, 1, 2):
+        A = ff.paper_construction(ctx, dev(S.xyz), dev(S.vol), dev(S.lam), dev(S.mu), S.K, basis=basis)
+        lam, W, res, info = ff.eigenmodes(ctx, S.K, A.row_ptr, A.col, A.H, A.M, A.hm32, k=4, precision=0, tol=1e-10,
+                                          precond=1, max_iter=20000)
+        mf = ff.MatFree(ctx, S.K, A.nb.nbr_off, A.nb.nbr_id, A.phi, A.dphi, dev(S.vol), dev(S.lam), dev(S.mu),
+                        precision=0)
+        u = host(mf.interpolate(W[:, 1:2].contiguous()))[:, 0]
+        mf.close()
+        got[basis] = (abs(lam[1] / s - (np.pi / 3) ** 2) / (np.pi / 3) ** 2, shape_err(u))
+        P = oracle.paper_pipeline(S.xyz, S.vol, S.lam, S.mu, S.K, basis=basis)
+        w, V = sl.eigh(P.Hs().toarray(), P.Ms().toarray(), subset_by_index=[0, 3])
+        uo = oracle.spmm(P.nbr_off, P.nbr_id, P.phi, V[:, 1:2])[:, 0]
+        ref[basis] = (abs(w[1] / s - (np.pi / 3) ** 2) / (np.pi / 3) ** 2, shape_err(uo))
+        assert abs(lam[1] - w[1]) <= 1e-8 * w[1]
+        assert abs(got[basis][1] - ref[basis][1]) <= 1e-6 * max(ref[basis][1], 1e-3)
+    print("\n[fig3b] relative eigenvalue error, mode-shape error by basis (RBF, PU-RBF, RKPM):", got)
+    assert got[2][0] < got[1][0] < got[0][0]
+    assert got[2][1] < got[0][1]
