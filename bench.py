@@ -40,7 +40,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_step(ff, ctx, dev_in, n, h, k, precision, tol, max_iter, use_graph=False, seed=0):
+def run_step(ff, ctx, dev_in, n, h, k, precision, tol, max_iter, use_graph=False, seed=0, eig_tol=0.0):
     import torch
     xyz, vol, lam, mu = dev_in
     torch.cuda.synchronize()
@@ -50,7 +50,7 @@ def run_step(ff, ctx, dev_in, n, h, k, precision, tol, max_iter, use_graph=False
     t1 = time.perf_counter()
     ev, W, res, info = ff.eigenmodes(ctx, n, A.row_ptr, A.col, A.H, A.M, A.hm32, k=k, precision=precision,
                                      tol=tol, max_iter=max_iter, use_graph=use_graph, allow_unconverged=True,
-                                     precond=PRECOND, precond_degree=PRECOND_DEGREE, seed=seed)
+                                     precond=PRECOND, precond_degree=PRECOND_DEGREE, seed=seed, eig_tol=eig_tol)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     return dict(total=t2 - t0, build=t1 - t0, solve=t2 - t1, ev=ev, res=res, info=info, A=A, W=W)
@@ -144,33 +144,186 @@ def counters_run(args):
     ctx.close()
 
 
-def cpu_baseline(n_sample, k, iters, gpu_iters, n_full):
-    """The FP64 oracle on a bounded sample: its build stages on n_sample particles and
-    `iters` LOBPCG iterations, scaled linearly in n to n_full and to the GPU's
-    iteration count."""
+CPU_LEG = r"""
+import json, os, sys, time
+sys.path.insert(0, sys.argv[1])
+from oracle import oracle as O
+from paper_2605_29318_amd import synth
+n, k, tol = int(sys.argv[2]), int(sys.argv[3]), float(sys.argv[4])
+c = synth.ellipsoid_union(n=n, seed=3, hetero=True, k=k, mc_samples=1_000_000)
+O.build()
+t = [time.perf_counter()]
+perm, cs, origin, dims = O.bin_nodes(c.xyz, c.h)
+xs = c.xyz[perm].copy()
+off, ids = O.neighbors(xs, xs, c.h, origin, dims, cs)
+t.append(time.perf_counter())
+phi, dphi = O.rkpm(xs, xs, off, ids, c.h)
+t.append(time.perf_counter())
+rp, col, H, M = O.assemble(c.n, off, ids, phi, dphi, c.vol[perm], c.lam[perm], c.mu[perm])
+t.append(time.perf_counter())
+Hs, Ms = O.to_scipy(c.n, rp, col, H), O.to_scipy(c.n, rp, col, M)
+lam, W, it, res = O.lobpcg(Hs, Ms, synth.initial_block(c.n, k, seed=1), k=k, tol=tol, maxiter=3000,
+                           precond="chebyshev")
+t.append(time.perf_counter())
+print(json.dumps(dict(n=n, nnz=int(rp[-1]), iters=int(it), max_resid=float(res.max()),
+                      stages=dict(binning_neighbours=t[1] - t[0], rkpm=t[2] - t[1], assembly=t[3] - t[2],
+                                  eigensolve=t[4] - t[3]))))
+"""
+
+
+def cpu_leg(n_sample, k, tol, threads):
+    """The FP64 oracle's own pipeline and its own eigensolver (LOBPCG with its Chebyshev-Jacobi
+    preconditioner) to its own convergence on a sample of the benchmark recipe, in a child
+    process with the given thread count (OpenMP and BLAS)."""
+    import subprocess
+    env = dict(os.environ)
+    if threads:
+        env["OMP_NUM_THREADS"] = env["OPENBLAS_NUM_THREADS"] = str(threads)
+    r = subprocess.run([sys.executable, "-c", CPU_LEG, ROOT, str(n_sample), str(k), str(tol)], env=env,
+                       capture_output=True, text=True, timeout=900)
+    if r.returncode != 0:
+        raise RuntimeError(r.stderr[-2000:])
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+def cpu_baseline(k, tol, n_full, n_all=20_000, n_one=5_000):
+    """The oracle on bounded samples: on all host cores (n_all particles) and on one core (n_one),
+    each stage timed; the projection to n_full scales every stage linearly in the particle count
+    at the sample's own iteration count (the GPU's count at n_full is of the same order)."""
+    cores = os.cpu_count() or 1
+    allc = cpu_leg(n_all, k, tol, None)
+    one = cpu_leg(n_one, k, tol, 1)
+    scale = n_full / n_all
+    est = sum(allc["stages"].values()) * scale
+    fmt = lambda d: ", ".join(f"{a} {b:.2f} s" for a, b in d["stages"].items())
+    return dict(value=round(est, 1), unit="s", cores=int(os.environ.get("OMP_NUM_THREADS", cores)), kind="oracle",
+                sample=(f"the oracle's whole path to its own convergence (its FP64 LOBPCG with its Chebyshev-Jacobi "
+                        f"preconditioner, k = {k}, residual {tol:g}) on {n_all} particles of the same recipe "
+                        f"on all cores ({fmt(allc)}; {allc['iters']} iterations), every stage scaled linearly to "
+                        f"{n_full} particles; on one core, {n_one} particles: {fmt(one)} ({one['iters']} iterations)"),
+                all_cores=allc, one_core=one,
+                one_core_projection_s=round(sum(one["stages"].values()) * n_full / n_one, 1))
+
+
+GOLDEN_DIR = os.path.join(ROOT, "tests", "golden")
+
+
+def golden_eigs(name, cloud, k=32):
+    """The oracle's reference eigenvalues of a named workload (residual 1e-10, stored with the
+    input's SHA-256 by tests/golden/make_reference_eigs.py), or None if absent or for another input."""
     import numpy as np
-    from oracle import oracle as O
+    path = os.path.join(GOLDEN_DIR, f"ref_eigs_{name}_k{k}.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("sha256") != cloud.sha256():
+        return None
+    return np.array(d["eigenvalues"][:k])
+
+
+def eig_rel_err(ev, ref):
+    """max over j >= 2 of |lambda_j - ref_j| / ref_j, and |lambda_1| / ref_2 for the constant mode."""
+    import numpy as np
+    if ref is None:
+        return None
+    rel = np.abs(ev[1:len(ref)] - ref[1:]) / ref[1:]
+    return dict(max_rel=float(rel.max()), const_mode=float(abs(ev[0]) / ref[1]))
+
+
+def time_solves(ff, ctx, dev_in, c, k, precision, seeds, tol, max_iter, eig_tol=0.0):
+    out = []
+    for sd in seeds:
+        r = run_step(ff, ctx, dev_in, c.n, c.h, k, precision, tol, max_iter, seed=sd, eig_tol=eig_tol)
+        out.append(r)
+    return out
+
+
+def batched_config(ff, ctx, tol, max_iter):
+    """64 sphere-union objects (particle counts log-uniform in 2e3-2e5, E uniform in 1e4-1e6 Pa),
+    k = 16, one launch per stage for all objects with the LOBPCG iteration replayed from a hipGraph."""
+    import numpy as np
+    import torch
     from paper_2605_29318_amd import synth
-    c = synth.ellipsoid_union(n=n_sample, seed=3, hetero=True, k=k, mc_samples=1_000_000)
     t0 = time.perf_counter()
-    P = O.pipeline(c)
-    t1 = time.perf_counter()
-    H, M = P.Hs(), P.Ms()
-    X0 = synth.initial_block(c.n, k, seed=1)
-    t2 = time.perf_counter()
-    O.lobpcg(H, M, X0, k=k, tol=1e-30, maxiter=iters, precond="jacobi")
-    t3 = time.perf_counter()
-    build = t1 - t0
-    per_iter = (t3 - t2) / iters
-    scale = n_full / n_sample
-    est = build * scale + per_iter * scale * gpu_iters
-    return dict(value=round(est, 2), unit="s", cores=os.cpu_count(), kind="oracle",
-                sample=(f"oracle binning+neighbours+RKPM+assembly on {n_sample} particles of the same recipe "
-                        f"({build:.2f} s) and {iters} FP64 Jacobi-preconditioned LOBPCG iterations "
-                        f"({per_iter*1e3:.1f} ms/iter), scaled linearly to {n_full} particles and the GPU's "
-                        f"{gpu_iters} iterations (a lower bound: each GPU iteration also applies the "
-                        f"Chebyshev polynomial, the oracle's applies diag(H)^-1)"),
-                measured_s=round(t3 - t0, 2))
+    clouds = synth.batch_objects(count=64, workers=16)
+    gen = time.perf_counter() - t0
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), device="cuda")
+    ins = [(dev(c.xyz), dev(c.vol), dev(c.lam), dev(c.mu), c.h) for c in clouds]
+    res = []
+    for rep in range(2):                      # the first call also autotunes nothing: same shapes both times
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        parts = [ff.assemble_cloud(ctx, *a) for a in ins]
+        off, rp, col, H, M, hm = ff.concat_objects(parts)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        lam, W, rs, infos, rc = ff.eigenmodes_batched(ctx, off, rp, col, H, M, hm, k=16, tol=tol, max_iter=max_iter,
+                                                      use_graph=True, allow_unconverged=True)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        res.append((t1 - t0, t2 - t1, infos, rc))
+        del parts, rp, col, H, M, hm, W
+    build, solve, infos, rc = res[-1]
+    its = [i["iters_fp32"] + i["iters_fp64"] for i in infos]
+    return dict(objects=64, particles=int(sum(c.n for c in clouds)), k=16, graph=bool(infos[0]["graph"]),
+                seconds=round(build + solve, 3), build_s=round(build, 3), solve_s=round(solve, 3),
+                iters_mean=round(float(np.mean(its)), 1), iters_max=int(max(its)),
+                converged=int(sum(i["converged"] for i in infos)), status=rc, generate_s=round(gen, 1))
+
+
+def paper_training(ff, ctx, S, k, reps=3):
+    """The paper's own construction and eigensolve on one object ("training time", Sec. 4): FPS
+    centres, radii, neighbour lists, RKPM shape functions, H and M, then k modes (mixed path,
+    refined to eigenvalue bound 1e-5)."""
+    import numpy as np
+    import torch
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), device="cuda")
+    ins = (dev(S.xyz), dev(S.vol), dev(S.lam), dev(S.mu))
+    times = []
+    for rep in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        A = ff.paper_construction(ctx, *ins, S.K)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        lam, W, res, info = ff.eigenmodes(ctx, S.K, A.row_ptr, A.col, A.H, A.M, A.hm32, k=k, tol=1e-6, eig_tol=1e-5,
+                                          allow_unconverged=True)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if rep:
+            times.append((t2 - t0, t1 - t0, t2 - t1))
+    tt = np.array(times).mean(axis=0)
+    return dict(integration_points=S.q, centres=S.K, k=k, seconds=round(float(tt[0]), 4),
+                construction_s=round(float(tt[1]), 4), eigensolve_s=round(float(tt[2]), 4),
+                nnz=int(A.col.numel()), converged=bool(info["converged"]), max_eig_bound=info["max_eig_bound"])
+
+
+def matfree_timing(ff, ctx, A, vol, lam, mu, m, reps=10):
+    """Matrix-free [H Y, M Y] (two passes over the neighbour lists, FP32) on the benchmark object,
+    timed with HIP events on torch's stream (the context's)."""
+    import torch
+    n = A.n
+    mf = ff.MatFree(ctx, n, A.nb.nbr_off, A.nb.nbr_id, A.phi, A.dphi, vol, lam, mu, perm=A.nb.perm, precision=1)
+    Y = torch.randn((n, m), dtype=torch.float32, device="cuda")
+    HY = torch.empty_like(Y)
+    MY = torch.empty_like(Y)
+    for _ in range(2):
+        mf.apply(Y, out=(HY, MY))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        mf.apply(Y, out=(HY, MY))
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    entries = int(A.nb.nbr_id.numel())
+    q = n
+    # per list entry: id + (phi, grad phi) FP32, once in each pass; per point: offset, two weights,
+    # the 4m-value pass buffer written and read; per node: offset, Y read, HY and MY written
+    alg = entries * 2 * (4 + 16) + q * (8 + 8 + 2 * 16 * m) + n * (8 + 4 * m + 8 * m)
+    mf.close()
+    return dict(launch_ms=round(ms, 4), bytes_per_launch=alg, achieved_gbps=round(alg / (ms * 1e-3) / 1e9, 1),
+                list_entries=entries, m=m)
 
 
 def main():
@@ -186,6 +339,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--graph", action="store_true")
     ap.add_argument("--no-k64", action="store_true", help="skip the k = 64 solve of the large-object configuration")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the other configurations (100k sphere union, 64-object batch, paper construction)")
     ap.add_argument("--counters", action="store_true",
                     help="run a short solve (--steps iterations) and a 1 GiB calibration kernel (for counter passes)")
     args = ap.parse_args()
@@ -235,15 +390,42 @@ def main():
     A = last["A"]
     nnz = int(A.col.numel())
 
+    ref = golden_eigs("ellipsoids1m", c) if args.n == 1_000_000 and args.k <= 32 else None
     fp64 = None
     if not args.no_fp64:
-        r64 = run_step(ff, ctx, dev_in, c.n, c.h, args.k, 0, args.tol, args.max_iter, args.graph,
-                       seed=args.steps - 1)
-        rel = np.abs(last["ev"][1:] - r64["ev"][1:]) / np.abs(r64["ev"][1:])
-        fp64 = dict(seconds=round(r64["total"], 3), iters=r64["info"]["iters_fp64"],
-                    max_resid=float(r64["res"].max()), converged=bool(r64["info"]["converged"]),
-                    mixed_vs_fp64_eig_rel_diff=float(rel.max()))
-        log(f"[bench] fp64 step: {r64['total']:.3f} s, iters {r64['info']['iters_fp64']}")
+        # the plain FP64 path from the same starts as the timed mixed steps
+        r64s = []
+        for sd in range(args.steps):
+            r64 = run_step(ff, ctx, dev_in, c.n, c.h, args.k, 0, args.tol, args.max_iter, args.graph, seed=sd)
+            r64s.append(r64)
+            log(f"[bench] fp64 seed {sd}: {r64['total']:.3f} s, iters {r64['info']['iters_fp64']}")
+        t64 = [r["total"] for r in r64s]
+        rel = np.abs(last["ev"][1:] - r64s[-1]["ev"][1:]) / np.abs(r64s[-1]["ev"][1:])
+        fp64 = dict(seconds=round(float(np.mean(t64)), 3), seconds_per_seed=[round(x, 3) for x in t64],
+                    iters_per_seed=[r["info"]["iters_fp64"] for r in r64s],
+                    max_resid=float(max(r["res"].max() for r in r64s)),
+                    converged=bool(all(r["info"]["converged"] for r in r64s)),
+                    speedup_per_seed=[round(a / b, 3) for a, b in zip(t64, times)],
+                    mixed_vs_fp64_eig_rel_diff_last_seed=float(rel.max()),
+                    eig_err_vs_reference=eig_rel_err(r64s[-1]["ev"], ref))
+        del r64s
+
+    # time to the eigenvalue tolerance: both paths refined until every pair's a-posteriori bound is
+    # <= 1e-5, then the eigenvalues' measured error against the oracle's reference
+    eig_tol_runs = {}
+    for prec, name in ((1, "mixed"), (0, "fp64")):
+        if prec == 0 and args.no_fp64:
+            continue
+        rs = time_solves(ff, ctx, dev_in, c, args.k, prec, range(min(args.steps, 3)), args.tol, args.max_iter,
+                         eig_tol=1e-5)
+        eig_tol_runs[name] = dict(
+            seconds=round(float(np.mean([r["total"] for r in rs])), 3),
+            iters=[(r["info"]["iters_fp32"], r["info"]["iters_fp64"]) for r in rs],
+            max_eig_bound=float(max(r["info"]["max_eig_bound"] for r in rs)),
+            certified=bool(all(r["info"]["eig_certified"] for r in rs)),
+            eig_err_vs_reference=[eig_rel_err(r["ev"], ref) for r in rs])
+        log(f"[bench] {name} to eigenvalue bound 1e-5: {eig_tol_runs[name]}")
+        del rs
 
     k64 = None
     if not args.no_k64 and args.k == 32:
@@ -254,6 +436,38 @@ def main():
                    converged=bool(r["info"]["converged"]))
         log(f"[bench] k = 64 step: {r['total']:.3f} s, iters {r['info']['iters_fp32']}+{r['info']['iters_fp64']}")
         del r
+    extra = {}
+    if not args.no_extra and args.k == 32:
+        mf = matfree_timing(ff, ctx, last["A"], dev_in[1], dev_in[2], dev_in[3], m=32)
+        extra["matfree_hm"] = mf
+        log(f"[bench] matrix-free [H, M] Y: {mf}")
+        cs = synth.workload("spheres100k")
+        ds = (dev(cs.xyz), dev(cs.vol), dev(cs.lam), dev(cs.mu))
+        ref2 = golden_eigs("spheres100k", cs)
+        time_solves(ff, ctx, ds, cs, 32, 1, [100], args.tol, args.max_iter)              # warm-up
+        mx = time_solves(ff, ctx, ds, cs, 32, 1, range(3), args.tol, args.max_iter)
+        f64 = time_solves(ff, ctx, ds, cs, 32, 0, range(3), args.tol, args.max_iter)
+        ce = time_solves(ff, ctx, ds, cs, 32, 1, range(3), args.tol, args.max_iter, eig_tol=1e-5)
+        extra["spheres100k"] = dict(
+            particles=cs.n, k=32, nnz=int(mx[-1]["A"].col.numel()),
+            mixed_s=round(float(np.mean([r["total"] for r in mx])), 4),
+            mixed_iters=[r["info"]["iters_fp32"] + r["info"]["iters_fp64"] for r in mx],
+            fp64_s=round(float(np.mean([r["total"] for r in f64])), 4),
+            fp64_iters=[r["info"]["iters_fp64"] for r in f64],
+            mixed_eig_tol_s=round(float(np.mean([r["total"] for r in ce])), 4),
+            eig_err_vs_reference=dict(mixed=eig_rel_err(mx[0]["ev"], ref2), fp64=eig_rel_err(f64[0]["ev"], ref2),
+                                      mixed_eig_tol=eig_rel_err(ce[0]["ev"], ref2)))
+        log(f"[bench] spheres100k: {extra['spheres100k']}")
+        del mx, f64, ce, ds
+        extra["paper_beam"] = paper_training(ff, ctx, synth.beam(spacing=0.05, K=1000), k=33)
+        log(f"[bench] paper construction, beam: {extra['paper_beam']}")
+        extra["paper_ellipsoid_blob"] = paper_training(ff, ctx, synth.ellipsoid_blob(spacing=0.02, K=1000), k=33)
+        log(f"[bench] paper construction, ellipsoid blob: {extra['paper_ellipsoid_blob']}")
+        try:
+            extra["batched64"] = batched_config(ff, ctx, args.tol, args.max_iter)
+            log(f"[bench] batched 64 objects: {extra['batched64']}")
+        except Exception as e:          # the batch's generator uses worker processes
+            extra["batched64"] = dict(error=str(e)[:300])
     copy_gbps = stream_copy_gbps()
     log(f"[bench] stream copy (1 GiB, device to device): {copy_gbps:.0f} GB/s")
 
@@ -274,8 +488,7 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        gpu_iters = int(round(sum(step_iters) / len(step_iters)))
-        cpu = cpu_baseline(50_000, args.k, 10, gpu_iters, c.n)
+        cpu = cpu_baseline(args.k, args.tol, c.n)
         log(f"[bench] cpu baseline: {cpu}")
 
     info = last["info"]
@@ -290,7 +503,7 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64",
+        "dtype": "f16+f32+f64",
         "data": "synthetic",
         "config": {"workload": "ellipsoids1m_hetero", "particles": c.n, "k": args.k, "tol": args.tol,
                    "nnz": nnz, "nnz_per_row": round(nnz / c.n, 1), "h": round(c.h, 6),
@@ -306,6 +519,8 @@ def main():
         "converged": bool(info["converged"]),
         "fp64": fp64,
         "speedup_vs_fp64": (round(fp64["seconds"] / (ms_per_step / 1e3), 3) if fp64 else None),
+        "eig_err_vs_reference": eig_rel_err(last["ev"], ref),
+        "eig_tol_1e-5": eig_tol_runs,
         "k64": k64,
         "stream_copy_gbps": round(copy_gbps, 1),
         "spmm_gbps": round(spmm_gbps, 1),
@@ -323,6 +538,7 @@ def main():
                     "launch_ms": round(spmm_avg, 4)},
         "cpu_baseline": cpu,
     }
+    out.update(extra)
     print(json.dumps(out), flush=True)
     ctx.close()
 
