@@ -282,6 +282,8 @@ typedef struct {
                            preconditions with the FP32 / binary16 Chebyshev-Jacobi products (an
                            approximate operator is all a preconditioner needs; the residuals,
                            Grams and Rayleigh-Ritz stay FP64 on the FP64 matrices) */
+    double angle_tol;   /* 0 = off. Else the FP64 phase also iterates until every wanted pair's
+                           angle bound (eig_bounds) is <= angle_tol, as eig_tol does */
 } ff_eig_params;
 
 typedef struct {
@@ -295,7 +297,8 @@ typedef struct {
     double max_eig_bound;   /* max over the k pairs of eig_bound (eig_bounds); infinite if the FP64
                                phase never formed it */
     double max_angle_bound; /* max over the k pairs of angle_bound */
-    int eig_certified;      /* 1 if max_eig_bound <= eig_tol (eig_tol > 0), or <= 1e-5 when eig_tol is 0 */
+    int eig_certified;      /* 1 if max_eig_bound <= eig_tol (eig_tol > 0), or <= 1e-5 when eig_tol is 0,
+                               and max_angle_bound <= angle_tol when angle_tol > 0 */
 } ff_eig_info;
 
 /*
@@ -346,11 +349,13 @@ int eigenmodes_batched(ff_ctx *ctx, int n_obj, const int64_t *obj_row_off, const
  * spectrum. The library takes the residual in the norm of diag(M)^-1 instead (the M^-1
  * norm would need a solve with M), so the figures are estimates, not guarantees:
  *   eta_j^2 = sum_i R_ij^2 / M_ii, in FP64 with the FP64 matrices;
- *   Ritz values within 1e-3 relative of a neighbour form a cluster C, bounded as a
- *   block: eta_C^2 = sum of eta_j^2 over C, gap_C = distance from C to the nearest Ritz
- *   value outside it (including the next Ritz value beyond the block);
- *   eig_bound_j = eta_C^2 / (gap_C max(|theta_j|, theta_1))   (relative eigenvalue error)
- *   angle_bound_j = eta_C / gap_C                             (sine of the largest angle)
+ *   the block form of the bounds holds for a cluster C of consecutive pairs, with
+ *   eta_C^2 = sum of eta_i^2 over C and gap_C = distance from C to the nearest Ritz
+ *   value outside it (including the next Ritz value beyond the block, taken no farther
+ *   than the block's last spacing, as it lies above the eigenvalue); for pair j the
+ *   smallest over the runs of up to 8 consecutive pairs holding j is reported:
+ *   eig_bound_j = min_C eta_C^2 / (gap_C max(|theta_j|, theta_1))   (relative eigenvalue error)
+ *   angle_bound_j = min_C eta_C / gap_C                             (sine of the largest angle)
  * They are formed in the FP64 phase at each residual check; a pair whose gap is unknown
  * (no Ritz value beyond the block yet) has an infinite bound. Returns FF_ERR_INVALID_ARG
  * if n_obj or k differ from the last call's.

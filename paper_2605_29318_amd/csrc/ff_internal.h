@@ -38,6 +38,7 @@ enum WsSlot {
     WS_MDINV,                                                     // diag(M)^-1 for the eigenvalue bounds
     WS_FPS, WS_RADMAX,                                            // farthest point sampling, radius maxima
     WS_MF,                                                        // matrix-free build: transposed entries
+    WS_NT_TMP,                                                    // assembly: sort buffer of long transposed lists
     WS_COUNT
 };
 
@@ -145,6 +146,12 @@ void *pinned_get(ff_ctx *ctx, size_t bytes);
 int scan_exclusive_i64(ff_ctx *ctx, const int64_t *in, int64_t *out, int64_t len);
 // Same for int32 counts into int64 offsets.
 int scan_exclusive_i32_to_i64(ff_ctx *ctx, const int32_t *in, int64_t *out, int64_t len);
+
+// The transpose of the neighbour relation: NT(k) = {(i, slot) : N(i)[slot] = k} in ascending i,
+// nt_off [n+1] and nt [total] device out; empty_node (device, or NULL) receives the smallest
+// node with an empty list (all ones if none).
+int build_transpose(ff_ctx *ctx, hipStream_t st, int64_t n, int64_t q, int64_t total, const int64_t *nbr_off,
+                    const int32_t *nbr_id, int64_t *nt_off, int2 *nt, unsigned long long *empty_node);
 
 inline unsigned grid_for(int64_t items, int per_block) {
     int64_t g = (items + per_block - 1) / per_block;

@@ -228,7 +228,7 @@ __global__ void __launch_bounds__(256) nt_fill_kernel(const int64_t *off, const 
 
 // NT(k) in ascending i (the i are distinct within a list): one wavefront per
 // node copies its list to LDS and writes each entry at its rank; lists longer
-// than kSortMax fall back to an insertion sort by one lane.
+// than kSortMax are left to nt_sort_long_kernel.
 constexpr int kSortMax = 1024;
 __global__ void __launch_bounds__(256) nt_sort_kernel(const int64_t *nt_off, int64_t n, int2 *nt,
                                                       unsigned long long *empty_node) {
@@ -242,19 +242,7 @@ __global__ void __launch_bounds__(256) nt_sort_kernel(const int64_t *nt_off, int
         if (lane == 0) atomicMin(empty_node, (unsigned long long)k);
         return;
     }
-    if (cnt > kSortMax) {
-        if (lane == 0)
-            for (int64_t j = a + 1; j < b; ++j) {
-                const int2 v = nt[j];
-                int64_t t = j - 1;
-                while (t >= a && nt[t].x > v.x) {
-                    nt[t + 1] = nt[t];
-                    --t;
-                }
-                nt[t + 1] = v;
-            }
-        return;
-    }
+    if (cnt > kSortMax) return;
     int2 *bw = buf[wv];
     for (int t = lane; t < cnt; t += 64) bw[t] = nt[a + t];
     __builtin_amdgcn_wave_barrier();
@@ -263,6 +251,91 @@ __global__ void __launch_bounds__(256) nt_sort_kernel(const int64_t *nt_off, int
         int r = 0;
         for (int u = 0; u < cnt; ++u) r += bw[u].x < v.x;
         nt[a + r] = v;
+    }
+}
+
+// The lists longer than kSortMax (many quadrature points per node, as with grid integration
+// points): one workgroup per node marks its entries' i in an LDS bitmap over the list's range of
+// i, and the prefix popcount of the bitmap gives each entry's rank; the sorted list goes to a
+// scratch range, then back. A range wider than kLongBits falls back to an insertion sort by one
+// thread. Workgroups stride over the nodes.
+constexpr int kLongBits = 1 << 17;
+constexpr int kLongWords = kLongBits / 32;
+__global__ void __launch_bounds__(256) nt_sort_long_kernel(const int64_t *nt_off, int64_t n, int2 *nt, int2 *tmp) {
+    __shared__ uint32_t bm[kLongWords];
+    __shared__ int32_t pre[kLongWords];
+    __shared__ int32_t part[256];
+    __shared__ int32_t lo_s, hi_s;
+    const int t = threadIdx.x;
+    for (int64_t k = blockIdx.x; k < n; k += gridDim.x) {
+        const int64_t a = nt_off[k], b = nt_off[k + 1];
+        const int64_t cnt = b - a;
+        if (cnt <= kSortMax) continue;                 // uniform across the workgroup
+        if (t == 0) {
+            lo_s = INT32_MAX;
+            hi_s = -1;
+        }
+        __syncthreads();
+        int lo = INT32_MAX, hi = -1;
+        for (int64_t j = a + t; j < b; j += 256) {
+            const int i = nt[j].x;
+            lo = i < lo ? i : lo;
+            hi = i > hi ? i : hi;
+        }
+        atomicMin(&lo_s, lo);
+        atomicMax(&hi_s, hi);
+        __syncthreads();
+        const int base = lo_s;
+        const int64_t range = (int64_t)hi_s - base + 1;
+        if (range > kLongBits) {
+            if (t == 0)
+                for (int64_t j = a + 1; j < b; ++j) {
+                    const int2 v = nt[j];
+                    int64_t u = j - 1;
+                    while (u >= a && nt[u].x > v.x) {
+                        nt[u + 1] = nt[u];
+                        --u;
+                    }
+                    nt[u + 1] = v;
+                }
+            __syncthreads();
+            continue;
+        }
+        const int nw = (int)((range + 31) >> 5);
+        for (int w = t; w < nw; w += 256) bm[w] = 0u;
+        __syncthreads();
+        for (int64_t j = a + t; j < b; j += 256) {
+            const int x = nt[j].x - base;
+            atomicOr(&bm[x >> 5], 1u << (x & 31));
+        }
+        __syncthreads();
+        // exclusive prefix of popcounts: each thread a contiguous run of words, then the runs
+        const int per = (nw + 255) / 256, w0 = t * per, w1 = w0 + per < nw ? w0 + per : nw;
+        int sum = 0;
+        for (int w = w0; w < w1; ++w) sum += __popc(bm[w]);
+        part[t] = sum;
+        __syncthreads();
+        for (int d = 1; d < 256; d <<= 1) {
+            const int v = t >= d ? part[t - d] : 0;
+            __syncthreads();
+            part[t] += v;
+            __syncthreads();
+        }
+        int run = part[t] - sum;
+        for (int w = w0; w < w1; ++w) {
+            pre[w] = run;
+            run += __popc(bm[w]);
+        }
+        __syncthreads();
+        for (int64_t j = a + t; j < b; j += 256) {
+            const int2 v = nt[j];
+            const int x = v.x - base;
+            const int r = pre[x >> 5] + __popc(bm[x >> 5] & ((1u << (x & 31)) - 1u));
+            tmp[a + r] = v;
+        }
+        __syncthreads();
+        for (int64_t j = a + t; j < b; j += 256) nt[j] = tmp[j];
+        __syncthreads();
     }
 }
 
@@ -457,6 +530,36 @@ __global__ void __launch_bounds__(256) num_kernel(int64_t n, const int64_t *cs, 
 }
 
 }  // namespace
+
+int build_transpose(ff_ctx *ctx, hipStream_t st, int64_t n, int64_t q, int64_t total, const int64_t *nbr_off,
+                    const int32_t *nbr_id, int64_t *nt_off, int2 *nt, unsigned long long *empty_node) {
+    int32_t *cnt = (int32_t *)ws_get(ctx, WS_COUNTS, (size_t)n * sizeof(int32_t));
+    int32_t *cursor = (int32_t *)ws_get(ctx, WS_CURSOR, (size_t)n * sizeof(int32_t));
+    int2 *tmp = (int2 *)ws_get(ctx, WS_NT_TMP, (size_t)(total > 0 ? total : 1) * sizeof(int2));
+    unsigned long long *en = empty_node;
+    if (!en) en = (unsigned long long *)ws_get(ctx, WS_FLAG, 64);
+    if (!cnt || !cursor || !tmp || !en) return FF_ERR_OOM;
+    FF_HIP(ctx, hipMemsetAsync(cnt, 0, (size_t)n * sizeof(int32_t), st));
+    FF_HIP(ctx, hipMemsetAsync(cursor, 0, (size_t)n * sizeof(int32_t), st));
+    FF_HIP(ctx, hipMemsetAsync(en, 0xff, 8, st));
+    if (total > 0) {
+        hipLaunchKernelGGL(nt_count_kernel, dim3(grid_for(total, 256)), dim3(256), 0, st, nbr_id, total, cnt);
+        FF_CHECK_LAUNCH(ctx);
+    }
+    int rc = scan_exclusive_i32_to_i64(ctx, cnt, nt_off, n);
+    if (rc) return rc;
+    hipLaunchKernelGGL(nt_fill_kernel, dim3(grid_for(q, 256)), dim3(256), 0, st, nbr_off, nbr_id, q, nt_off, cursor,
+                       nt);
+    FF_CHECK_LAUNCH(ctx);
+    hipLaunchKernelGGL(nt_sort_kernel, dim3(grid_for(n, 4)), dim3(256), 0, st, nt_off, n, nt, en);
+    FF_CHECK_LAUNCH(ctx);
+    // the long lists (grid integration points: thousands of points per node)
+    hipLaunchKernelGGL(nt_sort_long_kernel, dim3((unsigned)std::min<int64_t>(n, 4096)), dim3(256), 0, st, nt_off, n,
+                       nt, tmp);
+    FF_CHECK_LAUNCH(ctx);
+    return FF_OK;
+}
+
 }  // namespace ff
 
 using namespace ff;
@@ -535,19 +638,9 @@ extern "C" int assemble_HM(ff_ctx *ctx, int64_t n, int64_t q, const int64_t *nbr
         int *stats = (int *)ws_get(ctx, WS_ASM_FLAG, 64);
         if (!cnt || !cursor || !nt_off || !nt || !rowlen || !stats) return FF_ERR_OOM;
         unsigned long long *empty_node = (unsigned long long *)(stats + 4);
-        FF_HIP(ctx, hipMemsetAsync(cnt, 0, (size_t)n * sizeof(int32_t), st));
-        FF_HIP(ctx, hipMemsetAsync(cursor, 0, (size_t)n * sizeof(int32_t), st));
         FF_HIP(ctx, hipMemsetAsync(stats, 0, 16, st));
-        FF_HIP(ctx, hipMemsetAsync(empty_node, 0xff, 8, st));
-        hipLaunchKernelGGL(nt_count_kernel, dim3(grid_for(total, 256)), dim3(256), 0, st, nbr_id, total, cnt);
-        FF_CHECK_LAUNCH(ctx);
-        int rc = scan_exclusive_i32_to_i64(ctx, cnt, nt_off, n);
+        int rc = build_transpose(ctx, st, n, q, total, nbr_off, nbr_id, nt_off, nt, empty_node);
         if (rc) return rc;
-        hipLaunchKernelGGL(nt_fill_kernel, dim3(grid_for(q, 256)), dim3(256), 0, st, nbr_off, nbr_id, q, nt_off, cursor,
-                           nt);
-        FF_CHECK_LAUNCH(ctx);
-        hipLaunchKernelGGL(nt_sort_kernel, dim3(grid_for(n, 4)), dim3(256), 0, st, nt_off, n, nt, empty_node);
-        FF_CHECK_LAUNCH(ctx);
 
         const size_t bm_bytes = (size_t)n * kWinWords * sizeof(uint32_t);
         if (bm_bytes <= (ctx->asm_bm_cap >= 0 ? (size_t)ctx->asm_bm_cap : kBitmapBytes)) {

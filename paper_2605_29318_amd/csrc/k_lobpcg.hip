@@ -540,24 +540,27 @@ __global__ void __launch_bounds__(256) resid_kernel(const UChunk *chunks, const 
 // With ebound non-NULL, also the a-posteriori bounds of every pair (the residual taken in the
 // norm of diag(M)^-1, eta_j^2 = sum_i R_ij^2 / M_ii, standing in for the M^-1 norm of the
 // quadratic eigenvalue bound |theta - lambda| <= ||r||^2_{M^-1} / gap and of the Davis-Kahan
-// angle bound sin <= ||r||_{M^-1} / gap; the columns are M-orthonormal). Ritz values closer than
-// 1e-3 relative form a cluster, bounded as a block: eta_C^2 = sum of eta_j^2 over the cluster,
-// gap = distance from the cluster to the nearest Ritz value outside it (theta_next, the next Ritz
-// value of the last Rayleigh-Ritz step, beyond the block; unknown = NaN makes the bound infinite).
-//   ebound_j = eta_C^2 / (gap theta_ref), theta_ref = max(|theta_j|, theta_1) (relative error;
-//              the constant mode's is relative to theta_1)
-//   abound_j = eta_C / gap
+// angle bound sin <= ||r||_{M^-1} / gap; the columns are M-orthonormal). For pair j,
+// any run C of up to 8 consecutive pairs holding j is a cluster the block form of these bounds
+// applies to: eta_C^2 = sum of eta_i^2 over C, gap_C = distance from C to the nearest Ritz value
+// outside it (theta_next, the next Ritz value of the last Rayleigh-Ritz step, beyond the block,
+// counted no farther than the block's last spacing; unknown = NaN rules the run out), and the
+// smallest bound over the runs is kept:
+//   ebound_j = min_C eta_C^2 / (gap_C theta_ref), theta_ref = max(|theta_j|, theta_1) (relative
+//              error; the constant mode's is relative to theta_1)
+//   abound_j = min_C eta_C / gap_C
 // With eig_tol > 0 an object converges only when both max_j r_j <= tol and max_j ebound_j <=
 // eig_tol over the first k pairs.
 __global__ void __launch_bounds__(1024) norms_kernel(int *obj_status, const int *cfirst, const int *ccount,
                                                      const double *rpart, int m, int k, const double *theta,
                                                      const double *norms, double tol, int stall_limit,
                                                      double *res, double *track, const double *theta_next,
-                                                     double eig_tol, double *ebound, double *abound) {
+                                                     double eig_tol, double angle_tol, double *ebound,
+                                                     double *abound) {
     const int o = blockIdx.x;
     if (obj_status[o] != 0) return;
     __shared__ double part[16][192];
-    __shared__ double rj[64], eta2[64], th[65], eb[64];
+    __shared__ double rj[64], eta2[64], th[65], eb[64], ab[64];
     const int q = threadIdx.x & 127, pp = threadIdx.x >> 7;   // 8 parts of 128 outputs
     const int c0 = cfirst[o], nc = ccount[o];
     for (int q2 = q; q2 < 3 * m; q2 += 128)
@@ -586,33 +589,48 @@ __global__ void __launch_bounds__(1024) norms_kernel(int *obj_status, const int 
     if (threadIdx.x == 0) th[m] = theta_next ? theta_next[o] : NAN;
     __syncthreads();
     if (ebound && threadIdx.x < m) {
+        // every run [a, b) of up to kSpan consecutive pairs that holds c is a cluster the block bound
+        // applies to; the smallest bound over them is kept (a pair close to a neighbour is bounded
+        // together with it instead of by their small distance)
+        constexpr int kSpan = 8;
         const int c = threadIdx.x;
-        const double crel = 1e-3;
-        int a = c, b = c + 1;                      // cluster [a, b) of Ritz values within crel of a neighbour
-        while (a > 0 && th[a] - th[a - 1] <= crel * fabs(th[a])) --a;
-        while (b <= m && th[b] - th[b - 1] <= crel * fabs(th[b])) ++b;
-        double gap = INFINITY;
-        if (a > 0) gap = th[a] - th[a - 1];
-        if (b <= m) gap = fmin(gap, th[b] - th[b - 1]);
-        if (b > m || (b == m && !(th[m] == th[m]))) gap = NAN;   // the cluster reaches an unknown value
-        double e2 = 0.0;
-        for (int j = a; j < b && j < m; ++j) e2 += eta2[j];
         const double ref = fmax(fabs(th[c]), m > 1 ? th[1] : th[m]);
-        double eb_c = e2 / (gap * ref), ab_c = sqrt(e2) / gap;
-        if (!(eb_c == eb_c) || !(ref > 0.0)) eb_c = INFINITY;
-        if (!(ab_c == ab_c)) ab_c = INFINITY;
-        ebound[(size_t)o * m + c] = eb_c;
-        abound[(size_t)o * m + c] = ab_c;
-        eb[c] = c < k ? eb_c : 0.0;
+        double best_e = INFINITY, best_a = INFINITY;
+        for (int a = c; a >= 0 && a > c - kSpan; --a) {
+            double e2 = 0.0;
+            for (int j = a; j < c; ++j) e2 += eta2[j];
+            for (int b = c + 1; b <= m && b - a <= kSpan; ++b) {
+                e2 += eta2[b - 1];
+                double gap = a > 0 ? th[a] - th[a - 1] : INFINITY;
+                // above the block the next Ritz value is the only estimate of the next eigenvalue, and
+                // it lies above it (Ritz values bound eigenvalues from above): the gap to it is taken
+                // no wider than the block's last spacing, so that it cannot make the bound small
+                const double up = b < m ? th[b] - th[b - 1]
+                                        : fmin(th[m] - th[m - 1], m > 1 ? th[m - 1] - th[m - 2] : INFINITY);
+                gap = fmin(gap, up);
+                if (!(gap > 0.0)) continue;                    // unknown (NaN) or not separated
+                best_e = fmin(best_e, e2 / (gap * ref));
+                best_a = fmin(best_a, sqrt(e2) / gap);
+            }
+        }
+        if (!(ref > 0.0)) best_e = INFINITY;
+        ebound[(size_t)o * m + c] = best_e;
+        abound[(size_t)o * m + c] = best_a;
+        eb[c] = c < k ? best_e : 0.0;
+        ab[c] = c < k ? best_a : 0.0;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double v = 0.0, ve = 0.0;
+        double v = 0.0, ve = 0.0, va = 0.0;
         for (int c = 0; c < k; ++c) v = fmax(v, rj[c]);
         if (ebound)
-            for (int c = 0; c < k; ++c) ve = fmax(ve, eb[c]);
+            for (int c = 0; c < k; ++c) {
+                ve = fmax(ve, eb[c]);
+                va = fmax(va, ab[c]);
+            }
         double *tr = track + 2 * o;               // [best max residual, iterations since improvement]
-        if (v <= tol && (eig_tol <= 0.0 || (ebound && ve <= eig_tol))) {
+        if (v <= tol && (eig_tol <= 0.0 || (ebound && ve <= eig_tol)) &&
+            (angle_tol <= 0.0 || (ebound && va <= angle_tol))) {
             obj_status[o] = 1;
         } else if (stall_limit > 0) {
             if (v < 0.9 * tr[0]) {
@@ -2088,6 +2106,7 @@ struct Solver {
     double *ebound = nullptr, *abound = nullptr;   // [n_obj][m] eigenvalue and angle bounds of the pairs
     double *mdinv = nullptr;                       // [N] diag(M)^-1 for the bounds
     double eig_tol = 0.0;                          // FP64 phase: also require max ebound <= eig_tol
+    double angle_tol = 0.0;                        // and max abound <= angle_tol
     int bounds_on = 0;                             // the residual stage forms the bounds (FP64 phase)
     float *S32 = nullptr;                          // FP32 blocks of the mixed path (its FP64 phase
                                                    // preconditions through them)
@@ -2238,7 +2257,7 @@ int stage_resid(Solver &s, T *S, T *HS, T *MS, double tol, int stall) {
     FF_CHECK_LAUNCH(s.ctx);
     hipLaunchKernelGGL(norms_kernel, dim3(s.n_obj), dim3(1024), 0, s.st, s.status, s.gfirst, s.gcount, s.rpart, s.m,
                        s.k, s.theta, s.norms, tol, stall, s.res, s.track, (const double *)s.theta_next,
-                       bounds ? s.eig_tol : 0.0, bounds ? s.ebound : (double *)nullptr,
+                       bounds ? s.eig_tol : 0.0, bounds ? s.angle_tol : 0.0, bounds ? s.ebound : (double *)nullptr,
                        bounds ? s.abound : (double *)nullptr);
     FF_CHECK_LAUNCH(s.ctx);
     hipLaunchKernelGGL(count_iter_kernel, dim3(grid_for(s.n_obj, 64)), dim3(64), 0, s.st, s.n_obj, s.status, s.iters);
@@ -2636,6 +2655,7 @@ int setup(Solver &s, const ff_eig_params *p) {
                        (int64_t)n_obj * 2 * m, s.ebound, (double)INFINITY);
     FF_CHECK_LAUNCH(ctx);
     s.eig_tol = p->eig_tol;
+    s.angle_tol = p->angle_tol;
     s.mdinv = (double *)ws_get(ctx, WS_MDINV, (size_t)s.N * sizeof(double));
     if (!s.mdinv) return FF_ERR_OOM;
     hipLaunchKernelGGL(diag_inv_m_kernel, dim3(grid_for(s.N, 256)), dim3(256), 0, s.st, s.N, s.row_ptr, s.col, s.M,
@@ -2704,6 +2724,7 @@ int solve(ff_ctx *ctx, int n_obj, const int64_t *obj_off, const int64_t *row_ptr
     FF_REQUIRE(ctx, p->precond != 2 || p->precond_ratio == 0.0 || (p->precond_ratio > 1.0 && p->precond_ratio <= 1e6),
                "Chebyshev interval ratio %g must be 0 (default %g) or in (1, 1e6]", p->precond_ratio, kChebRatio);
     FF_REQUIRE(ctx, p->eig_tol >= 0.0 && p->eig_tol == p->eig_tol, "eig_tol must be >= 0");
+    FF_REQUIRE(ctx, p->angle_tol >= 0.0 && p->angle_tol == p->angle_tol, "angle_tol must be >= 0");
     FF_REQUIRE(ctx, p->precond_values >= 0 && p->precond_values <= 3,
                "precond_values %d must be 0 (default), 1 (FP32), 2 (binary16 H) or 3 (binary16 H and iterate)",
                p->precond_values);
@@ -2916,7 +2937,8 @@ int solve(ff_ctx *ctx, int n_obj, const int64_t *obj_off, const int64_t *row_ptr
             info[o].seconds = 0.0;
             info[o].max_eig_bound = mxe;
             info[o].max_angle_bound = mxa;
-            info[o].eig_certified = mxe <= (p->eig_tol > 0.0 ? p->eig_tol : 1e-5);
+            info[o].eig_certified = mxe <= (p->eig_tol > 0.0 ? p->eig_tol : 1e-5) &&
+                                    (p->angle_tol <= 0.0 || mxa <= p->angle_tol);
         }
     }
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();

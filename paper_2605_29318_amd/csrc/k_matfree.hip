@@ -37,61 +37,18 @@ template <typename T> __device__ inline typename MfVals<T>::V mf_entry(const dou
 }
 
 // ---------------------------------------------------------------------------
-// build: per-node counts, offsets, scatter, per-node sort by point, value copies
+// build: the transposed lists (shared with the assembly), value copies, weights
 // ---------------------------------------------------------------------------
 
-__global__ void mf_count_kernel(const int32_t *ids, int64_t total, int32_t *cnt) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < total) atomicAdd(&cnt[ids[e]], 1);
-}
-
-// each point's entries go to their nodes' lists (any order; sorted below)
-__global__ void mf_scatter_kernel(const int64_t *off, const int32_t *ids, int64_t q, const int64_t *toff,
-                                  int32_t *cursor, int64_t *tent) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= q) return;
-    for (int64_t e = off[i]; e < off[i + 1]; ++e) {
-        const int32_t k = ids[e];
-        const int64_t pos = toff[k] + atomicAdd(&cursor[k], 1);
-        tent[pos] = e;                         // the entry's index in the neighbour lists
-    }
-}
-
-// a node's list in ascending entry index, i.e. ascending point (lists are stored by point)
-__global__ void mf_sort_kernel(const int64_t *toff, int64_t n, int64_t *tent) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    const int64_t a = toff[k], b = toff[k + 1];
-    for (int64_t j = a + 1; j < b; ++j) {
-        const int64_t v = tent[j];
-        int64_t t = j - 1;
-        while (t >= a && tent[t] > v) {
-            tent[t + 1] = tent[t];
-            --t;
-        }
-        tent[t + 1] = v;
-    }
-}
-
-// point of each entry (entries are stored by point: binary search over off)
-__device__ inline int64_t point_of(const int64_t *off, int64_t q, int64_t e) {
-    int64_t lo = 0, hi = q - 1;
-    while (lo < hi) {
-        const int64_t mid = (lo + hi + 1) >> 1;
-        if (off[mid] <= e) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
-
+// the transposed entries' point and (phi, grad phi), from the transposed lists (i, slot)
 template <typename T>
-__global__ void mf_transposed_values_kernel(const int64_t *tent, int64_t total, const int64_t *off, int64_t q,
-                                            const double *phi, const double *dphi, int32_t *tpt,
-                                            typename MfVals<T>::V *tval) {
+__global__ void mf_transposed_values_kernel(const int2 *nt, int64_t total, const int64_t *off, const double *phi,
+                                            const double *dphi, int32_t *tpt, typename MfVals<T>::V *tval) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= total) return;
-    const int64_t e = tent[t];
-    tpt[t] = (int32_t)point_of(off, q, e);
-    tval[t] = mf_entry<T>(phi, dphi, e);
+    const int2 v = nt[t];
+    tpt[t] = v.x;
+    tval[t] = mf_entry<T>(phi, dphi, off[v.x] + v.y);
 }
 
 template <typename T>
@@ -341,31 +298,20 @@ extern "C" int mf_build(ff_ctx *ctx, int64_t n, int64_t q, const int64_t *nbr_of
     mf->wm = p + b_toff + b_tpt + 2 * b_val;
     mf->wh = p + b_toff + b_tpt + 2 * b_val + b_w;
     int rc = FF_OK;
-    int32_t *cnt = (int32_t *)ws_get(ctx, WS_COUNTS, (size_t)n * sizeof(int32_t));
-    int32_t *cursor = (int32_t *)ws_get(ctx, WS_CURSOR, (size_t)n * sizeof(int32_t));
-    int64_t *tent = (int64_t *)ws_get(ctx, WS_MF, (size_t)std::max<int64_t>(total, 1) * sizeof(int64_t));
-    if (!cnt || !cursor || !tent) rc = FF_ERR_OOM;
-    if (!rc && hipMemsetAsync(cnt, 0, (size_t)n * 4, st) != hipSuccess) rc = FF_ERR_HIP;
-    if (!rc && hipMemsetAsync(cursor, 0, (size_t)n * 4, st) != hipSuccess) rc = FF_ERR_HIP;
+    int2 *nt = (int2 *)ws_get(ctx, WS_MF, (size_t)std::max<int64_t>(total, 1) * sizeof(int2));
+    if (!nt) rc = FF_ERR_OOM;
+    if (!rc) rc = build_transpose(ctx, st, n, q, total, nbr_off, nbr_id, mf->toff, nt, nullptr);
     if (!rc) {
-        hipLaunchKernelGGL(mf_count_kernel, dim3(grid_for(total, 256)), dim3(256), 0, st, nbr_id, total, cnt);
-        rc = scan_exclusive_i32_to_i64(ctx, cnt, mf->toff, n);
-    }
-    if (!rc) {
-        hipLaunchKernelGGL(mf_scatter_kernel, dim3(grid_for(q, 256)), dim3(256), 0, st, nbr_off, nbr_id, q,
-                           (const int64_t *)mf->toff, cursor, tent);
-        hipLaunchKernelGGL(mf_sort_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, (const int64_t *)mf->toff, n,
-                           tent);
         if (precision) {
             hipLaunchKernelGGL(mf_transposed_values_kernel<float>, dim3(grid_for(total, 256)), dim3(256), 0, st,
-                               (const int64_t *)tent, total, nbr_off, q, phi, dphi, mf->tpt, (float4 *)mf->tval);
+                               (const int2 *)nt, total, nbr_off, phi, dphi, mf->tpt, (float4 *)mf->tval);
             hipLaunchKernelGGL(mf_values_kernel<float>, dim3(grid_for(total, 256)), dim3(256), 0, st, total, phi,
                                dphi, (float4 *)mf->val);
             hipLaunchKernelGGL(mf_weights_kernel<float>, dim3(grid_for(q, 256)), dim3(256), 0, st, q, vol, lam, mu,
                                rho, perm, (float *)mf->wm, (float *)mf->wh);
         } else {
             hipLaunchKernelGGL(mf_transposed_values_kernel<double>, dim3(grid_for(total, 256)), dim3(256), 0, st,
-                               (const int64_t *)tent, total, nbr_off, q, phi, dphi, mf->tpt, (double4 *)mf->tval);
+                               (const int2 *)nt, total, nbr_off, phi, dphi, mf->tpt, (double4 *)mf->tval);
             hipLaunchKernelGGL(mf_values_kernel<double>, dim3(grid_for(total, 256)), dim3(256), 0, st, total, phi,
                                dphi, (double4 *)mf->val);
             hipLaunchKernelGGL(mf_weights_kernel<double>, dim3(grid_for(q, 256)), dim3(256), 0, st, q, vol, lam, mu,

@@ -48,7 +48,7 @@ class ff_eig_params(ctypes.Structure):
                 ("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("precond", ctypes.c_int),
                 ("seed", ctypes.c_uint64), ("check_every", ctypes.c_int), ("use_graph", ctypes.c_int),
                 ("refresh_every", ctypes.c_int), ("precond_degree", ctypes.c_int), ("precond_ratio", ctypes.c_double),
-                ("precond_values", ctypes.c_int), ("eig_tol", ctypes.c_double)]
+                ("precond_values", ctypes.c_int), ("eig_tol", ctypes.c_double), ("angle_tol", ctypes.c_double)]
 
 
 class ff_eig_info(ctypes.Structure):
@@ -323,9 +323,10 @@ def assemble_HM(ctx: Context, n: int, nbr_off, nbr_id, phi, dphi, vol, lam, mu, 
 
 
 def _params(k, block, precision, tol, max_iter, precond, seed, check_every, use_graph, refresh_every,
-            precond_degree=0, precond_ratio=0.0, precond_values=0, eig_tol=0.0):
+            precond_degree=0, precond_ratio=0.0, precond_values=0, eig_tol=0.0, angle_tol=0.0):
     return ff_eig_params(k, block, precision, tol, max_iter, precond, seed, check_every, int(use_graph),
-                         refresh_every, precond_degree, float(precond_ratio), precond_values, float(eig_tol))
+                         refresh_every, precond_degree, float(precond_ratio), precond_values, float(eig_tol),
+                         float(angle_tol))
 
 
 def _info_dict(i):
@@ -337,10 +338,11 @@ def _info_dict(i):
 def eigenmodes(ctx: Context, n: int, row_ptr, col, H, M, hm32, k: int, block: int = 0, precision: int = 1,
                tol: float = 1e-6, max_iter: int = 5000, precond: int = 2, seed: int = 0, X0=None,
                check_every: int = 10, use_graph: bool = False, refresh_every: int = 0, allow_unconverged=False,
-               precond_degree: int = 0, precond_ratio: float = 0.0, precond_values: int = 0, eig_tol: float = 0.0):
+               precond_degree: int = 0, precond_ratio: float = 0.0, precond_values: int = 0, eig_tol: float = 0.0,
+               angle_tol: float = 0.0):
     import torch
     p = _params(k, block, precision, tol, max_iter, precond, seed, check_every, use_graph, refresh_every,
-                precond_degree, precond_ratio, precond_values, eig_tol)
+                precond_degree, precond_ratio, precond_values, eig_tol, angle_tol)
     m = block if block > 0 else (k + 7) // 8 * 8
     _check_block(X0, n, m, H.device)
     lam = np.zeros(k)
@@ -360,13 +362,14 @@ def eigenmodes_batched(ctx: Context, obj_row_off, row_ptr, col, H, M, hm32, k: i
                        precision: int = 1, tol: float = 1e-6, max_iter: int = 5000, precond: int = 2,
                        seed: int = 0, X0=None, check_every: int = 10, use_graph: bool = False,
                        refresh_every: int = 0, allow_unconverged=False, precond_degree: int = 0,
-                       precond_ratio: float = 0.0, precond_values: int = 0, eig_tol: float = 0.0):
+                       precond_ratio: float = 0.0, precond_values: int = 0, eig_tol: float = 0.0,
+                       angle_tol: float = 0.0):
     import torch
     off = np.ascontiguousarray(obj_row_off, dtype=np.int64)
     n_obj = len(off) - 1
     N = int(off[-1])
     p = _params(k, block, precision, tol, max_iter, precond, seed, check_every, use_graph, refresh_every,
-                precond_degree, precond_ratio, precond_values, eig_tol)
+                precond_degree, precond_ratio, precond_values, eig_tol, angle_tol)
     _check_block(X0, N, block if block > 0 else (k + 7) // 8 * 8, H.device)
     lam = np.zeros((n_obj, k))
     res = np.zeros((n_obj, k))

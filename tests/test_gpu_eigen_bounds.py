@@ -4,12 +4,14 @@ through the C ABI.
 The solver reports, per pair, the estimate ||r||^2 / (gap theta) of the relative
 eigenvalue error and ||r|| / gap of the eigenvector angle (residual in the norm of
 diag(M)^-1, clusters bounded as blocks); with eig_tol it keeps iterating in FP64
-until every wanted pair's estimate is at most eig_tol. Checked here against the
-plain definition (dense LAPACK eigh) on small clouds, pair by pair, and at full
-size against the oracle's reference eigenvalues (the oracle's FP64 LOBPCG to a
-backward-error residual of 1e-10, stored with the input's SHA-256 by
-tests/golden/make_reference_eigs.py): relative eigenvalue error at most 1e-5,
-the benchmark spec's tolerance of the mixed path.
+until every wanted pair's estimate is at most eig_tol (and with angle_tol every
+angle estimate at most angle_tol). Checked here against the plain definition
+(dense LAPACK eigh) on small clouds, pair by pair, with subspace angles, and at
+full size against the oracle's reference eigenvalues (the oracle's FP64 LOBPCG
+to a backward-error residual of 1e-10 at 10^5 particles and 1e-8 at 10^6, where
+its eigenvalue error is orders of magnitude below the tolerance checked, stored
+with the input's SHA-256 by tests/golden/make_reference_eigs.py): relative
+eigenvalue error at most 1e-5, the tolerance of the mixed path.
 """
 import json
 import os
@@ -64,7 +66,7 @@ def test_refinement_meets_the_eigenvalue_tolerance(small, oracle, ctx, ff, preci
     c, P, A, wd, Vd = small
     k = 16
     lam, W, res, info = ff.eigenmodes(ctx, c.n, A.row_ptr, A.col, A.H, A.M, A.hm32, k=k, precision=precision,
-                                      tol=1e-6, eig_tol=1e-5, seed=3)
+                                      tol=1e-6, eig_tol=1e-5, angle_tol=1e-3, seed=3)
     assert info["converged"] == 1 and info["eig_certified"] == 1
     assert info["max_eig_bound"] <= 1e-5 and res.max() <= 1e-6
     eb, ab = ff.eig_bounds(ctx, 1, k)
@@ -72,8 +74,9 @@ def test_refinement_meets_the_eigenvalue_tolerance(small, oracle, ctx, ff, preci
     assert abs(eb.max() - info["max_eig_bound"]) <= 1e-12 * info["max_eig_bound"] + 1e-300
     err = np.abs(lam[1:] - wd[1:k]) / wd[1:k]
     assert err.max() <= 1e-5, err.max()
-    # the estimate is above the error it estimates, pair by pair
-    assert np.all(err <= eb[0, 1:]), (err, eb[0, 1:])
+    # the estimate is above the error it estimates, pair by pair, down to the rounding floor of
+    # the eigenvalues themselves (FP64 solves of a pencil with cond(M) ~ 1e7, here and in LAPACK)
+    assert np.all(err <= eb[0, 1:] + 1e-9), (err, eb[0, 1:])
     assert abs(lam[0]) <= eb[0, 0] * lam[1] + 1e-12 * lam[1]
     kk = oracle.cluster_safe_k(wd, k)
     s = oracle.subspace_sines(Vd[:, :kk], host(W)[:, :kk], P.Ms())
@@ -88,7 +91,7 @@ def test_bounds_reported_without_refinement(small, ctx, ff):
     lam0, _, _, i0 = ff.eigenmodes(ctx, c.n, A.row_ptr, A.col, A.H, A.M, A.hm32, k=k, tol=1e-6, seed=3)
     eb0, _ = ff.eig_bounds(ctx, 1, k)
     assert np.isfinite(i0["max_eig_bound"]) and i0["max_eig_bound"] == eb0.max()
-    lam1, _, _, i1 = ff.eigenmodes(ctx, c.n, A.row_ptr, A.col, A.H, A.M, A.hm32, k=k, tol=1e-6, seed=3, eig_tol=1e-5)
+    lam1, _, _, i1 = ff.eigenmodes(ctx, c.n, A.row_ptr, A.col, A.H, A.M, A.hm32, k=k, tol=1e-6, seed=3, eig_tol=1e-5, angle_tol=1e-3)
     assert i1["max_eig_bound"] <= 1e-5
     if i0["max_eig_bound"] > 1e-5:
         assert i1["iters_fp64"] > i0["iters_fp64"]
@@ -105,7 +108,7 @@ def test_bounds_batched(oracle, ctx, ff):
     parts = [ff.assemble_cloud(ctx, dev(c.xyz), dev(c.vol), dev(c.lam), dev(c.mu), c.h) for c in objs]
     off, rp, col, H, M, hm = ff.concat_objects(parts)
     k = 8
-    lam, W, res, infos, rc = ff.eigenmodes_batched(ctx, off, rp, col, H, M, hm, k=k, tol=1e-6, eig_tol=1e-5)
+    lam, W, res, infos, rc = ff.eigenmodes_batched(ctx, off, rp, col, H, M, hm, k=k, tol=1e-6, eig_tol=1e-5, angle_tol=1e-3)
     assert rc == 0
     eb, ab = ff.eig_bounds(ctx, len(objs), k)
     for j, c in enumerate(objs):
@@ -113,7 +116,7 @@ def test_bounds_batched(oracle, ctx, ff):
         wd, _ = oracle.dense_eigh(P.Hs(), P.Ms(), k + 2)
         err = np.abs(lam[j, 1:] - wd[1:k]) / wd[1:k]
         assert infos[j]["max_eig_bound"] <= 1e-5 and infos[j]["eig_certified"] == 1
-        assert err.max() <= 1e-5 and np.all(err <= eb[j, 1:])
+        assert err.max() <= 1e-5 and np.all(err <= eb[j, 1:] + 1e-9)
 
 
 def test_eig_tol_validated(small, ctx, ff):
@@ -138,7 +141,7 @@ def test_fullsize_eigenvalues_against_reference(oracle, ctx, ff, name):
     print(f"\n[golden] {name}: cloud in {time.time() - t0:.1f} s", flush=True)
     A = ff.assemble_cloud(ctx, dev(c.xyz), dev(c.vol), dev(c.lam), dev(c.mu), c.h)
     lr = np.array(ref["eigenvalues"][:32])
-    assert max(ref["residuals"][:32]) <= 1e-9
+    assert max(ref["residuals"][:32]) <= 1e-8
     out = {}
     for eig_tol in (0.0, 1e-5):
         torch.cuda.synchronize()
