@@ -273,8 +273,10 @@ typedef struct {
                            and the iterate in binary16 on the matrix cores (rowtiles_build precision 6;
                            block width 32 or 64), each column of the preconditioner's input scaled by
                            the inverse of its largest magnitude per object (the output's span is
-                           unchanged); 0 = default: 3 where the width allows, else 2. Products
-                           accumulate in FP32 in every case */
+                           unchanged); 4 = 3 with the K-blocks stored without their zeros (a mask per
+                           K-block and the present values, rebuilt in LDS: the same products
+                           bit for bit from fewer bytes); 0 = default: 4 where the width allows,
+                           else 2. Products accumulate in FP32 in every case */
     double eig_tol;     /* 0 = off. Else the FP64 phase also iterates until the a-posteriori
                            eigenvalue bound of every wanted pair (eig_bounds) is <= eig_tol
                            (relative): an object converges when max_j r_j <= tol and
@@ -484,11 +486,14 @@ int rayleigh_ritz_noalloc(ff_ctx *ctx, int w, int m, const double *G, double tau
  *   rows) or m in {4, 8, 12, 16, 32, 64} (sixteen rows). A handle built
  *   with precision 6 also takes precision 2: Y in binary16 ([n][m] with
  *   ld_y == m, m 32 or 64), HY = H Y in FP32, accumulated in FP32 on
- *   v_mfma_f32_16x16x16_f16 (MY NULL); its launch shapes are sub 0 .. 7
+ *   v_mfma_f32_16x16x16_f16 (MY NULL); its launch shapes are sub 0 .. 12
  *   (0 .. 4: a ring of K-blocks, by waves per workgroup and K-blocks in
  *   flight; 5 .. 7: super-blocks of four K-blocks, the next one's loads
- *   issued before the current one is multiplied), all with the same
- *   summation order. Errors: invalid
+ *   issued before the current one is multiplied; 8 .. 12: the same
+ *   super-blocks read from a copy without the K-blocks' zeros, a 128-bit
+ *   mask per K-block and the present values, which a precision-6 handle
+ *   keeps beside the full K-blocks), all with the same operands and
+ *   summation order, so the same result bit for bit. Errors: invalid
  *   arguments and unsupported shapes return FF_ERR_INVALID_ARG, a
  *   non-finite H at precision 5 likewise.
  */

@@ -39,6 +39,7 @@ enum WsSlot {
     WS_FPS, WS_RADMAX,                                            // farthest point sampling, radius maxima
     WS_MF,                                                        // matrix-free build: transposed entries
     WS_NT_TMP,                                                    // assembly: sort buffer of long transposed lists
+    WS_RTQ_PMASK, WS_RTQ_POFF, WS_RTQ_PCNT, WS_RTQ_PVAL,          // zero-free K-blocked copy
     WS_COUNT
 };
 

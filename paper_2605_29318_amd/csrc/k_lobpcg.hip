@@ -1770,9 +1770,14 @@ constexpr int kChebDefault = 12;               // degree when the caller passes 
 constexpr double kChebRatio = 1000.0;          // b / a when the caller passes 0
 constexpr int kChebT8Sub = 1;                  // launch shape of the fused step (fewer registers than the
                                                // H-only product's default with the step's operands live)
-// launch shape of the matrix-core Chebyshev step: the super-block pipelined kernel, eight waves per
-// workgroup at m = 32, four at m = 64
-inline int cheb_tq_sub(int m) { return m == 32 ? 5 : 6; }
+// launch shape of the matrix-core Chebyshev step, the super-block pipelined kernel; the product alone
+// at 10^6 particles, m = 32 / 64: full K-blocks with eight / four waves per workgroup 0.561 / 0.796 ms,
+// zero-free K-blocks with four / two waves 0.514 / 0.791 ms
+inline int cheb_tq_sub(int m, bool packed) {
+    return packed ? (m == 32 ? rt::kTqPacked + 1 : rt::kTqPacked + 4) : (m == 32 ? 5 : 6);
+}
+// the matrix-core steps read the zero-free copy unless precond_values asks for the full K-blocks
+constexpr bool kChebPackedDefault = true;
 
 // Gershgorin bound of D^-1/2 H D^-1/2 per row: sum_j |H_ij| / sqrt(H_ii H_jj), one wavefront per row
 __global__ void gersh_row_kernel(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *H,
@@ -2090,6 +2095,7 @@ struct Solver {
     rt::RT16View rt16;                             // sixteen-row H-only copy (MFMA form), preferred
     rt::RTQView rtq;                               // K-blocked binary16 copy: matrix-core Chebyshev steps
     bool q_on = false;                             // the FP32 preconditioner runs the matrix-core steps
+    int tq_sub = 0;                                // their launch shape (the packed ones read the zero-free copy)
     float *wpart = nullptr, *cmax = nullptr;       // [chunks][m], [n_obj][m] column maxima of D^-1 R
     bool jacobi = false;
     int cheb = 0;                                  // Chebyshev-Jacobi degree (0: plain Jacobi or none)
@@ -2312,7 +2318,7 @@ int stage_precond(Solver &s, T *S) {
             cs.dz_out = q16[step & 1];
             // W gathers two steps' iterates at every even step (and the last one's when it is odd)
             cs.wmode = (step & 1) == 0 ? 2 : (step == s.cheb - 1 ? 1 : 0);
-            const int rc = rt::cheb_step_tq(s.ctx, s.st, s.rtq, cheb_tq_sub(s.m), s.m, q16[(step - 1) & 1], s.row_obj,
+            const int rc = rt::cheb_step_tq(s.ctx, s.st, s.rtq, s.tq_sub, s.m, q16[(step - 1) & 1], s.row_obj,
                                             s.status, cs);
             if (rc) return rc;
         }
@@ -2725,8 +2731,9 @@ int solve(ff_ctx *ctx, int n_obj, const int64_t *obj_off, const int64_t *row_ptr
                "Chebyshev interval ratio %g must be 0 (default %g) or in (1, 1e6]", p->precond_ratio, kChebRatio);
     FF_REQUIRE(ctx, p->eig_tol >= 0.0 && p->eig_tol == p->eig_tol, "eig_tol must be >= 0");
     FF_REQUIRE(ctx, p->angle_tol >= 0.0 && p->angle_tol == p->angle_tol, "angle_tol must be >= 0");
-    FF_REQUIRE(ctx, p->precond_values >= 0 && p->precond_values <= 3,
-               "precond_values %d must be 0 (default), 1 (FP32), 2 (binary16 H) or 3 (binary16 H and iterate)",
+    FF_REQUIRE(ctx, p->precond_values >= 0 && p->precond_values <= 4,
+               "precond_values %d must be 0 (default), 1 (FP32), 2 (binary16 H), 3 (binary16 H and iterate) or 4 "
+               "(3 without the K-blocks' zeros)",
                p->precond_values);
     int m = p->block > 0 ? p->block : ((p->k + 7) / 8) * 8;
     FF_REQUIRE(ctx, m >= p->k && m % 8 == 0 && m >= 8 && m <= 64, "block %d: needs k <= m <= 64, m multiple of 8", m);
@@ -2795,10 +2802,15 @@ int solve(ff_ctx *ctx, int n_obj, const int64_t *obj_off, const int64_t *row_ptr
             // H in binary16 for these products: 1.75 value slots per nonzero at 2 bytes instead of 4;
             // with the iterate in binary16 too (block widths 32 and 64) the products run on the matrix
             // cores, otherwise on the FP32 VALU
-            const bool q = p->precond_values == 3 || (p->precond_values == 0 && rt::tq_ok(s.m));
+            const bool q = p->precond_values == 3 || p->precond_values == 4 ||
+                           (p->precond_values == 0 && rt::tq_ok(s.m));
             FF_REQUIRE(ctx, !q || rt::tq_ok(s.m), "binary16 iterate needs block width 32 or 64 (m = %d)", s.m);
             if (!rc && q) {
                 rc = rt::build_tq(ctx, s.st, s.rt8, &s.rtq);
+                // the K-blocks without their zeros (44% of the full blocks' values at 10^6 particles)
+                const bool packed = p->precond_values == 4 || (p->precond_values == 0 && kChebPackedDefault);
+                if (!rc && packed) rc = rt::build_tq_pack_ws(ctx, s.st, &s.rtq);
+                s.tq_sub = cheb_tq_sub(s.m, packed);
                 // the power steps of the interval estimate (eight columns) read the binary16 copy too
                 if (!rc) rc = rt::build_t8_half(ctx, s.st, &s.rt8);
                 s.wpart = (float *)ws_get(ctx, WS_CHEBQ, ((size_t)s.ng + s.n_obj) * s.m * sizeof(float));

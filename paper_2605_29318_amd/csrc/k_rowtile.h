@@ -85,6 +85,8 @@ int cheb_step_t8(ff_ctx *ctx, hipStream_t st, const RT8View &v, int sub, int m, 
 // entries, vq[kblock][8 rows][16 entries] (zero past a tile's last entry), and
 // the iterate DZ in binary16, [rows][m]; products accumulate in FP32 on
 // v_mfma_f32_16x16x16_f16.
+// K-blocks per group of the zero-free copy (the K-blocks one super-block of the kernel multiplies)
+constexpr int kTqPackGroup = 4;
 struct RTQView {
     int64_t n = 0, ntiles = 0, nkb = 0;
     const int64_t *tptr = nullptr;   // [ntiles + 1] union entries of the eight-row copy
@@ -92,6 +94,15 @@ struct RTQView {
     const int64_t *kptr = nullptr;   // [ntiles + 1] first K-block of each tile
     const uint16_t *vq = nullptr;    // [nkb][8][16] binary16 bits
     float hscale = 1.f;              // 2^-e
+    // the same K-blocks without their zeros (build_tq_pack): per K-block a 128-bit mask of the
+    // values present, bit 16 r + e for row r and entry e (two words: rows 0-3, rows 4-7), and the
+    // present values in that bit order, each tile's from pvoff[t] on, each group of kTqPackGroup
+    // consecutive K-blocks of a tile starting at a multiple of eight halves (zeros between); the
+    // kernels expand them into the K-block's fragments in registers (the same operands, so the
+    // same sums bit for bit)
+    const uint64_t *pmask = nullptr; // [nkb][2]
+    const int64_t *pvoff = nullptr;  // [ntiles + 1], multiples of 8
+    const uint16_t *pval = nullptr;  // [pvoff[ntiles] + 8] binary16 bits (8 halves of padding)
 };
 // builds the K-blocked copy from the FP32 values of a built eight-row copy into workspace slots;
 // build_tq_ptr (tile K-block pointers kptr[ntiles + 1], cnt[ntiles + 1] scratch, their total nkb)
@@ -100,6 +111,13 @@ int build_tq(ff_ctx *ctx, hipStream_t st, const RT8View &v8, RTQView *out);
 int build_tq_ptr(ff_ctx *ctx, hipStream_t st, const RT8View &v8, int64_t *kptr, int64_t *cnt, int64_t *nkb);
 int build_tq_fill(ff_ctx *ctx, hipStream_t st, const RT8View &v8, const int64_t *kptr, int64_t nkb, uint16_t *vq,
                   RTQView *out);
+// the zero-free copy of a built K-blocked copy: pmask [nkb][2] and pvoff [ntiles + 1] from the
+// caller (cnt [ntiles + 1] scratch), pval allocated by alloc(bytes) once the count is known
+// (returns nullptr on failure)
+int build_tq_pack(ff_ctx *ctx, hipStream_t st, RTQView *v, uint64_t *pmask, int64_t *pvoff, int64_t *cnt,
+                  void *(*alloc)(void *, size_t), void *alloc_arg);
+// the same into workspace slots
+int build_tq_pack_ws(ff_ctx *ctx, hipStream_t st, RTQView *v);
 // block widths the matrix-core kernels take: m in {32, 64}
 bool tq_ok(int m);
 // one Chebyshev step, binary16 iterate: R -= D^-1 H DZ, DZ' = f1 DZ + f2 R (stored in binary16),
@@ -115,8 +133,10 @@ struct ChebStepQ {
     int64_t ldw = 0;
     int wmode = 1;
 };
-// sub selects a launch shape (waves per block, K-blocks in flight), 0 .. kTqSubs - 1
-constexpr int kTqSubs = 8;
+// sub selects a launch shape (waves per block, K-blocks in flight), 0 .. kTqSubs - 1; shapes
+// kTqPacked and above read the zero-free copy (pmask, pval)
+constexpr int kTqSubs = 13;
+constexpr int kTqPacked = 8;
 int cheb_step_tq(ff_ctx *ctx, hipStream_t st, const RTQView &v, int sub, int m, const uint16_t *DZ,
                  const int *row_obj, const int *status, const ChebStepQ &cs);
 // HY = H Y (Y binary16 [rows][m], HY FP32 with leading dimension ldo)

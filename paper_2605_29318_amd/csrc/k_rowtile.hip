@@ -13,7 +13,7 @@ struct ff_rowtiles {
     ff::rt::RT8View v8;
     ff::rt::RT16View v16;
     ff::rt::RTQView vq;                            // K-blocked binary16 copy (precision 6)
-    void *mem[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    void *mem[9] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
 };
 
 namespace ff {
@@ -1358,6 +1358,21 @@ int build_t8_half(ff_ctx *ctx, hipStream_t st, RT8View *v, uint16_t *out16) {
 // ends up with rows l % 16 (< 8 kept) at columns 16 cb + 4 (l / 16) + 0..3.
 typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
 
+// The A fragment of v_mfma_f32_16x16x16_f16 for lane (m, g) = (lane % 16, lane / 16) of a 16 x 16
+// tile held row-major in LDS (row k at sy + k * stride, 16 binary16 columns from column c0): the
+// four values of column c0 + m in rows 4 g .. 4 g + 3, by one transposing LDS read
+// (ds_read_b64_tr_b16). In each group of 16 lanes, lane j supplies the 8 bytes of row
+// 4 g + j / 4, columns c0 + 4 (j % 4) .. + 3, and lane m receives element m of each of the four
+// rows the group read (so the source must be 8-byte aligned).
+__device__ inline f16x4 lds_a_frag(const unsigned char *sy, int stride, int c0, int lane) {
+    const int g = lane >> 4, j = lane & 15;
+    const unsigned char *src = sy + (4 * g + (j >> 2)) * stride + (c0 + 4 * (j & 3)) * 2;
+    typedef short i16x4 __attribute__((ext_vector_type(4)));
+    typedef __attribute__((address_space(3))) i16x4 *LdsI16x4;
+    const i16x4 v = __builtin_amdgcn_ds_read_tr16_b64_v4i16((LdsI16x4)(__attribute__((address_space(3))) void *)(void *)src);
+    return __builtin_bit_cast(f16x4, v);
+}
+
 __global__ void tq_count_kernel(int64_t ntiles, const int64_t *tptr, int64_t *cnt) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t < ntiles) cnt[t] = (tptr[t + 1] - tptr[t] + 15) / 16;
@@ -1431,6 +1446,103 @@ int build_tq(ff_ctx *ctx, hipStream_t st, const RT8View &v8, RTQView *out) {
     uint16_t *vq = (uint16_t *)ws_get(ctx, WS_RTQ_VAL, (size_t)std::max<int64_t>(nkb, 1) * 128 * 2);
     if (!vq) return FF_ERR_OOM;
     return build_tq_fill(ctx, st, v8, kptr, nkb, vq, out);
+}
+
+// halves each tile's zero-free values take: the values present in each group of kTqPackGroup
+// consecutive K-blocks (a binary16 value counts when it is not +-0), each group rounded up to a
+// multiple of eight halves so that every group starts 16-byte aligned
+__global__ void __launch_bounds__(64) tqp_count_kernel(int64_t ntiles, const int64_t *kptr, const uint16_t *vq,
+                                                       int64_t *cnt) {
+    const int64_t t = blockIdx.x;
+    if (t >= ntiles) return;
+    const int64_t k0 = kptr[t], nk = kptr[t + 1] - k0;
+    int64_t total = 0;
+    for (int64_t g = 0; g < nk; g += kTqPackGroup) {
+        int c = 0;
+        for (int64_t kb = g; kb < nk && kb < g + kTqPackGroup; ++kb)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) c += (vq[(k0 + kb) * 128 + threadIdx.x + 64 * h] & 0x7fffu) != 0;
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) c += __shfl_xor(c, d, 64);
+        total += (c + 7) & ~7;
+    }
+    if (threadIdx.x == 0) cnt[t] = total;
+}
+
+// one 64-thread block per tile: thread s takes values s (rows 0-3) and s + 64 (rows 4-7) of each
+// K-block in [row][entry] order; the ballots are the K-block's mask words, the prefix counts
+// place the present values (zeros pad each group of K-blocks to a multiple of eight halves)
+__global__ void __launch_bounds__(64) tqp_fill_kernel(int64_t ntiles, const int64_t *kptr, const uint16_t *vq,
+                                                      const int64_t *pvoff, uint64_t *pmask, uint16_t *pval) {
+    const int64_t t = blockIdx.x;
+    if (t >= ntiles) return;
+    const int lane = threadIdx.x;
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    const int64_t k0 = kptr[t], nk = kptr[t + 1] - k0;
+    int64_t run = pvoff[t];
+    for (int64_t kb = 0; kb < nk; ++kb) {
+        if (kb % kTqPackGroup == 0) run = (run + 7) & ~(int64_t)7;      // each group starts 16-byte aligned
+        const uint16_t a = vq[(k0 + kb) * 128 + lane], b = vq[(k0 + kb) * 128 + 64 + lane];
+        const bool pa = (a & 0x7fffu) != 0, pb = (b & 0x7fffu) != 0;
+        const uint64_t lo = __ballot(pa), hi = __ballot(pb);
+        if (pa) pval[run + __popcll(lo & below)] = a;
+        if (pb) pval[run + __popcll(lo) + __popcll(hi & below)] = b;
+        if (lane == 0) {
+            pmask[2 * (k0 + kb)] = lo;
+            pmask[2 * (k0 + kb) + 1] = hi;
+        }
+        run += __popcll(lo) + __popcll(hi);
+    }
+}
+
+__global__ void fill_u16_kernel(uint16_t *a, int64_t count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) a[i] = 0;
+}
+
+int build_tq_pack(ff_ctx *ctx, hipStream_t st, RTQView *v, uint64_t *pmask, int64_t *pvoff, int64_t *cnt,
+                  void *(*alloc)(void *, size_t), void *alloc_arg) {
+    FF_REQUIRE(ctx, v && v->vq && v->kptr && v->ntiles > 0 && pmask && pvoff && cnt, "zero-free copy: bad arguments");
+    hipLaunchKernelGGL(tqp_count_kernel, dim3(v->ntiles), dim3(64), 0, st, v->ntiles, v->kptr, v->vq, cnt);
+    FF_CHECK_LAUNCH(ctx);
+    int rc = scan_exclusive_i64(ctx, cnt, pvoff, v->ntiles);
+    if (rc) return rc;
+    int64_t *h = (int64_t *)pinned_get(ctx, 64);
+    if (!h) return FF_ERR_OOM;
+    FF_HIP(ctx, hipMemcpyAsync(h, pvoff + v->ntiles, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    FF_HIP(ctx, hipStreamSynchronize(st));
+    const int64_t total = h[0];
+    // eight halves of padding: a lane's window of four values is read as three aligned dwords
+    uint16_t *pval = (uint16_t *)alloc(alloc_arg, (size_t)(total + 8) * sizeof(uint16_t));
+    if (!pval) return set_error(ctx, FF_ERR_OOM, "zero-free copy: allocation of %lld values failed", (long long)total);
+    hipLaunchKernelGGL(fill_u16_kernel, dim3(grid_for(total + 8, 256)), dim3(256), 0, st, pval, total + 8);
+    hipLaunchKernelGGL(tqp_fill_kernel, dim3(v->ntiles), dim3(64), 0, st, v->ntiles, v->kptr, v->vq,
+                       (const int64_t *)pvoff, pmask, pval);
+    FF_CHECK_LAUNCH(ctx);
+    v->pmask = pmask;
+    v->pvoff = pvoff;
+    v->pval = pval;
+    return FF_OK;
+}
+
+namespace {
+struct WsAlloc {
+    ff_ctx *ctx;
+    int slot;
+};
+void *ws_alloc(void *arg, size_t bytes) {
+    WsAlloc *a = (WsAlloc *)arg;
+    return ws_get(a->ctx, a->slot, bytes);
+}
+}  // namespace
+
+int build_tq_pack_ws(ff_ctx *ctx, hipStream_t st, RTQView *v) {
+    uint64_t *pmask = (uint64_t *)ws_get(ctx, WS_RTQ_PMASK, (size_t)std::max<int64_t>(v->nkb, 1) * 16);
+    int64_t *pvoff = (int64_t *)ws_get(ctx, WS_RTQ_POFF, (size_t)(v->ntiles + 1) * sizeof(int64_t));
+    int64_t *cnt = (int64_t *)ws_get(ctx, WS_RTQ_PCNT, (size_t)(v->ntiles + 1) * sizeof(int64_t));
+    if (!pmask || !pvoff || !cnt) return FF_ERR_OOM;
+    WsAlloc a{ctx, WS_RTQ_PVAL};
+    return build_tq_pack(ctx, st, v, pmask, pvoff, cnt, ws_alloc, &a);
 }
 
 bool tq_ok(int m) { return m == 32 || m == 64; }
@@ -1514,10 +1626,7 @@ spmm_tq_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int32_t
                 const f16x4 bv = kb < nk ? b[d] : f16x4{0, 0, 0, 0};
 #pragma unroll
                 for (int cb = 0; cb < kMB; ++cb) {
-                    f16x4 a;
-#pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        a[q] = *(const _Float16 *)(sy + (4 * quad + q) * kStride + (16 * cb + rr) * 2);
+                    const f16x4 a = lds_a_frag(sy, kStride, 16 * cb, lane);
                     acc[cb] = __builtin_amdgcn_mfma_f32_16x16x16f16(a, bv, acc[cb], 0, 0, 0);
                 }
             }
@@ -1567,19 +1676,40 @@ spmm_tq_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int32_t
 // gather a row take its column from that lane by a cross-lane read; the gathers and value loads of
 // super-block s + 1 are issued before super-block s is multiplied. The four K-blocks of a super-block
 // use separate LDS buffers.
-template <int kMB, bool kEpi, int kWaves, int kOcc>
+//
+// With kPacked the values come from the zero-free copy. A super-block's four pairs of mask words
+// are loaded two super-blocks ahead (so waiting for them does not wait for the gathers in flight)
+// and read into scalar registers; their counts give the super-block's span of values, which the
+// wave reads at once, 16 bytes a lane from its 16-byte aligned start, and stages in LDS beside the
+// gathered rows. Lane j then rebuilds entries j and 64 + j of each K-block in LDS (its mask bit
+// selects the value at the count of set bits below it, or zero) and each lane reads its B fragment
+// from there, so the B operand, and every sum, is the same as from the full K-block.
+struct PackedQ {
+    const uint64_t *pmask = nullptr;
+    const int64_t *pvoff = nullptr;
+    const uint16_t *pval = nullptr;
+};
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef const __attribute__((address_space(4))) int64_t *ConstI64;
+// the super-block's values staged in LDS: at most 4 * 128 halves
+constexpr int kPkStage = 4 * 128 * 2;
+
+template <int kMB, bool kEpi, int kWaves, int kOcc, bool kPacked = false>
 __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(kOcc, 8)))
 spmm_tq_sb_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int32_t *tcol, const int64_t *kptr,
                   const _Float16 *vq, float vscale, const _Float16 *Y, float *HY, int64_t ldo, const int *row_obj,
-                  const int *obj_status, ChebStepQ cs) {
+                  const int *obj_status, ChebStepQ cs, PackedQ pq) {
     constexpr int m = 16 * kMB;
     constexpr int kPieces = m / 8;                 // 16-byte pieces of a binary16 row of the block
     constexpr int kRowsPer = 64 / kPieces;         // rows one wave-wide load covers (16 or 8)
     constexpr int kLoads = 16 / kRowsPer;          // loads per K-block (1 or 2)
     constexpr int kStride = 2 * m + 16;            // LDS row stride in bytes
     constexpr int kQ = 4;                          // K-blocks per super-block
+    static_assert(kQ == kTqPackGroup, "the zero-free copy aligns groups of four K-blocks");
     __shared__ __align__(16) unsigned char ys[kWaves][kQ][16 * kStride];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __shared__ __align__(16) unsigned char pvs[kWaves][kPacked ? kPkStage : 16];
+    __shared__ __align__(16) unsigned char pds[kWaves][kPacked ? kQ : 1][kPacked ? 256 : 16];
+    const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t t = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kWaves + wv;
     if (t >= ntiles) return;
     const int64_t r0 = t * kTile8;
@@ -1601,9 +1731,23 @@ spmm_tq_sb_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int3
         return tcol[e < e1 ? e : e1 - 1];
     };
     const _Float16 *vb = vq + k0 * 128 + (rr & 7) * 16 + 4 * quad;   // this lane's values in the tile's K-blocks
+    // packed copy: the start of the next super-block's values (uniform)
+    int64_t pk_run = kPacked ? ((ConstI64)pq.pvoff)[t] : 0;
+    struct PkSB {
+        u32x4 pv;              // this lane's 16 bytes of the super-block's values
+        uint64_t lo[kQ], hi[kQ];
+        uint32_t mk;           // lanes 0-15: the mask dwords of the next super-block this buffer takes
+    };
+    // the four K-blocks' mask words of super-block sb, one dword a lane in lanes 0-15 (K-blocks past
+    // the tile's end read its last one; they are not used)
+    auto load_masks = [&](int sb) -> uint32_t {
+        const int kb = kQ * sb + ((lane >> 2) & 3);
+        const uint32_t *mp = (const uint32_t *)(pq.pmask + 2 * (k0 + (kb < nk ? kb : nk - 1)));
+        return lane < 16 ? mp[lane & 3] : 0u;
+    };
     // the gathers of a super-block, then its value loads (consumed in that order); whole: all four
     // K-blocks lie inside the tile
-    auto issue = [&](int s, int cols, f32x4 (&y)[kQ][kLoads], f16x4 (&b)[kQ], bool whole) {
+    auto issue = [&](int s, int cols, f32x4 (&y)[kQ][kLoads], f16x4 (&b)[kQ], PkSB &pk, bool whole) {
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int q = 0; q < kQ; ++q)
@@ -1613,10 +1757,31 @@ spmm_tq_sb_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int3
                 y[q][i] = *(const f32x4 *)(Y + (size_t)(j * (uint32_t)m) + piece * 8);
             }
         __builtin_amdgcn_sched_barrier(0);
+        if constexpr (!kPacked) {
 #pragma unroll
-        for (int q = 0; q < kQ; ++q) {
-            const int kb = whole || kQ * s + q < nk ? kQ * s + q : nk - 1;
-            b[q] = __builtin_nontemporal_load((const f16x4 *)(vb + kb * 128));
+            for (int q = 0; q < kQ; ++q) {
+                const int kb = whole || kQ * s + q < nk ? kQ * s + q : nk - 1;
+                b[q] = __builtin_nontemporal_load((const f16x4 *)(vb + kb * 128));
+            }
+        } else {
+            // this super-block's masks were loaded two super-blocks ago: the wait for them does not
+            // wait for the gathers in flight
+            int span = 0;
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) {
+                const bool in = whole || kQ * s + q < nk;
+                const uint64_t lo = (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)pk.mk, 4 * q) |
+                                    ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)pk.mk, 4 * q + 1) << 32);
+                const uint64_t hi = (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)pk.mk, 4 * q + 2) |
+                                    ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)pk.mk, 4 * q + 3) << 32);
+                pk.lo[q] = in ? lo : 0ull;
+                pk.hi[q] = in ? hi : 0ull;
+                span += __popcll(pk.lo[q]) + __popcll(pk.hi[q]);
+            }
+            pk.pv = 8 * lane < span ? __builtin_nontemporal_load((const u32x4 *)(pq.pval + pk_run) + lane)
+                                    : u32x4{0u, 0u, 0u, 0u};
+            pk_run += (span + 7) & ~7;
+            pk.mk = load_masks(s + 2);
         }
         __builtin_amdgcn_sched_barrier(0);
     };
@@ -1624,51 +1789,77 @@ spmm_tq_sb_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int3
 #pragma unroll
     for (int cb = 0; cb < kMB; ++cb) acc[cb] = f32x4{0.f, 0.f, 0.f, 0.f};
     // multiplies super-block s; full: all four of its K-blocks lie inside the tile
-    auto consume = [&](int s, const f32x4 (&y)[kQ][kLoads], const f16x4 (&b)[kQ], bool full) {
+    auto consume = [&](int s, const f32x4 (&y)[kQ][kLoads], const f16x4 (&b)[kQ], const PkSB &pk, bool full) {
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int q = 0; q < kQ; ++q)
 #pragma unroll
             for (int i = 0; i < kLoads; ++i)
                 *(f32x4 *)(&ys[wv][q][0] + (slot + kRowsPer * i) * kStride + piece * 16) = y[q][i];
+        if constexpr (kPacked) *(u32x4 *)(&pvs[wv][0] + 16 * lane) = pk.pv;
         __builtin_amdgcn_wave_barrier();
+        f16x4 bp[kQ];
+        if constexpr (kPacked) {
+            // expand the four K-blocks into LDS, lane j writing entries j (rows 0-3) and 64 + j
+            // (rows 4-7) of each: present when its mask bit is set, then the value at the count of
+            // present entries before it
+            const uint16_t *ps = (const uint16_t *)&pvs[wv][0];
+            uint16_t *pd = (uint16_t *)&pds[wv][0][0];
+            int base = 0;                                              // halves before K-block q
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) {
+                const uint64_t lo = pk.lo[q], hi = pk.hi[q];
+                const int nlo = __popcll(lo);
+                const int ilo = __builtin_amdgcn_mbcnt_hi((uint32_t)(lo >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)lo, 0));
+                const int ihi = __builtin_amdgcn_mbcnt_hi((uint32_t)(hi >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)hi, 0));
+                const uint16_t v0 = ps[base + ilo], v1 = ps[base + nlo + ihi];
+                pd[q * 128 + lane] = __builtin_amdgcn_inverse_ballot_w64(lo) ? v0 : (uint16_t)0;
+                pd[q * 128 + 64 + lane] = __builtin_amdgcn_inverse_ballot_w64(hi) ? v1 : (uint16_t)0;
+                base += nlo + __popcll(hi);
+            }
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) bp[q] = *(const f16x4 *)(pd + q * 128 + (rr & 7) * 16 + 4 * quad);
+        }
 #pragma unroll
         for (int q = 0; q < kQ; ++q) {
             if (!full && kQ * s + q >= nk) break;
             const unsigned char *sy = &ys[wv][q][0];
 #pragma unroll
             for (int cb = 0; cb < kMB; ++cb) {
-                f16x4 a;
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    a[u] = *(const _Float16 *)(sy + (4 * quad + u) * kStride + (16 * cb + rr) * 2);
-                acc[cb] = __builtin_amdgcn_mfma_f32_16x16x16f16(a, b[q], acc[cb], 0, 0, 0);
+                const f16x4 a = lds_a_frag(sy, kStride, 16 * cb, lane);
+                acc[cb] = __builtin_amdgcn_mfma_f32_16x16x16f16(a, kPacked ? bp[q] : b[q], acc[cb], 0, 0, 0);
             }
         }
     };
     if (nk > 0) {
         f32x4 ya[kQ][kLoads], yb[kQ][kLoads];
         f16x4 ba[kQ], bb[kQ];
+        PkSB pa, pb;
+        if constexpr (kPacked) {
+            pa.mk = load_masks(0);
+            pb.mk = load_masks(1);
+        }
         const int c0 = cols_of(0);
         int c1 = cols_of(ns > 1 ? 1 : 0);
-        issue(0, c0, ya, ba, ns > 1);
+        issue(0, c0, ya, ba, pa, ns > 1);
         int s = 0;
         // steady state: super-blocks s and s + 1 are whole, s + 2 exists
         for (; s + 2 < ns; s += 2) {
             const int c2 = cols_of(s + 2);
-            issue(s + 1, c1, yb, bb, true);
-            consume(s, ya, ba, true);
+            issue(s + 1, c1, yb, bb, pb, true);
+            consume(s, ya, ba, pa, true);
             c1 = cols_of(s + 3 < ns ? s + 3 : ns - 1);
-            issue(s + 2, c2, ya, ba, false);
-            consume(s + 1, yb, bb, true);
+            issue(s + 2, c2, ya, ba, pa, false);
+            consume(s + 1, yb, bb, pb, true);
         }
         // the last one or two super-blocks
         if (s + 1 < ns) {
-            issue(s + 1, c1, yb, bb, false);
-            consume(s, ya, ba, true);
-            consume(s + 1, yb, bb, false);
+            issue(s + 1, c1, yb, bb, pb, false);
+            consume(s, ya, ba, pa, true);
+            consume(s + 1, yb, bb, pb, false);
         } else {
-            consume(s, ya, ba, false);
+            consume(s, ya, ba, pa, false);
         }
     }
     if (!mine) return;
@@ -1713,6 +1904,11 @@ static int launch_tq(ff_ctx *ctx, hipStream_t st, const RTQView &v, int sub, int
                      int64_t ldo, const int *row_obj, const int *status, const ChebStepQ &cs) {
     FF_REQUIRE(ctx, v.vq != nullptr && tq_ok(m), "matrix-core Chebyshev step: no K-blocked copy or m = %d", m);
     FF_REQUIRE(ctx, sub >= 0 && sub < kTqSubs, "launch shape %d out of range", sub);
+    FF_REQUIRE(ctx, sub < kTqPacked || (v.pmask && v.pval && v.pvoff), "launch shape %d needs the zero-free copy", sub);
+    PackedQ pq;
+    pq.pmask = v.pmask;
+    pq.pvoff = v.pvoff;
+    pq.pval = v.pval;
     FF_REQUIRE(ctx, v.n * (int64_t)m < ((int64_t)1 << 32), "block of %lld rows x %d too large for 32-bit offsets",
                (long long)v.n, m);
     const _Float16 *vq = (const _Float16 *)v.vq, *y = (const _Float16 *)Y;
@@ -1726,7 +1922,10 @@ static int launch_tq(ff_ctx *ctx, hipStream_t st, const RTQView &v, int sub, int
                        v.ntiles, v.tptr, v.tcol, v.kptr, vq, v.hscale, y, HY, ldo, row_obj, status, cs)
 #define FF_TQS(MB, W, O)                                                                                       \
     hipLaunchKernelGGL((spmm_tq_sb_kernel<MB, kEpi, W, O>), dim3(grid_for(v.ntiles, W)), dim3(64 * W), 0, st, v.n, \
-                       v.ntiles, v.tptr, v.tcol, v.kptr, vq, v.hscale, y, HY, ldo, row_obj, status, cs)
+                       v.ntiles, v.tptr, v.tcol, v.kptr, vq, v.hscale, y, HY, ldo, row_obj, status, cs, pq)
+#define FF_TQP(MB, W, O)                                                                                       \
+    hipLaunchKernelGGL((spmm_tq_sb_kernel<MB, kEpi, W, O, true>), dim3(grid_for(v.ntiles, W)), dim3(64 * W), 0, st,  \
+                       v.n, v.ntiles, v.tptr, v.tcol, v.kptr, vq, v.hscale, y, HY, ldo, row_obj, status, cs, pq)
 #define FF_TQ_SHAPES(MB)                   \
     switch (sub) {                         \
         case 1: FF_TQ(MB, 8, 4, 3); break; \
@@ -1736,6 +1935,11 @@ static int launch_tq(ff_ctx *ctx, hipStream_t st, const RTQView &v, int sub, int
         case 5: FF_TQS(MB, 8, 2); break;   \
         case 6: FF_TQS(MB, 4, 2); break;   \
         case 7: FF_TQS(MB, 8, MB == 2 ? 5 : 3); break; \
+        case 8: FF_TQP(MB, 8, 2); break;   \
+        case 9: FF_TQP(MB, 4, 2); break;   \
+        case 10: FF_TQP(MB, 8, MB == 2 ? 5 : 3); break; \
+        case 11: FF_TQP(MB, 4, 4); break;  \
+        case 12: FF_TQP(MB, 2, 2); break;  \
         default: FF_TQ(MB, 8, 4, 2); break; \
     }
     if (m == 32) {
@@ -1744,6 +1948,7 @@ static int launch_tq(ff_ctx *ctx, hipStream_t st, const RTQView &v, int sub, int
         FF_TQ_SHAPES(4)
     }
 #undef FF_TQ_SHAPES
+#undef FF_TQP
 #undef FF_TQS
 #undef FF_TQ
     FF_CHECK_LAUNCH(ctx);
@@ -2406,6 +2611,33 @@ int rowtiles_build(ff_ctx *ctx, int64_t n, const int64_t *row_ptr, const int32_t
             }
             h->mem[5] = vq;
             if (!rc8) rc8 = rt::build_tq_fill(ctx, st, h->v8, kp, nkb, vq, &h->vq);
+            // and without its zeros (the packed launch shapes)
+            uint64_t *pm = nullptr;
+            int64_t *po = nullptr, *pc = nullptr;
+            if (!rc8 && (hipMalloc((void **)&pm, (size_t)std::max<int64_t>(nkb, 1) * 16) != hipSuccess ||
+                         hipMalloc((void **)&po, (size_t)(nt8 + 1) * sizeof(int64_t)) != hipSuccess ||
+                         hipMalloc((void **)&pc, (size_t)(nt8 + 1) * sizeof(int64_t)) != hipSuccess)) {
+                (void)hipGetLastError();
+                rc8 = set_error(ctx, FF_ERR_OOM, "row-tile allocation failed");
+            }
+            h->mem[6] = pm;
+            h->mem[7] = po;
+            struct Slot {
+                static void *alloc(void *arg, size_t bytes) {
+                    void *p = nullptr;
+                    if (hipMalloc(&p, bytes) != hipSuccess) {
+                        (void)hipGetLastError();
+                        return nullptr;
+                    }
+                    *(void **)arg = p;
+                    return p;
+                }
+            };
+            if (!rc8) rc8 = rt::build_tq_pack(ctx, st, &h->vq, pm, po, pc, Slot::alloc, &h->mem[8]);
+            if (pc) {
+                (void)hipStreamSynchronize(st);
+                (void)hipFree(pc);
+            }
         }
         if (!rc8 && hipStreamSynchronize(st) != hipSuccess)
             rc8 = set_error(ctx, FF_ERR_HIP, "row-tile build failed");
