@@ -326,6 +326,49 @@ def matfree_timing(ff, ctx, A, vol, lam, mu, m, reps=10):
                 list_entries=entries, m=m)
 
 
+def _event_ms(fn, reps):
+    import torch
+    for _ in range(2):
+        fn()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def sym_timing(ff, ctx, A, m, reps=10):
+    """FP64 [H, M] Y from the upper triangles (sym_build / spmm_sym) against the FP64 path's own
+    fused products on the benchmark object: the four-row tile copy (the FP64 solve's) and the CSR
+    (the mixed path's certification); HIP events on torch's stream (the context's)."""
+    import torch
+    n = A.n
+    nnz = int(A.col.numel())
+    s = ff.SymCSR(ctx, n, A.row_ptr, A.col, A.H, A.M, precision=0)
+    nu, nl = s.info()
+    Y = torch.randn((n, m), dtype=torch.float64, device="cuda")
+    HY, MY = torch.empty_like(Y), torch.empty_like(Y)
+    ms_sym = _event_ms(lambda: s.spmm(Y, out=(HY, MY)), reps)
+    s.close()
+    names = ff.spmm_variant_names()
+    csr = names.index("chunk64_waves4_batch4_occ8")
+    ms_csr = _event_ms(lambda: ff.spmm_hm(ctx, A.row_ptr, A.col, A.H, A.M, A.hm32, Y, 0, variant=csr,
+                                          out=(HY, MY)), reps)
+    rt = ff.RowTiles(ctx, n, A.row_ptr, A.col, A.H, A.M, precision=0)
+    ms_rt = _event_ms(lambda: rt.spmm(Y, 0, 0, out=(HY, MY)), reps)
+    rt.close()
+    # algorithmic bytes: per upper entry its column and two FP64 values, per lower entry its column
+    # and position (its values are the upper entries' own), two row pointers per row, Y read once,
+    # HY and MY written; the full CSR reads a column and two values per nonzero
+    alg_sym = nu * (4 + 16) + nl * (4 + 4) + 16 * (n + 1) + 8 * n * m * 3
+    alg_full = nnz * (4 + 16) + 8 * (n + 1) + 8 * n * m * 3
+    return dict(m=m, upper_entries=nu, lower_entries=nl, sym_ms=round(ms_sym, 4), csr_ms=round(ms_csr, 4),
+                rowtile4_ms=round(ms_rt, 4), sym_bytes=alg_sym, csr_bytes=alg_full,
+                sym_gbps=round(alg_sym / (ms_sym * 1e-3) / 1e9, 1), csr_gbps=round(alg_full / (ms_csr * 1e-3) / 1e9, 1))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -441,6 +484,8 @@ def main():
         mf = matfree_timing(ff, ctx, last["A"], dev_in[1], dev_in[2], dev_in[3], m=32)
         extra["matfree_hm"] = mf
         log(f"[bench] matrix-free [H, M] Y: {mf}")
+        extra["sym_hm_fp64"] = sym_timing(ff, ctx, last["A"], m=32)
+        log(f"[bench] upper-triangle FP64 [H, M] Y: {extra['sym_hm_fp64']}")
         cs = synth.workload("spheres100k")
         ds = (dev(cs.xyz), dev(cs.vol), dev(cs.lam), dev(cs.mu))
         ref2 = golden_eigs("spheres100k", cs)
@@ -528,10 +573,11 @@ def main():
         "stage_launches": {k: int(v[1]) for k, v in stages.items()},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "spmm_tq_sb_kernel<%d, true> (Chebyshev step on the matrix cores: binary16 H in "
-                               "K-blocks of the eight-row tiles times the binary16 iterate, FP32 accumulation on "
-                               "v_mfma_f32_16x16x16_f16, loads pipelined a super-block of four K-blocks ahead, "
-                               "fused with the step's vector update, m=%d)" % (m // 16, m),
+                     "kernel": "spmm_tq_sb_kernel<%d, true, %d, 2, true> (Chebyshev step on the matrix cores: "
+                               "binary16 H in K-blocks of the eight-row tiles, read without their zeros (a mask per "
+                               "K-block, the values rebuilt in LDS), times the binary16 iterate, FP32 accumulation "
+                               "on v_mfma_f32_16x16x16_f16, loads pipelined a super-block of four K-blocks ahead, "
+                               "fused with the step's vector update, m=%d)" % (m // 16, 4 if m == 32 else 2, m),
                      "bytes_per_launch": cheb_alg, "launch_ms": round(cheb_avg, 4),
                      "share_of_solve": round(cheb_ms / max(stages["total"][0], 1e-9), 3)},
         "spmm_hm": {"achieved": round(spmm_gbps, 1), "unit": "GB/s", "bytes_per_launch": spmm_alg,

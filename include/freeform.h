@@ -365,6 +365,31 @@ int eigenmodes_batched(ff_ctx *ctx, int n_obj, const int64_t *obj_row_off, const
 int eig_bounds(ff_ctx *ctx, int n_obj, int k, double *eig_bound, double *angle_bound);
 
 /*
+ * chebyshev_apply - the preconditioner of eigenmodes (precond = 2) alone, on one object:
+ *   Z = q(D^-1 H) D^-1 R,  D = diag(H),
+ * q the degree-d Chebyshev semi-iteration polynomial for D^-1 H z = D^-1 r on
+ * [b / ratio, b] (d - 1 products with H). The paper's eigensolve (Eq. (15), Supp. B.1
+ * "Eigenanalysis") states no preconditioner; this is the one the library's LOBPCG applies
+ * to its residuals, by the same set-up (tile copies, interval estimate) and the same
+ * launches, including the per-step update of the output block.
+ *   n, row_ptr, col, H, M, hm32: as eigenmodes (device).
+ *   m: block width (multiple of 8, 8 .. 64; values 3 and 4 need 32 or 64).
+ *   degree: d in [2, 16]; ratio: b / a (0 = default 1000, else in (1, 1e6]).
+ *   values: number formats of the products, as precond_values (1 .. 4).
+ *   upper: b; 0 = the library's estimate (min(1.1 x the largest Rayleigh quotient of
+ *     D^-1 H after 30 power steps, the Gershgorin bound)); upper_used (host out, may be
+ *     NULL) receives the b taken.
+ *   R: device FP32 [n][ld_r] input; Z: device FP32 [n][ld_z] output (may not alias R).
+ * With values 3 and 4 the recurrence runs on s_c D^-1 r_c, s_c = 1 / max_i |(D^-1 R)_ic|
+ * per column (the binary16 range), and Z holds s_c q(D^-1 H) D^-1 r_c: each column
+ * scaled, its direction unchanged. Synchronous. Errors: FF_ERR_INVALID_ARG for bad
+ * arguments, FF_ERR_OOM, FF_ERR_HIP.
+ */
+int chebyshev_apply(ff_ctx *ctx, int64_t n, const int64_t *row_ptr, const int32_t *col, const double *H,
+                    const double *M, const float *hm32, int m, int degree, double ratio, int values,
+                    double upper, const float *R, int64_t ld_r, float *Z, int64_t ld_z, double *upper_used);
+
+/*
  * spmm_hm - the fused block product [HY, MY] = [H, M] Y used inside eigenmodes,
  * exposed for measurement and tests. Y, HY, MY are [n][m] row-major with
  * leading dimension ld (>= m). precision 1 reads hm32 and FP32 blocks,
@@ -497,6 +522,34 @@ int rayleigh_ritz_noalloc(ff_ctx *ctx, int w, int m, const double *G, double tau
  *   arguments and unsupported shapes return FF_ERR_INVALID_ARG, a
  *   non-finite H at precision 5 likewise.
  */
+/*
+ * sym_build / spmm_sym - [HY, MY] = [H, M] Y from the upper triangles of H and M. H (Prop. 1)
+ * and M (Eq. (14)) are symmetric, so the values of the diagonal and above are stored once;
+ * each row's strict lower triangle keeps its columns and, per entry (i, j < i), the position
+ * of (j, i) in the upper arrays, from which the value is read. The lower triangle's values of
+ * the CSR are never read: the product is that of the matrix whose lower triangle mirrors its
+ * upper one (the same matrix for the library's assembly, which is bitwise symmetric).
+ *   sym_build: n, row_ptr, col, H (device, FP64 CSR with sorted rows and a symmetric
+ *     pattern), M (device or NULL: H only); precision 0 keeps FP64 values, 1 FP32 values.
+ *     *out receives a handle owning its device memory until sym_destroy (destroy it before
+ *     its context); the CSR may be freed afterwards. FF_ERR_INVALID_ARG if the pattern is
+ *     not symmetric or the upper triangle holds 2^31 entries or more.
+ *   sym_info: entries of the upper triangle (diagonal included) and of the strict lower one.
+ *   spmm_sym: m in {8, 16, 32, 64}; Y [n][ld_y], HY and MY [n][ld_out] device, 16-byte
+ *     aligned, in the handle's precision (FP64 / FP32), leading dimensions multiples of 2
+ *     (FP64) or 4 (FP32); MY NULL forms HY only. Sums accumulate in FP64, one wavefront per
+ *     row: the row's lower entries in ascending column, then its upper ones, each lane group
+ *     taking every (64 / (m / v))-th entry (v = 2 FP64, 4 FP32 values per 16-byte piece), the
+ *     groups' sums added in a fixed order: deterministic.
+ */
+typedef struct ff_sym ff_sym;
+int sym_build(ff_ctx *ctx, int64_t n, const int64_t *row_ptr, const int32_t *col, const double *H,
+              const double *M, int precision, ff_sym **out);
+int sym_info(const ff_sym *s, int64_t *nnz_upper, int64_t *nnz_lower);
+int spmm_sym(ff_ctx *ctx, const ff_sym *s, int m, const void *Y, int64_t ld_y, void *HY, void *MY,
+             int64_t ld_out);
+void sym_destroy(ff_sym *s);
+
 typedef struct ff_rowtiles ff_rowtiles;
 int rowtiles_build(ff_ctx *ctx, int64_t n, const int64_t *row_ptr, const int32_t *col, const double *H,
                    const double *M, int precision, ff_rowtiles **out);
@@ -594,6 +647,16 @@ int mlp_train_step(ff_mlp *mlp, int64_t n, const float *in, const double *T, int
 
 /* lumped_mass - d_i = sum_j M_ij (row sums of the FP64 CSR mass matrix). d [n] device out. */
 int lumped_mass(ff_ctx *ctx, int64_t n, const int64_t *row_ptr, const double *M, double *d);
+
+/*
+ * block_blend - the warm start's blended starting block (the learned start is this
+ * library's addition; the paper starts its eigensolve without one): column by column
+ *   X_c <- X_c / rms(X_c) + w R_c / rms(R_c),   rms(v) = sqrt(sum_i v_i^2 / n),
+ * in FP64, sums in a fixed order (deterministic). X [n][ldx] device in/out, R [n][ldr]
+ * device in (say rand_block's columns), 1 <= m <= 64, w >= 0 finite. A column of zero rms
+ * is taken as having rms 1e-300. Errors: FF_ERR_INVALID_ARG, FF_ERR_OOM.
+ */
+int block_blend(ff_ctx *ctx, int64_t n, int m, double *X, int64_t ldx, const double *R, int64_t ldr, double w);
 
 #ifdef __cplusplus
 }

@@ -142,6 +142,15 @@ def adam_step(p, g, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
     return p - lr * mh / (np.sqrt(vh) + eps), m, v
 
 
+def blend(X, R, w):
+    """The warm start's blended starting block: each column of X divided by its root mean
+    square, plus w times the matching column of R divided by its own."""
+    X = np.asarray(X, dtype=np.float64)
+    R = np.asarray(R, dtype=np.float64)
+    rms = lambda A: np.sqrt(np.mean(A * A, axis=0))
+    return X / rms(X)[None, :] + w * R / rms(R)[None, :]
+
+
 def inputs(xyz, feat, n_freq=0):
     """The network inputs from positions and the 8 raw RKPM features of rkpm_shape:
     position normalised to [-1, 1]^3 about the box centre by the largest half extent,

@@ -482,7 +482,8 @@ def chebyshev_jacobi(H, degree=12, ratio=1000.0, upper=None, mul=None):
     theta, delta = 0.5 * (upper + lo), 0.5 * (upper - lo)
     sigma = theta / delta
 
-    def apply(R):
+    def apply(R, record=None):
+        # record (a list, optional) receives a copy of each of the ``degree`` increments of z
         f = R / d[:, None]                     # right-hand side D^-1 r
         z = np.zeros_like(f)
         res = f.copy()                         # residual f - A z of the Chebyshev iteration
@@ -490,6 +491,8 @@ def chebyshev_jacobi(H, degree=12, ratio=1000.0, upper=None, mul=None):
         rho = 1.0 / sigma
         for j in range(degree):
             z += step
+            if record is not None:
+                record.append(step.copy())
             if j == degree - 1:
                 break
             res -= mul(H, step) / d[:, None]

@@ -28,6 +28,7 @@ SOURCES = [
     ("k_rowtile.hip", False),
     ("k_paper.hip", True),
     ("k_matfree.hip", False),
+    ("k_symspmm.hip", False),
 ]
 
 COMMON = ["-x", "hip", "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",

@@ -40,6 +40,8 @@ enum WsSlot {
     WS_MF,                                                        // matrix-free build: transposed entries
     WS_NT_TMP,                                                    // assembly: sort buffer of long transposed lists
     WS_RTQ_PMASK, WS_RTQ_POFF, WS_RTQ_PCNT, WS_RTQ_PVAL,          // zero-free K-blocked copy
+    WS_BLEND,                                                     // warm start: column blend partials
+    WS_SYM,                                                       // symmetric copy: row counts
     WS_COUNT
 };
 

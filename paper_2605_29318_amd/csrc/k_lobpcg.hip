@@ -2399,7 +2399,7 @@ int init_block(Solver &s, T *S, T *HS, T *MS, double tau) {
 // the largest Rayleigh quotient of D^-1 H after 30 steps of power iteration on 8
 // seeded vectors (in the working precision); b = min(1.1 x quotient, g), a = b / ratio.
 template <typename T>
-int cheb_setup(Solver &s, int degree, double ratio, uint64_t seed) {
+int cheb_setup(Solver &s, int degree, double ratio, uint64_t seed, double upper = 0.0, double *b_used = nullptr) {
     ff_ctx *ctx = s.ctx;
     const int64_t N = s.N;
     const int n_obj = s.n_obj;
@@ -2462,7 +2462,8 @@ int cheb_setup(Solver &s, int degree, double ratio, uint64_t seed) {
         for (int j = 0; j < 8; ++j)
             if (v[9 + j] > 0.0) lam = std::max(lam, v[1 + j] / v[9 + j]);
         const double g = v[0] > 0.0 ? v[0] : 1.0;
-        const double b = (lam > 0.0 && lam == lam) ? std::min(1.1 * lam, g) : g;
+        const double b = upper > 0.0 ? upper : (lam > 0.0 && lam == lam) ? std::min(1.1 * lam, g) : g;
+        if (b_used && o == 0) *b_used = b;
         const double a = b / ratio, theta = 0.5 * (a + b), delta = 0.5 * (b - a), sigma = theta / delta;
         double *c = coef.data() + (size_t)o * kChebCoef;
         c[0] = 1.0 / theta;
@@ -2585,6 +2586,42 @@ int alloc_blocks(Solver &s, int slot_s, int slot_h, int slot_m, T **S, T **HS, T
     *HS = (T *)ws_get(s.ctx, slot_h, bytes);
     *MS = (T *)ws_get(s.ctx, slot_m, bytes);
     if (!*S || !*HS || !*MS) return FF_ERR_OOM;
+    return FF_OK;
+}
+
+// The preconditioner alone (chebyshev_apply): its input R goes into the X-slot images HX with MX = 0
+// and theta = 0, so the residual kernel forms W = D^-1 R and the chunk maxima of |W| exactly as in an
+// iteration; then the same preconditioner stage, and W is the output.
+struct ChebApply {
+    const float *R;
+    int64_t ld_r;
+    float *Z;
+    int64_t ld_z;
+    double upper;
+    double *upper_used;
+};
+
+int cheb_apply_run(Solver &s, const ChebApply &a) {
+    float *S32, *HS32, *MS32;
+    int rc = alloc_blocks<float>(s, WS_S0, WS_HS0, WS_MS0, &S32, &HS32, &MS32);
+    if (rc) return rc;
+    const int64_t ld = 3 * (int64_t)s.m, cnt = s.N * ld;
+    FF_HIP(s.ctx, hipMemsetAsync(S32, 0, (size_t)cnt * sizeof(float), s.st));
+    FF_HIP(s.ctx, hipMemsetAsync(MS32, 0, (size_t)cnt * sizeof(float), s.st));
+    hipLaunchKernelGGL((copy_block_kernel<float, float>), dim3(grid_for(s.N * s.m, 256)), dim3(256), 0, s.st, s.N, s.m,
+                       a.R, a.ld_r, HS32, ld);
+    FF_CHECK_LAUNCH(s.ctx);
+    if ((rc = reset_status(s, 0))) return rc;
+    s.S32 = S32;
+    hipLaunchKernelGGL(resid_kernel<float>, dim3(s.ng), dim3(256), 0, s.st, s.gch, s.status, S32, (const float *)HS32,
+                       (const float *)MS32, ld, s.m, s.theta, (const float *)s.dinv32, (const double *)nullptr, s.rpart,
+                       s.q_on ? s.wpart : (float *)nullptr);
+    FF_CHECK_LAUNCH(s.ctx);
+    if ((rc = stage_precond<float>(s, S32))) return rc;
+    hipLaunchKernelGGL((copy_block_kernel<float, float>), dim3(grid_for(s.N * s.m, 256)), dim3(256), 0, s.st, s.N, s.m,
+                       (const float *)(S32 + s.m), ld, a.Z, a.ld_z);
+    FF_CHECK_LAUNCH(s.ctx);
+    FF_HIP(s.ctx, hipStreamSynchronize(s.st));
     return FF_OK;
 }
 
@@ -2715,10 +2752,13 @@ int lookup_variant(ff_ctx *ctx, int64_t n, int64_t nnz, int m, int precision) {
 
 int solve(ff_ctx *ctx, int n_obj, const int64_t *obj_off, const int64_t *row_ptr, const int32_t *col, const double *H,
           const double *M, const float *hm32, const ff_eig_params *p, const double *X0, double *eigval, double *W,
-          double *resid, ff_eig_info *info) {
+          double *resid, ff_eig_info *info, const ChebApply *apply = nullptr) {
     auto t_start = std::chrono::steady_clock::now();
     timing_reset(ctx);
-    FF_REQUIRE(ctx, p != nullptr && row_ptr && col && H && M && eigval && W && resid, "required pointer is NULL");
+    FF_REQUIRE(ctx, p != nullptr && row_ptr && col && H && M && (apply || (eigval && W && resid)),
+               "required pointer is NULL");
+    FF_REQUIRE(ctx, !apply || (n_obj == 1 && p->precision == 1 && p->precond == 2 && apply->R && apply->Z),
+               "the preconditioner alone runs on one object, mixed precision, Chebyshev-Jacobi");
     FF_REQUIRE(ctx, n_obj >= 1 && obj_off, "bad object list");
     FF_REQUIRE(ctx, p->k >= 1, "k must be >= 1");
     FF_REQUIRE(ctx, p->precision == 0 || p->precision == 1, "precision must be 0 or 1");
@@ -2737,6 +2777,10 @@ int solve(ff_ctx *ctx, int n_obj, const int64_t *obj_off, const int64_t *row_ptr
                p->precond_values);
     int m = p->block > 0 ? p->block : ((p->k + 7) / 8) * 8;
     FF_REQUIRE(ctx, m >= p->k && m % 8 == 0 && m >= 8 && m <= 64, "block %d: needs k <= m <= 64, m multiple of 8", m);
+    FF_REQUIRE(ctx,
+               p->precision != 1 || p->precond != 2 || (p->precond_values != 3 && p->precond_values != 4) ||
+                   rt::tq_ok(m),
+               "precond_values %d (binary16 iterate) needs block width 32 or 64 (m = %d)", p->precond_values, m);
     Solver s;
     s.ctx = ctx;
     FF_HIP(ctx, hipSetDevice(ctx->device));
@@ -2826,10 +2870,12 @@ int solve(ff_ctx *ctx, int n_obj, const int64_t *obj_off, const int64_t *row_ptr
             if (rc) return rc;
         }
         const double ratio = p->precond_ratio > 0.0 ? p->precond_ratio : kChebRatio;
-        rc = p->precision == 1 ? cheb_setup<float>(s, degree, ratio, p->seed)
+        rc = p->precision == 1 ? cheb_setup<float>(s, degree, ratio, p->seed, apply ? apply->upper : 0.0,
+                                                   apply ? apply->upper_used : nullptr)
                                : cheb_setup<double>(s, degree, ratio, p->seed);
         if (rc) return rc;
     }
+    if (apply) return cheb_apply_run(s, *apply);
     const int check_every = p->check_every > 0 ? p->check_every : 10;
     const double tau32 = 1e-5, tau64 = 1e-13;
     constexpr int kStall32 = 200;
@@ -2987,6 +3033,34 @@ extern "C" int eigenmodes_batched(ff_ctx *ctx, int n_obj, const int64_t *obj_row
                                   ff_eig_info *info) {
     if (!ctx) return FF_ERR_INVALID_ARG;
     return solve(ctx, n_obj, obj_row_off, row_ptr, col, H, M, hm32, p, X0, eigval, W, resid, info);
+}
+
+extern "C" int chebyshev_apply(ff_ctx *ctx, int64_t n, const int64_t *row_ptr, const int32_t *col, const double *H,
+                               const double *M, const float *hm32, int m, int degree, double ratio, int values,
+                               double upper, const float *R, int64_t ld_r, float *Z, int64_t ld_z,
+                               double *upper_used) {
+    if (!ctx) return FF_ERR_INVALID_ARG;
+    FF_REQUIRE(ctx, n > 0, "n must be positive");
+    FF_REQUIRE(ctx, R && Z && hm32, "required pointer is NULL");
+    FF_REQUIRE(ctx, m >= 8 && m <= 64 && m % 8 == 0, "block width %d must be a multiple of 8 in [8, 64]", m);
+    FF_REQUIRE(ctx, ld_r >= m && ld_z >= m, "leading dimensions must be >= m");
+    FF_REQUIRE(ctx, degree >= 2 && degree <= 16, "degree %d must be in [2, 16]", degree);
+    FF_REQUIRE(ctx, values >= 1 && values <= 4, "values %d must be 1 .. 4", values);
+    FF_REQUIRE(ctx, upper >= 0.0 && std::isfinite(upper), "upper must be finite and >= 0");
+    ff_eig_params p;
+    memset(&p, 0, sizeof(p));
+    p.k = m;
+    p.block = m;
+    p.precision = 1;
+    p.tol = 1e-6;
+    p.max_iter = 1;
+    p.precond = 2;
+    p.precond_degree = degree;
+    p.precond_ratio = ratio;
+    p.precond_values = values;
+    ChebApply a{R, ld_r, Z, ld_z, upper, upper_used};
+    const int64_t off[2] = {0, n};
+    return solve(ctx, 1, off, row_ptr, col, H, M, hm32, &p, nullptr, nullptr, nullptr, nullptr, nullptr, &a);
 }
 
 extern "C" int eig_bounds(ff_ctx *ctx, int n_obj, int k, double *eig_bound, double *angle_bound) {

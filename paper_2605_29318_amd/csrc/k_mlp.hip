@@ -500,9 +500,75 @@ int forward_impl(ff_mlp *mp, int64_t n, const float *in, double *Ydbl, int64_t l
     return FF_OK;
 }
 
+// Column sums of squares of X and R over a chunk of kBlendRows rows: thread t takes column t % m
+// (of X for t / m even, of R for t / m odd, so 2m <= 256) and every 256 / (2m)-th row of the
+// chunk; partials in a fixed order.
+constexpr int kBlendRows = 1024;
+__global__ void __launch_bounds__(256) blend_ss_kernel(int64_t n, int m, const double *X, int64_t ldx,
+                                                       const double *R, int64_t ldr, double *part) {
+    __shared__ double red[256];
+    const int t = threadIdx.x, per = 256 / (2 * m);
+    const int c = t % m, which = (t / m) & 1, lane_row = t / (2 * m);
+    const int64_t r0 = (int64_t)blockIdx.x * kBlendRows;
+    const int64_t r1 = r0 + kBlendRows < n ? r0 + kBlendRows : n;
+    double acc = 0.0;
+    if (lane_row < per)
+        for (int64_t r = r0 + lane_row; r < r1; r += per) {
+            const double v = which ? R[r * ldr + c] : X[r * ldx + c];
+            acc += v * v;
+        }
+    red[t] = lane_row < per ? acc : 0.0;
+    __syncthreads();
+    if (t < 2 * m) {
+        double sum = 0.0;
+        for (int q = 0; q < per; ++q) sum += red[q * 2 * m + t];
+        part[(size_t)blockIdx.x * 2 * m + t] = sum;
+    }
+}
+
+// scale[c] = 1 / rms(X_c), scale[m + c] = w / rms(R_c), chunk partials added in order
+__global__ void blend_scale_kernel(int64_t n, int m, int nchunks, const double *part, double w, double *scale) {
+    const int t = threadIdx.x;
+    if (t >= 2 * m) return;
+    double sum = 0.0;
+    for (int b = 0; b < nchunks; ++b) sum += part[(size_t)b * 2 * m + t];
+    const double rms = sqrt(sum / (double)n);
+    const double f = rms > 1e-300 ? 1.0 / rms : 1e300;
+    scale[t] = t < m ? f : w * f;
+}
+
+__global__ void blend_apply_kernel(int64_t n, int m, double *X, int64_t ldx, const double *R, int64_t ldr,
+                                   const double *scale) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * m) return;
+    const int64_t r = i / m;
+    const int c = (int)(i - r * m);
+    X[r * ldx + c] = X[r * ldx + c] * scale[c] + R[r * ldr + c] * scale[m + c];
+}
+
 }  // namespace
 
 extern "C" {
+
+int block_blend(ff_ctx *ctx, int64_t n, int m, double *X, int64_t ldx, const double *R, int64_t ldr, double w) {
+    if (!ctx) return FF_ERR_INVALID_ARG;
+    FF_REQUIRE(ctx, n > 0 && X && R, "bad arguments");
+    FF_REQUIRE(ctx, m >= 1 && m <= 64, "block width %d must be in [1, 64]", m);
+    FF_REQUIRE(ctx, ldx >= m && ldr >= m, "leading dimensions must be >= m");
+    FF_REQUIRE(ctx, std::isfinite(w) && w >= 0.0, "weight must be finite and >= 0");
+    FF_HIP(ctx, hipSetDevice(ctx->device));
+    const int nchunks = (int)((n + kBlendRows - 1) / kBlendRows);
+    double *part = (double *)ws_get(ctx, WS_BLEND, ((size_t)nchunks + 1) * 2 * m * sizeof(double));
+    if (!part) return FF_ERR_OOM;
+    double *scale = part + (size_t)nchunks * 2 * m;
+    hipStream_t st = ctx->stream;
+    hipLaunchKernelGGL(blend_ss_kernel, dim3(nchunks), dim3(256), 0, st, n, m, (const double *)X, ldx, R, ldr, part);
+    hipLaunchKernelGGL(blend_scale_kernel, dim3(1), dim3(128), 0, st, n, m, nchunks, (const double *)part, w, scale);
+    hipLaunchKernelGGL(blend_apply_kernel, dim3(grid_for(n * m, 256)), dim3(256), 0, st, n, m, X, ldx, R, ldr,
+                       (const double *)scale);
+    FF_CHECK_LAUNCH(ctx);
+    return FF_OK;
+}
 
 int mlp_param_count(int k, int n_in) {
     return (k >= 1 && k <= 64 && n_in >= 1 && n_in <= kH) ? layout(k, n_in).total : -1;

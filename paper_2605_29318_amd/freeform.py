@@ -94,6 +94,7 @@ def lib():
         "eigenmodes_batched": (i32, [vp, i32, vp, vp, vp, vp, vp, vp, P(ff_eig_params), vp, vp, vp, vp,
                                      vp]),
         "eig_bounds": (i32, [vp, i32, i32, vp, vp]),
+        "chebyshev_apply": (i32, [vp, i64, vp, vp, vp, vp, vp, i32, i32, f64, i32, f64, vp, i64, vp, i64, P(f64)]),
         "spmm_hm": (i32, [vp, i64, vp, vp, vp, vp, vp, i32, i32, vp, i64, vp, vp, i64, i32]),
         "spmm_autotune": (i32, [vp, i64, vp, vp, vp, vp, vp, i32, i32, ctypes.c_char_p, P(i32), P(f64)]),
         "gram_hm": (i32, [vp, i64, i32, i32, vp, vp, vp, i64, vp]),
@@ -122,6 +123,11 @@ def lib():
         "mlp_forward": (i32, [vp, i64, vp, vp, i64]),
         "mlp_train_step": (i32, [vp, i64, vp, vp, i64, vp, ctypes.c_float, P(f64)]),
         "lumped_mass": (i32, [vp, i64, vp, vp, vp]),
+        "block_blend": (i32, [vp, i64, i32, vp, i64, vp, i64, f64]),
+        "sym_build": (i32, [vp, i64, vp, vp, vp, vp, i32, P(vp)]),
+        "sym_info": (i32, [vp, P(i64), P(i64)]),
+        "spmm_sym": (i32, [vp, vp, i32, vp, i64, vp, vp, i64]),
+        "sym_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -392,6 +398,22 @@ def eig_bounds(ctx: Context, n_obj: int, k: int):
     return e, a
 
 
+def chebyshev_apply(ctx: Context, n: int, row_ptr, col, H, M, hm32, R, degree: int = 12, ratio: float = 0.0,
+                    values: int = 1, upper: float = 0.0):
+    """(Z, b): Z = q(D^-1 H) D^-1 R, the eigensolver's preconditioner alone on one object, R a
+    float32 [n][m] block on the device; b the interval's upper end taken (upper, or the library's
+    estimate when 0). With values 3 and 4 each column of Z is scaled by 1 / max |D^-1 r|."""
+    import torch
+    if R.dtype != torch.float32 or R.dim() != 2 or R.shape[0] != n or R.stride(1) != 1:
+        raise FFError(FF_ERR_INVALID_ARG, f"R must be a float32 [{n}][m] block with unit column stride")
+    Z = torch.empty((n, R.shape[1]), dtype=torch.float32, device=R.device)
+    b = ctypes.c_double()
+    ctx.check(lib().chebyshev_apply(ctx.h, n, _p(row_ptr), _p(col), _p(H), _p(M), _p(hm32), R.shape[1], degree,
+                                    float(ratio), values, float(upper), _p(R), R.stride(0), _p(Z), Z.stride(0),
+                                    ctypes.byref(b)))
+    return Z, b.value
+
+
 def _check_block(X0, n, m, device):
     """A starting block must be FP64, contiguous, on the solver's device and [n][m] (the library
     reads n * m doubles from it)."""
@@ -486,6 +508,56 @@ class RowTiles:
     def close(self):
         if self.h:
             lib().rowtiles_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class SymCSR:
+    """Handle of an ff_sym copy of [H, M]: the upper triangles' values and, per lower entry, the
+    position of its mirror (sym_build); precision 0 keeps FP64 values, 1 FP32."""
+
+    def __init__(self, ctx: Context, n: int, row_ptr, col, H, M=None, precision: int = 0):
+        self.ctx = ctx
+        self.h = None
+        self.n = n
+        self.precision = precision
+        self.has_m = M is not None
+        h = ctypes.c_void_p()
+        ctx.check(lib().sym_build(ctx.h, n, _p(row_ptr), _p(col), _p(H), _p(M), precision, ctypes.byref(h)))
+        self.h = h
+        ctx._children.add(self)
+
+    def info(self):
+        u, l = ctypes.c_int64(), ctypes.c_int64()
+        lib().sym_info(self.h, ctypes.byref(u), ctypes.byref(l))
+        return u.value, l.value
+
+    def spmm(self, Y, h_only: bool = False, out=None):
+        """(HY, MY) = [H, M] Y for Y [n][m] (float64 at precision 0, float32 at 1); MY is None
+        with h_only or a copy built without M."""
+        import torch
+        dt = torch.float32 if self.precision else torch.float64
+        if Y.dtype != dt or Y.dim() != 2 or Y.shape[0] != self.n or Y.stride(1) != 1:
+            raise FFError(FF_ERR_INVALID_ARG, f"Y must be [{self.n}][m] {dt} with unit column stride")
+        want_m = self.has_m and not h_only
+        if out is None:
+            HY = torch.empty(Y.shape, dtype=dt, device=Y.device)
+            MY = torch.empty(Y.shape, dtype=dt, device=Y.device) if want_m else None
+        else:
+            HY, MY = out
+            MY = MY if want_m else None
+        self.ctx.check(lib().spmm_sym(self.ctx.h, self.h, Y.shape[1], _p(Y), Y.stride(0), _p(HY), _p(MY),
+                                      HY.stride(0)))
+        return HY, MY
+
+    def close(self):
+        if self.h:
+            lib().sym_destroy(self.h)
             self.h = None
 
     def __del__(self):
@@ -661,6 +733,19 @@ def lumped_mass(ctx: Context, n: int, row_ptr, M):
     d = torch.empty(n, dtype=torch.float64, device=M.device)
     ctx.check(lib().lumped_mass(ctx.h, n, _p(row_ptr), _p(M), _p(d)))
     return d
+
+
+def block_blend(ctx: Context, X, R, w: float):
+    """In place, column by column: X_c <- X_c / rms(X_c) + w R_c / rms(R_c) (FP64 [n][m] blocks on
+    the device, unit column stride). Returns X."""
+    import torch
+    for name, A in (("X", X), ("R", R)):
+        if A.dtype != torch.float64 or A.dim() != 2 or A.stride(1) != 1:
+            raise FFError(FF_ERR_INVALID_ARG, f"{name} must be a float64 [n][m] block with unit column stride")
+    if tuple(R.shape) != tuple(X.shape) or R.device != X.device:
+        raise FFError(FF_ERR_INVALID_ARG, "X and R must have the same shape and device")
+    ctx.check(lib().block_blend(ctx.h, X.shape[0], X.shape[1], _p(X), X.stride(0), _p(R), R.stride(0), float(w)))
+    return X
 
 
 # ----------------------------------------------------------------------------

@@ -109,8 +109,7 @@ def warm_block(ctx: ff.Context, net: Optional[ff.MLP], s: Sample, block: int, se
     X = R.clone()
     net.forward(s.x, out=X)        # writes the first k columns
     if random_weight > 0.0:
-        rms = lambda A: A / A.pow(2).mean(dim=0, keepdim=True).sqrt().clamp_min(1e-300)
-        X = (rms(X) + random_weight * rms(R)).contiguous()
+        ff.block_blend(ctx, X, R, random_weight)
     if not fallback:
         return X, True
     try:

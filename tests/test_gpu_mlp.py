@@ -168,3 +168,25 @@ def test_mlp_rejects_bad_arguments(ctx, ff):
         net.train_step(X, T, d, 1e-3)          # n < k
     assert ei.value.code == ff.FF_ERR_INVALID_ARG
     net.close()
+
+
+@pytest.mark.parametrize("n,m,w", [(1, 1, 3.0), (1037, 8, 3.0), (5000, 32, 1.0), (70000, 33, 0.0), (3001, 64, 2.5)])
+def test_block_blend(ctx, ff, R, n, m, w):
+    """The warm start's column blend in the library against the FP64 reference: FP64 sums
+    (chunk partials added in a fixed order), 1e-13 relative; a strided X, and the argument checks."""
+    rng = np.random.default_rng(n + m)
+    X = rng.standard_normal((n, m)) * rng.uniform(0.1, 10.0, m)
+    Rb = rng.uniform(-1.0, 1.0, (n, m))
+    ref = R.blend(X, Rb, w)
+    Xd = dev(X)
+    ff.block_blend(ctx, Xd, dev(Rb), w)
+    assert np.abs(Xd.cpu().numpy() - ref).max() <= 1e-13 * np.abs(ref).max()
+    wide = dev(np.zeros((n, m + 5)))
+    wide[:, :m] = dev(X)
+    ff.block_blend(ctx, wide[:, :m], dev(Rb), w)
+    assert np.abs(wide[:, :m].cpu().numpy() - ref).max() <= 1e-13 * np.abs(ref).max()
+    assert np.all(wide[:, m:].cpu().numpy() == 0.0)
+    with pytest.raises(ff.FFError):
+        ff.block_blend(ctx, dev(X).float(), dev(Rb), w)
+    with pytest.raises(ff.FFError):
+        ff.block_blend(ctx, dev(X), dev(Rb), -1.0)

@@ -185,3 +185,24 @@ def test_gradient_with_encoded_inputs():
         pm[i] -= h
         fd = (R.loss_and_grad(pp, X, T, d, k)[0] - R.loss_and_grad(pm, X, T, d, k)[0]) / (2 * h)
         assert abs(fd - g[i]) <= 1e-6 * max(1.0, np.abs(g).max())
+
+
+def test_blend_closed_forms():
+    """The blended block: blending a block with itself gives (1 + w) X / rms(X); with columns
+    of X and R orthogonal, every output column has rms sqrt(1 + w^2); w = 0 leaves X's
+    directions, each column at rms 1; scaling X or R by any positive factors per column
+    changes nothing."""
+    rng = np.random.default_rng(3)
+    n, m = 400, 6
+    X = rng.standard_normal((n, m)) * rng.uniform(0.1, 10.0, m)
+    rmsX = np.sqrt((X * X).sum(axis=0) / n)
+    assert np.allclose(R.blend(X, X, 2.5), 3.5 * X / rmsX, rtol=1e-14, atol=0)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, 2 * m)))
+    Xo, Ro = Q[:, :m] * 7.0, Q[:, m:] * 0.01
+    for w in (0.0, 1.0, 3.0):
+        Y = R.blend(Xo, Ro, w)
+        assert np.allclose(np.sqrt((Y * Y).sum(axis=0) / n), np.sqrt(1 + w * w), rtol=1e-12)
+    Y0 = R.blend(X, Ro, 0.0)
+    assert np.allclose(Y0 * rmsX, X, rtol=1e-13)
+    s1, s2 = rng.uniform(0.5, 4.0, m), rng.uniform(0.5, 4.0, m)
+    assert np.allclose(R.blend(X * s1, Ro * s2, 3.0), R.blend(X, Ro, 3.0), rtol=1e-13)
