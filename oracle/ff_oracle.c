@@ -19,7 +19,13 @@
  *   orc_rkpm                RKPM shape functions and gradients, Sec. 3.2 Eq. (7)-(11)
  *   orc_transpose           N^T(k) = { i : k in N(i) } with slots
  *   orc_assemble            weight-space Hessian (Prop. 1) and RKPM mass matrix (Eq. (14))
- *   orc_spmm                y = A x on a CSR matrix (residual checks)
+ *   orc_spmm, orc_norm_inf  y = A x and max_i sum_j |A_ij| on a CSR matrix (residual checks)
+ *   orc_fps                 farthest point sampling of the kernel centres (Supp. B.1)
+ *   orc_radii               each centre's Gaussian radius: distance to its 2nd-nearest centre
+ *   orc_neighbors_var       lists with a radius per centre, d^2 < R_k^2 (Supp. B.1)
+ *   orc_neighbors_var_brute the same predicate by exhaustive search (pin)
+ *   orc_rkpm_var            shape functions on the centres' cut Gaussians for plain RBF,
+ *                           partition-of-unity RBF and RKPM (Sec. 3.2, Fig. 3b)
  *
  * Parity status: every function here is pinned by the "not gpu" tests
  * (brute force, reproducing conditions, finite differences of the
