@@ -42,6 +42,7 @@ enum WsSlot {
     WS_RTQ_PMASK, WS_RTQ_POFF, WS_RTQ_PCNT, WS_RTQ_PVAL,          // zero-free K-blocked copy
     WS_BLEND,                                                     // warm start: column blend partials
     WS_SYM,                                                       // symmetric copy: row counts
+    WS_T8Z_CNT, WS_T8Z_OFF, WS_T8Z_MASK, WS_T8Z_VAL,              // zero-free eight-row [H, M] copy
     WS_COUNT
 };
 

@@ -1970,8 +1970,10 @@ static const char *kVariantNames[] = {"waves4_unroll2_xcd", "waves4_unroll4_xcd"
                                       "rowtile8_mfma64_waves2_batch8", "rowtile8_mfma64_waves4_batch4_occ6",
                                       "rowtile8_mfma32x64_waves4_batch8", "rowtile8_mfma32x64_waves2_batch8",
                                       "rowtile8_mfma64_pipelined_waves4", "rowtile8_mfma32x64_pipelined_waves4",
-                                      "rowtile8_mfma64_pipelined_waves2"};
-constexpr int kNumVariants = 24;
+                                      "rowtile8_mfma64_pipelined_waves2", "rowtile8_mfma64_zerofree_waves2",
+                                      "rowtile8_mfma64_zerofree_waves4"};
+constexpr int kNumVariants = 26;
+constexpr int kZeroFreeBase = 24;              // from here on: the zero-free eight-row copy
 constexpr int kRowTileBase = 13;               // variants from here on run on a row-tile copy
 constexpr int kRowTile8Base = 16;              // from here on: the eight-row [H, M] copy on MFMA (FP32 blocks)
 constexpr int kCsrVariant = 11;                // fastest variant on the CSR itself
@@ -2817,8 +2819,11 @@ int solve(ff_ctx *ctx, int n_obj, const int64_t *obj_off, const int64_t *row_ptr
     s.var64 = lookup_variant(ctx, s.N, nnz, m, 0);
     {
         // the mixed path's FP64 phase is normally the certification alone: it keeps the CSR
-        // (kCsrVariant) rather than paying for an FP64 row-tile copy
-        if (p->precision == 1 && s.var64 >= kRowTileBase) s.var64 = kCsrVariant;
+        // (kCsrVariant) rather than paying for an FP64 row-tile copy; refining to an eigenvalue or
+        // angle bound takes hundreds of FP64 iterations at 10^6 rows, where the copy (tens of ms to
+        // build) halves each product (2.9 against 5.9 ms)
+        if (p->precision == 1 && s.var64 >= kRowTileBase && p->eig_tol == 0.0 && p->angle_tol == 0.0)
+            s.var64 = kCsrVariant;
         // the FP64 blocks never take the eight-row MFMA variants (FP32 only); nor do block widths they lack
         if (s.var64 >= kRowTile8Base) s.var64 = kDefaultVariant64;
         if (s.var32 >= kRowTile8Base && !rt::hm8_ok(m, 3 * (int64_t)m, 3 * (int64_t)m)) s.var32 = kDefaultVariant64;
@@ -2831,6 +2836,7 @@ int solve(ff_ctx *ctx, int n_obj, const int64_t *obj_off, const int64_t *row_ptr
         if (p->precision == 1 && s.var32 >= kRowTile8Base) {
             // one eight-row copy with H and M serves the fused products and the preconditioner
             int rc0 = rt::build_t8_ws(ctx, s.st, s.N, row_ptr, col, H, &s.rt8, M);
+            if (!rc0 && s.var32 >= kZeroFreeBase) rc0 = rt::build_t8z_ws(ctx, s.st, &s.rt8);
             if (rc0) return rc0;
         }
     }
@@ -3099,6 +3105,7 @@ extern "C" int spmm_hm(ff_ctx *ctx, int64_t n, const int64_t *row_ptr, const int
         FF_REQUIRE(ctx, H && M, "row-tile variants need H and M");
         FF_REQUIRE(ctx, rt::hm8_ok(m, ld_y, ld_out), "variant %d takes m in {4, 8, 12, 16, 32, 64}, m = %d", v, m);
         int rc = rt::build_t8_ws(ctx, ctx->stream, n, row_ptr, col, H, &view8, M);
+        if (!rc && v >= kZeroFreeBase) rc = rt::build_t8z_ws(ctx, ctx->stream, &view8);
         if (rc) return rc;
     } else if (v >= kRowTileBase) {
         FF_REQUIRE(ctx, H && M, "row-tile variants need H and M");
@@ -3184,6 +3191,7 @@ extern "C" int spmm_autotune(ff_ctx *ctx, int64_t n, const int64_t *row_ptr, con
         }
         if (v >= kRowTile8Base && !have_view8) {
             int rc0 = rt::build_t8_ws(ctx, ctx->stream, n, row_ptr, col, H, &view8, M);
+            if (!rc0) rc0 = rt::build_t8z_ws(ctx, ctx->stream, &view8);
             if (rc0) return rc0;
             have_view8 = 1;
         }

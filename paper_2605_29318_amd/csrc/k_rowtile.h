@@ -68,6 +68,11 @@ struct RT8View {
     // H-only products (spmm_h_t8, cheb_step_t8) read it instead of vh
     const uint16_t *vh16 = nullptr;  // [entries][8] binary16 bits
     float hscale = 1.f;
+    // the zero-free copy of (vh, vm) (build_t8z_ws): per entry a byte mask of the rows present (H or
+    // M not +-0), and their (H, M) pairs in entry and row order, each tile's from pair poff[t] on
+    const uint8_t *m8 = nullptr;     // [entries]
+    const int64_t *poff = nullptr;   // [ntiles + 1]
+    const float *pv = nullptr;       // [2 * pairs + 16]
 };
 int build_t8_ws(ff_ctx *ctx, hipStream_t st, int64_t n, const int64_t *row_ptr, const int32_t *col, const double *H,
                 RT8View *out, const double *M = nullptr);
@@ -164,8 +169,10 @@ int cheb_step_t16(ff_ctx *ctx, hipStream_t st, const RT16View &v, int sub, int m
 // [HY, MY] = [H, M] Y (FP32 blocks, FP64 accumulation on FP64 MFMA) on an
 // eight-row copy built with M; m in {4, 8, 12, 16, 32, 64}; sub 0 .. kHm8Subs - 1 (3, 4 and 6 take
 // four-entry steps on the FP32 matrix cores, each added in FP64; 5, 6 and 7 pipeline the loads).
-constexpr int kHm8Subs = 8;
+constexpr int kHm8Subs = 10;
 bool hm8_ok(int m, int64_t ldy, int64_t ldo);
+// builds the zero-free copy of a built eight-row [H, M] copy into workspace slots
+int build_t8z_ws(ff_ctx *ctx, hipStream_t st, RT8View *v);
 int spmm_hm8(ff_ctx *ctx, hipStream_t st, const RT8View &v, int sub, int m, const float *Y, int64_t ldy, float *HY,
              float *MY, int64_t ldo, const int *row_obj, const int *status);
 

@@ -2463,6 +2463,249 @@ spmm_hm8p_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int32
     }
 }
 
+// The pipelined [H, M] product of spmm_hm8p_kernel (FP64 matrix cores) reading the zero-free copy
+// of the eight-row tiles: per union entry a byte mask of the tile rows present and, in entry order,
+// their (H, M) value pairs. The columns and masks of a chunk of 64 entries are loaded two chunks
+// ahead and its pairs one chunk ahead (so waiting for a mask waits only for loads that were needed
+// already); each lane reads the 64 bytes from its entry's first pair (its pairs and, past them,
+// its neighbours', which it does not use), the wave's prefix count of present rows locating them,
+// and rebuilds the entry in LDS as the full tiles hold it: row r's pair is the one at the count of
+// mask bits below r (zeros when the bit is clear). The same operands as from the full tiles, so the
+// same sums bit for bit.
+template <int kMT, int kWaves, int kOcc>
+__global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(kOcc, 8)))
+spmm_hm8z_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int32_t *tcol, const uint8_t *m8,
+                 const int64_t *poff, const float *pv, const float *Y, int64_t ldy, float *HY, float *MY, int64_t ldo,
+                 int m, const int *row_obj, const int *obj_status) {
+    typedef typename YVec<kMT>::type YV;
+    constexpr int kB = 8;                          // quads (of four entries) per batch
+    __shared__ __align__(16) float sraw[kWaves][64 * 16];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t t = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kWaves + wv;
+    if (t >= ntiles) return;
+    const int li = lane & 15, lk = lane >> 4;
+    const int64_t r0 = t * kTile8;
+    bool any = false;
+#pragma unroll
+    for (int i = 0; i < kTile8; ++i)
+        any = any || (r0 + i < nrows && (!obj_status || obj_status[row_obj[r0 + i]] == 0));
+    if (!any) return;
+    float *sv = sraw[wv];
+    const int64_t e0 = tptr[t], e1 = tptr[t + 1];
+    const int nch = (int)((e1 - e0 + 63) >> 6);
+    const int col = kMT * (kMT > 1 || li < m ? li : 0);
+    int64_t pbase = poff[t];                       // first pair of the next chunk whose pairs are loaded
+    f64x4r d[kMT];
+#pragma unroll
+    for (int q = 0; q < kMT; ++q) d[q] = f64x4r{0.0, 0.0, 0.0, 0.0};
+    auto nquads = [&](int c) __attribute__((always_inline)) -> int {
+        const int64_t cnt = e1 - e0 - 64 * (int64_t)c;
+        return cnt >= 64 ? 16 : (int)((cnt + 3) >> 2);
+    };
+    struct Chunk {
+        int32_t j;
+        uint32_t mk;
+        bool in;
+        f32x4 v[4];
+    };
+    // columns and masks of chunk c (lanes past the tile's end: the last entry's column, no rows)
+    auto load_cols = [&](Chunk &ch, int c) __attribute__((always_inline)) {
+        const int64_t e = e0 + 64 * (int64_t)c + lane;
+        ch.in = e < e1;
+        const int64_t ec = ch.in ? e : e1 - 1;
+        __builtin_amdgcn_sched_barrier(0);
+        ch.j = __builtin_nontemporal_load(tcol + ec);
+        ch.mk = (uint32_t)m8[ec];
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    // the pairs of the chunk whose masks ch holds: 64 bytes from the lane's first pair
+    auto load_vals = [&](Chunk &ch) __attribute__((always_inline)) {
+        const uint32_t mk = ch.in ? ch.mk : 0u;
+        const int cnt = __popc(mk);
+        int incl = cnt;
+#pragma unroll
+        for (int dd = 1; dd < 64; dd <<= 1) {
+            const int v = __shfl_up(incl, dd, 64);
+            if (lane >= dd) incl += v;
+        }
+        const float *src = pv + 2 * (pbase + incl - cnt);
+        pbase += __shfl(incl, 63, 64);
+        __builtin_amdgcn_sched_barrier(0);
+        // pairs are 8-byte aligned: 16-byte loads at 8-byte alignment (the hardware takes dword alignment)
+        typedef float f32x4a8 __attribute__((ext_vector_type(4), aligned(8)));
+#pragma unroll
+        for (int q = 0; q < 4; ++q) ch.v[q] = __builtin_nontemporal_load((const f32x4a8 *)(src + 4 * q));
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    // the lane's entry laid out as the full tiles' (H rows 0-7, M rows 0-7, zeros for absent rows) in
+    // its LDS area: its pairs are written there, read back by rank, and the expanded entry written
+    // over them (only the lane touches its area here)
+    auto stage = [&](const Chunk &ch) __attribute__((always_inline)) {
+        float *a = sv + lane * 16;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) *(f32x4 *)(a + 4 * q) = ch.v[q];
+        const uint32_t mk = ch.in ? ch.mk : 0u;
+        float hv[8], mv[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const float2 pr = *(const float2 *)(a + 2 * __popc(mk & ((1u << r) - 1u)));
+            const bool on = (mk >> r) & 1u;
+            hv[r] = on ? pr.x : 0.f;
+            mv[r] = on ? pr.y : 0.f;
+        }
+        *(f32x4 *)(a + 0) = f32x4{hv[0], hv[1], hv[2], hv[3]};
+        *(f32x4 *)(a + 4) = f32x4{hv[4], hv[5], hv[6], hv[7]};
+        *(f32x4 *)(a + 8) = f32x4{mv[0], mv[1], mv[2], mv[3]};
+        *(f32x4 *)(a + 12) = f32x4{mv[4], mv[5], mv[6], mv[7]};
+    };
+    auto gather = [&](YV (&y)[kB], const Chunk &ch, int h) __attribute__((always_inline)) {
+        const int32_t jc = ch.in ? ch.j : 0;
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < kB; ++u) {
+            const uint32_t j = (uint32_t)__shfl(jc, 4 * (kB * h + u) + lk, 64);
+            y[u] = *(const YV *)(Y + (size_t)(j * (uint32_t)ldy) + col);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    auto multiply = [&](const YV (&y)[kB], int h, int nq, bool full) __attribute__((always_inline)) {
+#pragma unroll
+        for (int u = 0; u < kB; ++u) {
+            if (full || kB * h + u < nq) {
+                const int e = 4 * (kB * h + u) + lk;
+                const double a = (double)sv[e * 16 + li];
+#pragma unroll
+                for (int tt = 0; tt < kMT; ++tt) d[tt] = mfma64(a, (double)yget(y[u], tt), d[tt]);
+            }
+        }
+    };
+    // chunk c: cur holds its columns, masks and pairs, nxt the columns and masks of chunk c + 1, whose
+    // pairs are loaded here; cur is then reloaded with the columns of chunk c + 2
+    YV ya[kB], yb[kB];
+    auto step = [&](int c, Chunk &cur, Chunk &nxt, bool steady) __attribute__((always_inline)) {
+        const int nq = steady ? 16 : nquads(c);
+        __builtin_amdgcn_wave_barrier();
+        stage(cur);
+        __builtin_amdgcn_wave_barrier();
+        if (steady || nq > kB) gather(yb, cur, 1);
+        multiply(ya, 0, nq, steady);
+        if (steady || c + 1 < nch) {
+            gather(ya, nxt, 0);
+            load_vals(nxt);
+        }
+        if (steady || c + 2 < nch) load_cols(cur, c + 2);
+        if (steady || nq > kB) multiply(yb, 1, nq, steady);
+    };
+    if (nch > 0) {
+        Chunk pa, pb;
+        load_cols(pa, 0);
+        if (nch > 1) load_cols(pb, 1);
+        load_vals(pa);
+        gather(ya, pa, 0);
+        int c = 0;
+        for (; c + 3 < nch; c += 2) {
+            step(c, pa, pb, true);
+            step(c + 1, pb, pa, true);
+        }
+        step(c, pa, pb, false);
+        if (c + 1 < nch) step(c + 1, pb, pa, false);
+        if (c + 2 < nch) step(c + 2, pa, pb, false);
+    }
+    if (kMT == 1 && li >= m) return;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int o = 4 * v + lk;
+        const int64_t r = r0 + (o & 7);
+        if (r >= nrows || (obj_status && obj_status[row_obj[r]] != 0)) continue;
+        float *dst = (o < 8 ? HY : MY) + r * ldo + kMT * li;
+        if (kMT == 1) {
+            dst[0] = (float)d[0][v];
+        } else if (kMT == 2) {
+            *(float2 *)dst = make_float2((float)d[0][v], (float)d[1][v]);
+        } else {
+            *(f32x4 *)dst = f32x4{(float)d[0][v], (float)d[1][v], (float)d[2][v], (float)d[3][v]};
+        }
+    }
+}
+
+// value pairs present in each tile's entries (a row is present when its H or its M value is not +-0)
+__global__ void __launch_bounds__(64) t8z_count_kernel(int64_t ntiles, const int64_t *tptr, const float *vh,
+                                                       const float *vm, int64_t *cnt) {
+    const int64_t t = blockIdx.x;
+    if (t >= ntiles) return;
+    int c = 0;
+    for (int64_t e = tptr[t] + threadIdx.x; e < tptr[t + 1]; e += 64)
+#pragma unroll
+        for (int r = 0; r < 8; ++r) c += (vh[e * 8 + r] != 0.f || vm[e * 8 + r] != 0.f);
+#pragma unroll
+    for (int dd = 32; dd >= 1; dd >>= 1) c += __shfl_xor(c, dd, 64);
+    if (threadIdx.x == 0) cnt[t] = c;
+}
+
+// one 64-thread block per tile, an entry per lane per chunk of 64: its mask and its present pairs,
+// placed by the prefix count over the chunk's lanes after the tile's earlier chunks
+__global__ void __launch_bounds__(64) t8z_fill_kernel(int64_t ntiles, const int64_t *tptr, const float *vh,
+                                                      const float *vm, const int64_t *poff, uint8_t *m8, float *pv) {
+    const int64_t t = blockIdx.x;
+    if (t >= ntiles) return;
+    const int lane = threadIdx.x;
+    int64_t run = poff[t];
+    for (int64_t base = tptr[t]; base < tptr[t + 1]; base += 64) {
+        const int64_t e = base + lane;
+        const bool in = e < tptr[t + 1];
+        uint32_t mk = 0;
+        if (in)
+#pragma unroll
+            for (int r = 0; r < 8; ++r) mk |= (vh[e * 8 + r] != 0.f || vm[e * 8 + r] != 0.f) ? (1u << r) : 0u;
+        const int cnt = __popc(mk);
+        int incl = cnt;
+#pragma unroll
+        for (int dd = 1; dd < 64; dd <<= 1) {
+            const int v = __shfl_up(incl, dd, 64);
+            if (lane >= dd) incl += v;
+        }
+        if (in) {
+            m8[e] = (uint8_t)mk;
+            int64_t o = run + incl - cnt;
+            for (int r = 0; r < 8; ++r)
+                if ((mk >> r) & 1u) {
+                    pv[2 * o] = vh[e * 8 + r];
+                    pv[2 * o + 1] = vm[e * 8 + r];
+                    ++o;
+                }
+        }
+        run += __shfl(incl, 63, 64);
+    }
+}
+
+int build_t8z_ws(ff_ctx *ctx, hipStream_t st, RT8View *v) {
+    FF_REQUIRE(ctx, v && v->vh && v->vm && v->tptr && v->ntiles > 0, "zero-free [H, M] tiles: no eight-row copy");
+    int64_t *cnt = (int64_t *)ws_get(ctx, WS_T8Z_CNT, (size_t)(v->ntiles + 1) * sizeof(int64_t));
+    int64_t *poff = (int64_t *)ws_get(ctx, WS_T8Z_OFF, (size_t)(v->ntiles + 1) * sizeof(int64_t));
+    uint8_t *m8 = (uint8_t *)ws_get(ctx, WS_T8Z_MASK, (size_t)std::max<int64_t>(v->entries, 1));
+    if (!cnt || !poff || !m8) return FF_ERR_OOM;
+    hipLaunchKernelGGL(t8z_count_kernel, dim3(v->ntiles), dim3(64), 0, st, v->ntiles, v->tptr, v->vh, v->vm, cnt);
+    FF_CHECK_LAUNCH(ctx);
+    int rc = scan_exclusive_i64(ctx, cnt, poff, v->ntiles);
+    if (rc) return rc;
+    int64_t *h = (int64_t *)pinned_get(ctx, 64);
+    if (!h) return FF_ERR_OOM;
+    FF_HIP(ctx, hipMemcpyAsync(h, poff + v->ntiles, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    FF_HIP(ctx, hipStreamSynchronize(st));
+    const int64_t total = h[0];
+    // sixteen floats of padding: the last lanes read 64 bytes from their first pair
+    float *pv = (float *)ws_get(ctx, WS_T8Z_VAL, (size_t)(2 * total + 16) * sizeof(float));
+    if (!pv) return FF_ERR_OOM;
+    FF_HIP(ctx, hipMemsetAsync(pv + 2 * total, 0, 16 * sizeof(float), st));
+    hipLaunchKernelGGL(t8z_fill_kernel, dim3(v->ntiles), dim3(64), 0, st, v->ntiles, v->tptr, v->vh, v->vm,
+                       (const int64_t *)poff, m8, pv);
+    FF_CHECK_LAUNCH(ctx);
+    v->m8 = m8;
+    v->poff = poff;
+    v->pv = pv;
+    return FF_OK;
+}
+
 bool hm8_ok(int m, int64_t ldy, int64_t ldo) { return t16_ok(m, ldy, ldo); }
 
 int spmm_hm8(ff_ctx *ctx, hipStream_t st, const RT8View &v, int sub, int m, const float *Y, int64_t ldy, float *HY,
@@ -2479,9 +2722,27 @@ int spmm_hm8(ff_ctx *ctx, hipStream_t st, const RT8View &v, int sub, int m, cons
                        v.ntiles, v.tptr, v.tcol, v.vh, v.vm, Y, ldy, HY, MY, ldo, m, row_obj, status)
     // sub 0..2: FP64 matrix cores; 3, 4: FP32 matrix cores with FP64 accumulation of each four-entry step;
     // 5, 6: the pipelined kernel on the FP64 and the FP32 matrix cores; 7: the former with two waves per
-    // workgroup at m = 32 (as 5 at other widths)
+    // workgroup at m = 32 (as 5 at other widths); 8, 9: the pipelined kernel on the FP64 matrix cores from
+    // the zero-free copy, two and four waves per workgroup
     FF_REQUIRE(ctx, sub >= 0 && sub < kHm8Subs, "launch shape %d out of range", sub);
     const int mt = m <= 16 ? 1 : m / 16;
+    if (sub >= 8) {
+        FF_REQUIRE(ctx, v.m8 && v.poff && v.pv, "launch shape %d needs the zero-free copy", sub);
+#define FF_HM8Z(MT, W, O)                                                                                        \
+    hipLaunchKernelGGL((spmm_hm8z_kernel<MT, W, O>), dim3(grid_for(v.ntiles, W)), dim3(64 * W), 0, st, v.n,       \
+                       v.ntiles, v.tptr, v.tcol, v.m8, v.poff, v.pv, Y, ldy, HY, MY, ldo, m, row_obj, status)
+        const bool two = sub == 8;
+        if (mt == 1) {
+            if (two) FF_HM8Z(1, 2, 2); else FF_HM8Z(1, 4, 2);
+        } else if (mt == 2) {
+            if (two) FF_HM8Z(2, 2, 2); else FF_HM8Z(2, 4, 2);
+        } else {
+            if (two) FF_HM8Z(4, 2, 2); else FF_HM8Z(4, 4, 2);
+        }
+#undef FF_HM8Z
+        FF_CHECK_LAUNCH(ctx);
+        return FF_OK;
+    }
     if (sub >= 5) {
         const bool f32p = sub == 6;
         if (mt == 1) {

@@ -30,10 +30,32 @@ def _log(msg: str):
     print(msg, flush=True)
 
 
-def _shapes(count: int, nmin: int, nmax: int, seed0: int, rng, k: int):
-    for j in range(count):
-        n = int(round(math.exp(rng.uniform(math.log(nmin), math.log(nmax)))))
-        yield j, synth.ellipsoid_union(n=n, seed=seed0 + j, hetero=False, k=k, mc_samples=400_000)
+def _make_shape(args):
+    n, seed, k = args
+    return synth.ellipsoid_union(n=n, seed=seed, hetero=False, k=k, mc_samples=400_000)
+
+
+def _shapes(count: int, nmin: int, nmax: int, seed0: int, rng, k: int, workers: int = 1):
+    """Shapes j = 0 .. count - 1 (particle counts log-uniform in [nmin, nmax], seed seed0 + j); with
+    workers > 1 built ahead in freshly started worker processes (each shape from its own seed, so
+    the same shapes), yielded in order."""
+    jobs = [(int(round(math.exp(rng.uniform(math.log(nmin), math.log(nmax))))), seed0 + j, k) for j in range(count)]
+    if workers <= 1:
+        for j, a in enumerate(jobs):
+            yield j, _make_shape(a)
+        return
+    import multiprocessing as mp
+    with mp.get_context("spawn").Pool(min(workers, count)) as pool:
+        for j, c in enumerate(pool.imap(_make_shape, jobs, chunksize=1)):
+            yield j, c
+
+
+def _ci95(x):
+    """Mean and the half-width of its 95% confidence interval (normal approximation)."""
+    x = np.asarray(x, dtype=np.float64)
+    if x.size < 2:
+        return float(x.mean()) if x.size else float("nan"), float("nan")
+    return float(x.mean()), float(1.96 * x.std(ddof=1) / math.sqrt(x.size))
 
 
 def main(argv=None) -> int:
@@ -55,6 +77,7 @@ def main(argv=None) -> int:
                     help="random_weight of warm_block per preconditioner in --precond order")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--out", type=str, default=None, help="save the FP32 parameters (.npy)")
+    ap.add_argument("--workers", type=int, default=1, help="worker processes building the shapes")
     a = ap.parse_args(argv)
 
     import torch
@@ -66,12 +89,13 @@ def main(argv=None) -> int:
     rng = np.random.default_rng(a.seed)
     t0 = time.time()
     train = []
-    for j, c in _shapes(a.train, a.train_n[0], a.train_n[1], 10_000, rng, k):
+    for j, c in _shapes(a.train, a.train_n[0], a.train_n[1], 10_000, rng, k, a.workers):
         try:
             s = ws.with_targets(ctx, ws.prepare(ctx, c, n_freq=a.freq), k, tol=a.tol)
         except ff.FFError as e:            # e.g. a thin part sampled too sparsely for the kernel support
             _log(f"train shape {j}: skipped ({e})")
             continue
+        s.A = None                         # training reads only the inputs, lumped mass and targets
         train.append(s)
         _log(f"train shape {j}: n={s.n} iters={s.info['iters_fp32']}+{s.info['iters_fp64']} "
              f"({time.time() - t0:.1f} s)")
@@ -83,7 +107,7 @@ def main(argv=None) -> int:
     if a.out:
         np.save(a.out, net.get_params(), allow_pickle=False)
     rows = []
-    for j, c in _shapes(a.test, a.test_n[0], a.test_n[1], 90_000, rng, k):
+    for j, c in _shapes(a.test, a.test_n[0], a.test_n[1], 90_000, rng, k, a.workers):
         try:
             s = ws.prepare(ctx, c, n_freq=a.freq)
         except ff.FFError as e:
@@ -108,7 +132,8 @@ def main(argv=None) -> int:
                         row[f"{key}_dlam"] = float(np.abs(lam[1:] - lam_r[1:]).max() / np.abs(lam_r[1:]).max())
         rows.append(row)
         _log(json.dumps(row))
-    summ = dict(train_shapes=len(train), train_seconds=round(train_s, 2), k=k, freq=a.freq, epochs=a.epochs)
+    summ = dict(train_shapes=len(train), train_n=a.train_n, test_n=a.test_n, train_seconds=round(train_s, 2), k=k,
+                freq=a.freq, epochs=a.epochs, random_weight=a.random_weight, precond=a.precond)
     for prec in a.precision:
         for pc in a.precond:
             key = f"p{prec}c{pc}"
@@ -116,9 +141,11 @@ def main(argv=None) -> int:
             w = [x[f"{key}_warm"]["iters"] for x in rows]
             rs = [x[f"{key}_random"]["seconds"] for x in rows]
             wsec = [x[f"{key}_warm"]["seconds"] for x in rows]
-            summ[key] = dict(iters_random=float(np.mean(r)), iters_warm=float(np.mean(w)),
+            ratio, ci = _ci95(np.array(w) / np.array(r))
+            sratio, sci = _ci95(np.array(wsec) / np.array(rs))
+            summ[key] = dict(shapes=len(rows), iters_random=float(np.mean(r)), iters_warm=float(np.mean(w)),
                              seconds_random=float(np.mean(rs)), seconds_warm=float(np.mean(wsec)),
-                             iter_ratio=float(np.mean(np.array(w) / np.array(r))),
+                             iter_ratio=ratio, iter_ratio_ci95=ci, seconds_ratio=sratio, seconds_ratio_ci95=sci,
                              used_network=sum(x[f"{key}_warm"]["used_network"] for x in rows))
     _log("SUMMARY " + json.dumps(summ))
     net.close()

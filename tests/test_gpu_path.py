@@ -438,8 +438,11 @@ def test_rowtile_kernels_short_tiles(oracle, ctx, ff):
             assert np.all(np.abs(HY - refH) <= 2e-6 * absH + 1e-300), (name, m)
             assert np.all(np.abs(MY - refM) <= 2e-6 * absM + 1e-300), (name, m)
             out[name] = (HY, MY)
+        # the zero-free copy gives the same operands as the full tiles: the same sums
         for a, b in (("rowtile8_mfma64_pipelined_waves4", "rowtile8_mfma64_waves4_batch8"),
                      ("rowtile8_mfma64_pipelined_waves2", "rowtile8_mfma64_waves4_batch8"),
+                     ("rowtile8_mfma64_zerofree_waves2", "rowtile8_mfma64_waves4_batch8"),
+                     ("rowtile8_mfma64_zerofree_waves4", "rowtile8_mfma64_waves4_batch8"),
                      ("rowtile8_mfma32x64_pipelined_waves4", "rowtile8_mfma32x64_waves4_batch8")):
             assert np.array_equal(out[a][0], out[b][0]) and np.array_equal(out[a][1], out[b][1]), (a, m)
     rt = ff.RowTiles(ctx, n, rp, cl, Hd, None, precision=6)
