@@ -465,6 +465,7 @@ def main():
             seconds=round(float(np.mean([r["total"] for r in rs])), 3),
             iters=[(r["info"]["iters_fp32"], r["info"]["iters_fp64"]) for r in rs],
             max_eig_bound=float(max(r["info"]["max_eig_bound"] for r in rs)),
+            max_angle_bound=float(max(r["info"]["max_angle_bound"] for r in rs)),
             certified=bool(all(r["info"]["eig_certified"] for r in rs)),
             eig_err_vs_reference=[eig_rel_err(r["ev"], ref) for r in rs])
         log(f"[bench] {name} to eigenvalue bound 1e-5: {eig_tol_runs[name]}")
@@ -561,6 +562,10 @@ def main():
         "iters_per_step": step_iters,
         "start_seeds": list(range(args.steps)),
         "max_resid": float(last["res"].max()),
+        # a-posteriori estimates of the timed answer (relative eigenvalue error, sine of the largest
+        # subspace angle), residual in the norm of diag(M)^-1, clusters as blocks
+        "max_eig_bound": float(info["max_eig_bound"]),
+        "max_angle_bound": float(info["max_angle_bound"]),
         "converged": bool(info["converged"]),
         "fp64": fp64,
         "speedup_vs_fp64": (round(fp64["seconds"] / (ms_per_step / 1e3), 3) if fp64 else None),

@@ -79,13 +79,18 @@ def test_warm_start_reaches_the_same_eigenpairs_in_fewer_iterations(env):
 
 
 def test_warm_start_with_chebyshev_preconditioner(env):
-    """With the default Chebyshev-Jacobi preconditioner the network's block alone costs
-    iterations (mean ratio 1.29 on these shapes: it lacks a component along some wanted
-    mode, which the strong preconditioner cannot grow quickly); blended with random
-    columns of three times its RMS it reaches the same eigenpairs in fewer iterations
-    (measured 0.974)."""
+    """With the default Chebyshev-Jacobi preconditioner (a few dozen iterations from any start)
+    the network's block alone costs iterations (mean ratio 1.29 on these shapes: it lacks a
+    component along some wanted mode, which the strong preconditioner cannot grow quickly);
+    blended with random columns of three times its RMS it reaches the same eigenpairs, and at
+    the large configuration's scale (512 training shapes, 100 held-out shapes of 1e5-5e5
+    particles) its iteration ratio is 0.995 +- 0.039 (95% interval): no measurable gain and no
+    loss. The test checks the same eigenpairs and no loss beyond that interval on its shapes."""
     ratios = _ratios(env, precond=2, random_weight=3.0)
-    assert np.mean(ratios) < 1.0, ratios
+    mean = float(np.mean(ratios))
+    half = 1.96 * float(np.std(ratios, ddof=1)) / np.sqrt(len(ratios))
+    print(f"chebyshev: warm/random iteration ratio {mean:.3f} +- {half:.3f} over {len(ratios)} shapes")
+    assert mean <= 1.1, ratios
 
 
 def test_fallback_keeps_the_block_with_the_lower_ritz_sum(env):
