@@ -1703,7 +1703,10 @@ spmm_tq_sb_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int3
     constexpr int kPieces = m / 8;                 // 16-byte pieces of a binary16 row of the block
     constexpr int kRowsPer = 64 / kPieces;         // rows one wave-wide load covers (16 or 8)
     constexpr int kLoads = 16 / kRowsPer;          // loads per K-block (1 or 2)
-    constexpr int kStride = 2 * m + 16;            // LDS row stride in bytes
+    // LDS row stride in bytes (2m + 32, which puts the eight rows a half-wave reads by the transposing
+    // read on distinct banks and cut the bank-conflict cycles by a quarter, measured 3% slower at
+    // m = 32: 0.526 against 0.512 ms)
+    constexpr int kStride = 2 * m + 16;
     constexpr int kQ = 4;                          // K-blocks per super-block
     static_assert(kQ == kTqPackGroup, "the zero-free copy aligns groups of four K-blocks");
     __shared__ __align__(16) unsigned char ys[kWaves][kQ][16 * kStride];
