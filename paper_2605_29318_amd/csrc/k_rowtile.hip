@@ -638,9 +638,9 @@ spmm_rt_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int32_t
             __builtin_amdgcn_wave_barrier();
         }
     }
-    // after the butterfly every lane holds the sums and lane group i < 4 stores row i;
-    // otherwise group 0 stores all four rows
-    const bool all = (64 % G) == 0;
+    // after the butterfly every lane holds the sums and lane group i < 4 stores row i when there are
+    // at least four groups (FP64 at m = 64 has two); otherwise group 0 stores all four rows
+    const bool all = (64 % G) == 0 && NG >= kTileRows;
     if (all ? g < kTileRows : g == 0) {
 #pragma unroll
         for (int i = 0; i < kTileRows; ++i) {

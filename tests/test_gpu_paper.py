@@ -165,3 +165,21 @@ def test_first_mode_by_basis_on_the_gpu(oracle, ctx, ff):
     print("\n[fig3b] relative eigenvalue error, mode-shape error by basis (RBF, PU-RBF, RKPM):", got)
     assert got[2][0] < got[1][0] < got[0][0]
     assert got[2][1] < got[0][1]
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_eigenpairs_block64(paper, oracle, ctx, ff, precision):
+    """k = 33 with 31 guard columns (block 64): both paths, refined to the eigenvalue bound 1e-5.
+    (At block 64 the FP64 products run the four-row tile kernel with two lane groups per wave,
+    fewer than its four rows; every row must still be written.)"""
+    import scipy.linalg as sl
+    name, S, P, A = paper
+    k = 33
+    wd, Vd = sl.eigh(P.Hs().toarray(), P.Ms().toarray(), subset_by_index=[0, k + 3])
+    lam, W, res, info = ff.eigenmodes(ctx, P.K, A.row_ptr, A.col, A.H, A.M, A.hm32, k=k, block=64,
+                                      precision=precision, tol=1e-6, eig_tol=1e-5, seed=2)
+    assert info["converged"] == 1 and info["max_eig_bound"] <= 1e-5
+    rel = np.abs(lam[1:] - wd[1:k]) / wd[1:k]
+    assert rel.max() <= 1e-5, (name, precision, rel.max())
+    kk = oracle.cluster_safe_k(wd, k)
+    assert oracle.subspace_sines(Vd[:, :kk], host(W)[:, :kk], P.Ms()).max() <= 1e-3

@@ -288,7 +288,11 @@ def test_spmm(oracle, ctx, ff, precision, m):
             with pytest.raises(ff.FFError):
                 ff.spmm_hm(ctx, A.row_ptr, A.col, A.H, A.M, A.hm32, dev(Y, dt), precision, variant=v)
             continue
-        HY, MY = ff.spmm_hm(ctx, A.row_ptr, A.col, A.H, A.M, A.hm32, dev(Y, dt), precision, variant=v)
+        # outputs filled with NaN first, so that a row a kernel does not write cannot pass on what an
+        # earlier variant left in the same memory
+        out_nan = (torch.full((c.n, m), float("nan"), dtype=dt, device="cuda"),
+                   torch.full((c.n, m), float("nan"), dtype=dt, device="cuda"))
+        HY, MY = ff.spmm_hm(ctx, A.row_ptr, A.col, A.H, A.M, A.hm32, dev(Y, dt), precision, variant=v, out=out_nan)
         eps = 2e-6 if precision else 1e-13
         assert np.all(np.abs(host(HY) - refH) <= eps * absH + 1e-300), name
         assert np.all(np.abs(host(MY) - refM) <= eps * absM + 1e-300), name
@@ -315,20 +319,23 @@ def test_rowtiles_spmm(oracle, ctx, ff, precision):
     assert rl.max() <= entries <= rl.sum()
     dt = torch.float32 if precision else torch.float64
     eps = 2e-6 if precision else 1e-13
-    for m in (8, 24, 32):
+    nan = lambda m: torch.full((c.n, m), float("nan"), dtype=dt, device="cuda")
+    # m = 64 at FP64 leaves two lane groups per wave (fewer than the tile's four rows); outputs start
+    # as NaN so that a row a kernel does not write fails
+    for m in (8, 24, 32, 64):
         Y = np.random.default_rng(m).standard_normal((c.n, m))
         refH = oracle.spmm(P.row_ptr, P.col, P.H, Y)
         refM = oracle.spmm(P.row_ptr, P.col, P.M, Y)
         absH = oracle.spmm(P.row_ptr, P.col, np.abs(P.H), np.abs(Y))
         absM = oracle.spmm(P.row_ptr, P.col, np.abs(P.M), np.abs(Y))
         for sub in range(3):
-            HY, MY = rt.spmm(dev(Y, dt), precision, sub)
+            HY, MY = rt.spmm(dev(Y, dt), precision, sub, out=(nan(m), nan(m)))
             assert np.all(np.abs(host(HY) - refH) <= eps * absH + 1e-300)
             assert np.all(np.abs(host(MY) - refM) <= eps * absM + 1e-300)
             # H alone (the preconditioner's product): FP32 accumulation at precision 1, whose
             # longest chain of roundings is a lane group's share of a tile (at most 4 rows / 8)
             # plus the three cross-group additions and the rounding of the values and of Y
-            HO, none = rt.spmm(dev(Y, dt), precision, sub, h_only=True)
+            HO, none = rt.spmm(dev(Y, dt), precision, sub, h_only=True, out=(nan(m), None))
             assert none is None
             eps_h = (4 * rl.max() // 8 + 6) * 2.0 ** -24 if precision else 1e-13
             assert np.all(np.abs(host(HO) - refH) <= eps_h * absH + 1e-300)
