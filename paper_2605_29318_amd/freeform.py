@@ -141,6 +141,24 @@ def _p(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
+_POISON = os.environ.get("FF_POISON_OUTPUTS") == "1"
+
+
+def _out(shape, dtype, device):
+    """A buffer for the library to fill: uninitialised, or, with FF_POISON_OUTPUTS=1 (the tests set
+    it), filled with NaN (floating point) or -1 (integers), so that an element the library fails to
+    write cannot pass on what earlier work left in the same memory."""
+    import torch
+    if not _POISON:
+        return torch.empty(shape, dtype=dtype, device=device)
+    shape = (int(shape),) if isinstance(shape, (int, np.integer)) else tuple(shape)
+    if dtype.is_floating_point:
+        fill = float("nan")
+    else:
+        fill = -1 if dtype.is_signed else torch.iinfo(dtype).max
+    return torch.full(shape, fill, dtype=dtype, device=device)
+
+
 class Context:
     """A library context bound to a device and the current torch stream."""
 
@@ -207,15 +225,15 @@ def build_neighbors(ctx: Context, xyz, h: float, qxyz=None) -> Neighbors:
     n = xyz.shape[0]
     q = n if qxyz is None else qxyz.shape[0]
     grid = ff_grid()
-    perm = torch.empty(n, dtype=torch.int32, device=dev)
-    xs = torch.empty((n, 3), dtype=torch.float64, device=dev)
-    off = torch.empty(q + 1, dtype=torch.int64, device=dev)
+    perm = _out(n, torch.int32, dev)
+    xs = _out((n, 3), torch.float64, dev)
+    off = _out(q + 1, torch.int64, dev)
     tot = ctypes.c_int64()
     L = lib()
     ctx.check(L.build_neighbors(ctx.h, n, _p(xyz), q, _p(qxyz), float(h), ctypes.byref(grid), _p(perm), _p(xs),
                                 None, 0, _p(off), None, 0, ctypes.byref(tot)))
-    cs = torch.empty(grid.n_cells + 1, dtype=torch.int64, device=dev)
-    ids = torch.empty(max(tot.value, 1), dtype=torch.int32, device=dev)
+    cs = _out(grid.n_cells + 1, torch.int64, dev)
+    ids = _out(max(tot.value, 1), torch.int32, dev)
     ctx.check(L.build_neighbors(ctx.h, n, _p(xyz), q, _p(qxyz), float(h), ctypes.byref(grid), _p(perm), _p(xs),
                                 _p(cs), cs.numel(), _p(off), _p(ids), ids.numel(), ctypes.byref(tot)))
     return Neighbors(grid, perm, xs, cs, off, ids[:tot.value])
@@ -228,9 +246,9 @@ def rkpm_shape(ctx: Context, xyz_sorted, nbr_off, nbr_id, h: float, qxyz=None, k
     n = xyz_sorted.shape[0]
     q = nbr_off.shape[0] - 1
     tot = nbr_id.shape[0]
-    phi = torch.empty(max(tot, 1), dtype=torch.float64, device=dev)
-    dphi = torch.empty((max(tot, 1), 3), dtype=torch.float64, device=dev)
-    feat = torch.empty((q, 8), dtype=torch.float32, device=dev) if features else None
+    phi = _out(max(tot, 1), torch.float64, dev)
+    dphi = _out((max(tot, 1), 3), torch.float64, dev)
+    feat = _out((q, 8), torch.float32, dev) if features else None
     bad = ctypes.c_int64(-1)
     rc = lib().rkpm_shape(ctx.h, n, _p(xyz_sorted), q, _p(qxyz), _p(nbr_off), _p(nbr_id), tot, float(h), kernel,
                           _p(phi), _p(dphi), _p(feat), ctypes.byref(bad))
@@ -252,15 +270,15 @@ def build_neighbors_radii(ctx: Context, xyz, radius, qxyz) -> Neighbors:
     if radius.dtype != torch.float64 or radius.shape != (n,):
         raise FFError(FF_ERR_INVALID_ARG, "radius must be float64 [n]")
     grid = ff_grid()
-    perm = torch.empty(n, dtype=torch.int32, device=dev)
-    xs = torch.empty((n, 3), dtype=torch.float64, device=dev)
-    off = torch.empty(q + 1, dtype=torch.int64, device=dev)
+    perm = _out(n, torch.int32, dev)
+    xs = _out((n, 3), torch.float64, dev)
+    off = _out(q + 1, torch.int64, dev)
     tot = ctypes.c_int64()
     L = lib()
     ctx.check(L.build_neighbors_radii(ctx.h, n, _p(xyz), _p(radius), q, _p(qxyz), ctypes.byref(grid), _p(perm),
                                       _p(xs), None, 0, _p(off), None, 0, ctypes.byref(tot)))
-    cs = torch.empty(grid.n_cells + 1, dtype=torch.int64, device=dev)
-    ids = torch.empty(max(tot.value, 1), dtype=torch.int32, device=dev)
+    cs = _out(grid.n_cells + 1, torch.int64, dev)
+    ids = _out(max(tot.value, 1), torch.int32, dev)
     ctx.check(L.build_neighbors_radii(ctx.h, n, _p(xyz), _p(radius), q, _p(qxyz), ctypes.byref(grid), _p(perm),
                                       _p(xs), _p(cs), cs.numel(), _p(off), _p(ids), ids.numel(), ctypes.byref(tot)))
     return Neighbors(grid, perm, xs, cs, off, ids[:tot.value])
@@ -270,8 +288,8 @@ def fps_centers(ctx: Context, qxyz, K: int, start: int = 0):
     """(indices [K] int32, centres [K][3]) of farthest point sampling over the points."""
     import torch
     qxyz = qxyz.contiguous()
-    idx = torch.empty(K, dtype=torch.int32, device=qxyz.device)
-    cen = torch.empty((K, 3), dtype=torch.float64, device=qxyz.device)
+    idx = _out(K, torch.int32, qxyz.device)
+    cen = _out((K, 3), torch.float64, qxyz.device)
     ctx.check(lib().fps_centers(ctx.h, qxyz.shape[0], _p(qxyz), K, start, _p(idx), _p(cen)))
     return idx, cen
 
@@ -281,8 +299,8 @@ def kernel_radii(ctx: Context, centres, cut: float = 3.0):
     import torch
     centres = centres.contiguous()
     K = centres.shape[0]
-    r = torch.empty(K, dtype=torch.float64, device=centres.device)
-    R = torch.empty(K, dtype=torch.float64, device=centres.device)
+    r = _out(K, torch.float64, centres.device)
+    R = _out(K, torch.float64, centres.device)
     ctx.check(lib().kernel_radii(ctx.h, K, _p(centres), float(cut), _p(r), _p(R)))
     return r, R
 
@@ -295,8 +313,8 @@ def rkpm_shape_radii(ctx: Context, xyz_sorted, node_r, nbr_off, nbr_id, h: float
     q = nbr_off.shape[0] - 1
     tot = nbr_id.shape[0]
     qxyz = qxyz.contiguous()
-    phi = torch.empty(max(tot, 1), dtype=torch.float64, device=dev)
-    dphi = torch.empty((max(tot, 1), 3), dtype=torch.float64, device=dev)
+    phi = _out(max(tot, 1), torch.float64, dev)
+    dphi = _out((max(tot, 1), 3), torch.float64, dev)
     bad = ctypes.c_int64(-1)
     rc = lib().rkpm_shape_radii(ctx.h, n, _p(xyz_sorted), _p(node_r.contiguous()), _p(perm), q, _p(qxyz),
                                 _p(nbr_off), _p(nbr_id), tot, float(h), float(cut), int(basis), _p(phi), _p(dphi),
@@ -313,17 +331,17 @@ def assemble_HM(ctx: Context, n: int, nbr_off, nbr_id, phi, dphi, vol, lam, mu, 
     import torch
     dev = phi.device
     q = nbr_off.shape[0] - 1
-    row_ptr = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    row_ptr = _out(n + 1, torch.int64, dev)
     nnz = ctypes.c_int64()
     L = lib()
     args = (ctx.h, n, q, _p(nbr_off), _p(nbr_id), _p(phi), _p(dphi), _p(vol), _p(lam), _p(mu), _p(rho), _p(perm),
             ctypes.byref(grid), _p(cell_start), _p(row_ptr))
     ctx.check(L.assemble_HM(*args, None, None, None, None, 0, ctypes.byref(nnz)))
     m = nnz.value
-    col = torch.empty(max(m, 1), dtype=torch.int32, device=dev)
-    H = torch.empty(max(m, 1), dtype=torch.float64, device=dev)
-    M = torch.empty(max(m, 1), dtype=torch.float64, device=dev)
-    hm32 = torch.empty((max(m, 1), 2), dtype=torch.float32, device=dev) if fp32 else None
+    col = _out(max(m, 1), torch.int32, dev)
+    H = _out(max(m, 1), torch.float64, dev)
+    M = _out(max(m, 1), torch.float64, dev)
+    hm32 = _out((max(m, 1), 2), torch.float32, dev) if fp32 else None
     ctx.check(L.assemble_HM(*args, _p(col), _p(H), _p(M), _p(hm32), m, ctypes.byref(nnz)))
     return row_ptr, col[:m], H[:m], M[:m], (hm32[:m] if fp32 else None)
 
@@ -353,7 +371,7 @@ def eigenmodes(ctx: Context, n: int, row_ptr, col, H, M, hm32, k: int, block: in
     _check_block(X0, n, m, H.device)
     lam = np.zeros(k)
     res = np.zeros(k)
-    W = torch.empty((n, k), dtype=torch.float64, device=H.device)
+    W = _out((n, k), torch.float64, H.device)
     info = ff_eig_info()
     rc = lib().eigenmodes(ctx.h, n, _p(row_ptr), _p(col), _p(H), _p(M), _p(hm32), ctypes.byref(p),
                           _p(X0), lam.ctypes.data_as(vp), _p(W), res.ctypes.data_as(vp), ctypes.byref(info))
@@ -379,7 +397,7 @@ def eigenmodes_batched(ctx: Context, obj_row_off, row_ptr, col, H, M, hm32, k: i
     _check_block(X0, N, block if block > 0 else (k + 7) // 8 * 8, H.device)
     lam = np.zeros((n_obj, k))
     res = np.zeros((n_obj, k))
-    W = torch.empty((N, k), dtype=torch.float64, device=H.device)
+    W = _out((N, k), torch.float64, H.device)
     info = (ff_eig_info * n_obj)()
     rc = lib().eigenmodes_batched(ctx.h, n_obj, off.ctypes.data_as(vp), _p(row_ptr), _p(col), _p(H), _p(M),
                                   _p(hm32), ctypes.byref(p), _p(X0), lam.ctypes.data_as(vp), _p(W),
@@ -406,7 +424,7 @@ def chebyshev_apply(ctx: Context, n: int, row_ptr, col, H, M, hm32, R, degree: i
     import torch
     if R.dtype != torch.float32 or R.dim() != 2 or R.shape[0] != n or R.stride(1) != 1:
         raise FFError(FF_ERR_INVALID_ARG, f"R must be a float32 [{n}][m] block with unit column stride")
-    Z = torch.empty((n, R.shape[1]), dtype=torch.float32, device=R.device)
+    Z = _out((n, R.shape[1]), torch.float32, R.device)
     b = ctypes.c_double()
     ctx.check(lib().chebyshev_apply(ctx.h, n, _p(row_ptr), _p(col), _p(H), _p(M), _p(hm32), R.shape[1], degree,
                                     float(ratio), values, float(upper), _p(R), R.stride(0), _p(Z), Z.stride(0),
@@ -429,8 +447,8 @@ def spmm_hm(ctx: Context, row_ptr, col, H, M, hm32, Y, precision: int, variant: 
     import torch
     n, m = Y.shape
     if out is None:
-        HY = torch.empty_like(Y)
-        MY = torch.empty_like(Y)
+        HY = _out(Y.shape, Y.dtype, Y.device)
+        MY = _out(Y.shape, Y.dtype, Y.device)
     else:
         HY, MY = out
     ctx.check(lib().spmm_hm(ctx.h, n, _p(row_ptr), _p(col), _p(H), _p(M), _p(hm32), precision, m, _p(Y),
@@ -454,7 +472,7 @@ def gram_hm(ctx: Context, S, HS, MS, w: int = None):
     n = S.shape[0]
     w = S.shape[1] if w is None else w
     precision = 1 if S.dtype == torch.float32 else 0
-    G = torch.empty((2, w, w), dtype=torch.float64, device=S.device)
+    G = _out((2, w, w), torch.float64, S.device)
     ctx.check(lib().gram_hm(ctx.h, n, w, precision, _p(S), _p(HS), _p(MS), S.stride(0), _p(G)))
     return G
 
@@ -462,8 +480,8 @@ def gram_hm(ctx: Context, S, HS, MS, w: int = None):
 def rayleigh_ritz(ctx: Context, G, m: int, tau: float = 1e-13):
     import torch
     w = G.shape[1]
-    C = torch.empty((w, m), dtype=torch.float64, device=G.device)
-    theta = torch.empty(m, dtype=torch.float64, device=G.device)
+    C = _out((w, m), torch.float64, G.device)
+    theta = _out(m, torch.float64, G.device)
     kept = ctypes.c_int()
     ctx.check(lib().rayleigh_ritz(ctx.h, w, m, _p(G.contiguous()), tau, _p(C), _p(theta), ctypes.byref(kept)))
     return theta, C, kept.value
@@ -495,8 +513,8 @@ class RowTiles:
                 raise TypeError("precision 2 takes a float16 block")
             h_only = True
         if out is None:
-            HY = torch.empty_like(Y, dtype=torch.float32) if precision == 2 else torch.empty_like(Y)
-            MY = None if h_only else torch.empty_like(Y)
+            HY = _out(Y.shape, torch.float32 if precision == 2 else Y.dtype, Y.device)
+            MY = None if h_only else _out(Y.shape, Y.dtype, Y.device)
         else:
             HY, MY = out
             if h_only:
@@ -546,8 +564,8 @@ class SymCSR:
             raise FFError(FF_ERR_INVALID_ARG, f"Y must be [{self.n}][m] {dt} with unit column stride")
         want_m = self.has_m and not h_only
         if out is None:
-            HY = torch.empty(Y.shape, dtype=dt, device=Y.device)
-            MY = torch.empty(Y.shape, dtype=dt, device=Y.device) if want_m else None
+            HY = _out(Y.shape, dt, Y.device)
+            MY = _out(Y.shape, dt, Y.device) if want_m else None
         else:
             HY, MY = out
             MY = MY if want_m else None
@@ -592,8 +610,8 @@ class MatFree:
             raise FFError(FF_ERR_INVALID_ARG, f"Y must be [{self.n}][m] {dt} with unit column stride")
         k = Y.shape[1]
         if out is None:
-            HY = torch.empty((self.n, k), dtype=dt, device=Y.device) if h else None
-            MY = torch.empty((self.n, k), dtype=dt, device=Y.device) if m else None
+            HY = _out((self.n, k), dt, Y.device) if h else None
+            MY = _out((self.n, k), dt, Y.device) if m else None
         else:
             HY, MY = out
         ld = (HY if HY is not None else MY).stride(0)
@@ -606,7 +624,7 @@ class MatFree:
         dt = torch.float32 if self.precision else torch.float64
         if Y.dtype != dt or Y.shape[0] != self.n or Y.stride(1) != 1:
             raise FFError(FF_ERR_INVALID_ARG, f"Y must be [{self.n}][m] {dt} with unit column stride")
-        U = torch.empty((self.q, Y.shape[1]), dtype=dt, device=Y.device)
+        U = _out((self.q, Y.shape[1]), dt, Y.device)
         self.ctx.check(lib().mf_interpolate(self.ctx.h, self.h, Y.shape[1], _p(Y), Y.stride(0), _p(U), U.stride(0)))
         return U
 
@@ -635,7 +653,7 @@ def spmm_variant_names():
 
 def rand_block(ctx: Context, n: int, m: int, seed: int, device="cuda"):
     import torch
-    out = torch.empty((n, m), dtype=torch.float64, device=device)
+    out = _out((n, m), torch.float64, device)
     ctx.check(lib().rand_block(ctx.h, n, m, seed, _p(out)))
     return out
 
@@ -643,7 +661,7 @@ def rand_block(ctx: Context, n: int, m: int, seed: int, device="cuda"):
 def philox4x32_10(ctx: Context, ctr, key):
     """ctr: uint32 tensor (count, 4), key: (count, 2) on the device; returns (count, 4)."""
     import torch
-    out = torch.empty_like(ctr)
+    out = _out(ctr.shape, ctr.dtype, ctr.device)
     ctx.check(lib().philox4x32_10(ctx.h, ctr.shape[0], _p(ctr), _p(key), _p(out)))
     return out
 
@@ -723,14 +741,14 @@ class MLP:
 def mlp_inputs(ctx: Context, xyz_sorted, feat, n_freq: int = 0):
     import torch
     n = xyz_sorted.shape[0]
-    out = torch.empty((n, 11 + 6 * n_freq), dtype=torch.float32, device=xyz_sorted.device)
+    out = _out((n, 11 + 6 * n_freq), torch.float32, xyz_sorted.device)
     ctx.check(lib().mlp_inputs(ctx.h, n, _p(xyz_sorted), _p(feat), n_freq, _p(out)))
     return out
 
 
 def lumped_mass(ctx: Context, n: int, row_ptr, M):
     import torch
-    d = torch.empty(n, dtype=torch.float64, device=M.device)
+    d = _out(n, torch.float64, M.device)
     ctx.check(lib().lumped_mass(ctx.h, n, _p(row_ptr), _p(M), _p(d)))
     return d
 

@@ -7,6 +7,10 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+# every output buffer the binding allocates starts as NaN / -1, so that an element the library does
+# not write fails its test instead of passing on what an earlier call left in the same memory
+os.environ.setdefault("FF_POISON_OUTPUTS", "1")
+
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
