@@ -1,15 +1,15 @@
 """Reference eigenvalues of the named workloads, computed by the FP64 oracle alone.
 
     python tests/golden/make_reference_eigs.py spheres100k 32
-    python tests/golden/make_reference_eigs.py ellipsoids1m 32 --tol 1e-10
+    python tests/golden/make_reference_eigs.py ellipsoids1m 32 --tol 5e-8 --guard 16 --kc 36
 
 Builds the seeded workload (``synth.workload``), runs the oracle's whole
 pipeline (binning, neighbours, RKPM shape functions of Sec. 3.2 Eq. (7)-(11),
 the Hessian of Prop. 1 and the mass matrix of Eq. (14)), then the oracle's FP64
 block LOBPCG for the generalized eigenproblem of Eq. (15) with its
-Chebyshev-Jacobi preconditioner, from a seeded random start, with k + 8
-columns of which the first k + 4 must reach the backward-error residual
-``tol`` (those k + 4 are kept). The result file ``ref_eigs_<workload>_k<k>.json`` next to this script
+Chebyshev-Jacobi preconditioner, from a seeded random start, with k + guard
+columns (``--guard``, default 8) of which the first k + guard / 2 (or ``--kc``) must reach the
+backward-error residual ``tol``. The result file ``ref_eigs_<workload>_k<k>.json`` next to this script
 holds the input's SHA-256 (so a test can tell that it checks the same object),
 the eigenvalues and residuals of every column, the iteration count and the
 host threads used. Nothing here reads a GPU result.
@@ -36,6 +36,8 @@ def main(argv=None):
     ap.add_argument("--guard", type=int, default=8)
     ap.add_argument("--seed", type=int, default=7)
     ap.add_argument("--maxiter", type=int, default=3000)
+    ap.add_argument("--kc", type=int, default=None,
+                    help="columns that must reach tol (default k + guard / 2)")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
 
@@ -49,7 +51,8 @@ def main(argv=None):
     t_build = time.time() - t0
     H, M = P.Hs(), P.Ms()
     m = a.k + a.guard
-    kc = a.k + a.guard // 2
+    kc = a.kc if a.kc is not None else a.k + a.guard // 2
+    assert a.k <= kc <= m
     X0 = synth.initial_block(cloud.n, m, seed=a.seed)
     t1 = time.time()
     lam, W, it, res = O.lobpcg(H, M, X0, k=kc, tol=a.tol, maxiter=a.maxiter, precond="chebyshev", verbose=10)

@@ -8,7 +8,7 @@ until every wanted pair's estimate is at most eig_tol (and with angle_tol every
 angle estimate at most angle_tol). Checked here against the plain definition
 (dense LAPACK eigh) on small clouds, pair by pair, with subspace angles, and at
 full size against the oracle's reference eigenvalues (the oracle's FP64 LOBPCG
-to a backward-error residual of 1e-10 at 10^5 particles and 1e-8 at 10^6, where
+to a backward-error residual of 1e-10 at 10^5 particles and 5e-8 at 10^6, where
 its eigenvalue error is orders of magnitude below the tolerance checked, stored
 with the input's SHA-256 by tests/golden/make_reference_eigs.py): relative
 eigenvalue error at most 1e-5, the tolerance of the mixed path.
@@ -141,7 +141,7 @@ def test_fullsize_eigenvalues_against_reference(oracle, ctx, ff, name):
     print(f"\n[golden] {name}: cloud in {time.time() - t0:.1f} s", flush=True)
     A = ff.assemble_cloud(ctx, dev(c.xyz), dev(c.vol), dev(c.lam), dev(c.mu), c.h)
     lr = np.array(ref["eigenvalues"][:32])
-    assert max(ref["residuals"][:32]) <= 1e-8
+    assert max(ref["residuals"][:32]) <= ref["tol"] <= 1e-7
     out = {}
     for eig_tol in (0.0, 1e-5):
         torch.cuda.synchronize()
