@@ -89,6 +89,20 @@ def test_chebyshev_apply_matches_the_recurrence(cloud, oracle, ctx, ff, degree, 
     assert share >= 2 * TOL[values]
 
 
+@pytest.mark.parametrize("values", [1, 3, 4])
+def test_chebyshev_apply_block64(cloud, oracle, ctx, ff, values):
+    """Block width 64 (the matrix-core steps' other width: two tiles per workgroup from the
+    zero-free K-blocks, with values 4), degree 12."""
+    c, P, A, upper = cloud
+    R = np.random.default_rng(64 + values).standard_normal((c.n, 64)).astype(np.float32).astype(np.float64)
+    Z, b = ff.chebyshev_apply(ctx, c.n, A.row_ptr, A.col, A.H, A.M, A.hm32, dev(R, torch.float32), degree=12,
+                              values=values, upper=upper)
+    ref, share = _scaled_reference(oracle, P, R, 12, upper, values)
+    err = np.linalg.norm(host(Z).astype(np.float64) - ref, axis=0) / np.linalg.norm(ref, axis=0)
+    assert err.max() <= TOL[values], err.max()
+    assert share >= 2 * TOL[values]
+
+
 def test_chebyshev_interval_estimate(cloud, oracle, ctx, ff):
     """With upper = 0 the library takes min(1.1 x the Rayleigh quotient after 30 power steps,
     the Gershgorin bound): at least the top of D^-1 H's spectrum (the oracle's ARPACK value)
