@@ -1772,7 +1772,8 @@ constexpr int kChebT8Sub = 1;                  // launch shape of the fused step
                                                // H-only product's default with the step's operands live)
 // launch shape of the matrix-core Chebyshev step, the super-block pipelined kernel; the product alone
 // at 10^6 particles, m = 32 / 64: full K-blocks with eight / four waves per workgroup 0.561 / 0.796 ms,
-// zero-free K-blocks with four / two waves 0.514 / 0.791 ms
+// zero-free K-blocks with four / two waves 0.510 / 0.781 ms (at six waves per SIMD, 80 registers,
+// the four-wave form spilled and took 0.618 ms at m = 32)
 inline int cheb_tq_sub(int m, bool packed) {
     return packed ? (m == 32 ? rt::kTqPacked + 1 : rt::kTqPacked + 4) : (m == 32 ? 5 : 6);
 }

@@ -1710,8 +1710,8 @@ spmm_tq_sb_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int3
     constexpr int kQ = 4;                          // K-blocks per super-block
     static_assert(kQ == kTqPackGroup, "the zero-free copy aligns groups of four K-blocks");
     __shared__ __align__(16) unsigned char ys[kWaves][kQ][16 * kStride];
+    // the super-block's staged values, rebuilt in place into its four dense K-blocks (4 x 256 bytes)
     __shared__ __align__(16) unsigned char pvs[kWaves][kPacked ? kPkStage : 16];
-    __shared__ __align__(16) unsigned char pds[kWaves][kPacked ? kQ : 1][kPacked ? 256 : 16];
     const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t t = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kWaves + wv;
     if (t >= ntiles) return;
@@ -1803,11 +1803,12 @@ spmm_tq_sb_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int3
         __builtin_amdgcn_wave_barrier();
         f16x4 bp[kQ];
         if constexpr (kPacked) {
-            // expand the four K-blocks into LDS, lane j writing entries j (rows 0-3) and 64 + j
+            // expand the four K-blocks in place, lane j taking entries j (rows 0-3) and 64 + j
             // (rows 4-7) of each: present when its mask bit is set, then the value at the count of
-            // present entries before it
-            const uint16_t *ps = (const uint16_t *)&pvs[wv][0];
-            uint16_t *pd = (uint16_t *)&pds[wv][0][0];
+            // present entries before it. Every value is read before any is written (a wave's LDS
+            // instructions execute in order), so the dense blocks can overwrite the staged values.
+            uint16_t *ps = (uint16_t *)&pvs[wv][0];
+            uint16_t v0[kQ], v1[kQ];
             int base = 0;                                              // halves before K-block q
 #pragma unroll
             for (int q = 0; q < kQ; ++q) {
@@ -1815,10 +1816,15 @@ spmm_tq_sb_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int3
                 const int nlo = __popcll(lo);
                 const int ilo = __builtin_amdgcn_mbcnt_hi((uint32_t)(lo >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)lo, 0));
                 const int ihi = __builtin_amdgcn_mbcnt_hi((uint32_t)(hi >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)hi, 0));
-                const uint16_t v0 = ps[base + ilo], v1 = ps[base + nlo + ihi];
-                pd[q * 128 + lane] = __builtin_amdgcn_inverse_ballot_w64(lo) ? v0 : (uint16_t)0;
-                pd[q * 128 + 64 + lane] = __builtin_amdgcn_inverse_ballot_w64(hi) ? v1 : (uint16_t)0;
+                v0[q] = ps[base + ilo];
+                v1[q] = ps[base + nlo + ihi];
                 base += nlo + __popcll(hi);
+            }
+            uint16_t *pd = ps;
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) {
+                pd[q * 128 + lane] = __builtin_amdgcn_inverse_ballot_w64(pk.lo[q]) ? v0[q] : (uint16_t)0;
+                pd[q * 128 + 64 + lane] = __builtin_amdgcn_inverse_ballot_w64(pk.hi[q]) ? v1[q] : (uint16_t)0;
             }
             __builtin_amdgcn_wave_barrier();
 #pragma unroll
