@@ -1547,6 +1547,43 @@ int build_tq_pack_ws(ff_ctx *ctx, hipStream_t st, RTQView *v) {
 
 bool tq_ok(int m) { return m == 32 || m == 64; }
 
+// The Chebyshev step of the binary16 matrix-core products on one lane's columns 16 cb + 4 quad .. + 3
+// of row rme, acc holding (H dz) / vscale there: r -= D^-1 H dz, dz' = f1 dz + f2 r (stored in binary16,
+// clamped to its range), w += dz' (wmode 1) or w += dz + dz' (wmode 2, two steps' iterates at once).
+// FP32 arithmetic with fused multiply-adds: the iterate is rounded to binary16 (2^-11) at every step,
+// far above the FP32 rounding of these few operations.
+template <int kMB>
+__device__ __forceinline__ void cheb_q_epilogue(const ChebStepQ &cs, const f32x4 (&acc)[kMB], const _Float16 *Y,
+                                                int64_t rme, int quad, float vscale, int o) {
+    constexpr int m = 16 * kMB;
+    const float f1 = (float)cs.coef[(size_t)o * cs.stride + 2 * cs.step - 1];
+    const float f2 = (float)cs.coef[(size_t)o * cs.stride + 2 * cs.step];
+    const float dv = cs.dinv[rme] * vscale;
+    _Float16 *dzo = (_Float16 *)cs.dz_out;
+#pragma unroll
+    for (int cb = 0; cb < kMB; ++cb) {
+        const int c0 = 16 * cb + 4 * quad;
+        float *rp = cs.R + rme * m + c0, *wp = cs.W + rme * cs.ldw + c0;
+        const f32x4 er = *(const f32x4 *)rp;
+        const f32x4 ew = cs.wmode ? *(const f32x4 *)wp : f32x4{0.f, 0.f, 0.f, 0.f};
+        const f16x4 ez = *(const f16x4 *)(Y + rme * m + c0);
+        f32x4 rv1, w1;
+        f16x4 dz1;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float rv = __builtin_fmaf(-dv, acc[cb][q], er[q]);
+            float dz = __builtin_fmaf(f1, (float)ez[q], f2 * rv);
+            dz = dz > 65504.f ? 65504.f : (dz < -65504.f ? -65504.f : dz);   // binary16 range
+            rv1[q] = rv;
+            dz1[q] = (_Float16)dz;
+            w1[q] = cs.wmode == 2 ? (ew[q] + (float)ez[q]) + (float)dz1[q] : ew[q] + (float)dz1[q];
+        }
+        *(f32x4 *)rp = rv1;
+        *(f16x4 *)(dzo + rme * m + c0) = dz1;
+        if (cs.wmode) *(f32x4 *)wp = w1;
+    }
+}
+
 template <int kMB, bool kEpi, int kWaves, int kOcc, int kD>
 __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(kOcc, 8)))
 spmm_tq_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int32_t *tcol, const int64_t *kptr,
@@ -1634,34 +1671,7 @@ spmm_tq_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int32_t
     }
     if (!mine) return;
     if (kEpi) {
-        const int o = row_obj[rme];
-        const double f1 = cs.coef[(size_t)o * cs.stride + 2 * cs.step - 1];
-        const double f2 = cs.coef[(size_t)o * cs.stride + 2 * cs.step];
-        const double dv = (double)cs.dinv[rme] * (double)vscale;
-        _Float16 *dzo = (_Float16 *)cs.dz_out;
-#pragma unroll
-        for (int cb = 0; cb < kMB; ++cb) {
-            const int c0 = 16 * cb + 4 * quad;
-            float *rp = cs.R + rme * m + c0, *wp = cs.W + rme * cs.ldw + c0;
-            const f32x4 er = *(const f32x4 *)rp;
-            const f32x4 ew = cs.wmode ? *(const f32x4 *)wp : f32x4{0.f, 0.f, 0.f, 0.f};
-            const f16x4 ez = *(const f16x4 *)(Y + rme * m + c0);
-            f32x4 rv1, w1;
-            f16x4 dz1;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const double rv = (double)er[q] - dv * (double)acc[cb][q];
-                double dz = f1 * (double)(float)ez[q] + f2 * rv;
-                dz = dz > 65504.0 ? 65504.0 : (dz < -65504.0 ? -65504.0 : dz);   // binary16 range
-                rv1[q] = (float)rv;
-                dz1[q] = (_Float16)(float)dz;
-                w1[q] = cs.wmode == 2 ? (float)(((double)ew[q] + (double)(float)ez[q]) + (double)(float)dz1[q])
-                                      : (float)((double)ew[q] + (double)(float)dz1[q]);
-            }
-            *(f32x4 *)rp = rv1;
-            *(f16x4 *)(dzo + rme * m + c0) = dz1;
-            if (cs.wmode) *(f32x4 *)wp = w1;
-        }
+        cheb_q_epilogue<kMB>(cs, acc, Y, rme, quad, vscale, row_obj[rme]);
     } else {
 #pragma unroll
         for (int cb = 0; cb < kMB; ++cb)
@@ -1873,34 +1883,7 @@ spmm_tq_sb_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int3
     }
     if (!mine) return;
     if (kEpi) {
-        const int o = row_obj[rme];
-        const double f1 = cs.coef[(size_t)o * cs.stride + 2 * cs.step - 1];
-        const double f2 = cs.coef[(size_t)o * cs.stride + 2 * cs.step];
-        const double dv = (double)cs.dinv[rme] * (double)vscale;
-        _Float16 *dzo = (_Float16 *)cs.dz_out;
-#pragma unroll
-        for (int cb = 0; cb < kMB; ++cb) {
-            const int c0 = 16 * cb + 4 * quad;
-            float *rp = cs.R + rme * m + c0, *wp = cs.W + rme * cs.ldw + c0;
-            const f32x4 er = *(const f32x4 *)rp;
-            const f32x4 ew = cs.wmode ? *(const f32x4 *)wp : f32x4{0.f, 0.f, 0.f, 0.f};
-            const f16x4 ez = *(const f16x4 *)(Y + rme * m + c0);
-            f32x4 rv1, w1;
-            f16x4 dz1;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const double rv = (double)er[q] - dv * (double)acc[cb][q];
-                double dz = f1 * (double)(float)ez[q] + f2 * rv;
-                dz = dz > 65504.0 ? 65504.0 : (dz < -65504.0 ? -65504.0 : dz);   // binary16 range
-                rv1[q] = (float)rv;
-                dz1[q] = (_Float16)(float)dz;
-                w1[q] = cs.wmode == 2 ? (float)(((double)ew[q] + (double)(float)ez[q]) + (double)(float)dz1[q])
-                                      : (float)((double)ew[q] + (double)(float)dz1[q]);
-            }
-            *(f32x4 *)rp = rv1;
-            *(f16x4 *)(dzo + rme * m + c0) = dz1;
-            if (cs.wmode) *(f32x4 *)wp = w1;
-        }
+        cheb_q_epilogue<kMB>(cs, acc, Y, rme, quad, vscale, row_obj[rme]);
     } else {
 #pragma unroll
         for (int cb = 0; cb < kMB; ++cb)
