@@ -54,7 +54,10 @@ typedef enum {
  * FF_UNION_BITS=n caps the LDS bitmap of the row-tile copy build at n words
  * and FF_ASM_BITMAP_BYTES=n caps the row bitmaps assemble_HM keeps between
  * its passes at n bytes, so that the other paths of both can be exercised
- * (the results are the same either way). */
+ * (the results are the same either way); FF_CHEB_SHAPE=n runs the matrix-core
+ * Chebyshev steps in launch shape n of spmm_rowtiles precision 2 (8 .. 12 with
+ * the zero-free K-blocks, the default, 0 .. 7 with the full ones), for tuning:
+ * every shape gives the same sums bit for bit. */
 int ff_ctx_create(ff_ctx **ctx, int device, void *hip_stream);
 void ff_ctx_destroy(ff_ctx *ctx);
 const char *ff_last_error(const ff_ctx *ctx);

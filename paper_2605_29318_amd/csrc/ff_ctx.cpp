@@ -131,6 +131,8 @@ int ff_ctx_create(ff_ctx **out, int device, void *hip_stream) {
     // a cap on the row bitmaps the assembly's symbolic pass keeps, so that the numeric pass's own
     // marking can be exercised
     if (const char *b = getenv("FF_ASM_BITMAP_BYTES")) ctx->asm_bm_cap = atoll(b) < 0 ? 0 : atoll(b);
+    // the launch shape of the matrix-core Chebyshev steps, for tuning (every shape sums alike)
+    if (const char *b = getenv("FF_CHEB_SHAPE")) ctx->cheb_shape = atoi(b) < 0 ? -1 : atoi(b);
     // the fixed scratch of rayleigh_ritz_noalloc: its device address, once per device
     if (ff::lob::noalloc_setup(ctx) != FF_OK) {
         delete ctx;

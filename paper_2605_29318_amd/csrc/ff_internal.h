@@ -75,6 +75,7 @@ struct ff_ctx {
     int asm_wwords = 0;              // largest row window of that call, in bitmap words
     bool asm_bm = false;             // the sizing call kept its row bitmaps (workspace slot WS_ASM_BM)
     int64_t asm_bm_cap = -1;         // FF_ASM_BITMAP_BYTES: cap on that store (-1: the built-in 8 GiB)
+    int cheb_shape = -1;             // FF_CHEB_SHAPE: launch shape of the matrix-core Chebyshev steps (-1: default)
     hipStream_t graph_stream = nullptr;   // private stream for graph capture
     // a-posteriori bounds of the last eigensolve, [n_obj][k] each
     int eb_nobj = 0, eb_k = 0;

@@ -2862,6 +2862,12 @@ int solve(ff_ctx *ctx, int n_obj, const int64_t *obj_off, const int64_t *row_ptr
                 const bool packed = p->precond_values == 4 || (p->precond_values == 0 && kChebPackedDefault);
                 if (!rc && packed) rc = rt::build_tq_pack_ws(ctx, s.st, &s.rtq);
                 s.tq_sub = cheb_tq_sub(s.m, packed);
+                if (ctx->cheb_shape >= 0) {
+                    FF_REQUIRE(ctx, ctx->cheb_shape < rt::kTqSubs && (ctx->cheb_shape >= rt::kTqPacked) == packed,
+                               "FF_CHEB_SHAPE=%d is not a launch shape of the %s K-blocks", ctx->cheb_shape,
+                               packed ? "zero-free" : "full");
+                    s.tq_sub = ctx->cheb_shape;
+                }
                 // the power steps of the interval estimate (eight columns) read the binary16 copy too
                 if (!rc) rc = rt::build_t8_half(ctx, s.st, &s.rt8);
                 s.wpart = (float *)ws_get(ctx, WS_CHEBQ, ((size_t)s.ng + s.n_obj) * s.m * sizeof(float));
