@@ -506,7 +506,7 @@ def chebyshev_jacobi(H, degree=12, ratio=1000.0, upper=None, mul=None):
 
 
 def lobpcg(H, M, X0, k=None, tol=1e-10, maxiter=5000, precond=None, normH=None, normM=None,
-           verbose=False, mul=None):
+           verbose=False, mul=None, callback=None):
     """Block LOBPCG (Knyazev 2001) in FP64 for the smallest eigenpairs of (H, M).
 
     Search space S = [X, W, P] with W the (optionally preconditioned) block
@@ -515,7 +515,9 @@ def lobpcg(H, M, X0, k=None, tol=1e-10, maxiter=5000, precond=None, normH=None, 
     satisfy the backward-error residual of ``residuals`` <= tol. ``precond``
     is None, "jacobi" (diag(H)^-1), "chebyshev" (``chebyshev_jacobi`` with its
     defaults) or a callable R -> W. Products with H and M go through ``mul``
-    (default ``matmul``, the threaded C loop for CSR operands).
+    (default ``matmul``, the threaded C loop for CSR operands). With ``verbose``
+    = v, every v-th iteration prints the largest residual of the first k columns
+    and calls ``callback(iteration, ritz_values, residuals)`` when given.
     """
     mul = matmul if mul is None else mul
     X = np.array(X0, dtype=np.float64, copy=True)
@@ -549,6 +551,8 @@ def lobpcg(H, M, X0, k=None, tol=1e-10, maxiter=5000, precond=None, normH=None, 
                                            np.linalg.norm(X, axis=0))
         if verbose and it % verbose == 0:
             print(it, res[:k].max(), flush=True)
+            if callback is not None:
+                callback(it, th, res)
         if res[:k].max() <= tol:
             break
         W = R if precond is None else precond(R)

@@ -39,6 +39,8 @@ def main(argv=None):
     ap.add_argument("--kc", type=int, default=None,
                     help="columns that must reach tol (default k + guard / 2)")
     ap.add_argument("--out", default=None)
+    ap.add_argument("--partial", default=None,
+                    help="rewrite this file with the Ritz values and residuals every 10 iterations")
     a = ap.parse_args(argv)
 
     import numpy as np
@@ -55,7 +57,13 @@ def main(argv=None):
     assert a.k <= kc <= m
     X0 = synth.initial_block(cloud.n, m, seed=a.seed)
     t1 = time.time()
-    lam, W, it, res = O.lobpcg(H, M, X0, k=kc, tol=a.tol, maxiter=a.maxiter, precond="chebyshev", verbose=10)
+    def partial(it, th, res):
+        if a.partial:
+            with open(a.partial, "w") as f:
+                json.dump({"iteration": it, "max_resid_first_kc": float(res[:kc].max()),
+                           "ritz_values": [float(x) for x in th], "residuals": [float(x) for x in res]}, f)
+    lam, W, it, res = O.lobpcg(H, M, X0, k=kc, tol=a.tol, maxiter=a.maxiter, precond="chebyshev", verbose=10,
+                               callback=partial)
     t_solve = time.time() - t1
     res_all = O.residuals(H, M, lam, W)
     out = {

@@ -130,7 +130,15 @@ def test_eig_tol_validated(small, ctx, ff):
 def test_fullsize_eigenvalues_against_reference(oracle, ctx, ff, name):
     """The workloads at full size, k = 32, mixed path with FP64 refinement to eig_tol = 1e-5:
     every eigenvalue within 1e-5 relative of the oracle's reference (and the constant mode's
-    within 1e-5 of lambda_2); the plain residual-1e-6 answer's error is printed beside it."""
+    within 1e-5 of lambda_2); the plain residual-1e-6 answer's error is printed beside it.
+
+    The reference values are Ritz values of the oracle's solve, so they lie above the exact
+    eigenvalues by an amount that falls with the square of its residual. A reference solved to
+    a residual above 2e-8 is not accurate to 1e-5 (at 10^6 particles, residual 5e-8, it lies
+    0.5e-5 to 3.9e-5 above the refined answer on every pair, whose FP64 Ritz values cannot lie
+    below the exact eigenvalues by more than rounding either); against such a reference
+    only the side that its excess cannot hide is checked: each refined eigenvalue at most 1e-5
+    above the reference."""
     path = os.path.join(GOLDEN, f"ref_eigs_{name}_k32.json")
     if not os.path.exists(path):
         pytest.skip(f"no reference eigenvalues for {name}")
@@ -157,7 +165,13 @@ def test_fullsize_eigenvalues_against_reference(oracle, ctx, ff, name):
         assert info["converged"] == 1 and res.max() <= 1e-6
     rel, info = out[1e-5]
     assert info["max_eig_bound"] <= 1e-5
-    assert rel.max() <= 1e-5, rel.max()
+    if ref["tol"] <= 2e-8:
+        assert rel.max() <= 1e-5, rel.max()
+    else:
+        above = (lam[1:] - lr[1:]) / lr[1:]
+        print(f"[golden] {name}: reference residual {ref['tol']:g}; refined answer from {above.min():+.2e} to "
+              f"{above.max():+.2e} relative to it", flush=True)
+        assert above.max() <= 1e-5, above.max()
     assert abs(lam[0]) <= 1e-5 * lr[1]
     # the estimate covers the measured error of the unrefined answer too
     rel0, info0 = out[0.0]
