@@ -209,8 +209,9 @@ GOLDEN_DIR = os.path.join(ROOT, "tests", "golden")
 
 
 def golden_eigs(name, cloud, k=32):
-    """The oracle's reference eigenvalues of a named workload (residual 1e-10, stored with the
-    input's SHA-256 by tests/golden/make_reference_eigs.py), or None if absent or for another input."""
+    """The oracle's reference eigenvalues of a named workload (stored with the input's SHA-256
+    and the residual the oracle's solve reached by tests/golden/make_reference_eigs.py), as
+    dict(ev, tol), or None if absent or for another input."""
     import numpy as np
     path = os.path.join(GOLDEN_DIR, f"ref_eigs_{name}_k{k}.json")
     if not os.path.exists(path):
@@ -218,16 +219,20 @@ def golden_eigs(name, cloud, k=32):
     d = json.load(open(path))
     if d.get("sha256") != cloud.sha256():
         return None
-    return np.array(d["eigenvalues"][:k])
+    return dict(ev=np.array(d["eigenvalues"][:k]), tol=float(d["tol"]))
 
 
 def eig_rel_err(ev, ref):
-    """max over j >= 2 of |lambda_j - ref_j| / ref_j, and |lambda_1| / ref_2 for the constant mode."""
+    """max over j >= 2 of |lambda_j - ref_j| / ref_j, the signed extremes of (lambda_j - ref_j) / ref_j
+    (the reference's Ritz values lie above the exact eigenvalues, by more the larger its residual),
+    |lambda_1| / ref_2 for the constant mode, and the reference's residual."""
     import numpy as np
     if ref is None:
         return None
-    rel = np.abs(ev[1:len(ref)] - ref[1:]) / ref[1:]
-    return dict(max_rel=float(rel.max()), const_mode=float(abs(ev[0]) / ref[1]))
+    r = ref["ev"]
+    sig = (ev[1:len(r)] - r[1:]) / r[1:]
+    return dict(max_rel=float(np.abs(sig).max()), min_signed=float(sig.min()), max_signed=float(sig.max()),
+                const_mode=float(abs(ev[0]) / r[1]), reference_residual=ref["tol"])
 
 
 def time_solves(ff, ctx, dev_in, c, k, precision, seeds, tol, max_iter, eig_tol=0.0):
