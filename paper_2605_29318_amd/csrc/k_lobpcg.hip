@@ -1972,16 +1972,19 @@ static const char *kVariantNames[] = {"waves4_unroll2_xcd", "waves4_unroll4_xcd"
                                       "rowtile8_mfma32x64_waves4_batch8", "rowtile8_mfma32x64_waves2_batch8",
                                       "rowtile8_mfma64_pipelined_waves4", "rowtile8_mfma32x64_pipelined_waves4",
                                       "rowtile8_mfma64_pipelined_waves2", "rowtile8_mfma64_zerofree_waves2",
-                                      "rowtile8_mfma64_zerofree_waves4"};
-constexpr int kNumVariants = 26;
-constexpr int kZeroFreeBase = 24;              // from here on: the zero-free eight-row copy
+                                      "rowtile8_mfma64_zerofree_waves4", "rowtile8_mfma32c4_pipelined_waves2"};
+constexpr int kNumVariants = 27;
+constexpr int kZeroFreeBase = 24;              // this one and the next read the zero-free eight-row copy
+inline bool zero_free_variant(int v) { return v == kZeroFreeBase || v == kZeroFreeBase + 1; }
 constexpr int kRowTileBase = 13;               // variants from here on run on a row-tile copy
 constexpr int kRowTile8Base = 16;              // from here on: the eight-row [H, M] copy on MFMA (FP32 blocks)
 constexpr int kCsrVariant = 11;                // fastest variant on the CSR itself
 constexpr int kDefaultVariant64 = 14;  // fastest untuned FP64 choice on 10^5-10^6-row RKPM matrices (row tiles)
 constexpr int kDefaultVariant32 = 16;  // fastest untuned FP32 choice (eight-row tiles, MFMA)
-constexpr int kDefaultVariant32m32 = 23;  // at m = 32: the pipelined kernel, two waves per workgroup (1.72 ms
-                                          // against 1.85-1.89 ms for the others at 10^6 rows)
+constexpr int kDefaultVariant32m32 = 26;  // at m = 32: the pipelined kernel on the FP32 matrix cores, four
+                                          // steps chained before each FP64 addition, two waves per workgroup
+                                          // (1.65 ms against 1.72 ms on the FP64 matrix cores and 1.75-1.93
+                                          // ms for the others at 10^6 rows)
 constexpr int kDefaultVariant32m64 = 17;  // at m = 64: two waves per workgroup (3.07 against 3.16 ms)
 
 inline int rt_spmm(ff_ctx *ctx, hipStream_t st, const rt::RTView &v, int sub, int m, const float *Y, int64_t ldy,
@@ -2837,7 +2840,7 @@ int solve(ff_ctx *ctx, int n_obj, const int64_t *obj_off, const int64_t *row_ptr
         if (p->precision == 1 && s.var32 >= kRowTile8Base) {
             // one eight-row copy with H and M serves the fused products and the preconditioner
             int rc0 = rt::build_t8_ws(ctx, s.st, s.N, row_ptr, col, H, &s.rt8, M);
-            if (!rc0 && s.var32 >= kZeroFreeBase) rc0 = rt::build_t8z_ws(ctx, s.st, &s.rt8);
+            if (!rc0 && zero_free_variant(s.var32)) rc0 = rt::build_t8z_ws(ctx, s.st, &s.rt8);
             if (rc0) return rc0;
         }
     }
@@ -3112,7 +3115,7 @@ extern "C" int spmm_hm(ff_ctx *ctx, int64_t n, const int64_t *row_ptr, const int
         FF_REQUIRE(ctx, H && M, "row-tile variants need H and M");
         FF_REQUIRE(ctx, rt::hm8_ok(m, ld_y, ld_out), "variant %d takes m in {4, 8, 12, 16, 32, 64}, m = %d", v, m);
         int rc = rt::build_t8_ws(ctx, ctx->stream, n, row_ptr, col, H, &view8, M);
-        if (!rc && v >= kZeroFreeBase) rc = rt::build_t8z_ws(ctx, ctx->stream, &view8);
+        if (!rc && zero_free_variant(v)) rc = rt::build_t8z_ws(ctx, ctx->stream, &view8);
         if (rc) return rc;
     } else if (v >= kRowTileBase) {
         FF_REQUIRE(ctx, H && M, "row-tile variants need H and M");

@@ -168,8 +168,9 @@ int cheb_step_t16(ff_ctx *ctx, hipStream_t st, const RT16View &v, int sub, int m
 
 // [HY, MY] = [H, M] Y (FP32 blocks, FP64 accumulation on FP64 MFMA) on an
 // eight-row copy built with M; m in {4, 8, 12, 16, 32, 64}; sub 0 .. kHm8Subs - 1 (3, 4 and 6 take
-// four-entry steps on the FP32 matrix cores, each added in FP64; 5, 6 and 7 pipeline the loads).
-constexpr int kHm8Subs = 10;
+// four-entry steps on the FP32 matrix cores, each added in FP64; 5, 6 and 7 pipeline the loads; 8 and 9
+// read the zero-free copy; 10 chains four FP32 steps before each FP64 addition).
+constexpr int kHm8Subs = 11;
 bool hm8_ok(int m, int64_t ldy, int64_t ldo);
 // builds the zero-free copy of a built eight-row [H, M] copy into workspace slots
 int build_t8z_ws(ff_ctx *ctx, hipStream_t st, RT8View *v);

@@ -2320,7 +2320,10 @@ spmm_hm8_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int32_
 //   chunk c: stage values(c) in LDS; gather batch 2c+1; multiply batch 2c; gather batch 2c+2
 //   (columns of chunk c+1); load columns and values of chunk c+2; multiply batch 2c+1.
 // The MFMA sequence (entries in order, one accumulator per column group) is that of the kernel above.
-template <int kMT, int kWaves, int kOcc, bool kF32>
+// With kF32 and kChain > 1 the FP32 matrix-core steps accumulate kChain four-entry steps in FP32 before
+// each FP64 addition (a bound of about 4 kChain units of FP32 rounding of the summed magnitudes, the
+// order of the rounding of the FP32 values themselves), which divides the FP64 additions by kChain.
+template <int kMT, int kWaves, int kOcc, bool kF32, int kChain = 1>
 __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(kOcc, 8)))
 spmm_hm8p_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int32_t *tcol, const float *vh,
                  const float *vm, const float *Y, int64_t ldy, float *HY, float *MY, int64_t ldo, int m,
@@ -2388,11 +2391,19 @@ spmm_hm8p_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int32
     };
     // the quads below nq (all of them when full)
     auto multiply = [&](const YV (&y)[kB], int h, int nq, bool full) __attribute__((always_inline)) {
+        f32x4 pc[kMT];                             // the FP32 chain (kChain > 1)
+#pragma unroll
+        for (int tt = 0; tt < kMT; ++tt) pc[tt] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int u = 0; u < kB; ++u) {
             if (full || kB * h + u < nq) {
                 const int e = 4 * (kB * h + u) + lk;
-                if (kF32) {
+                if (kF32 && kChain > 1) {
+                    const float a = sv[e * 16 + li];
+#pragma unroll
+                    for (int tt = 0; tt < kMT; ++tt)
+                        pc[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, yget(y[u], tt), pc[tt], 0, 0, 0);
+                } else if (kF32) {
                     const float a = sv[e * 16 + li];
 #pragma unroll
                     for (int tt = 0; tt < kMT; ++tt) {
@@ -2405,6 +2416,14 @@ spmm_hm8p_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int32
                     const double a = (double)sv[e * 16 + li];
 #pragma unroll
                     for (int tt = 0; tt < kMT; ++tt) d[tt] = mfma64(a, (double)yget(y[u], tt), d[tt]);
+                }
+            }
+            if (kF32 && kChain > 1 && (u % kChain == kChain - 1 || u == kB - 1)) {
+#pragma unroll
+                for (int tt = 0; tt < kMT; ++tt) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) d[tt][v] += (double)pc[tt][v];
+                    pc[tt] = f32x4{0.f, 0.f, 0.f, 0.f};
                 }
             }
         }
@@ -2712,13 +2731,25 @@ int spmm_hm8(ff_ctx *ctx, hipStream_t st, const RT8View &v, int sub, int m, cons
 #define FF_HM8P(MT, W, O, F)                                                                                  \
     hipLaunchKernelGGL((spmm_hm8p_kernel<MT, W, O, F>), dim3(grid_for(v.ntiles, W)), dim3(64 * W), 0, st, v.n, \
                        v.ntiles, v.tptr, v.tcol, v.vh, v.vm, Y, ldy, HY, MY, ldo, m, row_obj, status)
+#define FF_HM8PC(MT, W, O, C)                                                                                 \
+    hipLaunchKernelGGL((spmm_hm8p_kernel<MT, W, O, true, C>), dim3(grid_for(v.ntiles, W)), dim3(64 * W), 0, st, \
+                       v.n, v.ntiles, v.tptr, v.tcol, v.vh, v.vm, Y, ldy, HY, MY, ldo, m, row_obj, status)
     // sub 0..2: FP64 matrix cores; 3, 4: FP32 matrix cores with FP64 accumulation of each four-entry step;
     // 5, 6: the pipelined kernel on the FP64 and the FP32 matrix cores; 7: the former with two waves per
     // workgroup at m = 32 (as 5 at other widths); 8, 9: the pipelined kernel on the FP64 matrix cores from
     // the zero-free copy, two and four waves per workgroup
+    // 10: the pipelined kernel on the FP32 matrix cores with four four-entry steps chained in FP32 before
+    // each FP64 addition, two waves per workgroup
     FF_REQUIRE(ctx, sub >= 0 && sub < kHm8Subs, "launch shape %d out of range", sub);
     const int mt = m <= 16 ? 1 : m / 16;
-    if (sub >= 8) {
+    if (sub == 10) {
+        if (mt == 1) FF_HM8PC(1, 2, 2, 4);
+        else if (mt == 2) FF_HM8PC(2, 2, 2, 4);
+        else FF_HM8PC(4, 2, 2, 4);
+        FF_CHECK_LAUNCH(ctx);
+        return FF_OK;
+    }
+    if (sub == 8 || sub == 9) {
         FF_REQUIRE(ctx, v.m8 && v.poff && v.pv, "launch shape %d needs the zero-free copy", sub);
 #define FF_HM8Z(MT, W, O)                                                                                        \
     hipLaunchKernelGGL((spmm_hm8z_kernel<MT, W, O>), dim3(grid_for(v.ntiles, W)), dim3(64 * W), 0, st, v.n,       \
@@ -2750,6 +2781,7 @@ int spmm_hm8(ff_ctx *ctx, hipStream_t st, const RT8View &v, int sub, int m, cons
         return FF_OK;
     }
 #undef FF_HM8P
+#undef FF_HM8PC
     const bool f32 = sub >= 3;
     if (mt == 1) {
         if (f32) FF_HM8(1, 4, 8, 4, true); else FF_HM8(1, 4, 8, 4, false);
