@@ -1980,12 +1980,14 @@ constexpr int kRowTileBase = 13;               // variants from here on run on a
 constexpr int kRowTile8Base = 16;              // from here on: the eight-row [H, M] copy on MFMA (FP32 blocks)
 constexpr int kCsrVariant = 11;                // fastest variant on the CSR itself
 constexpr int kDefaultVariant64 = 14;  // fastest untuned FP64 choice on 10^5-10^6-row RKPM matrices (row tiles)
-constexpr int kDefaultVariant32 = 16;  // fastest untuned FP32 choice (eight-row tiles, MFMA)
+constexpr int kDefaultVariant32 = 23;  // other widths: the pipelined kernel on the FP64 matrix cores (1.31 /
+                                       // 1.42 ms at m = 8 / 16 and 10^6 rows against 1.41-1.50 ms unpipelined)
 constexpr int kDefaultVariant32m32 = 26;  // at m = 32: the pipelined kernel on the FP32 matrix cores, four
                                           // steps chained before each FP64 addition, two waves per workgroup
                                           // (1.65 ms against 1.72 ms on the FP64 matrix cores and 1.75-1.93
                                           // ms for the others at 10^6 rows)
-constexpr int kDefaultVariant32m64 = 17;  // at m = 64: two waves per workgroup (3.07 against 3.16 ms)
+constexpr int kDefaultVariant32m64 = 26;  // at m = 64 too: 2.22 ms against 3.07 ms for the fastest FP64
+                                          // matrix-core form (two waves per workgroup), 3.10-3.47 ms for the rest
 
 inline int rt_spmm(ff_ctx *ctx, hipStream_t st, const rt::RTView &v, int sub, int m, const float *Y, int64_t ldy,
                    float *HY, float *MY, int64_t ldo, const int *row_obj, const int *status) {
