@@ -126,3 +126,26 @@ def test_chebyshev_apply_validates(cloud, ctx, ff):
         ff.chebyshev_apply(ctx, c.n, A.row_ptr, A.col, A.H, A.M, A.hm32, R[:, :24].contiguous(), values=3)
     with pytest.raises(ff.FFError):
         ff.chebyshev_apply(ctx, c.n, A.row_ptr, A.col, A.H, A.M, A.hm32, R.double())
+
+
+def test_chebyshev_shape_override(cloud, ctx, ff, monkeypatch):
+    """FF_CHEB_SHAPE (read at context creation) runs the matrix-core steps in another launch shape:
+    every shape sums alike, so the result is bitwise the default's; a shape of the other K-block
+    form is refused."""
+    c, P, A, upper = cloud
+    R = dev(np.random.default_rng(7).standard_normal((c.n, 32)), torch.float32)
+    Z0, _ = ff.chebyshev_apply(ctx, c.n, A.row_ptr, A.col, A.H, A.M, A.hm32, R, degree=12, values=4, upper=upper)
+    monkeypatch.setenv("FF_CHEB_SHAPE", "11")
+    c11 = ff.Context(0)
+    try:
+        Z1, _ = ff.chebyshev_apply(c11, c.n, A.row_ptr, A.col, A.H, A.M, A.hm32, R, degree=12, values=4, upper=upper)
+        assert torch.equal(Z0, Z1)
+    finally:
+        c11.close()
+    monkeypatch.setenv("FF_CHEB_SHAPE", "3")
+    c3 = ff.Context(0)
+    try:
+        with pytest.raises(ff.FFError):
+            ff.chebyshev_apply(c3, c.n, A.row_ptr, A.col, A.H, A.M, A.hm32, R, degree=12, values=4, upper=upper)
+    finally:
+        c3.close()
