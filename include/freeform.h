@@ -318,7 +318,11 @@ typedef struct {
  *
  *  row_ptr, col, H, M: FP64 CSR from assemble_HM (device in)
  *  hm32     FP32 interleaved copy (device in), required when precision = 1
- *  X0       [n][block] device in (row-major), or NULL: Philox uniform [-1, 1)
+ *  X0       [n][block] device in (row-major), or NULL: Philox uniform [-1, 1); an object
+ *           with fewer than 5 x block rows (and at most 192) leaves the block iteration no
+ *           room, and with X0 NULL starts instead from the lowest block eigenvectors of its
+ *           dense pencil (rayleigh_ritz on the identity basis), which the iteration then
+ *           certifies as any other answer
  *  eigval   [k] host out, ascending
  *  W        [n][k] device out (row-major, sorted node numbering): M-orthonormal
  *           eigenvectors; sign: the entry of largest magnitude is positive

@@ -43,6 +43,7 @@ enum WsSlot {
     WS_BLEND,                                                     // warm start: column blend partials
     WS_SYM,                                                       // symmetric copy: row counts
     WS_T8Z_CNT, WS_T8Z_OFF, WS_T8Z_MASK, WS_T8Z_VAL,              // zero-free eight-row [H, M] copy
+    WS_DENSE, WS_DENSE_X,                                         // small objects: dense pencil, start block
     WS_COUNT
 };
 

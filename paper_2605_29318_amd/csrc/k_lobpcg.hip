@@ -3036,12 +3036,49 @@ int solve(ff_ctx *ctx, int n_obj, const int64_t *obj_off, const int64_t *row_ptr
 using namespace ff;
 using namespace ff::lob;
 
+// row i of the dense pencil [H; M] (n x n each, row-major) from the CSR: the row is cleared, then its
+// entries are written (one workgroup per row)
+__global__ void __launch_bounds__(256) csr_dense_kernel(int64_t n, const int64_t *row_ptr, const int32_t *col,
+                                                        const double *H, const double *M, double *G) {
+    const int64_t i = blockIdx.x;
+    if (i >= n) return;
+    double *gh = G + i * n, *gm = G + n * n + i * n;
+    for (int64_t j = threadIdx.x; j < n; j += blockDim.x) gh[j] = gm[j] = 0.0;
+    __syncthreads();
+    for (int64_t e = row_ptr[i] + threadIdx.x; e < row_ptr[i + 1]; e += blockDim.x) {
+        gh[col[e]] = H[e];
+        gm[col[e]] = M[e];
+    }
+}
+
+// An object with fewer than five block widths of rows leaves the block iteration no room: its search
+// space [X, W, P] is most of the space and the basis loses rank (the oracle's LOBPCG stalls there
+// too). When such an object is small enough for the Rayleigh-Ritz kernels (at most 192 rows), its
+// start block is the exact lowest m eigenvectors of the dense pencil, Rayleigh-Ritz on the identity
+// basis; the iteration then finds them converged and certifies them as any other answer.
+constexpr int kDenseStartRows = 192;
+
 extern "C" int eigenmodes(ff_ctx *ctx, int64_t n, const int64_t *row_ptr, const int32_t *col, const double *H,
                           const double *M, const float *hm32, const ff_eig_params *p, const double *X0, double *eigval,
                           double *W, double *resid, ff_eig_info *info) {
     if (!ctx) return FF_ERR_INVALID_ARG;
     FF_REQUIRE(ctx, n > 0, "n must be positive");
+    FF_REQUIRE(ctx, p != nullptr, "bad arguments");
     const int64_t off[2] = {0, n};
+    const int m = p->block > 0 ? p->block : ((p->k + 7) / 8) * 8;
+    if (!X0 && p->k >= 1 && m >= 8 && m <= 64 && m <= n && n < 5 * (int64_t)m && n <= kDenseStartRows && row_ptr &&
+        col && H && M) {
+        FF_HIP(ctx, hipSetDevice(ctx->device));
+        double *G = (double *)ws_get(ctx, WS_DENSE, (size_t)2 * n * n * sizeof(double));
+        double *Xd = (double *)ws_get(ctx, WS_DENSE_X, ((size_t)n * m + m) * sizeof(double));
+        if (!G || !Xd) return FF_ERR_OOM;
+        hipLaunchKernelGGL(csr_dense_kernel, dim3((unsigned)n), dim3(256), 0, ctx->stream, n, row_ptr, col, H, M, G);
+        FF_CHECK_LAUNCH(ctx);
+        int kept = 0;
+        const int rc = rayleigh_ritz(ctx, (int)n, m, G, 1e-13, Xd, Xd + (size_t)n * m, &kept);
+        if (rc) return rc;
+        return solve(ctx, 1, off, row_ptr, col, H, M, hm32, p, Xd, eigval, W, resid, info);
+    }
     return solve(ctx, 1, off, row_ptr, col, H, M, hm32, p, X0, eigval, W, resid, info);
 }
 
