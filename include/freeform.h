@@ -55,7 +55,7 @@ typedef enum {
  * and FF_ASM_BITMAP_BYTES=n caps the row bitmaps assemble_HM keeps between
  * its passes at n bytes, so that the other paths of both can be exercised
  * (the results are the same either way); FF_CHEB_SHAPE=n runs the matrix-core
- * Chebyshev steps in launch shape n of spmm_rowtiles precision 2 (8 .. 12 with
+ * Chebyshev steps in launch shape n of spmm_rowtiles precision 2 (8 .. 14 with
  * the zero-free K-blocks, the default, 0 .. 7 with the full ones), for tuning:
  * every shape gives the same sums bit for bit. */
 int ff_ctx_create(ff_ctx **ctx, int device, void *hip_stream);
@@ -518,13 +518,15 @@ int rayleigh_ritz_noalloc(ff_ctx *ctx, int w, int m, const double *G, double tau
  *   rows) or m in {4, 8, 12, 16, 32, 64} (sixteen rows). A handle built
  *   with precision 6 also takes precision 2: Y in binary16 ([n][m] with
  *   ld_y == m, m 32 or 64), HY = H Y in FP32, accumulated in FP32 on
- *   v_mfma_f32_16x16x16_f16 (MY NULL); its launch shapes are sub 0 .. 12
+ *   v_mfma_f32_16x16x16_f16 (MY NULL); its launch shapes are sub 0 .. 14
  *   (0 .. 4: a ring of K-blocks, by waves per workgroup and K-blocks in
  *   flight; 5 .. 7: super-blocks of four K-blocks, the next one's loads
  *   issued before the current one is multiplied; 8 .. 12: the same
  *   super-blocks read from a copy without the K-blocks' zeros, a 128-bit
  *   mask per K-block and the present values, which a precision-6 handle
- *   keeps beside the full K-blocks), all with the same operands and
+ *   keeps beside the full K-blocks; 13, 14: those with one register buffer,
+ *   the next super-block gathered once the current one is staged in LDS,
+ *   four and two waves per workgroup), all with the same operands and
  *   summation order, so the same result bit for bit. Errors: invalid
  *   arguments and unsupported shapes return FF_ERR_INVALID_ARG, a
  *   non-finite H at precision 5 likewise.

@@ -1773,9 +1773,11 @@ constexpr int kChebT8Sub = 1;                  // launch shape of the fused step
 // launch shape of the matrix-core Chebyshev step, the super-block pipelined kernel; the product alone
 // at 10^6 particles, m = 32 / 64: full K-blocks with eight / four waves per workgroup 0.561 / 0.796 ms,
 // zero-free K-blocks with four / two waves 0.510 / 0.781 ms (at six waves per SIMD, 80 registers,
-// the four-wave form spilled and took 0.618 ms at m = 32)
+// the four-wave form spilled and took 0.618 ms at m = 32). At m = 64 the single-buffer form (shape
+// 13: 108 registers) takes the whole k = 64 solve from 1.403 to 1.395 s; at m = 32 it ties (0.557
+// against 0.558 ms per step)
 inline int cheb_tq_sub(int m, bool packed) {
-    return packed ? (m == 32 ? rt::kTqPacked + 1 : rt::kTqPacked + 4) : (m == 32 ? 5 : 6);
+    return packed ? (m == 32 ? rt::kTqPacked + 1 : 13) : (m == 32 ? 5 : 6);
 }
 // the matrix-core steps read the zero-free copy unless precond_values asks for the full K-blocks
 constexpr bool kChebPackedDefault = true;

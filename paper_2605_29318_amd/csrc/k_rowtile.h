@@ -140,7 +140,7 @@ struct ChebStepQ {
 };
 // sub selects a launch shape (waves per block, K-blocks in flight), 0 .. kTqSubs - 1; shapes
 // kTqPacked and above read the zero-free copy (pmask, pval)
-constexpr int kTqSubs = 13;
+constexpr int kTqSubs = 15;
 constexpr int kTqPacked = 8;
 int cheb_step_tq(ff_ctx *ctx, hipStream_t st, const RTQView &v, int sub, int m, const uint16_t *DZ,
                  const int *row_obj, const int *status, const ChebStepQ &cs);

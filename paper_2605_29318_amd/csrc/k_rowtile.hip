@@ -1704,7 +1704,7 @@ typedef const __attribute__((address_space(4))) int64_t *ConstI64;
 // the super-block's values staged in LDS: at most 4 * 128 halves
 constexpr int kPkStage = 4 * 128 * 2;
 
-template <int kMB, bool kEpi, int kWaves, int kOcc, bool kPacked = false>
+template <int kMB, bool kEpi, int kWaves, int kOcc, bool kPacked = false, int kDepth = 2>
 __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(kOcc, 8)))
 spmm_tq_sb_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int32_t *tcol, const int64_t *kptr,
                   const _Float16 *vq, float vscale, const _Float16 *Y, float *HY, int64_t ldo, const int *row_obj,
@@ -1794,7 +1794,7 @@ spmm_tq_sb_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int3
             pk.pv = 8 * lane < span ? __builtin_nontemporal_load((const u32x4 *)(pq.pval + pk_run) + lane)
                                     : u32x4{0u, 0u, 0u, 0u};
             pk_run += (span + 7) & ~7;
-            pk.mk = load_masks(s + 2);
+            pk.mk = load_masks(s + (kDepth == 1 ? 1 : 2));
         }
         __builtin_amdgcn_sched_barrier(0);
     };
@@ -1802,7 +1802,8 @@ spmm_tq_sb_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int3
 #pragma unroll
     for (int cb = 0; cb < kMB; ++cb) acc[cb] = f32x4{0.f, 0.f, 0.f, 0.f};
     // multiplies super-block s; full: all four of its K-blocks lie inside the tile
-    auto consume = [&](int s, const f32x4 (&y)[kQ][kLoads], const f16x4 (&b)[kQ], const PkSB &pk, bool full) {
+    // the gathered rows and the staged values of a super-block into LDS
+    auto stage_lds = [&](const f32x4 (&y)[kQ][kLoads], const PkSB &pk) __attribute__((always_inline)) {
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int q = 0; q < kQ; ++q)
@@ -1811,6 +1812,10 @@ spmm_tq_sb_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int3
                 *(f32x4 *)(&ys[wv][q][0] + (slot + kRowsPer * i) * kStride + piece * 16) = y[q][i];
         if constexpr (kPacked) *(u32x4 *)(&pvs[wv][0] + 16 * lane) = pk.pv;
         __builtin_amdgcn_wave_barrier();
+    };
+    // multiplies the staged super-block s (lo, hi: its K-blocks' masks)
+    auto compute = [&](int s, const f16x4 (&b)[kQ], const uint64_t (&mlo)[kQ], const uint64_t (&mhi)[kQ], bool full)
+        __attribute__((always_inline)) {
         f16x4 bp[kQ];
         if constexpr (kPacked) {
             // expand the four K-blocks in place, lane j taking entries j (rows 0-3) and 64 + j
@@ -1822,7 +1827,7 @@ spmm_tq_sb_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int3
             int base = 0;                                              // halves before K-block q
 #pragma unroll
             for (int q = 0; q < kQ; ++q) {
-                const uint64_t lo = pk.lo[q], hi = pk.hi[q];
+                const uint64_t lo = mlo[q], hi = mhi[q];
                 const int nlo = __popcll(lo);
                 const int ilo = __builtin_amdgcn_mbcnt_hi((uint32_t)(lo >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)lo, 0));
                 const int ihi = __builtin_amdgcn_mbcnt_hi((uint32_t)(hi >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)hi, 0));
@@ -1833,8 +1838,8 @@ spmm_tq_sb_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int3
             uint16_t *pd = ps;
 #pragma unroll
             for (int q = 0; q < kQ; ++q) {
-                pd[q * 128 + lane] = __builtin_amdgcn_inverse_ballot_w64(pk.lo[q]) ? v0[q] : (uint16_t)0;
-                pd[q * 128 + 64 + lane] = __builtin_amdgcn_inverse_ballot_w64(pk.hi[q]) ? v1[q] : (uint16_t)0;
+                pd[q * 128 + lane] = __builtin_amdgcn_inverse_ballot_w64(mlo[q]) ? v0[q] : (uint16_t)0;
+                pd[q * 128 + 64 + lane] = __builtin_amdgcn_inverse_ballot_w64(mhi[q]) ? v1[q] : (uint16_t)0;
             }
             __builtin_amdgcn_wave_barrier();
 #pragma unroll
@@ -1851,34 +1856,68 @@ spmm_tq_sb_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int3
             }
         }
     };
-    if (nk > 0) {
-        f32x4 ya[kQ][kLoads], yb[kQ][kLoads];
-        f16x4 ba[kQ], bb[kQ];
-        PkSB pa, pb;
-        if constexpr (kPacked) {
-            pa.mk = load_masks(0);
-            pb.mk = load_masks(1);
+    auto consume = [&](int s, const f32x4 (&y)[kQ][kLoads], const f16x4 (&b)[kQ], const PkSB &pk, bool full)
+        __attribute__((always_inline)) {
+        stage_lds(y, pk);
+        compute(s, b, pk.lo, pk.hi, full);
+    };
+    if constexpr (kDepth == 1) {
+        // one buffer: super-block s + 1 is gathered into the registers that held s once s is staged
+        // in LDS, while s is multiplied from there; its masks are loaded one super-block ahead (the
+        // wait for them only waits for loads that staging s waited for already)
+        static_assert(kPacked, "the single-buffer form reads the zero-free copy");
+        if (nk > 0) {
+            f32x4 y1[kQ][kLoads];
+            f16x4 b1[kQ];
+            PkSB p1;
+            p1.mk = load_masks(0);
+            issue(0, cols_of(0), y1, b1, p1, false);
+            int cn = cols_of(ns > 1 ? 1 : 0);
+            for (int s = 0; s < ns; ++s) {
+                stage_lds(y1, p1);
+                uint64_t mlo[kQ], mhi[kQ];
+#pragma unroll
+                for (int q = 0; q < kQ; ++q) {
+                    mlo[q] = p1.lo[q];
+                    mhi[q] = p1.hi[q];
+                }
+                if (s + 1 < ns) {
+                    issue(s + 1, cn, y1, b1, p1, false);
+                    cn = cols_of(s + 2 < ns ? s + 2 : ns - 1);
+                }
+                compute(s, b1, mlo, mhi, false);
+            }
         }
-        const int c0 = cols_of(0);
-        int c1 = cols_of(ns > 1 ? 1 : 0);
-        issue(0, c0, ya, ba, pa, ns > 1);
-        int s = 0;
-        // steady state: super-blocks s and s + 1 are whole, s + 2 exists
-        for (; s + 2 < ns; s += 2) {
-            const int c2 = cols_of(s + 2);
-            issue(s + 1, c1, yb, bb, pb, true);
-            consume(s, ya, ba, pa, true);
-            c1 = cols_of(s + 3 < ns ? s + 3 : ns - 1);
-            issue(s + 2, c2, ya, ba, pa, false);
-            consume(s + 1, yb, bb, pb, true);
-        }
-        // the last one or two super-blocks
-        if (s + 1 < ns) {
-            issue(s + 1, c1, yb, bb, pb, false);
-            consume(s, ya, ba, pa, true);
-            consume(s + 1, yb, bb, pb, false);
-        } else {
-            consume(s, ya, ba, pa, false);
+    } else {
+        if (nk > 0) {
+            f32x4 ya[kQ][kLoads], yb[kQ][kLoads];
+            f16x4 ba[kQ], bb[kQ];
+            PkSB pa, pb;
+            if constexpr (kPacked) {
+                pa.mk = load_masks(0);
+                pb.mk = load_masks(1);
+            }
+            const int c0 = cols_of(0);
+            int c1 = cols_of(ns > 1 ? 1 : 0);
+            issue(0, c0, ya, ba, pa, ns > 1);
+            int s = 0;
+            // steady state: super-blocks s and s + 1 are whole, s + 2 exists
+            for (; s + 2 < ns; s += 2) {
+                const int c2 = cols_of(s + 2);
+                issue(s + 1, c1, yb, bb, pb, true);
+                consume(s, ya, ba, pa, true);
+                c1 = cols_of(s + 3 < ns ? s + 3 : ns - 1);
+                issue(s + 2, c2, ya, ba, pa, false);
+                consume(s + 1, yb, bb, pb, true);
+            }
+            // the last one or two super-blocks
+            if (s + 1 < ns) {
+                issue(s + 1, c1, yb, bb, pb, false);
+                consume(s, ya, ba, pa, true);
+                consume(s + 1, yb, bb, pb, false);
+            } else {
+                consume(s, ya, ba, pa, false);
+            }
         }
     }
     if (!mine) return;
@@ -1918,6 +1957,9 @@ static int launch_tq(ff_ctx *ctx, hipStream_t st, const RTQView &v, int sub, int
 #define FF_TQP(MB, W, O)                                                                                       \
     hipLaunchKernelGGL((spmm_tq_sb_kernel<MB, kEpi, W, O, true>), dim3(grid_for(v.ntiles, W)), dim3(64 * W), 0, st,  \
                        v.n, v.ntiles, v.tptr, v.tcol, v.kptr, vq, v.hscale, y, HY, ldo, row_obj, status, cs, pq)
+#define FF_TQP1(MB, W, O)                                                                                     \
+    hipLaunchKernelGGL((spmm_tq_sb_kernel<MB, kEpi, W, O, true, 1>), dim3(grid_for(v.ntiles, W)), dim3(64 * W), 0,  \
+                       st, v.n, v.ntiles, v.tptr, v.tcol, v.kptr, vq, v.hscale, y, HY, ldo, row_obj, status, cs, pq)
 #define FF_TQ_SHAPES(MB)                   \
     switch (sub) {                         \
         case 1: FF_TQ(MB, 8, 4, 3); break; \
@@ -1932,6 +1974,8 @@ static int launch_tq(ff_ctx *ctx, hipStream_t st, const RTQView &v, int sub, int
         case 10: FF_TQP(MB, 8, MB == 2 ? 5 : 3); break; \
         case 11: FF_TQP(MB, 4, 4); break;  \
         case 12: FF_TQP(MB, 2, 2); break;  \
+        case 13: FF_TQP1(MB, 4, 6); break; \
+        case 14: FF_TQP1(MB, 2, 6); break; \
         default: FF_TQ(MB, 8, 4, 2); break; \
     }
     if (m == 32) {
@@ -1941,6 +1985,7 @@ static int launch_tq(ff_ctx *ctx, hipStream_t st, const RTQView &v, int sub, int
     }
 #undef FF_TQ_SHAPES
 #undef FF_TQP
+#undef FF_TQP1
 #undef FF_TQS
 #undef FF_TQ
     FF_CHECK_LAUNCH(ctx);
