@@ -526,7 +526,8 @@ int rayleigh_ritz_noalloc(ff_ctx *ctx, int w, int m, const double *G, double tau
  *   mask per K-block and the present values, which a precision-6 handle
  *   keeps beside the full K-blocks; 13, 14: those with one register buffer,
  *   the next super-block gathered once the current one is staged in LDS,
- *   four and two waves per workgroup), all with the same operands and
+ *   four waves per workgroup, 14 with unpadded rows in LDS so that eight
+ *   waves fit a SIMD), all with the same operands and
  *   summation order, so the same result bit for bit. Errors: invalid
  *   arguments and unsupported shapes return FF_ERR_INVALID_ARG, a
  *   non-finite H at precision 5 likewise.

@@ -1704,7 +1704,7 @@ typedef const __attribute__((address_space(4))) int64_t *ConstI64;
 // the super-block's values staged in LDS: at most 4 * 128 halves
 constexpr int kPkStage = 4 * 128 * 2;
 
-template <int kMB, bool kEpi, int kWaves, int kOcc, bool kPacked = false, int kDepth = 2>
+template <int kMB, bool kEpi, int kWaves, int kOcc, bool kPacked = false, int kDepth = 2, bool kPadRows = true>
 __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(kOcc, 8)))
 spmm_tq_sb_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int32_t *tcol, const int64_t *kptr,
                   const _Float16 *vq, float vscale, const _Float16 *Y, float *HY, int64_t ldo, const int *row_obj,
@@ -1716,7 +1716,8 @@ spmm_tq_sb_kernel(int64_t nrows, int64_t ntiles, const int64_t *tptr, const int3
     // LDS row stride in bytes (2m + 32, which puts the eight rows a half-wave reads by the transposing
     // read on distinct banks and cut the bank-conflict cycles by a quarter, measured 3% slower at
     // m = 32: 0.526 against 0.512 ms)
-    constexpr int kStride = 2 * m + 16;
+    // (unpadded rows: 2m bytes, so that eight four-wave workgroups fit a CU's LDS)
+    constexpr int kStride = kPadRows ? 2 * m + 16 : 2 * m;
     constexpr int kQ = 4;                          // K-blocks per super-block
     static_assert(kQ == kTqPackGroup, "the zero-free copy aligns groups of four K-blocks");
     __shared__ __align__(16) unsigned char ys[kWaves][kQ][16 * kStride];
@@ -1960,6 +1961,10 @@ static int launch_tq(ff_ctx *ctx, hipStream_t st, const RTQView &v, int sub, int
 #define FF_TQP1(MB, W, O)                                                                                     \
     hipLaunchKernelGGL((spmm_tq_sb_kernel<MB, kEpi, W, O, true, 1>), dim3(grid_for(v.ntiles, W)), dim3(64 * W), 0,  \
                        st, v.n, v.ntiles, v.tptr, v.tcol, v.kptr, vq, v.hscale, y, HY, ldo, row_obj, status, cs, pq)
+#define FF_TQP1U(MB, W, O)                                                                                    \
+    hipLaunchKernelGGL((spmm_tq_sb_kernel<MB, kEpi, W, O, true, 1, false>), dim3(grid_for(v.ntiles, W)),          \
+                       dim3(64 * W), 0, st, v.n, v.ntiles, v.tptr, v.tcol, v.kptr, vq, v.hscale, y, HY, ldo, row_obj,  \
+                       status, cs, pq)
 #define FF_TQ_SHAPES(MB)                   \
     switch (sub) {                         \
         case 1: FF_TQ(MB, 8, 4, 3); break; \
@@ -1975,7 +1980,7 @@ static int launch_tq(ff_ctx *ctx, hipStream_t st, const RTQView &v, int sub, int
         case 11: FF_TQP(MB, 4, 4); break;  \
         case 12: FF_TQP(MB, 2, 2); break;  \
         case 13: FF_TQP1(MB, 4, 6); break; \
-        case 14: FF_TQP1(MB, 2, 6); break; \
+        case 14: FF_TQP1U(MB, 4, 8); break; \
         default: FF_TQ(MB, 8, 4, 2); break; \
     }
     if (m == 32) {
@@ -1986,6 +1991,7 @@ static int launch_tq(ff_ctx *ctx, hipStream_t st, const RTQView &v, int sub, int
 #undef FF_TQ_SHAPES
 #undef FF_TQP
 #undef FF_TQP1
+#undef FF_TQP1U
 #undef FF_TQS
 #undef FF_TQ
     FF_CHECK_LAUNCH(ctx);
