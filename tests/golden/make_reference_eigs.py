@@ -2,6 +2,8 @@
 
     python tests/golden/make_reference_eigs.py spheres100k 32
     python tests/golden/make_reference_eigs.py ellipsoids1m 32 --tol 5e-8 --guard 16 --kc 36
+    python tests/golden/make_reference_eigs.py ellipsoids1m 32 --tol 1.5e-8 --guard 16 --kc 32 --partial P
+    python tests/golden/make_reference_eigs.py ellipsoids1m 32 --guard 16 --kc 32 --from-partial P
 
 Builds the seeded workload (``synth.workload``), runs the oracle's whole
 pipeline (binning, neighbours, RKPM shape functions of Sec. 3.2 Eq. (7)-(11),
@@ -41,6 +43,9 @@ def main(argv=None):
     ap.add_argument("--out", default=None)
     ap.add_argument("--partial", default=None,
                     help="rewrite this file with the Ritz values and residuals every 10 iterations")
+    ap.add_argument("--from-partial", default=None,
+                    help="write the reference from such a progress file of a run with the same arguments "
+                         "(the solve stopped there: its Ritz values, its own residuals) instead of solving")
     a = ap.parse_args(argv)
 
     import numpy as np
@@ -55,6 +60,25 @@ def main(argv=None):
     m = a.k + a.guard
     kc = a.kc if a.kc is not None else a.k + a.guard // 2
     assert a.k <= kc <= m
+    if a.from_partial:
+        d = json.load(open(a.from_partial))
+        lam, res = d["ritz_values"], d["residuals"]
+        assert len(lam) == m and all(x <= y for x, y in zip(lam, lam[1:]))
+        out = {
+            "workload": a.workload, "sha256": cloud.sha256(), "n": int(cloud.n), "nnz": int(P.row_ptr[-1]),
+            "h": float(cloud.h), "k": a.k, "block": m, "k_converged": kc,
+            "tol": float(max(res[:kc])), "max_resid_first_kc": float(max(res[:kc])),
+            "iterations": int(d["iteration"]), "stopped": "at the progress file's iteration, before tol",
+            "start": f"synth.initial_block(n, {m}, seed={a.seed})",
+            "precond": "oracle.chebyshev_jacobi defaults (degree 12, ratio 1000)",
+            "eigenvalues": [float(x) for x in lam], "residuals": [float(x) for x in res],
+            "residual_kind": "the solve's own (from its implicitly updated products)",
+        }
+        path = a.out or os.path.join(HERE, f"ref_eigs_{a.workload}_k{a.k}.json")
+        with open(path, "w") as f:
+            json.dump(out, f, indent=1)
+        print(json.dumps({k: v for k, v in out.items() if k not in ("eigenvalues", "residuals")}))
+        return 0
     X0 = synth.initial_block(cloud.n, m, seed=a.seed)
     t1 = time.time()
     def partial(it, th, res):
