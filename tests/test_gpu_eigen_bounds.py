@@ -133,12 +133,12 @@ def test_fullsize_eigenvalues_against_reference(oracle, ctx, ff, name):
     within 1e-5 of lambda_2); the plain residual-1e-6 answer's error is printed beside it.
 
     The reference values are Ritz values of the oracle's solve, so they lie above the exact
-    eigenvalues by an amount that falls with the square of its residual. A reference solved to
-    a residual above 2e-8 is not accurate to 1e-5 (at 10^6 particles, residual 5e-8, it lies
-    0.5e-5 to 3.9e-5 above the refined answer on every pair, whose FP64 Ritz values cannot lie
-    below the exact eigenvalues by more than rounding either); against such a reference
-    only the side that its excess cannot hide is checked: each refined eigenvalue at most 1e-5
-    above the reference."""
+    eigenvalues by an amount that falls with its residual. A reference solved to a residual above
+    2e-8 is not accurate to 1e-5 (at 10^6 particles a reference at residual 5e-8 lay 0.5e-5 to
+    3.9e-5 above the refined answer on every pair, whose FP64 Ritz values cannot lie below the
+    exact eigenvalues by more than rounding either; at residual 1.5e-8, within 1.7e-6 of it);
+    against such a reference only the side that its excess cannot hide is checked: each refined
+    eigenvalue at most 1e-5 above the reference."""
     path = os.path.join(GOLDEN, f"ref_eigs_{name}_k32.json")
     if not os.path.exists(path):
         pytest.skip(f"no reference eigenvalues for {name}")
