@@ -6,7 +6,7 @@ Binning, neighbours and the CSR pattern are integer work and bit-exact; values w
 largest (the FP64 sums in another order). Eigenvalues: the FP64 path to residual 1e-10 within 1e-8
 relative; the mixed path (FP32 products, at k = 32 the binary16 matrix-core Chebyshev steps) to
 residual 1e-6 within 1e-5 relative and its residual recomputed by the oracle within 2e-6, as the
-larger objects' tests state. An object with fewer rows than the block is refused.
+larger objects' tests state. An object with fewer rows than the block, and an empty one, are refused.
 """
 import numpy as np
 import pytest
@@ -90,4 +90,18 @@ def test_block_wider_than_object_is_refused(oracle, ctx, ff):
     A = ff.assemble_cloud(ctx, dev(c.xyz), dev(c.vol), dev(c.lam), dev(c.mu), c.h)
     with pytest.raises(ff.FFError) as ei:
         ff.eigenmodes(ctx, c.n, A.row_ptr, A.col, A.H, A.M, A.hm32, k=32)
+    assert ei.value.code == ff.FF_ERR_INVALID_ARG
+
+
+def test_empty_object_is_refused(ctx, ff):
+    """No particles: the entry points refuse the call (FF_ERR_INVALID_ARG), nothing is launched."""
+    with pytest.raises(ff.FFError) as ei:
+        ff.build_neighbors(ctx, dev(np.zeros((0, 3))), 0.5)
+    assert ei.value.code == ff.FF_ERR_INVALID_ARG
+    empty_i64 = torch.zeros(1, dtype=torch.int64, device="cuda")
+    empty_i32 = torch.zeros(0, dtype=torch.int32, device="cuda")
+    empty_f64 = torch.zeros(0, dtype=torch.float64, device="cuda")
+    empty_f32 = torch.zeros(0, dtype=torch.float32, device="cuda")
+    with pytest.raises(ff.FFError) as ei:
+        ff.eigenmodes(ctx, 0, empty_i64, empty_i32, empty_f64, empty_f64, empty_f32, k=4)
     assert ei.value.code == ff.FF_ERR_INVALID_ARG
